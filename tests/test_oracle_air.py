@@ -1,0 +1,145 @@
+"""Pins of the reference AIR (oracle/air_ref.py) by identities that hold for the
+ideal and local ideal restriction, PMIS validity, brute-force products, and
+convergence of the V-cycle to the exact sweep answer."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1910_11463_amd import workloads as wl
+from oracle import air_ref as AR, dg, quadrature as Q, source_iteration as si, sweep as SW
+
+
+def _transport_matrix(kind, n, m=0, order=4, seed=0):
+    mesh = wl.hex_mesh(n) if kind == "hex" else wl.kuhn_tet_mesh(n, jitter=0.2, seed=seed + 1)
+    E = mesh.n_elem
+    st = np.random.default_rng(seed).uniform(0.1, 3.0, E)
+    om, w = Q.level_symmetric(order)
+    prob = si.Problem(mesh, st, 0.5 * st, np.ones(E), om, w)
+    b = prob.blocks(m)
+    return prob, b, dg.scaled_csr(prob.topo, b)
+
+
+CASES = [("hex", 3, 0), ("hex", 3, 17), ("tet", 2, 5), ("tet", 2, 11)]
+
+
+@pytest.mark.parametrize("kind,n,m", CASES)
+def test_pmis_valid(kind, n, m):
+    """Properties any PMIS split has: every point decided; a point nobody
+    depends on is F; every other F-point strongly depends on a C-point; and if
+    C-point b strongly depends on C-point a, then b was chosen first, which
+    requires b's measure to exceed a's."""
+    _, _, A = _transport_matrix(kind, n, m)
+    S = AR.strength(A, 0.25)
+    seed = 1234
+    cf = AR.pmis(S, 0, seed)
+    assert set(np.unique(cf)) <= {-1, 1}
+    lam = np.diff(S.T.tocsr().indptr)
+    assert np.all(cf[lam == 0] < 0)
+    for i in np.flatnonzero((cf < 0) & (lam >= 1)):
+        dep = S.indices[S.indptr[i]:S.indptr[i + 1]]
+        assert np.any(cf[dep] > 0)
+    key = lambda i: (int(lam[i]), AR.pmis_random(int(i), 0, seed), int(i))
+    nC = 0
+    for b in np.flatnonzero(cf > 0):
+        for a in S.indices[S.indptr[b]:S.indptr[b + 1]]:
+            if cf[a] > 0:
+                nC += 1
+                assert key(b) > key(a)
+    assert np.count_nonzero(cf > 0) > 0
+
+
+def test_splitmix64_published_values():
+    """SplitMix64 from seed 0: the published generator's first outputs
+    (state advanced by the golden-gamma increment before mixing)."""
+    g = 0x9E3779B97F4A7C15
+    outs = [AR.splitmix64((k * g) & AR.MASK64) for k in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("kind,n,m", CASES)
+def test_ideal_restriction_gives_schur_complement(kind, n, m):
+    _, _, A = _transport_matrix(kind, n, m)
+    S = AR.strength(A, 0.25)
+    cf = AR.pmis(S, 0, 7)
+    opts = AR.Options(distance=None)
+    R = AR.lair_restriction(A, cf, opts)
+    Ad = A.toarray()
+    Fi, Ci = np.flatnonzero(cf < 0), np.flatnonzero(cf > 0)
+    Rd = np.zeros((Ci.size, A.shape[0]))
+    Rd[:, Ci] = np.eye(Ci.size)
+    Rd[:, Fi] = -Ad[np.ix_(Ci, Fi)] @ np.linalg.inv(Ad[np.ix_(Fi, Fi)])
+    assert np.abs(R.toarray() - Rd).max() <= 1e-12 * np.abs(Rd).max()
+    schur = Ad[np.ix_(Ci, Ci)] - Ad[np.ix_(Ci, Fi)] @ np.linalg.solve(Ad[np.ix_(Fi, Fi)], Ad[np.ix_(Fi, Ci)])
+    for p in (AR.one_point_interp(A, S, cf), np.where(cf > 0, AR.coarse_index(cf), -1)):
+        Ac = AR.galerkin(R, A, AR.p_matrix(p, Ci.size)).toarray()
+        assert np.abs(Ac - schur).max() <= 1e-12 * np.abs(schur).max()
+
+
+@pytest.mark.parametrize("kind,n,m", CASES)
+def test_two_level_exact_with_ideal_restriction(kind, n, m):
+    _, _, A = _transport_matrix(kind, n, m)
+    S = AR.strength(A, 0.25)
+    cf = AR.pmis(S, 0, 99)
+    R = AR.lair_restriction(A, cf, AR.Options(distance=None))
+    P = AR.p_matrix(AR.one_point_interp(A, S, cf), int((cf > 0).sum()))
+    Ac = AR.galerkin(R, A, P).toarray()
+    Ad = A.toarray()
+    b = np.random.default_rng(0).normal(size=A.shape[0])
+    Fi = np.flatnonzero(cf < 0)
+    x = np.zeros_like(b)
+    x[Fi] = np.linalg.solve(Ad[np.ix_(Fi, Fi)], (b - Ad @ x)[Fi])
+    x = x + P @ np.linalg.solve(Ac, R @ (b - Ad @ x))
+    x[Fi] += np.linalg.solve(Ad[np.ix_(Fi, Fi)], (b - Ad @ x)[Fi])
+    xe = np.linalg.solve(Ad, b)
+    assert np.abs(x - xe).max() <= 1e-11 * np.abs(xe).max()
+
+
+@pytest.mark.parametrize("kind,n,m", CASES)
+def test_lair_defining_identity_and_products(kind, n, m):
+    _, _, A = _transport_matrix(kind, n, m)
+    opts = AR.Options()
+    S = AR.strength(A, opts.theta)
+    cf = AR.pmis(S, 0, 5)
+    R = AR.lair_restriction(A, cf, opts)
+    SR = AR.strength(A, opts.eps_r)
+    RA = (R @ A).tocsr()
+    for I, i in enumerate(np.flatnonzero(cf > 0)):
+        Rset = AR._r_pattern(A, SR, cf, int(i), opts)
+        row = RA[I].toarray().ravel()
+        scale = np.abs(A[int(i)].toarray()).max()
+        assert np.abs(row[Rset]).max(initial=0.0) <= 1e-12 * scale
+        # the R row's F pattern is exactly R_i, plus the C-point itself with value 1
+        cols = R.indices[R.indptr[I]:R.indptr[I + 1]]
+        assert sorted(cols.tolist()) == sorted(Rset + [int(i)])
+        assert R[I, int(i)] == 1.0
+    P = AR.p_matrix(AR.one_point_interp(A, S, cf), int((cf > 0).sum()))
+    Ac = AR.galerkin(R, A, P)
+    dense = R.toarray() @ A.toarray() @ P.toarray()
+    assert np.abs(Ac.toarray() - dense).max() <= 1e-13 * np.abs(dense).max()
+
+
+def test_one_point_interpolation_picks_strongest_c_neighbour():
+    A = sp.csr_matrix(np.array([
+        [1.0, -0.5, 0.5, 0.0],
+        [0.0, 1.0, 0.0, 0.0],
+        [0.0, 0.0, 1.0, 0.0],
+        [0.3, -0.9, 0.9, 1.0]]))
+    S = AR.strength(A, 0.25)
+    cf = np.array([-1, 1, 1, -1])
+    p = AR.one_point_interp(A, S, cf)
+    # row 0: tie |-0.5| == |0.5| -> smaller column (1) -> coarse index 0
+    # row 3: tie between columns 1 and 2 again -> column 1; column 0 is F
+    assert p.tolist() == [0, 0, 1, 0]
+
+
+@pytest.mark.parametrize("kind,n,order,m", [("hex", 4, 2, 0), ("hex", 4, 8, 33), ("tet", 2, 4, 7)])
+def test_vcycle_converges_to_sweep(kind, n, order, m):
+    prob, b, A = _transport_matrix(kind, n, m, order=order)
+    f = prob.rhs(m, None)
+    bt = np.einsum("eab,eb->ea", np.linalg.inv(b.D), f).ravel()
+    levels = AR.setup(A, AR.Options(coarse_max=16))
+    assert len(levels) >= 2
+    x, it, hist = AR.solve(levels, bt, tol=1e-12, maxit=100)
+    assert hist[-1] <= 1e-12
+    xs = SW.sweep(b, f).ravel()
+    assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
