@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the pAIR S_N transport hot path on one MI355X.
+
+One step = one "sweep replacement": every direction of the workload solved by
+pAIR from a zero initial guess to a relative scaled residual of 1e-8, cold
+(upwind DG assembly + block scaling + AIR setup + V(1,1) FC-Jacobi cycles +
+scalar-flux sum), for the first source iteration (right-hand side from q).
+Metric: DOF x directions per second.  Inputs (mesh, materials, quadrature) are
+resident on the GPU before the timed region.
+
+Default workload: unit cube, 64^3 Q1 hexes (2.1M DOF per direction), S8 (80
+directions) solved one direction at a time, sigma_t log-uniform in [0.1, 10]
+(seed 2), sigma_s = 0.9 sigma_t, q = 1 in the central box.
+
+Printed JSON line also carries: the roofline of the dominant kernel (finest-level
+FC-Jacobi half-sweeps: algorithmic bytes / event-timed duration, against the
+8 TB/s HBM peak), the CPU oracle's exact sweep timed on a bounded sample of the
+same workload, and secondary measurements (batched mode, warm solve).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF·dirs/s to 1e-8 residual, batched vs per-direction pAIR; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_solver(w, mode_batch_size, device):
+    import torch
+    from paper_1910_11463_amd.solver import Solver
+    s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size)
+    s.set_mesh(w.mesh)
+    om, wt = Solver.level_symmetric(w.sn_order)
+    s.set_quadrature(om, wt)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device=device)
+    s.set_materials(dev(w.mats.sigma_t), dev(w.mats.sigma_s), dev(w.mats.q))
+    return s
+
+
+def timed_steps(s, mode, steps, warmup, cold=True, profile=False):
+    import torch
+    from paper_1910_11463_amd import binding as B
+    stats = None
+    for _ in range(warmup):
+        if cold:
+            s.clear_cache()
+        s.transport_sweep(mode=mode, want_psi=False, device=True)
+    torch.cuda.synchronize()
+    if profile:
+        B.check(B.pair_profile_enable(1))
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if cold:
+            s.clear_cache()
+        _, phi, stats, rc = s.transport_sweep(mode=mode, want_psi=False, device=True)
+        if rc != B.PAIR_OK:
+            raise RuntimeError("direction solves did not converge (rc=%d)" % rc)
+        log("  step %d/%d done" % (i + 1, steps))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if profile:
+        B.check(B.pair_profile_enable(0))
+    return (t1 - t0) / steps, stats
+
+
+def profile_kinds():
+    import ctypes
+    from paper_1910_11463_amd import binding as B
+    names = ["relax_fine", "residual_fine", "restrict_fine", "relax_coarse", "norm_fine"]
+    out = {}
+    for k, nm in enumerate(names):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        B.check(B.pair_profile_read(k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        out[nm] = {"launches": n.value, "ms": ms.value, "bytes": by.value,
+                   "avg_us": 1e3 * ms.value / max(1, n.value),
+                   "gbs": by.value / (ms.value * 1e-3) / 1e9 if ms.value > 0 else 0.0}
+    return out
+
+
+def cpu_baseline(w, sample_dirs, threads):
+    """The oracle's exact sweep (assembly + topological block solve) on a sample
+    of directions of the same workload, timed on the host."""
+    from oracle import quadrature as Q, source_iteration as si
+    om, wt = Q.level_symmetric(w.sn_order)
+    m = w.mats
+    prob = si.Problem(w.mesh, m.sigma_t, m.sigma_s, m.q, om, wt, cache_blocks=False)
+    M = om.shape[0]
+    dirs = [int(round(k * M / sample_dirs)) % M for k in range(sample_dirs)]
+    t0 = time.perf_counter()
+    si.transport_sweep(prob, None, threads=threads, dirs=dirs)
+    dt = time.perf_counter() - t0
+    return {"value": w.mesh.n_dof * len(dirs) / dt, "unit": "DOF*dirs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of %d directions (assembly + exact block sweep, numpy + C), %.1f s"
+                      % (len(dirs), M, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, help="workload number (1-5)")
+    ap.add_argument("--scale", type=int, default=None, help="elements per axis (default: full size)")
+    ap.add_argument("--mode", choices=["plain", "batched"], default="plain")
+    ap.add_argument("--batch-size", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--cpu-dirs", type=int, default=16)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the multi-GPU path (directions sharded over GPUs, "
+              "one all-reduce of phi per source iteration) is a design, not built; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1910_11463_amd import binding as B
+    from paper_1910_11463_amd import workloads as wl
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    B.load()
+    device = "cuda:0"
+    torch.cuda.set_device(0)
+    w = wl.make_config(args.config, scale=args.scale)
+    N, M = w.mesh.n_dof, w.n_dir
+    mode = B.PAIR_PLAIN if args.mode == "plain" else B.PAIR_BATCHED
+    log("workload %s: N=%d, M=%d, mode=%s" % (w.name, N, M, args.mode))
+
+    s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device)
+    sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
+    prof = profile_kinds()
+    value = N * M / sec
+    log("cold: %.3f s/step, %.3e DOF*dirs/s" % (sec, value))
+
+    extra = {}
+    # warm solve (hierarchies cached, as in every source iteration after the first)
+    wsec, wst = timed_steps(s, mode, 1, 0, cold=False)
+    extra["warm_solve"] = {"s_per_sweep": wsec, "dof_dirs_per_s": N * M / wsec,
+                           "vcycles_total": wst["vcycles_total"], "solve_ms": wst["t_solve_ms"]}
+    s.close()
+    if not args.no_extra:
+        other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
+        s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device)
+        osec, ost = timed_steps(s2, other, 1, 0, cold=True)
+        wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
+        extra["other_mode"] = {"mode": "batched" if other == B.PAIR_BATCHED else "plain",
+                               "batch_size": args.batch_size if other == B.PAIR_BATCHED else 1,
+                               "cold_dof_dirs_per_s": N * M / osec,
+                               "warm_dof_dirs_per_s": N * M / wsec2,
+                               "vcycles_max": ost["vcycles_max"]}
+        s2.close()
+
+    relax = prof["relax_fine"]
+    roofline = {"bound": "hbm", "achieved": relax["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": relax["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_relax<8> (finest-level FC-Jacobi half-sweeps)",
+                "launches": relax["launches"], "avg_us": relax["avg_us"],
+                "bytes_per_launch": relax["bytes"] / max(1, relax["launches"])}
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(8, os.cpu_count() or 1)
+        cpu = cpu_baseline(w, args.cpu_dirs, threads)
+        log("cpu baseline: %.3e DOF*dirs/s (%s)" % (cpu["value"], cpu["sample"]))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF*dirs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "mode": args.mode, "dof_per_dir": N, "dirs": M,
+                   "tol": 1e-8, "step": "cold sweep replacement: assembly + AIR setup + V-cycles + phi",
+                   "parallelism": "1 GPU"},
+        "stats": {"vcycles_total": st["vcycles_total"], "vcycles_max": st["vcycles_max"],
+                  "cf_mean": st["cf_mean"], "levels": st["levels_max"],
+                  "op_complexity": st["op_complexity"], "assemble_ms": st["t_assemble_ms"],
+                  "setup_ms": st["t_setup_ms"], "solve_ms": st["t_solve_ms"],
+                  "other_ms": st["t_other_ms"]},
+        "kernels": prof,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,144 @@
+// AIR algebraic multigrid on the GPU: hierarchy setup and V-cycles for a batch of
+// independent sparse matrices ("members", e.g. the directions of one S_N batch)
+// stored as one block-diagonal CSR matrix per level.
+//
+// Method (Sec. "Use of Algebraic Multigrid"; Sec. "SOC Parameter for Building R";
+// parameters of Sec. "Weak Scaling with Parallelism in Space"):
+//   strength (absolute values) -> PMIS C/F split -> lAIR restriction (distance 1)
+//   -> one-point interpolation by value -> R A P, repeated per level; dense inverse
+//   at the coarsest level; V(1,1) cycles with FC-Jacobi relaxation.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace pair {
+
+struct AmgParams {
+    double theta = 0.25;
+    double eps_r = 0.01;
+    double omega = 1.0;
+    int coarse_max = 256;
+    int max_levels = 25;
+    double max_coarse_ratio = 0.9;
+    int kmax = 64;
+    uint64_t seed = 0;
+    double tol = 1e-8;
+    int max_iter = 100;
+    int max_dense = 2048;   // largest coarsest level solved by a dense inverse
+    // lanes per row of the row kernels: index 0 = finest level, last entry used
+    // for all deeper levels.  A function of the level index only, so that every
+    // member's arithmetic (and its rounding) is the same whether it is solved
+    // alone or in a batch.
+    int lpr_a[4] = {8, 16, 16, 16};
+    int lpr_r = 8;
+};
+
+struct Csr {
+    int64_t n = 0, ncols = 0, nnz = 0;
+    DBuf<int64_t> rowptr;
+    DBuf<int32_t> col;
+    DBuf<double> val;
+};
+
+struct Level {
+    Csr A;                         // all members present at this level, concatenated
+    DBuf<double> dinv;             // 1 / a_ii
+    DBuf<uint16_t> seg;            // member id of every row
+    DBuf<int8_t> cf;               // +1 C, -1 F, 0 on rows of members coarsest here
+    DBuf<int32_t> p;               // one-point interpolation column (-1: empty row)
+    Csr R;                         // n_{l+1} x n_l
+    std::vector<int64_t> off;      // per member: first row, -1 if absent
+    std::vector<int64_t> cnt;      // per member: rows (0 if absent)
+    std::vector<uint8_t> relax_h;  // per member: 1 if it relaxes (not coarsest) here
+    DBuf<uint8_t> relax;           // device copy
+    // dense coarse solves of members whose coarsest level is this one
+    std::vector<int> coarse_members;
+    DBuf<int> coarse_member_d;     // member ids
+    DBuf<int64_t> coarse_off_d;    // first row of each coarse member
+    DBuf<int64_t> coarse_n_d;      // rows of each coarse member
+    DBuf<int64_t> coarse_inv_off_d;
+    DBuf<double> coarse_inv;       // packed dense inverses (row-major n x n)
+    // work vectors
+    DBuf<double> x, t, b, r;
+    int64_t n_f = 0, nnz_f = 0, n_c = 0, nnz_c = 0;   // rows / entries of relaxed F and C rows
+    int lpr = 8;                   // lanes per row for kernels on A
+    int lpr_r = 8;                 // lanes per row for kernels on R
+};
+
+struct SolveBufs {
+    DBuf<double> partial;          // per (member, chunk) partial sums
+    DBuf<double> bnorm2, rnorm2;   // per member
+    DBuf<double> relres;           // per member
+    DBuf<double> relres0;          // per member: first relative residual
+    DBuf<int> iters;               // per member
+    DBuf<uint8_t> active;          // per member
+    DBuf<int> n_active;            // scalar
+    int chunks = 0;
+};
+
+class Hierarchy {
+public:
+    Hierarchy(const AmgParams& prm, hipStream_t s) : prm_(prm), s_(s) {}
+
+    // Fine operator for B members; takes ownership of A.  off/cnt: member rows.
+    void setup(Csr&& A, const std::vector<int64_t>& off, const std::vector<int64_t>& cnt);
+
+    // V-cycles on all members from the current x of level 0 (set by the
+    // caller through x0()) for right-hand side b0() until every member meets
+    // tol or max_iter.  use_graph captures one cycle + convergence test as a
+    // hipGraph and replays it.  Returns true if all members converged.
+    bool solve(bool use_graph, bool x_is_zero);
+
+    double* b0() { return levels_[0].b.p; }
+    double* x0() { return levels_[0].x.p; }
+    int members() const { return B_; }
+    int num_levels() const { return static_cast<int>(levels_.size()); }
+    int member_levels(int b) const { return nlev_[b]; }
+    Level& level(int l) { return levels_[l]; }
+    const std::vector<int>& iters_h() const { return iters_h_; }
+    const std::vector<double>& relres_h() const { return relres_h_; }
+    const std::vector<double>& cf_h() const { return cf_h_; }
+    double solve_bytes_per_cycle() const;   // algorithmic bytes of one V-cycle (all members)
+    double last_solve_bytes() const { return last_bytes_; }
+    int64_t nnz_level(int l) const { return levels_[l].A.nnz; }
+    void set_params(const AmgParams& p) { prm_ = p; }
+
+private:
+    void build_level_aux(Level& L, int l);
+    void coarse_setup(Level& L, const std::vector<int>& members);
+    void vcycle_launches(bool x_is_zero);
+    void residual_norms();
+    void launch_cycle_and_test(bool x_is_zero, int it_offset);
+
+    AmgParams prm_;
+    hipStream_t s_;
+    int B_ = 0;
+    std::vector<Level> levels_;
+    std::vector<int> nlev_;
+    SolveBufs sb_;
+    std::vector<int> iters_h_;
+    std::vector<double> relres_h_, cf_h_;
+    DBuf<int64_t> moff_d_, mcnt_d_;   // finest-level member offsets / counts
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr;
+    double last_bytes_ = 0.0;
+
+public:
+    ~Hierarchy();
+    Hierarchy(const Hierarchy&) = delete;
+    Hierarchy& operator=(const Hierarchy&) = delete;
+};
+
+// ---------------------------------------------------------------- primitives
+// Exclusive scan of n int64 counts into out[0..n] (out[n] = total); returns total.
+int64_t exclusive_scan(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+
+// Member id per row from member row offsets.
+void fill_segments(uint16_t* seg, int64_t n, const std::vector<int64_t>& off,
+                   const std::vector<int64_t>& cnt, hipStream_t s);
+
+int choose_lpr(double avg_nnz_per_row);
+
+}  // namespace pair

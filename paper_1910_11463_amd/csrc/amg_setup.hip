@@ -1,0 +1,991 @@
+// AIR hierarchy setup on the GPU (all kernels FP64 / int32 indices).
+//
+// Per level, for every member still coarsening (Sec. "Use of Algebraic
+// Multigrid"; Sec. "SOC Parameter for Building R", eq. soc):
+//   1. diagonal inverse and max_{k != i} |a_ik| per row;
+//   2. strength flags per entry: bit 0 |a_ij| >= theta max (coarsening),
+//      bit 1 |a_ij| >= eps_R max (pattern of R); absolute values for both;
+//   3. PMIS C/F split: measure (lambda_i, rand_i, i) with lambda_i the number of
+//      rows strongly depending on i; rounds of "local maximum among undecided
+//      strong neighbours -> C, undecided points depending on a new C -> F";
+//   4. coarse numbering (exclusive scan), one-point interpolation by value
+//      (strongest strong C-neighbour, smallest column on ties);
+//   5. lAIR restriction: per C-point i, the eps_R-strong F-neighbours R_i
+//      (at most kmax, the largest |a_ij| kept), z solving
+//      A(R_i,R_i)^T z = -A(i,R_i)^T, row [z, 1];
+//   6. Galerkin product A_c = R A P: per coarse row all products r_Ik a_kj with
+//      P(j) >= 0 are gathered, sorted by (column, canonical position) and summed
+//      in canonical order, so the result is bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "amg.h"
+#include "kernels_common.h"
+
+namespace pair {
+namespace {
+
+constexpr int8_t ST_U = 0, ST_C = 1, ST_F = -1, ST_NP = 2;   // PMIS states
+constexpr uint64_t KEY_NONE = ~0ull;
+
+// ------------------------------------------------------------- row basics
+__global__ void k_diag_rowmax(int64_t n, const int64_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ col, const double* __restrict__ val,
+                              double* __restrict__ dinv, double* __restrict__ rowmax) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0, m = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        int64_t c = col[e];
+        double v = val[e];
+        if (c == i) d = v;
+        else m = fmax(m, fabs(v));
+    }
+    dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+    rowmax[i] = m;
+}
+
+__global__ void k_strength(int64_t n, const int64_t* __restrict__ rowptr,
+                           const int32_t* __restrict__ col, const double* __restrict__ val,
+                           const double* __restrict__ rowmax, const uint16_t* __restrict__ seg,
+                           const uint8_t* __restrict__ part, double theta, double eps_r,
+                           uint8_t* __restrict__ sflag, int* __restrict__ lam) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool on = part[seg[i]] != 0;
+    const double m = rowmax[i];
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        int32_t c = col[e];
+        uint8_t f = 0;
+        if (on && c != i && m > 0.0) {
+            double a = fabs(val[e]);
+            if (a >= theta * m) f |= 1;
+            if (a >= eps_r * m) f |= 2;
+        }
+        sflag[e] = f;
+        if (f & 1) atomicAdd(&lam[c], 1);
+    }
+}
+
+// ------------------------------------------------------------- PMIS
+__device__ __forceinline__ bool key_less(int li, uint64_t ri, int64_t ii, int lj, uint64_t rj,
+                                         int64_t ij) {
+    if (li != lj) return li < lj;
+    if (ri != rj) return ri < rj;
+    return ii < ij;
+}
+
+__global__ void k_pmis_init(int64_t n, const uint16_t* __restrict__ seg,
+                            const uint8_t* __restrict__ part, const int* __restrict__ lam,
+                            int8_t* __restrict__ state) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!part[seg[i]]) state[i] = ST_NP;
+    else state[i] = lam[i] == 0 ? ST_F : ST_U;
+}
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_pmis_compare(int64_t n, const int64_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ col, const uint8_t* __restrict__ sflag,
+                               const int8_t* __restrict__ state, const int* __restrict__ lam,
+                               const uint16_t* __restrict__ seg, const int64_t* __restrict__ off,
+                               int level, uint64_t seed, uint8_t* __restrict__ notmax) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n || state[i] != ST_U) return;
+    const int64_t base = off[seg[i]];
+    const int64_t li = i - base;
+    const uint64_t ri = pmis_rand(seed, level, li);
+    const int lami = lam[i];
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        if (!(sflag[e] & 1)) continue;
+        int64_t j = col[e];
+        if (state[j] != ST_U) continue;
+        int64_t lj = j - base;
+        uint64_t rj = pmis_rand(seed, level, lj);
+        if (key_less(lami, ri, li, lam[j], rj, lj)) notmax[i] = 1;
+        else notmax[j] = 1;
+    }
+}
+
+__global__ void k_pmis_select(int64_t n, int8_t* __restrict__ state,
+                              const uint8_t* __restrict__ notmax) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n && state[i] == ST_U && !notmax[i]) state[i] = ST_C;
+}
+
+__global__ void k_pmis_mark_f(int64_t n, const int64_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ col, const uint8_t* __restrict__ sflag,
+                              int8_t* __restrict__ state, int* __restrict__ undecided) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n || state[i] != ST_U) return;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        if ((sflag[e] & 1) && state[col[e]] == ST_C) {
+            state[i] = ST_F;
+            return;
+        }
+    }
+    atomicAdd(undecided, 1);
+}
+
+// ------------------------------------------------------------- coarse numbering
+__global__ void k_is_c(int64_t n, const int8_t* __restrict__ state, int64_t* __restrict__ flag) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = state[i] == ST_C ? 1 : 0;
+}
+
+__global__ void k_member_counts(int B, const int64_t* __restrict__ off,
+                                const int64_t* __restrict__ cnt, const int64_t* __restrict__ cidx,
+                                int64_t* __restrict__ nc) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    nc[b] = off[b] < 0 ? 0 : cidx[off[b] + cnt[b]] - cidx[off[b]];
+}
+
+__global__ void k_cmap(int64_t n, const uint16_t* __restrict__ seg, const int64_t* __restrict__ off,
+                       const int64_t* __restrict__ newoff, const int64_t* __restrict__ cidx,
+                       const int8_t* __restrict__ state, int32_t* __restrict__ cmap,
+                       int8_t* __restrict__ cf) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = seg[i];
+    int64_t no = newoff[b];
+    if (no < 0) {          // member does not continue: this level is its coarsest
+        cmap[i] = -1;
+        cf[i] = 0;
+        return;
+    }
+    bool c = state[i] == ST_C;
+    cf[i] = c ? 1 : -1;
+    cmap[i] = c ? static_cast<int32_t>(no + cidx[i] - cidx[off[b]]) : -1;
+}
+
+__global__ void k_cf_counts(int64_t n, const int64_t* __restrict__ rowptr,
+                            const int8_t* __restrict__ cf, unsigned long long* __restrict__ out) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n || cf[i] == 0) return;
+    const unsigned long long len = static_cast<unsigned long long>(rowptr[i + 1] - rowptr[i]);
+    const int k = cf[i] < 0 ? 0 : 2;
+    atomicAdd(&out[k], 1ull);
+    atomicAdd(&out[k + 1], len);
+}
+
+__global__ void k_interp(int64_t n, const int64_t* __restrict__ rowptr,
+                         const int32_t* __restrict__ col, const double* __restrict__ val,
+                         const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
+                         const int32_t* __restrict__ cmap, int32_t* __restrict__ p,
+                         int32_t* __restrict__ c2f) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == 0) { p[i] = -1; return; }
+    if (cf[i] > 0) {
+        p[i] = cmap[i];
+        c2f[cmap[i]] = static_cast<int32_t>(i);
+        return;
+    }
+    double best = -1.0;
+    int32_t bj = -1;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        int32_t j = col[e];
+        if ((sflag[e] & 1) && cf[j] > 0) {
+            double a = fabs(val[e]);
+            if (a > best) { best = a; bj = j; }   // sorted columns: first max = smallest column
+        }
+    }
+    p[i] = bj >= 0 ? cmap[bj] : -1;
+}
+
+// ------------------------------------------------------------- lAIR restriction
+__device__ __forceinline__ bool r_candidate(int64_t i, int32_t j, uint8_t f, const int8_t* cf) {
+    return j != i && (f & 2) && cf[j] < 0;
+}
+
+__global__ void k_r_count(int64_t nc, const int32_t* __restrict__ c2f,
+                          const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                          const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
+                          int kmax, int64_t* __restrict__ rcnt) {
+    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int64_t i = c2f[I];
+    int c = 0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+        if (r_candidate(i, col[e], sflag[e], cf)) ++c;
+    rcnt[I] = (c < kmax ? c : kmax) + 1;
+}
+
+constexpr int KCAP = 64;      // largest local system (one wave: lane = row)
+constexpr int KLD = KCAP + 1; // padded LDS stride
+
+// One wave per coarse row.  Local system in LDS, Gaussian elimination with
+// partial pivoting (lane r owns row r), back substitution with wave sums.
+__global__ void __launch_bounds__(64)
+k_r_build(int64_t nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+          const int32_t* __restrict__ col, const double* __restrict__ val,
+          const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf, int kmax,
+          const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
+          double* __restrict__ r_val, int* __restrict__ singular) {
+    __shared__ double Mloc[KCAP * KLD];
+    __shared__ double rhs[KCAP];
+    __shared__ double z[KCAP];
+    __shared__ int cols[KCAP];
+    const int lane = threadIdx.x;
+    for (int64_t I = blockIdx.x; I < nc; I += gridDim.x) {
+        const int64_t i = c2f[I];
+        const int64_t rs = rowptr[i], re = rowptr[i + 1];
+        // count candidates
+        int cnt = 0;
+        for (int64_t e0 = rs; e0 < re; e0 += 64) {
+            int64_t e = e0 + lane;
+            bool cand = e < re && r_candidate(i, col[e], sflag[e], cf);
+            cnt += __popcll(__ballot(cand));
+        }
+        const int K = cnt < kmax ? cnt : kmax;
+        // collect (in column order); when there are more than kmax candidates keep
+        // those whose rank by (|a| desc, column asc) is below kmax
+        int filled = 0;
+        for (int64_t e0 = rs; e0 < re; e0 += 64) {
+            int64_t e = e0 + lane;
+            bool keep = false;
+            int32_t cj = -1;
+            if (e < re) {
+                cj = col[e];
+                keep = r_candidate(i, cj, sflag[e], cf);
+                if (keep && cnt > kmax) {
+                    double a = fabs(val[e]);
+                    int rank = 0;
+                    for (int64_t g = rs; g < re; ++g) {
+                        if (g == e || !r_candidate(i, col[g], sflag[g], cf)) continue;
+                        double b = fabs(val[g]);
+                        if (b > a || (b == a && col[g] < cj)) ++rank;
+                    }
+                    keep = rank < kmax;
+                }
+            }
+            uint64_t m = __ballot(keep);
+            int pos = filled + __popcll(m & ((1ull << lane) - 1ull));
+            if (keep) cols[pos] = cj;
+            filled += __popcll(m);
+        }
+        __syncthreads();
+        // local matrix Mloc[r][c] = A(cols[c], cols[r]); rhs[r] = -A(i, cols[r])
+        for (int r = 0; r < K; ++r) Mloc[r * KLD + lane] = 0.0;
+        if (lane < K) rhs[lane] = 0.0;
+        __syncthreads();
+        for (int c = 0; c < K; ++c) {
+            const int64_t jc = cols[c];
+            for (int64_t e = rowptr[jc] + lane; e < rowptr[jc + 1]; e += 64) {
+                int32_t cc = col[e];
+                int lo = 0, hi = K - 1;
+                while (lo <= hi) {
+                    int mid = (lo + hi) >> 1;
+                    int v = cols[mid];
+                    if (v == cc) { Mloc[mid * KLD + c] = val[e]; break; }
+                    if (v < cc) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+        }
+        for (int64_t e = rs + lane; e < re; e += 64) {
+            int32_t cc = col[e];
+            int lo = 0, hi = K - 1;
+            while (lo <= hi) {
+                int mid = (lo + hi) >> 1;
+                int v = cols[mid];
+                if (v == cc) { rhs[mid] = -val[e]; break; }
+                if (v < cc) lo = mid + 1; else hi = mid - 1;
+            }
+        }
+        __syncthreads();
+        bool sing = false;
+        for (int p = 0; p < K; ++p) {
+            double v = (lane >= p && lane < K) ? fabs(Mloc[lane * KLD + p]) : -1.0;
+            int idx = lane;
+            for (int d = 32; d >= 1; d >>= 1) {
+                double ov = __shfl_xor(v, d, 64);
+                int oi = __shfl_xor(idx, d, 64);
+                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+            }
+            const int piv = idx;
+            if (!(v > 0.0)) { sing = true; break; }
+            if (piv != p) {
+                if (lane < K) {
+                    double t = Mloc[p * KLD + lane];
+                    Mloc[p * KLD + lane] = Mloc[piv * KLD + lane];
+                    Mloc[piv * KLD + lane] = t;
+                }
+                if (lane == 0) { double t = rhs[p]; rhs[p] = rhs[piv]; rhs[piv] = t; }
+            }
+            __syncthreads();
+            if (lane > p && lane < K) {
+                double l = Mloc[lane * KLD + p] / Mloc[p * KLD + p];
+                for (int c = p + 1; c < K; ++c) Mloc[lane * KLD + c] -= l * Mloc[p * KLD + c];
+                rhs[lane] -= l * rhs[p];
+            }
+            __syncthreads();
+        }
+        if (sing) {
+            if (lane == 0) atomicAdd(singular, 1);
+            if (lane < K) z[lane] = 0.0;
+        } else {
+            for (int r = K - 1; r >= 0; --r) {
+                double s = (lane > r && lane < K) ? Mloc[r * KLD + lane] * z[lane] : 0.0;
+                s = group_sum<64>(s);
+                if (lane == 0) z[r] = (rhs[r] - s) / Mloc[r * KLD + r];
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        const int64_t base = r_rowptr[I];
+        int before = 0;   // how many kept columns are < i
+        {
+            bool lt = lane < K && cols[lane] < i;
+            before = __popcll(__ballot(lt));
+        }
+        if (lane < K) {
+            int pos = lane + (cols[lane] > i ? 1 : 0);
+            r_col[base + pos] = cols[lane];
+            r_val[base + pos] = z[lane];
+        }
+        if (lane == 0) {
+            r_col[base + before] = static_cast<int32_t>(i);
+            r_val[base + before] = 1.0;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- R A P
+__global__ void k_rap_ub(int64_t nc, const int64_t* __restrict__ r_rowptr,
+                         const int32_t* __restrict__ r_col, const int64_t* __restrict__ rowptr,
+                         int64_t* __restrict__ ub) {
+    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int64_t s = 0;
+    for (int64_t e = r_rowptr[I]; e < r_rowptr[I + 1]; ++e) {
+        int64_t k = r_col[e];
+        s += rowptr[k + 1] - rowptr[k];
+    }
+    ub[I] = s;
+}
+
+__global__ void k_class_rows(int64_t nc, const int64_t* __restrict__ ub, int64_t lo, int64_t hi,
+                             int32_t* __restrict__ list, int* __restrict__ count) {
+    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int64_t u = ub[I];
+    if (u > lo && u <= hi) {
+        int pos = atomicAdd(count, 1);
+        list[pos] = static_cast<int32_t>(I);
+    }
+}
+
+// Products of one coarse row, sorted and reduced.  `key`/`pv` are scratch of
+// `cap` entries (a power of two >= the row's product count) in LDS or global
+// memory; NT threads cooperate.  SYMBOLIC: returns the number of distinct
+// columns (valid in thread 0).  NUMERIC: writes the row at out_col/out_val.
+constexpr int RMAX = KCAP + 1;   // longest R row (kmax + 1)
+
+template <int NT, bool NUMERIC>
+__device__ int rap_row(int64_t I, uint64_t* key, double* pv, int cap,
+                       const int64_t* __restrict__ r_rowptr, const int32_t* __restrict__ r_col,
+                       const double* __restrict__ r_val, const int64_t* __restrict__ rowptr,
+                       const int32_t* __restrict__ col, const double* __restrict__ val,
+                       const int32_t* __restrict__ p, int32_t* __restrict__ out_col,
+                       double* __restrict__ out_val, int64_t* s_pref, int64_t* s_abase,
+                       double* s_rv, int* s_red) {
+    const int tid = threadIdx.x;
+    const int64_t rs = r_rowptr[I];
+    const int rl = static_cast<int>(r_rowptr[I + 1] - rs);
+    for (int t = tid; t < rl; t += NT) {
+        int64_t k = r_col[rs + t];
+        s_abase[t] = rowptr[k];
+        s_pref[t + 1] = rowptr[k + 1] - rowptr[k];
+        s_rv[t] = r_val[rs + t];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_pref[0] = 0;
+        for (int t = 0; t < rl; ++t) s_pref[t + 1] += s_pref[t];
+    }
+    __syncthreads();
+    const int64_t total = s_pref[rl];
+    for (int q = tid; q < cap; q += NT) {
+        uint64_t kq = KEY_NONE;
+        if (q < total) {
+            int lo = 0, hi = rl - 1;   // last t with s_pref[t] <= q
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            int64_t e = s_abase[lo] + (q - s_pref[lo]);
+            int32_t c = p[col[e]];
+            if (c >= 0) {
+                kq = (static_cast<uint64_t>(static_cast<uint32_t>(c)) << 32) | static_cast<uint32_t>(q);
+                if (NUMERIC) pv[q] = s_rv[lo] * val[e];
+            }
+        }
+        key[q] = kq;
+    }
+    __syncthreads();
+    // bitonic sort (ascending)
+    for (int k = 2; k <= cap; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < cap; i += NT) {
+                int l = i ^ j;
+                if (l > i) {
+                    uint64_t a = key[i], b = key[l];
+                    bool up = (i & k) == 0;
+                    if ((a > b) == up) { key[i] = b; key[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // leaders: first entry of each distinct column
+    int nlead = 0;
+    int64_t out_base = 0;
+    for (int q0 = 0; q0 < cap; q0 += NT) {
+        int q = q0 + tid;
+        bool lead = false;
+        if (q < cap) {
+            uint64_t a = key[q];
+            lead = a != KEY_NONE && (q == 0 || (key[q - 1] >> 32) != (a >> 32));
+        }
+        // block-wide exclusive count of leaders (per-wave ballot + LDS)
+        uint64_t m = __ballot(lead);
+        int wid = tid >> 6, lane = tid & 63;
+        if (lane == 0) s_red[wid] = __popcll(m);
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            if (w < wid) before += s_red[w];
+            tot += s_red[w];
+        }
+        before += __popcll(m & ((1ull << lane) - 1ull));
+        if (NUMERIC && lead) {
+            uint64_t a = key[q];
+            uint32_t c = static_cast<uint32_t>(a >> 32);
+            double s = 0.0;
+            for (int t = q; t < cap && key[t] != KEY_NONE && static_cast<uint32_t>(key[t] >> 32) == c; ++t)
+                s += pv[static_cast<uint32_t>(key[t])];
+            out_col[out_base + nlead + before] = static_cast<int32_t>(c);
+            out_val[out_base + nlead + before] = s;
+        }
+        nlead += tot;
+        __syncthreads();
+    }
+    return nlead;
+}
+
+template <int NT, int CAP, bool NUMERIC>
+__global__ void __launch_bounds__(NT)
+k_rap_lds(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ r_rowptr,
+          const int32_t* __restrict__ r_col, const double* __restrict__ r_val,
+          const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+          const double* __restrict__ val, const int32_t* __restrict__ p,
+          const int64_t* __restrict__ ub, int64_t* __restrict__ cnt_out,
+          const int64_t* __restrict__ c_rowptr, int32_t* __restrict__ c_col,
+          double* __restrict__ c_val) {
+    __shared__ uint64_t key[CAP];
+    __shared__ double pv[NUMERIC ? CAP : 1];
+    __shared__ int64_t s_pref[RMAX + 1], s_abase[RMAX];
+    __shared__ double s_rv[RMAX];
+    __shared__ int s_red[NT / 64];
+    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+        int64_t I = list[r];
+        int cap = 1;
+        while (cap < ub[I]) cap <<= 1;
+        int nl = rap_row<NT, NUMERIC>(I, key, pv, cap, r_rowptr, r_col, r_val, rowptr, col, val, p,
+                                      NUMERIC ? c_col + c_rowptr[I] : nullptr,
+                                      NUMERIC ? c_val + c_rowptr[I] : nullptr, s_pref, s_abase,
+                                      s_rv, s_red);
+        if (!NUMERIC && threadIdx.x == 0) cnt_out[I] = nl;
+        __syncthreads();
+    }
+}
+
+// Rows with more products than fit in LDS: same algorithm on global scratch.
+template <bool NUMERIC>
+__global__ void __launch_bounds__(256)
+k_rap_global(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ scratch_off,
+             uint64_t* __restrict__ kscr, double* __restrict__ vscr,
+             const int64_t* __restrict__ r_rowptr, const int32_t* __restrict__ r_col,
+             const double* __restrict__ r_val, const int64_t* __restrict__ rowptr,
+             const int32_t* __restrict__ col, const double* __restrict__ val,
+             const int32_t* __restrict__ p, const int64_t* __restrict__ ub,
+             int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
+             int32_t* __restrict__ c_col, double* __restrict__ c_val) {
+    __shared__ int64_t s_pref[RMAX + 1], s_abase[RMAX];
+    __shared__ double s_rv[RMAX];
+    __shared__ int s_red[4];
+    int r = blockIdx.x;
+    if (r >= nrows) return;
+    int64_t I = list[r];
+    int cap = 1;
+    while (cap < ub[I]) cap <<= 1;
+    uint64_t* key = kscr + scratch_off[r];
+    double* pv = vscr + scratch_off[r];
+    int nl = rap_row<256, NUMERIC>(I, key, pv, cap, r_rowptr, r_col, r_val, rowptr, col, val, p,
+                                   NUMERIC ? c_col + c_rowptr[I] : nullptr,
+                                   NUMERIC ? c_val + c_rowptr[I] : nullptr, s_pref, s_abase, s_rv,
+                                   s_red);
+    if (!NUMERIC && threadIdx.x == 0) cnt_out[I] = nl;
+}
+
+// ------------------------------------------------------------- coarse dense inverse
+__global__ void k_dense_from_csr(int nmem, const int64_t* __restrict__ moff,
+                                 const int64_t* __restrict__ mn, const int64_t* __restrict__ inv_off,
+                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                 const double* __restrict__ val, double* __restrict__ work) {
+    int m = blockIdx.y;
+    if (m >= nmem) return;
+    const int64_t n = mn[m], o = moff[m];
+    double* W = work + 2 * inv_off[m];   // [n][2n] augmented [A | I]
+    // each block owns whole rows: clear, then scatter the CSR row
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        for (int64_t c = threadIdx.x; c < 2 * n; c += blockDim.x)
+            W[r * 2 * n + c] = (c >= n && c - n == r) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int64_t e = rowptr[o + r] + threadIdx.x; e < rowptr[o + r + 1]; e += blockDim.x) {
+            int64_t c = col[e] - o;
+            W[r * 2 * n + c] = val[e];
+        }
+        __syncthreads();
+    }
+}
+
+// Gauss-Jordan with partial pivoting, one block per member; the inverse is
+// written column-major (inv[c * n + r]) so the per-cycle product reads it coalesced.
+__global__ void __launch_bounds__(256)
+k_gauss_jordan(int nmem, const int64_t* __restrict__ mn, const int64_t* __restrict__ inv_off,
+               double* __restrict__ work, double* __restrict__ inv, int* __restrict__ singular) {
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    __shared__ double prow_scale;
+    __shared__ int s_piv;
+    int m = blockIdx.x;
+    if (m >= nmem) return;
+    const int64_t n = mn[m];
+    const int64_t w2 = 2 * n;
+    double* W = work + 2 * inv_off[m];
+    const int tid = threadIdx.x;
+    for (int64_t p = 0; p < n; ++p) {
+        double best = -1.0;
+        int bi = -1;
+        for (int64_t r = p + tid; r < n; r += 256) {
+            double v = fabs(W[r * w2 + p]);
+            if (v > best) { best = v; bi = static_cast<int>(r); }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) {
+                double ov = sv[tid + s];
+                int oi = si[tid + s];
+                if (ov > sv[tid] || (ov == sv[tid] && oi >= 0 && (si[tid] < 0 || oi < si[tid]))) {
+                    sv[tid] = ov;
+                    si[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            s_piv = si[0];
+            if (!(sv[0] > 0.0)) { atomicAdd(singular, 1); s_piv = -1; }
+        }
+        __syncthreads();
+        const int piv = s_piv;
+        if (piv < 0) return;
+        if (piv != p) {
+            for (int64_t c = tid; c < w2; c += 256) {
+                double t = W[p * w2 + c];
+                W[p * w2 + c] = W[piv * w2 + c];
+                W[piv * w2 + c] = t;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) prow_scale = 1.0 / W[p * w2 + p];
+        __syncthreads();
+        for (int64_t c = tid; c < w2; c += 256) W[p * w2 + c] *= prow_scale;
+        __syncthreads();
+        for (int64_t idx = tid; idx < n * w2; idx += 256) {
+            int64_t r = idx / w2, c = idx % w2;
+            if (r == p || c == p) continue;
+            double f = W[r * w2 + p];
+            if (f != 0.0) W[idx] -= f * W[p * w2 + c];
+        }
+        __syncthreads();
+        for (int64_t r = tid; r < n; r += 256)
+            if (r != p) W[r * w2 + p] = 0.0;
+        __syncthreads();
+    }
+    double* Inv = inv + inv_off[m];
+    for (int64_t idx = tid; idx < n * n; idx += 256) {
+        int64_t r = idx / n, c = idx % n;
+        Inv[c * n + r] = W[r * w2 + n + c];
+    }
+}
+
+}  // namespace
+
+// ========================================================================== host
+
+void Hierarchy::build_level_aux(Level& L, int l) {
+    const int64_t n = L.A.n;
+    L.dinv.alloc(n);
+    L.seg.alloc(n);
+    fill_segments(L.seg.p, n, L.off, L.cnt, s_);
+    L.x.alloc(n);
+    L.t.alloc(n);
+    L.b.alloc(n);
+    L.r.alloc(n);
+    L.lpr = prm_.lpr_a[l < 3 ? l : 3];
+    L.lpr_r = prm_.lpr_r;
+}
+
+void Hierarchy::coarse_setup(Level& L, const std::vector<int>& members) {
+    L.coarse_members = members;
+    const int nm = static_cast<int>(members.size());
+    if (nm == 0) return;
+    std::vector<int64_t> moff(nm), mn(nm), ioff(nm + 1, 0);
+    for (int k = 0; k < nm; ++k) {
+        int b = members[k];
+        moff[k] = L.off[b];
+        mn[k] = L.cnt[b];
+        PAIR_CHECK(mn[k] <= prm_.max_dense,
+                   "coarsest level of a member has " + std::to_string(mn[k]) +
+                       " rows, more than the dense limit " + std::to_string(prm_.max_dense) +
+                       " (coarsening stalled)");
+        ioff[k + 1] = ioff[k] + mn[k] * mn[k];
+    }
+    L.coarse_member_d.alloc(nm);
+    L.coarse_off_d.alloc(nm);
+    L.coarse_n_d.alloc(nm);
+    L.coarse_inv_off_d.alloc(nm + 1);
+    h2d(L.coarse_member_d.p, members.data(), nm, s_);
+    h2d(L.coarse_off_d.p, moff.data(), nm, s_);
+    h2d(L.coarse_n_d.p, mn.data(), nm, s_);
+    h2d(L.coarse_inv_off_d.p, ioff.data(), nm + 1, s_);
+    L.coarse_inv.alloc(ioff[nm]);
+    DBuf<double> work(2 * ioff[nm]);
+    DBuf<int> sing(1);
+    PAIR_HIP(hipMemsetAsync(sing.p, 0, sizeof(int), s_));
+    int64_t maxn = *std::max_element(mn.begin(), mn.end());
+    hipLaunchKernelGGL(k_dense_from_csr, dim3(grid_for(maxn, 1), nm), dim3(256), 0, s_, nm,
+                       L.coarse_off_d.p, L.coarse_n_d.p, L.coarse_inv_off_d.p, L.A.rowptr.p,
+                       L.A.col.p, L.A.val.p, work.p);
+    PAIR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(nm), dim3(256), 0, s_, nm, L.coarse_n_d.p,
+                       L.coarse_inv_off_d.p, work.p, L.coarse_inv.p, sing.p);
+    PAIR_LAUNCH_CHECK();
+    int hs = 0;
+    d2h(&hs, sing.p, 1, s_);
+    PAIR_HIP(hipStreamSynchronize(s_));
+    PAIR_CHECK(hs == 0, "singular coarsest-level matrix");
+}
+
+void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vector<int64_t>& cnt0) {
+    B_ = static_cast<int>(off0.size());
+    PAIR_CHECK(B_ >= 1 && B_ <= 65535, "member count out of range");
+    PAIR_CHECK(prm_.kmax >= 1 && prm_.kmax <= KCAP, "kmax must be in [1, 64]");
+    levels_.clear();
+    nlev_.assign(B_, 0);
+    if (graph_exec_) { (void)hipGraphExecDestroy(graph_exec_); graph_exec_ = nullptr; }
+    if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
+
+    levels_.emplace_back();
+    levels_[0].A = std::move(A0);
+    levels_[0].off = off0;
+    levels_[0].cnt = cnt0;
+
+    DBuf<int64_t> d_off(B_), d_cnt(B_), d_newoff(B_), d_nc(B_);
+    DBuf<uint8_t> d_part(B_);
+    DBuf<int> d_counter(1);
+
+    for (int l = 0;; ++l) {
+        Level& L = levels_[l];
+        build_level_aux(L, l);
+        const int64_t n = L.A.n;
+        DBuf<double> rowmax(n);
+        hipLaunchKernelGGL(k_diag_rowmax, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
+                           L.A.rowptr.p, L.A.col.p, L.A.val.p, L.dinv.p, rowmax.p);
+        PAIR_LAUNCH_CHECK();
+
+        // members that coarsen further
+        std::vector<uint8_t> part(B_, 0);
+        bool any = false;
+        for (int b = 0; b < B_; ++b) {
+            if (L.off[b] < 0) continue;
+            bool stop = L.cnt[b] <= prm_.coarse_max || l + 1 >= prm_.max_levels;
+            part[b] = stop ? 0 : 1;
+            any = any || !stop;
+        }
+        L.relax_h.assign(B_, 0);
+        L.cf.alloc(n);
+        L.p.alloc(n);
+        if (!any) {
+            std::vector<int> cm;
+            for (int b = 0; b < B_; ++b)
+                if (L.off[b] >= 0) { cm.push_back(b); nlev_[b] = l + 1; }
+            PAIR_HIP(hipMemsetAsync(L.cf.p, 0, n, s_));
+            PAIR_HIP(hipMemsetAsync(L.p.p, 0xff, n * sizeof(int32_t), s_));
+            L.relax.alloc(B_);
+            h2d(L.relax.p, L.relax_h.data(), B_, s_);
+            coarse_setup(L, cm);
+            break;
+        }
+        h2d(d_part.p, part.data(), B_, s_);
+        h2d(d_off.p, L.off.data(), B_, s_);
+        h2d(d_cnt.p, L.cnt.data(), B_, s_);
+
+        // strength + lambda
+        DBuf<uint8_t> sflag(L.A.nnz);
+        DBuf<int> lam(n);
+        PAIR_HIP(hipMemsetAsync(lam.p, 0, n * sizeof(int), s_));
+        hipLaunchKernelGGL(k_strength, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
+                           L.A.col.p, L.A.val.p, rowmax.p, L.seg.p, d_part.p, prm_.theta,
+                           prm_.eps_r, sflag.p, lam.p);
+        PAIR_LAUNCH_CHECK();
+
+        // PMIS
+        DBuf<int8_t> state(n);
+        DBuf<uint8_t> notmax(n);
+        hipLaunchKernelGGL(k_pmis_init, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.seg.p,
+                           d_part.p, lam.p, state.p);
+        PAIR_LAUNCH_CHECK();
+        for (int round = 0;; ++round) {
+            PAIR_CHECK(round < 100000, "PMIS did not terminate");
+            hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, s_, notmax.p, n,
+                               static_cast<uint8_t>(0));
+            hipLaunchKernelGGL(k_pmis_compare, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
+                               L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p, L.seg.p, d_off.p,
+                               l, prm_.seed, notmax.p);
+            hipLaunchKernelGGL(k_pmis_select, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
+                               state.p, notmax.p);
+            PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
+            hipLaunchKernelGGL(k_pmis_mark_f, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
+                               L.A.rowptr.p, L.A.col.p, sflag.p, state.p, d_counter.p);
+            PAIR_LAUNCH_CHECK();
+            int und = 0;
+            d2h(&und, d_counter.p, 1, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            if (und == 0) break;
+        }
+
+        // coarse numbering and the members that continue
+        DBuf<int64_t> isc(n), cidx(n + 1);
+        hipLaunchKernelGGL(k_is_c, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, state.p, isc.p);
+        PAIR_LAUNCH_CHECK();
+        exclusive_scan(isc.p, cidx.p, n, s_);
+        hipLaunchKernelGGL(k_member_counts, dim3(grid_for(B_, 64)), dim3(64), 0, s_, B_, d_off.p,
+                           d_cnt.p, cidx.p, d_nc.p);
+        PAIR_LAUNCH_CHECK();
+        std::vector<int64_t> nc(B_);
+        d2h(nc.data(), d_nc.p, B_, s_);
+        PAIR_HIP(hipStreamSynchronize(s_));
+        std::vector<int64_t> newoff(B_, -1), newcnt(B_, 0);
+        int64_t total_c = 0;
+        std::vector<int> coarse_here;
+        for (int b = 0; b < B_; ++b) {
+            if (L.off[b] < 0) continue;
+            bool cont = part[b] && nc[b] > 0 &&
+                        static_cast<double>(nc[b]) <= prm_.max_coarse_ratio * static_cast<double>(L.cnt[b]);
+            if (cont) {
+                newoff[b] = total_c;
+                newcnt[b] = nc[b];
+                total_c += nc[b];
+                L.relax_h[b] = 1;
+            } else {
+                coarse_here.push_back(b);
+                nlev_[b] = l + 1;
+            }
+        }
+        L.relax.alloc(B_);
+        h2d(L.relax.p, L.relax_h.data(), B_, s_);
+        h2d(d_newoff.p, newoff.data(), B_, s_);
+        DBuf<int32_t> cmap(n);
+        hipLaunchKernelGGL(k_cmap, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.seg.p, d_off.p,
+                           d_newoff.p, cidx.p, state.p, cmap.p, L.cf.p);
+        PAIR_LAUNCH_CHECK();
+        if (total_c == 0) {
+            PAIR_HIP(hipMemsetAsync(L.p.p, 0xff, n * sizeof(int32_t), s_));
+            coarse_setup(L, coarse_here);
+            break;
+        }
+        PAIR_CHECK(total_c < (int64_t(1) << 31), "coarse level too large for int32 indices");
+
+        {
+            DBuf<unsigned long long> cc(4);
+            PAIR_HIP(hipMemsetAsync(cc.p, 0, 4 * sizeof(unsigned long long), s_));
+            hipLaunchKernelGGL(k_cf_counts, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
+                               L.A.rowptr.p, L.cf.p, cc.p);
+            PAIR_LAUNCH_CHECK();
+            unsigned long long h[4];
+            d2h(h, cc.p, 4, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            L.n_f = static_cast<int64_t>(h[0]);
+            L.nnz_f = static_cast<int64_t>(h[1]);
+            L.n_c = static_cast<int64_t>(h[2]);
+            L.nnz_c = static_cast<int64_t>(h[3]);
+        }
+        // interpolation and coarse-to-fine map
+        DBuf<int32_t> c2f(total_c);
+        hipLaunchKernelGGL(k_interp, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
+                           L.A.col.p, L.A.val.p, sflag.p, L.cf.p, cmap.p, L.p.p, c2f.p);
+        PAIR_LAUNCH_CHECK();
+
+        // restriction
+        DBuf<int64_t> rcnt(total_c);
+        hipLaunchKernelGGL(k_r_count, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
+                           c2f.p, L.A.rowptr.p, L.A.col.p, sflag.p, L.cf.p, prm_.kmax, rcnt.p);
+        PAIR_LAUNCH_CHECK();
+        L.R.n = total_c;
+        L.R.ncols = n;
+        L.R.rowptr.alloc(total_c + 1);
+        L.R.nnz = exclusive_scan(rcnt.p, L.R.rowptr.p, total_c, s_);
+        L.R.col.alloc(L.R.nnz);
+        L.R.val.alloc(L.R.nnz);
+        PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
+        {
+            unsigned g = static_cast<unsigned>(std::min<int64_t>(total_c, 1 << 20));
+            hipLaunchKernelGGL(k_r_build, dim3(g), dim3(64), 0, s_, total_c, c2f.p, L.A.rowptr.p,
+                               L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, L.R.rowptr.p,
+                               L.R.col.p, L.R.val.p, d_counter.p);
+            PAIR_LAUNCH_CHECK();
+        }
+        int nsing = 0;
+        d2h(&nsing, d_counter.p, 1, s_);
+
+        // Galerkin product
+        DBuf<int64_t> ub(total_c), ccnt(total_c);
+        hipLaunchKernelGGL(k_rap_ub, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
+                           L.R.rowptr.p, L.R.col.p, L.A.rowptr.p, ub.p);
+        PAIR_LAUNCH_CHECK();
+        struct Cls { int64_t lo, hi; };
+        const Cls classes[3] = {{-1, 256}, {256, 2048}, {2048, int64_t(1) << 40}};
+        DBuf<int32_t> lists[3];
+        int lcount[3] = {0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+            lists[c].alloc(total_c);
+            PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
+            hipLaunchKernelGGL(k_class_rows, dim3(grid_for(total_c, 256)), dim3(256), 0, s_,
+                               total_c, ub.p, classes[c].lo, classes[c].hi, lists[c].p,
+                               d_counter.p);
+            PAIR_LAUNCH_CHECK();
+            d2h(&lcount[c], d_counter.p, 1, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+        }
+        // scratch for the global class
+        std::vector<int64_t> gscr_off_h;
+        DBuf<int64_t> gscr_off;
+        DBuf<uint64_t> gkeys;
+        DBuf<double> gvals;
+        if (lcount[2] > 0) {
+            std::vector<int32_t> rows(lcount[2]);
+            d2h(rows.data(), lists[2].p, lcount[2], s_);
+            std::vector<int64_t> ubh(total_c);
+            d2h(ubh.data(), ub.p, total_c, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            gscr_off_h.resize(lcount[2] + 1, 0);
+            for (int k = 0; k < lcount[2]; ++k) {
+                int64_t cap = 1;
+                while (cap < ubh[rows[k]]) cap <<= 1;
+                gscr_off_h[k + 1] = gscr_off_h[k] + cap;
+            }
+            gscr_off.alloc(lcount[2] + 1);
+            h2d(gscr_off.p, gscr_off_h.data(), lcount[2] + 1, s_);
+            gkeys.alloc(gscr_off_h.back());
+            gvals.alloc(gscr_off_h.back());
+        }
+        auto run_rap = [&](bool numeric, Csr* C) {
+            int64_t* cnt_out = ccnt.p;
+            const int64_t* crp = numeric ? C->rowptr.p : nullptr;
+            int32_t* ccol = numeric ? C->col.p : nullptr;
+            double* cval = numeric ? C->val.p : nullptr;
+            if (lcount[0] > 0) {
+                unsigned g = static_cast<unsigned>(std::min(lcount[0], 1 << 20));
+                if (numeric)
+                    hipLaunchKernelGGL((k_rap_lds<64, 256, true>), dim3(g), dim3(64), 0, s_,
+                                       lcount[0], lists[0].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
+                                       crp, ccol, cval);
+                else
+                    hipLaunchKernelGGL((k_rap_lds<64, 256, false>), dim3(g), dim3(64), 0, s_,
+                                       lcount[0], lists[0].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
+                                       crp, ccol, cval);
+                PAIR_LAUNCH_CHECK();
+            }
+            if (lcount[1] > 0) {
+                unsigned g = static_cast<unsigned>(std::min(lcount[1], 1 << 20));
+                if (numeric)
+                    hipLaunchKernelGGL((k_rap_lds<256, 2048, true>), dim3(g), dim3(256), 0, s_,
+                                       lcount[1], lists[1].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
+                                       crp, ccol, cval);
+                else
+                    hipLaunchKernelGGL((k_rap_lds<256, 2048, false>), dim3(g), dim3(256), 0, s_,
+                                       lcount[1], lists[1].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
+                                       crp, ccol, cval);
+                PAIR_LAUNCH_CHECK();
+            }
+            if (lcount[2] > 0) {
+                if (numeric)
+                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[2]), dim3(256), 0, s_,
+                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gvals.p,
+                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p, L.A.col.p,
+                                       L.A.val.p, L.p.p, ub.p, cnt_out, crp, ccol, cval);
+                else
+                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[2]), dim3(256), 0, s_,
+                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gvals.p,
+                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p, L.A.col.p,
+                                       L.A.val.p, L.p.p, ub.p, cnt_out, crp, ccol, cval);
+                PAIR_LAUNCH_CHECK();
+            }
+        };
+        run_rap(false, nullptr);
+        Csr C;
+        C.n = total_c;
+        C.ncols = total_c;
+        C.rowptr.alloc(total_c + 1);
+        C.nnz = exclusive_scan(ccnt.p, C.rowptr.p, total_c, s_);
+        C.col.alloc(C.nnz);
+        C.val.alloc(C.nnz);
+        run_rap(true, &C);
+        PAIR_HIP(hipStreamSynchronize(s_));
+        PAIR_CHECK(nsing == 0, "singular local lAIR system in " + std::to_string(nsing) + " rows");
+
+        coarse_setup(L, coarse_here);
+
+        Level next;
+        next.A = std::move(C);
+        next.off = newoff;
+        next.cnt = newcnt;
+        levels_.push_back(std::move(next));
+    }
+    // solve buffers
+    sb_.bnorm2.alloc(B_);
+    sb_.rnorm2.alloc(B_);
+    sb_.relres.alloc(B_);
+    sb_.relres0.alloc(B_);
+    sb_.iters.alloc(B_);
+    sb_.active.alloc(B_);
+    sb_.n_active.alloc(1);
+    int64_t maxcnt = 1;
+    for (int b = 0; b < B_; ++b) maxcnt = std::max(maxcnt, levels_[0].cnt[b]);
+    sb_.chunks = static_cast<int>((maxcnt + 2047) / 2048);
+    sb_.partial.alloc(static_cast<size_t>(sb_.chunks) * B_);
+    PAIR_HIP(hipStreamSynchronize(s_));
+}
+
+Hierarchy::~Hierarchy() {
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+}
+
+}  // namespace pair

@@ -1,0 +1,464 @@
+// AIR V(1,1) cycles with FC-Jacobi relaxation on all members of a hierarchy.
+//
+// Per level (Sec. "Use of Algebraic Multigrid": F-relaxation complements the
+// coarse-grid correction of AIR; pointwise Jacobi relaxation, Sec. "pAIR
+// Performance for Transport"):
+//   pre:  Jacobi over F-points, then over C-points   (x_i += w (b_i - (Ax)_i)/a_ii)
+//   r = b - A x;   b_c = R r;   recurse (dense inverse on a member's coarsest level)
+//   x += P x_c  (one-point interpolation by value)
+//   post: Jacobi over F-points, then over C-points
+// Every kernel covers all members present on a level in one launch; rows of
+// members that have converged (active = 0) or whose coarsest level this is
+// (relax = 0) are skipped.  Convergence is tested on |b - A x| / |b| of the
+// finest level after each cycle with fixed-order (reproducible) reductions.
+#include <cmath>
+
+#include "amg.h"
+#include "kernels_common.h"
+#include "profile.h"
+
+namespace pair {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 2048;   // rows per partial sum of the norm kernels
+
+template <int LPR>
+__global__ void __launch_bounds__(kBlock)
+k_relax(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+        const double* __restrict__ val, const double* __restrict__ dinv,
+        const int8_t* __restrict__ cf, int8_t which, const uint16_t* __restrict__ seg,
+        const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
+        const double* __restrict__ b, const double* __restrict__ xin, double* __restrict__ xout,
+        double omega, int xin_zero) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * (kBlock / LPR) + threadIdx.x / LPR;
+    const int sub = threadIdx.x % LPR;
+    if (row >= n) return;
+    const int m = seg[row];
+    if (!(active[m] && relax[m])) return;
+    const double xi = xin_zero ? 0.0 : xin[row];
+    if (cf[row] != which) {
+        if (sub == 0) xout[row] = xi;
+        return;
+    }
+    double s = 0.0;
+    if (!xin_zero) {
+        for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR) s += val[e] * xin[col[e]];
+        s = group_sum<LPR>(s);
+    }
+    if (sub == 0) xout[row] = xi + omega * (b[row] - s) * dinv[row];
+}
+
+template <int LPR>
+__global__ void __launch_bounds__(kBlock)
+k_residual(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+           const double* __restrict__ val, const uint16_t* __restrict__ seg,
+           const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
+           const double* __restrict__ b, const double* __restrict__ x, double* __restrict__ r) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * (kBlock / LPR) + threadIdx.x / LPR;
+    const int sub = threadIdx.x % LPR;
+    if (row >= n) return;
+    const int m = seg[row];
+    if (!(active[m] && relax[m])) return;
+    double s = 0.0;
+    for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR) s += val[e] * x[col[e]];
+    s = group_sum<LPR>(s);
+    if (sub == 0) r[row] = b[row] - s;
+}
+
+// b_c = R r over the rows of the next level (one row per coarse point).
+template <int LPR>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(int64_t nc, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+           const double* __restrict__ val, const uint16_t* __restrict__ seg_c,
+           const uint8_t* __restrict__ active, const double* __restrict__ r,
+           double* __restrict__ bc) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * (kBlock / LPR) + threadIdx.x / LPR;
+    const int sub = threadIdx.x % LPR;
+    if (row >= nc) return;
+    if (!active[seg_c[row]]) return;
+    double s = 0.0;
+    for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR) s += val[e] * r[col[e]];
+    s = group_sum<LPR>(s);
+    if (sub == 0) bc[row] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_interpolate(int64_t n, const int32_t* __restrict__ p, const uint16_t* __restrict__ seg,
+              const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
+              const double* __restrict__ xc, double* __restrict__ x) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
+    if (row >= n) return;
+    const int m = seg[row];
+    if (!(active[m] && relax[m])) return;
+    const int32_t c = p[row];
+    if (c >= 0) x[row] += xc[c];
+}
+
+// x = A^{-1} b on a member's coarsest level (inverse stored column-major).
+__global__ void __launch_bounds__(kBlock)
+k_coarse_solve(int nm, const int* __restrict__ member, const int64_t* __restrict__ moff,
+               const int64_t* __restrict__ mn, const int64_t* __restrict__ inv_off,
+               const double* __restrict__ inv, const uint8_t* __restrict__ active,
+               const double* __restrict__ b, double* __restrict__ x) {
+    __shared__ double sb[2048];
+    const int k = blockIdx.x;
+    if (k >= nm || !active[member[k]]) return;
+    const int64_t n = mn[k], o = moff[k];
+    const double* Inv = inv + inv_off[k];
+    for (int64_t c = threadIdx.x; c < n; c += kBlock) sb[c] = b[o + c];
+    __syncthreads();
+    for (int64_t r = threadIdx.x; r < n; r += kBlock) {
+        double s = 0.0;
+        for (int64_t c = 0; c < n; ++c) s += Inv[c * n + r] * sb[c];
+        x[o + r] = s;
+    }
+}
+
+// Partial sums of squares per (member, chunk of kChunk rows): of b (mode 0) or
+// of the residual b - A x (mode 1).  Fixed reduction order.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock)
+k_norm_partial(int mode, int chunks, const int64_t* __restrict__ moff,
+               const int64_t* __restrict__ mcnt, const int64_t* __restrict__ rowptr,
+               const int32_t* __restrict__ col, const double* __restrict__ val,
+               const uint8_t* __restrict__ active, const double* __restrict__ b,
+               const double* __restrict__ x, double* __restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    const int m = blockIdx.y;
+    const int chunk = blockIdx.x;
+    double acc = 0.0;
+    const bool on = moff[m] >= 0 && (mode == 0 || active[m]);
+    if (on) {
+        const int64_t begin = moff[m] + static_cast<int64_t>(chunk) * kChunk;
+        const int64_t end = moff[m] + mcnt[m];
+        const int rows_per_pass = kBlock / LPR;
+        const int sub = threadIdx.x % LPR;
+        for (int64_t row = begin + threadIdx.x / LPR; row < begin + kChunk && row < end;
+             row += rows_per_pass) {
+            double v;
+            if (mode == 0) {
+                v = sub == 0 ? b[row] : 0.0;
+            } else {
+                double s = 0.0;
+                for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR) s += val[e] * x[col[e]];
+                s = group_sum<LPR>(s);
+                v = sub == 0 ? b[row] - s : 0.0;
+            }
+            acc += v * v;
+        }
+    }
+    acc = group_sum<64>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+        partial[static_cast<int64_t>(m) * chunks + chunk] = s;
+    }
+}
+
+// mode 0: |b|^2 and initial state.  mode 1: |r|^2, relative residual, cycle
+// count and the active mask of every member; counts members still active.
+__global__ void k_norm_finalize(int mode, int B, int chunks, const int64_t* __restrict__ moff,
+                                const double* __restrict__ partial, double* __restrict__ bnorm2,
+                                double* __restrict__ rnorm2, double* __restrict__ relres,
+                                double* __restrict__ relres0, int* __restrict__ iters,
+                                uint8_t* __restrict__ active, int* __restrict__ n_active,
+                                double tol, int max_iter, int x_zero) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= B) return;
+    if (moff[m] < 0) {
+        if (mode == 0) { active[m] = 0; iters[m] = 0; relres[m] = 0.0; relres0[m] = 0.0; }
+        return;
+    }
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += partial[static_cast<int64_t>(m) * chunks + c];
+    if (mode == 0) {
+        bnorm2[m] = s;
+        iters[m] = 0;
+        if (x_zero) {
+            // the first residual is b itself; with b = 0, x = 0 is already exact
+            relres[m] = s > 0.0 ? 1.0 : 0.0;
+            relres0[m] = relres[m];
+            active[m] = s > 0.0 ? 1 : 0;
+        } else {
+            relres[m] = 0.0;
+            relres0[m] = 0.0;
+            active[m] = 1;   // mode 2 evaluates the initial guess
+        }
+        return;
+    }
+    if (!active[m]) return;
+    rnorm2[m] = s;
+    const double bb = bnorm2[m];
+    // relative residual; absolute when b = 0 (the solution is then x = 0)
+    const double rel = bb > 0.0 ? sqrt(s / bb) : sqrt(s);
+    if (mode == 2) {   // initial residual of a nonzero guess
+        relres[m] = rel;
+        relres0[m] = rel;
+        active[m] = (rel > tol) ? 1 : 0;
+        if (active[m]) atomicAdd(n_active, 1);
+        return;
+    }
+    relres[m] = rel;
+    iters[m] += 1;
+    const bool bad = !(rel == rel) || isinf(rel);
+    const bool go = !bad && rel > tol && iters[m] < max_iter;
+    active[m] = go ? 1 : 0;
+    if (go) atomicAdd(n_active, 1);
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+template <class F>
+void dispatch_lpr(int lpr, F&& f) {
+    switch (lpr) {
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 2: f(std::integral_constant<int, 2>()); break;
+        case 4: f(std::integral_constant<int, 4>()); break;
+        case 8: f(std::integral_constant<int, 8>()); break;
+        case 16: f(std::integral_constant<int, 16>()); break;
+        case 32: f(std::integral_constant<int, 32>()); break;
+        default: f(std::integral_constant<int, 64>()); break;
+    }
+}
+
+// Algorithmic bytes of one launch, all members of the level counted.
+// Half-sweep over the rows of one class (F: which = -1, C: which = +1): the
+// updated rows' entries and row offsets, b and 1/a_ii of those rows, the
+// gathered x (each entry once), the full output vector, cf and member ids of
+// all rows.  With a zero input vector no matrix entry or x is read.
+double relax_bytes(const Level& L, int which, bool x_zero) {
+    const double n = static_cast<double>(L.n_f + L.n_c);
+    const double nr = static_cast<double>(which < 0 ? L.n_f : L.n_c);
+    const double nnzr = static_cast<double>(which < 0 ? L.nnz_f : L.nnz_c);
+    double b = 16.0 * nr + 8.0 * n + 3.0 * n;
+    if (!x_zero) b += 12.0 * nnzr + 8.0 * nr + 8.0 * n;
+    return b;
+}
+
+double residual_bytes(const Level& L) {
+    const double n = static_cast<double>(L.n_f + L.n_c);
+    const double nnz = static_cast<double>(L.nnz_f + L.nnz_c);
+    return 12.0 * nnz + 8.0 * n /*row offsets*/ + 8.0 * n /*x*/ + 8.0 * n /*b*/ + 8.0 * n /*r*/ + 2.0 * n;
+}
+
+double restrict_bytes(const Level& L) {
+    const double n = static_cast<double>(L.n_f + L.n_c);
+    const double nc = static_cast<double>(L.R.n);
+    return 12.0 * static_cast<double>(L.R.nnz) + 8.0 * nc + 8.0 * n /*r*/ + 8.0 * nc /*b_c*/ + 2.0 * nc;
+}
+
+}  // namespace
+
+void Hierarchy::vcycle_launches(bool x_is_zero) {
+    const int nl = static_cast<int>(levels_.size());
+    const uint8_t* act = sb_.active.p;
+    // down
+    for (int l = 0; l < nl; ++l) {
+        Level& L = levels_[l];
+        const bool has_relax = l + 1 < nl && L.R.n > 0;
+        if (!L.coarse_members.empty()) {
+            hipLaunchKernelGGL(k_coarse_solve, dim3(static_cast<unsigned>(L.coarse_members.size())),
+                               dim3(kBlock), 0, s_, static_cast<int>(L.coarse_members.size()),
+                               L.coarse_member_d.p, L.coarse_off_d.p, L.coarse_n_d.p,
+                               L.coarse_inv_off_d.p, L.coarse_inv.p, act, L.b.p, L.x.p);
+            PAIR_LAUNCH_CHECK();
+        }
+        if (!has_relax) break;
+        const int64_t n = L.A.n;
+        const int xz = (l == 0) ? (x_is_zero ? 1 : 0) : 1;
+        const int kind_relax = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
+        dispatch_lpr(L.lpr, [&](auto lc) {
+            constexpr int LPR = decltype(lc)::value;
+            const unsigned g = grid_xcd(n, kBlock / LPR);
+            int h = prof_begin(s_, kind_relax);
+            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(-1),
+                               L.seg.p, act, L.relax.p, L.b.p, L.x.p, L.t.p, prm_.omega, xz);
+            prof_end(s_, h, relax_bytes(L, -1, xz != 0));
+            h = prof_begin(s_, kind_relax);
+            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(1),
+                               L.seg.p, act, L.relax.p, L.b.p, L.t.p, L.x.p, prm_.omega, 0);
+            prof_end(s_, h, relax_bytes(L, 1, false));
+            h = prof_begin(s_, l == 0 ? PROF_RESIDUAL_FINE : PROF_NKINDS);
+            hipLaunchKernelGGL(k_residual<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                               L.A.col.p, L.A.val.p, L.seg.p, act, L.relax.p, L.b.p, L.x.p, L.r.p);
+            prof_end(s_, h, residual_bytes(L));
+        });
+        PAIR_LAUNCH_CHECK();
+        Level& C = levels_[l + 1];
+        dispatch_lpr(L.lpr_r, [&](auto lc) {
+            constexpr int LPR = decltype(lc)::value;
+            int h = prof_begin(s_, l == 0 ? PROF_RESTRICT_FINE : PROF_NKINDS);
+            hipLaunchKernelGGL(k_restrict<LPR>, dim3(grid_xcd(L.R.n, kBlock / LPR)), dim3(kBlock), 0,
+                               s_, L.R.n, L.R.rowptr.p, L.R.col.p, L.R.val.p, C.seg.p, act, L.r.p,
+                               C.b.p);
+            prof_end(s_, h, restrict_bytes(L));
+        });
+        PAIR_LAUNCH_CHECK();
+    }
+    // up
+    for (int l = nl - 2; l >= 0; --l) {
+        Level& L = levels_[l];
+        if (L.R.n == 0) continue;
+        Level& C = levels_[l + 1];
+        const int64_t n = L.A.n;
+        hipLaunchKernelGGL(k_interpolate, dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_, n, L.p.p,
+                           L.seg.p, act, L.relax.p, C.x.p, L.x.p);
+        const int kind_relax = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
+        dispatch_lpr(L.lpr, [&](auto lc) {
+            constexpr int LPR = decltype(lc)::value;
+            const unsigned g = grid_xcd(n, kBlock / LPR);
+            int h = prof_begin(s_, kind_relax);
+            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(-1),
+                               L.seg.p, act, L.relax.p, L.b.p, L.x.p, L.t.p, prm_.omega, 0);
+            prof_end(s_, h, relax_bytes(L, -1, false));
+            h = prof_begin(s_, kind_relax);
+            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(1),
+                               L.seg.p, act, L.relax.p, L.b.p, L.t.p, L.x.p, prm_.omega, 0);
+            prof_end(s_, h, relax_bytes(L, 1, false));
+        });
+        PAIR_LAUNCH_CHECK();
+    }
+}
+
+void Hierarchy::launch_cycle_and_test(bool x_is_zero, int /*it_offset*/) {
+    Level& L0 = levels_[0];
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sb_.n_active.p);
+    vcycle_launches(x_is_zero);
+    dispatch_lpr(L0.lpr, [&](auto lc) {
+        constexpr int LPR = decltype(lc)::value;
+        int h = prof_begin(s_, PROF_NORM_FINE);
+        hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sb_.chunks, B_), dim3(kBlock), 0, s_, 1,
+                           sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p, L0.A.val.p,
+                           sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+        prof_end(s_, h, 12.0 * L0.A.nnz + 8.0 * L0.A.n * 3.0);
+    });
+    hipLaunchKernelGGL(k_norm_finalize, dim3(grid_for(B_, 64)), dim3(64), 0, s_, 1, B_, sb_.chunks,
+                       moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p, sb_.relres.p,
+                       sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p, prm_.tol,
+                       prm_.max_iter, 0);
+    PAIR_LAUNCH_CHECK();
+}
+
+bool Hierarchy::solve(bool use_graph, bool x_is_zero) {
+    Level& L0 = levels_[0];
+    if (!moff_d_.p) {
+        moff_d_.alloc(B_);
+        mcnt_d_.alloc(B_);
+        h2d(moff_d_.p, L0.off.data(), B_, s_);
+        h2d(mcnt_d_.p, L0.cnt.data(), B_, s_);
+    }
+    // |b| per member and the initial state
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sb_.n_active.p);
+    dispatch_lpr(L0.lpr, [&](auto lc) {
+        constexpr int LPR = decltype(lc)::value;
+        hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sb_.chunks, B_), dim3(kBlock), 0, s_, 0,
+                           sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p, L0.A.val.p,
+                           sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+    });
+    hipLaunchKernelGGL(k_norm_finalize, dim3(grid_for(B_, 64)), dim3(64), 0, s_, 0, B_, sb_.chunks,
+                       moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p, sb_.relres.p,
+                       sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p, prm_.tol,
+                       prm_.max_iter, x_is_zero ? 1 : 0);
+    PAIR_LAUNCH_CHECK();
+    if (!x_is_zero) {
+        dispatch_lpr(L0.lpr, [&](auto lc) {
+            constexpr int LPR = decltype(lc)::value;
+            hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sb_.chunks, B_), dim3(kBlock), 0, s_, 1,
+                               sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p,
+                               L0.A.val.p, sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+        });
+        hipLaunchKernelGGL(k_norm_finalize, dim3(grid_for(B_, 64)), dim3(64), 0, s_, 2, B_,
+                           sb_.chunks, moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p,
+                           sb_.relres.p, sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p,
+                           prm_.tol, prm_.max_iter, 0);
+        PAIR_LAUNCH_CHECK();
+    } else {
+        // x = 0 exactly on entry: members with b = 0 are done (x = 0 is exact)
+        PAIR_HIP(hipMemsetAsync(L0.x.p, 0, L0.A.n * sizeof(double), s_));
+    }
+    std::vector<uint8_t> act(B_);
+    d2h(act.data(), sb_.active.p, B_, s_);
+    PAIR_HIP(hipStreamSynchronize(s_));
+    int n_act = 0;
+    for (auto a : act) n_act += a;
+
+    int cycles = 0;
+    bool first = true;
+    while (n_act > 0) {
+        PAIR_CHECK(cycles <= prm_.max_iter + 1, "V-cycle loop did not stop");
+        if (first || !use_graph) {
+            launch_cycle_and_test(first && x_is_zero, cycles);
+        } else {
+            if (!graph_exec_) {
+                PAIR_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+                launch_cycle_and_test(false, cycles);
+                PAIR_HIP(hipStreamEndCapture(s_, &graph_));
+                PAIR_HIP(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0));
+            }
+            PAIR_HIP(hipGraphLaunch(graph_exec_, s_));
+        }
+        first = false;
+        ++cycles;
+        d2h(&n_act, sb_.n_active.p, 1, s_);
+        PAIR_HIP(hipStreamSynchronize(s_));
+    }
+    last_bytes_ = cycles * solve_bytes_per_cycle();
+    // per-member results
+    iters_h_.assign(B_, 0);
+    relres_h_.assign(B_, 0.0);
+    std::vector<double> r0(B_);
+    d2h(iters_h_.data(), sb_.iters.p, B_, s_);
+    d2h(relres_h_.data(), sb_.relres.p, B_, s_);
+    d2h(r0.data(), sb_.relres0.p, B_, s_);
+    PAIR_HIP(hipStreamSynchronize(s_));
+    cf_h_.assign(B_, 0.0);
+    bool ok = true;
+    for (int b = 0; b < B_; ++b) {
+        if (L0.off[b] < 0) continue;
+        if (iters_h_[b] > 0 && r0[b] > 0.0 && relres_h_[b] > 0.0)
+            cf_h_[b] = std::pow(relres_h_[b] / r0[b], 1.0 / iters_h_[b]);
+        if (!(relres_h_[b] <= prm_.tol)) ok = false;
+    }
+    return ok;
+}
+
+// Algorithmic bytes of one V-cycle over all members (FP64 values 8 B, int32
+// indices 4 B, int64 row offsets 8 B): what the kernels must read and write,
+// with gathered vector entries counted once per kernel.
+double Hierarchy::solve_bytes_per_cycle() const {
+    double bytes = 0.0;
+    const int nl = static_cast<int>(levels_.size());
+    for (int l = 0; l < nl; ++l) {
+        const Level& L = levels_[l];
+        const double n = static_cast<double>(L.A.n), nnz = static_cast<double>(L.A.nnz);
+        for (size_t k = 0; k < L.coarse_members.size(); ++k) {
+            double m = static_cast<double>(L.cnt[L.coarse_members[k]]);
+            bytes += 8.0 * m * m + 16.0 * m;
+        }
+        if (l + 1 >= nl || L.R.n == 0) continue;
+        const double mat = 12.0 * nnz + 8.0 * n;   // values + columns + row offsets
+        // relaxation: 4 half-sweeps; the first pre-smoothing F-half at coarse
+        // levels reads no matrix (x = 0); count 2 full matrix passes there
+        const double relax_mat = (l == 0) ? 2.0 * mat : 1.5 * mat;
+        const double relax_vec = 4.0 * (8.0 * n /*x in*/ + 8.0 * n /*x out*/ + 1.0 * n /*cf*/ + 2.0 * n /*seg*/)
+                                 + 2.0 * (8.0 * n /*b*/ + 8.0 * n /*dinv*/);
+        const double resid = mat + 8.0 * n /*x*/ + 8.0 * n /*b*/ + 8.0 * n /*r*/ + 2.0 * n;
+        const double nc = static_cast<double>(L.R.n), nnzr = static_cast<double>(L.R.nnz);
+        const double restr = 12.0 * nnzr + 8.0 * nc + 8.0 * n /*r*/ + 8.0 * nc /*b_c*/ + 2.0 * nc;
+        const double interp = 4.0 * n + 16.0 * n + 8.0 * nc + 2.0 * n;
+        bytes += relax_mat + relax_vec + resid + restr + interp;
+    }
+    // convergence test on the finest level
+    const Level& L0 = levels_[0];
+    bytes += 12.0 * L0.A.nnz + 8.0 * L0.A.n + 16.0 * L0.A.n;
+    return bytes;
+}
+
+}  // namespace pair

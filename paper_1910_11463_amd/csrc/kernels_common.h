@@ -1,0 +1,70 @@
+// Device-side helpers shared by the HIP kernels (wave64 reductions and scans,
+// the SplitMix64 generator).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pair {
+
+__device__ __forceinline__ int64_t wave_inclusive_scan(int64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_inclusive_scan_int(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Sum over groups of G consecutive lanes (G a power of two <= 64); every lane of
+// the group receives the group total.  The reduction tree is fixed, so the
+// result is bitwise reproducible.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_sum_int(int v) {
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): add the golden-ratio increment, then
+// the variant-13 finaliser.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// 53-bit random integer of local row i on a level (PMIS measure tie-breaker).
+__device__ __forceinline__ uint64_t pmis_rand(uint64_t seed, int level, int64_t i) {
+    uint64_t key = (seed << 40) + (static_cast<uint64_t>(level) << 32) + static_cast<uint64_t>(i);
+    return splitmix64(key) >> 11;
+}
+
+}  // namespace pair

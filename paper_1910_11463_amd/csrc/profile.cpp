@@ -1,0 +1,87 @@
+// Event-pair kernel timing (see profile.h).
+#include "profile.h"
+
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace pair {
+namespace {
+struct Rec {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    PAIR_HIP(hipEventCreate(&e));
+    return e;
+}
+}  // namespace
+
+bool prof_enabled() { return g_on; }
+
+int prof_begin(hipStream_t s, int kind) {
+    if (!g_on || kind < 0 || kind >= PROF_NKINDS) return -1;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    std::lock_guard<std::mutex> g(g_mu);
+    Rec r{take_event(), take_event(), kind, 0.0};
+    PAIR_HIP(hipEventRecord(r.a, s));
+    g_recs.push_back(r);
+    return static_cast<int>(g_recs.size()) - 1;
+}
+
+void prof_end(hipStream_t s, int h, double bytes) {
+    if (h < 0) return;
+    std::lock_guard<std::mutex> g(g_mu);
+    PAIR_HIP(hipEventRecord(g_recs[h].b, s));
+    g_recs[h].bytes = bytes;
+}
+
+void prof_enable(bool on) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (on) {
+        for (auto& r : g_recs) {
+            (void)hipEventSynchronize(r.b);
+            g_pool.push_back(r.a);
+            g_pool.push_back(r.b);
+        }
+        g_recs.clear();
+    }
+    g_on = on;
+}
+
+void prof_read(int kind, int64_t* launches, double* total_ms, double* total_bytes) {
+    std::lock_guard<std::mutex> g(g_mu);
+    int64_t n = 0;
+    double ms = 0.0, by = 0.0;
+    for (auto& r : g_recs) {
+        if (r.kind != kind) continue;
+        PAIR_HIP(hipEventSynchronize(r.b));
+        float t = 0.f;
+        PAIR_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        by += r.bytes;
+        ++n;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (total_bytes) *total_bytes = by;
+}
+
+}  // namespace pair

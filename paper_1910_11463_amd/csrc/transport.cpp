@@ -1,0 +1,200 @@
+// Source iteration driver: per-direction (or batched) assembly, AIR setup and
+// V-cycle solves, scalar-flux accumulation (eq. sn_transport, eq. angular_quad;
+// Sec. "Accuracy of Spatial Solves").
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "transport.h"
+
+namespace pair {
+
+namespace {
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+Context::~Context() {
+    batches.clear();
+    if (own_stream && s) (void)hipStreamDestroy(s);
+}
+
+void Context::check_ready() const {
+    if (!have_mesh) throw Error(E_STATE, "no mesh set");
+    if (!have_quad) throw Error(E_STATE, "no quadrature set");
+    if (!have_mats) throw Error(E_STATE, "no materials set");
+}
+
+AmgParams Context::amg_params() const {
+    AmgParams p;
+    p.theta = opt.theta;
+    p.eps_r = opt.eps_r;
+    p.omega = opt.omega;
+    p.coarse_max = opt.coarse_max;
+    p.max_levels = opt.max_levels;
+    p.max_coarse_ratio = opt.max_coarse_ratio;
+    p.kmax = opt.kmax;
+    p.seed = opt.pmis_seed;
+    p.tol = opt.tol_inner;
+    p.max_iter = opt.max_inner;
+    return p;
+}
+
+Csr Context::assemble_fine(Batch& bt, double* t_assemble_ms) {
+    const int B = static_cast<int>(bt.dirs.size());
+    const int64_t E = mesh.E, N = this->N();
+    double t0 = now_ms();
+    PAIR_CHECK(N * B < (int64_t(1) << 31), "batch too large for int32 column indices; lower batch_size");
+    DBuf<int> dirs_d(B);
+    h2d(dirs_d.p, bt.dirs.data(), B, s);
+    DBuf<int64_t> cnt(E * B), eoff(E * B + 1);
+    fine_counts(mesh, omega_d.p, dirs_d.p, B, cnt.p, s);
+    const int64_t nnz = exclusive_scan(cnt.p, eoff.p, E * B, s);
+    Csr A;
+    A.n = N * B;
+    A.ncols = N * B;
+    A.nnz = nnz;
+    A.rowptr.alloc(A.n + 1);
+    A.col.alloc(nnz);
+    A.val.alloc(nnz);
+    bt.dinv.alloc(static_cast<size_t>(B) * E * mesh.k * mesh.k);
+    fine_assemble(mesh, omega_d.p, dirs_d.p, B, sigt.p, eoff.p, nnz, A.rowptr.p, A.col.p, A.val.p,
+                  bt.dinv.p, s);
+    if (t_assemble_ms) *t_assemble_ms += now_ms() - t0;
+    return A;
+}
+
+void Context::assemble_batch(Batch& bt, double* t_assemble_ms) {
+    const int B = static_cast<int>(bt.dirs.size());
+    const int64_t N = this->N();
+    Csr A = assemble_fine(bt, t_assemble_ms);
+    std::vector<int64_t> off(B), cn(B, N);
+    for (int b = 0; b < B; ++b) off[b] = static_cast<int64_t>(b) * N;
+    bt.H.reset(new Hierarchy(amg_params(), s));
+    bt.H->setup(std::move(A), off, cn);
+}
+
+void Context::build_batches(int mode, pair_stats* st) {
+    if (cached_mode == mode && !batches.empty()) return;
+    batches.clear();
+    cached_mode = -1;
+    std::vector<std::vector<int>> groups;
+    if (mode == PAIR_PLAIN) {
+        for (int m = 0; m < M; ++m) groups.push_back({m});
+    } else {
+        int bs = opt.batch_size > 0 ? opt.batch_size : M;
+        for (int m0 = 0; m0 < M; m0 += bs) {
+            std::vector<int> g;
+            for (int m = m0; m < std::min(M, m0 + bs); ++m) g.push_back(m);
+            groups.push_back(g);
+        }
+    }
+    batches.resize(groups.size());
+    for (size_t i = 0; i < groups.size(); ++i) batches[i].dirs = groups[i];
+    (void)st;
+}
+
+void Context::rhs_batch(const Batch& bt, const SourceSpec& src, const double* phi_in, double* out) {
+    const int B = static_cast<int>(bt.dirs.size());
+    DBuf<int> dirs_d(B);
+    h2d(dirs_d.p, bt.dirs.data(), B, s);
+    rhs_kernel(mesh, B, dirs_d.p, bt.dinv.p, sigs.p, src.q, phi_in, src.ext, src.ext_per_dir, N(),
+               out, s);
+    PAIR_HIP(hipStreamSynchronize(s));
+}
+
+bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, double* psi_out,
+                    double* phi_out, pair_stats* st, bool warm) {
+    check_ready();
+    build_batches(mode, st);
+    const int64_t N = this->N();
+    bool all_ok = true;
+    dir_iters.assign(M, 0);
+    dir_cf.assign(M, 0.0);
+    dir_relres.assign(M, 0.0);
+    bool first_phi = true;
+    double t_asm = 0.0, t_setup = 0.0, t_solve = 0.0, t_other = 0.0, bytes = 0.0;
+    for (auto& bt : batches) {
+        const int B = static_cast<int>(bt.dirs.size());
+        double t0 = now_ms();
+        if (!bt.H) {
+            double ta = 0.0;
+            assemble_batch(bt, &ta);
+            t_asm += ta;
+            t_setup += now_ms() - t0 - ta;
+        }
+        double t1 = now_ms();
+        rhs_batch(bt, src, phi_in, bt.H->b0());
+        double* x0 = bt.H->x0();
+        const bool use_warm = warm && psi_valid && psi.p;
+        if (use_warm)
+            for (int b = 0; b < B; ++b) d2d(x0 + b * N, psi.p + static_cast<int64_t>(bt.dirs[b]) * N, N, s);
+        double t2 = now_ms();
+        bool ok = bt.H->solve(opt.use_graph && mode == PAIR_BATCHED, !use_warm);
+        double t3 = now_ms();
+        bytes += bt.H->last_solve_bytes();
+        all_ok = all_ok && ok;
+        for (int b = 0; b < B; ++b) {
+            const int m = bt.dirs[b];
+            dir_iters[m] = bt.H->iters_h()[b];
+            dir_cf[m] = bt.H->cf_h()[b];
+            dir_relres[m] = bt.H->relres_h()[b];
+            if (psi_out) d2d(psi_out + static_cast<int64_t>(m) * N, x0 + b * N, N, s);
+        }
+        if (phi_out) {
+            std::vector<double> wb(B);
+            for (int b = 0; b < B; ++b) wb[b] = w_h[bt.dirs[b]];
+            DBuf<double> wbd(B);
+            h2d(wbd.p, wb.data(), B, s);
+            phi_accumulate(N, B, wbd.p, x0, phi_out, first_phi, s);
+            first_phi = false;
+        }
+        PAIR_HIP(hipStreamSynchronize(s));
+        double t4 = now_ms();
+        t_other += (t2 - t1) + (t4 - t3);
+        t_solve += t3 - t2;
+        if (st) {
+            if (&bt == &batches.front()) {
+                Hierarchy& H = *bt.H;
+                st->levels_max = std::max(st->levels_max, H.member_levels(0));
+                for (int l = 0; l < std::min(H.num_levels(), PAIR_MAX_LEVELS); ++l) {
+                    Level& L = H.level(l);
+                    st->level_n[l] = L.off[0] >= 0 ? L.cnt[0] : 0;
+                    st->level_nnz[l] = L.off[0] >= 0 ? L.A.nnz : 0;
+                }
+            }
+            for (int b = 0; b < B; ++b) st->levels_max = std::max(st->levels_max, bt.H->member_levels(b));
+        }
+        if (!opt.keep_hierarchy) {
+            bt.H.reset();
+            bt.dinv.reset();
+        }
+    }
+    if (phi_out && first_phi) PAIR_HIP(hipMemsetAsync(phi_out, 0, N * sizeof(double), s));
+    if (!opt.keep_hierarchy) cached_mode = -1;
+    else cached_mode = mode;
+    if (st) {
+        st->n_dir = M;
+        st->t_assemble_ms += t_asm;
+        st->t_setup_ms += t_setup;
+        st->t_solve_ms += t_solve;
+        st->t_other_ms += t_other;
+        st->bytes_solve += bytes;
+        int vmax = 0;
+        double cfs = 0.0, rmax = 0.0;
+        for (int m = 0; m < M; ++m) {
+            st->vcycles_total += dir_iters[m];
+            vmax = std::max(vmax, dir_iters[m]);
+            cfs += dir_cf[m];
+            rmax = std::max(rmax, dir_relres[m]);
+        }
+        st->vcycles_max = vmax;
+        st->cf_mean = M ? cfs / M : 0.0;
+        st->relres_max = rmax;
+    }
+    return all_ok;
+}
+
+}  // namespace pair

@@ -1,0 +1,120 @@
+// S_N transport problem on the GPU: mesh, materials, quadrature, per-direction
+// upwind DG assembly with block-inverse scaling, and source iteration with pAIR
+// direction solves.
+#pragma once
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "amg.h"
+#include "../../include/pair.h"
+
+namespace pair {
+
+constexpr double kFourPi = 12.566370614359172953850573533118;
+constexpr double kZeroFluxTol = 1e-12;
+
+struct DeviceMesh {
+    int kind = -1;            // PAIR_HEX8 / PAIR_TET4
+    int64_t E = 0;
+    int k = 0;                // nodes per element
+    int F = 0;                // faces per element
+    int nf = 0;               // nodes per face
+    // structured hex
+    int nx = 0, ny = 0, nz = 0;
+    double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+    DBuf<double> ref;         // hex reference matrices (see k_hex_reference)
+    // tets: per element geometry (k_tet_geometry)
+    DBuf<double> xyz;         // [n_vert][3]
+    DBuf<int32_t> ev;         // [E][4]
+    DBuf<int32_t> nbr;        // [E][4] neighbour across the face opposite vertex f
+    DBuf<int8_t> unode;       // [E][4][3] neighbour's local node matching face vertex t
+    DBuf<double> nvec;        // [E][4][3] outward canonical face vector (|n| = 2 area)
+    DBuf<double> mass;        // [E][16] (tets) element mass matrices
+    DBuf<double> vol;         // [E]
+    int64_t n_dof() const { return E * k; }
+};
+
+// Fine operators of one batch of directions and their AIR hierarchy.
+struct Batch {
+    std::vector<int> dirs;                 // directions, in order
+    DBuf<double> dinv;                     // [B][E][k*k] element block inverses
+    std::unique_ptr<Hierarchy> H;
+};
+
+struct SourceSpec {
+    const double* q = nullptr;        // [E] isotropic element source (device) or null
+    const double* ext = nullptr;      // dual-space source (device) or null
+    bool ext_per_dir = false;         // ext is [M][N] instead of [N]
+};
+
+struct Context {
+    pair_options opt{};
+    hipStream_t s = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    DeviceMesh mesh;
+    bool have_mesh = false;
+
+    int M = 0;
+    std::vector<double> omega_h, w_h;   // [M][3], [M]
+    DBuf<double> omega_d, w_d;
+    bool have_quad = false;
+
+    DBuf<double> sigt, sigs, q;
+    std::vector<double> sigt_h;
+    bool have_mats = false;
+
+    DBuf<double> ext;                   // dual source
+    bool ext_per_dir = false;
+    bool have_ext = false;
+
+    // cached operators
+    std::vector<Batch> batches;
+    int cached_mode = -1;
+
+    // state
+    DBuf<double> psi;                   // [M][N] last angular flux
+    bool psi_valid = false;
+    DBuf<double> phi;                   // [N] last scalar flux
+    std::vector<int> dir_iters;
+    std::vector<double> dir_cf, dir_relres;
+
+    ~Context();
+
+    // building blocks
+    void check_ready() const;
+    void build_batches(int mode, pair_stats* st);
+    Csr assemble_fine(Batch& b, double* t_assemble_ms);
+    void assemble_batch(Batch& b, double* t_assemble_ms);
+    void rhs_batch(const Batch& b, const SourceSpec& src, const double* phi_in, double* out);
+    // one sweep replacement over all directions: psi_out [M][N] may be null
+    // unless needed, phi_out [N] accumulated in direction order.
+    bool sweep(int mode, const SourceSpec& src, const double* phi_in, double* psi_out,
+               double* phi_out, pair_stats* st, bool warm);
+    int64_t N() const { return mesh.n_dof(); }
+    AmgParams amg_params() const;
+};
+
+// kernels (assemble.hip)
+void hex_reference(DeviceMesh& m, hipStream_t s);
+void tet_geometry(DeviceMesh& m, int64_t n_vert, hipStream_t s);
+// count nonzeros per (direction, element) for the scaled fine operator
+void fine_counts(const DeviceMesh& m, const double* omega_d, const int* dirs_d, int B,
+                 int64_t* cnt, hipStream_t s);
+void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d, int B,
+                   const double* sigt, const int64_t* elem_off, int64_t total_nnz, int64_t* rowptr,
+                   int32_t* col, double* val, double* dinv, hipStream_t s);
+void rhs_kernel(const DeviceMesh& m, int B, const int* dirs_d, const double* dinv,
+                const double* sigs, const double* q, const double* phi, const double* ext,
+                bool ext_per_dir, int64_t N, double* out, hipStream_t s);
+void phi_accumulate(int64_t N, int B, const double* w_batch_d, const double* x, double* phi,
+                    bool first, hipStream_t s);
+void diff_norms(int64_t N, const double* a, const double* b, double* out2, hipStream_t s);
+void adjoint_contract(const DeviceMesh& m, int M, const double* w_d, const int* refl_d,
+                      const double* psi, const double* psi_adj, const double* phi,
+                      const double* phi_adj, double* g_t, double* g_s, hipStream_t s);
+
+}  // namespace pair

@@ -1,0 +1,130 @@
+"""GPU parity of the transport path against the CPU oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1910_11463_amd import binding as B
+from paper_1910_11463_amd import workloads as wl
+from tests.gpu_util import need_gpu, oracle_problem, rel, solver_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("cfg,scale,dirs", [(1, 8, [0, 3, 7]), (3, 3, [0, 11, 23]), (5, 5, [1, 20])])
+def test_fine_operator_matches_oracle(cfg, scale, dirs):
+    """Scaled DG operator D^{-1}A and scaled rhs of individual directions."""
+    need_gpu()
+    from oracle import dg
+    w = wl.make_config(cfg, scale=scale)
+    s = solver_for(w)
+    prob = oracle_problem(w)
+    for m in dirs:
+        _print("fine operator", w.name, "direction", m)
+        rp, col, val, b = s.export_fine_operator(m)
+        blk = prob.blocks(m)
+        A = dg.scaled_csr(prob.topo, blk)
+        assert np.array_equal(rp, A.indptr)
+        assert np.array_equal(col, A.indices)
+        assert np.abs(val - A.data).max() <= 1e-13 * np.abs(A.data).max()
+        f = prob.rhs(m, None)
+        bo = np.einsum("eab,eb->ea", np.linalg.inv(blk.D), f).ravel()
+        assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
+    s.close()
+
+
+@pytest.mark.parametrize("cfg,scale,mode", [(1, 8, B.PAIR_PLAIN), (1, 8, B.PAIR_BATCHED),
+                                            (3, 3, B.PAIR_PLAIN), (2, 6, B.PAIR_BATCHED)])
+def test_sweep_replacement_matches_exact_sweep(cfg, scale, mode):
+    """One sweep replacement (all directions) against the oracle's exact sweep."""
+    need_gpu()
+    from oracle import source_iteration as si
+    w = wl.make_config(cfg, scale=scale)
+    s = solver_for(w, tol_inner=1e-12, max_inner=200)
+    _print("sweep", w.name, "mode", mode)
+    psi, phi, st, rc = s.transport_sweep(mode=mode)
+    assert rc == B.PAIR_OK
+    prob = oracle_problem(w)
+    ref = si.transport_sweep(prob, None)
+    for m in range(prob.M):
+        assert rel(psi[m], ref[m]) <= 1e-9, (m, rel(psi[m], ref[m]))
+    assert rel(phi, si.scalar_flux(prob, ref)) <= 1e-9
+    assert st["relres_max"] <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("cfg,scale", [(1, 8), (3, 3), (4, 4)])
+def test_source_iteration_phi(cfg, scale):
+    """phi of the converged source iteration within 1e-8 of the oracle."""
+    need_gpu()
+    from oracle import source_iteration as si
+    w = wl.make_config(cfg, scale=scale)
+    s = solver_for(w, tol_inner=1e-12, tol_outer=1e-11, outer_estimate=1, max_inner=200)
+    _print("source iteration", w.name)
+    phi, _, st, rc = s.solve(mode=B.PAIR_BATCHED)
+    assert rc == B.PAIR_OK
+    ref = si.source_iteration(oracle_problem(w), tol=1e-13).phi
+    err = rel(phi, ref)
+    _print("  phi rel err %.3e after %d source iterations" % (err, st["outer_iters"]))
+    assert err <= 1e-8
+    s.close()
+
+
+def test_batched_equals_plain_bitwise():
+    """Batched launches give bit-identical psi to one-direction-at-a-time solves."""
+    need_gpu()
+    w = wl.make_config(4, scale=8)
+    a = solver_for(w)
+    b = solver_for(w)
+    _print("batched vs plain", w.name)
+    psi_p, phi_p, st_p, rc_p = a.transport_sweep(mode=B.PAIR_PLAIN)
+    psi_b, phi_b, st_b, rc_b = b.transport_sweep(mode=B.PAIR_BATCHED)
+    assert rc_p == B.PAIR_OK and rc_b == B.PAIR_OK
+    assert np.array_equal(psi_p, psi_b)
+    assert np.array_equal(phi_p, phi_b)
+    for m in range(w.n_dir):
+        assert a.direction_info(m) == b.direction_info(m)
+    a.close()
+    b.close()
+
+
+def test_repeat_is_bitwise_deterministic():
+    need_gpu()
+    w = wl.make_config(3, scale=3)
+    out = []
+    for _ in range(2):
+        s = solver_for(w)
+        psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_BATCHED)
+        out.append((psi, phi))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_error_paths():
+    need_gpu()
+    from paper_1910_11463_amd.solver import Solver
+    w = wl.make_config(1, scale=4)
+    s = Solver()
+    with pytest.raises(B.PairError) as e:
+        s.solve()
+    assert e.value.code == B.PAIR_E_STATE
+    s.set_mesh(w.mesh)
+    om, wt = Solver.level_symmetric(2)
+    s.set_quadrature(om, wt)
+    bad = w.mats.sigma_t.copy()
+    bad[3] = np.nan
+    with pytest.raises(B.PairError) as e:
+        s.set_materials(bad, w.mats.sigma_s, w.mats.q)
+    assert e.value.code == B.PAIR_E_INVALID
+    with pytest.raises(B.PairError):
+        s.set_quadrature(om, wt * 2.0)
+    s.set_materials(w.mats.sigma_t, w.mats.sigma_s, w.mats.q)
+    s.set_options(max_inner=1, tol_inner=1e-14)
+    psi, phi, st, rc = s.transport_sweep()
+    assert rc == B.PAIR_E_NOCONV
+    assert np.all(np.isfinite(phi)) and np.linalg.norm(phi) > 0
+    s.close()
