@@ -35,10 +35,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_solver(w, mode_batch_size, device):
+def make_solver(w, mode_batch_size, device, pre="FC", post="FC"):
     import torch
     from paper_1910_11463_amd.solver import Solver
-    s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size)
+    s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
+               relax_pre=pre, relax_post=post)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -117,6 +118,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--cpu-dirs", type=int, default=16)
+    ap.add_argument("--relax-pre", default="FC")
+    ap.add_argument("--relax-post", default="FC")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -139,7 +142,8 @@ def main():
     mode = B.PAIR_PLAIN if args.mode == "plain" else B.PAIR_BATCHED
     log("workload %s: N=%d, M=%d, mode=%s" % (w.name, N, M, args.mode))
 
-    s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device)
+    s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
+                    args.relax_pre, args.relax_post)
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
     value = N * M / sec
@@ -153,7 +157,8 @@ def main():
     s.close()
     if not args.no_extra:
         other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
-        s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device)
+        s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device,
+                         args.relax_pre, args.relax_post)
         osec, ost = timed_steps(s2, other, 1, 0, cold=True)
         wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
         extra["other_mode"] = {"mode": "batched" if other == B.PAIR_BATCHED else "plain",
@@ -182,6 +187,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "mode": args.mode, "dof_per_dir": N, "dirs": M,
                    "tol": 1e-8, "step": "cold sweep replacement: assembly + AIR setup + V-cycles + phi",
+                   "relax": "V(%s,%s) Jacobi half-sweeps" % (args.relax_pre, args.relax_post),
                    "parallelism": "1 GPU"},
         "stats": {"vcycles_total": st["vcycles_total"], "vcycles_max": st["vcycles_max"],
                   "cf_mean": st["cf_mean"], "levels": st["levels_max"],

@@ -61,7 +61,7 @@ typedef struct pair_options {
     double theta;             /* coarsening strength threshold (0.25)           */
     double eps_r;             /* strength threshold for the pattern of R (0.01) */
     double omega;             /* Jacobi damping (1.0)                           */
-    int coarse_max;           /* stop coarsening at <= this many rows (256)     */
+    int coarse_max;           /* stop coarsening at <= this many rows (64)      */
     int max_levels;           /* at most this many levels (25)                  */
     double max_coarse_ratio;  /* stop when n_c > ratio * n (0.9)                */
     int kmax;                 /* max F-points per local lAIR solve (64)         */
@@ -77,6 +77,9 @@ typedef struct pair_options {
     int batch_size;           /* directions per batch in PAIR_BATCHED, 0 = all  */
     int use_graph;            /* capture batched V-cycles in a hipGraph (1)     */
     int allow_any_weight_sum; /* accept quadrature weights not summing to 4 pi  */
+    char relax_pre[8];        /* pre-smoothing half-sweeps, e.g. "FC" (default) */
+    char relax_post[8];       /* post-smoothing half-sweeps, e.g. "FC"; "FFC" = two
+                                 Jacobi sweeps over F-points, then one over C-points */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

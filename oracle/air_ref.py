@@ -17,7 +17,7 @@ Sec. "SOC Parameter for Building R"):
 4. interpolation "by value": each F-point takes the value of its strongest
    strongly-connected C-point (one-point interpolation), C-points by injection;
 5. Petrov-Galerkin coarse operator A_c = R A P;
-6. recursion until the level is small (<= 256 rows), coarsening stalls
+6. recursion until the level is small (<= 64 rows), coarsening stalls
    (n_c > 0.9 n) or 25 levels; a dense LU at the coarsest level;
 7. V(1,1) cycles with FC-Jacobi relaxation: one Jacobi sweep over the
    F-points, then one over the C-points, before and after the coarse
@@ -72,10 +72,12 @@ class Options:
     distance: Optional[int] = 1       # 1, 2, or None (= all F points: ideal R)
     kmax: int = 64
     omega: float = 1.0
-    coarse_max: int = 256
+    coarse_max: int = 64
     max_levels: int = 25
     max_coarse_ratio: float = 0.9
     seed: int = 0
+    relax_pre: str = "FC"      # half-sweeps before the coarse correction
+    relax_post: str = "FC"     # and after it ("FFC": F, F, then C)
 
 
 def _rows(A: sp.csr_matrix):
@@ -298,26 +300,28 @@ def _relax(A, d, b, x, mask, omega):
 
 
 def vcycle(levels: List[Level], b: np.ndarray, x: np.ndarray, lev: int = 0,
-           omega: float = 1.0) -> np.ndarray:
+           omega: float = 1.0, pre: str = "FC", post: str = "FC") -> np.ndarray:
+    """One V-cycle; each character of pre/post is one Jacobi half-sweep over the
+    F-points ("F") or the C-points ("C")."""
     L = levels[lev]
     if lev == len(levels) - 1:
         return np.linalg.solve(L.A.toarray(), b)
     d = L.A.diagonal()
     F = L.cf < 0
     C = ~F
-    x = _relax(L.A, d, b, x, F, omega)
-    x = _relax(L.A, d, b, x, C, omega)
+    for ch in pre:
+        x = _relax(L.A, d, b, x, F if ch == "F" else C, omega)
     r = b - L.A @ x
     bc = L.R @ r
-    xc = vcycle(levels, bc, np.zeros(L.R.shape[0]), lev + 1, omega)
+    xc = vcycle(levels, bc, np.zeros(L.R.shape[0]), lev + 1, omega, pre, post)
     x = x + L.P @ xc
-    x = _relax(L.A, d, b, x, F, omega)
-    x = _relax(L.A, d, b, x, C, omega)
+    for ch in post:
+        x = _relax(L.A, d, b, x, F if ch == "F" else C, omega)
     return x
 
 
 def solve(levels: List[Level], b: np.ndarray, tol: float = 1e-10, maxit: int = 200,
-          x0=None, omega: float = 1.0):
+          x0=None, omega: float = 1.0, pre: str = "FC", post: str = "FC"):
     A = levels[0].A
     x = np.zeros_like(b) if x0 is None else x0.copy()
     nb = np.linalg.norm(b)
@@ -327,7 +331,7 @@ def solve(levels: List[Level], b: np.ndarray, tol: float = 1e-10, maxit: int = 2
         hist.append(rel)
         if rel <= tol:
             return x, it, hist
-        x = vcycle(levels, b, x, 0, omega)
+        x = vcycle(levels, b, x, 0, omega, pre, post)
     rel = np.linalg.norm(b - A @ x) / nb
     hist.append(rel)
     return x, maxit, hist

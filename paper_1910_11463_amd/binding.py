@@ -35,7 +35,8 @@ class pair_options(ctypes.Structure):
                 ("tol_inner", c_double), ("max_inner", c_int), ("tol_outer", c_double),
                 ("max_outer", c_int), ("outer_estimate", c_int), ("keep_psi", c_int),
                 ("keep_hierarchy", c_int), ("warm_start", c_int), ("batch_size", c_int),
-                ("use_graph", c_int), ("allow_any_weight_sum", c_int)]
+                ("use_graph", c_int), ("allow_any_weight_sum", c_int),
+                ("relax_pre", ctypes.c_char * 8), ("relax_post", ctypes.c_char * 8)]
 
 
 class pair_stats(ctypes.Structure):
@@ -172,5 +173,7 @@ def default_options(**overrides) -> pair_options:
     for k, v in overrides.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k in ("relax_pre", "relax_post") and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o

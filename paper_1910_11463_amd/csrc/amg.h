@@ -9,6 +9,8 @@
 //   at the coarsest level; V(1,1) cycles with FC-Jacobi relaxation.
 #pragma once
 
+#include <memory>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -19,7 +21,7 @@ struct AmgParams {
     double theta = 0.25;
     double eps_r = 0.01;
     double omega = 1.0;
-    int coarse_max = 256;
+    int coarse_max = 64;
     int max_levels = 25;
     double max_coarse_ratio = 0.9;
     int kmax = 64;
@@ -27,6 +29,7 @@ struct AmgParams {
     double tol = 1e-8;
     int max_iter = 100;
     int max_dense = 2048;   // largest coarsest level solved by a dense inverse
+    std::string relax_pre = "FC", relax_post = "FC";   // half-sweep schedules
     // lanes per row of the row kernels: index 0 = finest level, last entry used
     // for all deeper levels.  A function of the level index only, so that every
     // member's arithmetic (and its rounding) is the same whether it is solved
@@ -39,6 +42,19 @@ struct Csr {
     int64_t n = 0, ncols = 0, nnz = 0;
     DBuf<int64_t> rowptr;
     DBuf<int32_t> col;
+    DBuf<double> val;
+};
+
+// Element-block ("ELL") storage of a block-scaled DG operator on the finest
+// level: unit diagonal, and for each element up to three upwind neighbour
+// blocks of k rows x nf columns.  Slot s of element g holds the neighbour's
+// global element index nbr[s*nel+g] (-1: empty) and its nf face nodes packed
+// 3 bits each in nodes[s*nel+g]; values are stored slot-major
+// val[(s*nf + j) * nrows + row] so that consecutive rows are contiguous.
+struct FineEll {
+    int k = 0, nf = 0;
+    int64_t nel = 0, nrows = 0;
+    DBuf<int32_t> nbr, nodes;
     DBuf<double> val;
 };
 
@@ -103,12 +119,19 @@ public:
     double solve_bytes_per_cycle() const;   // algorithmic bytes of one V-cycle (all members)
     double last_solve_bytes() const { return last_bytes_; }
     int64_t nnz_level(int l) const { return levels_[l].A.nnz; }
-    void set_params(const AmgParams& p) { prm_ = p; }
+    // Use an element-block copy of the finest level for its relaxation,
+    // residual and convergence test (its diagonal must be the identity).
+    void set_fine_ell(std::shared_ptr<FineEll> e) { ell_ = std::move(e); drop_graph(); }
+    // New parameters (tolerance, iteration limit, relaxation schedule); the
+    // captured cycle graph bakes them in, so it is dropped.
+    void set_params(const AmgParams& p);
 
 private:
     void build_level_aux(Level& L, int l);
     void coarse_setup(Level& L, const std::vector<int>& members);
     void vcycle_launches(bool x_is_zero);
+    double* sweeps(Level& L, int l, const std::string& sched, double* cur, double* other, bool zero);
+    void drop_graph();
     void residual_norms();
     void launch_cycle_and_test(bool x_is_zero, int it_offset);
 
@@ -121,6 +144,7 @@ private:
     std::vector<int> iters_h_;
     std::vector<double> relres_h_, cf_h_;
     DBuf<int64_t> moff_d_, mcnt_d_;   // finest-level member offsets / counts
+    std::shared_ptr<FineEll> ell_;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr;
     double last_bytes_ = 0.0;

@@ -164,14 +164,30 @@ __global__ void k_cmap(int64_t n, const uint16_t* __restrict__ seg, const int64_
     cmap[i] = c ? static_cast<int32_t>(no + cidx[i] - cidx[off[b]]) : -1;
 }
 
-__global__ void k_cf_counts(int64_t n, const int64_t* __restrict__ rowptr,
-                            const int8_t* __restrict__ cf, unsigned long long* __restrict__ out) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n || cf[i] == 0) return;
-    const unsigned long long len = static_cast<unsigned long long>(rowptr[i + 1] - rowptr[i]);
-    const int k = cf[i] < 0 ? 0 : 2;
-    atomicAdd(&out[k], 1ull);
-    atomicAdd(&out[k + 1], len);
+__global__ void __launch_bounds__(256)
+k_cf_counts(int64_t n, const int64_t* __restrict__ rowptr, const int8_t* __restrict__ cf,
+            unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[4][4];
+    unsigned long long v[4] = {0, 0, 0, 0};
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        if (cf[i] == 0) continue;
+        const unsigned long long len = static_cast<unsigned long long>(rowptr[i + 1] - rowptr[i]);
+        const int k = cf[i] < 0 ? 0 : 2;
+        v[k] += 1ull;
+        v[k + 1] += len;
+    }
+    for (int k = 0; k < 4; ++k) {
+        unsigned long long x = v[k];
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long x = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                               red[3][threadIdx.x];
+        atomicAdd(&out[threadIdx.x], x);
+    }
 }
 
 __global__ void k_interp(int64_t n, const int64_t* __restrict__ rowptr,
@@ -218,143 +234,165 @@ __global__ void k_r_count(int64_t nc, const int32_t* __restrict__ c2f,
 }
 
 constexpr int KCAP = 64;      // largest local system (one wave: lane = row)
-constexpr int KLD = KCAP + 1; // padded LDS stride
 
-// One wave per coarse row.  Local system in LDS, Gaussian elimination with
-// partial pivoting (lane r owns row r), back substitution with wave sums.
+// lAIR rows, G lanes per coarse row (G = 16, 32 or 64 >= the row's local system
+// size K), 64 / G rows per wave.  Local system A(R_i,R_i)^T z = -A(i,R_i)^T in
+// LDS, Gaussian elimination with partial pivoting (lane r owns row r), back
+// substitution with group sums.  Loops run to the largest K of the wave so every
+// lane reaches every barrier.
+template <int G>
 __global__ void __launch_bounds__(64)
-k_r_build(int64_t nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
-          const int32_t* __restrict__ col, const double* __restrict__ val,
-          const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf, int kmax,
-          const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
-          double* __restrict__ r_val, int* __restrict__ singular) {
-    __shared__ double Mloc[KCAP * KLD];
-    __shared__ double rhs[KCAP];
-    __shared__ double z[KCAP];
-    __shared__ int cols[KCAP];
+k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict__ c2f,
+          const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+          const double* __restrict__ val, const uint8_t* __restrict__ sflag,
+          const int8_t* __restrict__ cf, int kmax, const int64_t* __restrict__ r_rowptr,
+          int32_t* __restrict__ r_col, double* __restrict__ r_val, int* __restrict__ singular) {
+    constexpr int RPW = 64 / G;
+    constexpr int LD = G + 1;
+    __shared__ double Mloc[RPW][G * LD];
+    __shared__ double rhs[RPW][G];
+    __shared__ double z[RPW][G];
+    __shared__ int cols[RPW][G];
+    __shared__ int kw[RPW];
     const int lane = threadIdx.x;
-    for (int64_t I = blockIdx.x; I < nc; I += gridDim.x) {
-        const int64_t i = c2f[I];
-        const int64_t rs = rowptr[i], re = rowptr[i + 1];
-        // count candidates
+    const int g = lane / G, sub = lane % G;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
+    for (int base = blockIdx.x * RPW; base < nrows; base += gridDim.x * RPW) {
+        const bool have = base + g < nrows;
+        const int64_t I = have ? list[base + g] : 0;
+        const int64_t i = have ? c2f[I] : 0;
+        const int64_t rs = have ? rowptr[i] : 0, re = have ? rowptr[i + 1] : 0;
+        const int K = have ? static_cast<int>(r_rowptr[I + 1] - r_rowptr[I]) - 1 : 0;
+        // row length bound for uniform loops over the rows' entries
+        int64_t len = re - rs, lenw = len;
+        for (int d = 32; d >= 1; d >>= 1) lenw = max(lenw, static_cast<int64_t>(__shfl_xor(lenw, d, 64)));
+        // candidates (count, then collect in column order; rank-limited if > kmax)
         int cnt = 0;
-        for (int64_t e0 = rs; e0 < re; e0 += 64) {
-            int64_t e = e0 + lane;
-            bool cand = e < re && r_candidate(i, col[e], sflag[e], cf);
-            cnt += __popcll(__ballot(cand));
+        for (int64_t e0 = 0; e0 < lenw; e0 += G) {
+            int64_t e = rs + e0 + sub;
+            bool cand = have && e < re && r_candidate(i, col[e], sflag[e], cf);
+            cnt += __popcll(__ballot(cand) & gmask);
         }
-        const int K = cnt < kmax ? cnt : kmax;
-        // collect (in column order); when there are more than kmax candidates keep
-        // those whose rank by (|a| desc, column asc) is below kmax
         int filled = 0;
-        for (int64_t e0 = rs; e0 < re; e0 += 64) {
-            int64_t e = e0 + lane;
+        for (int64_t e0 = 0; e0 < lenw; e0 += G) {
+            int64_t e = rs + e0 + sub;
             bool keep = false;
             int32_t cj = -1;
-            if (e < re) {
+            if (have && e < re) {
                 cj = col[e];
                 keep = r_candidate(i, cj, sflag[e], cf);
                 if (keep && cnt > kmax) {
                     double a = fabs(val[e]);
                     int rank = 0;
-                    for (int64_t g = rs; g < re; ++g) {
-                        if (g == e || !r_candidate(i, col[g], sflag[g], cf)) continue;
-                        double b = fabs(val[g]);
-                        if (b > a || (b == a && col[g] < cj)) ++rank;
+                    for (int64_t q = rs; q < re; ++q) {
+                        if (q == e || !r_candidate(i, col[q], sflag[q], cf)) continue;
+                        double bq = fabs(val[q]);
+                        if (bq > a || (bq == a && col[q] < cj)) ++rank;
                     }
                     keep = rank < kmax;
                 }
             }
-            uint64_t m = __ballot(keep);
+            uint64_t m = __ballot(keep) & gmask;
             int pos = filled + __popcll(m & ((1ull << lane) - 1ull));
-            if (keep) cols[pos] = cj;
+            if (keep) cols[g][pos] = cj;
             filled += __popcll(m);
         }
+        if (sub == 0) kw[g] = K;
         __syncthreads();
-        // local matrix Mloc[r][c] = A(cols[c], cols[r]); rhs[r] = -A(i, cols[r])
-        for (int r = 0; r < K; ++r) Mloc[r * KLD + lane] = 0.0;
-        if (lane < K) rhs[lane] = 0.0;
+        int Kw = 0;
+        for (int q = 0; q < RPW; ++q) Kw = max(Kw, kw[q]);
+        for (int r = 0; r < G; ++r) Mloc[g][r * LD + sub] = 0.0;
+        rhs[g][sub] = 0.0;
         __syncthreads();
-        for (int c = 0; c < K; ++c) {
-            const int64_t jc = cols[c];
-            for (int64_t e = rowptr[jc] + lane; e < rowptr[jc + 1]; e += 64) {
+        // Mloc[r][c] = A(cols[c], cols[r]); rhs[r] = -A(i, cols[r])
+        for (int c = 0; c < Kw; ++c) {
+            const bool on = c < K;
+            const int64_t jc = on ? cols[g][c] : 0;
+            const int64_t js = on ? rowptr[jc] : 0, je = on ? rowptr[jc + 1] : 0;
+            for (int64_t e = js + sub; e < je; e += G) {
                 int32_t cc = col[e];
                 int lo = 0, hi = K - 1;
                 while (lo <= hi) {
                     int mid = (lo + hi) >> 1;
-                    int v = cols[mid];
-                    if (v == cc) { Mloc[mid * KLD + c] = val[e]; break; }
+                    int v = cols[g][mid];
+                    if (v == cc) { Mloc[g][mid * LD + c] = val[e]; break; }
                     if (v < cc) lo = mid + 1; else hi = mid - 1;
                 }
             }
         }
-        for (int64_t e = rs + lane; e < re; e += 64) {
+        for (int64_t e = rs + sub; e < re; e += G) {
             int32_t cc = col[e];
             int lo = 0, hi = K - 1;
             while (lo <= hi) {
                 int mid = (lo + hi) >> 1;
-                int v = cols[mid];
-                if (v == cc) { rhs[mid] = -val[e]; break; }
+                int v = cols[g][mid];
+                if (v == cc) { rhs[g][mid] = -val[e]; break; }
                 if (v < cc) lo = mid + 1; else hi = mid - 1;
             }
         }
         __syncthreads();
         bool sing = false;
-        for (int p = 0; p < K; ++p) {
-            double v = (lane >= p && lane < K) ? fabs(Mloc[lane * KLD + p]) : -1.0;
-            int idx = lane;
-            for (int d = 32; d >= 1; d >>= 1) {
+        for (int p = 0; p < Kw; ++p) {
+            const bool act = p < K && !sing;
+            double v = (act && sub >= p && sub < K) ? fabs(Mloc[g][sub * LD + p]) : -1.0;
+            int idx = sub;
+            for (int d = G / 2; d >= 1; d >>= 1) {
                 double ov = __shfl_xor(v, d, 64);
                 int oi = __shfl_xor(idx, d, 64);
                 if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
             }
+            if (act && !(v > 0.0)) sing = true;
+            const bool go = act && !sing;
             const int piv = idx;
-            if (!(v > 0.0)) { sing = true; break; }
-            if (piv != p) {
-                if (lane < K) {
-                    double t = Mloc[p * KLD + lane];
-                    Mloc[p * KLD + lane] = Mloc[piv * KLD + lane];
-                    Mloc[piv * KLD + lane] = t;
+            if (go && piv != p) {
+                if (sub < K) {
+                    double t = Mloc[g][p * LD + sub];
+                    Mloc[g][p * LD + sub] = Mloc[g][piv * LD + sub];
+                    Mloc[g][piv * LD + sub] = t;
                 }
-                if (lane == 0) { double t = rhs[p]; rhs[p] = rhs[piv]; rhs[piv] = t; }
+                if (sub == 0) { double t = rhs[g][p]; rhs[g][p] = rhs[g][piv]; rhs[g][piv] = t; }
             }
             __syncthreads();
-            if (lane > p && lane < K) {
-                double l = Mloc[lane * KLD + p] / Mloc[p * KLD + p];
-                for (int c = p + 1; c < K; ++c) Mloc[lane * KLD + c] -= l * Mloc[p * KLD + c];
-                rhs[lane] -= l * rhs[p];
+            if (go && sub > p && sub < K) {
+                double l = Mloc[g][sub * LD + p] / Mloc[g][p * LD + p];
+                for (int c = p + 1; c < K; ++c) Mloc[g][sub * LD + c] -= l * Mloc[g][p * LD + c];
+                rhs[g][sub] -= l * rhs[g][p];
             }
             __syncthreads();
         }
-        if (sing) {
-            if (lane == 0) atomicAdd(singular, 1);
-            if (lane < K) z[lane] = 0.0;
-        } else {
-            for (int r = K - 1; r >= 0; --r) {
-                double s = (lane > r && lane < K) ? Mloc[r * KLD + lane] * z[lane] : 0.0;
-                s = group_sum<64>(s);
-                if (lane == 0) z[r] = (rhs[r] - s) / Mloc[r * KLD + r];
-                __syncthreads();
-            }
-        }
+        z[g][sub] = 0.0;
         __syncthreads();
-        const int64_t base = r_rowptr[I];
-        int before = 0;   // how many kept columns are < i
-        {
-            bool lt = lane < K && cols[lane] < i;
-            before = __popcll(__ballot(lt));
+        for (int r = Kw - 1; r >= 0; --r) {
+            double sv = (!sing && r < K && sub > r && sub < K) ? Mloc[g][r * LD + sub] * z[g][sub] : 0.0;
+            sv = group_sum<G>(sv);
+            if (!sing && r < K && sub == 0) z[g][r] = (rhs[g][r] - sv) / Mloc[g][r * LD + r];
+            __syncthreads();
         }
-        if (lane < K) {
-            int pos = lane + (cols[lane] > i ? 1 : 0);
-            r_col[base + pos] = cols[lane];
-            r_val[base + pos] = z[lane];
-        }
-        if (lane == 0) {
-            r_col[base + before] = static_cast<int32_t>(i);
-            r_val[base + before] = 1.0;
+        if (have && sing && sub == 0) atomicAdd(singular, 1);
+        if (have) {
+            const int64_t rb = r_rowptr[I];
+            const bool lt = sub < K && cols[g][sub] < i;
+            const int before = __popcll(__ballot(lt) & gmask);
+            if (sub < K) {
+                int pos = sub + (cols[g][sub] > i ? 1 : 0);
+                r_col[rb + pos] = cols[g][sub];
+                r_val[rb + pos] = sing ? 0.0 : z[g][sub];
+            }
+            if (sub == 0) {
+                r_col[rb + before] = static_cast<int32_t>(i);
+                r_val[rb + before] = 1.0;
+            }
         }
         __syncthreads();
     }
+}
+
+__global__ void k_r_class(int64_t nc, const int64_t* __restrict__ r_rowptr, int lo, int hi,
+                          int32_t* __restrict__ list, int* __restrict__ count) {
+    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int K = static_cast<int>(r_rowptr[I + 1] - r_rowptr[I]) - 1;
+    if (K > lo && K <= hi) list[atomicAdd(count, 1)] = static_cast<int32_t>(I);
 }
 
 // ------------------------------------------------------------- R A P
@@ -557,74 +595,161 @@ __global__ void k_dense_from_csr(int nmem, const int64_t* __restrict__ moff,
     }
 }
 
-// Gauss-Jordan with partial pivoting, one block per member; the inverse is
-// written column-major (inv[c * n + r]) so the per-cycle product reads it coalesced.
+// Coarsest levels up to kLdsDense rows: LU with partial pivoting in LDS, then
+// every thread solves for one column of the inverse.  The inverse is written
+// column-major (inv[c * n + r] = (A^{-1})_{rc}) so the per-cycle product reads it
+// coalesced.
+constexpr int kLdsDense = 88;
+
+__global__ void __launch_bounds__(256)
+k_dense_inverse_lds(int nmem, const int64_t* __restrict__ moff, const int64_t* __restrict__ mn,
+                    const int64_t* __restrict__ inv_off, const int64_t* __restrict__ rowptr,
+                    const int32_t* __restrict__ col, const double* __restrict__ val,
+                    double* __restrict__ inv, int* __restrict__ singular) {
+    __shared__ double A[kLdsDense * kLdsDense];
+    __shared__ int perm[kLdsDense];
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    const int m = blockIdx.x;
+    if (m >= nmem) return;
+    const int n = static_cast<int>(mn[m]);
+    if (n > kLdsDense) return;
+    const int64_t o = moff[m];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n * n; i += 256) A[i] = 0.0;
+    for (int i = tid; i < n; i += 256) perm[i] = i;
+    __syncthreads();
+    for (int r = 0; r < n; ++r)
+        for (int64_t e = rowptr[o + r] + tid; e < rowptr[o + r + 1]; e += 256)
+            A[r * n + (col[e] - o)] = val[e];
+    __syncthreads();
+    for (int p = 0; p < n; ++p) {
+        double best = -1.0;
+        int bi = n;
+        for (int r = p + tid; r < n; r += 256) {
+            double v = fabs(A[r * n + p]);
+            if (v > best) { best = v; bi = r; }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st) {
+                double ov = sv[tid + st];
+                int oi = si[tid + st];
+                if (ov > sv[tid] || (ov == sv[tid] && oi < si[tid])) { sv[tid] = ov; si[tid] = oi; }
+            }
+            __syncthreads();
+        }
+        const int piv = si[0];
+        const bool ok = sv[0] > 0.0;
+        __syncthreads();
+        if (!ok) {
+            if (tid == 0) atomicAdd(singular, 1);
+            return;
+        }
+        if (piv != p) {
+            for (int c = tid; c < n; c += 256) {
+                double t = A[p * n + c]; A[p * n + c] = A[piv * n + c]; A[piv * n + c] = t;
+            }
+            if (tid == 0) { int t = perm[p]; perm[p] = perm[piv]; perm[piv] = t; }
+        }
+        __syncthreads();
+        const double d = A[p * n + p];
+        for (int r = p + 1 + tid; r < n; r += 256) A[r * n + p] /= d;
+        __syncthreads();
+        const int rem = n - p - 1;
+        for (int idx = tid; idx < rem * rem; idx += 256) {
+            int r = p + 1 + idx / rem, c = p + 1 + idx % rem;
+            A[r * n + c] -= A[r * n + p] * A[p * n + c];
+        }
+        __syncthreads();
+    }
+    // column c of the inverse: L U x = P e_c
+    double* Inv = inv + inv_off[m];
+    for (int c = tid; c < n; c += 256) {
+        double* x = Inv + static_cast<int64_t>(c) * n;
+        for (int i = 0; i < n; ++i) {
+            double s = perm[i] == c ? 1.0 : 0.0;
+            for (int j = 0; j < i; ++j) s -= A[i * n + j] * x[j];
+            x[i] = s;
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = x[i];
+            for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+            x[i] = s / A[i * n + i];
+        }
+    }
+}
+
+// Larger coarsest levels (coarsening stalled): Gauss-Jordan with partial
+// pivoting on the augmented matrix in global memory, one block per member.
 __global__ void __launch_bounds__(256)
 k_gauss_jordan(int nmem, const int64_t* __restrict__ mn, const int64_t* __restrict__ inv_off,
                double* __restrict__ work, double* __restrict__ inv, int* __restrict__ singular) {
     __shared__ double sv[256];
     __shared__ int si[256];
-    __shared__ double prow_scale;
-    __shared__ int s_piv;
-    int m = blockIdx.x;
+    __shared__ double colp[2048];
+    const int m = blockIdx.x;
     if (m >= nmem) return;
-    const int64_t n = mn[m];
-    const int64_t w2 = 2 * n;
+    const int n = static_cast<int>(mn[m]);
+    if (n <= kLdsDense) return;
+    const int w2 = 2 * n;
     double* W = work + 2 * inv_off[m];
     const int tid = threadIdx.x;
-    for (int64_t p = 0; p < n; ++p) {
+    for (int p = 0; p < n; ++p) {
         double best = -1.0;
-        int bi = -1;
-        for (int64_t r = p + tid; r < n; r += 256) {
-            double v = fabs(W[r * w2 + p]);
-            if (v > best) { best = v; bi = static_cast<int>(r); }
+        int bi = n;
+        for (int r = p + tid; r < n; r += 256) {
+            double v = fabs(W[static_cast<int64_t>(r) * w2 + p]);
+            if (v > best) { best = v; bi = r; }
         }
         sv[tid] = best;
         si[tid] = bi;
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) {
-                double ov = sv[tid + s];
-                int oi = si[tid + s];
-                if (ov > sv[tid] || (ov == sv[tid] && oi >= 0 && (si[tid] < 0 || oi < si[tid]))) {
-                    sv[tid] = ov;
-                    si[tid] = oi;
-                }
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st) {
+                double ov = sv[tid + st];
+                int oi = si[tid + st];
+                if (ov > sv[tid] || (ov == sv[tid] && oi < si[tid])) { sv[tid] = ov; si[tid] = oi; }
             }
             __syncthreads();
         }
-        if (tid == 0) {
-            s_piv = si[0];
-            if (!(sv[0] > 0.0)) { atomicAdd(singular, 1); s_piv = -1; }
-        }
+        const int piv = si[0];
+        const bool ok = sv[0] > 0.0;
         __syncthreads();
-        const int piv = s_piv;
-        if (piv < 0) return;
+        if (!ok) {
+            if (tid == 0) atomicAdd(singular, 1);
+            return;
+        }
+        double* Wp = W + static_cast<int64_t>(p) * w2;
         if (piv != p) {
-            for (int64_t c = tid; c < w2; c += 256) {
-                double t = W[p * w2 + c];
-                W[p * w2 + c] = W[piv * w2 + c];
-                W[piv * w2 + c] = t;
-            }
+            double* Wq = W + static_cast<int64_t>(piv) * w2;
+            for (int c = tid; c < w2; c += 256) { double t = Wp[c]; Wp[c] = Wq[c]; Wq[c] = t; }
             __syncthreads();
         }
-        if (tid == 0) prow_scale = 1.0 / W[p * w2 + p];
+        const double sc = 1.0 / Wp[p];
         __syncthreads();
-        for (int64_t c = tid; c < w2; c += 256) W[p * w2 + c] *= prow_scale;
+        for (int c = tid; c < w2; c += 256) Wp[c] *= sc;
+        for (int r = tid; r < n; r += 256) colp[r] = W[static_cast<int64_t>(r) * w2 + p];
         __syncthreads();
-        for (int64_t idx = tid; idx < n * w2; idx += 256) {
-            int64_t r = idx / w2, c = idx % w2;
-            if (r == p || c == p) continue;
-            double f = W[r * w2 + p];
-            if (f != 0.0) W[idx] -= f * W[p * w2 + c];
+        // each thread owns a set of columns and streams down the rows
+        for (int c = tid; c < w2; c += 256) {
+            if (c == p) continue;
+            const double pc = Wp[c];
+            if (pc == 0.0) continue;
+            for (int r = 0; r < n; ++r) {
+                if (r == p) continue;
+                W[static_cast<int64_t>(r) * w2 + c] -= colp[r] * pc;
+            }
         }
         __syncthreads();
-        for (int64_t r = tid; r < n; r += 256)
-            if (r != p) W[r * w2 + p] = 0.0;
+        for (int r = tid; r < n; r += 256)
+            if (r != p) W[static_cast<int64_t>(r) * w2 + p] = 0.0;
         __syncthreads();
     }
     double* Inv = inv + inv_off[m];
-    for (int64_t idx = tid; idx < n * n; idx += 256) {
+    for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += 256) {
         int64_t r = idx / n, c = idx % n;
         Inv[c * n + r] = W[r * w2 + n + c];
     }
@@ -671,17 +796,24 @@ void Hierarchy::coarse_setup(Level& L, const std::vector<int>& members) {
     h2d(L.coarse_n_d.p, mn.data(), nm, s_);
     h2d(L.coarse_inv_off_d.p, ioff.data(), nm + 1, s_);
     L.coarse_inv.alloc(ioff[nm]);
-    DBuf<double> work(2 * ioff[nm]);
     DBuf<int> sing(1);
     PAIR_HIP(hipMemsetAsync(sing.p, 0, sizeof(int), s_));
-    int64_t maxn = *std::max_element(mn.begin(), mn.end());
-    hipLaunchKernelGGL(k_dense_from_csr, dim3(grid_for(maxn, 1), nm), dim3(256), 0, s_, nm,
-                       L.coarse_off_d.p, L.coarse_n_d.p, L.coarse_inv_off_d.p, L.A.rowptr.p,
-                       L.A.col.p, L.A.val.p, work.p);
+    hipLaunchKernelGGL(k_dense_inverse_lds, dim3(nm), dim3(256), 0, s_, nm, L.coarse_off_d.p,
+                       L.coarse_n_d.p, L.coarse_inv_off_d.p, L.A.rowptr.p, L.A.col.p, L.A.val.p,
+                       L.coarse_inv.p, sing.p);
     PAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(nm), dim3(256), 0, s_, nm, L.coarse_n_d.p,
-                       L.coarse_inv_off_d.p, work.p, L.coarse_inv.p, sing.p);
-    PAIR_LAUNCH_CHECK();
+    const int64_t maxn = *std::max_element(mn.begin(), mn.end());
+    if (maxn > kLdsDense) {
+        DBuf<double> work(2 * ioff[nm]);
+        hipLaunchKernelGGL(k_dense_from_csr, dim3(grid_for(maxn, 1), nm), dim3(256), 0, s_, nm,
+                           L.coarse_off_d.p, L.coarse_n_d.p, L.coarse_inv_off_d.p, L.A.rowptr.p,
+                           L.A.col.p, L.A.val.p, work.p);
+        PAIR_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(nm), dim3(256), 0, s_, nm, L.coarse_n_d.p,
+                           L.coarse_inv_off_d.p, work.p, L.coarse_inv.p, sing.p);
+        PAIR_LAUNCH_CHECK();
+        PAIR_HIP(hipStreamSynchronize(s_));
+    }
     int hs = 0;
     d2h(&hs, sing.p, 1, s_);
     PAIR_HIP(hipStreamSynchronize(s_));
@@ -694,8 +826,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
     PAIR_CHECK(prm_.kmax >= 1 && prm_.kmax <= KCAP, "kmax must be in [1, 64]");
     levels_.clear();
     nlev_.assign(B_, 0);
-    if (graph_exec_) { (void)hipGraphExecDestroy(graph_exec_); graph_exec_ = nullptr; }
-    if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
+    drop_graph();
 
     levels_.emplace_back();
     levels_[0].A = std::move(A0);
@@ -821,8 +952,8 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         {
             DBuf<unsigned long long> cc(4);
             PAIR_HIP(hipMemsetAsync(cc.p, 0, 4 * sizeof(unsigned long long), s_));
-            hipLaunchKernelGGL(k_cf_counts, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
-                               L.A.rowptr.p, L.cf.p, cc.p);
+            const unsigned g = static_cast<unsigned>(std::min<int64_t>(grid_for(n, 256), 1024));
+            hipLaunchKernelGGL(k_cf_counts, dim3(g), dim3(256), 0, s_, n, L.A.rowptr.p, L.cf.p, cc.p);
             PAIR_LAUNCH_CHECK();
             unsigned long long h[4];
             d2h(h, cc.p, 4, s_);
@@ -849,13 +980,37 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.nnz = exclusive_scan(rcnt.p, L.R.rowptr.p, total_c, s_);
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
-        PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
         {
-            unsigned g = static_cast<unsigned>(std::min<int64_t>(total_c, 1 << 20));
-            hipLaunchKernelGGL(k_r_build, dim3(g), dim3(64), 0, s_, total_c, c2f.p, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, L.R.rowptr.p,
-                               L.R.col.p, L.R.val.p, d_counter.p);
-            PAIR_LAUNCH_CHECK();
+            DBuf<int32_t> rlist(total_c);
+            DBuf<int> rcount(1), rsing(1);
+            PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
+            const int bounds[4] = {-1, 16, 32, 64};
+            for (int c = 0; c < 3; ++c) {
+                PAIR_HIP(hipMemsetAsync(rcount.p, 0, sizeof(int), s_));
+                hipLaunchKernelGGL(k_r_class, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
+                                   L.R.rowptr.p, bounds[c], bounds[c + 1], rlist.p, rcount.p);
+                PAIR_LAUNCH_CHECK();
+                int nr = 0;
+                d2h(&nr, rcount.p, 1, s_);
+                PAIR_HIP(hipStreamSynchronize(s_));
+                if (nr == 0) continue;
+                const int rpw = c == 0 ? 4 : (c == 1 ? 2 : 1);
+                const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
+                if (c == 0)
+                    hipLaunchKernelGGL(k_r_build<16>, dim3(g), dim3(64), 0, s_, nr, rlist.p, c2f.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
+                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
+                else if (c == 1)
+                    hipLaunchKernelGGL(k_r_build<32>, dim3(g), dim3(64), 0, s_, nr, rlist.p, c2f.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
+                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
+                else
+                    hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, nr, rlist.p, c2f.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
+                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
+                PAIR_LAUNCH_CHECK();
+            }
+            PAIR_HIP(hipMemcpyAsync(d_counter.p, rsing.p, sizeof(int), hipMemcpyDeviceToDevice, s_));
         }
         int nsing = 0;
         d2h(&nsing, d_counter.p, 1, s_);
@@ -978,14 +1133,11 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
     sb_.n_active.alloc(1);
     int64_t maxcnt = 1;
     for (int b = 0; b < B_; ++b) maxcnt = std::max(maxcnt, levels_[0].cnt[b]);
-    sb_.chunks = static_cast<int>((maxcnt + 2047) / 2048);
+    sb_.chunks = static_cast<int>((maxcnt + 511) / 512);
     sb_.partial.alloc(static_cast<size_t>(sb_.chunks) * B_);
     PAIR_HIP(hipStreamSynchronize(s_));
 }
 
-Hierarchy::~Hierarchy() {
-    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
-    if (graph_) (void)hipGraphDestroy(graph_);
-}
+Hierarchy::~Hierarchy() { drop_graph(); }
 
 }  // namespace pair

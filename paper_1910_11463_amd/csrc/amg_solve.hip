@@ -21,7 +21,7 @@ namespace pair {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kChunk = 2048;   // rows per partial sum of the norm kernels
+constexpr int kChunk = 512;    // rows per partial sum of the norm kernels
 
 template <int LPR>
 __global__ void __launch_bounds__(kBlock)
@@ -160,20 +160,33 @@ k_norm_partial(int mode, int chunks, const int64_t* __restrict__ moff,
 
 // mode 0: |b|^2 and initial state.  mode 1: |r|^2, relative residual, cycle
 // count and the active mask of every member; counts members still active.
-__global__ void k_norm_finalize(int mode, int B, int chunks, const int64_t* __restrict__ moff,
-                                const double* __restrict__ partial, double* __restrict__ bnorm2,
-                                double* __restrict__ rnorm2, double* __restrict__ relres,
-                                double* __restrict__ relres0, int* __restrict__ iters,
-                                uint8_t* __restrict__ active, int* __restrict__ n_active,
-                                double tol, int max_iter, int x_zero) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+// mode 2: initial residual of a nonzero guess.  One block per member; the
+// partial sums are added in a fixed order (strided per thread, then a fixed
+// tree), so the result is reproducible.
+__global__ void __launch_bounds__(256)
+k_norm_finalize(int mode, int B, int chunks, const int64_t* __restrict__ moff,
+                const double* __restrict__ partial, double* __restrict__ bnorm2,
+                double* __restrict__ rnorm2, double* __restrict__ relres,
+                double* __restrict__ relres0, int* __restrict__ iters,
+                uint8_t* __restrict__ active, int* __restrict__ n_active, double tol,
+                int max_iter, int x_zero) {
+    __shared__ double red[4];
+    const int m = blockIdx.x;
     if (m >= B) return;
     if (moff[m] < 0) {
-        if (mode == 0) { active[m] = 0; iters[m] = 0; relres[m] = 0.0; relres0[m] = 0.0; }
+        if (mode == 0 && threadIdx.x == 0) {
+            active[m] = 0; iters[m] = 0; relres[m] = 0.0; relres0[m] = 0.0;
+        }
         return;
     }
+    if (mode != 0 && !active[m]) return;
     double s = 0.0;
-    for (int c = 0; c < chunks; ++c) s += partial[static_cast<int64_t>(m) * chunks + c];
+    for (int c = threadIdx.x; c < chunks; c += blockDim.x) s += partial[static_cast<int64_t>(m) * chunks + c];
+    s = group_sum<64>(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    s = (red[0] + red[1]) + (red[2] + red[3]);
     if (mode == 0) {
         bnorm2[m] = s;
         iters[m] = 0;
@@ -189,12 +202,11 @@ __global__ void k_norm_finalize(int mode, int B, int chunks, const int64_t* __re
         }
         return;
     }
-    if (!active[m]) return;
     rnorm2[m] = s;
     const double bb = bnorm2[m];
     // relative residual; absolute when b = 0 (the solution is then x = 0)
     const double rel = bb > 0.0 ? sqrt(s / bb) : sqrt(s);
-    if (mode == 2) {   // initial residual of a nonzero guess
+    if (mode == 2) {
         relres[m] = rel;
         relres0[m] = rel;
         active[m] = (rel > tol) ? 1 : 0;
@@ -209,7 +221,130 @@ __global__ void k_norm_finalize(int mode, int B, int chunks, const int64_t* __re
     if (go) atomicAdd(n_active, 1);
 }
 
+// ---------------------------------------------------------------- finest level, element blocks
+// Off-diagonal part of row `row` of an element-block operator times x.
+template <int K, int NF>
+__device__ __forceinline__ double ell_offdiag(int64_t row, int64_t n, int64_t nel,
+                                              const int32_t* __restrict__ nbr,
+                                              const int32_t* __restrict__ nodes,
+                                              const double* __restrict__ val,
+                                              const double* __restrict__ x) {
+    const int64_t g = row / K;
+    double s = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+        const int32_t U = nbr[sl * nel + g];
+        if (U < 0) continue;
+        const int pk = nodes[sl * nel + g];
+        const double* xu = x + static_cast<int64_t>(U) * K;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) s += val[(sl * NF + j) * n + row] * xu[(pk >> (3 * j)) & 7];
+    }
+    return s;
+}
+
+template <int K, int NF>
+__global__ void __launch_bounds__(kBlock)
+k_ell_relax(int64_t n, int64_t nel, const int32_t* __restrict__ nbr,
+            const int32_t* __restrict__ nodes, const double* __restrict__ val,
+            const int8_t* __restrict__ cf, int8_t which, const uint16_t* __restrict__ seg,
+            const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
+            const double* __restrict__ b, const double* __restrict__ xin, double* __restrict__ xout,
+            double omega, int xin_zero) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
+    if (row >= n) return;
+    const int m = seg[row];
+    if (!(active[m] && relax[m])) return;
+    const double xi = xin_zero ? 0.0 : xin[row];
+    if (cf[row] != which) {
+        xout[row] = xi;
+        return;
+    }
+    // unit diagonal: (A x)_row = x_row + offdiag
+    const double ax = xin_zero ? 0.0 : xi + ell_offdiag<K, NF>(row, n, nel, nbr, nodes, val, xin);
+    xout[row] = xi + omega * (b[row] - ax);
+}
+
+template <int K, int NF>
+__global__ void __launch_bounds__(kBlock)
+k_ell_residual(int64_t n, int64_t nel, const int32_t* __restrict__ nbr,
+               const int32_t* __restrict__ nodes, const double* __restrict__ val,
+               const uint16_t* __restrict__ seg, const uint8_t* __restrict__ active,
+               const uint8_t* __restrict__ relax, const double* __restrict__ b,
+               const double* __restrict__ x, double* __restrict__ r) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
+    if (row >= n) return;
+    const int m = seg[row];
+    if (!(active[m] && relax[m])) return;
+    r[row] = b[row] - (x[row] + ell_offdiag<K, NF>(row, n, nel, nbr, nodes, val, x));
+}
+
+template <int K, int NF>
+__global__ void __launch_bounds__(kBlock)
+k_ell_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* __restrict__ mcnt,
+                   int64_t n, int64_t nel, const int32_t* __restrict__ nbr,
+                   const int32_t* __restrict__ nodes, const double* __restrict__ val,
+                   const uint8_t* __restrict__ active, const double* __restrict__ b,
+                   const double* __restrict__ x, double* __restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    const int m = blockIdx.y;
+    const int chunk = blockIdx.x;
+    double acc = 0.0;
+    if (moff[m] >= 0 && active[m]) {
+        const int64_t begin = moff[m] + static_cast<int64_t>(chunk) * kChunk;
+        const int64_t end = moff[m] + mcnt[m];
+        for (int64_t row = begin + threadIdx.x; row < begin + kChunk && row < end; row += kBlock) {
+            const double v = b[row] - (x[row] + ell_offdiag<K, NF>(row, n, nel, nbr, nodes, val, x));
+            acc += v * v;
+        }
+    }
+    acc = group_sum<64>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+        partial[static_cast<int64_t>(m) * chunks + chunk] = s;
+    }
+}
+
+template <class F>
+void dispatch_ell(const FineEll& e, F&& f) {
+    if (e.k == 8) f(std::integral_constant<int, 8>(), std::integral_constant<int, 4>());
+    else f(std::integral_constant<int, 4>(), std::integral_constant<int, 3>());
+}
+
+double ell_relax_bytes(const Level& L, const FineEll& e, int which, bool zero) {
+    const double n = static_cast<double>(L.n_f + L.n_c);
+    const double nr = static_cast<double>(which < 0 ? L.n_f : L.n_c);
+    if (zero) return 8.0 * nr + n * (8.0 + 3.0);
+    return nr * (24.0 * e.nf + 8.0) + n * (8.0 + 8.0 + 3.0) + 24.0 * static_cast<double>(e.nel);
+}
+
+double ell_residual_bytes(const Level& L, const FineEll& e) {
+    const double n = static_cast<double>(L.n_f + L.n_c);
+    return n * (24.0 * e.nf + 8.0 + 8.0 + 8.0 + 2.0) + 24.0 * static_cast<double>(e.nel);
+}
+
 __global__ void k_zero_int(int* p) { *p = 0; }
+
+__global__ void __launch_bounds__(kBlock)
+k_zero_rows(int64_t n, const uint16_t* __restrict__ seg, const uint8_t* __restrict__ active,
+            const uint8_t* __restrict__ relax, double* __restrict__ x) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
+    if (row >= n) return;
+    const int m = seg[row];
+    if (active[m] && relax[m]) x[row] = 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_copy_rows(int64_t n, const uint16_t* __restrict__ seg, const uint8_t* __restrict__ active,
+            const uint8_t* __restrict__ relax, const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
+    if (row >= n) return;
+    const int m = seg[row];
+    if (active[m] && relax[m]) dst[row] = src[row];
+}
 
 template <class F>
 void dispatch_lpr(int lpr, F&& f) {
@@ -252,9 +387,51 @@ double restrict_bytes(const Level& L) {
 
 }  // namespace
 
+// Half-sweeps of a schedule ("FC", "FFC", ...) alternating between two buffers;
+// returns the buffer holding the result.  `zero`: cur is known to be 0 (the
+// first half-sweep then reads neither the matrix nor cur).
+double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur, double* other,
+                          bool zero) {
+    const int64_t n = L.A.n;
+    const uint8_t* act = sb_.active.p;
+    const int kind = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
+    for (char ch : sched) {
+        const int8_t which = ch == 'F' ? -1 : 1;
+        if (l == 0 && ell_) {
+            const FineEll& E = *ell_;
+            dispatch_ell(E, [&](auto kc, auto fc) {
+                constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
+                int h = prof_begin(s_, kind);
+                hipLaunchKernelGGL((k_ell_relax<K, NF>), dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_,
+                                   n, E.nel, E.nbr.p, E.nodes.p, E.val.p, L.cf.p, which, L.seg.p, act,
+                                   L.relax.p, L.b.p, cur, other, prm_.omega, zero ? 1 : 0);
+                prof_end(s_, h, ell_relax_bytes(L, E, which, zero));
+            });
+            PAIR_LAUNCH_CHECK();
+            std::swap(cur, other);
+            zero = false;
+            continue;
+        }
+        dispatch_lpr(L.lpr, [&](auto lc) {
+            constexpr int LPR = decltype(lc)::value;
+            const unsigned g = grid_xcd(n, kBlock / LPR);
+            int h = prof_begin(s_, kind);
+            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, which, L.seg.p, act,
+                               L.relax.p, L.b.p, cur, other, prm_.omega, zero ? 1 : 0);
+            prof_end(s_, h, relax_bytes(L, which, zero));
+        });
+        PAIR_LAUNCH_CHECK();
+        std::swap(cur, other);
+        zero = false;
+    }
+    return cur;
+}
+
 void Hierarchy::vcycle_launches(bool x_is_zero) {
     const int nl = static_cast<int>(levels_.size());
     const uint8_t* act = sb_.active.p;
+    std::vector<double*> cur(nl, nullptr);
     // down
     for (int l = 0; l < nl; ++l) {
         Level& L = levels_[l];
@@ -268,24 +445,29 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
         }
         if (!has_relax) break;
         const int64_t n = L.A.n;
-        const int xz = (l == 0) ? (x_is_zero ? 1 : 0) : 1;
-        const int kind_relax = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
-        dispatch_lpr(L.lpr, [&](auto lc) {
+        const bool zero = (l == 0) ? x_is_zero : true;
+        if (zero && prm_.relax_pre.empty()) {
+            hipLaunchKernelGGL(k_zero_rows, dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_, n, L.seg.p,
+                               act, L.relax.p, L.x.p);
+            PAIR_LAUNCH_CHECK();
+        }
+        cur[l] = sweeps(L, l, prm_.relax_pre, L.x.p, L.t.p, zero);
+        if (l == 0 && ell_) {
+            const FineEll& E = *ell_;
+            dispatch_ell(E, [&](auto kc, auto fc) {
+                constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
+                int h = prof_begin(s_, PROF_RESIDUAL_FINE);
+                hipLaunchKernelGGL((k_ell_residual<K, NF>), dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0,
+                                   s_, n, E.nel, E.nbr.p, E.nodes.p, E.val.p, L.seg.p, act, L.relax.p,
+                                   L.b.p, cur[l], L.r.p);
+                prof_end(s_, h, ell_residual_bytes(L, E));
+            });
+        } else dispatch_lpr(L.lpr, [&](auto lc) {
             constexpr int LPR = decltype(lc)::value;
             const unsigned g = grid_xcd(n, kBlock / LPR);
-            int h = prof_begin(s_, kind_relax);
-            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(-1),
-                               L.seg.p, act, L.relax.p, L.b.p, L.x.p, L.t.p, prm_.omega, xz);
-            prof_end(s_, h, relax_bytes(L, -1, xz != 0));
-            h = prof_begin(s_, kind_relax);
-            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(1),
-                               L.seg.p, act, L.relax.p, L.b.p, L.t.p, L.x.p, prm_.omega, 0);
-            prof_end(s_, h, relax_bytes(L, 1, false));
-            h = prof_begin(s_, l == 0 ? PROF_RESIDUAL_FINE : PROF_NKINDS);
+            int h = prof_begin(s_, l == 0 ? PROF_RESIDUAL_FINE : PROF_NKINDS);
             hipLaunchKernelGGL(k_residual<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, L.seg.p, act, L.relax.p, L.b.p, L.x.p, L.r.p);
+                               L.A.col.p, L.A.val.p, L.seg.p, act, L.relax.p, L.b.p, cur[l], L.r.p);
             prof_end(s_, h, residual_bytes(L));
         });
         PAIR_LAUNCH_CHECK();
@@ -306,32 +488,45 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
         if (L.R.n == 0) continue;
         Level& C = levels_[l + 1];
         const int64_t n = L.A.n;
+        double* c = cur[l];
+        double* o = c == L.x.p ? L.t.p : L.x.p;
         hipLaunchKernelGGL(k_interpolate, dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_, n, L.p.p,
-                           L.seg.p, act, L.relax.p, C.x.p, L.x.p);
-        const int kind_relax = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
-        dispatch_lpr(L.lpr, [&](auto lc) {
-            constexpr int LPR = decltype(lc)::value;
-            const unsigned g = grid_xcd(n, kBlock / LPR);
-            int h = prof_begin(s_, kind_relax);
-            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(-1),
-                               L.seg.p, act, L.relax.p, L.b.p, L.x.p, L.t.p, prm_.omega, 0);
-            prof_end(s_, h, relax_bytes(L, -1, false));
-            h = prof_begin(s_, kind_relax);
-            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, static_cast<int8_t>(1),
-                               L.seg.p, act, L.relax.p, L.b.p, L.t.p, L.x.p, prm_.omega, 0);
-            prof_end(s_, h, relax_bytes(L, 1, false));
-        });
+                           L.seg.p, act, L.relax.p, C.x.p, c);
         PAIR_LAUNCH_CHECK();
+        double* fin = sweeps(L, l, prm_.relax_post, c, o, false);
+        if (fin != L.x.p) {
+            hipLaunchKernelGGL(k_copy_rows, dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_, n, L.seg.p,
+                               act, L.relax.p, fin, L.x.p);
+            PAIR_LAUNCH_CHECK();
+        }
     }
+}
+
+void Hierarchy::drop_graph() {
+    if (graph_exec_) { (void)hipGraphExecDestroy(graph_exec_); graph_exec_ = nullptr; }
+    if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
+}
+
+void Hierarchy::set_params(const AmgParams& p) {
+    prm_ = p;
+    drop_graph();
 }
 
 void Hierarchy::launch_cycle_and_test(bool x_is_zero, int /*it_offset*/) {
     Level& L0 = levels_[0];
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sb_.n_active.p);
     vcycle_launches(x_is_zero);
-    dispatch_lpr(L0.lpr, [&](auto lc) {
+    if (ell_) {
+        const FineEll& E = *ell_;
+        dispatch_ell(E, [&](auto kc, auto fc) {
+            constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
+            int h = prof_begin(s_, PROF_NORM_FINE);
+            hipLaunchKernelGGL((k_ell_norm_partial<K, NF>), dim3(sb_.chunks, B_), dim3(kBlock), 0, s_,
+                               sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.n, E.nel, E.nbr.p, E.nodes.p,
+                               E.val.p, sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+            prof_end(s_, h, ell_residual_bytes(L0, E) - 8.0 * L0.A.n);
+        });
+    } else dispatch_lpr(L0.lpr, [&](auto lc) {
         constexpr int LPR = decltype(lc)::value;
         int h = prof_begin(s_, PROF_NORM_FINE);
         hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sb_.chunks, B_), dim3(kBlock), 0, s_, 1,
@@ -339,7 +534,7 @@ void Hierarchy::launch_cycle_and_test(bool x_is_zero, int /*it_offset*/) {
                            sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
         prof_end(s_, h, 12.0 * L0.A.nnz + 8.0 * L0.A.n * 3.0);
     });
-    hipLaunchKernelGGL(k_norm_finalize, dim3(grid_for(B_, 64)), dim3(64), 0, s_, 1, B_, sb_.chunks,
+    hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 1, B_, sb_.chunks,
                        moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p, sb_.relres.p,
                        sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p, prm_.tol,
                        prm_.max_iter, 0);
@@ -362,7 +557,7 @@ bool Hierarchy::solve(bool use_graph, bool x_is_zero) {
                            sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p, L0.A.val.p,
                            sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
     });
-    hipLaunchKernelGGL(k_norm_finalize, dim3(grid_for(B_, 64)), dim3(64), 0, s_, 0, B_, sb_.chunks,
+    hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 0, B_, sb_.chunks,
                        moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p, sb_.relres.p,
                        sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p, prm_.tol,
                        prm_.max_iter, x_is_zero ? 1 : 0);
@@ -374,7 +569,7 @@ bool Hierarchy::solve(bool use_graph, bool x_is_zero) {
                                sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p,
                                L0.A.val.p, sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
         });
-        hipLaunchKernelGGL(k_norm_finalize, dim3(grid_for(B_, 64)), dim3(64), 0, s_, 2, B_,
+        hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 2, B_,
                            sb_.chunks, moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p,
                            sb_.relres.p, sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p,
                            prm_.tol, prm_.max_iter, 0);

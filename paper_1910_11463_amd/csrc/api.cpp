@@ -86,6 +86,16 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.tol_inner > 0.0 && o.tol_outer > 0.0, "tolerances must be positive");
     PAIR_CHECK(o.max_inner >= 1 && o.max_outer >= 1, "iteration limits must be >= 1");
     PAIR_CHECK(o.batch_size >= 0, "batch_size must be >= 0");
+    auto sched_ok = [](const char* c) {
+        size_t n = strnlen(c, 8);
+        if (n >= 8) return false;
+        for (size_t i = 0; i < n; ++i)
+            if (c[i] != 'F' && c[i] != 'C') return false;
+        return true;
+    };
+    PAIR_CHECK(sched_ok(o.relax_pre) && sched_ok(o.relax_post),
+               "relax_pre / relax_post: up to 7 characters from {F, C}");
+    PAIR_CHECK(strnlen(o.relax_pre, 8) + strnlen(o.relax_post, 8) >= 1, "no relaxation at all");
 }
 
 hipStream_t make_stream(void* user, bool& own) {
@@ -154,7 +164,7 @@ void pair_default_options(pair_options* o) {
     o->theta = 0.25;
     o->eps_r = 0.01;
     o->omega = 1.0;
-    o->coarse_max = 256;
+    o->coarse_max = 64;
     o->max_levels = 25;
     o->max_coarse_ratio = 0.9;
     o->kmax = 64;
@@ -170,6 +180,8 @@ void pair_default_options(pair_options* o) {
     o->batch_size = 0;
     o->use_graph = 1;
     o->allow_any_weight_sum = 0;
+    std::strcpy(o->relax_pre, "FC");
+    std::strcpy(o->relax_post, "FC");
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
@@ -207,7 +219,9 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
             opt->theta != c.opt.theta || opt->eps_r != c.opt.eps_r || opt->coarse_max != c.opt.coarse_max ||
             opt->max_levels != c.opt.max_levels || opt->max_coarse_ratio != c.opt.max_coarse_ratio ||
             opt->kmax != c.opt.kmax || opt->pmis_seed != c.opt.pmis_seed ||
-            opt->batch_size != c.opt.batch_size;
+            opt->batch_size != c.opt.batch_size ||
+            std::strncmp(opt->relax_pre, c.opt.relax_pre, 8) != 0 ||
+            std::strncmp(opt->relax_post, c.opt.relax_post, 8) != 0;
         c.opt = *opt;
         if (amg_changed) invalidate(c);
         AmgParams p = c.amg_params();
@@ -731,6 +745,8 @@ int pair_amg_setup(pair_amg* amg, int n_seg, const int64_t* seg_rows, int64_t n,
         p.seed = amg->opt.pmis_seed;
         p.tol = amg->opt.tol_inner;
         p.max_iter = amg->opt.max_inner;
+        p.relax_pre = amg->opt.relax_pre;
+        p.relax_post = amg->opt.relax_post;
         amg->H.reset(new Hierarchy(p, amg->s));
         amg->H->setup(std::move(A), off, cnt);
         amg->n_seg = n_seg;

@@ -272,7 +272,8 @@ k_fine_hex(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
            const double* __restrict__ omega, const int* __restrict__ dirs, int B,
            const double* __restrict__ sigt, const int64_t* __restrict__ elem_off,
            int64_t* __restrict__ rowptr, int32_t* __restrict__ col, double* __restrict__ val,
-           double* __restrict__ dinv, int* __restrict__ bad) {
+           double* __restrict__ dinv, int* __restrict__ bad, int32_t* __restrict__ ell_nbr,
+           int32_t* __restrict__ ell_nodes, double* __restrict__ ell_val) {
     int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= E * B) return;
     const int b = static_cast<int>(g / E);
@@ -312,6 +313,22 @@ k_fine_hex(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
     const int64_t row0 = static_cast<int64_t>(b) * N + 8 * e;
     const int64_t base = elem_off[g];
     const int64_t coff = static_cast<int64_t>(b) * N;   // column offset of this member
+    // element-block (ELL) copy of the off-diagonal blocks: slot = face axis
+    const int64_t nrows = N * B, nel = E * B;
+    for (int sl = 0; sl < 3; ++sl) {
+        ell_nbr[sl * nel + g] = -1;
+        ell_nodes[sl * nel + g] = 0;
+    }
+    for (int q = 0; q < ni; ++q) {
+        const int ax = fc[q].face >> 1, side = fc[q].face & 1;
+        ell_nbr[ax * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + fc[q].U);
+        int packed = 0, j = 0;
+        for (int cu = 0; cu < 8; ++cu)
+            if (((cu >> ax) & 1) == 1 - side) { packed |= cu << (3 * j); ++j; }
+        ell_nodes[ax * nel + g] = packed;
+    }
+    for (int a = 0; a < 8; ++a)
+        for (int j = 0; j < 12; ++j) ell_val[j * nrows + row0 + a] = 0.0;
     for (int a = 0; a < 8; ++a) {
         const int64_t rb = base + static_cast<int64_t>(a) * L;
         rowptr[row0 + a] = rb;
@@ -326,6 +343,7 @@ k_fine_hex(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
             const HexFace& F = fc[gface[gi]];
             const int ax = F.face >> 1, side = F.face & 1;
             // U's nodes on the shared face have bit ax == 1 - side; ascending local order
+            int j = 0;
             for (int cu = 0; cu < 8; ++cu) {
                 if (((cu >> ax) & 1) != 1 - side) continue;
                 double s = 0.0;
@@ -333,7 +351,9 @@ k_fine_hex(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
                     s += Di[a * 8 + c] * (F.odn * ref[REF_X + F.face * 64 + c * 8 + cu]);
                 col[rb + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
                 val[rb + pos] = s;
+                ell_val[(ax * 4 + j) * nrows + row0 + a] = s;
                 ++pos;
+                ++j;
             }
         }
     }
@@ -345,7 +365,8 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
            const double* __restrict__ omega, const int* __restrict__ dirs, int B,
            const double* __restrict__ sigt, const int64_t* __restrict__ elem_off,
            int64_t* __restrict__ rowptr, int32_t* __restrict__ col, double* __restrict__ val,
-           double* __restrict__ dinv, int* __restrict__ bad) {
+           double* __restrict__ dinv, int* __restrict__ bad, int32_t* __restrict__ ell_nbr,
+           int32_t* __restrict__ ell_nodes, double* __restrict__ ell_val) {
     int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= E * B) return;
     const int b = static_cast<int>(g / E);
@@ -393,6 +414,24 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
     const int64_t row0 = static_cast<int64_t>(b) * N + 4 * t;
     const int64_t base = elem_off[g];
     const int64_t coff = static_cast<int64_t>(b) * N;
+    // element-block (ELL) copy: slot = position in the inflow-face list, U's
+    // three face nodes in ascending local order
+    const int64_t nrows = N * B, nel = E * B;
+    for (int sl = 0; sl < 3; ++sl) {
+        ell_nbr[sl * nel + g] = -1;
+        ell_nodes[sl * nel + g] = 0;
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int j = 0; j < 9; ++j) ell_val[j * nrows + row0 + a] = 0.0;
+    for (int q = 0; q < ni; ++q) {
+        int un[3], qq = 0;
+        for (int a2 = 0; a2 < 4; ++a2)
+            if (a2 != fc[q].face) { un[qq] = unode[(t * 4 + fc[q].face) * 3 + qq]; ++qq; }
+        for (int i = 1; i < 3; ++i)
+            for (int j = i; j > 0 && un[j - 1] > un[j]; --j) { int tmp = un[j]; un[j] = un[j - 1]; un[j - 1] = tmp; }
+        ell_nbr[q * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + fc[q].U);
+        ell_nodes[q * nel + g] = un[0] | (un[1] << 3) | (un[2] << 6);
+    }
     for (int a = 0; a < 4; ++a) {
         const int64_t rb = base + static_cast<int64_t>(a) * L;
         rowptr[row0 + a] = rb;
@@ -425,6 +464,7 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
                 }
                 col[rb + pos] = static_cast<int32_t>(coff + 4 * F.U + un[jcol]);
                 val[rb + pos] = s;
+                ell_val[(gface[gi] * 3 + oi) * nrows + row0 + a] = s;
                 ++pos;
             }
         }
@@ -574,17 +614,25 @@ void fine_counts(const DeviceMesh& m, const double* omega_d, const int* dirs_d, 
 
 void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d, int B,
                    const double* sigt, const int64_t* elem_off, int64_t total_nnz, int64_t* rowptr,
-                   int32_t* col, double* val, double* dinv, hipStream_t s) {
+                   int32_t* col, double* val, double* dinv, FineEll& ell, hipStream_t s) {
+    const int nf = m.kind == PAIR_HEX8 ? 4 : 3;
+    ell.k = m.k;
+    ell.nf = nf;
+    ell.nel = m.E * B;
+    ell.nrows = m.n_dof() * B;
+    ell.nbr.alloc(3 * ell.nel);
+    ell.nodes.alloc(3 * ell.nel);
+    ell.val.alloc(static_cast<size_t>(3 * nf) * ell.nrows);
     DBuf<int> bad(1);
     PAIR_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
     if (m.kind == PAIR_HEX8)
         hipLaunchKernelGGL(k_fine_hex, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, m.nx,
                            m.ny, m.nz, m.ref.p, omega_d, dirs_d, B, sigt, elem_off, rowptr, col,
-                           val, dinv, bad.p);
+                           val, dinv, bad.p, ell.nbr.p, ell.nodes.p, ell.val.p);
     else
         hipLaunchKernelGGL(k_fine_tet, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, m.nbr.p,
                            m.unode.p, m.nvec.p, m.mass.p, omega_d, dirs_d, B, sigt, elem_off,
-                           rowptr, col, val, dinv, bad.p);
+                           rowptr, col, val, dinv, bad.p, ell.nbr.p, ell.nodes.p, ell.val.p);
     PAIR_LAUNCH_CHECK();
     const int64_t nrows = m.n_dof() * B;
     hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, s, rowptr, nrows, total_nnz);

@@ -39,6 +39,8 @@ AmgParams Context::amg_params() const {
     p.seed = opt.pmis_seed;
     p.tol = opt.tol_inner;
     p.max_iter = opt.max_inner;
+    p.relax_pre = opt.relax_pre;
+    p.relax_post = opt.relax_post;
     return p;
 }
 
@@ -60,8 +62,9 @@ Csr Context::assemble_fine(Batch& bt, double* t_assemble_ms) {
     A.col.alloc(nnz);
     A.val.alloc(nnz);
     bt.dinv.alloc(static_cast<size_t>(B) * E * mesh.k * mesh.k);
+    bt.ell = std::make_shared<FineEll>();
     fine_assemble(mesh, omega_d.p, dirs_d.p, B, sigt.p, eoff.p, nnz, A.rowptr.p, A.col.p, A.val.p,
-                  bt.dinv.p, s);
+                  bt.dinv.p, *bt.ell, s);
     if (t_assemble_ms) *t_assemble_ms += now_ms() - t0;
     return A;
 }
@@ -74,6 +77,7 @@ void Context::assemble_batch(Batch& bt, double* t_assemble_ms) {
     for (int b = 0; b < B; ++b) off[b] = static_cast<int64_t>(b) * N;
     bt.H.reset(new Hierarchy(amg_params(), s));
     bt.H->setup(std::move(A), off, cn);
+    bt.H->set_fine_ell(bt.ell);
 }
 
 void Context::build_batches(int mode, pair_stats* st) {
@@ -132,7 +136,7 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
         if (use_warm)
             for (int b = 0; b < B; ++b) d2d(x0 + b * N, psi.p + static_cast<int64_t>(bt.dirs[b]) * N, N, s);
         double t2 = now_ms();
-        bool ok = bt.H->solve(opt.use_graph && mode == PAIR_BATCHED, !use_warm);
+        bool ok = bt.H->solve(opt.use_graph != 0, !use_warm);
         double t3 = now_ms();
         bytes += bt.H->last_solve_bytes();
         all_ok = all_ok && ok;

@@ -41,6 +41,7 @@ struct Batch {
     std::vector<int> dirs;                 // directions, in order
     DBuf<double> dinv;                     // [B][E][k*k] element block inverses
     std::unique_ptr<Hierarchy> H;
+    std::shared_ptr<FineEll> ell;          // element-block copy of the finest level
 };
 
 struct SourceSpec {
@@ -106,7 +107,7 @@ void fine_counts(const DeviceMesh& m, const double* omega_d, const int* dirs_d, 
                  int64_t* cnt, hipStream_t s);
 void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d, int B,
                    const double* sigt, const int64_t* elem_off, int64_t total_nnz, int64_t* rowptr,
-                   int32_t* col, double* val, double* dinv, hipStream_t s);
+                   int32_t* col, double* val, double* dinv, FineEll& ell, hipStream_t s);
 void rhs_kernel(const DeviceMesh& m, int B, const int* dirs_d, const double* dinv,
                 const double* sigs, const double* q, const double* phi, const double* ext,
                 bool ext_per_dir, int64_t N, double* out, hipStream_t s);

@@ -45,6 +45,8 @@ class Solver:
         self.opt = options if options is not None else B.default_options(**overrides)
         if options is not None:
             for k, v in overrides.items():
+                if k in ("relax_pre", "relax_post") and isinstance(v, str):
+                    v = v.encode()
                 setattr(self.opt, k, v)
         if stream is None:
             try:
@@ -74,6 +76,8 @@ class Solver:
     # ---------------------------------------------------------------- problem
     def set_options(self, **kw):
         for k, v in kw.items():
+            if k in ("relax_pre", "relax_post") and isinstance(v, str):
+                v = v.encode()
             setattr(self.opt, k, v)
         self._chk(B.pair_set_options(self.h, ctypes.byref(self.opt)))
 

@@ -39,7 +39,7 @@ def test_struct_layout_matches():
 def test_default_options():
     o = B.default_options()
     assert (o.lair_distance, o.theta, o.eps_r, o.omega) == (1, 0.25, 0.01, 1.0)
-    assert (o.coarse_max, o.max_levels, o.kmax) == (256, 25, 64)
+    assert (o.coarse_max, o.max_levels, o.kmax) == (64, 25, 64)
     assert o.tol_inner == 1e-8 and o.max_inner == 100
 
 

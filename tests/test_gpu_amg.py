@@ -1,0 +1,117 @@
+"""Component parity of the GPU AIR setup and V-cycle against the reference AIR
+(oracle/air_ref.py) on the same input matrices, through the generic C ABI."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from paper_1910_11463_amd import binding as B
+from paper_1910_11463_amd import workloads as wl
+from tests.gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _matrix(cfg, scale, m):
+    from oracle import dg, quadrature as Q, source_iteration as si
+    w = wl.make_config(cfg, scale=scale)
+    om, wt = Q.level_symmetric(w.sn_order)
+    prob = si.Problem(w.mesh, w.mats.sigma_t, w.mats.sigma_s, w.mats.q, om, wt)
+    blk = prob.blocks(m)
+    A = dg.scaled_csr(prob.topo, blk)
+    b = np.einsum("eab,eb->ea", np.linalg.inv(blk.D), prob.rhs(m, None)).ravel()
+    return A, b
+
+
+CASES = [(2, 6, 5), (3, 2, 7), (5, 5, 13), (4, 6, 40)]
+
+
+def _amg(A, coarse_max, seed=0, seg=None, kmax=64, pre="FC", post="FC"):
+    from paper_1910_11463_amd.solver import Amg
+    a = Amg(coarse_max=coarse_max, pmis_seed=seed, tol_inner=1e-10, max_inner=200, kmax=kmax,
+            relax_pre=pre.encode(), relax_post=post.encode())
+    a.setup(A.indptr, A.indices, A.data, seg)
+    return a
+
+
+@pytest.mark.parametrize("cfg,scale,m,kmax", [c + (64,) for c in CASES] + [(2, 6, 5, 3), (3, 2, 7, 2)])
+def test_hierarchy_matches_reference(cfg, scale, m, kmax):
+    """Same C/F split, interpolation, restriction and coarse operators, level by
+    level: integer data bit-exact, values within 1e-12 relative.  Small kmax
+    exercises the truncation of long local systems to the strongest entries."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A, _ = _matrix(cfg, scale, m)
+    print("hierarchy parity", cfg, scale, m, kmax, A.shape, flush=True)
+    seed = 3
+    ref = AR.setup(A, AR.Options(coarse_max=64, seed=seed, kmax=kmax))
+    g = _amg(A, 64, seed, kmax=kmax)
+    assert g.num_levels() == len(ref)
+    for l, L in enumerate(ref):
+        got = g.level(l)
+        assert np.array_equal(got["rowptr"], L.A.indptr), l
+        assert np.array_equal(got["col"], L.A.indices), l
+        scale_v = np.abs(L.A.data).max()
+        assert np.abs(got["val"] - L.A.data).max() <= 1e-12 * scale_v, l
+        if L.cf is None:
+            assert np.all(got["cf"] == 0)
+            break
+        assert np.array_equal(got["cf"], L.cf.astype(np.int8)), l
+        assert np.array_equal(got["p"], L.p.astype(np.int32)), l
+        assert np.array_equal(got["r_rowptr"], L.R.indptr), l
+        assert np.array_equal(got["r_col"], L.R.indices), l
+        assert np.abs(got["r_val"] - L.R.data).max() <= 1e-12 * np.abs(L.R.data).max(), l
+
+
+@pytest.mark.parametrize("cfg,scale,m,pre,post", [c + ("FC", "FC") for c in CASES] +
+                         [(2, 6, 5, "FFC", "FFC"), (3, 2, 7, "", "FFC"), (5, 5, 13, "FC", "FFC")])
+def test_vcycles_match_reference(cfg, scale, m, pre, post):
+    """Same iteration count as the reference cycle for each relaxation schedule."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A, b = _matrix(cfg, scale, m)
+    ref = AR.setup(A, AR.Options(coarse_max=64))
+    xr, itr, hist = AR.solve(ref, b, tol=1e-10, maxit=200, pre=pre, post=post)
+    g = _amg(A, 64, pre=pre, post=post)
+    x, iters, rel, rc = g.solve(b)
+    assert rc == B.PAIR_OK
+    assert iters[0] == itr, (iters[0], itr)
+    assert rel[0] <= 1e-10
+    xe = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x - xe) <= 1e-8 * np.linalg.norm(xe)
+    assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xe)
+
+
+def test_segments_are_independent_and_bitwise_equal():
+    """A block-diagonal batch of three matrices gives each segment exactly the
+    hierarchy and iterates it gets alone."""
+    need_gpu()
+    mats = [_matrix(2, 5, 3), _matrix(3, 2, 1), _matrix(2, 5, 70)]
+    blocks = sp.block_diag([a for a, _ in mats], format="csr")
+    blocks.sort_indices()
+    rhs = np.concatenate([b for _, b in mats])
+    sizes = [a.shape[0] for a, _ in mats]
+    seg = np.concatenate([[0], np.cumsum(sizes)])
+    g = _amg(blocks, 32, seg=seg)
+    xb, itb, relb, rc = g.solve(rhs)
+    assert rc == B.PAIR_OK
+    for k, (a, b) in enumerate(mats):
+        s = _amg(a, 32)
+        x, it, rel, rc1 = s.solve(b)
+        assert rc1 == B.PAIR_OK
+        assert itb[k] == it[0]
+        assert np.array_equal(xb[seg[k]:seg[k + 1]], x)
+        assert g.segment_levels(k) == s.num_levels()
+
+
+def test_invalid_inputs_rejected():
+    need_gpu()
+    from paper_1910_11463_amd.solver import Amg
+    a = Amg()
+    A = sp.csr_matrix(np.array([[1.0, 0.5], [0.0, 0.0]]))   # row 1 lacks its diagonal entry
+    A.eliminate_zeros()
+    with pytest.raises(B.PairError):
+        a.setup(A.indptr, A.indices, A.data)
+    C = sp.csr_matrix(np.array([[1.0, 0.5], [0.5, 1.0]]))
+    with pytest.raises(B.PairError):   # coupling across two one-row segments
+        a.setup(C.indptr, C.indices, C.data, [0, 1, 2])
