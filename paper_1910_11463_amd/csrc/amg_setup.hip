@@ -13,9 +13,11 @@
 //   5. lAIR restriction: per C-point i, the eps_R-strong F-neighbours R_i
 //      (at most kmax, the largest |a_ij| kept), z solving
 //      A(R_i,R_i)^T z = -A(i,R_i)^T, row [z, 1];
-//   6. Galerkin product A_c = R A P: per coarse row all products r_Ik a_kj with
-//      P(j) >= 0 are gathered, sorted by (column, canonical position) and summed
-//      in canonical order, so the result is bitwise reproducible.
+//   6. Galerkin product A_c = R (A P): rows of A P merge the entries of A that
+//      interpolate from the same coarse point (sorted by (column, position),
+//      summed in position order); each row of R (A P) collects its distinct
+//      columns in an LDS hash set and adds the rows of A P in the order of the
+//      row of R, so the result is bitwise reproducible.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -396,19 +398,6 @@ __global__ void k_r_class(int64_t nc, const int64_t* __restrict__ r_rowptr, int 
 }
 
 // ------------------------------------------------------------- R A P
-__global__ void k_rap_ub(int64_t nc, const int64_t* __restrict__ r_rowptr,
-                         const int32_t* __restrict__ r_col, const int64_t* __restrict__ rowptr,
-                         int64_t* __restrict__ ub) {
-    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    int64_t s = 0;
-    for (int64_t e = r_rowptr[I]; e < r_rowptr[I + 1]; ++e) {
-        int64_t k = r_col[e];
-        s += rowptr[k + 1] - rowptr[k];
-    }
-    ub[I] = s;
-}
-
 __global__ void k_class_rows(int64_t nc, const int64_t* __restrict__ ub, int64_t lo, int64_t hi,
                              int32_t* __restrict__ list, int* __restrict__ count) {
     int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -420,58 +409,19 @@ __global__ void k_class_rows(int64_t nc, const int64_t* __restrict__ ub, int64_t
     }
 }
 
-// Products of one coarse row, sorted and reduced.  `key`/`pv` are scratch of
-// `cap` entries (a power of two >= the row's product count) in LDS or global
-// memory; NT threads cooperate.  SYMBOLIC: returns the number of distinct
-// columns (valid in thread 0).  NUMERIC: writes the row at out_col/out_val.
+// ------------------------------------------------------------- A P and R (A P)
+// One-point interpolation maps column j to coarse column p[j], so row i of A P
+// merges the entries of row i of A that share p[j]: keys (p[j], position) are
+// sorted and each run summed in position order (reproducible).  A P is stored
+// in the row slots of A (same row offsets) with ap_len[i] entries per row.
 constexpr int RMAX = KCAP + 1;   // longest R row (kmax + 1)
+constexpr uint32_t HASH_EMPTY = 0xffffffffu;
 
-template <int NT, bool NUMERIC>
-__device__ int rap_row(int64_t I, uint64_t* key, double* pv, int cap,
-                       const int64_t* __restrict__ r_rowptr, const int32_t* __restrict__ r_col,
-                       const double* __restrict__ r_val, const int64_t* __restrict__ rowptr,
-                       const int32_t* __restrict__ col, const double* __restrict__ val,
-                       const int32_t* __restrict__ p, int32_t* __restrict__ out_col,
-                       double* __restrict__ out_val, int64_t* s_pref, int64_t* s_abase,
-                       double* s_rv, int* s_red) {
-    const int tid = threadIdx.x;
-    const int64_t rs = r_rowptr[I];
-    const int rl = static_cast<int>(r_rowptr[I + 1] - rs);
-    for (int t = tid; t < rl; t += NT) {
-        int64_t k = r_col[rs + t];
-        s_abase[t] = rowptr[k];
-        s_pref[t + 1] = rowptr[k + 1] - rowptr[k];
-        s_rv[t] = r_val[rs + t];
-    }
-    __syncthreads();
-    if (tid == 0) {
-        s_pref[0] = 0;
-        for (int t = 0; t < rl; ++t) s_pref[t + 1] += s_pref[t];
-    }
-    __syncthreads();
-    const int64_t total = s_pref[rl];
-    for (int q = tid; q < cap; q += NT) {
-        uint64_t kq = KEY_NONE;
-        if (q < total) {
-            int lo = 0, hi = rl - 1;   // last t with s_pref[t] <= q
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (s_pref[mid] <= q) lo = mid; else hi = mid - 1;
-            }
-            int64_t e = s_abase[lo] + (q - s_pref[lo]);
-            int32_t c = p[col[e]];
-            if (c >= 0) {
-                kq = (static_cast<uint64_t>(static_cast<uint32_t>(c)) << 32) | static_cast<uint32_t>(q);
-                if (NUMERIC) pv[q] = s_rv[lo] * val[e];
-            }
-        }
-        key[q] = kq;
-    }
-    __syncthreads();
-    // bitonic sort (ascending)
-    for (int k = 2; k <= cap; k <<= 1) {
+template <int NT>
+__device__ void bitonic_sort_u64(uint64_t* key, int cap) {
+    for (int k = 2; k <= cap; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < cap; i += NT) {
+            for (int i = threadIdx.x; i < cap; i += NT) {
                 int l = i ^ j;
                 if (l > i) {
                     uint64_t a = key[i], b = key[l];
@@ -481,65 +431,215 @@ __device__ int rap_row(int64_t I, uint64_t* key, double* pv, int cap,
             }
             __syncthreads();
         }
-    }
-    // leaders: first entry of each distinct column
-    int nlead = 0;
-    int64_t out_base = 0;
-    for (int q0 = 0; q0 < cap; q0 += NT) {
-        int q = q0 + tid;
-        bool lead = false;
-        if (q < cap) {
-            uint64_t a = key[q];
-            lead = a != KEY_NONE && (q == 0 || (key[q - 1] >> 32) != (a >> 32));
-        }
-        // block-wide exclusive count of leaders (per-wave ballot + LDS)
-        uint64_t m = __ballot(lead);
-        int wid = tid >> 6, lane = tid & 63;
-        if (lane == 0) s_red[wid] = __popcll(m);
-        __syncthreads();
-        int before = 0, tot = 0;
-        for (int w = 0; w < NT / 64; ++w) {
-            if (w < wid) before += s_red[w];
-            tot += s_red[w];
-        }
-        before += __popcll(m & ((1ull << lane) - 1ull));
-        if (NUMERIC && lead) {
-            uint64_t a = key[q];
-            uint32_t c = static_cast<uint32_t>(a >> 32);
-            double s = 0.0;
-            for (int t = q; t < cap && key[t] != KEY_NONE && static_cast<uint32_t>(key[t] >> 32) == c; ++t)
-                s += pv[static_cast<uint32_t>(key[t])];
-            out_col[out_base + nlead + before] = static_cast<int32_t>(c);
-            out_val[out_base + nlead + before] = s;
-        }
-        nlead += tot;
-        __syncthreads();
-    }
-    return nlead;
 }
 
-template <int NT, int CAP, bool NUMERIC>
+template <int NT>
+__device__ void bitonic_sort_u32(uint32_t* key, int cap) {
+    for (int k = 2; k <= cap; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < cap; i += NT) {
+                int l = i ^ j;
+                if (l > i) {
+                    uint32_t a = key[i], b = key[l];
+                    bool up = (i & k) == 0;
+                    if ((a > b) == up) { key[i] = b; key[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// Block-wide exclusive count of `flag` over the block; returns (before, total).
+template <int NT>
+__device__ __forceinline__ void block_count(bool flag, int* s_red, int& before, int& total) {
+    uint64_t m = __ballot(flag);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) s_red[wid] = __popcll(m);
+    __syncthreads();
+    before = 0;
+    total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < wid) before += s_red[w];
+        total += s_red[w];
+    }
+    before += __popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();
+}
+
+template <int NT, int CAP>
+__global__ void __launch_bounds__(NT)
+k_ap(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ rowptr,
+     const int32_t* __restrict__ col, const double* __restrict__ val, const int32_t* __restrict__ p,
+     int32_t* __restrict__ ap_col, double* __restrict__ ap_val, int* __restrict__ ap_len) {
+    __shared__ uint64_t key[CAP];
+    __shared__ double pv[CAP];
+    __shared__ int s_red[NT / 64];
+    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int64_t i = list[r];
+        const int64_t rs = rowptr[i];
+        const int len = static_cast<int>(rowptr[i + 1] - rs);
+        int cap = 1;
+        while (cap < len) cap <<= 1;
+        for (int q = threadIdx.x; q < cap; q += NT) {
+            uint64_t kq = KEY_NONE;
+            if (q < len) {
+                int32_t c = p[col[rs + q]];
+                if (c >= 0) {
+                    kq = (static_cast<uint64_t>(static_cast<uint32_t>(c)) << 32) | static_cast<uint32_t>(q);
+                    pv[q] = val[rs + q];
+                }
+            }
+            key[q] = kq;
+        }
+        __syncthreads();
+        bitonic_sort_u64<NT>(key, cap);
+        int nlead = 0;
+        for (int q0 = 0; q0 < cap; q0 += NT) {
+            const int q = q0 + threadIdx.x;
+            bool lead = false;
+            if (q < cap) {
+                uint64_t a = key[q];
+                lead = a != KEY_NONE && (q == 0 || (key[q - 1] >> 32) != (a >> 32));
+            }
+            int before, tot;
+            block_count<NT>(lead, s_red, before, tot);
+            if (lead) {
+                const uint32_t c = static_cast<uint32_t>(key[q] >> 32);
+                double sum = 0.0;
+                for (int t = q; t < cap && key[t] != KEY_NONE && static_cast<uint32_t>(key[t] >> 32) == c; ++t)
+                    sum += pv[static_cast<uint32_t>(key[t])];
+                ap_col[rs + nlead + before] = static_cast<int32_t>(c);
+                ap_val[rs + nlead + before] = sum;
+            }
+            nlead += tot;
+        }
+        if (threadIdx.x == 0) ap_len[i] = nlead;
+        __syncthreads();
+    }
+}
+
+__global__ void k_len_class(int64_t n, const int64_t* __restrict__ rowptr, int lo, int hi,
+                            int32_t* __restrict__ list, int* __restrict__ count) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t len = rowptr[i + 1] - rowptr[i];
+    if (len > lo && len <= hi) list[atomicAdd(count, 1)] = static_cast<int32_t>(i);
+}
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t c, uint32_t mask) {
+    return (c * 2654435761u) & mask;
+}
+
+// Row I of R (A P).  Columns go into an open-addressing hash set of `tbl` slots
+// (a power of two, at least twice the number of products, so probing ends).
+// SYMBOLIC: the number of distinct columns.  NUMERIC: the distinct columns are
+// sorted, then the rows of A P are added one R entry after the other (within
+// one row of A P every column is distinct, so no slot is updated twice in a
+// step): the sum runs over k in the order of row I of R, reproducibly.
+template <int NT, bool NUMERIC>
+__device__ int rap_hash_row(int64_t I, int tbl, uint32_t* tkeys, int32_t* tpos, uint32_t* ucol,
+                            double* uval, const int64_t* __restrict__ r_rowptr,
+                            const int32_t* __restrict__ r_col, const double* __restrict__ r_val,
+                            const int64_t* __restrict__ rowptr, const int* __restrict__ ap_len,
+                            const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
+                            int32_t* __restrict__ out_col, double* __restrict__ out_val,
+                            int* s_pref, int64_t* s_base, double* s_rv, int* s_cnt) {
+    const int tid = threadIdx.x;
+    const int64_t rs = r_rowptr[I];
+    const int rl = static_cast<int>(r_rowptr[I + 1] - rs);
+    const uint32_t mask = static_cast<uint32_t>(tbl - 1);
+    for (int t = tid; t < rl; t += NT) {
+        const int64_t k = r_col[rs + t];
+        s_base[t] = rowptr[k];
+        s_pref[t + 1] = ap_len[k];
+        s_rv[t] = r_val[rs + t];
+    }
+    for (int h = tid; h < tbl; h += NT) tkeys[h] = HASH_EMPTY;
+    if (tid == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
+    __syncthreads();
+    if (tid == 0) {
+        s_pref[0] = 0;
+        for (int t = 0; t < rl; ++t) s_pref[t + 1] += s_pref[t];
+    }
+    __syncthreads();
+    const int total = s_pref[rl];
+    for (int q = tid; q < total; q += NT) {
+        int lo = 0, hi = rl - 1;   // last t with s_pref[t] <= q
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t c = static_cast<uint32_t>(ap_col[s_base[lo] + (q - s_pref[lo])]);
+        uint32_t h = hash_slot(c, mask);
+        while (true) {
+            uint32_t old = atomicCAS(&tkeys[h], HASH_EMPTY, c);
+            if (old == HASH_EMPTY) { atomicAdd(&s_cnt[0], 1); break; }
+            if (old == c) break;
+            h = (h + 1) & mask;
+        }
+    }
+    __syncthreads();
+    const int nu = s_cnt[0];
+    if (!NUMERIC) return nu;
+    int cap = 1;
+    while (cap < nu) cap <<= 1;
+    for (int h = tid; h < tbl; h += NT)
+        if (tkeys[h] != HASH_EMPTY) ucol[atomicAdd(&s_cnt[1], 1)] = tkeys[h];
+    for (int q = nu + tid; q < cap; q += NT) ucol[q] = HASH_EMPTY;
+    __syncthreads();
+    bitonic_sort_u32<NT>(ucol, cap);
+    for (int q = tid; q < nu; q += NT) {
+        const uint32_t c = ucol[q];
+        uint32_t h = hash_slot(c, mask);
+        while (tkeys[h] != c) h = (h + 1) & mask;
+        tpos[h] = q;
+        uval[q] = 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < rl; ++t) {
+        const int64_t base = s_base[t];
+        const int len = s_pref[t + 1] - s_pref[t];
+        const double rv = s_rv[t];
+        for (int j = tid; j < len; j += NT) {
+            const uint32_t c = static_cast<uint32_t>(ap_col[base + j]);
+            uint32_t h = hash_slot(c, mask);
+            while (tkeys[h] != c) h = (h + 1) & mask;
+            const int q = tpos[h];
+            uval[q] = fma(rv, ap_val[base + j], uval[q]);
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < nu; q += NT) {
+        out_col[q] = static_cast<int32_t>(ucol[q]);
+        out_val[q] = uval[q];
+    }
+    __syncthreads();
+    return nu;
+}
+
+template <int NT, int TBL, bool NUMERIC>
 __global__ void __launch_bounds__(NT)
 k_rap_lds(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ r_rowptr,
           const int32_t* __restrict__ r_col, const double* __restrict__ r_val,
-          const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-          const double* __restrict__ val, const int32_t* __restrict__ p,
-          const int64_t* __restrict__ ub, int64_t* __restrict__ cnt_out,
-          const int64_t* __restrict__ c_rowptr, int32_t* __restrict__ c_col,
-          double* __restrict__ c_val) {
-    __shared__ uint64_t key[CAP];
-    __shared__ double pv[NUMERIC ? CAP : 1];
-    __shared__ int64_t s_pref[RMAX + 1], s_abase[RMAX];
+          const int64_t* __restrict__ rowptr, const int* __restrict__ ap_len,
+          const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
+          int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
+          int32_t* __restrict__ c_col, double* __restrict__ c_val) {
+    __shared__ uint32_t tkeys[TBL];
+    __shared__ int32_t tpos[NUMERIC ? TBL : 1];
+    __shared__ uint32_t ucol[NUMERIC ? TBL / 2 : 1];
+    __shared__ double uval[NUMERIC ? TBL / 2 : 1];
+    __shared__ int s_pref[RMAX + 1];
+    __shared__ int64_t s_base[RMAX];
     __shared__ double s_rv[RMAX];
-    __shared__ int s_red[NT / 64];
+    __shared__ int s_cnt[2];
     for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
-        int64_t I = list[r];
-        int cap = 1;
-        while (cap < ub[I]) cap <<= 1;
-        int nl = rap_row<NT, NUMERIC>(I, key, pv, cap, r_rowptr, r_col, r_val, rowptr, col, val, p,
-                                      NUMERIC ? c_col + c_rowptr[I] : nullptr,
-                                      NUMERIC ? c_val + c_rowptr[I] : nullptr, s_pref, s_abase,
-                                      s_rv, s_red);
+        const int64_t I = list[r];
+        int nl = rap_hash_row<NT, NUMERIC>(I, TBL, tkeys, tpos, ucol, uval, r_rowptr, r_col, r_val,
+                                           rowptr, ap_len, ap_col, ap_val,
+                                           NUMERIC ? c_col + c_rowptr[I] : nullptr,
+                                           NUMERIC ? c_val + c_rowptr[I] : nullptr, s_pref, s_base,
+                                           s_rv, s_cnt);
         if (!NUMERIC && threadIdx.x == 0) cnt_out[I] = nl;
         __syncthreads();
     }
@@ -549,28 +649,38 @@ k_rap_lds(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
 template <bool NUMERIC>
 __global__ void __launch_bounds__(256)
 k_rap_global(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ scratch_off,
-             uint64_t* __restrict__ kscr, double* __restrict__ vscr,
-             const int64_t* __restrict__ r_rowptr, const int32_t* __restrict__ r_col,
-             const double* __restrict__ r_val, const int64_t* __restrict__ rowptr,
-             const int32_t* __restrict__ col, const double* __restrict__ val,
-             const int32_t* __restrict__ p, const int64_t* __restrict__ ub,
+             uint32_t* __restrict__ kscr, int32_t* __restrict__ pscr, uint32_t* __restrict__ cscr,
+             double* __restrict__ vscr, const int64_t* __restrict__ r_rowptr,
+             const int32_t* __restrict__ r_col, const double* __restrict__ r_val,
+             const int64_t* __restrict__ rowptr, const int* __restrict__ ap_len,
+             const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
              int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
              int32_t* __restrict__ c_col, double* __restrict__ c_val) {
-    __shared__ int64_t s_pref[RMAX + 1], s_abase[RMAX];
+    __shared__ int s_pref[RMAX + 1];
+    __shared__ int64_t s_base[RMAX];
     __shared__ double s_rv[RMAX];
-    __shared__ int s_red[4];
-    int r = blockIdx.x;
+    __shared__ int s_cnt[2];
+    const int r = blockIdx.x;
     if (r >= nrows) return;
-    int64_t I = list[r];
-    int cap = 1;
-    while (cap < ub[I]) cap <<= 1;
-    uint64_t* key = kscr + scratch_off[r];
-    double* pv = vscr + scratch_off[r];
-    int nl = rap_row<256, NUMERIC>(I, key, pv, cap, r_rowptr, r_col, r_val, rowptr, col, val, p,
-                                   NUMERIC ? c_col + c_rowptr[I] : nullptr,
-                                   NUMERIC ? c_val + c_rowptr[I] : nullptr, s_pref, s_abase, s_rv,
-                                   s_red);
+    const int64_t I = list[r];
+    const int64_t o = scratch_off[r];
+    const int tbl = static_cast<int>(scratch_off[r + 1] - o);
+    int nl = rap_hash_row<256, NUMERIC>(I, tbl, kscr + o, pscr + o, cscr + o / 2, vscr + o / 2,
+                                        r_rowptr, r_col, r_val, rowptr, ap_len, ap_col, ap_val,
+                                        NUMERIC ? c_col + c_rowptr[I] : nullptr,
+                                        NUMERIC ? c_val + c_rowptr[I] : nullptr, s_pref, s_base,
+                                        s_rv, s_cnt);
     if (!NUMERIC && threadIdx.x == 0) cnt_out[I] = nl;
+}
+
+__global__ void k_rap_ub(int64_t nc, const int64_t* __restrict__ r_rowptr,
+                         const int32_t* __restrict__ r_col, const int* __restrict__ ap_len,
+                         int64_t* __restrict__ ub) {
+    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int64_t s = 0;
+    for (int64_t e = r_rowptr[I]; e < r_rowptr[I + 1]; ++e) s += ap_len[r_col[e]];
+    ub[I] = s;
 }
 
 // ------------------------------------------------------------- coarse dense inverse
@@ -1015,10 +1125,40 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         int nsing = 0;
         d2h(&nsing, d_counter.p, 1, s_);
 
-        // Galerkin product
+        // A P: merge the entries of each row of A that interpolate from the same
+        // coarse point (rows classed by length)
+        DBuf<int32_t> ap_col(L.A.nnz);
+        DBuf<double> ap_val(L.A.nnz);
+        DBuf<int> ap_len(n);
+        {
+            DBuf<int32_t> alist(n);
+            const int bnd[4] = {-1, 64, 2048, 1 << 30};
+            for (int c = 0; c < 3; ++c) {
+                PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
+                hipLaunchKernelGGL(k_len_class, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
+                                   L.A.rowptr.p, bnd[c], bnd[c + 1], alist.p, d_counter.p);
+                PAIR_LAUNCH_CHECK();
+                int na = 0;
+                d2h(&na, d_counter.p, 1, s_);
+                PAIR_HIP(hipStreamSynchronize(s_));
+                if (na == 0) continue;
+                PAIR_CHECK(c < 2, "a row of a coarse operator has more than 2048 entries");
+                const unsigned g = static_cast<unsigned>(std::min(na, 1 << 20));
+                if (c == 0)
+                    hipLaunchKernelGGL((k_ap<64, 64>), dim3(g), dim3(64), 0, s_, na, alist.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
+                                       ap_len.p);
+                else
+                    hipLaunchKernelGGL((k_ap<256, 2048>), dim3(g), dim3(256), 0, s_, na, alist.p,
+                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
+                                       ap_len.p);
+                PAIR_LAUNCH_CHECK();
+            }
+        }
+        // Galerkin product R (A P), rows classed by their number of products
         DBuf<int64_t> ub(total_c), ccnt(total_c);
         hipLaunchKernelGGL(k_rap_ub, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
-                           L.R.rowptr.p, L.R.col.p, L.A.rowptr.p, ub.p);
+                           L.R.rowptr.p, L.R.col.p, ap_len.p, ub.p);
         PAIR_LAUNCH_CHECK();
         struct Cls { int64_t lo, hi; };
         const Cls classes[3] = {{-1, 256}, {256, 2048}, {2048, int64_t(1) << 40}};
@@ -1034,10 +1174,11 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             d2h(&lcount[c], d_counter.p, 1, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
         }
-        // scratch for the global class
+        // hash-table scratch for the global class: 2 * pow2(products) slots per row
         std::vector<int64_t> gscr_off_h;
         DBuf<int64_t> gscr_off;
-        DBuf<uint64_t> gkeys;
+        DBuf<uint32_t> gkeys, gcols;
+        DBuf<int32_t> gpos;
         DBuf<double> gvals;
         if (lcount[2] > 0) {
             std::vector<int32_t> rows(lcount[2]);
@@ -1049,12 +1190,14 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             for (int k = 0; k < lcount[2]; ++k) {
                 int64_t cap = 1;
                 while (cap < ubh[rows[k]]) cap <<= 1;
-                gscr_off_h[k + 1] = gscr_off_h[k] + cap;
+                gscr_off_h[k + 1] = gscr_off_h[k] + 2 * cap;
             }
             gscr_off.alloc(lcount[2] + 1);
             h2d(gscr_off.p, gscr_off_h.data(), lcount[2] + 1, s_);
             gkeys.alloc(gscr_off_h.back());
-            gvals.alloc(gscr_off_h.back());
+            gpos.alloc(gscr_off_h.back());
+            gcols.alloc(gscr_off_h.back() / 2);
+            gvals.alloc(gscr_off_h.back() / 2);
         }
         auto run_rap = [&](bool numeric, Csr* C) {
             int64_t* cnt_out = ccnt.p;
@@ -1064,42 +1207,42 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             if (lcount[0] > 0) {
                 unsigned g = static_cast<unsigned>(std::min(lcount[0], 1 << 20));
                 if (numeric)
-                    hipLaunchKernelGGL((k_rap_lds<64, 256, true>), dim3(g), dim3(64), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<64, 512, true>), dim3(g), dim3(64), 0, s_,
                                        lcount[0], lists[0].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
-                                       crp, ccol, cval);
+                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
+                                       cval);
                 else
-                    hipLaunchKernelGGL((k_rap_lds<64, 256, false>), dim3(g), dim3(64), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<64, 512, false>), dim3(g), dim3(64), 0, s_,
                                        lcount[0], lists[0].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
-                                       crp, ccol, cval);
+                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
+                                       cval);
                 PAIR_LAUNCH_CHECK();
             }
             if (lcount[1] > 0) {
                 unsigned g = static_cast<unsigned>(std::min(lcount[1], 1 << 20));
                 if (numeric)
-                    hipLaunchKernelGGL((k_rap_lds<256, 2048, true>), dim3(g), dim3(256), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<256, 4096, true>), dim3(g), dim3(256), 0, s_,
                                        lcount[1], lists[1].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
-                                       crp, ccol, cval);
+                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
+                                       cval);
                 else
-                    hipLaunchKernelGGL((k_rap_lds<256, 2048, false>), dim3(g), dim3(256), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<256, 4096, false>), dim3(g), dim3(256), 0, s_,
                                        lcount[1], lists[1].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ub.p, cnt_out,
-                                       crp, ccol, cval);
+                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
+                                       cval);
                 PAIR_LAUNCH_CHECK();
             }
             if (lcount[2] > 0) {
                 if (numeric)
                     hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[2]), dim3(256), 0, s_,
-                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gvals.p,
-                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p, L.A.col.p,
-                                       L.A.val.p, L.p.p, ub.p, cnt_out, crp, ccol, cval);
+                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                                       gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
+                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 else
                     hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[2]), dim3(256), 0, s_,
-                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gvals.p,
-                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p, L.A.col.p,
-                                       L.A.val.p, L.p.p, ub.p, cnt_out, crp, ccol, cval);
+                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                                       gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
+                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 PAIR_LAUNCH_CHECK();
             }
         };
