@@ -39,7 +39,7 @@ def make_solver(w, mode_batch_size, device, pre="FC", post="FC"):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
-               relax_pre=pre, relax_post=post)
+               relax_pre=pre, relax_post=post, autotune=1)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)

@@ -80,6 +80,8 @@ typedef struct pair_options {
     char relax_pre[8];        /* pre-smoothing half-sweeps, e.g. "FC" (default) */
     char relax_post[8];       /* post-smoothing half-sweeps, e.g. "FC"; "FFC" = two
                                  Jacobi sweeps over F-points, then one over C-points */
+    int autotune;             /* 1: time the row kernels of each level once per context
+                                 and keep the fastest lanes-per-row (0: fixed table)  */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

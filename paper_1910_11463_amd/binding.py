@@ -36,7 +36,8 @@ class pair_options(ctypes.Structure):
                 ("max_outer", c_int), ("outer_estimate", c_int), ("keep_psi", c_int),
                 ("keep_hierarchy", c_int), ("warm_start", c_int), ("batch_size", c_int),
                 ("use_graph", c_int), ("allow_any_weight_sum", c_int),
-                ("relax_pre", ctypes.c_char * 8), ("relax_post", ctypes.c_char * 8)]
+                ("relax_pre", ctypes.c_char * 8), ("relax_post", ctypes.c_char * 8),
+                ("autotune", c_int)]
 
 
 class pair_stats(ctypes.Structure):

@@ -9,6 +9,7 @@
 //   at the coarsest level; V(1,1) cycles with FC-Jacobi relaxation.
 #pragma once
 
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -30,6 +31,9 @@ struct AmgParams {
     int max_iter = 100;
     int max_dense = 2048;   // largest coarsest level solved by a dense inverse
     std::string relax_pre = "FC", relax_post = "FC";   // half-sweep schedules
+    // Autotuned lanes per row, keyed by level index: (A kernels, R kernels).
+    // Shared by every hierarchy built with these parameters; null = fixed table.
+    std::shared_ptr<std::map<int, std::pair<int, int>>> tune;
     // lanes per row of the row kernels: index 0 = finest level, last entry used
     // for all deeper levels.  A function of the level index only, so that every
     // member's arithmetic (and its rounding) is the same whether it is solved
@@ -132,6 +136,7 @@ private:
     void vcycle_launches(bool x_is_zero);
     double* sweeps(Level& L, int l, const std::string& sched, double* cur, double* other, bool zero);
     void drop_graph();
+    void tune_lanes();
     void residual_norms();
     void launch_cycle_and_test(bool x_is_zero, int it_offset);
 

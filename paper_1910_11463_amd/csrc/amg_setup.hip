@@ -32,36 +32,35 @@ constexpr int8_t ST_U = 0, ST_C = 1, ST_F = -1, ST_NP = 2;   // PMIS states
 constexpr uint64_t KEY_NONE = ~0ull;
 
 // ------------------------------------------------------------- row basics
-__global__ void k_diag_rowmax(int64_t n, const int64_t* __restrict__ rowptr,
-                              const int32_t* __restrict__ col, const double* __restrict__ val,
-                              double* __restrict__ dinv, double* __restrict__ rowmax) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+
+
+// Fused per-row pass, G lanes per row: 1/a_ii, max_{k != i}|a_ik|, strength
+// flags of every entry and lambda (number of rows strongly depending on a column).
+template <int G>
+__global__ void __launch_bounds__(256)
+k_strength_fused(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const double* __restrict__ val, const uint16_t* __restrict__ seg,
+                 const uint8_t* __restrict__ part, double theta, double eps_r,
+                 double* __restrict__ dinv, uint8_t* __restrict__ sflag, int* __restrict__ lam) {
+    const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / G;
+    const int sub = threadIdx.x % G;
+    if (row >= n) return;
+    const int64_t rs = rowptr[row], re = rowptr[row + 1];
     double d = 0.0, m = 0.0;
-    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        int64_t c = col[e];
-        double v = val[e];
-        if (c == i) d = v;
+    for (int64_t e = rs + sub; e < re; e += G) {
+        const double v = val[e];
+        if (col[e] == row) d = v;
         else m = fmax(m, fabs(v));
     }
-    dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
-    rowmax[i] = m;
-}
-
-__global__ void k_strength(int64_t n, const int64_t* __restrict__ rowptr,
-                           const int32_t* __restrict__ col, const double* __restrict__ val,
-                           const double* __restrict__ rowmax, const uint16_t* __restrict__ seg,
-                           const uint8_t* __restrict__ part, double theta, double eps_r,
-                           uint8_t* __restrict__ sflag, int* __restrict__ lam) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const bool on = part[seg[i]] != 0;
-    const double m = rowmax[i];
-    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        int32_t c = col[e];
+    m = group_max<G>(m);
+    d = group_sum<G>(d);   // exactly one lane holds the diagonal
+    if (sub == 0) dinv[row] = d != 0.0 ? 1.0 / d : 0.0;
+    const bool on = part[seg[row]] != 0 && m > 0.0;
+    for (int64_t e = rs + sub; e < re; e += G) {
+        const int32_t c = col[e];
         uint8_t f = 0;
-        if (on && c != i && m > 0.0) {
-            double a = fabs(val[e]);
+        if (on && c != row) {
+            const double a = fabs(val[e]);
             if (a >= theta * m) f |= 1;
             if (a >= eps_r * m) f |= 2;
         }
@@ -78,60 +77,111 @@ __device__ __forceinline__ bool key_less(int li, uint64_t ri, int64_t ii, int lj
     return ii < ij;
 }
 
-__global__ void k_pmis_init(int64_t n, const uint16_t* __restrict__ seg,
-                            const uint8_t* __restrict__ part, const int* __restrict__ lam,
-                            int8_t* __restrict__ state) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (!part[seg[i]]) state[i] = ST_NP;
-    else state[i] = lam[i] == 0 ? ST_F : ST_U;
-}
 
-__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
-__global__ void k_pmis_compare(int64_t n, const int64_t* __restrict__ rowptr,
-                               const int32_t* __restrict__ col, const uint8_t* __restrict__ sflag,
-                               const int8_t* __restrict__ state, const int* __restrict__ lam,
-                               const uint16_t* __restrict__ seg, const int64_t* __restrict__ off,
-                               int level, uint64_t seed, uint8_t* __restrict__ notmax) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n || state[i] != ST_U) return;
-    const int64_t base = off[seg[i]];
-    const int64_t li = i - base;
-    const uint64_t ri = pmis_rand(seed, level, li);
-    const int lami = lam[i];
-    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        if (!(sflag[e] & 1)) continue;
-        int64_t j = col[e];
-        if (state[j] != ST_U) continue;
-        int64_t lj = j - base;
-        uint64_t rj = pmis_rand(seed, level, lj);
-        if (key_less(lami, ri, li, lam[j], rj, lj)) notmax[i] = 1;
-        else notmax[j] = 1;
+
+
+
+// List-driven rounds: the undecided rows of a round are listed (in any order;
+// every decision depends only on the states, so the split is reproducible).
+// Kernels read the list length from device memory, so several rounds can be
+// queued without host synchronisation.
+__global__ void k_pmis_init_list(int64_t n, const uint16_t* __restrict__ seg,
+                                 const uint8_t* __restrict__ part, const int* __restrict__ lam,
+                                 int8_t* __restrict__ state, int32_t* __restrict__ list,
+                                 int* __restrict__ cnt) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool und = false;
+    if (i < n) {
+        if (!part[seg[i]]) state[i] = ST_NP;
+        else if (lam[i] == 0) state[i] = ST_F;
+        else { state[i] = ST_U; und = true; }
     }
+    const int slot = wave_append(und, cnt);
+    if (und) list[slot] = static_cast<int32_t>(i);
 }
 
-__global__ void k_pmis_select(int64_t n, int8_t* __restrict__ state,
-                              const uint8_t* __restrict__ notmax) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n && state[i] == ST_U && !notmax[i]) state[i] = ST_C;
-}
-
-__global__ void k_pmis_mark_f(int64_t n, const int64_t* __restrict__ rowptr,
-                              const int32_t* __restrict__ col, const uint8_t* __restrict__ sflag,
-                              int8_t* __restrict__ state, int* __restrict__ undecided) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n || state[i] != ST_U) return;
-    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        if ((sflag[e] & 1) && state[col[e]] == ST_C) {
-            state[i] = ST_F;
-            return;
+__global__ void k_pmis_compare_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
+                                    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                    const uint8_t* __restrict__ sflag, const int8_t* __restrict__ state,
+                                    const int* __restrict__ lam, const uint16_t* __restrict__ seg,
+                                    const int64_t* __restrict__ off, int level, uint64_t seed,
+                                    uint8_t* __restrict__ notmax) {
+    const int c = *cnt;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < c; k += gridDim.x * blockDim.x) {
+        const int64_t i = list[k];
+        const int64_t base = off[seg[i]];
+        const int64_t li = i - base;
+        const uint64_t ri = pmis_rand(seed, level, li);
+        const int lami = lam[i];
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (!(sflag[e] & 1)) continue;
+            const int64_t j = col[e];
+            if (state[j] != ST_U) continue;
+            const int64_t lj = j - base;
+            if (key_less(lami, ri, li, lam[j], pmis_rand(seed, level, lj), lj)) notmax[i] = 1;
+            else notmax[j] = 1;
         }
     }
-    atomicAdd(undecided, 1);
+}
+
+__global__ void k_pmis_select_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
+                                   int8_t* __restrict__ state, uint8_t* __restrict__ notmax) {
+    const int c = *cnt;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < c; k += gridDim.x * blockDim.x) {
+        const int32_t i = list[k];
+        if (!notmax[i]) state[i] = ST_C;
+        notmax[i] = 0;   // ready for the next round
+    }
+}
+
+__global__ void k_zero_one(int* p) { *p = 0; }
+
+__global__ void k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
+                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                 const uint8_t* __restrict__ sflag, int8_t* __restrict__ state,
+                                 int32_t* __restrict__ next, int* __restrict__ next_cnt) {
+    const int c = *cnt;
+    const int stride = gridDim.x * blockDim.x;
+    // uniform trip count per wave so every lane reaches wave_append
+    for (int k0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); k0 < c; k0 += stride) {
+        const int k = k0 + (threadIdx.x & 63);
+        bool keep = false;
+        int32_t i = -1;
+        if (k < c) {
+            i = list[k];
+            if (state[i] == ST_U) {
+                bool f = false;
+                for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                    if ((sflag[e] & 1) && state[col[e]] == ST_C) { f = true; break; }
+                if (f) state[i] = ST_F;
+                else keep = true;
+            }
+        }
+        const int slot = wave_append(keep, next_cnt);
+        if (keep) next[slot] = i;
+    }
+}
+
+// Rows (or coarse rows) sorted into three size classes in one pass:
+// mode 0: row length of A; mode 1: local lAIR system size (R row length - 1);
+// mode 2: product upper bound ub[i].
+__global__ void k_class3(int64_t n, int mode, const int64_t* __restrict__ a,
+                         const int64_t* __restrict__ ub, int64_t b1, int64_t b2,
+                         int32_t* __restrict__ l0, int32_t* __restrict__ l1,
+                         int32_t* __restrict__ l2, int* __restrict__ cnt) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int cls = -1;
+    if (i < n) {
+        const int64_t v = mode == 2 ? ub[i] : (a[i + 1] - a[i] - (mode == 1 ? 1 : 0));
+        cls = v <= b1 ? 0 : (v <= b2 ? 1 : 2);
+    }
+    const int s0 = wave_append(cls == 0, &cnt[0]);
+    const int s1 = wave_append(cls == 1, &cnt[1]);
+    const int s2 = wave_append(cls == 2, &cnt[2]);
+    if (cls == 0) l0[s0] = static_cast<int32_t>(i);
+    if (cls == 1) l1[s1] = static_cast<int32_t>(i);
+    if (cls == 2) l2[s2] = static_cast<int32_t>(i);
 }
 
 // ------------------------------------------------------------- coarse numbering
@@ -389,25 +439,8 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
     }
 }
 
-__global__ void k_r_class(int64_t nc, const int64_t* __restrict__ r_rowptr, int lo, int hi,
-                          int32_t* __restrict__ list, int* __restrict__ count) {
-    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    int K = static_cast<int>(r_rowptr[I + 1] - r_rowptr[I]) - 1;
-    if (K > lo && K <= hi) list[atomicAdd(count, 1)] = static_cast<int32_t>(I);
-}
 
 // ------------------------------------------------------------- R A P
-__global__ void k_class_rows(int64_t nc, const int64_t* __restrict__ ub, int64_t lo, int64_t hi,
-                             int32_t* __restrict__ list, int* __restrict__ count) {
-    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    int64_t u = ub[I];
-    if (u > lo && u <= hi) {
-        int pos = atomicAdd(count, 1);
-        list[pos] = static_cast<int32_t>(I);
-    }
-}
 
 // ------------------------------------------------------------- A P and R (A P)
 // One-point interpolation maps column j to coarse column p[j], so row i of A P
@@ -518,13 +551,6 @@ k_ap(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ ro
     }
 }
 
-__global__ void k_len_class(int64_t n, const int64_t* __restrict__ rowptr, int lo, int hi,
-                            int32_t* __restrict__ list, int* __restrict__ count) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t len = rowptr[i + 1] - rowptr[i];
-    if (len > lo && len <= hi) list[atomicAdd(count, 1)] = static_cast<int32_t>(i);
-}
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t c, uint32_t mask) {
     return (c * 2654435761u) & mask;
@@ -951,11 +977,6 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         Level& L = levels_[l];
         build_level_aux(L, l);
         const int64_t n = L.A.n;
-        DBuf<double> rowmax(n);
-        hipLaunchKernelGGL(k_diag_rowmax, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
-                           L.A.rowptr.p, L.A.col.p, L.A.val.p, L.dinv.p, rowmax.p);
-        PAIR_LAUNCH_CHECK();
-
         // members that coarsen further
         std::vector<uint8_t> part(B_, 0);
         bool any = false;
@@ -983,38 +1004,51 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         h2d(d_off.p, L.off.data(), B_, s_);
         h2d(d_cnt.p, L.cnt.data(), B_, s_);
 
-        // strength + lambda
+        // strength + lambda (fused with 1/a_ii)
         DBuf<uint8_t> sflag(L.A.nnz);
         DBuf<int> lam(n);
         PAIR_HIP(hipMemsetAsync(lam.p, 0, n * sizeof(int), s_));
-        hipLaunchKernelGGL(k_strength, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
-                           L.A.col.p, L.A.val.p, rowmax.p, L.seg.p, d_part.p, prm_.theta,
-                           prm_.eps_r, sflag.p, lam.p);
+        hipLaunchKernelGGL(k_strength_fused<8>, dim3(grid_for(n * 8, 256)), dim3(256), 0, s_, n,
+                           L.A.rowptr.p, L.A.col.p, L.A.val.p, L.seg.p, d_part.p, prm_.theta,
+                           prm_.eps_r, L.dinv.p, sflag.p, lam.p);
         PAIR_LAUNCH_CHECK();
 
-        // PMIS
+        // PMIS: list-driven rounds, host check every few rounds
         DBuf<int8_t> state(n);
         DBuf<uint8_t> notmax(n);
-        hipLaunchKernelGGL(k_pmis_init, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.seg.p,
-                           d_part.p, lam.p, state.p);
+        DBuf<int32_t> plist[2];
+        plist[0].alloc(n);
+        plist[1].alloc(n);
+        DBuf<int> pcnt(2);
+        PAIR_HIP(hipMemsetAsync(pcnt.p, 0, 2 * sizeof(int), s_));
+        PAIR_HIP(hipMemsetAsync(notmax.p, 0, n, s_));
+        hipLaunchKernelGGL(k_pmis_init_list, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.seg.p,
+                           d_part.p, lam.p, state.p, plist[0].p, pcnt.p);
         PAIR_LAUNCH_CHECK();
-        for (int round = 0;; ++round) {
-            PAIR_CHECK(round < 100000, "PMIS did not terminate");
-            hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, s_, notmax.p, n,
-                               static_cast<uint8_t>(0));
-            hipLaunchKernelGGL(k_pmis_compare, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
-                               L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p, L.seg.p, d_off.p,
-                               l, prm_.seed, notmax.p);
-            hipLaunchKernelGGL(k_pmis_select, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
-                               state.p, notmax.p);
-            PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
-            hipLaunchKernelGGL(k_pmis_mark_f, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
-                               L.A.rowptr.p, L.A.col.p, sflag.p, state.p, d_counter.p);
-            PAIR_LAUNCH_CHECK();
-            int und = 0;
-            d2h(&und, d_counter.p, 1, s_);
-            PAIR_HIP(hipStreamSynchronize(s_));
-            if (und == 0) break;
+        {
+            const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(n, 256), 4096));
+            int cur = 0;
+            for (int round = 0;; ++round) {
+                PAIR_CHECK(round < 100000, "PMIS did not terminate");
+                const int nxt = cur ^ 1;
+                hipLaunchKernelGGL(k_pmis_compare_list, dim3(pg), dim3(256), 0, s_, plist[cur].p,
+                                   pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p,
+                                   L.seg.p, d_off.p, l, prm_.seed, notmax.p);
+                hipLaunchKernelGGL(k_pmis_select_list, dim3(pg), dim3(256), 0, s_, plist[cur].p,
+                                   pcnt.p + cur, state.p, notmax.p);
+                hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(1), 0, s_, pcnt.p + nxt);
+                hipLaunchKernelGGL(k_pmis_mark_list, dim3(pg), dim3(256), 0, s_, plist[cur].p,
+                                   pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p,
+                                   plist[nxt].p, pcnt.p + nxt);
+                PAIR_LAUNCH_CHECK();
+                cur = nxt;
+                if (round % 3 == 2) {
+                    int und = 0;
+                    d2h(&und, pcnt.p + cur, 1, s_);
+                    PAIR_HIP(hipStreamSynchronize(s_));
+                    if (und == 0) break;
+                }
+            }
         }
 
         // coarse numbering and the members that continue
@@ -1091,31 +1125,34 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
         {
-            DBuf<int32_t> rlist(total_c);
-            DBuf<int> rcount(1), rsing(1);
+            DBuf<int32_t> rl0(total_c), rl1(total_c), rl2(total_c);
+            DBuf<int> rcnt3(3), rsing(1);
             PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
-            const int bounds[4] = {-1, 16, 32, 64};
+            PAIR_HIP(hipMemsetAsync(rcnt3.p, 0, 3 * sizeof(int), s_));
+            hipLaunchKernelGGL(k_class3, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c, 1,
+                               L.R.rowptr.p, nullptr, int64_t(16), int64_t(32), rl0.p, rl1.p, rl2.p,
+                               rcnt3.p);
+            PAIR_LAUNCH_CHECK();
+            int nrc[3];
+            d2h(nrc, rcnt3.p, 3, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            const int32_t* rlists[3] = {rl0.p, rl1.p, rl2.p};
             for (int c = 0; c < 3; ++c) {
-                PAIR_HIP(hipMemsetAsync(rcount.p, 0, sizeof(int), s_));
-                hipLaunchKernelGGL(k_r_class, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
-                                   L.R.rowptr.p, bounds[c], bounds[c + 1], rlist.p, rcount.p);
-                PAIR_LAUNCH_CHECK();
-                int nr = 0;
-                d2h(&nr, rcount.p, 1, s_);
-                PAIR_HIP(hipStreamSynchronize(s_));
+                const int nr = nrc[c];
                 if (nr == 0) continue;
+                const int32_t* rlist = rlists[c];
                 const int rpw = c == 0 ? 4 : (c == 1 ? 2 : 1);
                 const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
                 if (c == 0)
-                    hipLaunchKernelGGL(k_r_build<16>, dim3(g), dim3(64), 0, s_, nr, rlist.p, c2f.p,
+                    hipLaunchKernelGGL(k_r_build<16>, dim3(g), dim3(64), 0, s_, nr, rlist, c2f.p,
                                        L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
                                        L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
                 else if (c == 1)
-                    hipLaunchKernelGGL(k_r_build<32>, dim3(g), dim3(64), 0, s_, nr, rlist.p, c2f.p,
+                    hipLaunchKernelGGL(k_r_build<32>, dim3(g), dim3(64), 0, s_, nr, rlist, c2f.p,
                                        L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
                                        L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
                 else
-                    hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, nr, rlist.p, c2f.p,
+                    hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, nr, rlist, c2f.p,
                                        L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
                                        L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
                 PAIR_LAUNCH_CHECK();
@@ -1131,47 +1168,42 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         DBuf<double> ap_val(L.A.nnz);
         DBuf<int> ap_len(n);
         {
-            DBuf<int32_t> alist(n);
-            const int bnd[4] = {-1, 64, 2048, 1 << 30};
-            for (int c = 0; c < 3; ++c) {
-                PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
-                hipLaunchKernelGGL(k_len_class, dim3(grid_for(n, 256)), dim3(256), 0, s_, n,
-                                   L.A.rowptr.p, bnd[c], bnd[c + 1], alist.p, d_counter.p);
-                PAIR_LAUNCH_CHECK();
-                int na = 0;
-                d2h(&na, d_counter.p, 1, s_);
-                PAIR_HIP(hipStreamSynchronize(s_));
-                if (na == 0) continue;
-                PAIR_CHECK(c < 2, "a row of a coarse operator has more than 2048 entries");
-                const unsigned g = static_cast<unsigned>(std::min(na, 1 << 20));
-                if (c == 0)
-                    hipLaunchKernelGGL((k_ap<64, 64>), dim3(g), dim3(64), 0, s_, na, alist.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
-                                       ap_len.p);
-                else
-                    hipLaunchKernelGGL((k_ap<256, 2048>), dim3(g), dim3(256), 0, s_, na, alist.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
-                                       ap_len.p);
-                PAIR_LAUNCH_CHECK();
-            }
+            DBuf<int32_t> al0(n), al1(n), al2(n);
+            DBuf<int> acnt(3);
+            PAIR_HIP(hipMemsetAsync(acnt.p, 0, 3 * sizeof(int), s_));
+            hipLaunchKernelGGL(k_class3, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, 0, L.A.rowptr.p,
+                               nullptr, int64_t(64), int64_t(2048), al0.p, al1.p, al2.p, acnt.p);
+            PAIR_LAUNCH_CHECK();
+            int na[3];
+            d2h(na, acnt.p, 3, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            PAIR_CHECK(na[2] == 0, "a row of a coarse operator has more than 2048 entries");
+            if (na[0] > 0)
+                hipLaunchKernelGGL((k_ap<64, 64>), dim3(std::min(na[0], 1 << 20)), dim3(64), 0, s_, na[0],
+                                   al0.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
+                                   ap_len.p);
+            if (na[1] > 0)
+                hipLaunchKernelGGL((k_ap<256, 2048>), dim3(std::min(na[1], 1 << 20)), dim3(256), 0, s_,
+                                   na[1], al1.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p,
+                                   ap_val.p, ap_len.p);
+            PAIR_LAUNCH_CHECK();
         }
         // Galerkin product R (A P), rows classed by their number of products
         DBuf<int64_t> ub(total_c), ccnt(total_c);
         hipLaunchKernelGGL(k_rap_ub, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
                            L.R.rowptr.p, L.R.col.p, ap_len.p, ub.p);
         PAIR_LAUNCH_CHECK();
-        struct Cls { int64_t lo, hi; };
-        const Cls classes[3] = {{-1, 256}, {256, 2048}, {2048, int64_t(1) << 40}};
         DBuf<int32_t> lists[3];
+        for (int c = 0; c < 3; ++c) lists[c].alloc(total_c);
         int lcount[3] = {0, 0, 0};
-        for (int c = 0; c < 3; ++c) {
-            lists[c].alloc(total_c);
-            PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
-            hipLaunchKernelGGL(k_class_rows, dim3(grid_for(total_c, 256)), dim3(256), 0, s_,
-                               total_c, ub.p, classes[c].lo, classes[c].hi, lists[c].p,
-                               d_counter.p);
+        {
+            DBuf<int> lc(3);
+            PAIR_HIP(hipMemsetAsync(lc.p, 0, 3 * sizeof(int), s_));
+            hipLaunchKernelGGL(k_class3, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c, 2,
+                               nullptr, ub.p, int64_t(256), int64_t(2048), lists[0].p, lists[1].p,
+                               lists[2].p, lc.p);
             PAIR_LAUNCH_CHECK();
-            d2h(&lcount[c], d_counter.p, 1, s_);
+            d2h(lcount, lc.p, 3, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
         }
         // hash-table scratch for the global class: 2 * pow2(products) slots per row
@@ -1279,6 +1311,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
     sb_.chunks = static_cast<int>((maxcnt + 511) / 512);
     sb_.partial.alloc(static_cast<size_t>(sb_.chunks) * B_);
     PAIR_HIP(hipStreamSynchronize(s_));
+    if (prm_.tune) tune_lanes();
 }
 
 Hierarchy::~Hierarchy() { drop_graph(); }

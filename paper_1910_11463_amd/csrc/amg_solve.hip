@@ -502,6 +502,76 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
     }
 }
 
+// Lanes per row of the row kernels, chosen per level index by timing the
+// residual (A) and restriction (R) kernels on the level's own data; the first
+// hierarchy measures, later ones reuse the choice.  Levels below a size
+// threshold keep the fixed table (their launches are latency-bound).
+void Hierarchy::tune_lanes() {
+    auto& cache = *prm_.tune;
+    const int nl = static_cast<int>(levels_.size());
+    DBuf<uint8_t> ones(B_);
+    PAIR_HIP(hipMemsetAsync(ones.p, 1, B_, s_));
+    hipEvent_t e0, e1;
+    PAIR_HIP(hipEventCreate(&e0));
+    PAIR_HIP(hipEventCreate(&e1));
+    auto time_it = [&](auto&& launch) {
+        launch();   // warm
+        PAIR_HIP(hipEventRecord(e0, s_));
+        for (int r = 0; r < 3; ++r) launch();
+        PAIR_HIP(hipEventRecord(e1, s_));
+        PAIR_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        PAIR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return ms;
+    };
+    for (int l = 0; l < nl; ++l) {
+        Level& L = levels_[l];
+        if (l + 1 >= nl || L.R.n == 0) continue;
+        auto it = cache.find(l);
+        if (it != cache.end()) {
+            L.lpr = it->second.first;
+            L.lpr_r = it->second.second;
+            continue;
+        }
+        if (L.A.n < 20000 || (l == 0 && ell_)) continue;
+        Level& C = levels_[l + 1];
+        const int cand[5] = {2, 4, 8, 16, 32};
+        float best = 1e30f;
+        int best_a = L.lpr, best_r = L.lpr_r;
+        for (int c : cand) {
+            float ms = 0.f;
+            dispatch_lpr(c, [&](auto lc) {
+                constexpr int LPR = decltype(lc)::value;
+                ms = time_it([&] {
+                    hipLaunchKernelGGL(k_residual<LPR>, dim3(grid_xcd(L.A.n, kBlock / LPR)), dim3(kBlock),
+                                       0, s_, L.A.n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.seg.p, ones.p,
+                                       L.relax.p, L.b.p, L.x.p, L.r.p);
+                });
+            });
+            if (ms < best) { best = ms; best_a = c; }
+        }
+        best = 1e30f;
+        for (int c : cand) {
+            float ms = 0.f;
+            dispatch_lpr(c, [&](auto lc) {
+                constexpr int LPR = decltype(lc)::value;
+                ms = time_it([&] {
+                    hipLaunchKernelGGL(k_restrict<LPR>, dim3(grid_xcd(L.R.n, kBlock / LPR)), dim3(kBlock),
+                                       0, s_, L.R.n, L.R.rowptr.p, L.R.col.p, L.R.val.p, C.seg.p, ones.p,
+                                       L.r.p, C.b.p);
+                });
+            });
+            if (ms < best) { best = ms; best_r = c; }
+        }
+        PAIR_LAUNCH_CHECK();
+        L.lpr = best_a;
+        L.lpr_r = best_r;
+        cache[l] = {best_a, best_r};
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
 void Hierarchy::drop_graph() {
     if (graph_exec_) { (void)hipGraphExecDestroy(graph_exec_); graph_exec_ = nullptr; }
     if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }

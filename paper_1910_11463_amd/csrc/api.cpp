@@ -182,6 +182,7 @@ void pair_default_options(pair_options* o) {
     o->allow_any_weight_sum = 0;
     std::strcpy(o->relax_pre, "FC");
     std::strcpy(o->relax_post, "FC");
+    o->autotune = 0;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {

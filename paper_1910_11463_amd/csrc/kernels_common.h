@@ -52,6 +52,20 @@ __device__ __forceinline__ double group_max(double v) {
     return v;
 }
 
+// Append to a global list with one atomic per wave: every lane of the wave must
+// call this (pred false for lanes with nothing to add).  Returns the slot of the
+// calling lane, or -1.  The order of entries across waves is not fixed.
+__device__ __forceinline__ int wave_append(bool pred, int* counter) {
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader, 64);
+    return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
 // SplitMix64 (Steele, Lea & Flood 2014): add the golden-ratio increment, then
 // the variant-13 finaliser.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {

@@ -41,6 +41,7 @@ AmgParams Context::amg_params() const {
     p.max_iter = opt.max_inner;
     p.relax_pre = opt.relax_pre;
     p.relax_post = opt.relax_post;
+    if (opt.autotune) p.tune = tune_cache;
     return p;
 }
 

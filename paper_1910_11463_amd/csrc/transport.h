@@ -74,6 +74,8 @@ struct Context {
 
     // cached operators
     std::vector<Batch> batches;
+    std::shared_ptr<std::map<int, std::pair<int, int>>> tune_cache =
+        std::make_shared<std::map<int, std::pair<int, int>>>();
     int cached_mode = -1;
 
     // state
