@@ -118,8 +118,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--cpu-dirs", type=int, default=16)
-    ap.add_argument("--relax-pre", default="FC")
-    ap.add_argument("--relax-post", default="FC")
+    ap.add_argument("--relax-pre", default="FFC")
+    ap.add_argument("--relax-post", default="FFC")
     args = ap.parse_args()
 
     if args.gpus != 1:
