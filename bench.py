@@ -35,11 +35,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_solver(w, mode_batch_size, device, pre="FC", post="FC"):
+def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
-               relax_pre=pre, relax_post=post, autotune=1)
+               relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
+               autotune=1, streams=streams)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -120,6 +121,10 @@ def main():
     ap.add_argument("--cpu-dirs", type=int, default=16)
     ap.add_argument("--relax-pre", default="FFC")
     ap.add_argument("--relax-post", default="FFC")
+    ap.add_argument("--relax-pre-coarse", default="=")
+    ap.add_argument("--relax-post-coarse", default="=")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="direction batches set up and solved at once, one HIP stream each")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -143,7 +148,8 @@ def main():
     log("workload %s: N=%d, M=%d, mode=%s" % (w.name, N, M, args.mode))
 
     s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                    args.relax_pre, args.relax_post)
+                    args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse,
+                    args.streams)
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
     value = N * M / sec
@@ -158,7 +164,8 @@ def main():
     if not args.no_extra:
         other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
         s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device,
-                         args.relax_pre, args.relax_post)
+                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
+                         args.relax_post_coarse, args.streams)
         osec, ost = timed_steps(s2, other, 1, 0, cold=True)
         wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
         extra["other_mode"] = {"mode": "batched" if other == B.PAIR_BATCHED else "plain",
@@ -187,8 +194,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "mode": args.mode, "dof_per_dir": N, "dirs": M,
                    "tol": 1e-8, "step": "cold sweep replacement: assembly + AIR setup + V-cycles + phi",
-                   "relax": "V(%s,%s) Jacobi half-sweeps" % (args.relax_pre, args.relax_post),
-                   "parallelism": "1 GPU"},
+                   "relax": "V(%s,%s) Jacobi half-sweeps, coarser levels V(%s,%s)" % (
+                       args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse),
+                   "streams": args.streams, "parallelism": "1 GPU"},
         "stats": {"vcycles_total": st["vcycles_total"], "vcycles_max": st["vcycles_max"],
                   "cf_mean": st["cf_mean"], "levels": st["levels_max"],
                   "op_complexity": st["op_complexity"], "assemble_ms": st["t_assemble_ms"],

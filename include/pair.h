@@ -82,6 +82,13 @@ typedef struct pair_options {
                                  Jacobi sweeps over F-points, then one over C-points */
     int autotune;             /* 1: time the row kernels of each level once per context
                                  and keep the fastest lanes-per-row (0: fixed table)  */
+    char relax_pre_coarse[8]; /* schedules on the coarser levels; "=" (default) means */
+    char relax_post_coarse[8];/* the same as on the finest level                     */
+    int streams;              /* plain/batched sweeps: number of direction batches set
+                                 up and solved at once, each on its own HIP stream
+                                 driven by its own host thread (default 1).  Results
+                                 do not depend on it: every batch does the same
+                                 arithmetic, and phi is accumulated in batch order. */
 } pair_options;
 
 void pair_default_options(pair_options* opt);
@@ -100,7 +107,8 @@ typedef struct pair_stats {
     double op_complexity;     /* sum_l nnz_l / nnz_0, mean over directions      */
     int64_t level_n[PAIR_MAX_LEVELS];   /* direction 0: rows per level           */
     int64_t level_nnz[PAIR_MAX_LEVELS]; /* direction 0: nonzeros per level       */
-    double t_assemble_ms, t_setup_ms, t_solve_ms, t_other_ms; /* GPU-synchronised wall times */
+    double t_assemble_ms, t_setup_ms, t_solve_ms, t_other_ms; /* GPU-synchronised wall times,
+                                 summed over the streams (see pair_options.streams) */
     double bytes_solve;       /* algorithmic bytes moved by the V-cycle kernels  */
 } pair_stats;
 

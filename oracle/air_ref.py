@@ -300,10 +300,15 @@ def _relax(A, d, b, x, mask, omega):
 
 
 def vcycle(levels: List[Level], b: np.ndarray, x: np.ndarray, lev: int = 0,
-           omega: float = 1.0, pre: str = "FC", post: str = "FC") -> np.ndarray:
+           omega: float = 1.0, pre: str = "FC", post: str = "FC", pre_c=None,
+           post_c=None) -> np.ndarray:
     """One V-cycle; each character of pre/post is one Jacobi half-sweep over the
-    F-points ("F") or the C-points ("C")."""
+    F-points ("F") or the C-points ("C"); pre_c/post_c (default: the same) apply
+    on the coarser levels."""
     L = levels[lev]
+    if lev > 0:
+        pre = pre if pre_c is None else pre_c
+        post = post if post_c is None else post_c
     if lev == len(levels) - 1:
         return np.linalg.solve(L.A.toarray(), b)
     d = L.A.diagonal()
@@ -313,7 +318,9 @@ def vcycle(levels: List[Level], b: np.ndarray, x: np.ndarray, lev: int = 0,
         x = _relax(L.A, d, b, x, F if ch == "F" else C, omega)
     r = b - L.A @ x
     bc = L.R @ r
-    xc = vcycle(levels, bc, np.zeros(L.R.shape[0]), lev + 1, omega, pre, post)
+    pc = pre if pre_c is None else pre_c
+    qc = post if post_c is None else post_c
+    xc = vcycle(levels, bc, np.zeros(L.R.shape[0]), lev + 1, omega, pc, qc)
     x = x + L.P @ xc
     for ch in post:
         x = _relax(L.A, d, b, x, F if ch == "F" else C, omega)
@@ -321,7 +328,8 @@ def vcycle(levels: List[Level], b: np.ndarray, x: np.ndarray, lev: int = 0,
 
 
 def solve(levels: List[Level], b: np.ndarray, tol: float = 1e-10, maxit: int = 200,
-          x0=None, omega: float = 1.0, pre: str = "FC", post: str = "FC"):
+          x0=None, omega: float = 1.0, pre: str = "FC", post: str = "FC", pre_c=None,
+          post_c=None):
     A = levels[0].A
     x = np.zeros_like(b) if x0 is None else x0.copy()
     nb = np.linalg.norm(b)
@@ -331,7 +339,7 @@ def solve(levels: List[Level], b: np.ndarray, tol: float = 1e-10, maxit: int = 2
         hist.append(rel)
         if rel <= tol:
             return x, it, hist
-        x = vcycle(levels, b, x, 0, omega, pre, post)
+        x = vcycle(levels, b, x, 0, omega, pre, post, pre_c, post_c)
     rel = np.linalg.norm(b - A @ x) / nb
     hist.append(rel)
     return x, maxit, hist

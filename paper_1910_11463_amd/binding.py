@@ -37,7 +37,9 @@ class pair_options(ctypes.Structure):
                 ("keep_hierarchy", c_int), ("warm_start", c_int), ("batch_size", c_int),
                 ("use_graph", c_int), ("allow_any_weight_sum", c_int),
                 ("relax_pre", ctypes.c_char * 8), ("relax_post", ctypes.c_char * 8),
-                ("autotune", c_int)]
+                ("autotune", c_int),
+                ("relax_pre_coarse", ctypes.c_char * 8), ("relax_post_coarse", ctypes.c_char * 8),
+                ("streams", c_int)]
 
 
 class pair_stats(ctypes.Structure):
@@ -174,7 +176,7 @@ def default_options(**overrides) -> pair_options:
     for k, v in overrides.items():
         if not hasattr(o, k):
             raise KeyError(k)
-        if k in ("relax_pre", "relax_post") and isinstance(v, str):
+        if k.startswith("relax_") and isinstance(v, str):
             v = v.encode()
         setattr(o, k, v)
     return o

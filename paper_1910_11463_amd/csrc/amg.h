@@ -11,12 +11,21 @@
 
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "common.h"
 
 namespace pair {
+
+// Autotuned lanes per row, keyed by level index: (A kernels, R kernels).
+// Shared by every hierarchy built with the same parameters; the first hierarchy
+// to reach a level measures it (holding the lock), later ones reuse the choice.
+struct TuneCache {
+    std::mutex mu;
+    std::map<int, std::pair<int, int>> lanes;
+};
 
 struct AmgParams {
     double theta = 0.25;
@@ -30,10 +39,9 @@ struct AmgParams {
     double tol = 1e-8;
     int max_iter = 100;
     int max_dense = 2048;   // largest coarsest level solved by a dense inverse
-    std::string relax_pre = "FC", relax_post = "FC";   // half-sweep schedules
-    // Autotuned lanes per row, keyed by level index: (A kernels, R kernels).
-    // Shared by every hierarchy built with these parameters; null = fixed table.
-    std::shared_ptr<std::map<int, std::pair<int, int>>> tune;
+    std::string relax_pre = "FC", relax_post = "FC";   // half-sweep schedules, finest level
+    std::string relax_pre_coarse = "FC", relax_post_coarse = "FC";   // coarser levels
+    std::shared_ptr<TuneCache> tune;   // null: fixed lanes-per-row table
     // lanes per row of the row kernels: index 0 = finest level, last entry used
     // for all deeper levels.  A function of the level index only, so that every
     // member's arithmetic (and its rounding) is the same whether it is solved

@@ -166,22 +166,28 @@ __global__ void k_pmis_mark_list(const int32_t* __restrict__ list, const int* __
 // Rows (or coarse rows) sorted into three size classes in one pass:
 // mode 0: row length of A; mode 1: local lAIR system size (R row length - 1);
 // mode 2: product upper bound ub[i].
+// Split rows into up to four classes by a per-row size v (mode 0: row length of
+// a, mode 1: row length minus one, mode 2: ub[i]); class k holds the rows with
+// b_k < v <= b_{k+1} (b_0 = -inf, b_3 = +inf when only three classes are used).
 __global__ void k_class3(int64_t n, int mode, const int64_t* __restrict__ a,
                          const int64_t* __restrict__ ub, int64_t b1, int64_t b2,
                          int32_t* __restrict__ l0, int32_t* __restrict__ l1,
-                         int32_t* __restrict__ l2, int* __restrict__ cnt) {
+                         int32_t* __restrict__ l2, int* __restrict__ cnt,
+                         int64_t b3 = INT64_MAX, int32_t* __restrict__ l3 = nullptr) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     int cls = -1;
     if (i < n) {
         const int64_t v = mode == 2 ? ub[i] : (a[i + 1] - a[i] - (mode == 1 ? 1 : 0));
-        cls = v <= b1 ? 0 : (v <= b2 ? 1 : 2);
+        cls = v <= b1 ? 0 : (v <= b2 ? 1 : (v <= b3 ? 2 : 3));
     }
     const int s0 = wave_append(cls == 0, &cnt[0]);
     const int s1 = wave_append(cls == 1, &cnt[1]);
     const int s2 = wave_append(cls == 2, &cnt[2]);
+    const int s3 = wave_append(cls == 3, &cnt[3]);
     if (cls == 0) l0[s0] = static_cast<int32_t>(i);
     if (cls == 1) l1[s1] = static_cast<int32_t>(i);
     if (cls == 2) l2[s2] = static_cast<int32_t>(i);
+    if (cls == 3) l3[s3] = static_cast<int32_t>(i);
 }
 
 // ------------------------------------------------------------- coarse numbering
@@ -497,6 +503,67 @@ __device__ __forceinline__ void block_count(bool flag, int* s_red, int& before, 
     }
     before += __popcll(m & ((1ull << lane) - 1ull));
     __syncthreads();
+}
+
+// Rows of A with at most G entries (every finest-level row fits G = 32): G
+// lanes per row, keys sorted in registers with a shuffle bitonic network, each
+// run of equal coarse columns summed by a segmented scan in a fixed tree order
+// (reproducible; a row always takes the same kernel, whatever the batch).
+template <int G>
+__global__ void __launch_bounds__(256)
+k_ap_reg(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ rowptr,
+           const int32_t* __restrict__ col, const double* __restrict__ val,
+           const int32_t* __restrict__ p, int32_t* __restrict__ ap_col, double* __restrict__ ap_val,
+           int* __restrict__ ap_len) {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & (G - 1);
+    const int base_l = lane & ~(G - 1);
+    const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull)) << base_l;
+    const int64_t r = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const bool have = r < nrows;
+    const int64_t i = have ? list[r] : 0;
+    const int64_t rs = have ? rowptr[i] : 0;
+    const int len = have ? static_cast<int>(rowptr[i + 1] - rs) : 0;
+    uint64_t key = KEY_NONE;
+    double v = 0.0;
+    if (sub < len) {
+        const int32_t c = p[col[rs + sub]];
+        v = val[rs + sub];
+        if (c >= 0) key = (static_cast<uint64_t>(static_cast<uint32_t>(c)) << 32) | static_cast<uint32_t>(sub);
+    }
+#pragma unroll
+    for (int k = 2; k <= G; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t other = __shfl_xor(key, j, 64);
+            const bool up = (sub & k) == 0;
+            const bool lower = (sub & j) == 0;
+            key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
+        }
+    const uint64_t prev = __shfl(key, base_l + (sub > 0 ? sub - 1 : 0), 64);
+    const uint64_t next = __shfl(key, base_l + (sub + 1 < G ? sub + 1 : G - 1), 64);
+    const bool lead = key != KEY_NONE && (sub == 0 || (prev >> 32) != (key >> 32));
+    // segmented suffix sums (Hillis-Steele): after the log2(G) steps the first
+    // lane of each run holds the sum of the run's values
+    double acc = __shfl(v, base_l + static_cast<int>(key & (G - 1)), 64);
+    bool tail = sub == G - 1 || (next >> 32) != (key >> 32);
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const int src = base_l + (sub + d < G ? sub + d : G - 1);
+        const double va = __shfl(acc, src, 64);
+        const bool ta = __shfl(static_cast<int>(tail), src, 64) != 0;
+        if (!tail) {
+            acc += va;
+            tail = ta;
+        }
+    }
+    const uint64_t lm = __ballot(lead) & gmask;
+    const int rank = __popcll(lm & ((1ull << lane) - 1ull) & gmask);
+    if (have && lead) {
+        ap_col[rs + rank] = static_cast<int32_t>(key >> 32);
+        ap_val[rs + rank] = acc;
+    }
+    if (have && sub == 0) ap_len[i] = __popcll(lm);
 }
 
 template <int NT, int CAP>
@@ -1168,23 +1235,28 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         DBuf<double> ap_val(L.A.nnz);
         DBuf<int> ap_len(n);
         {
-            DBuf<int32_t> al0(n), al1(n), al2(n);
-            DBuf<int> acnt(3);
-            PAIR_HIP(hipMemsetAsync(acnt.p, 0, 3 * sizeof(int), s_));
+            DBuf<int32_t> al0(n), al1(n), al2(n), al3(n);
+            DBuf<int> acnt(4);
+            PAIR_HIP(hipMemsetAsync(acnt.p, 0, 4 * sizeof(int), s_));
             hipLaunchKernelGGL(k_class3, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, 0, L.A.rowptr.p,
-                               nullptr, int64_t(64), int64_t(2048), al0.p, al1.p, al2.p, acnt.p);
+                               nullptr, int64_t(32), int64_t(64), al0.p, al1.p, al2.p, acnt.p,
+                               int64_t(2048), al3.p);
             PAIR_LAUNCH_CHECK();
-            int na[3];
-            d2h(na, acnt.p, 3, s_);
+            int na[4];
+            d2h(na, acnt.p, 4, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            PAIR_CHECK(na[2] == 0, "a row of a coarse operator has more than 2048 entries");
+            PAIR_CHECK(na[3] == 0, "a row of a coarse operator has more than 2048 entries");
             if (na[0] > 0)
-                hipLaunchKernelGGL((k_ap<64, 64>), dim3(std::min(na[0], 1 << 20)), dim3(64), 0, s_, na[0],
-                                   al0.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
-                                   ap_len.p);
+                hipLaunchKernelGGL(k_ap_reg<32>, dim3(grid_for(static_cast<int64_t>(na[0]) * 32, 256)),
+                                   dim3(256), 0, s_, na[0], al0.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p,
+                                   ap_col.p, ap_val.p, ap_len.p);
             if (na[1] > 0)
-                hipLaunchKernelGGL((k_ap<256, 2048>), dim3(std::min(na[1], 1 << 20)), dim3(256), 0, s_,
-                                   na[1], al1.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p,
+                hipLaunchKernelGGL((k_ap<64, 64>), dim3(std::min(na[1], 1 << 20)), dim3(64), 0, s_, na[1],
+                                   al1.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
+                                   ap_len.p);
+            if (na[2] > 0)
+                hipLaunchKernelGGL((k_ap<256, 2048>), dim3(std::min(na[2], 1 << 20)), dim3(256), 0, s_,
+                                   na[2], al2.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p,
                                    ap_val.p, ap_len.p);
             PAIR_LAUNCH_CHECK();
         }

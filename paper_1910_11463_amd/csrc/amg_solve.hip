@@ -446,12 +446,13 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
         if (!has_relax) break;
         const int64_t n = L.A.n;
         const bool zero = (l == 0) ? x_is_zero : true;
-        if (zero && prm_.relax_pre.empty()) {
+        const std::string& pre = l == 0 ? prm_.relax_pre : prm_.relax_pre_coarse;
+        if (zero && pre.empty()) {
             hipLaunchKernelGGL(k_zero_rows, dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_, n, L.seg.p,
                                act, L.relax.p, L.x.p);
             PAIR_LAUNCH_CHECK();
         }
-        cur[l] = sweeps(L, l, prm_.relax_pre, L.x.p, L.t.p, zero);
+        cur[l] = sweeps(L, l, pre, L.x.p, L.t.p, zero);
         if (l == 0 && ell_) {
             const FineEll& E = *ell_;
             dispatch_ell(E, [&](auto kc, auto fc) {
@@ -493,7 +494,7 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
         hipLaunchKernelGGL(k_interpolate, dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_, n, L.p.p,
                            L.seg.p, act, L.relax.p, C.x.p, c);
         PAIR_LAUNCH_CHECK();
-        double* fin = sweeps(L, l, prm_.relax_post, c, o, false);
+        double* fin = sweeps(L, l, l == 0 ? prm_.relax_post : prm_.relax_post_coarse, c, o, false);
         if (fin != L.x.p) {
             hipLaunchKernelGGL(k_copy_rows, dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_, n, L.seg.p,
                                act, L.relax.p, fin, L.x.p);
@@ -507,7 +508,8 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
 // hierarchy measures, later ones reuse the choice.  Levels below a size
 // threshold keep the fixed table (their launches are latency-bound).
 void Hierarchy::tune_lanes() {
-    auto& cache = *prm_.tune;
+    std::lock_guard<std::mutex> lock(prm_.tune->mu);
+    auto& cache = prm_.tune->lanes;
     const int nl = static_cast<int>(levels_.size());
     DBuf<uint8_t> ones(B_);
     PAIR_HIP(hipMemsetAsync(ones.p, 1, B_, s_));

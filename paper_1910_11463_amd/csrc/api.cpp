@@ -31,15 +31,22 @@ struct pair_amg {
     int64_t n = 0;
     ~pair_amg() {
         H.reset();
-        if (own_stream && s) (void)hipStreamDestroy(s);
+        if (own_stream && s) {
+            (void)hipStreamSynchronize(s);
+            pool_retire_stream(s);
+            (void)hipStreamDestroy(s);
+        }
     }
 };
 
 namespace {
 
+// Runs f with the library's exceptions turned into return codes; device
+// buffers allocated inside are binned for stream s (see PoolStream).
 template <class F>
-int guarded(std::string& err, F&& f) {
+int guarded(std::string& err, hipStream_t s, F&& f) {
     try {
+        PoolStream ps(s);
         f();
         return PAIR_OK;
     } catch (const Error& e) {
@@ -86,6 +93,7 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.tol_inner > 0.0 && o.tol_outer > 0.0, "tolerances must be positive");
     PAIR_CHECK(o.max_inner >= 1 && o.max_outer >= 1, "iteration limits must be >= 1");
     PAIR_CHECK(o.batch_size >= 0, "batch_size must be >= 0");
+    PAIR_CHECK(o.streams >= 1 && o.streams <= 16, "streams must be in [1, 16]");
     auto sched_ok = [](const char* c) {
         size_t n = strnlen(c, 8);
         if (n >= 8) return false;
@@ -95,6 +103,9 @@ void validate_options(const pair_options& o) {
     };
     PAIR_CHECK(sched_ok(o.relax_pre) && sched_ok(o.relax_post),
                "relax_pre / relax_post: up to 7 characters from {F, C}");
+    auto coarse_ok = [&](const char* c) { return std::strncmp(c, "=", 8) == 0 || sched_ok(c); };
+    PAIR_CHECK(coarse_ok(o.relax_pre_coarse) && coarse_ok(o.relax_post_coarse),
+               "relax_pre_coarse / relax_post_coarse: \"=\" or up to 7 characters from {F, C}");
     PAIR_CHECK(strnlen(o.relax_pre, 8) + strnlen(o.relax_post, 8) >= 1, "no relaxation at all");
 }
 
@@ -183,6 +194,9 @@ void pair_default_options(pair_options* o) {
     std::strcpy(o->relax_pre, "FC");
     std::strcpy(o->relax_post, "FC");
     o->autotune = 0;
+    std::strcpy(o->relax_pre_coarse, "=");
+    std::strcpy(o->relax_post_coarse, "=");
+    o->streams = 1;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
@@ -190,7 +204,7 @@ int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
     *out = nullptr;
     std::string err;
     pair_ctx* ctx = nullptr;
-    int rc = guarded(err, [&] {
+    int rc = guarded(err, nullptr, [&] {
         ctx = new pair_ctx();
         pair_default_options(&ctx->c.opt);
         if (opt) {
@@ -213,16 +227,18 @@ const char* pair_last_error(const pair_ctx* ctx) { return ctx ? ctx->c.err.c_str
 
 int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
     if (!ctx || !opt) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         validate_options(*opt);
         Context& c = ctx->c;
         const bool amg_changed =
             opt->theta != c.opt.theta || opt->eps_r != c.opt.eps_r || opt->coarse_max != c.opt.coarse_max ||
             opt->max_levels != c.opt.max_levels || opt->max_coarse_ratio != c.opt.max_coarse_ratio ||
             opt->kmax != c.opt.kmax || opt->pmis_seed != c.opt.pmis_seed ||
-            opt->batch_size != c.opt.batch_size ||
+            opt->batch_size != c.opt.batch_size || opt->streams != c.opt.streams ||
             std::strncmp(opt->relax_pre, c.opt.relax_pre, 8) != 0 ||
-            std::strncmp(opt->relax_post, c.opt.relax_post, 8) != 0;
+            std::strncmp(opt->relax_post, c.opt.relax_post, 8) != 0 ||
+            std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, 8) != 0 ||
+            std::strncmp(opt->relax_post_coarse, c.opt.relax_post_coarse, 8) != 0;
         c.opt = *opt;
         if (amg_changed) invalidate(c);
         AmgParams p = c.amg_params();
@@ -243,7 +259,7 @@ int pair_quadrature_level_symmetric(int order, int* M, double* omega, double* w)
 
 int pair_set_mesh_hex(pair_ctx* ctx, int nx, int ny, int nz, const double* lo3, const double* hi3) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         PAIR_CHECK(nx >= 1 && ny >= 1 && nz >= 1, "mesh dimensions must be >= 1");
         const int64_t E = static_cast<int64_t>(nx) * ny * nz;
@@ -279,7 +295,7 @@ int pair_set_mesh_hex(pair_ctx* ctx, int nx, int ny, int nz, const double* lo3, 
 int pair_set_mesh(pair_ctx* ctx, int elem_type, int64_t n_vert, const double* xyz, int64_t n_elem,
                   const int32_t* elem_vert) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         PAIR_CHECK(elem_type == PAIR_TET4, "pair_set_mesh supports PAIR_TET4; use pair_set_mesh_hex for hexes");
         PAIR_CHECK(n_vert >= 4 && n_elem >= 1 && xyz && elem_vert, "empty mesh");
@@ -312,7 +328,7 @@ int pair_set_mesh(pair_ctx* ctx, int elem_type, int64_t n_vert, const double* xy
 
 int pair_set_quadrature(pair_ctx* ctx, int M, const double* omega, const double* w) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         PAIR_CHECK(M >= 1 && M <= 65535 && omega && w, "bad quadrature");
         double sw = 0.0;
@@ -342,7 +358,7 @@ int pair_set_quadrature(pair_ctx* ctx, int M, const double* omega, const double*
 int pair_set_materials(pair_ctx* ctx, const double* sigma_t, const double* sigma_s, const double* q,
                        int where) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         check_where(where);
         if (!c.have_mesh) throw Error(E_STATE, "set the mesh before the materials");
@@ -381,7 +397,7 @@ int pair_set_materials(pair_ctx* ctx, const double* sigma_t, const double* sigma
 
 int pair_set_dual_source(pair_ctx* ctx, const double* src, int per_direction, int where) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         if (!src) {
             c.ext.reset();
@@ -418,7 +434,7 @@ int pair_transport_sweep(pair_ctx* ctx, int mode, const double* phi_in, double* 
                          double* phi_out, int where, pair_stats* st) {
     if (!ctx) return PAIR_E_INVALID;
     int rc = PAIR_OK;
-    int grc = guarded(ctx->c.err, [&] {
+    int grc = guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         check_where(where);
         c.check_ready();
@@ -512,7 +528,7 @@ int pair_solve(pair_ctx* ctx, int mode, const double* phi0, double* phi_out, dou
                pair_stats* st) {
     if (!ctx) return PAIR_E_INVALID;
     int rc = PAIR_OK;
-    int grc = guarded(ctx->c.err, [&] {
+    int grc = guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         check_where(where);
         c.check_ready();
@@ -539,7 +555,7 @@ int pair_adjoint(pair_ctx* ctx, int mode, const double* grad_phi, double* dJ_dsi
                  double* phi_adj_out, int where, pair_stats* st) {
     if (!ctx) return PAIR_E_INVALID;
     int rc = PAIR_OK;
-    int grc = guarded(ctx->c.err, [&] {
+    int grc = guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         check_where(where);
         c.check_ready();
@@ -597,7 +613,7 @@ int pair_adjoint(pair_ctx* ctx, int mode, const double* grad_phi, double* dJ_dsi
 
 int pair_clear_cache(pair_ctx* ctx) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         ctx->c.batches.clear();
         ctx->c.cached_mode = -1;
     });
@@ -605,7 +621,7 @@ int pair_clear_cache(pair_ctx* ctx) {
 
 int pair_direction_info(pair_ctx* ctx, int m, int* vcycles, double* cf, double* relres) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         PAIR_CHECK(m >= 0 && m < static_cast<int>(c.dir_iters.size()), "direction index out of range");
         if (vcycles) *vcycles = c.dir_iters[m];
@@ -617,13 +633,13 @@ int pair_direction_info(pair_ctx* ctx, int m, int* vcycles, double* cf, double* 
 int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowptr, int32_t* col,
                               double* val, double* b) {
     if (!ctx) return PAIR_E_INVALID;
-    return guarded(ctx->c.err, [&] {
+    return guarded(ctx->c.err, ctx->c.s, [&] {
         Context& c = ctx->c;
         c.check_ready();
         PAIR_CHECK(m >= 0 && m < c.M, "direction index out of range");
         Batch bt;
         bt.dirs = {m};
-        Csr A = c.assemble_fine(bt, nullptr);
+        Csr A = c.assemble_fine(bt, c.s, nullptr);
         const int64_t N = c.N();
         if (nnz) *nnz = A.nnz;
         if (rowptr) {
@@ -638,7 +654,7 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
             src.ext = c.have_ext ? c.ext.p : nullptr;
             src.ext_per_dir = c.ext_per_dir;
             DBuf<double> tmp(N);
-            c.rhs_batch(bt, src, nullptr, tmp.p);
+            c.rhs_batch(bt, src, nullptr, tmp.p, c.s);
             d2h(b, tmp.p, N, c.s);
         }
         PAIR_HIP(hipStreamSynchronize(c.s));
@@ -648,13 +664,13 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
 // ----------------------------------------------------------------- profiling
 int pair_profile_enable(int on) {
     std::string err;
-    return guarded(err, [&] { prof_enable(on != 0); });
+    return guarded(err, nullptr, [&] { prof_enable(on != 0); });
 }
 
 int pair_profile_read(int kind, int64_t* launches, double* total_ms, double* total_bytes) {
     if (kind < 0 || kind >= PROF_NKINDS) return PAIR_E_INVALID;
     std::string err;
-    return guarded(err, [&] { prof_read(kind, launches, total_ms, total_bytes); });
+    return guarded(err, nullptr, [&] { prof_read(kind, launches, total_ms, total_bytes); });
 }
 
 // ----------------------------------------------------------------- generic AMG
@@ -663,7 +679,7 @@ int pair_amg_create(pair_amg** out, const pair_options* opt, void* hip_stream) {
     *out = nullptr;
     std::string err;
     pair_amg* a = nullptr;
-    int rc = guarded(err, [&] {
+    int rc = guarded(err, nullptr, [&] {
         a = new pair_amg();
         pair_default_options(&a->opt);
         if (opt) {
@@ -687,7 +703,7 @@ const char* pair_amg_last_error(const pair_amg* amg) { return amg ? amg->err.c_s
 int pair_amg_setup(pair_amg* amg, int n_seg, const int64_t* seg_rows, int64_t n, const int64_t* rowptr,
                    const int32_t* col, const double* val, int where) {
     if (!amg) return PAIR_E_INVALID;
-    return guarded(amg->err, [&] {
+    return guarded(amg->err, amg->s, [&] {
         check_where(where);
         PAIR_CHECK(n_seg >= 1 && n_seg <= 65535 && seg_rows && rowptr && col && val, "bad arguments");
         PAIR_CHECK(n >= 1 && n < (int64_t(1) << 31), "matrix size out of range");
@@ -748,6 +764,8 @@ int pair_amg_setup(pair_amg* amg, int n_seg, const int64_t* seg_rows, int64_t n,
         p.max_iter = amg->opt.max_inner;
         p.relax_pre = amg->opt.relax_pre;
         p.relax_post = amg->opt.relax_post;
+        p.relax_pre_coarse = std::strcmp(amg->opt.relax_pre_coarse, "=") ? amg->opt.relax_pre_coarse : p.relax_pre;
+        p.relax_post_coarse = std::strcmp(amg->opt.relax_post_coarse, "=") ? amg->opt.relax_post_coarse : p.relax_post;
         amg->H.reset(new Hierarchy(p, amg->s));
         amg->H->setup(std::move(A), off, cnt);
         amg->n_seg = n_seg;
@@ -764,7 +782,7 @@ int pair_amg_segment_levels(const pair_amg* amg, int s) {
 
 int pair_amg_level_sizes(pair_amg* amg, int level, int64_t* n, int64_t* nnz, int64_t* nnz_r) {
     if (!amg) return PAIR_E_INVALID;
-    return guarded(amg->err, [&] {
+    return guarded(amg->err, amg->s, [&] {
         if (!amg->H) throw Error(E_STATE, "no hierarchy");
         PAIR_CHECK(level >= 0 && level < amg->H->num_levels(), "level out of range");
         Level& L = amg->H->level(level);
@@ -777,7 +795,7 @@ int pair_amg_level_sizes(pair_amg* amg, int level, int64_t* n, int64_t* nnz, int
 int pair_amg_get_level(pair_amg* amg, int level, int64_t* rowptr, int32_t* col, double* val, int8_t* cf,
                        int32_t* p, int64_t* r_rowptr, int32_t* r_col, double* r_val) {
     if (!amg) return PAIR_E_INVALID;
-    return guarded(amg->err, [&] {
+    return guarded(amg->err, amg->s, [&] {
         if (!amg->H) throw Error(E_STATE, "no hierarchy");
         PAIR_CHECK(level >= 0 && level < amg->H->num_levels(), "level out of range");
         Level& L = amg->H->level(level);
@@ -799,7 +817,7 @@ int pair_amg_get_level(pair_amg* amg, int level, int64_t* rowptr, int32_t* col, 
 int pair_amg_solve(pair_amg* amg, const double* b, double* x, int where, int* iters, double* relres) {
     if (!amg) return PAIR_E_INVALID;
     int rc = PAIR_OK;
-    int grc = guarded(amg->err, [&] {
+    int grc = guarded(amg->err, amg->s, [&] {
         check_where(where);
         if (!amg->H) throw Error(E_STATE, "no hierarchy");
         PAIR_CHECK(b && x, "null vector");

@@ -267,37 +267,82 @@ __device__ bool small_inverse(double Amat[K * K], double Inv[K * K]) {
     return true;
 }
 
-__global__ void __launch_bounds__(128)
-k_fine_hex(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
-           const double* __restrict__ omega, const int* __restrict__ dirs, int B,
-           const double* __restrict__ sigt, const int64_t* __restrict__ elem_off,
-           int64_t* __restrict__ rowptr, int32_t* __restrict__ col, double* __restrict__ val,
-           double* __restrict__ dinv, int* __restrict__ bad, int32_t* __restrict__ ell_nbr,
-           int32_t* __restrict__ ell_nodes, double* __restrict__ ell_val) {
-    int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= E * B) return;
+// In-register Gauss-Jordan inverse of a K x K block held one row per lane in a
+// group of K lanes (K = 8 or 4): lane a holds row a of [D | I] and ends with row
+// a of D^{-1}.  Partial pivoting; the same operation sequence as a serial
+// Gauss-Jordan.  Returns false (on every lane) for a singular block.
+template <int K>
+__device__ __forceinline__ bool group_inverse(double row[2 * K], int a, int lane_base) {
+    bool ok = true;
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+        double v = a >= p ? fabs(row[p]) : -1.0;
+        int idx = a;
+#pragma unroll
+        for (int d = K / 2; d >= 1; d >>= 1) {
+            const double ov = __shfl_xor(v, d, 64);
+            const int oi = __shfl_xor(idx, d, 64);
+            if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+        }
+        if (!(v > 0.0)) ok = false;
+        const int piv = idx;
+        const int src = a == p ? piv : (a == piv ? p : a);
+#pragma unroll
+        for (int c = 0; c < 2 * K; ++c) row[c] = __shfl(row[c], lane_base + src, 64);
+        const double sc = 1.0 / __shfl(row[p], lane_base + p, 64);
+        const double f = row[p];
+#pragma unroll
+        for (int c = 0; c < 2 * K; ++c) {
+            const double pc = __shfl(row[c], lane_base + p, 64) * sc;
+            row[c] = (a == p) ? pc : row[c] - f * pc;
+        }
+    }
+    return ok;
+}
+
+// Fine operator of a structured hex mesh, 8 lanes per (direction, element):
+// lane a builds row a of D_e, the group inverts D_e, and lane a writes row a of
+// D_e^{-1}, of the scaled CSR operator and of the element-block copy.
+__global__ void __launch_bounds__(256)
+k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
+                 const double* __restrict__ omega, const int* __restrict__ dirs, int B,
+                 const double* __restrict__ sigt, const int64_t* __restrict__ elem_off,
+                 int64_t* __restrict__ rowptr, int32_t* __restrict__ col, double* __restrict__ val,
+                 double* __restrict__ dinv, int* __restrict__ bad, int32_t* __restrict__ ell_nbr,
+                 int32_t* __restrict__ ell_nodes, double* __restrict__ ell_val) {
+    const int64_t gl = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int a = static_cast<int>(gl & 7);
+    const int lane_base = (threadIdx.x & 63) & ~7;
+    const bool valid = (gl >> 3) < E * B;
+    const int64_t g = valid ? (gl >> 3) : 0;
     const int b = static_cast<int>(g / E);
     const int64_t e = g % E;
     const int m = dirs[b];
     const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
     const double st = sigt[e];
-    double D[64], Di[64];
-    for (int r = 0; r < 64; ++r)
-        D[r] = st * ref[REF_M + r] -
-               (om[0] * ref[REF_C + r] + om[1] * ref[REF_C + 64 + r] + om[2] * ref[REF_C + 128 + r]);
-    for (int d = 0; d < 3; ++d) {
-        if (fabs(om[d]) <= kZeroFluxTol) continue;
-        const int fout = 2 * d + (om[d] > 0.0 ? 1 : 0);
-        const double on = fabs(om[d]);
-        for (int r = 0; r < 64; ++r) D[r] += on * ref[REF_F + fout * 64 + r];
+    double row[16];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int r = a * 8 + c;
+        double v = st * ref[REF_M + r] -
+                   (om[0] * ref[REF_C + r] + om[1] * ref[REF_C + 64 + r] + om[2] * ref[REF_C + 128 + r]);
+        for (int d = 0; d < 3; ++d) {
+            if (fabs(om[d]) <= kZeroFluxTol) continue;
+            const int fout = 2 * d + (om[d] > 0.0 ? 1 : 0);
+            v += fabs(om[d]) * ref[REF_F + fout * 64 + r];
+        }
+        row[c] = v;
+        row[8 + c] = (c == a) ? 1.0 : 0.0;
     }
-    if (!small_inverse<8>(D, Di)) atomicAdd(bad, 1);
-    double* dst = dinv + (static_cast<int64_t>(b) * E + e) * 64;
-    for (int r = 0; r < 64; ++r) dst[r] = Di[r];
+    const bool ok = group_inverse<8>(row, a, lane_base);
+    if (!valid) return;
+    if (!ok && a == 0) atomicAdd(bad, 1);
+    const double* Di = row + 8;
+    double* dst = dinv + g * 64 + a * 8;
+    for (int c = 0; c < 8; ++c) dst[c] = Di[c];
 
     HexFace fc[3];
     const int ni = hex_inflow_faces(e, nx, ny, nz, om, fc);
-    // order the column groups (self + upwind neighbours) by element id
     int64_t gid[4];
     int gface[4];
     int ng = 0;
@@ -310,51 +355,46 @@ k_fine_hex(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
         }
     const int L = 1 + 4 * ni;
     const int64_t N = E * 8;
-    const int64_t row0 = static_cast<int64_t>(b) * N + 8 * e;
-    const int64_t base = elem_off[g];
-    const int64_t coff = static_cast<int64_t>(b) * N;   // column offset of this member
-    // element-block (ELL) copy of the off-diagonal blocks: slot = face axis
+    const int64_t row_g = static_cast<int64_t>(b) * N + 8 * e + a;
+    const int64_t coff = static_cast<int64_t>(b) * N;
     const int64_t nrows = N * B, nel = E * B;
-    for (int sl = 0; sl < 3; ++sl) {
-        ell_nbr[sl * nel + g] = -1;
-        ell_nodes[sl * nel + g] = 0;
+    if (a == 0) {
+        for (int sl = 0; sl < 3; ++sl) {
+            ell_nbr[sl * nel + g] = -1;
+            ell_nodes[sl * nel + g] = 0;
+        }
+        for (int q = 0; q < ni; ++q) {
+            const int ax = fc[q].face >> 1, side = fc[q].face & 1;
+            ell_nbr[ax * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + fc[q].U);
+            int packed = 0, j = 0;
+            for (int cu = 0; cu < 8; ++cu)
+                if (((cu >> ax) & 1) == 1 - side) { packed |= cu << (3 * j); ++j; }
+            ell_nodes[ax * nel + g] = packed;
+        }
     }
-    for (int q = 0; q < ni; ++q) {
-        const int ax = fc[q].face >> 1, side = fc[q].face & 1;
-        ell_nbr[ax * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + fc[q].U);
-        int packed = 0, j = 0;
-        for (int cu = 0; cu < 8; ++cu)
-            if (((cu >> ax) & 1) == 1 - side) { packed |= cu << (3 * j); ++j; }
-        ell_nodes[ax * nel + g] = packed;
-    }
-    for (int a = 0; a < 8; ++a)
-        for (int j = 0; j < 12; ++j) ell_val[j * nrows + row0 + a] = 0.0;
-    for (int a = 0; a < 8; ++a) {
-        const int64_t rb = base + static_cast<int64_t>(a) * L;
-        rowptr[row0 + a] = rb;
-        int pos = 0;
-        for (int gi = 0; gi < ng; ++gi) {
-            if (gface[gi] < 0) {
-                col[rb + pos] = static_cast<int32_t>(coff + 8 * e + a);
-                val[rb + pos] = 1.0;
-                ++pos;
-                continue;
-            }
-            const HexFace& F = fc[gface[gi]];
-            const int ax = F.face >> 1, side = F.face & 1;
-            // U's nodes on the shared face have bit ax == 1 - side; ascending local order
-            int j = 0;
-            for (int cu = 0; cu < 8; ++cu) {
-                if (((cu >> ax) & 1) != 1 - side) continue;
-                double s = 0.0;
-                for (int c = 0; c < 8; ++c)
-                    s += Di[a * 8 + c] * (F.odn * ref[REF_X + F.face * 64 + c * 8 + cu]);
-                col[rb + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
-                val[rb + pos] = s;
-                ell_val[(ax * 4 + j) * nrows + row0 + a] = s;
-                ++pos;
-                ++j;
-            }
+    for (int j = 0; j < 12; ++j) ell_val[j * nrows + row_g] = 0.0;
+    const int64_t rb = elem_off[g] + static_cast<int64_t>(a) * L;
+    rowptr[row_g] = rb;
+    int pos = 0;
+    for (int gi = 0; gi < ng; ++gi) {
+        if (gface[gi] < 0) {
+            col[rb + pos] = static_cast<int32_t>(coff + 8 * e + a);
+            val[rb + pos] = 1.0;
+            ++pos;
+            continue;
+        }
+        const HexFace& F = fc[gface[gi]];
+        const int ax = F.face >> 1, side = F.face & 1;
+        int j = 0;
+        for (int cu = 0; cu < 8; ++cu) {
+            if (((cu >> ax) & 1) != 1 - side) continue;
+            double sv = 0.0;
+            for (int c = 0; c < 8; ++c) sv += Di[c] * (F.odn * ref[REF_X + F.face * 64 + c * 8 + cu]);
+            col[rb + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
+            val[rb + pos] = sv;
+            ell_val[(ax * 4 + j) * nrows + row_g] = sv;
+            ++pos;
+            ++j;
         }
     }
 }
@@ -626,7 +666,7 @@ void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d
     DBuf<int> bad(1);
     PAIR_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
     if (m.kind == PAIR_HEX8)
-        hipLaunchKernelGGL(k_fine_hex, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, m.nx,
+        hipLaunchKernelGGL(k_fine_hex_lanes, dim3(grid_for(m.E * B * 8, 256)), dim3(256), 0, s, m.E, m.nx,
                            m.ny, m.nz, m.ref.p, omega_d, dirs_d, B, sigt, elem_off, rowptr, col,
                            val, dinv, bad.p, ell.nbr.p, ell.nodes.p, ell.val.p);
     else

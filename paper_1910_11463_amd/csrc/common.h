@@ -44,13 +44,28 @@ enum : int {
 #define PAIR_LAUNCH_CHECK() PAIR_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------- device memory
-// Caching allocator: freed blocks are kept in per-size bins (sizes rounded up to
-// a power of two) and handed out again, so repeated setups and solves do not pay
-// for hipMalloc/hipFree.  All memory is returned by pool_release_all().
+// Caching allocator: freed blocks are kept in bins by size (rounded up to a
+// power of two) and by the stream their owner works on, and are handed out again
+// only to allocations for that same stream, so stream order makes reuse safe
+// without synchronisation while several streams work at once.  The stream of an
+// allocation is the calling thread's pool stream (PoolStream).  All cached
+// memory is returned by pool_release_all().
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 void pool_release_all();
 size_t pool_bytes_in_use();
+// Call once s is synchronised and no longer used: its cached blocks become
+// available to every stream.
+void pool_retire_stream(hipStream_t s);
+
+// Sets the calling thread's pool stream for its lifetime (restored after).
+struct PoolStream {
+    explicit PoolStream(hipStream_t s);
+    ~PoolStream();
+    PoolStream(const PoolStream&) = delete;
+    PoolStream& operator=(const PoolStream&) = delete;
+    hipStream_t prev;
+};
 
 template <class T>
 struct DBuf {

@@ -10,16 +10,23 @@ namespace pair {
 
 // ---------------------------------------------------------------- allocator
 namespace {
+struct Block {
+    size_t size;
+    hipStream_t stream;
+};
 struct Pool {
     std::mutex mu;
-    std::multimap<size_t, void*> free_blocks;       // size -> ptr
-    std::unordered_map<void*, size_t> live;         // ptr -> size
+    std::multimap<std::pair<hipStream_t, size_t>, void*> free_blocks;   // (stream, size) -> ptr
+    std::unordered_map<void*, Block> live;
     size_t in_use = 0;
 };
 Pool& pool() {
     static Pool* p = new Pool();   // intentionally leaked: outlives static destructors
     return *p;
 }
+thread_local hipStream_t t_pool_stream = nullptr;
+// blocks of retired streams, usable by all
+hipStream_t const kShared = reinterpret_cast<hipStream_t>(~uintptr_t(0));
 size_t round_size(size_t b) {
     size_t r = 256;
     while (r < b) r <<= 1;
@@ -27,18 +34,24 @@ size_t round_size(size_t b) {
 }
 }  // namespace
 
+PoolStream::PoolStream(hipStream_t s) : prev(t_pool_stream) { t_pool_stream = s; }
+PoolStream::~PoolStream() { t_pool_stream = prev; }
+
 void* pool_alloc(size_t bytes) {
     Pool& P = pool();
-    size_t sz = round_size(bytes);
+    const size_t sz = round_size(bytes);
+    const hipStream_t st = t_pool_stream;
     {
         std::lock_guard<std::mutex> g(P.mu);
-        auto it = P.free_blocks.find(sz);
-        if (it != P.free_blocks.end()) {
-            void* p = it->second;
-            P.free_blocks.erase(it);
-            P.live[p] = sz;
-            P.in_use += sz;
-            return p;
+        for (hipStream_t key : {st, kShared}) {
+            auto it = P.free_blocks.find({key, sz});
+            if (it != P.free_blocks.end()) {
+                void* p = it->second;
+                P.free_blocks.erase(it);
+                P.live[p] = Block{sz, st};
+                P.in_use += sz;
+                return p;
+            }
         }
     }
     void* p = nullptr;
@@ -54,7 +67,7 @@ void* pool_alloc(size_t bytes) {
         }
     }
     std::lock_guard<std::mutex> g(P.mu);
-    P.live[p] = sz;
+    P.live[p] = Block{sz, st};
     P.in_use += sz;
     return p;
 }
@@ -65,9 +78,24 @@ void pool_free(void* p) {
     std::lock_guard<std::mutex> g(P.mu);
     auto it = P.live.find(p);
     if (it == P.live.end()) return;
-    P.free_blocks.emplace(it->second, p);
-    P.in_use -= it->second;
+    P.free_blocks.emplace(std::make_pair(it->second.stream, it->second.size), p);
+    P.in_use -= it->second.size;
     P.live.erase(it);
+}
+
+void pool_retire_stream(hipStream_t s) {
+    Pool& P = pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (auto it = P.free_blocks.begin(); it != P.free_blocks.end();) {
+        if (it->first.first == s) {
+            P.free_blocks.emplace(std::make_pair(kShared, it->first.second), it->second);
+            it = P.free_blocks.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto& kv : P.live)
+        if (kv.second.stream == s) kv.second.stream = kShared;
 }
 
 void pool_release_all() {

@@ -4,6 +4,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 #include "transport.h"
 
@@ -18,7 +23,21 @@ double now_ms() {
 
 Context::~Context() {
     batches.clear();
-    if (own_stream && s) (void)hipStreamDestroy(s);
+    for (hipStream_t w : worker_streams) {
+        (void)hipStreamSynchronize(w);
+        pool_retire_stream(w);
+        (void)hipStreamDestroy(w);
+    }
+    if (own_stream && s) {
+        (void)hipStreamSynchronize(s);
+        pool_retire_stream(s);
+        (void)hipStreamDestroy(s);
+    }
+}
+
+hipStream_t Context::batch_stream(size_t i) const {
+    const size_t L = static_cast<size_t>(std::max(1, opt.streams));
+    return L == 1 ? s : worker_streams[i % L];
 }
 
 void Context::check_ready() const {
@@ -41,11 +60,13 @@ AmgParams Context::amg_params() const {
     p.max_iter = opt.max_inner;
     p.relax_pre = opt.relax_pre;
     p.relax_post = opt.relax_post;
+    p.relax_pre_coarse = std::strcmp(opt.relax_pre_coarse, "=") ? opt.relax_pre_coarse : p.relax_pre;
+    p.relax_post_coarse = std::strcmp(opt.relax_post_coarse, "=") ? opt.relax_post_coarse : p.relax_post;
     if (opt.autotune) p.tune = tune_cache;
     return p;
 }
 
-Csr Context::assemble_fine(Batch& bt, double* t_assemble_ms) {
+Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     const int B = static_cast<int>(bt.dirs.size());
     const int64_t E = mesh.E, N = this->N();
     double t0 = now_ms();
@@ -70,10 +91,10 @@ Csr Context::assemble_fine(Batch& bt, double* t_assemble_ms) {
     return A;
 }
 
-void Context::assemble_batch(Batch& bt, double* t_assemble_ms) {
+void Context::assemble_batch(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     const int B = static_cast<int>(bt.dirs.size());
     const int64_t N = this->N();
-    Csr A = assemble_fine(bt, t_assemble_ms);
+    Csr A = assemble_fine(bt, s, t_assemble_ms);
     std::vector<int64_t> off(B), cn(B, N);
     for (int b = 0; b < B; ++b) off[b] = static_cast<int64_t>(b) * N;
     bt.H.reset(new Hierarchy(amg_params(), s));
@@ -101,7 +122,8 @@ void Context::build_batches(int mode, pair_stats* st) {
     (void)st;
 }
 
-void Context::rhs_batch(const Batch& bt, const SourceSpec& src, const double* phi_in, double* out) {
+void Context::rhs_batch(const Batch& bt, const SourceSpec& src, const double* phi_in, double* out,
+                        hipStream_t s) {
     const int B = static_cast<int>(bt.dirs.size());
     DBuf<int> dirs_d(B);
     h2d(dirs_d.p, bt.dirs.data(), B, s);
@@ -110,74 +132,143 @@ void Context::rhs_batch(const Batch& bt, const SourceSpec& src, const double* ph
     PAIR_HIP(hipStreamSynchronize(s));
 }
 
+// Batches run in turn on one stream, or (options.streams > 1) batch i on
+// worker stream i mod streams, driven by one host thread per stream so that one
+// batch's host synchronisations and small launches overlap the others' kernels.
+// Every batch does the same arithmetic either way, and the scalar flux is
+// accumulated in batch order (each accumulation waits for the previous one).
 bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, double* psi_out,
                     double* phi_out, pair_stats* st, bool warm) {
     check_ready();
     build_batches(mode, st);
     const int64_t N = this->N();
-    bool all_ok = true;
+    const size_t nb = batches.size();
+    const int L = static_cast<int>(std::min<size_t>(static_cast<size_t>(std::max(1, opt.streams)), nb));
+    if (opt.streams > 1)
+        while (static_cast<int>(worker_streams.size()) < opt.streams) {
+            hipStream_t w = nullptr;
+            PAIR_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+            worker_streams.push_back(w);
+        }
     dir_iters.assign(M, 0);
     dir_cf.assign(M, 0.0);
     dir_relres.assign(M, 0.0);
-    bool first_phi = true;
+    const bool use_warm = warm && psi_valid && psi.p;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    size_t turn = 0;          // next batch whose phi contribution may be added
+    bool failed = false;
+    std::exception_ptr first_error;
+    bool all_ok = true;
     double t_asm = 0.0, t_setup = 0.0, t_solve = 0.0, t_other = 0.0, bytes = 0.0;
-    for (auto& bt : batches) {
+    hipEvent_t ready = nullptr, acc = nullptr;
+    PAIR_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    PAIR_HIP(hipEventCreateWithFlags(&acc, hipEventDisableTiming));
+    PAIR_HIP(hipEventRecord(ready, s));   // work queued before the sweep (phi_in, psi)
+
+    auto run_batch = [&](size_t i) {
+        Batch& bt = batches[i];
+        const hipStream_t ss = batch_stream(i);
         const int B = static_cast<int>(bt.dirs.size());
-        double t0 = now_ms();
+        double ta = 0.0, tsu = 0.0;
+        const double t0 = now_ms();
         if (!bt.H) {
-            double ta = 0.0;
-            assemble_batch(bt, &ta);
-            t_asm += ta;
-            t_setup += now_ms() - t0 - ta;
+            assemble_batch(bt, ss, &ta);
+            tsu = now_ms() - t0 - ta;
         }
-        double t1 = now_ms();
-        rhs_batch(bt, src, phi_in, bt.H->b0());
+        const double t1 = now_ms();
+        rhs_batch(bt, src, phi_in, bt.H->b0(), ss);
         double* x0 = bt.H->x0();
-        const bool use_warm = warm && psi_valid && psi.p;
         if (use_warm)
-            for (int b = 0; b < B; ++b) d2d(x0 + b * N, psi.p + static_cast<int64_t>(bt.dirs[b]) * N, N, s);
-        double t2 = now_ms();
-        bool ok = bt.H->solve(opt.use_graph != 0, !use_warm);
-        double t3 = now_ms();
-        bytes += bt.H->last_solve_bytes();
-        all_ok = all_ok && ok;
+            for (int b = 0; b < B; ++b) d2d(x0 + b * N, psi.p + static_cast<int64_t>(bt.dirs[b]) * N, N, ss);
+        const double t2 = now_ms();
+        const bool ok = bt.H->solve(opt.use_graph != 0, !use_warm);
+        const double t3 = now_ms();
         for (int b = 0; b < B; ++b) {
             const int m = bt.dirs[b];
             dir_iters[m] = bt.H->iters_h()[b];
             dir_cf[m] = bt.H->cf_h()[b];
             dir_relres[m] = bt.H->relres_h()[b];
-            if (psi_out) d2d(psi_out + static_cast<int64_t>(m) * N, x0 + b * N, N, s);
+            if (psi_out) d2d(psi_out + static_cast<int64_t>(m) * N, x0 + b * N, N, ss);
         }
         if (phi_out) {
             std::vector<double> wb(B);
             for (int b = 0; b < B; ++b) wb[b] = w_h[bt.dirs[b]];
             DBuf<double> wbd(B);
-            h2d(wbd.p, wb.data(), B, s);
-            phi_accumulate(N, B, wbd.p, x0, phi_out, first_phi, s);
-            first_phi = false;
+            h2d(wbd.p, wb.data(), B, ss);
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return turn == i || failed; });
+            if (failed) return;
+            if (i > 0) PAIR_HIP(hipStreamWaitEvent(ss, acc, 0));
+            phi_accumulate(N, B, wbd.p, x0, phi_out, i == 0, ss);
+            PAIR_HIP(hipEventRecord(acc, ss));
+            turn = i + 1;
+            lk.unlock();
+            cv.notify_all();
         }
-        PAIR_HIP(hipStreamSynchronize(s));
-        double t4 = now_ms();
+        PAIR_HIP(hipStreamSynchronize(ss));
+        const double t4 = now_ms();
+        std::lock_guard<std::mutex> g(mu);
+        all_ok = all_ok && ok;
+        bytes += bt.H->last_solve_bytes();
+        t_asm += ta;
+        t_setup += tsu;
         t_other += (t2 - t1) + (t4 - t3);
         t_solve += t3 - t2;
         if (st) {
-            if (&bt == &batches.front()) {
-                Hierarchy& H = *bt.H;
-                st->levels_max = std::max(st->levels_max, H.member_levels(0));
+            Hierarchy& H = *bt.H;
+            if (i == 0)
                 for (int l = 0; l < std::min(H.num_levels(), PAIR_MAX_LEVELS); ++l) {
-                    Level& L = H.level(l);
-                    st->level_n[l] = L.off[0] >= 0 ? L.cnt[0] : 0;
-                    st->level_nnz[l] = L.off[0] >= 0 ? L.A.nnz : 0;
+                    Level& Lv = H.level(l);
+                    st->level_n[l] = Lv.off[0] >= 0 ? Lv.cnt[0] : 0;
+                    st->level_nnz[l] = Lv.off[0] >= 0 ? Lv.A.nnz : 0;
                 }
-            }
-            for (int b = 0; b < B; ++b) st->levels_max = std::max(st->levels_max, bt.H->member_levels(b));
+            for (int b = 0; b < B; ++b) st->levels_max = std::max(st->levels_max, H.member_levels(b));
         }
         if (!opt.keep_hierarchy) {
             bt.H.reset();
             bt.dinv.reset();
         }
+    };
+    auto worker = [&](int w, int dev) {
+        try {
+            if (dev >= 0) PAIR_HIP(hipSetDevice(dev));
+            const hipStream_t ss = batch_stream(static_cast<size_t>(w));
+            PoolStream ps(ss);
+            PAIR_HIP(hipStreamWaitEvent(ss, ready, 0));
+            for (size_t i = static_cast<size_t>(w); i < nb; i += static_cast<size_t>(L)) {
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    if (failed) return;
+                }
+                run_batch(i);
+            }
+        } catch (...) {
+            std::lock_guard<std::mutex> g(mu);
+            if (!first_error) first_error = std::current_exception();
+            failed = true;
+            cv.notify_all();
+        }
+    };
+    if (L <= 1) {
+        worker(0, -1);
+    } else {
+        int dev = 0;
+        PAIR_HIP(hipGetDevice(&dev));
+        std::vector<std::thread> th;
+        for (int w = 0; w < L; ++w) th.emplace_back(worker, w, dev);
+        for (auto& t : th) t.join();
+        for (int w = 0; w < L; ++w) (void)hipStreamSynchronize(batch_stream(static_cast<size_t>(w)));
     }
-    if (phi_out && first_phi) PAIR_HIP(hipMemsetAsync(phi_out, 0, N * sizeof(double), s));
+    (void)hipEventDestroy(ready);
+    (void)hipEventDestroy(acc);
+    if (first_error) {
+        cached_mode = -1;
+        batches.clear();
+        std::rethrow_exception(first_error);
+    }
+    if (phi_out && nb == 0) PAIR_HIP(hipMemsetAsync(phi_out, 0, N * sizeof(double), s));
     if (!opt.keep_hierarchy) cached_mode = -1;
     else cached_mode = mode;
     if (st) {

@@ -74,8 +74,8 @@ struct Context {
 
     // cached operators
     std::vector<Batch> batches;
-    std::shared_ptr<std::map<int, std::pair<int, int>>> tune_cache =
-        std::make_shared<std::map<int, std::pair<int, int>>>();
+    std::vector<hipStream_t> worker_streams;   // one per concurrent batch (options.streams)
+    std::shared_ptr<TuneCache> tune_cache = std::make_shared<TuneCache>();
     int cached_mode = -1;
 
     // state
@@ -90,15 +90,18 @@ struct Context {
     // building blocks
     void check_ready() const;
     void build_batches(int mode, pair_stats* st);
-    Csr assemble_fine(Batch& b, double* t_assemble_ms);
-    void assemble_batch(Batch& b, double* t_assemble_ms);
-    void rhs_batch(const Batch& b, const SourceSpec& src, const double* phi_in, double* out);
+    Csr assemble_fine(Batch& b, hipStream_t st, double* t_assemble_ms);
+    void assemble_batch(Batch& b, hipStream_t st, double* t_assemble_ms);
+    void rhs_batch(const Batch& b, const SourceSpec& src, const double* phi_in, double* out,
+                   hipStream_t st);
     // one sweep replacement over all directions: psi_out [M][N] may be null
     // unless needed, phi_out [N] accumulated in direction order.
     bool sweep(int mode, const SourceSpec& src, const double* phi_in, double* psi_out,
                double* phi_out, pair_stats* st, bool warm);
     int64_t N() const { return mesh.n_dof(); }
     AmgParams amg_params() const;
+    // hierarchies are built on the stream that later solves with them
+    hipStream_t batch_stream(size_t i) const;
 };
 
 // kernels (assemble.hip)

@@ -45,7 +45,7 @@ class Solver:
         self.opt = options if options is not None else B.default_options(**overrides)
         if options is not None:
             for k, v in overrides.items():
-                if k in ("relax_pre", "relax_post") and isinstance(v, str):
+                if k.startswith("relax_") and isinstance(v, str):
                     v = v.encode()
                 setattr(self.opt, k, v)
         if stream is None:
@@ -76,7 +76,7 @@ class Solver:
     # ---------------------------------------------------------------- problem
     def set_options(self, **kw):
         for k, v in kw.items():
-            if k in ("relax_pre", "relax_post") and isinstance(v, str):
+            if k.startswith("relax_") and isinstance(v, str):
                 v = v.encode()
             setattr(self.opt, k, v)
         self._chk(B.pair_set_options(self.h, ctypes.byref(self.opt)))

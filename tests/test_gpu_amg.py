@@ -26,10 +26,12 @@ def _matrix(cfg, scale, m):
 CASES = [(2, 6, 5), (3, 2, 7), (5, 5, 13), (4, 6, 40)]
 
 
-def _amg(A, coarse_max, seed=0, seg=None, kmax=64, pre="FC", post="FC", max_levels=25):
+def _amg(A, coarse_max, seed=0, seg=None, kmax=64, pre="FC", post="FC", max_levels=25,
+         pre_c="=", post_c="="):
     from paper_1910_11463_amd.solver import Amg
     a = Amg(coarse_max=coarse_max, pmis_seed=seed, tol_inner=1e-10, max_inner=200, kmax=kmax,
-            relax_pre=pre.encode(), relax_post=post.encode(), max_levels=max_levels)
+            relax_pre=pre.encode(), relax_post=post.encode(), max_levels=max_levels,
+            relax_pre_coarse=pre_c.encode(), relax_post_coarse=post_c.encode())
     a.setup(A.indptr, A.indices, A.data, seg)
     return a
 
@@ -69,9 +71,11 @@ def test_hierarchy_matches_reference(cfg, scale, m, kmax):
         assert np.abs(nxt["val"] - R1.A.data).max() <= 1e-12 * np.abs(R1.A.data).max(), l
 
 
-@pytest.mark.parametrize("cfg,scale,m,pre,post", [c + ("FC", "FC") for c in CASES] +
-                         [(2, 6, 5, "FFC", "FFC"), (3, 2, 7, "", "FFC"), (5, 5, 13, "FC", "FFC")])
-def test_vcycles_match_reference(cfg, scale, m, pre, post):
+@pytest.mark.parametrize("cfg,scale,m,pre,post,pre_c,post_c",
+                         [c + ("FC", "FC", "=", "=") for c in CASES] +
+                         [(2, 6, 5, "FFC", "FFC", "=", "="), (3, 2, 7, "", "FFC", "=", "="),
+                          (5, 5, 13, "FC", "FFC", "=", "="), (2, 6, 5, "FFC", "FFC", "F", "FC")])
+def test_vcycles_match_reference(cfg, scale, m, pre, post, pre_c, post_c):
     """Same iteration count as the reference cycle for each relaxation schedule
     (within one: the two full hierarchies may settle a near-tie in a coarse
     level differently, since their Galerkin sums round in different orders)."""
@@ -79,8 +83,10 @@ def test_vcycles_match_reference(cfg, scale, m, pre, post):
     from oracle import air_ref as AR
     A, b = _matrix(cfg, scale, m)
     ref = AR.setup(A, AR.Options(coarse_max=64))
-    xr, itr, hist = AR.solve(ref, b, tol=1e-10, maxit=200, pre=pre, post=post)
-    g = _amg(A, 64, pre=pre, post=post)
+    xr, itr, hist = AR.solve(ref, b, tol=1e-10, maxit=200, pre=pre, post=post,
+                             pre_c=None if pre_c == "=" else pre_c,
+                             post_c=None if post_c == "=" else post_c)
+    g = _amg(A, 64, pre=pre, post=post, pre_c=pre_c, post_c=post_c)
     x, iters, rel, rc = g.solve(b)
     assert rc == B.PAIR_OK
     assert abs(int(iters[0]) - itr) <= 1, (iters[0], itr)
