@@ -9,8 +9,9 @@ Metric: DOF x directions per second.  Inputs (mesh, materials, quadrature) are
 resident on the GPU before the timed region.
 
 Default workload: unit cube, 64^3 Q1 hexes (2.1M DOF per direction), S8 (80
-directions) solved one direction at a time, sigma_t log-uniform in [0.1, 10]
-(seed 2), sigma_s = 0.9 sigma_t, q = 1 in the central box.
+directions) solved one direction at a time, eight directions in flight on
+eight HIP streams, sigma_t log-uniform in [0.1, 10] (seed 2), sigma_s = 0.9
+sigma_t, q = 1 in the central box.
 
 Printed JSON line also carries: the roofline of the dominant kernel (finest-level
 FC-Jacobi half-sweeps: algorithmic bytes / event-timed duration, against the
@@ -29,6 +30,10 @@ if ROOT not in sys.path:
 
 METRIC = "DOF·dirs/s to 1e-8 residual, batched vs per-direction pAIR; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 FETCH_SIZE + WRITE_SIZE of the roofline kernel, scaled by a copy
+# kernel of known size; valid only for the kernel source it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ell_relax_hex64_s8_traffic.txt")
+ROOFLINE_SRC = os.path.join(ROOT, "paper_1910_11463_amd", "csrc", "amg_solve.hip")
 
 
 def log(*a):
@@ -47,6 +52,36 @@ def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device=device)
     s.set_materials(dev(w.mats.sigma_t), dev(w.mats.sigma_s), dev(w.mats.q))
     return s
+
+
+def measured_traffic():
+    """Bytes per launch of the roofline kernel from the committed counter
+    summary, or None if there is none or the kernel source has changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(ROOFLINE_SRC, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def copy_probe(mib):
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters (run under rocprofv3 --pmc with the benchmark)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy probe: 3 copies of %d MiB" % mib)
 
 
 def timed_steps(s, mode, steps, warmup, cold=True, profile=False):
@@ -115,16 +150,18 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="workload number (1-5)")
     ap.add_argument("--scale", type=int, default=None, help="elements per axis (default: full size)")
     ap.add_argument("--mode", choices=["plain", "batched"], default="plain")
-    ap.add_argument("--batch-size", type=int, default=16)
+    ap.add_argument("--batch-size", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--cpu-dirs", type=int, default=16)
     ap.add_argument("--relax-pre", default="FFC")
     ap.add_argument("--relax-post", default="FFC")
-    ap.add_argument("--relax-pre-coarse", default="=")
-    ap.add_argument("--relax-post-coarse", default="=")
-    ap.add_argument("--streams", type=int, default=1,
+    ap.add_argument("--relax-pre-coarse", default="F")
+    ap.add_argument("--relax-post-coarse", default="F")
+    ap.add_argument("--streams", type=int, default=8,
                     help="direction batches set up and solved at once, one HIP stream each")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also copy MIB MiB device-to-device (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -142,6 +179,8 @@ def main():
     B.load()
     device = "cuda:0"
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
     w = wl.make_config(args.config, scale=args.scale)
     N, M = w.mesh.n_dof, w.n_dir
     mode = B.PAIR_PLAIN if args.mode == "plain" else B.PAIR_BATCHED
@@ -162,6 +201,16 @@ def main():
                            "vcycles_total": wst["vcycles_total"], "solve_ms": wst["t_solve_ms"]}
     s.close()
     if not args.no_extra:
+        # the roofline kernel alone on the GPU: one stream, warm solve
+        s1 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
+                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
+                         args.relax_post_coarse, 1)
+        timed_steps(s1, mode, 1, 0, cold=False)
+        timed_steps(s1, mode, 1, 0, cold=False, profile=True)
+        iso = profile_kinds()["relax_fine"]
+        extra["roofline_one_stream"] = {"achieved": iso["gbs"], "frac": iso["gbs"] / HBM_PEAK_GBS,
+                                        "avg_us": iso["avg_us"], "launches": iso["launches"]}
+        s1.close()
         other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
         s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
@@ -177,8 +226,8 @@ def main():
 
     relax = prof["relax_fine"]
     roofline = {"bound": "hbm", "achieved": relax["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": relax["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_relax<8> (finest-level FC-Jacobi half-sweeps)",
+                "frac": relax["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                "kernel": "k_ell_relax<8,4> (finest-level F/C Jacobi half-sweeps)",
                 "launches": relax["launches"], "avg_us": relax["avg_us"],
                 "bytes_per_launch": relax["bytes"] / max(1, relax["launches"])}
     cpu = None
@@ -201,7 +250,7 @@ def main():
                   "cf_mean": st["cf_mean"], "levels": st["levels_max"],
                   "op_complexity": st["op_complexity"], "assemble_ms": st["t_assemble_ms"],
                   "setup_ms": st["t_setup_ms"], "solve_ms": st["t_solve_ms"],
-                  "other_ms": st["t_other_ms"]},
+                  "other_ms": st["t_other_ms"], "level_n": st["level_n"], "level_nnz": st["level_nnz"]},
         "kernels": prof,
         "roofline": roofline,
         "cpu_baseline": cpu,

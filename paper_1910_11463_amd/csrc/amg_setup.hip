@@ -86,7 +86,8 @@ __device__ __forceinline__ bool key_less(int li, uint64_t ri, int64_t ii, int lj
 // every decision depends only on the states, so the split is reproducible).
 // Kernels read the list length from device memory, so several rounds can be
 // queued without host synchronisation.
-__global__ void k_pmis_init_list(int64_t n, const uint16_t* __restrict__ seg,
+__global__ void __launch_bounds__(256)
+k_pmis_init_list(int64_t n, const uint16_t* __restrict__ seg,
                                  const uint8_t* __restrict__ part, const int* __restrict__ lam,
                                  int8_t* __restrict__ state, int32_t* __restrict__ list,
                                  int* __restrict__ cnt) {
@@ -97,10 +98,14 @@ __global__ void k_pmis_init_list(int64_t n, const uint16_t* __restrict__ seg,
         else if (lam[i] == 0) state[i] = ST_F;
         else { state[i] = ST_U; und = true; }
     }
-    const int slot = wave_append(und, cnt);
+    const int slot = block_append<256>(und, cnt);
     if (und) list[slot] = static_cast<int32_t>(i);
 }
 
+// G lanes per undecided row, striding over its entries.  For every strong
+// pair of undecided points the one with the smaller key (lambda, random value,
+// local index) is marked as not a local maximum.
+template <int G>
 __global__ void k_pmis_compare_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
                                     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                     const uint8_t* __restrict__ sflag, const int8_t* __restrict__ state,
@@ -108,13 +113,16 @@ __global__ void k_pmis_compare_list(const int32_t* __restrict__ list, const int*
                                     const int64_t* __restrict__ off, int level, uint64_t seed,
                                     uint8_t* __restrict__ notmax) {
     const int c = *cnt;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < c; k += gridDim.x * blockDim.x) {
+    const int sub = threadIdx.x & (G - 1);
+    const int stride = gridDim.x * (blockDim.x / G);
+    for (int k = (blockIdx.x * blockDim.x + threadIdx.x) / G; k < c; k += stride) {
         const int64_t i = list[k];
         const int64_t base = off[seg[i]];
         const int64_t li = i - base;
         const uint64_t ri = pmis_rand(seed, level, li);
         const int lami = lam[i];
-        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int64_t re = rowptr[i + 1];
+        for (int64_t e = rowptr[i] + sub; e < re; e += G) {
             if (!(sflag[e] & 1)) continue;
             const int64_t j = col[e];
             if (state[j] != ST_U) continue;
@@ -137,39 +145,50 @@ __global__ void k_pmis_select_list(const int32_t* __restrict__ list, const int* 
 
 __global__ void k_zero_one(int* p) { *p = 0; }
 
-__global__ void k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
-                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                 const uint8_t* __restrict__ sflag, int8_t* __restrict__ state,
-                                 int32_t* __restrict__ next, int* __restrict__ next_cnt) {
+// Undecided rows with a strong C neighbour become F; the others form the next
+// round's list.  G lanes per row, NT-thread blocks; the loop runs the same
+// number of times on every thread of a block, so all reach block_append.
+template <int G, int NT>
+__global__ void __launch_bounds__(NT)
+k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
+                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const uint8_t* __restrict__ sflag, int8_t* __restrict__ state,
+                 int32_t* __restrict__ next, int* __restrict__ next_cnt) {
+    constexpr int RPB = NT / G;   // rows per block and iteration
     const int c = *cnt;
-    const int stride = gridDim.x * blockDim.x;
-    // uniform trip count per wave so every lane reaches wave_append
-    for (int k0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); k0 < c; k0 += stride) {
-        const int k = k0 + (threadIdx.x & 63);
-        bool keep = false;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const int stride = gridDim.x * RPB;
+    for (int kb = blockIdx.x * RPB; kb < c; kb += stride) {
+        const int k = kb + static_cast<int>(threadIdx.x) / G;
         int32_t i = -1;
+        bool live = false;
         if (k < c) {
             i = list[k];
-            if (state[i] == ST_U) {
-                bool f = false;
-                for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
-                    if ((sflag[e] & 1) && state[col[e]] == ST_C) { f = true; break; }
-                if (f) state[i] = ST_F;
-                else keep = true;
-            }
+            live = state[i] == ST_U;
         }
-        const int slot = wave_append(keep, next_cnt);
+        bool f = false;
+        if (live) {
+            const int64_t re = rowptr[i + 1];
+            for (int64_t e = rowptr[i] + sub; e < re; e += G)
+                if ((sflag[e] & 1) && state[col[e]] == ST_C) { f = true; break; }
+        }
+        const uint64_t fm = __ballot(f);
+        const bool anyf = ((fm >> gbase) & ((G == 64) ? ~0ull : ((1ull << (G & 63)) - 1ull))) != 0;
+        const bool lead = live && sub == 0;
+        if (lead && anyf) state[i] = ST_F;
+        const bool keep = lead && !anyf;
+        const int slot = block_append<NT>(keep, next_cnt);
         if (keep) next[slot] = i;
     }
 }
 
-// Rows (or coarse rows) sorted into three size classes in one pass:
-// mode 0: row length of A; mode 1: local lAIR system size (R row length - 1);
-// mode 2: product upper bound ub[i].
 // Split rows into up to four classes by a per-row size v (mode 0: row length of
 // a, mode 1: row length minus one, mode 2: ub[i]); class k holds the rows with
 // b_k < v <= b_{k+1} (b_0 = -inf, b_3 = +inf when only three classes are used).
-__global__ void k_class3(int64_t n, int mode, const int64_t* __restrict__ a,
+__global__ void __launch_bounds__(256)
+k_class3(int64_t n, int mode, const int64_t* __restrict__ a,
                          const int64_t* __restrict__ ub, int64_t b1, int64_t b2,
                          int32_t* __restrict__ l0, int32_t* __restrict__ l1,
                          int32_t* __restrict__ l2, int* __restrict__ cnt,
@@ -180,10 +199,10 @@ __global__ void k_class3(int64_t n, int mode, const int64_t* __restrict__ a,
         const int64_t v = mode == 2 ? ub[i] : (a[i + 1] - a[i] - (mode == 1 ? 1 : 0));
         cls = v <= b1 ? 0 : (v <= b2 ? 1 : (v <= b3 ? 2 : 3));
     }
-    const int s0 = wave_append(cls == 0, &cnt[0]);
-    const int s1 = wave_append(cls == 1, &cnt[1]);
-    const int s2 = wave_append(cls == 2, &cnt[2]);
-    const int s3 = wave_append(cls == 3, &cnt[3]);
+    const int s0 = block_append<256>(cls == 0, &cnt[0]);
+    const int s1 = block_append<256>(cls == 1, &cnt[1]);
+    const int s2 = block_append<256>(cls == 2, &cnt[2]);
+    const int s3 = block_append<256>(cls == 3, &cnt[3]);
     if (cls == 0) l0[s0] = static_cast<int32_t>(i);
     if (cls == 1) l1[s1] = static_cast<int32_t>(i);
     if (cls == 2) l2[s2] = static_cast<int32_t>(i);
@@ -293,7 +312,7 @@ __global__ void k_r_count(int64_t nc, const int32_t* __restrict__ c2f,
 
 constexpr int KCAP = 64;      // largest local system (one wave: lane = row)
 
-// lAIR rows, G lanes per coarse row (G = 16, 32 or 64 >= the row's local system
+// lAIR rows, G lanes per coarse row (G = 8, 16, 32 or 64 >= the row's local system
 // size K), 64 / G rows per wave.  Local system A(R_i,R_i)^T z = -A(i,R_i)^T in
 // LDS, Gaussian elimination with partial pivoting (lane r owns row r), back
 // substitution with group sums.  Loops run to the largest K of the wave so every
@@ -312,6 +331,8 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
     __shared__ double z[RPW][G];
     __shared__ int cols[RPW][G];
     __shared__ int kw[RPW];
+    __shared__ int64_t rbeg[RPW][G];
+    __shared__ int rpref[RPW][G + 1];
     const int lane = threadIdx.x;
     const int g = lane / G, sub = lane % G;
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
@@ -361,21 +382,42 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         for (int q = 0; q < RPW; ++q) Kw = max(Kw, kw[q]);
         for (int r = 0; r < G; ++r) Mloc[g][r * LD + sub] = 0.0;
         rhs[g][sub] = 0.0;
+        // rows cols[c] of A (lane c): start, and the prefix of their lengths
+        int64_t myb = 0;
+        int inc = 0;
+        if (sub < K) {
+            const int64_t jc = cols[g][sub];
+            myb = rowptr[jc];
+            inc = static_cast<int>(rowptr[jc + 1] - myb);
+        }
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            const int u = __shfl_up(inc, d, 64);
+            if (sub >= d) inc += u;
+        }
+        rbeg[g][sub] = myb;
+        rpref[g][sub + 1] = inc;
+        if (sub == 0) rpref[g][0] = 0;
+        const int tot = __shfl(inc, (lane & ~(G - 1)) + G - 1, 64);
         __syncthreads();
-        // Mloc[r][c] = A(cols[c], cols[r]); rhs[r] = -A(i, cols[r])
-        for (int c = 0; c < Kw; ++c) {
-            const bool on = c < K;
-            const int64_t jc = on ? cols[g][c] : 0;
-            const int64_t js = on ? rowptr[jc] : 0, je = on ? rowptr[jc + 1] : 0;
-            for (int64_t e = js + sub; e < je; e += G) {
-                int32_t cc = col[e];
-                int lo = 0, hi = K - 1;
-                while (lo <= hi) {
-                    int mid = (lo + hi) >> 1;
-                    int v = cols[g][mid];
-                    if (v == cc) { Mloc[g][mid * LD + c] = val[e]; break; }
-                    if (v < cc) lo = mid + 1; else hi = mid - 1;
-                }
+        // Mloc[r][c] = A(cols[c], cols[r]); rhs[r] = -A(i, cols[r]).  The
+        // entries of all K rows are spread over the lanes as one flat list, so
+        // every lane's loads are independent of the others'.
+        for (int q = sub; q < tot; q += G) {
+            int c = 0, hi = K - 1;   // last c with rpref[c] <= q
+            while (c < hi) {
+                const int mid = (c + hi + 1) >> 1;
+                if (rpref[g][mid] <= q) c = mid; else hi = mid - 1;
+            }
+            const int64_t e = rbeg[g][c] + (q - rpref[g][c]);
+            const int32_t cc = col[e];
+            int lo = 0;
+            hi = K - 1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int v = cols[g][mid];
+                if (v == cc) { Mloc[g][mid * LD + c] = val[e]; break; }
+                if (v < cc) lo = mid + 1; else hi = mid - 1;
             }
         }
         for (int64_t e = rs + sub; e < re; e += G) {
@@ -738,6 +780,107 @@ k_rap_lds(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
     }
 }
 
+// Numeric R (A P) for rows of at most PCAP products (hash table of 2 PCAP
+// slots).  The products' columns and values are staged in LDS, the distinct
+// columns found with the hash set and ranked (counting for short lists, bitonic
+// sort otherwise); then one thread per distinct column walks the R entries in
+// order and binary-searches the column in each (sorted) staged row of A P,
+// accumulating with fma in R's entry order: the same sum, rounded the same way,
+// as adding the rows of A P one R entry after the other, with no barrier per
+// R entry.
+template <int NT, int PCAP>
+__global__ void __launch_bounds__(NT)
+k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ r_rowptr,
+          const int32_t* __restrict__ r_col, const double* __restrict__ r_val,
+          const int64_t* __restrict__ rowptr, const int* __restrict__ ap_len,
+          const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
+          const int64_t* __restrict__ c_rowptr, int32_t* __restrict__ c_col, double* __restrict__ c_val) {
+    constexpr int TBL = 2 * PCAP;
+    constexpr uint32_t mask = TBL - 1;
+    __shared__ uint32_t tkeys[TBL];
+    __shared__ uint32_t ulist[PCAP];
+    __shared__ uint32_t ucol[PCAP];
+    __shared__ int32_t pc[PCAP];
+    __shared__ double pv[PCAP];
+    __shared__ int s_pref[RMAX + 1];
+    __shared__ int64_t s_base[RMAX];
+    __shared__ double s_rv[RMAX];
+    __shared__ int s_cnt;
+    const int tid = threadIdx.x;
+    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int64_t I = list[r];
+        const int64_t rs = r_rowptr[I];
+        const int rl = static_cast<int>(r_rowptr[I + 1] - rs);
+        for (int t = tid; t < rl; t += NT) {
+            const int64_t k = r_col[rs + t];
+            s_base[t] = rowptr[k];
+            s_pref[t + 1] = ap_len[k];
+            s_rv[t] = r_val[rs + t];
+        }
+        for (int h = tid; h < TBL; h += NT) tkeys[h] = HASH_EMPTY;
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        if (tid == 0) {
+            s_pref[0] = 0;
+            for (int t = 0; t < rl; ++t) s_pref[t + 1] += s_pref[t];
+        }
+        __syncthreads();
+        const int total = s_pref[rl];
+        for (int q = tid; q < total; q += NT) {
+            int lo = 0, hi = rl - 1;   // last t with s_pref[t] <= q
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            const int64_t e = s_base[lo] + (q - s_pref[lo]);
+            const uint32_t c = static_cast<uint32_t>(ap_col[e]);
+            pc[q] = static_cast<int32_t>(c);
+            pv[q] = ap_val[e];
+            uint32_t h = hash_slot(c, mask);
+            while (true) {
+                const uint32_t old = atomicCAS(&tkeys[h], HASH_EMPTY, c);
+                if (old == HASH_EMPTY) { ulist[atomicAdd(&s_cnt, 1)] = c; break; }
+                if (old == c) break;
+                h = (h + 1) & mask;
+            }
+        }
+        __syncthreads();
+        const int nu = s_cnt;
+        if (nu <= 128) {
+            for (int u = tid; u < nu; u += NT) {
+                const uint32_t c = ulist[u];
+                int rank = 0;
+                for (int j = 0; j < nu; ++j) rank += ulist[j] < c ? 1 : 0;
+                ucol[rank] = c;
+            }
+        } else {
+            int cap = 1;
+            while (cap < nu) cap <<= 1;
+            for (int u = tid; u < cap; u += NT) ucol[u] = u < nu ? ulist[u] : HASH_EMPTY;
+            __syncthreads();
+            bitonic_sort_u32<NT>(ucol, cap);
+        }
+        __syncthreads();
+        const int64_t ob = c_rowptr[I];
+        for (int u = tid; u < nu; u += NT) {
+            const int32_t c = static_cast<int32_t>(ucol[u]);
+            double acc = 0.0;
+            for (int t = 0; t < rl; ++t) {
+                int lo = s_pref[t], hi = s_pref[t + 1] - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int32_t cm = pc[mid];
+                    if (cm == c) { acc = fma(s_rv[t], pv[mid], acc); break; }
+                    if (cm < c) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            c_col[ob + u] = c;
+            c_val[ob + u] = acc;
+        }
+        __syncthreads();
+    }
+}
+
 // Rows with more products than fit in LDS: same algorithm on global scratch.
 template <bool NUMERIC>
 __global__ void __launch_bounds__(256)
@@ -1093,18 +1236,19 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                            d_part.p, lam.p, state.p, plist[0].p, pcnt.p);
         PAIR_LAUNCH_CHECK();
         {
-            const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(n, 256), 4096));
+            const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(n * 8, 256), 8192));
+            const unsigned pgm = static_cast<unsigned>(std::min<int64_t>(grid_for(n * 8, 1024), 2048));
             int cur = 0;
             for (int round = 0;; ++round) {
                 PAIR_CHECK(round < 100000, "PMIS did not terminate");
                 const int nxt = cur ^ 1;
-                hipLaunchKernelGGL(k_pmis_compare_list, dim3(pg), dim3(256), 0, s_, plist[cur].p,
+                hipLaunchKernelGGL(k_pmis_compare_list<8>, dim3(pg), dim3(256), 0, s_, plist[cur].p,
                                    pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p,
                                    L.seg.p, d_off.p, l, prm_.seed, notmax.p);
                 hipLaunchKernelGGL(k_pmis_select_list, dim3(pg), dim3(256), 0, s_, plist[cur].p,
                                    pcnt.p + cur, state.p, notmax.p);
                 hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(1), 0, s_, pcnt.p + nxt);
-                hipLaunchKernelGGL(k_pmis_mark_list, dim3(pg), dim3(256), 0, s_, plist[cur].p,
+                hipLaunchKernelGGL((k_pmis_mark_list<8, 1024>), dim3(pgm), dim3(1024), 0, s_, plist[cur].p,
                                    pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p,
                                    plist[nxt].p, pcnt.p + nxt);
                 PAIR_LAUNCH_CHECK();
@@ -1192,36 +1336,31 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
         {
-            DBuf<int32_t> rl0(total_c), rl1(total_c), rl2(total_c);
-            DBuf<int> rcnt3(3), rsing(1);
+            // local systems by size K: <= 8, <= 16, <= 32, <= 64 (64 / G rows per wave)
+            DBuf<int32_t> rl[4];
+            for (auto& x : rl) x.alloc(total_c);
+            DBuf<int> rcnt4(4), rsing(1);
             PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
-            PAIR_HIP(hipMemsetAsync(rcnt3.p, 0, 3 * sizeof(int), s_));
+            PAIR_HIP(hipMemsetAsync(rcnt4.p, 0, 4 * sizeof(int), s_));
             hipLaunchKernelGGL(k_class3, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c, 1,
-                               L.R.rowptr.p, nullptr, int64_t(16), int64_t(32), rl0.p, rl1.p, rl2.p,
-                               rcnt3.p);
+                               L.R.rowptr.p, nullptr, int64_t(8), int64_t(16), rl[0].p, rl[1].p, rl[2].p,
+                               rcnt4.p, int64_t(32), rl[3].p);
             PAIR_LAUNCH_CHECK();
-            int nrc[3];
-            d2h(nrc, rcnt3.p, 3, s_);
+            int nrc[4];
+            d2h(nrc, rcnt4.p, 4, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            const int32_t* rlists[3] = {rl0.p, rl1.p, rl2.p};
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < 4; ++c) {
                 const int nr = nrc[c];
                 if (nr == 0) continue;
-                const int32_t* rlist = rlists[c];
-                const int rpw = c == 0 ? 4 : (c == 1 ? 2 : 1);
+                const int rpw = 8 >> c;
                 const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
-                if (c == 0)
-                    hipLaunchKernelGGL(k_r_build<16>, dim3(g), dim3(64), 0, s_, nr, rlist, c2f.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
-                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
-                else if (c == 1)
-                    hipLaunchKernelGGL(k_r_build<32>, dim3(g), dim3(64), 0, s_, nr, rlist, c2f.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
-                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
-                else
-                    hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, nr, rlist, c2f.p,
-                                       L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
-                                       L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p);
+#define PAIR_RB_ARGS nr, rl[c].p, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, \
+                     L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p
+                if (c == 0) hipLaunchKernelGGL(k_r_build<8>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 1) hipLaunchKernelGGL(k_r_build<16>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 2) hipLaunchKernelGGL(k_r_build<32>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+#undef PAIR_RB_ARGS
                 PAIR_LAUNCH_CHECK();
             }
             PAIR_HIP(hipMemcpyAsync(d_counter.p, rsing.p, sizeof(int), hipMemcpyDeviceToDevice, s_));
@@ -1265,17 +1404,17 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         hipLaunchKernelGGL(k_rap_ub, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
                            L.R.rowptr.p, L.R.col.p, ap_len.p, ub.p);
         PAIR_LAUNCH_CHECK();
-        DBuf<int32_t> lists[3];
-        for (int c = 0; c < 3; ++c) lists[c].alloc(total_c);
-        int lcount[3] = {0, 0, 0};
+        DBuf<int32_t> lists[4];
+        for (int c = 0; c < 4; ++c) lists[c].alloc(total_c);
+        int lcount[4] = {0, 0, 0, 0};
         {
-            DBuf<int> lc(3);
-            PAIR_HIP(hipMemsetAsync(lc.p, 0, 3 * sizeof(int), s_));
+            DBuf<int> lc(4);
+            PAIR_HIP(hipMemsetAsync(lc.p, 0, 4 * sizeof(int), s_));
             hipLaunchKernelGGL(k_class3, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c, 2,
-                               nullptr, ub.p, int64_t(256), int64_t(2048), lists[0].p, lists[1].p,
-                               lists[2].p, lc.p);
+                               nullptr, ub.p, int64_t(256), int64_t(1024), lists[0].p, lists[1].p,
+                               lists[2].p, lc.p, int64_t(2048), lists[3].p);
             PAIR_LAUNCH_CHECK();
-            d2h(lcount, lc.p, 3, s_);
+            d2h(lcount, lc.p, 4, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
         }
         // hash-table scratch for the global class: 2 * pow2(products) slots per row
@@ -1284,67 +1423,66 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         DBuf<uint32_t> gkeys, gcols;
         DBuf<int32_t> gpos;
         DBuf<double> gvals;
-        if (lcount[2] > 0) {
-            std::vector<int32_t> rows(lcount[2]);
-            d2h(rows.data(), lists[2].p, lcount[2], s_);
+        if (lcount[3] > 0) {
+            std::vector<int32_t> rows(lcount[3]);
+            d2h(rows.data(), lists[3].p, lcount[3], s_);
             std::vector<int64_t> ubh(total_c);
             d2h(ubh.data(), ub.p, total_c, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            gscr_off_h.resize(lcount[2] + 1, 0);
-            for (int k = 0; k < lcount[2]; ++k) {
+            gscr_off_h.resize(lcount[3] + 1, 0);
+            for (int k = 0; k < lcount[3]; ++k) {
                 int64_t cap = 1;
                 while (cap < ubh[rows[k]]) cap <<= 1;
                 gscr_off_h[k + 1] = gscr_off_h[k] + 2 * cap;
             }
-            gscr_off.alloc(lcount[2] + 1);
-            h2d(gscr_off.p, gscr_off_h.data(), lcount[2] + 1, s_);
+            gscr_off.alloc(lcount[3] + 1);
+            h2d(gscr_off.p, gscr_off_h.data(), lcount[3] + 1, s_);
             gkeys.alloc(gscr_off_h.back());
             gpos.alloc(gscr_off_h.back());
             gcols.alloc(gscr_off_h.back() / 2);
             gvals.alloc(gscr_off_h.back() / 2);
         }
+        // classes by products: <= 256, <= 1024, <= 2048 in LDS, the rest global
         auto run_rap = [&](bool numeric, Csr* C) {
             int64_t* cnt_out = ccnt.p;
             const int64_t* crp = numeric ? C->rowptr.p : nullptr;
             int32_t* ccol = numeric ? C->col.p : nullptr;
             double* cval = numeric ? C->val.p : nullptr;
-            if (lcount[0] > 0) {
-                unsigned g = static_cast<unsigned>(std::min(lcount[0], 1 << 20));
-                if (numeric)
-                    hipLaunchKernelGGL((k_rap_lds<64, 512, true>), dim3(g), dim3(64), 0, s_,
-                                       lcount[0], lists[0].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
-                                       cval);
-                else
-                    hipLaunchKernelGGL((k_rap_lds<64, 512, false>), dim3(g), dim3(64), 0, s_,
-                                       lcount[0], lists[0].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
-                                       cval);
-                PAIR_LAUNCH_CHECK();
+            auto grid = [](int n) { return dim3(static_cast<unsigned>(std::min(n, 1 << 20))); };
+#define PAIR_RAP_ARGS(c) lcount[c], lists[c].p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p, \
+                         ap_len.p, ap_col.p, ap_val.p
+            if (numeric) {
+                if (lcount[0] > 0)
+                    hipLaunchKernelGGL((k_rap_num<64, 256>), grid(lcount[0]), dim3(64), 0, s_,
+                                       PAIR_RAP_ARGS(0), crp, ccol, cval);
+                if (lcount[1] > 0)
+                    hipLaunchKernelGGL((k_rap_num<128, 1024>), grid(lcount[1]), dim3(128), 0, s_,
+                                       PAIR_RAP_ARGS(1), crp, ccol, cval);
+                if (lcount[2] > 0)
+                    hipLaunchKernelGGL((k_rap_num<256, 2048>), grid(lcount[2]), dim3(256), 0, s_,
+                                       PAIR_RAP_ARGS(2), crp, ccol, cval);
+            } else {
+                if (lcount[0] > 0)
+                    hipLaunchKernelGGL((k_rap_lds<64, 512, false>), grid(lcount[0]), dim3(64), 0, s_,
+                                       PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval);
+                if (lcount[1] > 0)
+                    hipLaunchKernelGGL((k_rap_lds<128, 2048, false>), grid(lcount[1]), dim3(128), 0, s_,
+                                       PAIR_RAP_ARGS(1), cnt_out, crp, ccol, cval);
+                if (lcount[2] > 0)
+                    hipLaunchKernelGGL((k_rap_lds<256, 4096, false>), grid(lcount[2]), dim3(256), 0, s_,
+                                       PAIR_RAP_ARGS(2), cnt_out, crp, ccol, cval);
             }
-            if (lcount[1] > 0) {
-                unsigned g = static_cast<unsigned>(std::min(lcount[1], 1 << 20));
+#undef PAIR_RAP_ARGS
+            PAIR_LAUNCH_CHECK();
+            if (lcount[3] > 0) {
                 if (numeric)
-                    hipLaunchKernelGGL((k_rap_lds<256, 4096, true>), dim3(g), dim3(256), 0, s_,
-                                       lcount[1], lists[1].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
-                                       cval);
-                else
-                    hipLaunchKernelGGL((k_rap_lds<256, 4096, false>), dim3(g), dim3(256), 0, s_,
-                                       lcount[1], lists[1].p, L.R.rowptr.p, L.R.col.p, L.R.val.p,
-                                       L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol,
-                                       cval);
-                PAIR_LAUNCH_CHECK();
-            }
-            if (lcount[2] > 0) {
-                if (numeric)
-                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[2]), dim3(256), 0, s_,
-                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[3]), dim3(256), 0, s_,
+                                       lcount[3], lists[3].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
                                        ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 else
-                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[2]), dim3(256), 0, s_,
-                                       lcount[2], lists[2].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[3]), dim3(256), 0, s_,
+                                       lcount[3], lists[3].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
                                        ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 PAIR_LAUNCH_CHECK();

@@ -52,18 +52,30 @@ __device__ __forceinline__ double group_max(double v) {
     return v;
 }
 
-// Append to a global list with one atomic per wave: every lane of the wave must
-// call this (pred false for lanes with nothing to add).  Returns the slot of the
-// calling lane, or -1.  The order of entries across waves is not fixed.
-__device__ __forceinline__ int wave_append(bool pred, int* counter) {
+// Append to a global list with one atomic per block: every thread of the
+// one-dimensional NT-thread block must call this.  Returns the slot of the
+// calling thread, or -1.  The order of entries across blocks is not fixed.
+template <int NT>
+__device__ __forceinline__ int block_append(bool pred, int* counter) {
+    __shared__ int s_cnt[NT / 64];
+    __shared__ int s_base;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t m = __ballot(pred);
-    if (m == 0) return -1;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, leader, 64);
-    return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+    if (lane == 0) s_cnt[wid] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            const int t = s_cnt[w];
+            s_cnt[w] = tot;
+            tot += t;
+        }
+        s_base = tot > 0 ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    const int slot = s_base + s_cnt[wid] + __popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();   // the next call may overwrite s_cnt / s_base
+    return pred ? slot : -1;
 }
 
 // SplitMix64 (Steele, Lea & Flood 2014): add the golden-ratio increment, then

@@ -23,6 +23,7 @@ double now_ms() {
 
 Context::~Context() {
     batches.clear();
+    if (acc_stream) worker_streams.push_back(acc_stream);
     for (hipStream_t w : worker_streams) {
         (void)hipStreamSynchronize(w);
         pool_retire_stream(w);
@@ -136,7 +137,9 @@ void Context::rhs_batch(const Batch& bt, const SourceSpec& src, const double* ph
 // worker stream i mod streams, driven by one host thread per stream so that one
 // batch's host synchronisations and small launches overlap the others' kernels.
 // Every batch does the same arithmetic either way, and the scalar flux is
-// accumulated in batch order (each accumulation waits for the previous one).
+// accumulated in batch order: the sums are queued in that order on one stream
+// that is never captured into a graph (a worker stream may be capturing its
+// cycle graph while another worker hands over its batch).
 bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, double* psi_out,
                     double* phi_out, pair_stats* st, bool warm) {
     check_ready();
@@ -144,12 +147,14 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
     const int64_t N = this->N();
     const size_t nb = batches.size();
     const int L = static_cast<int>(std::min<size_t>(static_cast<size_t>(std::max(1, opt.streams)), nb));
-    if (opt.streams > 1)
+    if (opt.streams > 1) {
         while (static_cast<int>(worker_streams.size()) < opt.streams) {
             hipStream_t w = nullptr;
             PAIR_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
             worker_streams.push_back(w);
         }
+        if (!acc_stream) PAIR_HIP(hipStreamCreateWithFlags(&acc_stream, hipStreamNonBlocking));
+    }
     dir_iters.assign(M, 0);
     dir_cf.assign(M, 0.0);
     dir_relres.assign(M, 0.0);
@@ -162,12 +167,15 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
     std::exception_ptr first_error;
     bool all_ok = true;
     double t_asm = 0.0, t_setup = 0.0, t_solve = 0.0, t_other = 0.0, bytes = 0.0;
-    hipEvent_t ready = nullptr, acc = nullptr;
+    hipEvent_t ready = nullptr;
+    std::vector<hipEvent_t> ev(2 * static_cast<size_t>(std::max(L, 1)), nullptr);   // per worker
     PAIR_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-    PAIR_HIP(hipEventCreateWithFlags(&acc, hipEventDisableTiming));
+    for (auto& e : ev) PAIR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     PAIR_HIP(hipEventRecord(ready, s));   // work queued before the sweep (phi_in, psi)
+    const hipStream_t acc_s = L > 1 ? acc_stream : nullptr;
+    if (acc_s) PAIR_HIP(hipStreamWaitEvent(acc_s, ready, 0));
 
-    auto run_batch = [&](size_t i) {
+    auto run_batch = [&](size_t i, int w) {
         Batch& bt = batches[i];
         const hipStream_t ss = batch_stream(i);
         const int B = static_cast<int>(bt.dirs.size());
@@ -193,16 +201,22 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
             if (psi_out) d2d(psi_out + static_cast<int64_t>(m) * N, x0 + b * N, N, ss);
         }
         if (phi_out) {
-            std::vector<double> wb(B);
-            for (int b = 0; b < B; ++b) wb[b] = w_h[bt.dirs[b]];
-            DBuf<double> wbd(B);
-            h2d(wbd.p, wb.data(), B, ss);
+            // the members of a batch are consecutive directions
+            PAIR_CHECK(bt.dirs.back() - bt.dirs.front() == B - 1, "batch directions not consecutive");
+            const double* wbd = w_d.p + bt.dirs.front();
             std::unique_lock<std::mutex> lk(mu);
             cv.wait(lk, [&] { return turn == i || failed; });
             if (failed) return;
-            if (i > 0) PAIR_HIP(hipStreamWaitEvent(ss, acc, 0));
-            phi_accumulate(N, B, wbd.p, x0, phi_out, i == 0, ss);
-            PAIR_HIP(hipEventRecord(acc, ss));
+            if (acc_s) {
+                hipEvent_t x_ready = ev[2 * w], summed = ev[2 * w + 1];
+                PAIR_HIP(hipEventRecord(x_ready, ss));
+                PAIR_HIP(hipStreamWaitEvent(acc_s, x_ready, 0));
+                phi_accumulate(N, B, wbd, x0, phi_out, i == 0, acc_s);
+                PAIR_HIP(hipEventRecord(summed, acc_s));
+                PAIR_HIP(hipStreamWaitEvent(ss, summed, 0));   // x0 is read until then
+            } else {
+                phi_accumulate(N, B, wbd, x0, phi_out, i == 0, ss);
+            }
             turn = i + 1;
             lk.unlock();
             cv.notify_all();
@@ -242,7 +256,7 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
                     std::lock_guard<std::mutex> g(mu);
                     if (failed) return;
                 }
-                run_batch(i);
+                run_batch(i, w);
             }
         } catch (...) {
             std::lock_guard<std::mutex> g(mu);
@@ -260,9 +274,10 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
         for (int w = 0; w < L; ++w) th.emplace_back(worker, w, dev);
         for (auto& t : th) t.join();
         for (int w = 0; w < L; ++w) (void)hipStreamSynchronize(batch_stream(static_cast<size_t>(w)));
+        (void)hipStreamSynchronize(acc_s);
     }
     (void)hipEventDestroy(ready);
-    (void)hipEventDestroy(acc);
+    for (auto e : ev) (void)hipEventDestroy(e);
     if (first_error) {
         cached_mode = -1;
         batches.clear();

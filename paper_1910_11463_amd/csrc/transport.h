@@ -75,6 +75,7 @@ struct Context {
     // cached operators
     std::vector<Batch> batches;
     std::vector<hipStream_t> worker_streams;   // one per concurrent batch (options.streams)
+    hipStream_t acc_stream = nullptr;          // scalar-flux sums of concurrent batches
     std::shared_ptr<TuneCache> tune_cache = std::make_shared<TuneCache>();
     int cached_mode = -1;
 
