@@ -63,11 +63,22 @@ struct Csr {
 // global element index nbr[s*nel+g] (-1: empty) and its nf face nodes packed
 // 3 bits each in nodes[s*nel+g]; values are stored slot-major
 // val[(s*nf + j) * nrows + row] so that consecutive rows are contiguous.
+//
+// Once the finest level's C/F split is known the values are regrouped by class
+// (Hierarchy::set_fine_ell): F rows (every row that is not a C point) first,
+// val[(s*nf + j)*nF + posF], then C rows, val[3*nf*nF + (s*nf + j)*nC + posC],
+// so that a half-sweep over one class reads only that class's cache lines.
+// cmask[w] has bit i set if row 64w+i is a C point and fbase[w] counts the F
+// rows before row 64w, which gives a row's position within its class.
 struct FineEll {
     int k = 0, nf = 0;
     int64_t nel = 0, nrows = 0;
     DBuf<int32_t> nbr, nodes;
     DBuf<double> val;
+    bool split = false;
+    int64_t nF = 0;
+    DBuf<uint64_t> cmask;
+    DBuf<int64_t> fbase;
 };
 
 struct Level {
@@ -133,7 +144,8 @@ public:
     int64_t nnz_level(int l) const { return levels_[l].A.nnz; }
     // Use an element-block copy of the finest level for its relaxation,
     // residual and convergence test (its diagonal must be the identity).
-    void set_fine_ell(std::shared_ptr<FineEll> e) { ell_ = std::move(e); drop_graph(); }
+    // Regroups its values by the finest level's C/F split (see FineEll).
+    void set_fine_ell(std::shared_ptr<FineEll> e);
     // New parameters (tolerance, iteration limit, relaxation schedule); the
     // captured cycle graph bakes them in, so it is dropped.
     void set_params(const AmgParams& p);

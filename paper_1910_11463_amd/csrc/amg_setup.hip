@@ -19,6 +19,7 @@
 //      columns in an LDS hash set and adds the rows of A P in the order of the
 //      row of R, so the result is bitwise reproducible.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 
@@ -184,29 +185,51 @@ k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
     }
 }
 
-// Split rows into up to four classes by a per-row size v (mode 0: row length of
-// a, mode 1: row length minus one, mode 2: ub[i]); class k holds the rows with
-// b_k < v <= b_{k+1} (b_0 = -inf, b_3 = +inf when only three classes are used).
+// Split rows into classes by a per-row size v (mode 0: row length of a, mode
+// 1: row length minus one, mode 2: ub[i]): class k < NC - 1 holds the rows
+// with bound[k-1] < v <= bound[k], class NC - 1 the rest.
+constexpr int kMaxClasses = 5;
+struct RowClasses {
+    int64_t bound[kMaxClasses - 1];
+    int32_t* list[kMaxClasses];
+};
+
+template <int NC>
 __global__ void __launch_bounds__(256)
-k_class3(int64_t n, int mode, const int64_t* __restrict__ a,
-                         const int64_t* __restrict__ ub, int64_t b1, int64_t b2,
-                         int32_t* __restrict__ l0, int32_t* __restrict__ l1,
-                         int32_t* __restrict__ l2, int* __restrict__ cnt,
-                         int64_t b3 = INT64_MAX, int32_t* __restrict__ l3 = nullptr) {
+k_classify(int64_t n, int mode, const int64_t* __restrict__ a, const int64_t* __restrict__ ub,
+           RowClasses rc, int* __restrict__ cnt) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     int cls = -1;
     if (i < n) {
         const int64_t v = mode == 2 ? ub[i] : (a[i + 1] - a[i] - (mode == 1 ? 1 : 0));
-        cls = v <= b1 ? 0 : (v <= b2 ? 1 : (v <= b3 ? 2 : 3));
+        cls = NC - 1;
+        for (int k = NC - 2; k >= 0; --k)
+            if (v <= rc.bound[k]) cls = k;
     }
-    const int s0 = block_append<256>(cls == 0, &cnt[0]);
-    const int s1 = block_append<256>(cls == 1, &cnt[1]);
-    const int s2 = block_append<256>(cls == 2, &cnt[2]);
-    const int s3 = block_append<256>(cls == 3, &cnt[3]);
-    if (cls == 0) l0[s0] = static_cast<int32_t>(i);
-    if (cls == 1) l1[s1] = static_cast<int32_t>(i);
-    if (cls == 2) l2[s2] = static_cast<int32_t>(i);
-    if (cls == 3) l3[s3] = static_cast<int32_t>(i);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int slot = block_append<256>(cls == k, &cnt[k]);
+        if (cls == k) rc.list[k][slot] = static_cast<int32_t>(i);
+    }
+}
+
+// Host side: classes of n rows; counts[k] = rows in class k.
+template <int NC>
+void classify(int64_t n, int mode, const int64_t* a, const int64_t* ub,
+              const std::array<int64_t, NC - 1>& bounds, DBuf<int32_t> (&lists)[NC], int (&counts)[NC],
+              hipStream_t s) {
+    RowClasses rc{};
+    for (int k = 0; k < NC; ++k) {
+        lists[k].alloc(static_cast<size_t>(std::max<int64_t>(n, 1)));
+        rc.list[k] = lists[k].p;
+        if (k < NC - 1) rc.bound[k] = bounds[k];
+    }
+    DBuf<int> cnt(NC);
+    PAIR_HIP(hipMemsetAsync(cnt.p, 0, NC * sizeof(int), s));
+    hipLaunchKernelGGL(k_classify<NC>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, mode, a, ub, rc, cnt.p);
+    PAIR_LAUNCH_CHECK();
+    d2h(counts, cnt.p, NC, s);
+    PAIR_HIP(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------------- coarse numbering
@@ -401,23 +424,40 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         const int tot = __shfl(inc, (lane & ~(G - 1)) + G - 1, 64);
         __syncthreads();
         // Mloc[r][c] = A(cols[c], cols[r]); rhs[r] = -A(i, cols[r]).  The
-        // entries of all K rows are spread over the lanes as one flat list, so
-        // every lane's loads are independent of the others'.
-        for (int q = sub; q < tot; q += G) {
-            int c = 0, hi = K - 1;   // last c with rpref[c] <= q
-            while (c < hi) {
-                const int mid = (c + hi + 1) >> 1;
-                if (rpref[g][mid] <= q) c = mid; else hi = mid - 1;
+        // entries of all K rows are spread over the lanes as one flat list, four
+        // per lane at a time with all their loads issued before any is used.
+        constexpr int U = 4;
+        for (int q0 = sub; q0 < tot; q0 += U * G) {
+            int cq[U];
+            int64_t eq[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * G;
+                int c = 0, hi = K - 1;   // last c with rpref[c] <= q
+                while (c < hi) {
+                    const int mid = (c + hi + 1) >> 1;
+                    if (rpref[g][mid] <= q) c = mid; else hi = mid - 1;
+                }
+                cq[u] = c;
+                eq[u] = q < tot ? rbeg[g][c] + (q - rpref[g][c]) : -1;
             }
-            const int64_t e = rbeg[g][c] + (q - rpref[g][c]);
-            const int32_t cc = col[e];
-            int lo = 0;
-            hi = K - 1;
-            while (lo <= hi) {
-                const int mid = (lo + hi) >> 1;
-                const int v = cols[g][mid];
-                if (v == cc) { Mloc[g][mid * LD + c] = val[e]; break; }
-                if (v < cc) lo = mid + 1; else hi = mid - 1;
+            int32_t cc[U];
+            double vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cc[u] = eq[u] >= 0 ? col[eq[u]] : -1;
+                vv[u] = eq[u] >= 0 ? val[eq[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (eq[u] < 0) continue;
+                int lo = 0, hi = K - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int v = cols[g][mid];
+                    if (v == cc[u]) { Mloc[g][mid * LD + cq[u]] = vv[u]; break; }
+                    if (v < cc[u]) lo = mid + 1; else hi = mid - 1;
+                }
             }
         }
         for (int64_t e = rs + sub; e < re; e += G) {
@@ -783,12 +823,13 @@ k_rap_lds(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
 // Numeric R (A P) for rows of at most PCAP products (hash table of 2 PCAP
 // slots).  The products' columns and values are staged in LDS, the distinct
 // columns found with the hash set and ranked (counting for short lists, bitonic
-// sort otherwise); then one thread per distinct column walks the R entries in
-// order and binary-searches the column in each (sorted) staged row of A P,
-// accumulating with fma in R's entry order: the same sum, rounded the same way,
-// as adding the rows of A P one R entry after the other, with no barrier per
-// R entry.
-template <int NT, int PCAP>
+// sort otherwise).  Then one thread per distinct column adds its products in
+// the order of the R entries with fma: the same sum, rounded the same way, as
+// adding the rows of A P one R entry after the other, with no barrier per R
+// entry.  The thread finds its product of R entry t in a (distinct column x
+// R entry) table of at most TCAP entries, or, for rows whose table would not
+// fit, by binary search in the sorted staged row t of A P.
+template <int NT, int PCAP, int TCAP>
 __global__ void __launch_bounds__(NT)
 k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ r_rowptr,
           const int32_t* __restrict__ r_col, const double* __restrict__ r_val,
@@ -802,10 +843,14 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
     __shared__ uint32_t ucol[PCAP];
     __shared__ int32_t pc[PCAP];
     __shared__ double pv[PCAP];
+    __shared__ uint8_t pt[PCAP];      // R entry of each product
+    __shared__ int16_t idx[TCAP];     // [distinct column][R entry] -> product, or -1
     __shared__ int s_pref[RMAX + 1];
     __shared__ int64_t s_base[RMAX];
     __shared__ double s_rv[RMAX];
     __shared__ int s_cnt;
+    static_assert(RMAX < 256 && PCAP <= 32767 && TBL * sizeof(int16_t) <= PCAP * sizeof(uint32_t),
+                  "index widths");
     const int tid = threadIdx.x;
     for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
         const int64_t I = list[r];
@@ -836,6 +881,7 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
             const uint32_t c = static_cast<uint32_t>(ap_col[e]);
             pc[q] = static_cast<int32_t>(c);
             pv[q] = ap_val[e];
+            pt[q] = static_cast<uint8_t>(lo);
             uint32_t h = hash_slot(c, mask);
             while (true) {
                 const uint32_t old = atomicCAS(&tkeys[h], HASH_EMPTY, c);
@@ -862,20 +908,50 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
         }
         __syncthreads();
         const int64_t ob = c_rowptr[I];
-        for (int u = tid; u < nu; u += NT) {
-            const int32_t c = static_cast<int32_t>(ucol[u]);
-            double acc = 0.0;
-            for (int t = 0; t < rl; ++t) {
-                int lo = s_pref[t], hi = s_pref[t + 1] - 1;
-                while (lo <= hi) {
-                    const int mid = (lo + hi) >> 1;
-                    const int32_t cm = pc[mid];
-                    if (cm == c) { acc = fma(s_rv[t], pv[mid], acc); break; }
-                    if (cm < c) lo = mid + 1; else hi = mid - 1;
-                }
+        if (nu * rl <= TCAP) {
+            // table of which product each (distinct column, R entry) pair is:
+            // the sums then read independent entries instead of searching
+            int16_t* tpos = reinterpret_cast<int16_t*>(ulist);   // hash slot -> rank
+            for (int u = tid; u < nu; u += NT) {
+                const uint32_t c = ucol[u];
+                uint32_t h = hash_slot(c, mask);
+                while (tkeys[h] != c) h = (h + 1) & mask;
+                tpos[h] = static_cast<int16_t>(u);
             }
-            c_col[ob + u] = c;
-            c_val[ob + u] = acc;
+            for (int k = tid; k < nu * rl; k += NT) idx[k] = -1;
+            __syncthreads();
+            for (int q = tid; q < total; q += NT) {
+                const uint32_t c = static_cast<uint32_t>(pc[q]);
+                uint32_t h = hash_slot(c, mask);
+                while (tkeys[h] != c) h = (h + 1) & mask;
+                idx[tpos[h] * rl + pt[q]] = static_cast<int16_t>(q);
+            }
+            __syncthreads();
+            for (int u = tid; u < nu; u += NT) {
+                double acc = 0.0;
+                for (int t = 0; t < rl; ++t) {
+                    const int q = idx[u * rl + t];
+                    if (q >= 0) acc = fma(s_rv[t], pv[q], acc);
+                }
+                c_col[ob + u] = static_cast<int32_t>(ucol[u]);
+                c_val[ob + u] = acc;
+            }
+        } else {
+            for (int u = tid; u < nu; u += NT) {
+                const int32_t c = static_cast<int32_t>(ucol[u]);
+                double acc = 0.0;
+                for (int t = 0; t < rl; ++t) {
+                    int lo = s_pref[t], hi = s_pref[t + 1] - 1;
+                    while (lo <= hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const int32_t cm = pc[mid];
+                        if (cm == c) { acc = fma(s_rv[t], pv[mid], acc); break; }
+                        if (cm < c) lo = mid + 1; else hi = mid - 1;
+                    }
+                }
+                c_col[ob + u] = c;
+                c_val[ob + u] = acc;
+            }
         }
         __syncthreads();
     }
@@ -1338,17 +1414,10 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         {
             // local systems by size K: <= 8, <= 16, <= 32, <= 64 (64 / G rows per wave)
             DBuf<int32_t> rl[4];
-            for (auto& x : rl) x.alloc(total_c);
-            DBuf<int> rcnt4(4), rsing(1);
-            PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
-            PAIR_HIP(hipMemsetAsync(rcnt4.p, 0, 4 * sizeof(int), s_));
-            hipLaunchKernelGGL(k_class3, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c, 1,
-                               L.R.rowptr.p, nullptr, int64_t(8), int64_t(16), rl[0].p, rl[1].p, rl[2].p,
-                               rcnt4.p, int64_t(32), rl[3].p);
-            PAIR_LAUNCH_CHECK();
             int nrc[4];
-            d2h(nrc, rcnt4.p, 4, s_);
-            PAIR_HIP(hipStreamSynchronize(s_));
+            DBuf<int> rsing(1);
+            PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
+            classify<4>(total_c, 1, L.R.rowptr.p, nullptr, {8, 16, 32}, rl, nrc, s_);
             for (int c = 0; c < 4; ++c) {
                 const int nr = nrc[c];
                 if (nr == 0) continue;
@@ -1374,28 +1443,26 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         DBuf<double> ap_val(L.A.nnz);
         DBuf<int> ap_len(n);
         {
-            DBuf<int32_t> al0(n), al1(n), al2(n), al3(n);
-            DBuf<int> acnt(4);
-            PAIR_HIP(hipMemsetAsync(acnt.p, 0, 4 * sizeof(int), s_));
-            hipLaunchKernelGGL(k_class3, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, 0, L.A.rowptr.p,
-                               nullptr, int64_t(32), int64_t(64), al0.p, al1.p, al2.p, acnt.p,
-                               int64_t(2048), al3.p);
-            PAIR_LAUNCH_CHECK();
-            int na[4];
-            d2h(na, acnt.p, 4, s_);
-            PAIR_HIP(hipStreamSynchronize(s_));
-            PAIR_CHECK(na[3] == 0, "a row of a coarse operator has more than 2048 entries");
+            // rows by length: <= 16, <= 32 (registers), <= 64, <= 2048 (LDS)
+            DBuf<int32_t> al[5];
+            int na[5];
+            classify<5>(n, 0, L.A.rowptr.p, nullptr, {16, 32, 64, 2048}, al, na, s_);
+            PAIR_CHECK(na[4] == 0, "a row of a coarse operator has more than 2048 entries");
             if (na[0] > 0)
-                hipLaunchKernelGGL(k_ap_reg<32>, dim3(grid_for(static_cast<int64_t>(na[0]) * 32, 256)),
-                                   dim3(256), 0, s_, na[0], al0.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p,
+                hipLaunchKernelGGL(k_ap_reg<16>, dim3(grid_for(static_cast<int64_t>(na[0]) * 16, 256)),
+                                   dim3(256), 0, s_, na[0], al[0].p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p,
                                    ap_col.p, ap_val.p, ap_len.p);
             if (na[1] > 0)
-                hipLaunchKernelGGL((k_ap<64, 64>), dim3(std::min(na[1], 1 << 20)), dim3(64), 0, s_, na[1],
-                                   al1.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
-                                   ap_len.p);
+                hipLaunchKernelGGL(k_ap_reg<32>, dim3(grid_for(static_cast<int64_t>(na[1]) * 32, 256)),
+                                   dim3(256), 0, s_, na[1], al[1].p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p,
+                                   ap_col.p, ap_val.p, ap_len.p);
             if (na[2] > 0)
-                hipLaunchKernelGGL((k_ap<256, 2048>), dim3(std::min(na[2], 1 << 20)), dim3(256), 0, s_,
-                                   na[2], al2.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p,
+                hipLaunchKernelGGL((k_ap<64, 64>), dim3(std::min(na[2], 1 << 20)), dim3(64), 0, s_, na[2],
+                                   al[2].p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p, ap_val.p,
+                                   ap_len.p);
+            if (na[3] > 0)
+                hipLaunchKernelGGL((k_ap<256, 2048>), dim3(std::min(na[3], 1 << 20)), dim3(256), 0, s_,
+                                   na[3], al[3].p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.p.p, ap_col.p,
                                    ap_val.p, ap_len.p);
             PAIR_LAUNCH_CHECK();
         }
@@ -1405,18 +1472,8 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                            L.R.rowptr.p, L.R.col.p, ap_len.p, ub.p);
         PAIR_LAUNCH_CHECK();
         DBuf<int32_t> lists[4];
-        for (int c = 0; c < 4; ++c) lists[c].alloc(total_c);
-        int lcount[4] = {0, 0, 0, 0};
-        {
-            DBuf<int> lc(4);
-            PAIR_HIP(hipMemsetAsync(lc.p, 0, 4 * sizeof(int), s_));
-            hipLaunchKernelGGL(k_class3, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c, 2,
-                               nullptr, ub.p, int64_t(256), int64_t(1024), lists[0].p, lists[1].p,
-                               lists[2].p, lc.p, int64_t(2048), lists[3].p);
-            PAIR_LAUNCH_CHECK();
-            d2h(lcount, lc.p, 4, s_);
-            PAIR_HIP(hipStreamSynchronize(s_));
-        }
+        int lcount[4];
+        classify<4>(total_c, 2, nullptr, ub.p, {256, 1024, 2048}, lists, lcount, s_);
         // hash-table scratch for the global class: 2 * pow2(products) slots per row
         std::vector<int64_t> gscr_off_h;
         DBuf<int64_t> gscr_off;
@@ -1453,13 +1510,13 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                          ap_len.p, ap_col.p, ap_val.p
             if (numeric) {
                 if (lcount[0] > 0)
-                    hipLaunchKernelGGL((k_rap_num<64, 256>), grid(lcount[0]), dim3(64), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<64, 256, 2048>), grid(lcount[0]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(0), crp, ccol, cval);
                 if (lcount[1] > 0)
-                    hipLaunchKernelGGL((k_rap_num<128, 1024>), grid(lcount[1]), dim3(128), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<128, 1024, 4096>), grid(lcount[1]), dim3(128), 0, s_,
                                        PAIR_RAP_ARGS(1), crp, ccol, cval);
                 if (lcount[2] > 0)
-                    hipLaunchKernelGGL((k_rap_num<256, 2048>), grid(lcount[2]), dim3(256), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<256, 2048, 2048>), grid(lcount[2]), dim3(256), 0, s_,
                                        PAIR_RAP_ARGS(2), crp, ccol, cval);
             } else {
                 if (lcount[0] > 0)

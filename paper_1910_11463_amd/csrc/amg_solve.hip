@@ -222,12 +222,38 @@ k_norm_finalize(int mode, int B, int chunks, const int64_t* __restrict__ moff,
 }
 
 // ---------------------------------------------------------------- finest level, element blocks
-// Off-diagonal part of row `row` of an element-block operator times x.
+// Values of the finest level are grouped by class (see FineEll): a row's block
+// of values, the stride between its value slots and its position there.
+template <int NF>
+struct EllRow {
+    const double* v;
+    int64_t stride, p;
+    bool c;
+    __device__ __forceinline__ EllRow(int64_t row, int64_t n, int64_t nF, const uint64_t* __restrict__ cmask,
+                                      const int64_t* __restrict__ fbase, const double* __restrict__ val) {
+        const int64_t w = row >> 6;
+        const uint64_t below = (1ull << (row & 63)) - 1ull;
+        const uint64_t m = cmask[w];
+        const int64_t fb = fbase[w];
+        c = ((m >> (row & 63)) & 1ull) != 0;
+        if (c) {
+            v = val + 3 * NF * nF;
+            stride = n - nF;
+            p = w * 64 - fb + __popcll(m & below);
+        } else {
+            v = val;
+            stride = nF;
+            p = fb + __popcll(~m & below);
+        }
+    }
+};
+
+// Off-diagonal part of row `row` (element g = row / K) of an element-block
+// operator times x.
 template <int K, int NF>
-__device__ __forceinline__ double ell_offdiag(int64_t row, int64_t n, int64_t nel,
+__device__ __forceinline__ double ell_offdiag(int64_t row, const EllRow<NF>& er, int64_t nel,
                                               const int32_t* __restrict__ nbr,
                                               const int32_t* __restrict__ nodes,
-                                              const double* __restrict__ val,
                                               const double* __restrict__ x) {
     const int64_t g = row / K;
     double s = 0.0;
@@ -238,37 +264,42 @@ __device__ __forceinline__ double ell_offdiag(int64_t row, int64_t n, int64_t ne
         const int pk = nodes[sl * nel + g];
         const double* xu = x + static_cast<int64_t>(U) * K;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) s += val[(sl * NF + j) * n + row] * xu[(pk >> (3 * j)) & 7];
+        for (int j = 0; j < NF; ++j) s += er.v[(sl * NF + j) * er.stride + er.p] * xu[(pk >> (3 * j)) & 7];
     }
     return s;
 }
 
+// One half-sweep over the F points (which = -1) or the C points (+1).  Rows of
+// members not relaxed on this level (their C/F flag is 0) return early, so the
+// class of every remaining row is its cmask bit.
 template <int K, int NF>
 __global__ void __launch_bounds__(kBlock)
-k_ell_relax(int64_t n, int64_t nel, const int32_t* __restrict__ nbr,
+k_ell_relax(int64_t n, int64_t nel, int64_t nF, const int32_t* __restrict__ nbr,
             const int32_t* __restrict__ nodes, const double* __restrict__ val,
-            const int8_t* __restrict__ cf, int8_t which, const uint16_t* __restrict__ seg,
-            const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
-            const double* __restrict__ b, const double* __restrict__ xin, double* __restrict__ xout,
-            double omega, int xin_zero) {
+            const uint64_t* __restrict__ cmask, const int64_t* __restrict__ fbase, int8_t which,
+            const uint16_t* __restrict__ seg, const uint8_t* __restrict__ active,
+            const uint8_t* __restrict__ relax, const double* __restrict__ b,
+            const double* __restrict__ xin, double* __restrict__ xout, double omega, int xin_zero) {
     const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
     if (row >= n) return;
     const int m = seg[row];
     if (!(active[m] && relax[m])) return;
     const double xi = xin_zero ? 0.0 : xin[row];
-    if (cf[row] != which) {
+    const EllRow<NF> er(row, n, nF, cmask, fbase, val);
+    if (er.c != (which > 0)) {
         xout[row] = xi;
         return;
     }
     // unit diagonal: (A x)_row = x_row + offdiag
-    const double ax = xin_zero ? 0.0 : xi + ell_offdiag<K, NF>(row, n, nel, nbr, nodes, val, xin);
+    const double ax = xin_zero ? 0.0 : xi + ell_offdiag<K, NF>(row, er, nel, nbr, nodes, xin);
     xout[row] = xi + omega * (b[row] - ax);
 }
 
 template <int K, int NF>
 __global__ void __launch_bounds__(kBlock)
-k_ell_residual(int64_t n, int64_t nel, const int32_t* __restrict__ nbr,
+k_ell_residual(int64_t n, int64_t nel, int64_t nF, const int32_t* __restrict__ nbr,
                const int32_t* __restrict__ nodes, const double* __restrict__ val,
+               const uint64_t* __restrict__ cmask, const int64_t* __restrict__ fbase,
                const uint16_t* __restrict__ seg, const uint8_t* __restrict__ active,
                const uint8_t* __restrict__ relax, const double* __restrict__ b,
                const double* __restrict__ x, double* __restrict__ r) {
@@ -276,14 +307,16 @@ k_ell_residual(int64_t n, int64_t nel, const int32_t* __restrict__ nbr,
     if (row >= n) return;
     const int m = seg[row];
     if (!(active[m] && relax[m])) return;
-    r[row] = b[row] - (x[row] + ell_offdiag<K, NF>(row, n, nel, nbr, nodes, val, x));
+    const EllRow<NF> er(row, n, nF, cmask, fbase, val);
+    r[row] = b[row] - (x[row] + ell_offdiag<K, NF>(row, er, nel, nbr, nodes, x));
 }
 
 template <int K, int NF>
 __global__ void __launch_bounds__(kBlock)
 k_ell_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* __restrict__ mcnt,
-                   int64_t n, int64_t nel, const int32_t* __restrict__ nbr,
+                   int64_t n, int64_t nel, int64_t nF, const int32_t* __restrict__ nbr,
                    const int32_t* __restrict__ nodes, const double* __restrict__ val,
+                   const uint64_t* __restrict__ cmask, const int64_t* __restrict__ fbase,
                    const uint8_t* __restrict__ active, const double* __restrict__ b,
                    const double* __restrict__ x, double* __restrict__ partial) {
     __shared__ double red[kBlock / 64];
@@ -294,7 +327,8 @@ k_ell_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* 
         const int64_t begin = moff[m] + static_cast<int64_t>(chunk) * kChunk;
         const int64_t end = moff[m] + mcnt[m];
         for (int64_t row = begin + threadIdx.x; row < begin + kChunk && row < end; row += kBlock) {
-            const double v = b[row] - (x[row] + ell_offdiag<K, NF>(row, n, nel, nbr, nodes, val, x));
+            const EllRow<NF> er(row, n, nF, cmask, fbase, val);
+            const double v = b[row] - (x[row] + ell_offdiag<K, NF>(row, er, nel, nbr, nodes, x));
             acc += v * v;
         }
     }
@@ -308,22 +342,50 @@ k_ell_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* 
     }
 }
 
+// Class masks of the finest level: one wave per 64 rows.
+__global__ void __launch_bounds__(256)
+k_ell_cmask(int64_t n, const int8_t* __restrict__ cf, uint64_t* __restrict__ cmask,
+            int64_t* __restrict__ fcnt) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool in = row < n;
+    const bool c = in && cf[row] > 0;
+    const uint64_t cm = __ballot(c);
+    const uint64_t fm = __ballot(in && !c);
+    if ((threadIdx.x & 63) == 0 && in) {
+        cmask[row >> 6] = cm;
+        fcnt[row >> 6] = __popcll(fm);
+    }
+}
+
+template <int NF>
+__global__ void __launch_bounds__(256)
+k_ell_regroup(int64_t n, int64_t nF, const uint64_t* __restrict__ cmask,
+              const int64_t* __restrict__ fbase, const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const EllRow<NF> er(row, n, nF, cmask, fbase, dst);
+    double* d = const_cast<double*>(er.v);
+#pragma unroll
+    for (int q = 0; q < 3 * NF; ++q) d[q * er.stride + er.p] = src[q * n + row];
+}
+
 template <class F>
 void dispatch_ell(const FineEll& e, F&& f) {
     if (e.k == 8) f(std::integral_constant<int, 8>(), std::integral_constant<int, 4>());
     else f(std::integral_constant<int, 4>(), std::integral_constant<int, 3>());
 }
 
+// Per row: 2 B member id, 1/4 B of class mask and base (16 B per 64 rows).
 double ell_relax_bytes(const Level& L, const FineEll& e, int which, bool zero) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     const double nr = static_cast<double>(which < 0 ? L.n_f : L.n_c);
-    if (zero) return 8.0 * nr + n * (8.0 + 3.0);
-    return nr * (24.0 * e.nf + 8.0) + n * (8.0 + 8.0 + 3.0) + 24.0 * static_cast<double>(e.nel);
+    if (zero) return 8.0 * nr + n * (8.0 + 2.25);
+    return nr * (24.0 * e.nf + 8.0) + n * (8.0 + 8.0 + 2.25) + 24.0 * static_cast<double>(e.nel);
 }
 
 double ell_residual_bytes(const Level& L, const FineEll& e) {
     const double n = static_cast<double>(L.n_f + L.n_c);
-    return n * (24.0 * e.nf + 8.0 + 8.0 + 8.0 + 2.0) + 24.0 * static_cast<double>(e.nel);
+    return n * (24.0 * e.nf + 8.0 + 8.0 + 8.0 + 2.25) + 24.0 * static_cast<double>(e.nel);
 }
 
 __global__ void k_zero_int(int* p) { *p = 0; }
@@ -403,8 +465,9 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
                 constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
                 int h = prof_begin(s_, kind);
                 hipLaunchKernelGGL((k_ell_relax<K, NF>), dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_,
-                                   n, E.nel, E.nbr.p, E.nodes.p, E.val.p, L.cf.p, which, L.seg.p, act,
-                                   L.relax.p, L.b.p, cur, other, prm_.omega, zero ? 1 : 0);
+                                   n, E.nel, E.nF, E.nbr.p, E.nodes.p, E.val.p, E.cmask.p, E.fbase.p,
+                                   which, L.seg.p, act, L.relax.p, L.b.p, cur, other, prm_.omega,
+                                   zero ? 1 : 0);
                 prof_end(s_, h, ell_relax_bytes(L, E, which, zero));
             });
             PAIR_LAUNCH_CHECK();
@@ -459,8 +522,8 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
                 constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
                 int h = prof_begin(s_, PROF_RESIDUAL_FINE);
                 hipLaunchKernelGGL((k_ell_residual<K, NF>), dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0,
-                                   s_, n, E.nel, E.nbr.p, E.nodes.p, E.val.p, L.seg.p, act, L.relax.p,
-                                   L.b.p, cur[l], L.r.p);
+                                   s_, n, E.nel, E.nF, E.nbr.p, E.nodes.p, E.val.p, E.cmask.p,
+                                   E.fbase.p, L.seg.p, act, L.relax.p, L.b.p, cur[l], L.r.p);
                 prof_end(s_, h, ell_residual_bytes(L, E));
             });
         } else dispatch_lpr(L.lpr, [&](auto lc) {
@@ -501,6 +564,32 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
             PAIR_LAUNCH_CHECK();
         }
     }
+}
+
+void Hierarchy::set_fine_ell(std::shared_ptr<FineEll> e) {
+    ell_ = std::move(e);
+    drop_graph();
+    if (!ell_ || ell_->split) return;
+    FineEll& E = *ell_;
+    const Level& L0 = levels_[0];
+    const int64_t n = E.nrows;
+    PAIR_CHECK(n == L0.A.n && L0.cf.p, "element-block operator does not match the finest level");
+    const int64_t nb = (n + 63) / 64;
+    E.cmask.alloc(nb);
+    E.fbase.alloc(nb + 1);
+    DBuf<int64_t> fcnt(nb);
+    hipLaunchKernelGGL(k_ell_cmask, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L0.cf.p, E.cmask.p, fcnt.p);
+    PAIR_LAUNCH_CHECK();
+    E.nF = exclusive_scan(fcnt.p, E.fbase.p, nb, s_);
+    DBuf<double> nv(E.val.n);
+    dispatch_ell(E, [&](auto, auto fc) {
+        constexpr int NF = decltype(fc)::value;
+        hipLaunchKernelGGL(k_ell_regroup<NF>, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, E.nF, E.cmask.p,
+                           E.fbase.p, E.val.p, nv.p);
+    });
+    PAIR_LAUNCH_CHECK();
+    E.val = std::move(nv);   // the old block is reused only on this stream, after the copy
+    E.split = true;
 }
 
 // Lanes per row of the row kernels, chosen per level index by timing the
@@ -594,8 +683,9 @@ void Hierarchy::launch_cycle_and_test(bool x_is_zero, int /*it_offset*/) {
             constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
             int h = prof_begin(s_, PROF_NORM_FINE);
             hipLaunchKernelGGL((k_ell_norm_partial<K, NF>), dim3(sb_.chunks, B_), dim3(kBlock), 0, s_,
-                               sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.n, E.nel, E.nbr.p, E.nodes.p,
-                               E.val.p, sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+                               sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.n, E.nel, E.nF, E.nbr.p,
+                               E.nodes.p, E.val.p, E.cmask.p, E.fbase.p, sb_.active.p, L0.b.p, L0.x.p,
+                               sb_.partial.p);
             prof_end(s_, h, ell_residual_bytes(L0, E) - 8.0 * L0.A.n);
         });
     } else dispatch_lpr(L0.lpr, [&](auto lc) {
