@@ -154,8 +154,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--cpu-dirs", type=int, default=16)
-    ap.add_argument("--relax-pre", default="FFC")
-    ap.add_argument("--relax-post", default="FFC")
+    ap.add_argument("--relax-pre", default="FFCF")
+    ap.add_argument("--relax-post", default="FFCF")
     ap.add_argument("--relax-pre-coarse", default="F")
     ap.add_argument("--relax-post-coarse", default="F")
     ap.add_argument("--streams", type=int, default=8,

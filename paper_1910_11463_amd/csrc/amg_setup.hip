@@ -338,8 +338,8 @@ constexpr int KCAP = 64;      // largest local system (one wave: lane = row)
 // lAIR rows, G lanes per coarse row (G = 8, 16, 32 or 64 >= the row's local system
 // size K), 64 / G rows per wave.  Local system A(R_i,R_i)^T z = -A(i,R_i)^T in
 // LDS, Gaussian elimination with partial pivoting (lane r owns row r), back
-// substitution with group sums.  Loops run to the largest K of the wave so every
-// lane reaches every barrier.
+// substitution by columns with the solution entries broadcast by shuffles.
+// Loops run to the largest K of the wave so every lane reaches every barrier.
 template <int G>
 __global__ void __launch_bounds__(64)
 k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict__ c2f,
@@ -351,7 +351,6 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
     constexpr int LD = G + 1;
     __shared__ double Mloc[RPW][G * LD];
     __shared__ double rhs[RPW][G];
-    __shared__ double z[RPW][G];
     __shared__ int cols[RPW][G];
     __shared__ int kw[RPW];
     __shared__ int64_t rbeg[RPW][G];
@@ -494,19 +493,21 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
             }
             __syncthreads();
             if (go && sub > p && sub < K) {
-                double l = Mloc[g][sub * LD + p] / Mloc[g][p * LD + p];
+                const double l = Mloc[g][sub * LD + p] / Mloc[g][p * LD + p];
                 for (int c = p + 1; c < K; ++c) Mloc[g][sub * LD + c] -= l * Mloc[g][p * LD + c];
                 rhs[g][sub] -= l * rhs[g][p];
             }
             __syncthreads();
         }
-        z[g][sub] = 0.0;
-        __syncthreads();
+        // back substitution by columns: lane r finishes z_r, every lane above
+        // removes its multiple from its own right-hand side
+        const int gl = lane & ~(G - 1);
+        double rr = sub < K ? rhs[g][sub] : 0.0;
+        double zr = 0.0;
         for (int r = Kw - 1; r >= 0; --r) {
-            double sv = (!sing && r < K && sub > r && sub < K) ? Mloc[g][r * LD + sub] * z[g][sub] : 0.0;
-            sv = group_sum<G>(sv);
-            if (!sing && r < K && sub == 0) z[g][r] = (rhs[g][r] - sv) / Mloc[g][r * LD + r];
-            __syncthreads();
+            if (!sing && r < K && sub == r) zr = rr / Mloc[g][r * LD + r];
+            const double zb = __shfl(zr, gl + r, 64);
+            if (!sing && r < K && sub < r) rr -= Mloc[g][sub * LD + r] * zb;
         }
         if (have && sing && sub == 0) atomicAdd(singular, 1);
         if (have) {
@@ -516,7 +517,7 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
             if (sub < K) {
                 int pos = sub + (cols[g][sub] > i ? 1 : 0);
                 r_col[rb + pos] = cols[g][sub];
-                r_val[rb + pos] = sing ? 0.0 : z[g][sub];
+                r_val[rb + pos] = sing ? 0.0 : zr;
             }
             if (sub == 0) {
                 r_col[rb + before] = static_cast<int32_t>(i);
@@ -1471,36 +1472,36 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         hipLaunchKernelGGL(k_rap_ub, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
                            L.R.rowptr.p, L.R.col.p, ap_len.p, ub.p);
         PAIR_LAUNCH_CHECK();
-        DBuf<int32_t> lists[4];
-        int lcount[4];
-        classify<4>(total_c, 2, nullptr, ub.p, {256, 1024, 2048}, lists, lcount, s_);
+        // classes by products: <= 128, <= 256, <= 1024, <= 2048 in LDS, the rest global
+        DBuf<int32_t> lists[5];
+        int lcount[5];
+        classify<5>(total_c, 2, nullptr, ub.p, {128, 256, 1024, 2048}, lists, lcount, s_);
         // hash-table scratch for the global class: 2 * pow2(products) slots per row
         std::vector<int64_t> gscr_off_h;
         DBuf<int64_t> gscr_off;
         DBuf<uint32_t> gkeys, gcols;
         DBuf<int32_t> gpos;
         DBuf<double> gvals;
-        if (lcount[3] > 0) {
-            std::vector<int32_t> rows(lcount[3]);
-            d2h(rows.data(), lists[3].p, lcount[3], s_);
+        if (lcount[4] > 0) {
+            std::vector<int32_t> rows(lcount[4]);
+            d2h(rows.data(), lists[4].p, lcount[4], s_);
             std::vector<int64_t> ubh(total_c);
             d2h(ubh.data(), ub.p, total_c, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            gscr_off_h.resize(lcount[3] + 1, 0);
-            for (int k = 0; k < lcount[3]; ++k) {
+            gscr_off_h.resize(lcount[4] + 1, 0);
+            for (int k = 0; k < lcount[4]; ++k) {
                 int64_t cap = 1;
                 while (cap < ubh[rows[k]]) cap <<= 1;
                 gscr_off_h[k + 1] = gscr_off_h[k] + 2 * cap;
             }
-            gscr_off.alloc(lcount[3] + 1);
-            h2d(gscr_off.p, gscr_off_h.data(), lcount[3] + 1, s_);
+            gscr_off.alloc(lcount[4] + 1);
+            h2d(gscr_off.p, gscr_off_h.data(), lcount[4] + 1, s_);
             gkeys.alloc(gscr_off_h.back());
             gpos.alloc(gscr_off_h.back());
             gcols.alloc(gscr_off_h.back() / 2);
             gvals.alloc(gscr_off_h.back() / 2);
         }
-        // classes by products: <= 256, <= 1024, <= 2048 in LDS, the rest global
-        auto run_rap = [&](bool numeric, Csr* C) {
+                auto run_rap = [&](bool numeric, Csr* C) {
             int64_t* cnt_out = ccnt.p;
             const int64_t* crp = numeric ? C->rowptr.p : nullptr;
             int32_t* ccol = numeric ? C->col.p : nullptr;
@@ -1510,36 +1511,42 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                          ap_len.p, ap_col.p, ap_val.p
             if (numeric) {
                 if (lcount[0] > 0)
-                    hipLaunchKernelGGL((k_rap_num<64, 256, 2048>), grid(lcount[0]), dim3(64), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<64, 128, 1024>), grid(lcount[0]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(0), crp, ccol, cval);
                 if (lcount[1] > 0)
-                    hipLaunchKernelGGL((k_rap_num<128, 1024, 4096>), grid(lcount[1]), dim3(128), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<64, 256, 2048>), grid(lcount[1]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(1), crp, ccol, cval);
                 if (lcount[2] > 0)
-                    hipLaunchKernelGGL((k_rap_num<256, 2048, 2048>), grid(lcount[2]), dim3(256), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<128, 1024, 4096>), grid(lcount[2]), dim3(128), 0, s_,
                                        PAIR_RAP_ARGS(2), crp, ccol, cval);
+                if (lcount[3] > 0)
+                    hipLaunchKernelGGL((k_rap_num<256, 2048, 2048>), grid(lcount[3]), dim3(256), 0, s_,
+                                       PAIR_RAP_ARGS(3), crp, ccol, cval);
             } else {
                 if (lcount[0] > 0)
-                    hipLaunchKernelGGL((k_rap_lds<64, 512, false>), grid(lcount[0]), dim3(64), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<64, 256, false>), grid(lcount[0]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval);
                 if (lcount[1] > 0)
-                    hipLaunchKernelGGL((k_rap_lds<128, 2048, false>), grid(lcount[1]), dim3(128), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<64, 512, false>), grid(lcount[1]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(1), cnt_out, crp, ccol, cval);
                 if (lcount[2] > 0)
-                    hipLaunchKernelGGL((k_rap_lds<256, 4096, false>), grid(lcount[2]), dim3(256), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<128, 2048, false>), grid(lcount[2]), dim3(128), 0, s_,
                                        PAIR_RAP_ARGS(2), cnt_out, crp, ccol, cval);
+                if (lcount[3] > 0)
+                    hipLaunchKernelGGL((k_rap_lds<256, 4096, false>), grid(lcount[3]), dim3(256), 0, s_,
+                                       PAIR_RAP_ARGS(3), cnt_out, crp, ccol, cval);
             }
 #undef PAIR_RAP_ARGS
             PAIR_LAUNCH_CHECK();
-            if (lcount[3] > 0) {
+            if (lcount[4] > 0) {
                 if (numeric)
-                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[3]), dim3(256), 0, s_,
-                                       lcount[3], lists[3].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[4]), dim3(256), 0, s_,
+                                       lcount[4], lists[4].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
                                        ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 else
-                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[3]), dim3(256), 0, s_,
-                                       lcount[3], lists[3].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[4]), dim3(256), 0, s_,
+                                       lcount[4], lists[4].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
                                        ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 PAIR_LAUNCH_CHECK();

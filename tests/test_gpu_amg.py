@@ -74,7 +74,8 @@ def test_hierarchy_matches_reference(cfg, scale, m, kmax):
 @pytest.mark.parametrize("cfg,scale,m,pre,post,pre_c,post_c",
                          [c + ("FC", "FC", "=", "=") for c in CASES] +
                          [(2, 6, 5, "FFC", "FFC", "=", "="), (3, 2, 7, "", "FFC", "=", "="),
-                          (5, 5, 13, "FC", "FFC", "=", "="), (2, 6, 5, "FFC", "FFC", "F", "FC")])
+                          (5, 5, 13, "FC", "FFC", "=", "="), (2, 6, 5, "FFC", "FFC", "F", "FC"),
+                          (2, 6, 5, "FFCF", "FFCF", "F", "F"), (3, 2, 7, "FFCF", "FFCF", "F", "F")])
 def test_vcycles_match_reference(cfg, scale, m, pre, post, pre_c, post_c):
     """Same iteration count as the reference cycle for each relaxation schedule
     (within one: the two full hierarchies may settle a near-tie in a coarse

@@ -11,11 +11,16 @@ from tests.gpu_util import need_gpu, oracle_problem, rel, solver_for
 pytestmark = pytest.mark.gpu
 
 
+# the benchmark's launch configuration
+BENCH_OPTS = dict(relax_pre="FFCF", relax_post="FFCF", relax_pre_coarse="F", relax_post_coarse="F",
+                  autotune=1, streams=8)
+
+
 def _sampled(cfg, dirs, mode, tol=1e-12):
     from oracle import source_iteration as si
     w = wl.make_config(cfg)
     print("full size", w.name, "mode", mode, flush=True)
-    s = solver_for(w, tol_inner=tol, max_inner=300, relax_pre="FFC", relax_post="FFC", autotune=1)
+    s = solver_for(w, tol_inner=tol, max_inner=300, **BENCH_OPTS)
     psi, phi, st, rc = s.transport_sweep(mode=mode)
     assert rc == B.PAIR_OK
     assert st["relres_max"] <= tol
@@ -70,8 +75,7 @@ def test_adjoint_duality_full_size():
     w = wl.make_config(5)
     prob = oracle_problem(w)
     c = ADJ.detector_source(prob, w.detector)
-    s = solver_for(w, tol_inner=1e-12, tol_outer=1e-12, outer_estimate=1, max_inner=300,
-                   relax_pre="FFC", relax_post="FFC")
+    s = solver_for(w, tol_inner=1e-12, tol_outer=1e-12, outer_estimate=1, max_inner=300, **BENCH_OPTS)
     phi, _, st, rc = s.solve(mode=B.PAIR_BATCHED)
     assert rc == B.PAIR_OK
     gt, gs, phia, _, rc2 = s.adjoint(c, mode=B.PAIR_BATCHED)

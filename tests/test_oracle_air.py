@@ -132,14 +132,40 @@ def test_one_point_interpolation_picks_strongest_c_neighbour():
     assert p.tolist() == [0, 0, 1, 0]
 
 
-@pytest.mark.parametrize("kind,n,order,m", [("hex", 4, 2, 0), ("hex", 4, 8, 33), ("tet", 2, 4, 7)])
-def test_vcycle_converges_to_sweep(kind, n, order, m):
+def test_empty_schedule_is_the_coarse_grid_correction():
+    """With no relaxation a two-level cycle is x + P A_c^{-1} R (b - A x) exactly
+    (pins where the schedules act and the order of the correction)."""
+    prob, b, A = _transport_matrix("hex", 3, 5, order=4)
+    levels = AR.setup(A, AR.Options(coarse_max=16, max_levels=2))
+    assert len(levels) == 2
+    rng = np.random.default_rng(4)
+    bb = rng.standard_normal(A.shape[0])
+    x0 = rng.standard_normal(A.shape[0])
+    L0, L1 = levels
+    want = x0 + L0.P @ np.linalg.solve(L1.A.toarray(), L0.R @ (bb - A @ x0))
+    got = AR.vcycle(levels, bb, x0, 0, 1.0, "", "")
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # one F half-sweep after the correction changes exactly the F rows
+    got_f = AR.vcycle(levels, bb, x0, 0, 1.0, "", "F")
+    fmask = L0.cf < 0
+    assert np.array_equal(got_f[~fmask], got[~fmask])
+    d = A.diagonal()
+    assert np.abs(got_f[fmask] - (got + (bb - A @ got) / d)[fmask]).max() <= 1e-12 * np.abs(got).max()
+
+
+@pytest.mark.parametrize("kind,n,order,m,sched", [
+    ("hex", 4, 2, 0, ("FC", "FC", None, None)), ("hex", 4, 8, 33, ("FC", "FC", None, None)),
+    ("tet", 2, 4, 7, ("FC", "FC", None, None)), ("hex", 4, 8, 33, ("FFCF", "FFCF", "F", "F")),
+    ("tet", 2, 4, 7, ("FFCF", "FFCF", "F", "F"))])
+def test_vcycle_converges_to_sweep(kind, n, order, m, sched):
     prob, b, A = _transport_matrix(kind, n, m, order=order)
     f = prob.rhs(m, None)
     bt = np.einsum("eab,eb->ea", np.linalg.inv(b.D), f).ravel()
     levels = AR.setup(A, AR.Options(coarse_max=16))
     assert len(levels) >= 2
-    x, it, hist = AR.solve(levels, bt, tol=1e-12, maxit=100)
+    pre, post, pre_c, post_c = sched
+    x, it, hist = AR.solve(levels, bt, tol=1e-12, maxit=100, pre=pre, post=post, pre_c=pre_c,
+                           post_c=post_c)
     assert hist[-1] <= 1e-12
     xs = SW.sweep(b, f).ravel()
     assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
