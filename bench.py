@@ -14,9 +14,11 @@ eight HIP streams, sigma_t log-uniform in [0.1, 10] (seed 2), sigma_s = 0.9
 sigma_t, q = 1 in the central box.
 
 Printed JSON line also carries: the roofline of the dominant kernel (finest-level
-FC-Jacobi half-sweeps: algorithmic bytes / event-timed duration, against the
-8 TB/s HBM peak), the CPU oracle's exact sweep timed on a bounded sample of the
-same workload, and secondary measurements (batched mode, warm solve).
+F/C Jacobi half-sweeps: algorithmic bytes / event-timed duration, against the
+8 TB/s HBM peak and a measured device copy; HBM traffic from the committed counter
+summary), the CPU oracle's exact sweep timed on the same workload, and secondary
+measurements in `extra`: warm solve (hierarchies kept), setup only, the roofline
+kernel alone on one stream, the batched mode, and full source iterations to 1e-8.
 """
 import argparse
 import json
@@ -124,22 +126,72 @@ def profile_kinds():
     return out
 
 
-def cpu_baseline(w, sample_dirs, threads):
+def cpu_baseline(w, sample_dirs, threads, repeats=2):
     """The oracle's exact sweep (assembly + topological block solve) on a sample
-    of directions of the same workload, timed on the host."""
+    of directions of the same workload, timed on the host: one short warm-up,
+    then the best of `repeats` timed runs."""
     from oracle import quadrature as Q, source_iteration as si
     om, wt = Q.level_symmetric(w.sn_order)
     m = w.mats
     prob = si.Problem(w.mesh, m.sigma_t, m.sigma_s, m.q, om, wt, cache_blocks=False)
     M = om.shape[0]
     dirs = [int(round(k * M / sample_dirs)) % M for k in range(sample_dirs)]
-    t0 = time.perf_counter()
-    si.transport_sweep(prob, None, threads=threads, dirs=dirs)
-    dt = time.perf_counter() - t0
-    return {"value": w.mesh.n_dof * len(dirs) / dt, "unit": "DOF*dirs/s", "cores": threads,
+    si.transport_sweep(prob, None, threads=threads, dirs=dirs[:threads])
+    best = None
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        si.transport_sweep(prob, None, threads=threads, dirs=dirs)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return {"value": w.mesh.n_dof * len(dirs) / best, "unit": "DOF*dirs/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%d of %d directions (assembly + exact block sweep, numpy + C), %.1f s"
-                      % (len(dirs), M, dt)}
+            "sample": "%d of %d directions (assembly + exact block sweep, numpy + C), best of %d: %.1f s"
+                      % (len(dirs), M, repeats, best)}
+
+
+def copy_bandwidth(mib=1024, reps=5):
+    """Device-to-device copy rate (bytes read + written per second), the
+    stream-copy reference the roofline is also compared with."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2.0 * n * 8 / sec / 1e9
+
+
+def source_iteration_time(cfg, device, streams):
+    """End-to-end source iteration to 1e-8 in phi (error-estimate stop) on a
+    workload: cold start, hierarchies built once and kept."""
+    import torch
+    from paper_1910_11463_amd import binding as B
+    from paper_1910_11463_amd import workloads as wl
+    from paper_1910_11463_amd.solver import Solver
+    w = wl.make_config(cfg)
+    s = Solver(tol_inner=1e-9, max_inner=200, tol_outer=1e-8, outer_estimate=1, max_outer=2000,
+               keep_hierarchy=1, relax_pre="FFCF", relax_post="FFCF", relax_pre_coarse="F",
+               relax_post_coarse="F", autotune=1, streams=streams)
+    s.set_mesh(w.mesh)
+    om, wt = Solver.level_symmetric(w.sn_order)
+    s.set_quadrature(om, wt)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device=device)
+    s.set_materials(dev(w.mats.sigma_t), dev(w.mats.sigma_s), dev(w.mats.q))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st, rc = s.solve(mode=B.PAIR_PLAIN, device=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"workload": w.name, "seconds": dt, "outer_iters": st["outer_iters"],
+            "vcycles_total": st["vcycles_total"], "converged": rc == B.PAIR_OK}
 
 
 def main():
@@ -153,7 +205,9 @@ def main():
     ap.add_argument("--batch-size", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--cpu-dirs", type=int, default=16)
+    ap.add_argument("--cpu-dirs", type=int, default=80)
+    ap.add_argument("--si", default="1,3", help="workloads whose full source iteration is timed "
+                    "(extra.source_iteration); empty for none")
     ap.add_argument("--relax-pre", default="FFCF")
     ap.add_argument("--relax-post", default="FFCF")
     ap.add_argument("--relax-pre-coarse", default="F")
@@ -199,6 +253,14 @@ def main():
     wsec, wst = timed_steps(s, mode, 1, 0, cold=False)
     extra["warm_solve"] = {"s_per_sweep": wsec, "dof_dirs_per_s": N * M / wsec,
                            "vcycles_total": wst["vcycles_total"], "solve_ms": wst["t_solve_ms"]}
+    # setup only (assembly + AIR setup of every direction, no solve)
+    s.clear_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sst = s.prepare(mode)
+    torch.cuda.synchronize()
+    ssec = time.perf_counter() - t0
+    extra["setup_only"] = {"s": ssec, "dof_dirs_per_s": N * M / ssec}
     s.close()
     if not args.no_extra:
         # the roofline kernel alone on the GPU: one stream, warm solve
@@ -217,22 +279,39 @@ def main():
                          args.relax_post_coarse, args.streams)
         osec, ost = timed_steps(s2, other, 1, 0, cold=True)
         wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
+        s2.clear_cache()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s2.prepare(other)
+        torch.cuda.synchronize()
+        ssec2 = time.perf_counter() - t0
         extra["other_mode"] = {"mode": "batched" if other == B.PAIR_BATCHED else "plain",
                                "batch_size": args.batch_size if other == B.PAIR_BATCHED else 1,
                                "cold_dof_dirs_per_s": N * M / osec,
                                "warm_dof_dirs_per_s": N * M / wsec2,
+                               "setup_only_dof_dirs_per_s": N * M / ssec2,
                                "vcycles_max": ost["vcycles_max"]}
         s2.close()
+        extra["source_iteration"] = []
+        for c in [int(x) for x in args.si.split(",") if x.strip()]:
+            r = source_iteration_time(c, device, args.streams)
+            log("source iteration %s: %.2f s, %d outer iterations" % (r["workload"], r["seconds"],
+                                                                    r["outer_iters"]))
+            extra["source_iteration"].append(r)
 
     relax = prof["relax_fine"]
+    traffic = measured_traffic()
+    copy_gbs = copy_bandwidth()
     roofline = {"bound": "hbm", "achieved": relax["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": relax["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                "frac": relax["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_ell_relax<8,4> (finest-level F/C Jacobi half-sweeps)",
                 "launches": relax["launches"], "avg_us": relax["avg_us"],
-                "bytes_per_launch": relax["bytes"] / max(1, relax["launches"])}
+                "bytes_per_launch": relax["bytes"] / max(1, relax["launches"]),
+                "traffic_gbs": traffic / (relax["avg_us"] * 1e-6) / 1e9 if traffic else None,
+                "copy_gbs": copy_gbs, "frac_of_copy": relax["gbs"] / copy_gbs}
     cpu = None
     if not args.no_cpu_baseline:
-        threads = min(8, os.cpu_count() or 1)
+        threads = min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(w, args.cpu_dirs, threads)
         log("cpu baseline: %.3e DOF*dirs/s (%s)" % (cpu["value"], cpu["sample"]))
 

@@ -177,6 +177,13 @@ int pair_solve(pair_ctx* ctx, int mode, const double* phi0, double* phi_out, dou
 int pair_transport_sweep(pair_ctx* ctx, int mode, const double* phi_in, double* psi_out,
                          double* phi_out, int where, pair_stats* st);
 
+/* Setup only: assemble the fine operators and build the pAIR hierarchies of
+ * every direction (per batch in PAIR_BATCHED mode) without solving, so that
+ * later pair_transport_sweep / pair_solve calls in the same mode are warm.
+ * Requires options.keep_hierarchy = 1 (else PAIR_E_STATE).  st (may be NULL)
+ * receives the setup statistics: t_assemble_ms, t_setup_ms, levels, sizes. */
+int pair_prepare(pair_ctx* ctx, int mode, pair_stats* st);
+
 /* Drop cached fine operators and hierarchies (the next solve is cold). */
 int pair_clear_cache(pair_ctx* ctx);
 

@@ -79,6 +79,7 @@ _SIGS = {
     "pair_set_dual_source": (c_int, [P, P, c_int, c_int]),
     "pair_solve": (c_int, [P, c_int, P, P, P, c_int, P]),
     "pair_transport_sweep": (c_int, [P, c_int, P, P, P, c_int, P]),
+    "pair_prepare": (c_int, [P, c_int, P]),
     "pair_clear_cache": (c_int, [P]),
     "pair_adjoint": (c_int, [P, c_int, P, P, P, P, c_int, P]),
     "pair_direction_info": (c_int, [P, c_int, P, P, P]),

@@ -36,6 +36,7 @@ struct pair_amg {
             pool_retire_stream(s);
             (void)hipStreamDestroy(s);
         }
+        pool_release_all();
     }
 };
 
@@ -609,6 +610,21 @@ int pair_adjoint(pair_ctx* ctx, int mode, const double* grad_phi, double* dJ_dsi
         rc = r;
     });
     return grc != PAIR_OK ? grc : rc;
+}
+
+int pair_prepare(pair_ctx* ctx, int mode, pair_stats* st) {
+    if (!ctx) return PAIR_E_INVALID;
+    return guarded(ctx->c.err, ctx->c.s, [&] {
+        Context& c = ctx->c;
+        c.check_ready();
+        PAIR_CHECK(mode == PAIR_PLAIN || mode == PAIR_BATCHED, "mode must be PAIR_PLAIN or PAIR_BATCHED");
+        if (!c.opt.keep_hierarchy) throw Error(E_STATE, "pair_prepare needs keep_hierarchy = 1");
+        if (st) std::memset(st, 0, sizeof(*st));
+        SourceSpec src;
+        c.sweep(mode, src, nullptr, nullptr, nullptr, st, false, true);
+        PAIR_HIP(hipStreamSynchronize(c.s));
+        fill_stats_complexity(c, st);
+    });
 }
 
 int pair_clear_cache(pair_ctx* ctx) {

@@ -49,7 +49,8 @@ enum : int {
 // only to allocations for that same stream, so stream order makes reuse safe
 // without synchronisation while several streams work at once.  The stream of an
 // allocation is the calling thread's pool stream (PoolStream).  All cached
-// memory is returned by pool_release_all().
+// memory is returned by pool_release_all() (hipFree synchronises the device),
+// which destroying a context or an AMG handle calls.
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 void pool_release_all();

@@ -34,6 +34,8 @@ Context::~Context() {
         pool_retire_stream(s);
         (void)hipStreamDestroy(s);
     }
+    // hand the cached device memory back (other callers, e.g. torch, share the GPU)
+    pool_release_all();
 }
 
 hipStream_t Context::batch_stream(size_t i) const {
@@ -141,7 +143,7 @@ void Context::rhs_batch(const Batch& bt, const SourceSpec& src, const double* ph
 // that is never captured into a graph (a worker stream may be capturing its
 // cycle graph while another worker hands over its batch).
 bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, double* psi_out,
-                    double* phi_out, pair_stats* st, bool warm) {
+                    double* phi_out, pair_stats* st, bool warm, bool setup_only) {
     check_ready();
     build_batches(mode, st);
     const int64_t N = this->N();
@@ -175,6 +177,24 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
     const hipStream_t acc_s = L > 1 ? acc_stream : nullptr;
     if (acc_s) PAIR_HIP(hipStreamWaitEvent(acc_s, ready, 0));
 
+    // level statistics of a finished batch, then its hierarchy is dropped unless
+    // kept (called with mu held)
+    auto finish = [&](size_t i, Batch& bt) {
+        if (st) {
+            Hierarchy& H = *bt.H;
+            if (i == 0)
+                for (int l = 0; l < std::min(H.num_levels(), PAIR_MAX_LEVELS); ++l) {
+                    Level& Lv = H.level(l);
+                    st->level_n[l] = Lv.off[0] >= 0 ? Lv.cnt[0] : 0;
+                    st->level_nnz[l] = Lv.off[0] >= 0 ? Lv.A.nnz : 0;
+                }
+            for (int b = 0; b < H.members(); ++b) st->levels_max = std::max(st->levels_max, H.member_levels(b));
+        }
+        if (!opt.keep_hierarchy) {
+            bt.H.reset();
+            bt.dinv.reset();
+        }
+    };
     auto run_batch = [&](size_t i, int w) {
         Batch& bt = batches[i];
         const hipStream_t ss = batch_stream(i);
@@ -184,6 +204,14 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
         if (!bt.H) {
             assemble_batch(bt, ss, &ta);
             tsu = now_ms() - t0 - ta;
+        }
+        if (setup_only) {
+            PAIR_HIP(hipStreamSynchronize(ss));
+            std::lock_guard<std::mutex> g(mu);
+            t_asm += ta;
+            t_setup += tsu;
+            finish(i, bt);
+            return;
         }
         const double t1 = now_ms();
         rhs_batch(bt, src, phi_in, bt.H->b0(), ss);
@@ -230,20 +258,7 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
         t_setup += tsu;
         t_other += (t2 - t1) + (t4 - t3);
         t_solve += t3 - t2;
-        if (st) {
-            Hierarchy& H = *bt.H;
-            if (i == 0)
-                for (int l = 0; l < std::min(H.num_levels(), PAIR_MAX_LEVELS); ++l) {
-                    Level& Lv = H.level(l);
-                    st->level_n[l] = Lv.off[0] >= 0 ? Lv.cnt[0] : 0;
-                    st->level_nnz[l] = Lv.off[0] >= 0 ? Lv.A.nnz : 0;
-                }
-            for (int b = 0; b < B; ++b) st->levels_max = std::max(st->levels_max, H.member_levels(b));
-        }
-        if (!opt.keep_hierarchy) {
-            bt.H.reset();
-            bt.dinv.reset();
-        }
+        finish(i, bt);
     };
     auto worker = [&](int w, int dev) {
         try {

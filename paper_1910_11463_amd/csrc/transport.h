@@ -97,8 +97,10 @@ struct Context {
                    hipStream_t st);
     // one sweep replacement over all directions: psi_out [M][N] may be null
     // unless needed, phi_out [N] accumulated in direction order.
+    // setup_only: build the fine operators and hierarchies of every batch and
+    // stop (they are kept only if options.keep_hierarchy is set).
     bool sweep(int mode, const SourceSpec& src, const double* phi_in, double* psi_out,
-               double* phi_out, pair_stats* st, bool warm);
+               double* phi_out, pair_stats* st, bool warm, bool setup_only = false);
     int64_t N() const { return mesh.n_dof(); }
     AmgParams amg_params() const;
     // hierarchies are built on the stream that later solves with them

@@ -178,6 +178,13 @@ class Solver:
                        allow_noconv=True)
         return gt, gs, pa, st.as_dict(), rc
 
+    def prepare(self, mode=B.PAIR_PLAIN):
+        """Build every direction's fine operator and hierarchy without solving
+        (needs keep_hierarchy=1); returns the setup statistics."""
+        st = B.pair_stats()
+        self._chk(B.pair_prepare(self.h, mode, ctypes.byref(st)))
+        return st.as_dict()
+
     def clear_cache(self):
         self._chk(B.pair_clear_cache(self.h))
 

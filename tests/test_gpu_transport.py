@@ -118,6 +118,29 @@ def test_concurrent_streams_bitwise(mode, streams, bs):
             assert x == y
 
 
+@pytest.mark.parametrize("mode", [B.PAIR_PLAIN, B.PAIR_BATCHED])
+def test_prepare_then_sweep_equals_cold_sweep(mode):
+    """Setup only (pair_prepare) followed by a sweep gives the cold sweep's
+    results bitwise; pair_prepare needs keep_hierarchy."""
+    need_gpu()
+    w = wl.make_config(4, scale=8)
+    _print("prepare", w.name, mode)
+    a = solver_for(w, keep_hierarchy=1, streams=3, batch_size=16)
+    st = a.prepare(mode)
+    assert st["t_setup_ms"] > 0 and st["levels_max"] >= 2 and st["op_complexity"] > 1
+    psi_a, phi_a, sta, rca = a.transport_sweep(mode=mode)
+    b = solver_for(w, keep_hierarchy=1, streams=3, batch_size=16)
+    psi_b, phi_b, stb, rcb = b.transport_sweep(mode=mode)
+    assert rca == B.PAIR_OK and rcb == B.PAIR_OK
+    assert sta["t_setup_ms"] == 0.0 and stb["t_setup_ms"] > 0
+    assert np.array_equal(psi_a, psi_b) and np.array_equal(phi_a, phi_b)
+    c = solver_for(w, keep_hierarchy=0)
+    with pytest.raises(B.PairError):
+        c.prepare(mode)
+    for x in (a, b, c):
+        x.close()
+
+
 def test_repeat_is_bitwise_deterministic():
     need_gpu()
     w = wl.make_config(3, scale=3)
