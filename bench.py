@@ -9,9 +9,9 @@ Metric: DOF x directions per second.  Inputs (mesh, materials, quadrature) are
 resident on the GPU before the timed region.
 
 Default workload: unit cube, 64^3 Q1 hexes (2.1M DOF per direction), S8 (80
-directions) solved one direction at a time, eight directions in flight on
-eight HIP streams, sigma_t log-uniform in [0.1, 10] (seed 2), sigma_s = 0.9
-sigma_t, q = 1 in the central box.
+directions) in batches of 16 directions (one block-diagonal hierarchy each),
+five batches in flight on five HIP streams, sigma_t log-uniform in [0.1, 10]
+(seed 2), sigma_s = 0.9 sigma_t, q = 1 in the central box.
 
 Printed JSON line also carries: the roofline of the dominant kernel (finest-level
 F/C Jacobi half-sweeps: algorithmic bytes / event-timed duration, against the
@@ -42,12 +42,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1):
+def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1,
+                coarse_fp32=0):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
                relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
-               autotune=1, streams=streams)
+               autotune=1, streams=streams, coarse_fp32=coarse_fp32)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -109,6 +110,7 @@ def timed_steps(s, mode, steps, warmup, cold=True, profile=False):
     t1 = time.perf_counter()
     if profile:
         B.check(B.pair_profile_enable(0))
+    timed_steps.last_phi = phi
     return (t1 - t0) / steps, stats
 
 
@@ -201,8 +203,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload number (1-5)")
     ap.add_argument("--scale", type=int, default=None, help="elements per axis (default: full size)")
-    ap.add_argument("--mode", choices=["plain", "batched"], default="plain")
-    ap.add_argument("--batch-size", type=int, default=8)
+    ap.add_argument("--mode", choices=["plain", "batched"], default="batched")
+    ap.add_argument("--batch-size", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--cpu-dirs", type=int, default=80)
@@ -212,8 +214,9 @@ def main():
     ap.add_argument("--relax-post", default="FFCF")
     ap.add_argument("--relax-pre-coarse", default="F")
     ap.add_argument("--relax-post-coarse", default="F")
-    ap.add_argument("--streams", type=int, default=8,
+    ap.add_argument("--streams", type=int, default=5,
                     help="direction batches set up and solved at once, one HIP stream each")
+    ap.add_argument("--other-streams", type=int, default=8, help="streams for the other mode")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also copy MIB MiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -245,6 +248,7 @@ def main():
                     args.streams)
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
+    phi64 = timed_steps.last_phi.clone()
     value = N * M / sec
     log("cold: %.3f s/step, %.3e DOF*dirs/s" % (sec, value))
 
@@ -276,7 +280,7 @@ def main():
         other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
         s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, args.streams)
+                         args.relax_post_coarse, args.other_streams)
         osec, ost = timed_steps(s2, other, 1, 0, cold=True)
         wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
         s2.clear_cache()
@@ -287,11 +291,24 @@ def main():
         ssec2 = time.perf_counter() - t0
         extra["other_mode"] = {"mode": "batched" if other == B.PAIR_BATCHED else "plain",
                                "batch_size": args.batch_size if other == B.PAIR_BATCHED else 1,
+                               "streams": args.other_streams,
                                "cold_dof_dirs_per_s": N * M / osec,
                                "warm_dof_dirs_per_s": N * M / wsec2,
                                "setup_only_dof_dirs_per_s": N * M / ssec2,
                                "vcycles_max": ost["vcycles_max"]}
         s2.close()
+        # optional FP32 operators below the finest level: rate and effect on phi
+        s3 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
+                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
+                         args.relax_post_coarse, args.streams, coarse_fp32=1)
+        csec, cst = timed_steps(s3, mode, 1, 1, cold=True)
+        phi32 = timed_steps.last_phi
+        wsec3, _ = timed_steps(s3, mode, 1, 0, cold=False)
+        extra["coarse_fp32"] = {"cold_dof_dirs_per_s": N * M / csec, "warm_dof_dirs_per_s": N * M / wsec3,
+                                "vcycles_total": cst["vcycles_total"],
+                                "phi_rel_diff_vs_fp64": float(torch.linalg.norm(phi32 - phi64) /
+                                                              torch.linalg.norm(phi64))}
+        s3.close()
         extra["source_iteration"] = []
         for c in [int(x) for x in args.si.split(",") if x.strip()]:
             r = source_iteration_time(c, device, args.streams)

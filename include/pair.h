@@ -89,6 +89,12 @@ typedef struct pair_options {
                                  driven by its own host thread (default 1).  Results
                                  do not depend on it: every batch does the same
                                  arithmetic, and phi is accumulated in batch order. */
+    int coarse_fp32;          /* 1: the V-cycle uses FP32 copies of the operator values
+                                 on every level below the finest (A, 1/a_ii) and of R;
+                                 vectors and sums stay FP64, and the finest level's
+                                 relaxation, residual and convergence test use the FP64
+                                 operator, so the converged solution is the FP64 one
+                                 (default 0: FP64 throughout)                         */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

@@ -48,6 +48,11 @@ struct AmgParams {
     // alone or in a batch.
     int lpr_a[4] = {8, 16, 16, 16};
     int lpr_r = 8;
+    // FP32 operator values below the finest level (and in R): the finest-level
+    // relaxation, residual and convergence test stay FP64, so the cycle's fixed
+    // point (the FP64 solution) is unchanged; only the coarse-grid correction
+    // is perturbed.
+    bool coarse_fp32 = false;
 };
 
 struct Csr {
@@ -88,6 +93,9 @@ struct Level {
     DBuf<int8_t> cf;               // +1 C, -1 F, 0 on rows of members coarsest here
     DBuf<int32_t> p;               // one-point interpolation column (-1: empty row)
     Csr R;                         // n_{l+1} x n_l
+    // optional FP32 copies for the V-cycle (AmgParams::coarse_fp32): A values
+    // and 1/a_ii on levels >= 1, R values on every level; null when unused
+    DBuf<float> valf, dinvf, rvalf;
     std::vector<int64_t> off;      // per member: first row, -1 if absent
     std::vector<int64_t> cnt;      // per member: rows (0 if absent)
     std::vector<uint8_t> relax_h;  // per member: 1 if it relaxes (not coarsest) here
@@ -157,6 +165,7 @@ private:
     double* sweeps(Level& L, int l, const std::string& sched, double* cur, double* other, bool zero);
     void drop_graph();
     void tune_lanes();
+    void make_fp32_copies();
     void residual_norms();
     void launch_cycle_and_test(bool x_is_zero, int it_offset);
 

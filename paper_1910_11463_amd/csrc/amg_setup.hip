@@ -232,6 +232,11 @@ void classify(int64_t n, int mode, const int64_t* a, const int64_t* ub,
     PAIR_HIP(hipStreamSynchronize(s));
 }
 
+__global__ void k_to_float(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = static_cast<float>(src[i]);
+}
+
 // ------------------------------------------------------------- coarse numbering
 __global__ void k_is_c(int64_t n, const int8_t* __restrict__ state, int64_t* __restrict__ flag) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1584,8 +1589,29 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
     for (int b = 0; b < B_; ++b) maxcnt = std::max(maxcnt, levels_[0].cnt[b]);
     sb_.chunks = static_cast<int>((maxcnt + 511) / 512);
     sb_.partial.alloc(static_cast<size_t>(sb_.chunks) * B_);
+    if (prm_.coarse_fp32) make_fp32_copies();
     PAIR_HIP(hipStreamSynchronize(s_));
     if (prm_.tune) tune_lanes();
+}
+
+void Hierarchy::make_fp32_copies() {
+    auto narrow = [&](const DBuf<double>& src, size_t n, DBuf<float>& dst) {
+        dst.alloc(n);
+        if (n == 0) return;
+        hipLaunchKernelGGL(k_to_float, dim3(grid_for(static_cast<int64_t>(n), 256)), dim3(256), 0, s_,
+                           static_cast<int64_t>(n), src.p, dst.p);
+        PAIR_LAUNCH_CHECK();
+    };
+    for (size_t l = 0; l < levels_.size(); ++l) {
+        Level& L = levels_[l];
+        const bool relaxes = l + 1 < levels_.size() && L.R.n > 0;
+        if (!relaxes) continue;
+        if (l >= 1) {
+            narrow(L.A.val, static_cast<size_t>(L.A.nnz), L.valf);
+            narrow(L.dinv, static_cast<size_t>(L.A.n), L.dinvf);
+        }
+        narrow(L.R.val, static_cast<size_t>(L.R.nnz), L.rvalf);
+    }
 }
 
 Hierarchy::~Hierarchy() { drop_graph(); }

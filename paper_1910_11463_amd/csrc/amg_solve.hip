@@ -23,10 +23,12 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kChunk = 512;    // rows per partial sum of the norm kernels
 
-template <int LPR>
+// VT: type the level's matrix values and 1/a_ii are stored in (double, or
+// float for the optional FP32 coarse levels); vectors and sums stay FP64.
+template <int LPR, class VT = double>
 __global__ void __launch_bounds__(kBlock)
 k_relax(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-        const double* __restrict__ val, const double* __restrict__ dinv,
+        const VT* __restrict__ val, const VT* __restrict__ dinv,
         const int8_t* __restrict__ cf, int8_t which, const uint16_t* __restrict__ seg,
         const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
         const double* __restrict__ b, const double* __restrict__ xin, double* __restrict__ xout,
@@ -43,16 +45,17 @@ k_relax(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict
     }
     double s = 0.0;
     if (!xin_zero) {
-        for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR) s += val[e] * xin[col[e]];
+        for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR)
+            s += static_cast<double>(val[e]) * xin[col[e]];
         s = group_sum<LPR>(s);
     }
-    if (sub == 0) xout[row] = xi + omega * (b[row] - s) * dinv[row];
+    if (sub == 0) xout[row] = xi + omega * (b[row] - s) * static_cast<double>(dinv[row]);
 }
 
-template <int LPR>
+template <int LPR, class VT = double>
 __global__ void __launch_bounds__(kBlock)
 k_residual(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-           const double* __restrict__ val, const uint16_t* __restrict__ seg,
+           const VT* __restrict__ val, const uint16_t* __restrict__ seg,
            const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
            const double* __restrict__ b, const double* __restrict__ x, double* __restrict__ r) {
     const int64_t row = static_cast<int64_t>(xcd_block()) * (kBlock / LPR) + threadIdx.x / LPR;
@@ -61,16 +64,17 @@ k_residual(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restr
     const int m = seg[row];
     if (!(active[m] && relax[m])) return;
     double s = 0.0;
-    for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR) s += val[e] * x[col[e]];
+    for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR)
+        s += static_cast<double>(val[e]) * x[col[e]];
     s = group_sum<LPR>(s);
     if (sub == 0) r[row] = b[row] - s;
 }
 
 // b_c = R r over the rows of the next level (one row per coarse point).
-template <int LPR>
+template <int LPR, class VT = double>
 __global__ void __launch_bounds__(kBlock)
 k_restrict(int64_t nc, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-           const double* __restrict__ val, const uint16_t* __restrict__ seg_c,
+           const VT* __restrict__ val, const uint16_t* __restrict__ seg_c,
            const uint8_t* __restrict__ active, const double* __restrict__ r,
            double* __restrict__ bc) {
     const int64_t row = static_cast<int64_t>(xcd_block()) * (kBlock / LPR) + threadIdx.x / LPR;
@@ -78,7 +82,8 @@ k_restrict(int64_t nc, const int64_t* __restrict__ rowptr, const int32_t* __rest
     if (row >= nc) return;
     if (!active[seg_c[row]]) return;
     double s = 0.0;
-    for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR) s += val[e] * r[col[e]];
+    for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += LPR)
+        s += static_cast<double>(val[e]) * r[col[e]];
     s = group_sum<LPR>(s);
     if (sub == 0) bc[row] = s;
 }
@@ -426,25 +431,28 @@ void dispatch_lpr(int lpr, F&& f) {
 // updated rows' entries and row offsets, b and 1/a_ii of those rows, the
 // gathered x (each entry once), the full output vector, cf and member ids of
 // all rows.  With a zero input vector no matrix entry or x is read.
-double relax_bytes(const Level& L, int which, bool x_zero) {
+// vb: bytes per stored matrix value (8, or 4 for FP32 coarse levels).
+double relax_bytes(const Level& L, int which, bool x_zero, double vb = 8.0) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     const double nr = static_cast<double>(which < 0 ? L.n_f : L.n_c);
     const double nnzr = static_cast<double>(which < 0 ? L.nnz_f : L.nnz_c);
-    double b = 16.0 * nr + 8.0 * n + 3.0 * n;
-    if (!x_zero) b += 12.0 * nnzr + 8.0 * nr + 8.0 * n;
+    double b = (8.0 + vb) * nr + 8.0 * n + 3.0 * n;
+    if (!x_zero) b += (4.0 + vb) * nnzr + 8.0 * nr + 8.0 * n;
     return b;
 }
 
-double residual_bytes(const Level& L) {
+double residual_bytes(const Level& L, double vb = 8.0) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     const double nnz = static_cast<double>(L.nnz_f + L.nnz_c);
-    return 12.0 * nnz + 8.0 * n /*row offsets*/ + 8.0 * n /*x*/ + 8.0 * n /*b*/ + 8.0 * n /*r*/ + 2.0 * n;
+    return (4.0 + vb) * nnz + 8.0 * n /*row offsets*/ + 8.0 * n /*x*/ + 8.0 * n /*b*/ + 8.0 * n /*r*/ +
+           2.0 * n;
 }
 
-double restrict_bytes(const Level& L) {
+double restrict_bytes(const Level& L, double vb = 8.0) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     const double nc = static_cast<double>(L.R.n);
-    return 12.0 * static_cast<double>(L.R.nnz) + 8.0 * nc + 8.0 * n /*r*/ + 8.0 * nc /*b_c*/ + 2.0 * nc;
+    return (4.0 + vb) * static_cast<double>(L.R.nnz) + 8.0 * nc + 8.0 * n /*r*/ + 8.0 * nc /*b_c*/ +
+           2.0 * nc;
 }
 
 }  // namespace
@@ -475,14 +483,20 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
             zero = false;
             continue;
         }
+        const bool f32 = L.valf.p != nullptr;
         dispatch_lpr(L.lpr, [&](auto lc) {
             constexpr int LPR = decltype(lc)::value;
             const unsigned g = grid_xcd(n, kBlock / LPR);
             int h = prof_begin(s_, kind);
-            hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, which, L.seg.p, act,
-                               L.relax.p, L.b.p, cur, other, prm_.omega, zero ? 1 : 0);
-            prof_end(s_, h, relax_bytes(L, which, zero));
+            if (f32)
+                hipLaunchKernelGGL((k_relax<LPR, float>), dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                                   L.A.col.p, L.valf.p, L.dinvf.p, L.cf.p, which, L.seg.p, act,
+                                   L.relax.p, L.b.p, cur, other, prm_.omega, zero ? 1 : 0);
+            else
+                hipLaunchKernelGGL(k_relax<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                                   L.A.col.p, L.A.val.p, L.dinv.p, L.cf.p, which, L.seg.p, act,
+                                   L.relax.p, L.b.p, cur, other, prm_.omega, zero ? 1 : 0);
+            prof_end(s_, h, relax_bytes(L, which, zero, f32 ? 4.0 : 8.0));
         });
         PAIR_LAUNCH_CHECK();
         std::swap(cur, other);
@@ -530,19 +544,28 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
             constexpr int LPR = decltype(lc)::value;
             const unsigned g = grid_xcd(n, kBlock / LPR);
             int h = prof_begin(s_, l == 0 ? PROF_RESIDUAL_FINE : PROF_NKINDS);
-            hipLaunchKernelGGL(k_residual<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
-                               L.A.col.p, L.A.val.p, L.seg.p, act, L.relax.p, L.b.p, cur[l], L.r.p);
-            prof_end(s_, h, residual_bytes(L));
+            if (L.valf.p)
+                hipLaunchKernelGGL((k_residual<LPR, float>), dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                                   L.A.col.p, L.valf.p, L.seg.p, act, L.relax.p, L.b.p, cur[l], L.r.p);
+            else
+                hipLaunchKernelGGL(k_residual<LPR>, dim3(g), dim3(kBlock), 0, s_, n, L.A.rowptr.p,
+                                   L.A.col.p, L.A.val.p, L.seg.p, act, L.relax.p, L.b.p, cur[l], L.r.p);
+            prof_end(s_, h, residual_bytes(L, L.valf.p ? 4.0 : 8.0));
         });
         PAIR_LAUNCH_CHECK();
         Level& C = levels_[l + 1];
         dispatch_lpr(L.lpr_r, [&](auto lc) {
             constexpr int LPR = decltype(lc)::value;
             int h = prof_begin(s_, l == 0 ? PROF_RESTRICT_FINE : PROF_NKINDS);
-            hipLaunchKernelGGL(k_restrict<LPR>, dim3(grid_xcd(L.R.n, kBlock / LPR)), dim3(kBlock), 0,
-                               s_, L.R.n, L.R.rowptr.p, L.R.col.p, L.R.val.p, C.seg.p, act, L.r.p,
-                               C.b.p);
-            prof_end(s_, h, restrict_bytes(L));
+            if (L.rvalf.p)
+                hipLaunchKernelGGL((k_restrict<LPR, float>), dim3(grid_xcd(L.R.n, kBlock / LPR)), dim3(kBlock),
+                                   0, s_, L.R.n, L.R.rowptr.p, L.R.col.p, L.rvalf.p, C.seg.p, act, L.r.p,
+                                   C.b.p);
+            else
+                hipLaunchKernelGGL(k_restrict<LPR>, dim3(grid_xcd(L.R.n, kBlock / LPR)), dim3(kBlock), 0,
+                                   s_, L.R.n, L.R.rowptr.p, L.R.col.p, L.R.val.p, C.seg.p, act, L.r.p,
+                                   C.b.p);
+            prof_end(s_, h, restrict_bytes(L, L.rvalf.p ? 4.0 : 8.0));
         });
         PAIR_LAUNCH_CHECK();
     }
@@ -786,35 +809,42 @@ bool Hierarchy::solve(bool use_graph, bool x_is_zero) {
     return ok;
 }
 
-// Algorithmic bytes of one V-cycle over all members (FP64 values 8 B, int32
-// indices 4 B, int64 row offsets 8 B): what the kernels must read and write,
-// with gathered vector entries counted once per kernel.
+// Algorithmic bytes of one V-cycle over all members (FP64 vectors; matrix
+// values 8 B, or 4 B on FP32 coarse levels; int32 indices 4 B, int64 row
+// offsets 8 B): the relaxation schedules' half-sweeps, residual, restriction
+// and interpolation per level, the coarsest solves and the convergence test.
 double Hierarchy::solve_bytes_per_cycle() const {
     double bytes = 0.0;
     const int nl = static_cast<int>(levels_.size());
     for (int l = 0; l < nl; ++l) {
         const Level& L = levels_[l];
-        const double n = static_cast<double>(L.A.n), nnz = static_cast<double>(L.A.nnz);
+        const double n = static_cast<double>(L.A.n);
         for (size_t k = 0; k < L.coarse_members.size(); ++k) {
             double m = static_cast<double>(L.cnt[L.coarse_members[k]]);
             bytes += 8.0 * m * m + 16.0 * m;
         }
         if (l + 1 >= nl || L.R.n == 0) continue;
-        const double mat = 12.0 * nnz + 8.0 * n;   // values + columns + row offsets
-        // relaxation: 4 half-sweeps; the first pre-smoothing F-half at coarse
-        // levels reads no matrix (x = 0); count 2 full matrix passes there
-        const double relax_mat = (l == 0) ? 2.0 * mat : 1.5 * mat;
-        const double relax_vec = 4.0 * (8.0 * n /*x in*/ + 8.0 * n /*x out*/ + 1.0 * n /*cf*/ + 2.0 * n /*seg*/)
-                                 + 2.0 * (8.0 * n /*b*/ + 8.0 * n /*dinv*/);
-        const double resid = mat + 8.0 * n /*x*/ + 8.0 * n /*b*/ + 8.0 * n /*r*/ + 2.0 * n;
-        const double nc = static_cast<double>(L.R.n), nnzr = static_cast<double>(L.R.nnz);
-        const double restr = 12.0 * nnzr + 8.0 * nc + 8.0 * n /*r*/ + 8.0 * nc /*b_c*/ + 2.0 * nc;
-        const double interp = 4.0 * n + 16.0 * n + 8.0 * nc + 2.0 * n;
-        bytes += relax_mat + relax_vec + resid + restr + interp;
+        const std::string& pre = l == 0 ? prm_.relax_pre : prm_.relax_pre_coarse;
+        const std::string& post = l == 0 ? prm_.relax_post : prm_.relax_post_coarse;
+        const double vb = L.valf.p ? 4.0 : 8.0;
+        bool zero = l > 0;   // coarse levels start from x = 0
+        for (const std::string* sc : {&pre, &post}) {
+            for (char ch : *sc) {
+                const int which = ch == 'F' ? -1 : 1;
+                bytes += (l == 0 && ell_) ? ell_relax_bytes(L, *ell_, which, zero)
+                                          : relax_bytes(L, which, zero, vb);
+                zero = false;
+            }
+        }
+        bytes += (l == 0 && ell_) ? ell_residual_bytes(L, *ell_) : residual_bytes(L, vb);
+        bytes += restrict_bytes(L, L.rvalf.p ? 4.0 : 8.0);
+        const double nc = static_cast<double>(L.R.n);
+        bytes += 4.0 * n + 16.0 * n + 8.0 * nc + 2.0 * n;   // interpolation
     }
     // convergence test on the finest level
     const Level& L0 = levels_[0];
-    bytes += 12.0 * L0.A.nnz + 8.0 * L0.A.n + 16.0 * L0.A.n;
+    bytes += ell_ ? ell_residual_bytes(L0, *ell_) - 8.0 * L0.A.n
+                  : 12.0 * L0.A.nnz + 8.0 * L0.A.n + 16.0 * L0.A.n;
     return bytes;
 }
 

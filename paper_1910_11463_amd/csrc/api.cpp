@@ -198,6 +198,7 @@ void pair_default_options(pair_options* o) {
     std::strcpy(o->relax_pre_coarse, "=");
     std::strcpy(o->relax_post_coarse, "=");
     o->streams = 1;
+    o->coarse_fp32 = 0;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
@@ -236,6 +237,7 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
             opt->max_levels != c.opt.max_levels || opt->max_coarse_ratio != c.opt.max_coarse_ratio ||
             opt->kmax != c.opt.kmax || opt->pmis_seed != c.opt.pmis_seed ||
             opt->batch_size != c.opt.batch_size || opt->streams != c.opt.streams ||
+            opt->coarse_fp32 != c.opt.coarse_fp32 ||
             std::strncmp(opt->relax_pre, c.opt.relax_pre, 8) != 0 ||
             std::strncmp(opt->relax_post, c.opt.relax_post, 8) != 0 ||
             std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, 8) != 0 ||
@@ -767,21 +769,7 @@ int pair_amg_setup(pair_amg* amg, int n_seg, const int64_t* seg_rows, int64_t n,
             off[k] = sr[k];
             cnt[k] = sr[k + 1] - sr[k];
         }
-        AmgParams p;
-        p.theta = amg->opt.theta;
-        p.eps_r = amg->opt.eps_r;
-        p.omega = amg->opt.omega;
-        p.coarse_max = amg->opt.coarse_max;
-        p.max_levels = amg->opt.max_levels;
-        p.max_coarse_ratio = amg->opt.max_coarse_ratio;
-        p.kmax = amg->opt.kmax;
-        p.seed = amg->opt.pmis_seed;
-        p.tol = amg->opt.tol_inner;
-        p.max_iter = amg->opt.max_inner;
-        p.relax_pre = amg->opt.relax_pre;
-        p.relax_post = amg->opt.relax_post;
-        p.relax_pre_coarse = std::strcmp(amg->opt.relax_pre_coarse, "=") ? amg->opt.relax_pre_coarse : p.relax_pre;
-        p.relax_post_coarse = std::strcmp(amg->opt.relax_post_coarse, "=") ? amg->opt.relax_post_coarse : p.relax_post;
+        AmgParams p = params_from_options(amg->opt);
         amg->H.reset(new Hierarchy(p, amg->s));
         amg->H->setup(std::move(A), off, cnt);
         amg->n_seg = n_seg;

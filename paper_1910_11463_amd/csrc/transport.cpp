@@ -49,22 +49,28 @@ void Context::check_ready() const {
     if (!have_mats) throw Error(E_STATE, "no materials set");
 }
 
-AmgParams Context::amg_params() const {
+AmgParams params_from_options(const pair_options& o) {
     AmgParams p;
-    p.theta = opt.theta;
-    p.eps_r = opt.eps_r;
-    p.omega = opt.omega;
-    p.coarse_max = opt.coarse_max;
-    p.max_levels = opt.max_levels;
-    p.max_coarse_ratio = opt.max_coarse_ratio;
-    p.kmax = opt.kmax;
-    p.seed = opt.pmis_seed;
-    p.tol = opt.tol_inner;
-    p.max_iter = opt.max_inner;
-    p.relax_pre = opt.relax_pre;
-    p.relax_post = opt.relax_post;
-    p.relax_pre_coarse = std::strcmp(opt.relax_pre_coarse, "=") ? opt.relax_pre_coarse : p.relax_pre;
-    p.relax_post_coarse = std::strcmp(opt.relax_post_coarse, "=") ? opt.relax_post_coarse : p.relax_post;
+    p.theta = o.theta;
+    p.eps_r = o.eps_r;
+    p.omega = o.omega;
+    p.coarse_max = o.coarse_max;
+    p.max_levels = o.max_levels;
+    p.max_coarse_ratio = o.max_coarse_ratio;
+    p.kmax = o.kmax;
+    p.seed = o.pmis_seed;
+    p.tol = o.tol_inner;
+    p.max_iter = o.max_inner;
+    p.relax_pre = o.relax_pre;
+    p.relax_post = o.relax_post;
+    p.relax_pre_coarse = std::strcmp(o.relax_pre_coarse, "=") ? o.relax_pre_coarse : p.relax_pre;
+    p.relax_post_coarse = std::strcmp(o.relax_post_coarse, "=") ? o.relax_post_coarse : p.relax_post;
+    p.coarse_fp32 = o.coarse_fp32 != 0;
+    return p;
+}
+
+AmgParams Context::amg_params() const {
+    AmgParams p = params_from_options(opt);
     if (opt.autotune) p.tune = tune_cache;
     return p;
 }

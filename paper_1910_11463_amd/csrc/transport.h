@@ -107,6 +107,9 @@ struct Context {
     hipStream_t batch_stream(size_t i) const;
 };
 
+// AIR parameters from the C options (no autotuning cache).
+AmgParams params_from_options(const pair_options& o);
+
 // kernels (assemble.hip)
 void hex_reference(DeviceMesh& m, hipStream_t s);
 void tet_geometry(DeviceMesh& m, int64_t n_vert, hipStream_t s);

@@ -97,6 +97,27 @@ def test_vcycles_match_reference(cfg, scale, m, pre, post, pre_c, post_c):
     assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xe)
 
 
+@pytest.mark.parametrize("cfg,scale,m", [(2, 6, 5), (3, 2, 7)])
+def test_coarse_fp32_keeps_the_fp64_solution(cfg, scale, m):
+    """FP32 operators below the finest level perturb only the coarse-grid
+    correction: the cycle still converges to the FP64 solution, in about as many
+    cycles."""
+    need_gpu()
+    from paper_1910_11463_amd.solver import Amg
+    A, b = _matrix(cfg, scale, m)
+    xe = spla.spsolve(A.tocsc(), b)
+    its = []
+    for f32 in (0, 1):
+        g = Amg(coarse_max=64, tol_inner=1e-12, max_inner=200, relax_pre=b"FFCF", relax_post=b"FFCF",
+                relax_pre_coarse=b"F", relax_post_coarse=b"F", coarse_fp32=f32)
+        g.setup(A.indptr, A.indices, A.data)
+        x, iters, rel, rc = g.solve(b)
+        assert rc == B.PAIR_OK and rel[0] <= 1e-12
+        assert np.linalg.norm(x - xe) <= 1e-10 * np.linalg.norm(xe)
+        its.append(int(iters[0]))
+    assert its[1] <= its[0] + 2, its
+
+
 def test_segments_are_independent_and_bitwise_equal():
     """A block-diagonal batch of three matrices gives each segment exactly the
     hierarchy and iterates it gets alone."""

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 # the benchmark's launch configuration
 BENCH_OPTS = dict(relax_pre="FFCF", relax_post="FFCF", relax_pre_coarse="F", relax_post_coarse="F",
-                  autotune=1, streams=8)
+                  autotune=1, streams=5, batch_size=16)
 
 
 def _sampled(cfg, dirs, mode, tol=1e-12):
@@ -34,10 +34,12 @@ def _sampled(cfg, dirs, mode, tol=1e-12):
     return errs
 
 
-def test_structured_64_plain():
-    """64^3 hexes, S8, one direction at a time (the benchmark's workload)."""
+@pytest.mark.parametrize("mode", [B.PAIR_BATCHED, B.PAIR_PLAIN])
+def test_structured_64(mode):
+    """64^3 hexes, S8 (the benchmark's workload), batches of 16 directions on
+    5 streams and one direction at a time."""
     need_gpu()
-    errs = _sampled(2, [0, 37, 79], B.PAIR_PLAIN)
+    errs = _sampled(2, [0, 37, 79], mode)
     assert max(errs) <= 1e-9
 
 

@@ -141,6 +141,27 @@ def test_prepare_then_sweep_equals_cold_sweep(mode):
         x.close()
 
 
+def test_coarse_fp32_sweep_matches_exact_sweep():
+    """The FP32 coarse-level variant reaches the exact sweep's answer as closely
+    as the FP64 path (the finest level and the convergence test stay FP64)."""
+    need_gpu()
+    from oracle import source_iteration as si
+    w = wl.make_config(2, scale=8)
+    prob = oracle_problem(w)
+    ref = si.transport_sweep(prob, None, threads=4)
+    out = {}
+    for f32 in (0, 1):
+        s = solver_for(w, tol_inner=1e-12, max_inner=300, coarse_fp32=f32, relax_pre="FFCF",
+                       relax_post="FFCF", relax_pre_coarse="F", relax_post_coarse="F")
+        psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_PLAIN)
+        assert rc == B.PAIR_OK
+        out[f32] = (psi, st["vcycles_total"])
+        s.close()
+    for f32 in (0, 1):
+        assert rel(out[f32][0], ref) <= 1e-9
+    assert out[1][1] <= out[0][1] + 2 * w.n_dir
+
+
 def test_repeat_is_bitwise_deterministic():
     need_gpu()
     w = wl.make_config(3, scale=3)
