@@ -257,6 +257,13 @@ def main():
     wsec, wst = timed_steps(s, mode, 1, 0, cold=False)
     extra["warm_solve"] = {"s_per_sweep": wsec, "dof_dirs_per_s": N * M / wsec,
                            "vcycles_total": wst["vcycles_total"], "solve_ms": wst["t_solve_ms"]}
+    # a fixed 4 V-cycles per direction (enough for discretisation accuracy at
+    # 32^3 in the accuracy study; not the 1e-8 metric): warm sweep rate
+    s.set_options(fixed_cycles=4)
+    fsec, fst = timed_steps(s, mode, 1, 0, cold=False)
+    extra["warm_fixed_4_cycles"] = {"s_per_sweep": fsec, "dof_dirs_per_s": N * M / fsec,
+                                    "vcycles_total": fst["vcycles_total"]}
+    s.set_options(fixed_cycles=0)
     # setup only (assembly + AIR setup of every direction, no solve)
     s.clear_cache()
     torch.cuda.synchronize()

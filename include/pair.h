@@ -95,6 +95,12 @@ typedef struct pair_options {
                                  relaxation, residual and convergence test use the FP64
                                  operator, so the converged solution is the FP64 one
                                  (default 0: FP64 throughout)                         */
+    int fixed_cycles;         /* > 0: every direction solve applies exactly this many
+                                 V-cycles (from x = 0, or from the last psi with
+                                 warm_start) instead of iterating to tol_inner; source
+                                 iteration then converges to the fixed point of the
+                                 inexact inverses (Sec. "Accuracy of Spatial Solves").
+                                 0 (default): iterate to tol_inner                    */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

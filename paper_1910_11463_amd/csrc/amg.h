@@ -53,6 +53,10 @@ struct AmgParams {
     // point (the FP64 solution) is unchanged; only the coarse-grid correction
     // is perturbed.
     bool coarse_fp32 = false;
+    // exactly max_iter cycles per solve (tol = 0), counted as converged: the
+    // inexact inverse of the paper's accuracy study (Sec. "Accuracy of Spatial
+    // Solves")
+    bool fixed_cycles = false;
 };
 
 struct Csr {

@@ -804,7 +804,7 @@ bool Hierarchy::solve(bool use_graph, bool x_is_zero) {
         if (L0.off[b] < 0) continue;
         if (iters_h_[b] > 0 && r0[b] > 0.0 && relres_h_[b] > 0.0)
             cf_h_[b] = std::pow(relres_h_[b] / r0[b], 1.0 / iters_h_[b]);
-        if (!(relres_h_[b] <= prm_.tol)) ok = false;
+        if (!prm_.fixed_cycles && !(relres_h_[b] <= prm_.tol)) ok = false;
     }
     return ok;
 }

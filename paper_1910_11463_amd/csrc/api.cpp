@@ -95,6 +95,7 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.max_inner >= 1 && o.max_outer >= 1, "iteration limits must be >= 1");
     PAIR_CHECK(o.batch_size >= 0, "batch_size must be >= 0");
     PAIR_CHECK(o.streams >= 1 && o.streams <= 16, "streams must be in [1, 16]");
+    PAIR_CHECK(o.fixed_cycles >= 0 && o.fixed_cycles <= 10000, "fixed_cycles must be in [0, 10000]");
     auto sched_ok = [](const char* c) {
         size_t n = strnlen(c, 8);
         if (n >= 8) return false;
@@ -199,6 +200,7 @@ void pair_default_options(pair_options* o) {
     std::strcpy(o->relax_post_coarse, "=");
     o->streams = 1;
     o->coarse_fp32 = 0;
+    o->fixed_cycles = 0;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
