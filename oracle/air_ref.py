@@ -78,6 +78,7 @@ class Options:
     seed: int = 0
     relax_pre: str = "FC"      # half-sweeps before the coarse correction
     relax_post: str = "FC"     # and after it ("FFC": F, F, then C)
+    filter_r: float = 0.0      # phi_R: drop R entries below phi_R * row max (0: keep all)
 
 
 def _rows(A: sp.csr_matrix):
@@ -196,7 +197,14 @@ def lair_restriction(A: sp.csr_matrix, cf: np.ndarray, opts: Options) -> sp.csr_
             z = np.linalg.solve(sub.T, rhs)
         else:
             z = np.zeros(0)
-        entries = list(zip(Rset, z)) + [(int(i), 1.0)]
+        entries = list(zip(Rset, z))
+        if opts.filter_r > 0.0 and len(z):
+            # filtering of R after its construction (Sec. "SOC Parameter for
+            # Building R"): the strength test of eq. (soc) with tolerance phi_R
+            # applied to the computed row; the C point's own entry always stays
+            zmax = float(np.abs(z).max())
+            entries = [(j, v) for j, v in entries if abs(v) >= opts.filter_r * zmax]
+        entries = entries + [(int(i), 1.0)]
         entries.sort()
         for j, v in entries:
             rows.append(ci[i])

@@ -118,6 +118,32 @@ def test_lair_defining_identity_and_products(kind, n, m):
     assert np.abs(Ac.toarray() - dense).max() <= 1e-13 * np.abs(dense).max()
 
 
+@pytest.mark.parametrize("kind,n,m", CASES)
+@pytest.mark.parametrize("phi_r", [0.2, 1.0])
+def test_r_filter_drops_exactly_the_weak_entries(kind, n, m, phi_r):
+    """Filtering R after its construction: an off-C entry stays iff its |z| is at
+    least phi_R times the largest |z| of the unfiltered row (the C point's own
+    entry, 1, always stays and does not enter the maximum); kept values are the
+    unfiltered ones."""
+    prob, b, A = _transport_matrix(kind, n, m)
+    lev = AR.setup(A, AR.Options(coarse_max=8, max_levels=2))
+    cf = lev[0].cf
+    R0 = AR.lair_restriction(A, cf, AR.Options()).tocsr()
+    Rf = AR.lair_restriction(A, cf, AR.Options(filter_r=phi_r)).tocsr()
+    cpts = np.flatnonzero(cf > 0)
+    assert Rf.shape == R0.shape
+    for I, i in enumerate(cpts):
+        c0, v0 = R0.indices[R0.indptr[I]:R0.indptr[I + 1]], R0.data[R0.indptr[I]:R0.indptr[I + 1]]
+        cf_, vf = Rf.indices[Rf.indptr[I]:Rf.indptr[I + 1]], Rf.data[Rf.indptr[I]:Rf.indptr[I + 1]]
+        off = c0 != i
+        zmax = np.abs(v0[off]).max() if off.any() else 0.0
+        want = [(c, v) for c, v in zip(c0, v0) if c == i or abs(v) >= phi_r * zmax]
+        assert [c for c, _ in want] == cf_.tolist()
+        assert np.array_equal(np.array([v for _, v in want]), vf)
+        assert vf[cf_.tolist().index(i)] == 1.0
+    assert Rf.nnz < R0.nnz
+
+
 def test_one_point_interpolation_picks_strongest_c_neighbour():
     A = sp.csr_matrix(np.array([
         [1.0, -0.5, 0.5, 0.0],
