@@ -101,6 +101,10 @@ typedef struct pair_options {
                                  iteration then converges to the fixed point of the
                                  inexact inverses (Sec. "Accuracy of Spatial Solves").
                                  0 (default): iterate to tol_inner                    */
+    double filter_r;          /* phi_R: after R is built, entries with |r_ij| below
+                                 phi_R times the largest off-C |r_ik| of their row are
+                                 dropped (the C point's own entry stays) — Sec. "SOC
+                                 Parameter for Building R"; 0 (default) keeps all      */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

@@ -39,7 +39,8 @@ class pair_options(ctypes.Structure):
                 ("relax_pre", ctypes.c_char * 8), ("relax_post", ctypes.c_char * 8),
                 ("autotune", c_int),
                 ("relax_pre_coarse", ctypes.c_char * 8), ("relax_post_coarse", ctypes.c_char * 8),
-                ("streams", c_int), ("coarse_fp32", c_int), ("fixed_cycles", c_int)]
+                ("streams", c_int), ("coarse_fp32", c_int), ("fixed_cycles", c_int),
+                ("filter_r", c_double)]
 
 
 class pair_stats(ctypes.Structure):

@@ -57,6 +57,9 @@ struct AmgParams {
     // inexact inverse of the paper's accuracy study (Sec. "Accuracy of Spatial
     // Solves")
     bool fixed_cycles = false;
+    // phi_R: filtering of R after its construction (Sec. "SOC Parameter for
+    // Building R"); 0 keeps every entry
+    double filter_r = 0.0;
 };
 
 struct Csr {
@@ -170,6 +173,7 @@ private:
     void drop_graph();
     void tune_lanes();
     void make_fp32_copies();
+    void filter_restriction(Level& L, const int32_t* c2f, int64_t nc);
     void residual_norms();
     void launch_cycle_and_test(bool x_is_zero, int it_offset);
 

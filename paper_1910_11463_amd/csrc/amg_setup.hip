@@ -536,6 +536,46 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 
 // ------------------------------------------------------------- R A P
 
+// Filtering of R after its construction (phi_R): in row I (C point i =
+// c2f[I]) an entry j != i stays iff |z_j| >= phi_R * max_{k != i} |z_k|; the
+// entry of i itself always stays.  Count, then copy in column order.
+__global__ void k_r_filter_count(int64_t nc, const int32_t* __restrict__ c2f,
+                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                 const double* __restrict__ val, double phi, int64_t* __restrict__ cnt) {
+    const int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int32_t i = c2f[I];
+    double zmax = 0.0;
+    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
+        if (col[e] != i) zmax = fmax(zmax, fabs(val[e]));
+    const double thr = phi * zmax;
+    int64_t c = 0;
+    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
+        if (col[e] == i || fabs(val[e]) >= thr) ++c;
+    cnt[I] = c;
+}
+
+__global__ void k_r_filter_copy(int64_t nc, const int32_t* __restrict__ c2f,
+                                const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                const double* __restrict__ val, double phi,
+                                const int64_t* __restrict__ nrowptr, int32_t* __restrict__ ncol,
+                                double* __restrict__ nval) {
+    const int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int32_t i = c2f[I];
+    double zmax = 0.0;
+    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
+        if (col[e] != i) zmax = fmax(zmax, fabs(val[e]));
+    const double thr = phi * zmax;
+    int64_t o = nrowptr[I];
+    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
+        if (col[e] == i || fabs(val[e]) >= thr) {
+            ncol[o] = col[e];
+            nval[o] = val[e];
+            ++o;
+        }
+}
+
 // ------------------------------------------------------------- A P and R (A P)
 // One-point interpolation maps column j to coarse column p[j], so row i of A P
 // merges the entries of row i of A that share p[j]: keys (p[j], position) are
@@ -1442,6 +1482,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         }
         int nsing = 0;
         d2h(&nsing, d_counter.p, 1, s_);
+        if (prm_.filter_r > 0.0) filter_restriction(L, c2f.p, total_c);
 
         // A P: merge the entries of each row of A that interpolate from the same
         // coarse point (rows classed by length)
@@ -1612,6 +1653,25 @@ void Hierarchy::make_fp32_copies() {
         }
         narrow(L.R.val, static_cast<size_t>(L.R.nnz), L.rvalf);
     }
+}
+
+void Hierarchy::filter_restriction(Level& L, const int32_t* c2f, int64_t nc) {
+    if (nc == 0) return;
+    DBuf<int64_t> cnt(nc);
+    hipLaunchKernelGGL(k_r_filter_count, dim3(grid_for(nc, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
+                       L.R.col.p, L.R.val.p, prm_.filter_r, cnt.p);
+    PAIR_LAUNCH_CHECK();
+    Csr F;
+    F.n = L.R.n;
+    F.ncols = L.R.ncols;
+    F.rowptr.alloc(nc + 1);
+    F.nnz = exclusive_scan(cnt.p, F.rowptr.p, nc, s_);
+    F.col.alloc(F.nnz);
+    F.val.alloc(F.nnz);
+    hipLaunchKernelGGL(k_r_filter_copy, dim3(grid_for(nc, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
+                       L.R.col.p, L.R.val.p, prm_.filter_r, F.rowptr.p, F.col.p, F.val.p);
+    PAIR_LAUNCH_CHECK();
+    L.R = std::move(F);   // the old arrays are reused only on this stream, after the copy
 }
 
 Hierarchy::~Hierarchy() { drop_graph(); }

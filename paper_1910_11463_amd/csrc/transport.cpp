@@ -66,6 +66,7 @@ AmgParams params_from_options(const pair_options& o) {
     p.relax_pre_coarse = std::strcmp(o.relax_pre_coarse, "=") ? o.relax_pre_coarse : p.relax_pre;
     p.relax_post_coarse = std::strcmp(o.relax_post_coarse, "=") ? o.relax_post_coarse : p.relax_post;
     p.coarse_fp32 = o.coarse_fp32 != 0;
+    p.filter_r = o.filter_r;
     if (o.fixed_cycles > 0) {
         p.fixed_cycles = true;
         p.tol = 0.0;

@@ -27,11 +27,11 @@ CASES = [(2, 6, 5), (3, 2, 7), (5, 5, 13), (4, 6, 40)]
 
 
 def _amg(A, coarse_max, seed=0, seg=None, kmax=64, pre="FC", post="FC", max_levels=25,
-         pre_c="=", post_c="="):
+         pre_c="=", post_c="=", filter_r=0.0):
     from paper_1910_11463_amd.solver import Amg
     a = Amg(coarse_max=coarse_max, pmis_seed=seed, tol_inner=1e-10, max_inner=200, kmax=kmax,
             relax_pre=pre.encode(), relax_post=post.encode(), max_levels=max_levels,
-            relax_pre_coarse=pre_c.encode(), relax_post_coarse=post_c.encode())
+            relax_pre_coarse=pre_c.encode(), relax_post_coarse=post_c.encode(), filter_r=filter_r)
     a.setup(A.indptr, A.indices, A.data, seg)
     return a
 
@@ -71,23 +71,60 @@ def test_hierarchy_matches_reference(cfg, scale, m, kmax):
         assert np.abs(nxt["val"] - R1.A.data).max() <= 1e-12 * np.abs(R1.A.data).max(), l
 
 
+@pytest.mark.parametrize("cfg,scale,m", CASES[:3])
+def test_filtered_restriction_matches_reference(cfg, scale, m):
+    """R filtered with phi_R = 0.2 from the reference's level matrix: the kept
+    pattern is the reference's except for entries within 1e-9 (relative) of the
+    threshold, and the values agree to 1e-12."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A, _ = _matrix(cfg, scale, m)
+    phi = 0.2
+    one = AR.setup(A, AR.Options(coarse_max=64, seed=3, max_levels=2, filter_r=phi))
+    full = AR.lair_restriction(A, one[0].cf, AR.Options()).tocsr()   # unfiltered values
+    g = _amg(A, 64, 3, max_levels=2, filter_r=phi)
+    got = g.level(0)
+    assert np.array_equal(got["cf"], one[0].cf.astype(np.int8))
+    cpts = np.flatnonzero(one[0].cf > 0)
+    rp, rc, rv = got["r_rowptr"], got["r_col"], got["r_val"]
+    Rr = one[0].R.tocsr()
+    scale_v = np.abs(Rr.data).max()
+    for I, i in enumerate(cpts):
+        c0 = full.indices[full.indptr[I]:full.indptr[I + 1]]
+        v0 = full.data[full.indptr[I]:full.indptr[I + 1]]
+        off = c0 != i
+        thr = phi * (np.abs(v0[off]).max() if off.any() else 0.0)
+        want = set(Rr.indices[Rr.indptr[I]:Rr.indptr[I + 1]].tolist())
+        have = dict(zip(rc[rp[I]:rp[I + 1]].tolist(), rv[rp[I]:rp[I + 1]].tolist()))
+        for c, v in zip(c0, v0):
+            if abs(abs(v) - thr) <= 1e-9 * max(thr, 1e-300):
+                continue   # on the threshold: either side is right
+            assert (c in have) == (c in want), (I, c)
+            if c in have:
+                assert abs(have[c] - v) <= 1e-12 * scale_v
+    nxt, R1 = g.level(1), one[1]
+    if np.array_equal(nxt["rowptr"], R1.A.indptr):
+        assert np.abs(nxt["val"] - R1.A.data).max() <= 1e-12 * np.abs(R1.A.data).max()
+
+
 @pytest.mark.parametrize("cfg,scale,m,pre,post,pre_c,post_c",
                          [c + ("FC", "FC", "=", "=") for c in CASES] +
                          [(2, 6, 5, "FFC", "FFC", "=", "="), (3, 2, 7, "", "FFC", "=", "="),
                           (5, 5, 13, "FC", "FFC", "=", "="), (2, 6, 5, "FFC", "FFC", "F", "FC"),
                           (2, 6, 5, "FFCF", "FFCF", "F", "F"), (3, 2, 7, "FFCF", "FFCF", "F", "F")])
-def test_vcycles_match_reference(cfg, scale, m, pre, post, pre_c, post_c):
+@pytest.mark.parametrize("filter_r", [0.0, 0.2])
+def test_vcycles_match_reference(cfg, scale, m, pre, post, pre_c, post_c, filter_r):
     """Same iteration count as the reference cycle for each relaxation schedule
     (within one: the two full hierarchies may settle a near-tie in a coarse
     level differently, since their Galerkin sums round in different orders)."""
     need_gpu()
     from oracle import air_ref as AR
     A, b = _matrix(cfg, scale, m)
-    ref = AR.setup(A, AR.Options(coarse_max=64))
+    ref = AR.setup(A, AR.Options(coarse_max=64, filter_r=filter_r))
     xr, itr, hist = AR.solve(ref, b, tol=1e-10, maxit=200, pre=pre, post=post,
                              pre_c=None if pre_c == "=" else pre_c,
                              post_c=None if post_c == "=" else post_c)
-    g = _amg(A, 64, pre=pre, post=post, pre_c=pre_c, post_c=post_c)
+    g = _amg(A, 64, pre=pre, post=post, pre_c=pre_c, post_c=post_c, filter_r=filter_r)
     x, iters, rel, rc = g.solve(b)
     assert rc == B.PAIR_OK
     assert abs(int(iters[0]) - itr) <= 1, (iters[0], itr)
