@@ -112,8 +112,9 @@ __global__ void k_pmis_compare_list(const int32_t* __restrict__ list, const int*
                                     const uint8_t* __restrict__ sflag, const int8_t* __restrict__ state,
                                     const int* __restrict__ lam, const uint16_t* __restrict__ seg,
                                     const int64_t* __restrict__ off, int level, uint64_t seed,
-                                    uint8_t* __restrict__ notmax) {
+                                    uint8_t* __restrict__ notmax, int* __restrict__ next_cnt) {
     const int c = *cnt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next_cnt = 0;   // the next list is built by the mark pass
     const int sub = threadIdx.x & (G - 1);
     const int stride = gridDim.x * (blockDim.x / G);
     for (int k = (blockIdx.x * blockDim.x + threadIdx.x) / G; k < c; k += stride) {
@@ -134,26 +135,21 @@ __global__ void k_pmis_compare_list(const int32_t* __restrict__ list, const int*
     }
 }
 
-__global__ void k_pmis_select_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
-                                   int8_t* __restrict__ state, uint8_t* __restrict__ notmax) {
-    const int c = *cnt;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < c; k += gridDim.x * blockDim.x) {
-        const int32_t i = list[k];
-        if (!notmax[i]) state[i] = ST_C;
-        notmax[i] = 0;   // ready for the next round
-    }
-}
-
-__global__ void k_zero_one(int* p) { *p = 0; }
-
-// Undecided rows with a strong C neighbour become F; the others form the next
-// round's list.  G lanes per row, NT-thread blocks; the loop runs the same
-// number of times on every thread of a block, so all reach block_append.
+// Selection and marking of one round in one pass.  An undecided row that no
+// strong neighbour beat (notmax == 0) becomes C.  Otherwise it becomes F if a
+// strong neighbour is C, either decided earlier or selected in this round
+// (undecided with notmax == 0: its own thread may be writing C at the same
+// time, and either value it reads means C); rows left undecided form the next
+// round's list.  Each row also clears its flag in the other notmax buffer,
+// which the next round's compare pass fills.  G lanes per row, NT-thread
+// blocks; the loop runs the same number of times on every thread of a block,
+// so all reach block_append.
 template <int G, int NT>
 __global__ void __launch_bounds__(NT)
 k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                  const uint8_t* __restrict__ sflag, int8_t* __restrict__ state,
+                 const uint8_t* __restrict__ notmax, uint8_t* __restrict__ notmax_other,
                  int32_t* __restrict__ next, int* __restrict__ next_cnt) {
     constexpr int RPB = NT / G;   // rows per block and iteration
     const int c = *cnt;
@@ -164,22 +160,31 @@ k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
     for (int kb = blockIdx.x * RPB; kb < c; kb += stride) {
         const int k = kb + static_cast<int>(threadIdx.x) / G;
         int32_t i = -1;
-        bool live = false;
+        bool live = false, sel = false;
         if (k < c) {
             i = list[k];
-            live = state[i] == ST_U;
+            live = true;   // every row of the list is undecided at the start of the round
+            sel = notmax[i] == 0;
         }
         bool f = false;
-        if (live) {
+        if (live && !sel) {
             const int64_t re = rowptr[i + 1];
-            for (int64_t e = rowptr[i] + sub; e < re; e += G)
-                if ((sflag[e] & 1) && state[col[e]] == ST_C) { f = true; break; }
+            for (int64_t e = rowptr[i] + sub; e < re; e += G) {
+                if (!(sflag[e] & 1)) continue;
+                const int32_t j = col[e];
+                const int8_t sj = state[j];
+                if (sj == ST_C || (sj == ST_U && notmax[j] == 0)) { f = true; break; }
+            }
         }
         const uint64_t fm = __ballot(f);
         const bool anyf = ((fm >> gbase) & ((G == 64) ? ~0ull : ((1ull << (G & 63)) - 1ull))) != 0;
         const bool lead = live && sub == 0;
-        if (lead && anyf) state[i] = ST_F;
-        const bool keep = lead && !anyf;
+        if (lead) {
+            notmax_other[i] = 0;
+            if (sel) state[i] = ST_C;
+            else if (anyf) state[i] = ST_F;
+        }
+        const bool keep = lead && !sel && !anyf;
         const int slot = block_append<NT>(keep, next_cnt);
         if (keep) next[slot] = i;
     }
@@ -1347,13 +1352,13 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 
         // PMIS: list-driven rounds, host check every few rounds
         DBuf<int8_t> state(n);
-        DBuf<uint8_t> notmax(n);
+        DBuf<uint8_t> notmax(2 * n);   // one flag buffer per round parity
         DBuf<int32_t> plist[2];
         plist[0].alloc(n);
         plist[1].alloc(n);
         DBuf<int> pcnt(2);
         PAIR_HIP(hipMemsetAsync(pcnt.p, 0, 2 * sizeof(int), s_));
-        PAIR_HIP(hipMemsetAsync(notmax.p, 0, n, s_));
+        PAIR_HIP(hipMemsetAsync(notmax.p, 0, 2 * n, s_));
         hipLaunchKernelGGL(k_pmis_init_list, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.seg.p,
                            d_part.p, lam.p, state.p, plist[0].p, pcnt.p);
         PAIR_LAUNCH_CHECK();
@@ -1364,15 +1369,14 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             for (int round = 0;; ++round) {
                 PAIR_CHECK(round < 100000, "PMIS did not terminate");
                 const int nxt = cur ^ 1;
+                uint8_t* nm_cur = notmax.p + (round & 1) * n;
+                uint8_t* nm_other = notmax.p + ((round & 1) ^ 1) * n;
                 hipLaunchKernelGGL(k_pmis_compare_list<8>, dim3(pg), dim3(256), 0, s_, plist[cur].p,
                                    pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p,
-                                   L.seg.p, d_off.p, l, prm_.seed, notmax.p);
-                hipLaunchKernelGGL(k_pmis_select_list, dim3(pg), dim3(256), 0, s_, plist[cur].p,
-                                   pcnt.p + cur, state.p, notmax.p);
-                hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(1), 0, s_, pcnt.p + nxt);
+                                   L.seg.p, d_off.p, l, prm_.seed, nm_cur, pcnt.p + nxt);
                 hipLaunchKernelGGL((k_pmis_mark_list<8, 1024>), dim3(pgm), dim3(1024), 0, s_, plist[cur].p,
-                                   pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p,
-                                   plist[nxt].p, pcnt.p + nxt);
+                                   pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, nm_cur,
+                                   nm_other, plist[nxt].p, pcnt.p + nxt);
                 PAIR_LAUNCH_CHECK();
                 cur = nxt;
                 if (round % 3 == 2) {

@@ -253,23 +253,32 @@ struct EllRow {
     }
 };
 
-// Off-diagonal part of row `row` (element g = row / K) of an element-block
-// operator times x.
+// The three upwind neighbours of element g (-1: none) and their face nodes;
+// loaded up front, independently of the row's other loads.
+struct EllNbr {
+    int32_t u[3], pk[3];
+    __device__ __forceinline__ EllNbr(int64_t g, int64_t nel, const int32_t* __restrict__ nbr,
+                                      const int32_t* __restrict__ nodes) {
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+            u[sl] = nbr[sl * nel + g];
+            pk[sl] = nodes[sl * nel + g];
+        }
+    }
+};
+
+// Off-diagonal part of a row of an element-block operator times x.
 template <int K, int NF>
-__device__ __forceinline__ double ell_offdiag(int64_t row, const EllRow<NF>& er, int64_t nel,
-                                              const int32_t* __restrict__ nbr,
-                                              const int32_t* __restrict__ nodes,
+__device__ __forceinline__ double ell_offdiag(const EllRow<NF>& er, const EllNbr& nb,
                                               const double* __restrict__ x) {
-    const int64_t g = row / K;
     double s = 0.0;
 #pragma unroll
     for (int sl = 0; sl < 3; ++sl) {
-        const int32_t U = nbr[sl * nel + g];
-        if (U < 0) continue;
-        const int pk = nodes[sl * nel + g];
-        const double* xu = x + static_cast<int64_t>(U) * K;
+        if (nb.u[sl] < 0) continue;
+        const double* xu = x + static_cast<int64_t>(nb.u[sl]) * K;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) s += er.v[(sl * NF + j) * er.stride + er.p] * xu[(pk >> (3 * j)) & 7];
+        for (int j = 0; j < NF; ++j)
+            s += er.v[(sl * NF + j) * er.stride + er.p] * xu[(nb.pk[sl] >> (3 * j)) & 7];
     }
     return s;
 }
@@ -287,16 +296,18 @@ k_ell_relax(int64_t n, int64_t nel, int64_t nF, const int32_t* __restrict__ nbr,
             const double* __restrict__ xin, double* __restrict__ xout, double omega, int xin_zero) {
     const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
     if (row >= n) return;
+    // independent loads first (member, class position, neighbours, x_row)
     const int m = seg[row];
-    if (!(active[m] && relax[m])) return;
-    const double xi = xin_zero ? 0.0 : xin[row];
     const EllRow<NF> er(row, n, nF, cmask, fbase, val);
+    const EllNbr nb(row / K, nel, nbr, nodes);
+    const double xi = xin_zero ? 0.0 : xin[row];
+    if (!(active[m] && relax[m])) return;
     if (er.c != (which > 0)) {
         xout[row] = xi;
         return;
     }
     // unit diagonal: (A x)_row = x_row + offdiag
-    const double ax = xin_zero ? 0.0 : xi + ell_offdiag<K, NF>(row, er, nel, nbr, nodes, xin);
+    const double ax = xin_zero ? 0.0 : xi + ell_offdiag<K, NF>(er, nb, xin);
     xout[row] = xi + omega * (b[row] - ax);
 }
 
@@ -311,9 +322,10 @@ k_ell_residual(int64_t n, int64_t nel, int64_t nF, const int32_t* __restrict__ n
     const int64_t row = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
     if (row >= n) return;
     const int m = seg[row];
-    if (!(active[m] && relax[m])) return;
     const EllRow<NF> er(row, n, nF, cmask, fbase, val);
-    r[row] = b[row] - (x[row] + ell_offdiag<K, NF>(row, er, nel, nbr, nodes, x));
+    const EllNbr nb(row / K, nel, nbr, nodes);
+    if (!(active[m] && relax[m])) return;
+    r[row] = b[row] - (x[row] + ell_offdiag<K, NF>(er, nb, x));
 }
 
 template <int K, int NF>
@@ -333,7 +345,8 @@ k_ell_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* 
         const int64_t end = moff[m] + mcnt[m];
         for (int64_t row = begin + threadIdx.x; row < begin + kChunk && row < end; row += kBlock) {
             const EllRow<NF> er(row, n, nF, cmask, fbase, val);
-            const double v = b[row] - (x[row] + ell_offdiag<K, NF>(row, er, nel, nbr, nodes, x));
+            const EllNbr nb(row / K, nel, nbr, nodes);
+            const double v = b[row] - (x[row] + ell_offdiag<K, NF>(er, nb, x));
             acc += v * v;
         }
     }
