@@ -300,6 +300,8 @@ k_cf_counts(int64_t n, const int64_t* __restrict__ rowptr, const int8_t* __restr
     }
 }
 
+// One-point interpolation: the strongest strong C neighbour (largest |a_ij|,
+// then smallest column), one thread per row.
 __global__ void k_interp(int64_t n, const int64_t* __restrict__ rowptr,
                          const int32_t* __restrict__ col, const double* __restrict__ val,
                          const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
@@ -330,20 +332,67 @@ __device__ __forceinline__ bool r_candidate(int64_t i, int32_t j, uint8_t f, con
     return j != i && (f & 2) && cf[j] < 0;
 }
 
-__global__ void k_r_count(int64_t nc, const int32_t* __restrict__ c2f,
-                          const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                          const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
-                          int kmax, int64_t* __restrict__ rcnt) {
-    int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    int64_t i = c2f[I];
+template <int G>
+__global__ void __launch_bounds__(256)
+k_r_count(int64_t nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+          const int32_t* __restrict__ col, const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
+          int kmax, int64_t* __restrict__ rcnt) {
+    const int64_t I = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const int sub = threadIdx.x & (G - 1);
+    if (I >= nc) return;   // uniform within the group
+    const int64_t i = c2f[I];
     int c = 0;
-    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+    for (int64_t e = rowptr[i] + sub; e < rowptr[i + 1]; e += G)
         if (r_candidate(i, col[e], sflag[e], cf)) ++c;
-    rcnt[I] = (c < kmax ? c : kmax) + 1;
+    c = group_sum_int<G>(c);
+    if (sub == 0) rcnt[I] = (c < kmax ? c : kmax) + 1;
 }
 
 constexpr int KCAP = 64;      // largest local system (one wave: lane = row)
+
+// The F points of the local system of C point i (strong R-candidates of row i,
+// at most kmax of them: the largest |a_ij|, ties to the smaller column), in
+// column order, into out[0..K).  Called by every lane of the wave (ballots);
+// lanes of a group whose `have` is false take part without contributing.
+template <int G>
+__device__ __forceinline__ void r_collect(bool have, int64_t i, int64_t rs, int64_t re, int sub, int lane,
+                                          uint64_t gmask, int kmax, const int32_t* __restrict__ col,
+                                          const double* __restrict__ val, const uint8_t* __restrict__ sflag,
+                                          const int8_t* __restrict__ cf, int* out) {
+    // row length bound for uniform loops over the rows' entries
+    int64_t lenw = re - rs;
+    for (int d = 32; d >= 1; d >>= 1) lenw = max(lenw, static_cast<int64_t>(__shfl_xor(lenw, d, 64)));
+    int cnt = 0;
+    for (int64_t e0 = 0; e0 < lenw; e0 += G) {
+        const int64_t e = rs + e0 + sub;
+        const bool cand = have && e < re && r_candidate(i, col[e], sflag[e], cf);
+        cnt += __popcll(__ballot(cand) & gmask);
+    }
+    int filled = 0;
+    for (int64_t e0 = 0; e0 < lenw; e0 += G) {
+        const int64_t e = rs + e0 + sub;
+        bool keep = false;
+        int32_t cj = -1;
+        if (have && e < re) {
+            cj = col[e];
+            keep = r_candidate(i, cj, sflag[e], cf);
+            if (keep && cnt > kmax) {
+                const double a = fabs(val[e]);
+                int rank = 0;
+                for (int64_t q = rs; q < re; ++q) {
+                    if (q == e || !r_candidate(i, col[q], sflag[q], cf)) continue;
+                    const double bq = fabs(val[q]);
+                    if (bq > a || (bq == a && col[q] < cj)) ++rank;
+                }
+                keep = rank < kmax;
+            }
+        }
+        const uint64_t m = __ballot(keep) & gmask;
+        const int pos = filled + __popcll(m & ((1ull << lane) - 1ull));
+        if (keep) out[pos] = cj;
+        filled += __popcll(m);
+    }
+}
 
 // lAIR rows, G lanes per coarse row (G = 8, 16, 32 or 64 >= the row's local system
 // size K), 64 / G rows per wave.  Local system A(R_i,R_i)^T z = -A(i,R_i)^T in
@@ -374,40 +423,7 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         const int64_t i = have ? c2f[I] : 0;
         const int64_t rs = have ? rowptr[i] : 0, re = have ? rowptr[i + 1] : 0;
         const int K = have ? static_cast<int>(r_rowptr[I + 1] - r_rowptr[I]) - 1 : 0;
-        // row length bound for uniform loops over the rows' entries
-        int64_t len = re - rs, lenw = len;
-        for (int d = 32; d >= 1; d >>= 1) lenw = max(lenw, static_cast<int64_t>(__shfl_xor(lenw, d, 64)));
-        // candidates (count, then collect in column order; rank-limited if > kmax)
-        int cnt = 0;
-        for (int64_t e0 = 0; e0 < lenw; e0 += G) {
-            int64_t e = rs + e0 + sub;
-            bool cand = have && e < re && r_candidate(i, col[e], sflag[e], cf);
-            cnt += __popcll(__ballot(cand) & gmask);
-        }
-        int filled = 0;
-        for (int64_t e0 = 0; e0 < lenw; e0 += G) {
-            int64_t e = rs + e0 + sub;
-            bool keep = false;
-            int32_t cj = -1;
-            if (have && e < re) {
-                cj = col[e];
-                keep = r_candidate(i, cj, sflag[e], cf);
-                if (keep && cnt > kmax) {
-                    double a = fabs(val[e]);
-                    int rank = 0;
-                    for (int64_t q = rs; q < re; ++q) {
-                        if (q == e || !r_candidate(i, col[q], sflag[q], cf)) continue;
-                        double bq = fabs(val[q]);
-                        if (bq > a || (bq == a && col[q] < cj)) ++rank;
-                    }
-                    keep = rank < kmax;
-                }
-            }
-            uint64_t m = __ballot(keep) & gmask;
-            int pos = filled + __popcll(m & ((1ull << lane) - 1ull));
-            if (keep) cols[g][pos] = cj;
-            filled += __popcll(m);
-        }
+        r_collect<G>(have, i, rs, re, sub, lane, gmask, kmax, col, val, sflag, cf, cols[g]);
         if (sub == 0) kw[g] = K;
         __syncthreads();
         int Kw = 0;
@@ -543,42 +559,64 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 
 // Filtering of R after its construction (phi_R): in row I (C point i =
 // c2f[I]) an entry j != i stays iff |z_j| >= phi_R * max_{k != i} |z_k|; the
-// entry of i itself always stays.  Count, then copy in column order.
-__global__ void k_r_filter_count(int64_t nc, const int32_t* __restrict__ c2f,
-                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                 const double* __restrict__ val, double phi, int64_t* __restrict__ cnt) {
-    const int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    const int32_t i = c2f[I];
+// entry of i itself always stays.  Count, then copy in column order; G lanes
+// per row.
+template <int G>
+__device__ __forceinline__ double r_filter_threshold(int32_t i, int64_t rs, int64_t re, int sub,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val, double phi) {
     double zmax = 0.0;
-    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
+    for (int64_t e = rs + sub; e < re; e += G)
         if (col[e] != i) zmax = fmax(zmax, fabs(val[e]));
-    const double thr = phi * zmax;
-    int64_t c = 0;
-    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
-        if (col[e] == i || fabs(val[e]) >= thr) ++c;
-    cnt[I] = c;
+    return phi * group_max<G>(zmax);
 }
 
-__global__ void k_r_filter_copy(int64_t nc, const int32_t* __restrict__ c2f,
-                                const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                const double* __restrict__ val, double phi,
-                                const int64_t* __restrict__ nrowptr, int32_t* __restrict__ ncol,
-                                double* __restrict__ nval) {
-    const int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
+template <int G>
+__global__ void __launch_bounds__(256)
+k_r_filter_count(int64_t nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+                 const int32_t* __restrict__ col, const double* __restrict__ val, double phi,
+                 int64_t* __restrict__ cnt) {
+    const int64_t I = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const int sub = threadIdx.x & (G - 1);
+    if (I >= nc) return;   // uniform within the group
     const int32_t i = c2f[I];
-    double zmax = 0.0;
-    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
-        if (col[e] != i) zmax = fmax(zmax, fabs(val[e]));
-    const double thr = phi * zmax;
-    int64_t o = nrowptr[I];
-    for (int64_t e = rowptr[I]; e < rowptr[I + 1]; ++e)
-        if (col[e] == i || fabs(val[e]) >= thr) {
-            ncol[o] = col[e];
-            nval[o] = val[e];
-            ++o;
+    const int64_t rs = rowptr[I], re = rowptr[I + 1];
+    const double thr = r_filter_threshold<G>(i, rs, re, sub, col, val, phi);
+    int c = 0;
+    for (int64_t e = rs + sub; e < re; e += G)
+        if (col[e] == i || fabs(val[e]) >= thr) ++c;
+    c = group_sum_int<G>(c);
+    if (sub == 0) cnt[I] = c;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256)
+k_r_filter_copy(int64_t nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+                const int32_t* __restrict__ col, const double* __restrict__ val, double phi,
+                const int64_t* __restrict__ nrowptr, int32_t* __restrict__ ncol, double* __restrict__ nval) {
+    const int64_t I = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & (G - 1);
+    const uint64_t gmask = ((G == 64) ? ~0ull : ((1ull << (G & 63)) - 1ull)) << (lane & ~(G - 1));
+    const bool have = I < nc;
+    const int32_t i = have ? c2f[I] : -1;
+    const int64_t rs = have ? rowptr[I] : 0, re = have ? rowptr[I + 1] : 0;
+    // the ballots below need every lane of the wave: loop to the wave's longest row
+    int64_t len = re - rs;
+    for (int d = 32; d >= 1; d >>= 1) len = max(len, static_cast<int64_t>(__shfl_xor(len, d, 64)));
+    const double thr = r_filter_threshold<G>(i, rs, re, sub, col, val, phi);
+    int64_t o = have ? nrowptr[I] : 0;
+    for (int64_t e0 = 0; e0 < len; e0 += G) {
+        const int64_t e = rs + e0 + sub;
+        const bool keep = e < re && (col[e] == i || fabs(val[e]) >= thr);
+        const uint64_t m = __ballot(keep) & gmask;
+        if (keep) {
+            const int64_t pos = o + __popcll(m & ((1ull << lane) - 1ull));
+            ncol[pos] = col[e];
+            nval[pos] = val[e];
         }
+        o += __popcll(m);
+    }
 }
 
 // ------------------------------------------------------------- A P and R (A P)
@@ -1452,7 +1490,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 
         // restriction
         DBuf<int64_t> rcnt(total_c);
-        hipLaunchKernelGGL(k_r_count, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
+        hipLaunchKernelGGL(k_r_count<8>, dim3(grid_for(total_c * 8, 256)), dim3(256), 0, s_, total_c,
                            c2f.p, L.A.rowptr.p, L.A.col.p, sflag.p, L.cf.p, prm_.kmax, rcnt.p);
         PAIR_LAUNCH_CHECK();
         L.R.n = total_c;
@@ -1662,7 +1700,7 @@ void Hierarchy::make_fp32_copies() {
 void Hierarchy::filter_restriction(Level& L, const int32_t* c2f, int64_t nc) {
     if (nc == 0) return;
     DBuf<int64_t> cnt(nc);
-    hipLaunchKernelGGL(k_r_filter_count, dim3(grid_for(nc, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
+    hipLaunchKernelGGL(k_r_filter_count<8>, dim3(grid_for(nc * 8, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
                        L.R.col.p, L.R.val.p, prm_.filter_r, cnt.p);
     PAIR_LAUNCH_CHECK();
     Csr F;
@@ -1672,7 +1710,7 @@ void Hierarchy::filter_restriction(Level& L, const int32_t* c2f, int64_t nc) {
     F.nnz = exclusive_scan(cnt.p, F.rowptr.p, nc, s_);
     F.col.alloc(F.nnz);
     F.val.alloc(F.nnz);
-    hipLaunchKernelGGL(k_r_filter_copy, dim3(grid_for(nc, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
+    hipLaunchKernelGGL(k_r_filter_copy<8>, dim3(grid_for(nc * 8, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
                        L.R.col.p, L.R.val.p, prm_.filter_r, F.rowptr.p, F.col.p, F.val.p);
     PAIR_LAUNCH_CHECK();
     L.R = std::move(F);   // the old arrays are reused only on this stream, after the copy
