@@ -199,3 +199,21 @@ def test_error_paths():
     assert rc == B.PAIR_E_NOCONV
     assert np.all(np.isfinite(phi)) and np.linalg.norm(phi) > 0
     s.close()
+
+
+@pytest.mark.parametrize("streams", [1, 3])
+def test_setup_error_in_a_worker_is_reported(streams):
+    """An error raised while a batch is set up on a worker stream (here: a
+    one-level hierarchy whose coarsest level exceeds the dense-solve limit, a
+    host-side check) comes back as an error code and message; the context then
+    works again with valid options."""
+    need_gpu()
+    w = wl.make_config(1, scale=8)          # 4096 DOF per direction > 2048
+    s = solver_for(w, streams=streams, max_levels=1)
+    with pytest.raises(B.PairError) as e:
+        s.transport_sweep(mode=B.PAIR_PLAIN)
+    assert e.value.code == B.PAIR_E_INVALID and "dense limit" in str(e.value)
+    s.set_options(max_levels=25)
+    psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_PLAIN)
+    assert rc == B.PAIR_OK and np.all(np.isfinite(phi))
+    s.close()
