@@ -43,12 +43,13 @@ def log(*a):
 
 
 def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1,
-                coarse_fp32=0, filter_r=0.0):
+                coarse_fp32=0, filter_r=0.0, use_graph=1):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
                relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
-               autotune=1, streams=streams, coarse_fp32=coarse_fp32, filter_r=filter_r)
+               autotune=1, streams=streams, coarse_fp32=coarse_fp32, filter_r=filter_r,
+               use_graph=use_graph)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -217,6 +218,10 @@ def main():
     ap.add_argument("--streams", type=int, default=5,
                     help="direction batches set up and solved at once, one HIP stream each")
     ap.add_argument("--other-streams", type=int, default=8, help="streams for the other mode")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each batch's V-cycle as a captured hipGraph (default: eager "
+                         "launches, equally fast with several worker streams, and every "
+                         "launch of the roofline kernel is then event-timed)")
     ap.add_argument("--filter-r", type=float, default=0.2,
                     help="phi_R: drop R entries below phi_R x the row's largest (0 = keep all)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -247,7 +252,7 @@ def main():
 
     s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                     args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse,
-                    args.streams, filter_r=args.filter_r)
+                    args.streams, filter_r=args.filter_r, use_graph=int(args.graph))
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
     phi64 = timed_steps.last_phi.clone()
@@ -279,7 +284,8 @@ def main():
         # the roofline kernel alone on the GPU: one stream, warm solve
         s1 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, 1, filter_r=args.filter_r)
+                         args.relax_post_coarse, 1, filter_r=args.filter_r,
+                         use_graph=int(args.graph))
         timed_steps(s1, mode, 1, 0, cold=False)
         timed_steps(s1, mode, 1, 0, cold=False, profile=True)
         iso = profile_kinds()["relax_fine"]
@@ -289,7 +295,8 @@ def main():
         other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
         s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, args.other_streams, filter_r=args.filter_r)
+                         args.relax_post_coarse, args.other_streams, filter_r=args.filter_r,
+                         use_graph=int(args.graph))
         osec, ost = timed_steps(s2, other, 1, 0, cold=True)
         wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
         s2.clear_cache()
@@ -309,7 +316,8 @@ def main():
         # optional FP32 operators below the finest level: rate and effect on phi
         s3 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, args.streams, coarse_fp32=1, filter_r=args.filter_r)
+                         args.relax_post_coarse, args.streams, coarse_fp32=1,
+                         filter_r=args.filter_r, use_graph=int(args.graph))
         csec, cst = timed_steps(s3, mode, 1, 1, cold=True)
         phi32 = timed_steps.last_phi
         wsec3, _ = timed_steps(s3, mode, 1, 0, cold=False)
@@ -350,7 +358,8 @@ def main():
                    "tol": 1e-8, "step": "cold sweep replacement: assembly + AIR setup + V-cycles + phi",
                    "relax": "V(%s,%s) Jacobi half-sweeps, coarser levels V(%s,%s)" % (
                        args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse),
-                   "streams": args.streams, "filter_r": args.filter_r, "parallelism": "1 GPU"},
+                   "streams": args.streams, "filter_r": args.filter_r, "graph": bool(args.graph),
+                   "parallelism": "1 GPU"},
         "stats": {"vcycles_total": st["vcycles_total"], "vcycles_max": st["vcycles_max"],
                   "cf_mean": st["cf_mean"], "levels": st["levels_max"],
                   "op_complexity": st["op_complexity"], "assemble_ms": st["t_assemble_ms"],

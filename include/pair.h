@@ -105,6 +105,14 @@ typedef struct pair_options {
                                  phi_R times the largest off-C |r_ik| of their row are
                                  dropped (the C point's own entry stays) — Sec. "SOC
                                  Parameter for Building R"; 0 (default) keeps all      */
+    int fine_factored;        /* 1 (default): on a structured hex mesh, the finest
+                                 level's relaxation, residual and convergence test
+                                 apply the block-scaled operator D_e^{-1} A_eU in
+                                 factored form, from sigma_t and the direction alone
+                                 (no stored values; the same operator up to
+                                 rounding).  Batches with a direction component of
+                                 magnitude <= 1e-12 use the stored form.  0: always
+                                 use the stored element-block values                  */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

@@ -82,6 +82,17 @@ struct Csr {
 // so that a half-sweep over one class reads only that class's cache lines.
 // cmask[w] has bit i set if row 64w+i is a C point and fbase[w] counts the F
 // rows before row 64w, which gives a row's position within its class.
+//
+// Factored form (structured hex meshes, factored = true): no values, neighbour
+// lists or node lists are stored.  With M the Q1 mass matrix, the element
+// matrix is D_e = V M [sigma_t I + T_x (+) T_y (+) T_z] (a Kronecker sum of
+// one-dimensional 2 x 2 operators T_d = |Omega_d|/h_d * T_+-), and an upwind
+// block is D_e^{-1} A_eU = [.]^{-1} (-|Omega_d|/h_d) (M1^{-1} E) (x) I (x) I, so a
+// row of the scaled operator follows from sigma_t of the element, kap_d =
+// |Omega_d|/h_d and the inflow side of each axis (see hex_offdiag).  Members are
+// the directions of a batch, member b on rows [b*8E, (b+1)*8E).  Requires every
+// |Omega_d| above the zero-flux tolerance (otherwise T_d is not diagonalisable
+// and the stored form is used).
 struct FineEll {
     int k = 0, nf = 0;
     int64_t nel = 0, nrows = 0;
@@ -91,6 +102,13 @@ struct FineEll {
     int64_t nF = 0;
     DBuf<uint64_t> cmask;
     DBuf<int64_t> fbase;
+    // factored structured-hex form
+    bool factored = false;
+    int nx = 0, ny = 0, nz = 0;
+    int64_t E = 0;                 // elements per member
+    DBuf<double> kap;              // [member][3] |Omega_d| / h_d
+    DBuf<int32_t> inflow;          // [member] bit d set: inflow through the high face (Omega_d < 0)
+    DBuf<double> sigt;             // [E] sigma_t per element
 };
 
 struct Level {

@@ -360,6 +360,266 @@ k_ell_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* 
     }
 }
 
+// ---------------------------------------------------------------- finest level, factored hexes
+// Off-diagonal part y = D_e^{-1} sum_U A_eU x_U of the rows of element g of a
+// structured hex mesh (member element e; node a = a_x + 2 a_y + 4 a_z), from
+// sigma_t of the element and its direction's kap_d = |Omega_d| / h_d and
+// inflow sides s_d (bit d of `in`: 1 when Omega_d < 0, inflow through the high
+// face).  Derivation (Q1 hexes, 2-point Gauss rules, M1 = [1/3 1/6; 1/6 1/3]):
+//   D_e = V (M1 (x) M1 (x) M1) [sigma_t I + T_x (+) T_y (+) T_z],
+//   T_d = kap_d M1^{-1}(-sgn(Omega_d) G1 + E_out) = kap_d [3 1; -3 1] (Omega_d > 0,
+//         mirrored for Omega_d < 0),  eigenvalues kap_d (2 +- i sqrt2),
+//   D_e^{-1} A_eU x_U = [.]^{-1} g,  g_a = -kap_d M1^{-1}[a_d][s_d] x_U(a with
+//         bit d on U's shared face),  M1^{-1} = [4 -2; -2 4].
+// The Kronecker-sum system is solved in the product eigenbasis: W^{-1} along
+// z, y, x, a division by sigma_t + sum of eigenvalues, W along x, y, z.  The
+// transform of a real vector is conjugate-symmetric, so the four coefficients
+// with the z eigen-index 0 carry it all (y = 2 Re of their back-transform).
+struct HexDir {
+    double kap[3];
+    int in;
+};
+
+__device__ __forceinline__ void hex_offdiag(int64_t g, uint32_t e, int nx, int ny, int nz, double sig,
+                                            const HexDir& dr, const double* __restrict__ x, double y[8]) {
+    constexpr double kS2 = 1.4142135623730950488;      // sqrt 2
+    constexpr double kC = 0.35355339059327376220;      // 1 / (2 sqrt 2)
+    const int sx = dr.in & 1, sy = (dr.in >> 1) & 1, sz = (dr.in >> 2) & 1;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * static_cast<uint32_t>(ny);
+    const uint32_t k = e / nxy, rem = e - k * nxy;
+    const uint32_t j = rem / static_cast<uint32_t>(nx), i = rem - j * static_cast<uint32_t>(nx);
+    // upwind face values: v_d[t], t the node index with bit d removed
+    double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0}, v2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (sx ? (i + 1 < static_cast<uint32_t>(nx)) : (i > 0)) {
+        const double* xu = x + (g + (sx ? 1 : -1)) * 8 + (1 - sx);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v0[t] = xu[2 * t];
+    }
+    if (sy ? (j + 1 < static_cast<uint32_t>(ny)) : (j > 0)) {
+        const double2* xu = reinterpret_cast<const double2*>(
+            x + (g + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
+        const double2 lo = xu[0], hi = xu[2];
+        v1[0] = lo.x; v1[1] = lo.y; v1[2] = hi.x; v1[3] = hi.y;
+    }
+    if (sz ? (k + 1 < static_cast<uint32_t>(nz)) : (k > 0)) {
+        const int64_t st = static_cast<int64_t>(nxy);
+        const double2* xu = reinterpret_cast<const double2*>(x + (g + (sz ? st : -st)) * 8 + 4 * (1 - sz));
+        const double2 lo = xu[0], hi = xu[1];
+        v2[0] = lo.x; v2[1] = lo.y; v2[2] = hi.x; v2[3] = hi.y;
+    }
+    // g = sum_d -kap_d M1^{-1}[a_d][s_d] v_d
+    double al[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int sd = (dr.in >> d) & 1;
+        al[d][0] = sd == 0 ? -4.0 * dr.kap[d] : 2.0 * dr.kap[d];
+        al[d][1] = sd == 1 ? -4.0 * dr.kap[d] : 2.0 * dr.kap[d];
+    }
+    double gv[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+        gv[a] = al[0][ax] * v0[ay + 2 * az] + al[1][ay] * v1[ax + 2 * az] + al[2][az] * v2[ax + 2 * ay];
+    }
+    // W^{-1} along z (row 0: 1/2 on the inflow-side node, -i C on both)
+    double ur[2][2], ui[2][2];
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax)
+#pragma unroll
+        for (int ay = 0; ay < 2; ++ay) {
+            const double lo = gv[ax + 2 * ay], hi = gv[ax + 2 * ay + 4];
+            ur[ax][ay] = 0.5 * (sz ? hi : lo);
+            ui[ax][ay] = -kC * (lo + hi);
+        }
+    // along y: both eigen-indices (row 1 is the conjugate of row 0)
+    double vr[2][2], vi[2][2];
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        const double hr = 0.5 * (sy ? ur[ax][1] : ur[ax][0]), hi = 0.5 * (sy ? ui[ax][1] : ui[ax][0]);
+        const double sr = ur[ax][0] + ur[ax][1], si = ui[ax][0] + ui[ax][1];
+        vr[ax][0] = hr + kC * si; vi[ax][0] = hi - kC * sr;
+        vr[ax][1] = hr - kC * si; vi[ax][1] = hi + kC * sr;
+    }
+    // along x
+    double gr[2][2], gi[2][2];
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+        const double hr = 0.5 * (sx ? vr[1][ey] : vr[0][ey]), hi = 0.5 * (sx ? vi[1][ey] : vi[0][ey]);
+        const double sr = vr[0][ey] + vr[1][ey], si = vi[0][ey] + vi[1][ey];
+        gr[0][ey] = hr + kC * si; gi[0][ey] = hi - kC * sr;
+        gr[1][ey] = hr - kC * si; gi[1][ey] = hi + kC * sr;
+    }
+    // divide by sigma_t + kap_x lam_ex + kap_y lam_ey + kap_z lam_0, lam = 2 +- i sqrt2
+    const double mr = sig + 2.0 * (dr.kap[0] + dr.kap[1] + dr.kap[2]);
+    double zr[2][2], zi[2][2];
+#pragma unroll
+    for (int ex = 0; ex < 2; ++ex)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey) {
+            const double mi = kS2 * ((ex ? -dr.kap[0] : dr.kap[0]) + (ey ? -dr.kap[1] : dr.kap[1]) + dr.kap[2]);
+            const double inv = 1.0 / (mr * mr + mi * mi);
+            zr[ex][ey] = (gr[ex][ey] * mr + gi[ex][ey] * mi) * inv;
+            zi[ex][ey] = (gi[ex][ey] * mr - gr[ex][ey] * mi) * inv;
+        }
+    // W along x (column 0: 1 on the inflow-side node, -1 + i sqrt2 on the other)
+    double pr[2][2], pi[2][2];
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+        const double sr = zr[0][ey] + zr[1][ey], si = zi[0][ey] + zi[1][ey];
+        const double dre = zr[0][ey] - zr[1][ey], dim = zi[0][ey] - zi[1][ey];
+        const double orr = -sr - kS2 * dim, oi = -si + kS2 * dre;
+        pr[0][ey] = sx ? orr : sr; pi[0][ey] = sx ? oi : si;
+        pr[1][ey] = sx ? sr : orr; pi[1][ey] = sx ? si : oi;
+    }
+    // along y
+    double qr[2][2], qi[2][2];
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        const double sr = pr[ax][0] + pr[ax][1], si = pi[ax][0] + pi[ax][1];
+        const double dre = pr[ax][0] - pr[ax][1], dim = pi[ax][0] - pi[ax][1];
+        const double orr = -sr - kS2 * dim, oi = -si + kS2 * dre;
+        qr[ax][0] = sy ? orr : sr; qi[ax][0] = sy ? oi : si;
+        qr[ax][1] = sy ? sr : orr; qi[ax][1] = sy ? si : oi;
+    }
+    // along z, real part doubled
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax)
+#pragma unroll
+        for (int ay = 0; ay < 2; ++ay) {
+            const double same = 2.0 * qr[ax][ay];
+            const double other = -2.0 * (qr[ax][ay] + kS2 * qi[ax][ay]);
+            y[ax + 2 * ay] = sz ? other : same;
+            y[ax + 2 * ay + 4] = sz ? same : other;
+        }
+}
+
+__device__ __forceinline__ HexDir load_hex_dir(uint32_t m, const double* __restrict__ kap,
+                                               const int32_t* __restrict__ inflow) {
+    HexDir d;
+    d.kap[0] = kap[3 * m];
+    d.kap[1] = kap[3 * m + 1];
+    d.kap[2] = kap[3 * m + 2];
+    d.in = inflow[m];
+    return d;
+}
+
+__device__ __forceinline__ void load8(const double* __restrict__ p, double v[8]) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 t = q[i];
+        v[2 * i] = t.x;
+        v[2 * i + 1] = t.y;
+    }
+}
+
+__device__ __forceinline__ void store8(double* __restrict__ p, const double v[8]) {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+
+// One half-sweep of a factored hex operator, a thread per element: rows of the
+// class `which` (F: -1, C: +1, per cmask) get x + omega (b - A x), the others
+// keep x.  Member m's elements are [m E, (m+1) E).
+__global__ void __launch_bounds__(kBlock)
+k_hex_relax(int64_t nel, uint32_t E, int nx, int ny, int nz, const double* __restrict__ kap,
+            const int32_t* __restrict__ inflow, const double* __restrict__ sigt,
+            const uint64_t* __restrict__ cmask, int8_t which, const uint8_t* __restrict__ active,
+            const uint8_t* __restrict__ relax, const double* __restrict__ b,
+            const double* __restrict__ xin, double* __restrict__ xout, double omega, int xin_zero) {
+    const int64_t g = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
+    if (g >= nel) return;
+    const uint32_t m = static_cast<uint32_t>(g) / E;
+    if (!(active[m] && relax[m])) return;
+    const uint32_t e = static_cast<uint32_t>(g) - m * E;
+    const uint32_t cm = static_cast<uint32_t>(cmask[g >> 3] >> (8 * (g & 7))) & 0xffu;
+    const uint32_t rel = which > 0 ? cm : (~cm & 0xffu);
+    double xo[8];
+    if (xin_zero) {
+        if (rel == 0) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a) xo[a] = 0.0;
+        } else {
+            double bv[8];
+            load8(b + g * 8, bv);
+#pragma unroll
+            for (int a = 0; a < 8; ++a) xo[a] = ((rel >> a) & 1u) ? omega * bv[a] : 0.0;
+        }
+        store8(xout + g * 8, xo);
+        return;
+    }
+    double xv[8];
+    load8(xin + g * 8, xv);
+    if (rel == 0) {
+        store8(xout + g * 8, xv);
+        return;
+    }
+    const HexDir dr = load_hex_dir(m, kap, inflow);
+    const double sig = sigt[e];
+    double bv[8], y[8];
+    load8(b + g * 8, bv);
+    hex_offdiag(g, e, nx, ny, nz, sig, dr, xin, y);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+        xo[a] = ((rel >> a) & 1u) ? xv[a] + omega * (bv[a] - (xv[a] + y[a])) : xv[a];
+    store8(xout + g * 8, xo);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_hex_residual(int64_t nel, uint32_t E, int nx, int ny, int nz, const double* __restrict__ kap,
+               const int32_t* __restrict__ inflow, const double* __restrict__ sigt,
+               const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
+               const double* __restrict__ b, const double* __restrict__ x, double* __restrict__ r) {
+    const int64_t g = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x;
+    if (g >= nel) return;
+    const uint32_t m = static_cast<uint32_t>(g) / E;
+    if (!(active[m] && relax[m])) return;
+    const uint32_t e = static_cast<uint32_t>(g) - m * E;
+    const HexDir dr = load_hex_dir(m, kap, inflow);
+    const double sig = sigt[e];
+    double xv[8], bv[8], y[8], rv[8];
+    load8(x + g * 8, xv);
+    load8(b + g * 8, bv);
+    hex_offdiag(g, e, nx, ny, nz, sig, dr, x, y);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) rv[a] = bv[a] - (xv[a] + y[a]);
+    store8(r + g * 8, rv);
+}
+
+// Partial sums of |b - A x|^2 per (member, chunk of kChunk rows): one wave per
+// chunk, a thread per element, fixed reduction order.
+__global__ void __launch_bounds__(64)
+k_hex_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* __restrict__ mcnt,
+                   uint32_t E, int nx, int ny, int nz, const double* __restrict__ kap,
+                   const int32_t* __restrict__ inflow, const double* __restrict__ sigt,
+                   const uint8_t* __restrict__ active, const double* __restrict__ b,
+                   const double* __restrict__ x, double* __restrict__ partial) {
+    static_assert(kChunk == 8 * 64, "one element per lane");
+    const int m = blockIdx.y;
+    const int chunk = blockIdx.x;
+    double acc = 0.0;
+    if (moff[m] >= 0 && active[m]) {
+        const int64_t row = moff[m] + static_cast<int64_t>(chunk) * kChunk + 8 * threadIdx.x;
+        if (row < moff[m] + mcnt[m]) {
+            const int64_t g = row >> 3;
+            const uint32_t e = static_cast<uint32_t>((row - moff[m]) >> 3);
+            const HexDir dr = load_hex_dir(static_cast<uint32_t>(m), kap, inflow);
+            double xv[8], bv[8], y[8];
+            load8(x + g * 8, xv);
+            load8(b + g * 8, bv);
+            hex_offdiag(g, e, nx, ny, nz, sigt[e], dr, x, y);
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const double v = bv[a] - (xv[a] + y[a]);
+                acc += v * v;
+            }
+        }
+    }
+    acc = group_sum<64>(acc);
+    if (threadIdx.x == 0) partial[static_cast<int64_t>(m) * chunks + chunk] = acc;
+}
+
 // Class masks of the finest level: one wave per 64 rows.
 __global__ void __launch_bounds__(256)
 k_ell_cmask(int64_t n, const int8_t* __restrict__ cf, uint64_t* __restrict__ cmask,
@@ -393,16 +653,25 @@ void dispatch_ell(const FineEll& e, F&& f) {
     else f(std::integral_constant<int, 4>(), std::integral_constant<int, 3>());
 }
 
-// Per row: 2 B member id, 1/4 B of class mask and base (16 B per 64 rows).
+// Stored form, per row: 2 B member id, 1/4 B of class mask and base (16 B per
+// 64 rows).  Factored form: b of the relaxed rows, x in and out (each entry
+// once), sigma_t per element and the class mask (1/8 B per row); the
+// per-direction data are negligible.
 double ell_relax_bytes(const Level& L, const FineEll& e, int which, bool zero) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     const double nr = static_cast<double>(which < 0 ? L.n_f : L.n_c);
+    if (e.factored) {
+        if (zero) return 8.0 * nr + 8.0 * n + n / 8.0;
+        return 8.0 * nr + 16.0 * n + 8.0 * static_cast<double>(e.nel) + n / 8.0;
+    }
     if (zero) return 8.0 * nr + n * (8.0 + 2.25);
     return nr * (24.0 * e.nf + 8.0) + n * (8.0 + 8.0 + 2.25) + 24.0 * static_cast<double>(e.nel);
 }
 
+// r = b - A x (the convergence test reads the same without writing r)
 double ell_residual_bytes(const Level& L, const FineEll& e) {
     const double n = static_cast<double>(L.n_f + L.n_c);
+    if (e.factored) return 24.0 * n + 8.0 * static_cast<double>(e.nel);
     return n * (24.0 * e.nf + 8.0 + 8.0 + 8.0 + 2.25) + 24.0 * static_cast<double>(e.nel);
 }
 
@@ -482,7 +751,14 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
         const int8_t which = ch == 'F' ? -1 : 1;
         if (l == 0 && ell_) {
             const FineEll& E = *ell_;
-            dispatch_ell(E, [&](auto kc, auto fc) {
+            if (E.factored) {
+                int h = prof_begin(s_, kind);
+                hipLaunchKernelGGL(k_hex_relax, dim3(grid_xcd(E.nel, kBlock)), dim3(kBlock), 0, s_, E.nel,
+                                   static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, E.kap.p, E.inflow.p,
+                                   E.sigt.p, E.cmask.p, which, act, L.relax.p, L.b.p, cur, other,
+                                   prm_.omega, zero ? 1 : 0);
+                prof_end(s_, h, ell_relax_bytes(L, E, which, zero));
+            } else dispatch_ell(E, [&](auto kc, auto fc) {
                 constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
                 int h = prof_begin(s_, kind);
                 hipLaunchKernelGGL((k_ell_relax<K, NF>), dim3(grid_xcd(n, kBlock)), dim3(kBlock), 0, s_,
@@ -543,7 +819,14 @@ void Hierarchy::vcycle_launches(bool x_is_zero) {
             PAIR_LAUNCH_CHECK();
         }
         cur[l] = sweeps(L, l, pre, L.x.p, L.t.p, zero);
-        if (l == 0 && ell_) {
+        if (l == 0 && ell_ && ell_->factored) {
+            const FineEll& E = *ell_;
+            int h = prof_begin(s_, PROF_RESIDUAL_FINE);
+            hipLaunchKernelGGL(k_hex_residual, dim3(grid_xcd(E.nel, kBlock)), dim3(kBlock), 0, s_, E.nel,
+                               static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, E.kap.p, E.inflow.p,
+                               E.sigt.p, act, L.relax.p, L.b.p, cur[l], L.r.p);
+            prof_end(s_, h, ell_residual_bytes(L, E));
+        } else if (l == 0 && ell_) {
             const FineEll& E = *ell_;
             dispatch_ell(E, [&](auto kc, auto fc) {
                 constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
@@ -617,6 +900,10 @@ void Hierarchy::set_fine_ell(std::shared_ptr<FineEll> e) {
     hipLaunchKernelGGL(k_ell_cmask, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L0.cf.p, E.cmask.p, fcnt.p);
     PAIR_LAUNCH_CHECK();
     E.nF = exclusive_scan(fcnt.p, E.fbase.p, nb, s_);
+    if (E.factored) {   // no stored values to regroup
+        E.split = true;
+        return;
+    }
     DBuf<double> nv(E.val.n);
     dispatch_ell(E, [&](auto, auto fc) {
         constexpr int NF = decltype(fc)::value;
@@ -713,7 +1000,14 @@ void Hierarchy::launch_cycle_and_test(bool x_is_zero, int /*it_offset*/) {
     Level& L0 = levels_[0];
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sb_.n_active.p);
     vcycle_launches(x_is_zero);
-    if (ell_) {
+    if (ell_ && ell_->factored) {
+        const FineEll& E = *ell_;
+        int h = prof_begin(s_, PROF_NORM_FINE);
+        hipLaunchKernelGGL(k_hex_norm_partial, dim3(sb_.chunks, B_), dim3(64), 0, s_, sb_.chunks,
+                           moff_d_.p, mcnt_d_.p, static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, E.kap.p,
+                           E.inflow.p, E.sigt.p, sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+        prof_end(s_, h, ell_residual_bytes(L0, E) - 8.0 * L0.A.n);
+    } else if (ell_) {
         const FineEll& E = *ell_;
         dispatch_ell(E, [&](auto kc, auto fc) {
             constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;

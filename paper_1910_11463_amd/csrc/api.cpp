@@ -97,6 +97,7 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.streams >= 1 && o.streams <= 16, "streams must be in [1, 16]");
     PAIR_CHECK(o.fixed_cycles >= 0 && o.fixed_cycles <= 10000, "fixed_cycles must be in [0, 10000]");
     PAIR_CHECK(o.filter_r >= 0.0 && o.filter_r <= 1.0, "filter_r must be in [0, 1]");
+    PAIR_CHECK(o.fine_factored == 0 || o.fine_factored == 1, "fine_factored must be 0 or 1");
     auto sched_ok = [](const char* c) {
         size_t n = strnlen(c, 8);
         if (n >= 8) return false;
@@ -203,6 +204,7 @@ void pair_default_options(pair_options* o) {
     o->coarse_fp32 = 0;
     o->fixed_cycles = 0;
     o->filter_r = 0.0;
+    o->fine_factored = 1;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
@@ -242,6 +244,7 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
             opt->kmax != c.opt.kmax || opt->pmis_seed != c.opt.pmis_seed ||
             opt->batch_size != c.opt.batch_size || opt->streams != c.opt.streams ||
             opt->coarse_fp32 != c.opt.coarse_fp32 || opt->filter_r != c.opt.filter_r ||
+            opt->fine_factored != c.opt.fine_factored ||
             std::strncmp(opt->relax_pre, c.opt.relax_pre, 8) != 0 ||
             std::strncmp(opt->relax_post, c.opt.relax_post, 8) != 0 ||
             std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, 8) != 0 ||

@@ -358,7 +358,8 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
     const int64_t row_g = static_cast<int64_t>(b) * N + 8 * e + a;
     const int64_t coff = static_cast<int64_t>(b) * N;
     const int64_t nrows = N * B, nel = E * B;
-    if (a == 0) {
+    const bool ell = ell_val != nullptr;   // no element-block copy for the factored form
+    if (ell && a == 0) {
         for (int sl = 0; sl < 3; ++sl) {
             ell_nbr[sl * nel + g] = -1;
             ell_nodes[sl * nel + g] = 0;
@@ -372,7 +373,8 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
             ell_nodes[ax * nel + g] = packed;
         }
     }
-    for (int j = 0; j < 12; ++j) ell_val[j * nrows + row_g] = 0.0;
+    if (ell)
+        for (int j = 0; j < 12; ++j) ell_val[j * nrows + row_g] = 0.0;
     const int64_t rb = elem_off[g] + static_cast<int64_t>(a) * L;
     rowptr[row_g] = rb;
     int pos = 0;
@@ -392,7 +394,7 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
             for (int c = 0; c < 8; ++c) sv += Di[c] * (F.odn * ref[REF_X + F.face * 64 + c * 8 + cu]);
             col[rb + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
             val[rb + pos] = sv;
-            ell_val[(ax * 4 + j) * nrows + row_g] = sv;
+            if (ell) ell_val[(ax * 4 + j) * nrows + row_g] = sv;
             ++pos;
             ++j;
         }
@@ -656,13 +658,16 @@ void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d
                    const double* sigt, const int64_t* elem_off, int64_t total_nnz, int64_t* rowptr,
                    int32_t* col, double* val, double* dinv, FineEll& ell, hipStream_t s) {
     const int nf = m.kind == PAIR_HEX8 ? 4 : 3;
+    PAIR_CHECK(!ell.factored || m.kind == PAIR_HEX8, "factored form needs a structured hex mesh");
     ell.k = m.k;
     ell.nf = nf;
     ell.nel = m.E * B;
     ell.nrows = m.n_dof() * B;
-    ell.nbr.alloc(3 * ell.nel);
-    ell.nodes.alloc(3 * ell.nel);
-    ell.val.alloc(static_cast<size_t>(3 * nf) * ell.nrows);
+    if (!ell.factored) {
+        ell.nbr.alloc(3 * ell.nel);
+        ell.nodes.alloc(3 * ell.nel);
+        ell.val.alloc(static_cast<size_t>(3 * nf) * ell.nrows);
+    }
     DBuf<int> bad(1);
     PAIR_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
     if (m.kind == PAIR_HEX8)

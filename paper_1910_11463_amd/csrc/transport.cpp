@@ -100,8 +100,36 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     A.val.alloc(nnz);
     bt.dinv.alloc(static_cast<size_t>(B) * E * mesh.k * mesh.k);
     bt.ell = std::make_shared<FineEll>();
+    FineEll& fe = *bt.ell;
+    // factored finest-level operator: structured hexes, every |Omega_d| > tol
+    bool fact = opt.fine_factored && mesh.kind == PAIR_HEX8;
+    for (int m : bt.dirs)
+        for (int d = 0; d < 3; ++d) fact = fact && std::fabs(omega_h[3 * m + d]) > kZeroFluxTol;
+    std::vector<double> kap;      // host sources of the copies below: kept until the
+    std::vector<int32_t> in;      // stream synchronisation at the end of fine_assemble
+    if (fact) {
+        kap.assign(3 * B, 0.0);
+        in.assign(B, 0);
+        for (int b = 0; b < B; ++b)
+            for (int d = 0; d < 3; ++d) {
+                const double o = omega_h[3 * bt.dirs[b] + d];
+                kap[3 * b + d] = std::fabs(o) / mesh.h[d];
+                if (o < 0.0) in[b] |= 1 << d;
+            }
+        fe.factored = true;
+        fe.nx = mesh.nx;
+        fe.ny = mesh.ny;
+        fe.nz = mesh.nz;
+        fe.E = E;
+        fe.kap.alloc(3 * B);
+        fe.inflow.alloc(B);
+        fe.sigt.alloc(E);
+        h2d(fe.kap.p, kap.data(), 3 * B, s);
+        h2d(fe.inflow.p, in.data(), B, s);
+        PAIR_HIP(hipMemcpyAsync(fe.sigt.p, sigt.p, E * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     fine_assemble(mesh, omega_d.p, dirs_d.p, B, sigt.p, eoff.p, nnz, A.rowptr.p, A.col.p, A.val.p,
-                  bt.dinv.p, *bt.ell, s);
+                  bt.dinv.p, fe, s);
     if (t_assemble_ms) *t_assemble_ms += now_ms() - t0;
     return A;
 }

@@ -41,7 +41,7 @@ def test_default_options():
     assert (o.lair_distance, o.theta, o.eps_r, o.omega) == (1, 0.25, 0.01, 1.0)
     assert (o.coarse_max, o.max_levels, o.kmax) == (64, 25, 64)
     assert o.tol_inner == 1e-8 and o.max_inner == 100
-    assert o.streams == 1 and o.coarse_fp32 == 0
+    assert o.streams == 1 and o.coarse_fp32 == 0 and o.fine_factored == 1
 
 
 def test_quadrature_matches_oracle():
