@@ -34,7 +34,7 @@ METRIC = "DOF·dirs/s to 1e-8 residual, batched vs per-direction pAIR; % HBM pea
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE + WRITE_SIZE of the roofline kernel, scaled by a copy
 # kernel of known size; valid only for the kernel source it was measured on
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ell_relax_hex64_s8_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hex_relax_hex64_s8_traffic.txt")
 ROOFLINE_SRC = os.path.join(ROOT, "paper_1910_11463_amd", "csrc", "amg_solve.hip")
 
 
@@ -194,7 +194,8 @@ def source_iteration_time(cfg, device, streams):
     dt = time.perf_counter() - t0
     s.close()
     return {"workload": w.name, "seconds": dt, "outer_iters": st["outer_iters"],
-            "vcycles_total": st["vcycles_total"], "converged": rc == B.PAIR_OK}
+            "vcycles_total": st["vcycles_total"], "converged": rc == B.PAIR_OK,
+            "relax": "V(FFCF,FFCF), coarser levels V(F,F)", "tol_inner": 1e-9}
 
 
 def main():
@@ -211,8 +212,8 @@ def main():
     ap.add_argument("--cpu-dirs", type=int, default=80)
     ap.add_argument("--si", default="1,3", help="workloads whose full source iteration is timed "
                     "(extra.source_iteration); empty for none")
-    ap.add_argument("--relax-pre", default="FFCF")
-    ap.add_argument("--relax-post", default="FFCF")
+    ap.add_argument("--relax-pre", default="FCFCFCFCFCFCF")
+    ap.add_argument("--relax-post", default="FCFCFCFCFCFCF")
     ap.add_argument("--relax-pre-coarse", default="F")
     ap.add_argument("--relax-post-coarse", default="F")
     ap.add_argument("--streams", type=int, default=5,
@@ -338,7 +339,7 @@ def main():
     copy_gbs = copy_bandwidth()
     roofline = {"bound": "hbm", "achieved": relax["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": relax["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_ell_relax<8,4> (finest-level F/C Jacobi half-sweeps)",
+                "kernel": "k_hex_relax (finest-level F/C Jacobi half-sweeps, factored hex operator)",
                 "launches": relax["launches"], "avg_us": relax["avg_us"],
                 "bytes_per_launch": relax["bytes"] / max(1, relax["launches"]),
                 "traffic_gbs": traffic / (relax["avg_us"] * 1e-6) / 1e9 if traffic else None,

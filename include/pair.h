@@ -77,13 +77,14 @@ typedef struct pair_options {
     int batch_size;           /* directions per batch in PAIR_BATCHED, 0 = all  */
     int use_graph;            /* capture batched V-cycles in a hipGraph (1)     */
     int allow_any_weight_sum; /* accept quadrature weights not summing to 4 pi  */
-    char relax_pre[8];        /* pre-smoothing half-sweeps, e.g. "FC" (default) */
-    char relax_post[8];       /* post-smoothing half-sweeps, e.g. "FC"; "FFC" = two
+    char relax_pre[16];       /* pre-smoothing half-sweeps, e.g. "FC" (default); up
+                                 to 15 characters from {F, C}                      */
+    char relax_post[16];      /* post-smoothing half-sweeps, e.g. "FC"; "FFC" = two
                                  Jacobi sweeps over F-points, then one over C-points */
     int autotune;             /* 1: time the row kernels of each level once per context
                                  and keep the fastest lanes-per-row (0: fixed table)  */
-    char relax_pre_coarse[8]; /* schedules on the coarser levels; "=" (default) means */
-    char relax_post_coarse[8];/* the same as on the finest level                     */
+    char relax_pre_coarse[16];  /* schedules on the coarser levels; "=" (default)   */
+    char relax_post_coarse[16]; /* means the same as on the finest level            */
     int streams;              /* plain/batched sweeps: number of direction batches set
                                  up and solved at once, each on its own HIP stream
                                  driven by its own host thread (default 1).  Results

@@ -36,9 +36,9 @@ class pair_options(ctypes.Structure):
                 ("max_outer", c_int), ("outer_estimate", c_int), ("keep_psi", c_int),
                 ("keep_hierarchy", c_int), ("warm_start", c_int), ("batch_size", c_int),
                 ("use_graph", c_int), ("allow_any_weight_sum", c_int),
-                ("relax_pre", ctypes.c_char * 8), ("relax_post", ctypes.c_char * 8),
+                ("relax_pre", ctypes.c_char * 16), ("relax_post", ctypes.c_char * 16),
                 ("autotune", c_int),
-                ("relax_pre_coarse", ctypes.c_char * 8), ("relax_post_coarse", ctypes.c_char * 8),
+                ("relax_pre_coarse", ctypes.c_char * 16), ("relax_post_coarse", ctypes.c_char * 16),
                 ("streams", c_int), ("coarse_fp32", c_int), ("fixed_cycles", c_int),
                 ("filter_r", c_double), ("fine_factored", c_int)]
 

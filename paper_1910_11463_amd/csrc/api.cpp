@@ -98,19 +98,20 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.fixed_cycles >= 0 && o.fixed_cycles <= 10000, "fixed_cycles must be in [0, 10000]");
     PAIR_CHECK(o.filter_r >= 0.0 && o.filter_r <= 1.0, "filter_r must be in [0, 1]");
     PAIR_CHECK(o.fine_factored == 0 || o.fine_factored == 1, "fine_factored must be 0 or 1");
-    auto sched_ok = [](const char* c) {
-        size_t n = strnlen(c, 8);
-        if (n >= 8) return false;
+    constexpr size_t kS = sizeof(o.relax_pre);
+    auto sched_ok = [&](const char* c) {
+        size_t n = strnlen(c, kS);
+        if (n >= kS) return false;
         for (size_t i = 0; i < n; ++i)
             if (c[i] != 'F' && c[i] != 'C') return false;
         return true;
     };
     PAIR_CHECK(sched_ok(o.relax_pre) && sched_ok(o.relax_post),
-               "relax_pre / relax_post: up to 7 characters from {F, C}");
-    auto coarse_ok = [&](const char* c) { return std::strncmp(c, "=", 8) == 0 || sched_ok(c); };
+               "relax_pre / relax_post: up to 15 characters from {F, C}");
+    auto coarse_ok = [&](const char* c) { return std::strncmp(c, "=", kS) == 0 || sched_ok(c); };
     PAIR_CHECK(coarse_ok(o.relax_pre_coarse) && coarse_ok(o.relax_post_coarse),
-               "relax_pre_coarse / relax_post_coarse: \"=\" or up to 7 characters from {F, C}");
-    PAIR_CHECK(strnlen(o.relax_pre, 8) + strnlen(o.relax_post, 8) >= 1, "no relaxation at all");
+               "relax_pre_coarse / relax_post_coarse: \"=\" or up to 15 characters from {F, C}");
+    PAIR_CHECK(strnlen(o.relax_pre, kS) + strnlen(o.relax_post, kS) >= 1, "no relaxation at all");
 }
 
 hipStream_t make_stream(void* user, bool& own) {
@@ -245,10 +246,10 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
             opt->batch_size != c.opt.batch_size || opt->streams != c.opt.streams ||
             opt->coarse_fp32 != c.opt.coarse_fp32 || opt->filter_r != c.opt.filter_r ||
             opt->fine_factored != c.opt.fine_factored ||
-            std::strncmp(opt->relax_pre, c.opt.relax_pre, 8) != 0 ||
-            std::strncmp(opt->relax_post, c.opt.relax_post, 8) != 0 ||
-            std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, 8) != 0 ||
-            std::strncmp(opt->relax_post_coarse, c.opt.relax_post_coarse, 8) != 0;
+            std::strncmp(opt->relax_pre, c.opt.relax_pre, sizeof(opt->relax_pre)) != 0 ||
+            std::strncmp(opt->relax_post, c.opt.relax_post, sizeof(opt->relax_post)) != 0 ||
+            std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, sizeof(opt->relax_pre_coarse)) != 0 ||
+            std::strncmp(opt->relax_post_coarse, c.opt.relax_post_coarse, sizeof(opt->relax_post_coarse)) != 0;
         c.opt = *opt;
         if (amg_changed) invalidate(c);
         AmgParams p = c.amg_params();

@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 
 
 # the benchmark's launch configuration
-BENCH_OPTS = dict(relax_pre="FFCF", relax_post="FFCF", relax_pre_coarse="F", relax_post_coarse="F",
+BENCH_OPTS = dict(relax_pre="FCFCFCFCFCFCF", relax_post="FCFCFCFCFCFCF", relax_pre_coarse="F",
+                  relax_post_coarse="F",
                   autotune=1, streams=5, batch_size=16, filter_r=0.2)
 
 
