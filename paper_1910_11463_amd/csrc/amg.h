@@ -179,6 +179,10 @@ public:
     // residual and convergence test (its diagonal must be the identity).
     // Regroups its values by the finest level's C/F split (see FineEll).
     void set_fine_ell(std::shared_ptr<FineEll> e);
+    // Declares that every lAIR local system of the finest level is the
+    // identity (block-scaled DG operator on a structured hex mesh), so R is
+    // built there without local solves.  Call before setup().
+    void set_finest_identity_local_systems(bool on) { finest_identity_ = on; }
     // New parameters (tolerance, iteration limit, relaxation schedule); the
     // captured cycle graph bakes them in, so it is dropped.
     void set_params(const AmgParams& p);
@@ -205,6 +209,7 @@ private:
     std::vector<double> relres_h_, cf_h_;
     DBuf<int64_t> moff_d_, mcnt_d_;   // finest-level member offsets / counts
     std::shared_ptr<FineEll> ell_;
+    bool finest_identity_ = false;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr;
     double last_bytes_ = 0.0;

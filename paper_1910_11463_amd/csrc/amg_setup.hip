@@ -555,6 +555,77 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 }
 
 
+// Restriction rows whose local systems are the identity, z = -A(i, R_i)^T and
+// the row [z, 1] in column order.  This holds on the finest level of a block-
+// scaled operator on a structured hex mesh: R_i lies in the upwind neighbours
+// of i's element (its own block is I, with no stored off-diagonal entries), and
+// two upwind neighbours of one element are never face neighbours, so
+// A(R_i, R_i) = I.  The same selection of R_i as k_r_build (strong F points, at
+// most kmax of the largest |a_ij|); G lanes per row, loops uniform over the wave.
+template <int G>
+__global__ void __launch_bounds__(64)
+k_r_direct(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+           const int32_t* __restrict__ col, const double* __restrict__ val,
+           const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf, int kmax,
+           const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
+           double* __restrict__ r_val) {
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x;
+    const int g = lane / G, sub = lane % G;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int base = blockIdx.x * RPW; base < nrows; base += gridDim.x * RPW) {
+        const bool have = base + g < nrows;
+        const int64_t I = have ? base + g : 0;
+        const int64_t i = have ? c2f[I] : 0;
+        const int64_t rs = have ? rowptr[i] : 0, re = have ? rowptr[i + 1] : 0;
+        int64_t lenw = re - rs;
+        for (int d = 32; d >= 1; d >>= 1) lenw = max(lenw, static_cast<int64_t>(__shfl_xor(lenw, d, 64)));
+        int cnt = 0;
+        for (int64_t e0 = 0; e0 < lenw; e0 += G) {
+            const int64_t e = rs + e0 + sub;
+            const bool cand = have && e < re && r_candidate(i, col[e], sflag[e], cf);
+            cnt += __popcll(__ballot(cand) & gmask);
+        }
+        const int64_t rb = have ? r_rowptr[I] : 0;
+        int filled = 0, before_i = 0;
+        for (int64_t e0 = 0; e0 < lenw; e0 += G) {
+            const int64_t e = rs + e0 + sub;
+            bool keep = false;
+            int32_t cj = -1;
+            double a = 0.0;
+            if (have && e < re) {
+                cj = col[e];
+                keep = r_candidate(i, cj, sflag[e], cf);
+                if (keep) a = val[e];
+                if (keep && cnt > kmax) {
+                    const double am = fabs(a);
+                    int rank = 0;
+                    for (int64_t q = rs; q < re; ++q) {
+                        if (q == e || !r_candidate(i, col[q], sflag[q], cf)) continue;
+                        const double bq = fabs(val[q]);
+                        if (bq > am || (bq == am && col[q] < cj)) ++rank;
+                    }
+                    keep = rank < kmax;
+                }
+            }
+            const uint64_t m = __ballot(keep) & gmask;
+            const uint64_t lt = __ballot(keep && cj < i) & gmask;
+            if (keep) {
+                const int64_t pos = rb + filled + __popcll(m & below) + (cj > i ? 1 : 0);
+                r_col[pos] = cj;
+                r_val[pos] = -a;
+            }
+            filled += __popcll(m);
+            before_i += __popcll(lt);
+        }
+        if (have && sub == 0) {
+            r_col[rb + before_i] = static_cast<int32_t>(i);
+            r_val[rb + before_i] = 1.0;
+        }
+    }
+}
+
 // ------------------------------------------------------------- R A P
 
 // Filtering of R after its construction (phi_R): in row I (C point i =
@@ -1499,7 +1570,14 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.nnz = exclusive_scan(rcnt.p, L.R.rowptr.p, total_c, s_);
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
-        {
+        if (l == 0 && finest_identity_) {
+            const unsigned g = static_cast<unsigned>(std::min<int64_t>((total_c + 3) / 4, 1 << 20));
+            hipLaunchKernelGGL(k_r_direct<16>, dim3(g), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
+                               L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
+                               L.R.rowptr.p, L.R.col.p, L.R.val.p);
+            PAIR_LAUNCH_CHECK();
+            PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
+        } else {
             // local systems by size K: <= 8, <= 16, <= 32, <= 64 (64 / G rows per wave)
             DBuf<int32_t> rl[4];
             int nrc[4];

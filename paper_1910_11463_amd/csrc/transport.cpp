@@ -141,6 +141,7 @@ void Context::assemble_batch(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     std::vector<int64_t> off(B), cn(B, N);
     for (int b = 0; b < B; ++b) off[b] = static_cast<int64_t>(b) * N;
     bt.H.reset(new Hierarchy(amg_params(), s));
+    bt.H->set_finest_identity_local_systems(mesh.kind == PAIR_HEX8);
     bt.H->setup(std::move(A), off, cn);
     bt.H->set_fine_ell(bt.ell);
 }
