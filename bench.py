@@ -43,13 +43,13 @@ def log(*a):
 
 
 def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1,
-                coarse_fp32=0, filter_r=0.0, use_graph=1):
+                coarse_fp32=0, filter_r=0.0, use_graph=1, fine_factored=1):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
                relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
                autotune=1, streams=streams, coarse_fp32=coarse_fp32, filter_r=filter_r,
-               use_graph=use_graph)
+               use_graph=use_graph, fine_factored=fine_factored)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -327,6 +327,16 @@ def main():
                                 "phi_rel_diff_vs_fp64": float(torch.linalg.norm(phi32 - phi64) /
                                                               torch.linalg.norm(phi64))}
         s3.close()
+        # the finest level from stored element-block values instead of the factored form
+        s4 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
+                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
+                         args.relax_post_coarse, args.streams, filter_r=args.filter_r,
+                         use_graph=int(args.graph), fine_factored=0)
+        ssec4, _ = timed_steps(s4, mode, 1, 1, cold=True)
+        wsec4, _ = timed_steps(s4, mode, 1, 0, cold=False)
+        extra["stored_fine_operator"] = {"cold_dof_dirs_per_s": N * M / ssec4,
+                                         "warm_dof_dirs_per_s": N * M / wsec4}
+        s4.close()
         extra["source_iteration"] = []
         for c in [int(x) for x in args.si.split(",") if x.strip()]:
             r = source_iteration_time(c, device, args.streams)
