@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--relax-pre", default="FCFCFCFCFCFCF")
     ap.add_argument("--relax-post", default="FCFCFCFCFCFCF")
     ap.add_argument("--relax-pre-coarse", default="F")
-    ap.add_argument("--relax-post-coarse", default="F")
+    ap.add_argument("--relax-post-coarse", default="")
     ap.add_argument("--streams", type=int, default=5,
                     help="direction batches set up and solved at once, one HIP stream each")
     ap.add_argument("--other-streams", type=int, default=8, help="streams for the other mode")
@@ -223,7 +223,7 @@ def main():
                     help="replay each batch's V-cycle as a captured hipGraph (default: eager "
                          "launches, equally fast with several worker streams, and every "
                          "launch of the roofline kernel is then event-timed)")
-    ap.add_argument("--filter-r", type=float, default=0.2,
+    ap.add_argument("--filter-r", type=float, default=1.0,
                     help="phi_R: drop R entries below phi_R x the row's largest (0 = keep all)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also copy MIB MiB device-to-device (counter calibration)")
@@ -368,7 +368,8 @@ def main():
         "config": {"workload": w.name, "mode": args.mode, "dof_per_dir": N, "dirs": M,
                    "tol": 1e-8, "step": "cold sweep replacement: assembly + AIR setup + V-cycles + phi",
                    "relax": "V(%s,%s) Jacobi half-sweeps, coarser levels V(%s,%s)" % (
-                       args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse),
+                       args.relax_pre or "-", args.relax_post or "-", args.relax_pre_coarse or "-",
+                       args.relax_post_coarse or "-"),
                    "streams": args.streams, "filter_r": args.filter_r, "graph": bool(args.graph),
                    "parallelism": "1 GPU"},
         "stats": {"vcycles_total": st["vcycles_total"], "vcycles_max": st["vcycles_max"],

@@ -13,8 +13,7 @@ pytestmark = pytest.mark.gpu
 
 # the benchmark's launch configuration
 BENCH_OPTS = dict(relax_pre="FCFCFCFCFCFCF", relax_post="FCFCFCFCFCFCF", relax_pre_coarse="F",
-                  relax_post_coarse="F",
-                  autotune=1, streams=5, batch_size=16, filter_r=0.2)
+                  relax_post_coarse="", autotune=1, streams=5, batch_size=16, filter_r=1.0)
 
 
 def _sampled(cfg, dirs, mode, tol=1e-12):
