@@ -193,7 +193,7 @@ k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
 // Split rows into classes by a per-row size v (mode 0: row length of a, mode
 // 1: row length minus one, mode 2: ub[i]): class k < NC - 1 holds the rows
 // with bound[k-1] < v <= bound[k], class NC - 1 the rest.
-constexpr int kMaxClasses = 5;
+constexpr int kMaxClasses = 6;
 struct RowClasses {
     int64_t bound[kMaxClasses - 1];
     int32_t* list[kMaxClasses];
@@ -1117,6 +1117,104 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
     }
 }
 
+// R (A P) for rows with at most kMergeR entries of R, one thread per row: the
+// rows of A P are sorted by column, so the row of R A P is their merge; a
+// column present in several of them is summed in the order of the R entries
+// with fma from 0 (the operation sequence of k_rap_num).  The symbolic pass
+// writes the number of distinct columns.  The numeric pass runs one wave per
+// block: when the wave's rows are consecutive (their output is one contiguous
+// range) and the range fits kMergeStage entries, the rows are merged into LDS
+// and the range is written out by the whole wave, coalesced; otherwise each
+// thread writes its row directly.
+constexpr int kMergeR = 4;
+constexpr int kMergeStage = 2048;
+
+template <bool NUMERIC>
+__global__ void __launch_bounds__(NUMERIC ? 64 : 256)
+k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ r_rowptr,
+            const int32_t* __restrict__ r_col, const double* __restrict__ r_val,
+            const int64_t* __restrict__ rowptr, const int* __restrict__ ap_len,
+            const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
+            int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
+            int32_t* __restrict__ c_col, double* __restrict__ c_val) {
+    constexpr int32_t kEnd = 0x7fffffff;
+    __shared__ int32_t s_col[NUMERIC ? kMergeStage : 1];
+    __shared__ double s_val[NUMERIC ? kMergeStage : 1];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool have = r < nrows;
+    const int64_t I = have ? list[r] : 0;
+    // staging decision (numeric pass; the block is one wave)
+    bool staged = false;
+    int64_t lo = 0, hi = 0;
+    if (NUMERIC) {
+        const int lane = threadIdx.x;
+        const int64_t I0 = __shfl(I, 0, 64);
+        const uint64_t valid = __ballot(have);
+        const bool contig = __ballot(have && I != I0 + lane) == 0ull;
+        const int nvalid = __popcll(valid);
+        if (contig && nvalid > 0) {
+            lo = c_rowptr[I0];
+            hi = c_rowptr[I0 + nvalid];
+            staged = hi - lo <= kMergeStage;
+        }
+    }
+    if (have) {
+        const int64_t rs = r_rowptr[I];
+        const int rl = static_cast<int>(r_rowptr[I + 1] - rs);   // <= kMergeR
+        int64_t pos[kMergeR], end[kMergeR];
+        double rv[kMergeR];
+        int32_t head[kMergeR];
+#pragma unroll
+        for (int t = 0; t < kMergeR; ++t) {
+            pos[t] = 0;
+            end[t] = 0;
+            rv[t] = 0.0;
+            if (t < rl) {
+                const int64_t k = r_col[rs + t];
+                pos[t] = rowptr[k];
+                end[t] = pos[t] + ap_len[k];
+                rv[t] = r_val[rs + t];
+            }
+            head[t] = pos[t] < end[t] ? ap_col[pos[t]] : kEnd;
+        }
+        const int64_t ob = NUMERIC ? c_rowptr[I] : 0;
+        int64_t n = 0;
+        while (true) {
+            int32_t c = head[0];
+#pragma unroll
+            for (int t = 1; t < kMergeR; ++t) c = min(c, head[t]);
+            if (c == kEnd) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < kMergeR; ++t) {
+                if (head[t] != c) continue;
+                if (NUMERIC) acc = fma(rv[t], ap_val[pos[t]], acc);
+                ++pos[t];
+                head[t] = pos[t] < end[t] ? ap_col[pos[t]] : kEnd;
+            }
+            if (NUMERIC) {
+                if (staged) {
+                    s_col[ob - lo + n] = c;
+                    s_val[ob - lo + n] = acc;
+                } else {
+                    c_col[ob + n] = c;
+                    c_val[ob + n] = acc;
+                }
+            }
+            ++n;
+        }
+        if (!NUMERIC) cnt_out[I] = n;
+    }
+    if (NUMERIC) {
+        __syncthreads();
+        if (staged)
+            for (int64_t q = threadIdx.x; q < hi - lo; q += blockDim.x) {
+                c_col[lo + q] = s_col[q];
+                c_val[lo + q] = s_val[q];
+            }
+    }
+}
+
 // Rows with more products than fit in LDS: same algorithm on global scratch.
 template <bool NUMERIC>
 __global__ void __launch_bounds__(256)
@@ -1152,7 +1250,8 @@ __global__ void k_rap_ub(int64_t nc, const int64_t* __restrict__ r_rowptr,
     if (I >= nc) return;
     int64_t s = 0;
     for (int64_t e = r_rowptr[I]; e < r_rowptr[I + 1]; ++e) s += ap_len[r_col[e]];
-    ub[I] = s;
+    // rows of at most kMergeR R entries are merged (class 0, marked by 0)
+    ub[I] = r_rowptr[I + 1] - r_rowptr[I] <= kMergeR ? 0 : (s > 0 ? s : 1);
 }
 
 // ------------------------------------------------------------- coarse dense inverse
@@ -1638,30 +1737,31 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         hipLaunchKernelGGL(k_rap_ub, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
                            L.R.rowptr.p, L.R.col.p, ap_len.p, ub.p);
         PAIR_LAUNCH_CHECK();
-        // classes by products: <= 128, <= 256, <= 1024, <= 2048 in LDS, the rest global
-        DBuf<int32_t> lists[5];
-        int lcount[5];
-        classify<5>(total_c, 2, nullptr, ub.p, {128, 256, 1024, 2048}, lists, lcount, s_);
+        // classes: rows of at most kMergeR R entries (merged), then by products:
+        // <= 128, <= 256, <= 1024, <= 2048 in LDS, the rest global
+        DBuf<int32_t> lists[6];
+        int lcount[6];
+        classify<6>(total_c, 2, nullptr, ub.p, {0, 128, 256, 1024, 2048}, lists, lcount, s_);
         // hash-table scratch for the global class: 2 * pow2(products) slots per row
         std::vector<int64_t> gscr_off_h;
         DBuf<int64_t> gscr_off;
         DBuf<uint32_t> gkeys, gcols;
         DBuf<int32_t> gpos;
         DBuf<double> gvals;
-        if (lcount[4] > 0) {
-            std::vector<int32_t> rows(lcount[4]);
-            d2h(rows.data(), lists[4].p, lcount[4], s_);
+        if (lcount[5] > 0) {
+            std::vector<int32_t> rows(lcount[5]);
+            d2h(rows.data(), lists[5].p, lcount[5], s_);
             std::vector<int64_t> ubh(total_c);
             d2h(ubh.data(), ub.p, total_c, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            gscr_off_h.resize(lcount[4] + 1, 0);
-            for (int k = 0; k < lcount[4]; ++k) {
+            gscr_off_h.resize(lcount[5] + 1, 0);
+            for (int k = 0; k < lcount[5]; ++k) {
                 int64_t cap = 1;
                 while (cap < ubh[rows[k]]) cap <<= 1;
                 gscr_off_h[k + 1] = gscr_off_h[k] + 2 * cap;
             }
-            gscr_off.alloc(lcount[4] + 1);
-            h2d(gscr_off.p, gscr_off_h.data(), lcount[4] + 1, s_);
+            gscr_off.alloc(lcount[5] + 1);
+            h2d(gscr_off.p, gscr_off_h.data(), lcount[5] + 1, s_);
             gkeys.alloc(gscr_off_h.back());
             gpos.alloc(gscr_off_h.back());
             gcols.alloc(gscr_off_h.back() / 2);
@@ -1675,44 +1775,52 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             auto grid = [](int n) { return dim3(static_cast<unsigned>(std::min(n, 1 << 20))); };
 #define PAIR_RAP_ARGS(c) lcount[c], lists[c].p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p, \
                          ap_len.p, ap_col.p, ap_val.p
+            if (lcount[0] > 0) {
+                if (numeric)
+                    hipLaunchKernelGGL(k_rap_merge<true>, dim3(grid_for(lcount[0], 64)), dim3(64), 0, s_,
+                                       PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval);
+                else
+                    hipLaunchKernelGGL(k_rap_merge<false>, dim3(grid_for(lcount[0], 256)), dim3(256), 0,
+                                       s_, PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval);
+            }
             if (numeric) {
-                if (lcount[0] > 0)
-                    hipLaunchKernelGGL((k_rap_num<64, 128, 1024>), grid(lcount[0]), dim3(64), 0, s_,
-                                       PAIR_RAP_ARGS(0), crp, ccol, cval);
                 if (lcount[1] > 0)
-                    hipLaunchKernelGGL((k_rap_num<64, 256, 2048>), grid(lcount[1]), dim3(64), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<64, 128, 1024>), grid(lcount[1]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(1), crp, ccol, cval);
                 if (lcount[2] > 0)
-                    hipLaunchKernelGGL((k_rap_num<128, 1024, 4096>), grid(lcount[2]), dim3(128), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<64, 256, 2048>), grid(lcount[2]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(2), crp, ccol, cval);
                 if (lcount[3] > 0)
-                    hipLaunchKernelGGL((k_rap_num<256, 2048, 2048>), grid(lcount[3]), dim3(256), 0, s_,
+                    hipLaunchKernelGGL((k_rap_num<128, 1024, 4096>), grid(lcount[3]), dim3(128), 0, s_,
                                        PAIR_RAP_ARGS(3), crp, ccol, cval);
+                if (lcount[4] > 0)
+                    hipLaunchKernelGGL((k_rap_num<256, 2048, 2048>), grid(lcount[4]), dim3(256), 0, s_,
+                                       PAIR_RAP_ARGS(4), crp, ccol, cval);
             } else {
-                if (lcount[0] > 0)
-                    hipLaunchKernelGGL((k_rap_lds<64, 256, false>), grid(lcount[0]), dim3(64), 0, s_,
-                                       PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval);
                 if (lcount[1] > 0)
-                    hipLaunchKernelGGL((k_rap_lds<64, 512, false>), grid(lcount[1]), dim3(64), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<64, 256, false>), grid(lcount[1]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(1), cnt_out, crp, ccol, cval);
                 if (lcount[2] > 0)
-                    hipLaunchKernelGGL((k_rap_lds<128, 2048, false>), grid(lcount[2]), dim3(128), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<64, 512, false>), grid(lcount[2]), dim3(64), 0, s_,
                                        PAIR_RAP_ARGS(2), cnt_out, crp, ccol, cval);
                 if (lcount[3] > 0)
-                    hipLaunchKernelGGL((k_rap_lds<256, 4096, false>), grid(lcount[3]), dim3(256), 0, s_,
+                    hipLaunchKernelGGL((k_rap_lds<128, 2048, false>), grid(lcount[3]), dim3(128), 0, s_,
                                        PAIR_RAP_ARGS(3), cnt_out, crp, ccol, cval);
+                if (lcount[4] > 0)
+                    hipLaunchKernelGGL((k_rap_lds<256, 4096, false>), grid(lcount[4]), dim3(256), 0, s_,
+                                       PAIR_RAP_ARGS(4), cnt_out, crp, ccol, cval);
             }
 #undef PAIR_RAP_ARGS
             PAIR_LAUNCH_CHECK();
-            if (lcount[4] > 0) {
+            if (lcount[5] > 0) {
                 if (numeric)
-                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[4]), dim3(256), 0, s_,
-                                       lcount[4], lists[4].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[5]), dim3(256), 0, s_,
+                                       lcount[5], lists[5].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
                                        ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 else
-                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[4]), dim3(256), 0, s_,
-                                       lcount[4], lists[4].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
+                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[5]), dim3(256), 0, s_,
+                                       lcount[5], lists[5].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
                                        ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
                 PAIR_LAUNCH_CHECK();
