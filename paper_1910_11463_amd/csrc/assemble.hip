@@ -301,15 +301,23 @@ __device__ __forceinline__ bool group_inverse(double row[2 * K], int a, int lane
 }
 
 // Fine operator of a structured hex mesh, 8 lanes per (direction, element):
-// lane a builds row a of D_e, the group inverts D_e, and lane a writes row a of
-// D_e^{-1}, of the scaled CSR operator and of the element-block copy.
-__global__ void __launch_bounds__(256)
+// lane a builds row a of D_e, the group inverts D_e, and lane a produces row a
+// of D_e^{-1}, of the scaled CSR operator and of the element-block copy.  The
+// block's 32 elements own one contiguous range of D^{-1} and (their rows being
+// consecutive) one contiguous range of CSR entries; both are assembled in LDS
+// and written by the whole block, so each store covers whole cache lines
+// instead of one lane's 8 bytes.
+constexpr int kHexBlock = 256;
+constexpr int kHexStage = kHexBlock * 13;   // CSR entries of 32 elements (<= 13 per row)
+__global__ void __launch_bounds__(kHexBlock)
 k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ ref,
                  const double* __restrict__ omega, const int* __restrict__ dirs, int B,
                  const double* __restrict__ sigt, const int64_t* __restrict__ elem_off,
                  int64_t* __restrict__ rowptr, int32_t* __restrict__ col, double* __restrict__ val,
                  double* __restrict__ dinv, int* __restrict__ bad, int32_t* __restrict__ ell_nbr,
                  int32_t* __restrict__ ell_nodes, double* __restrict__ ell_val) {
+    __shared__ double s_val[kHexStage];
+    __shared__ int32_t s_col[kHexStage];
     const int64_t gl = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int a = static_cast<int>(gl & 7);
     const int lane_base = (threadIdx.x & 63) & ~7;
@@ -335,11 +343,18 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
         row[8 + c] = (c == a) ? 1.0 : 0.0;
     }
     const bool ok = group_inverse<8>(row, a, lane_base);
-    if (!valid) return;
-    if (!ok && a == 0) atomicAdd(bad, 1);
+    if (valid && !ok && a == 0) atomicAdd(bad, 1);
     const double* Di = row + 8;
-    double* dst = dinv + g * 64 + a * 8;
-    for (int c = 0; c < 8; ++c) dst[c] = Di[c];
+    // D^{-1}: the block's elements are consecutive, rows [g0 * 64, g0 * 64 + 64 * nvalid)
+    const int64_t nel_all = E * B;
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * (kHexBlock / 8);
+    const int64_t gend = g0 + kHexBlock / 8 < nel_all ? g0 + kHexBlock / 8 : nel_all;
+    if (valid)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s_val[threadIdx.x * 8 + c] = Di[c];
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < (gend - g0) * 64; q += kHexBlock) dinv[g0 * 64 + q] = s_val[q];
+    __syncthreads();
 
     HexFace fc[3];
     const int ni = hex_inflow_faces(e, nx, ny, nz, om, fc);
@@ -358,7 +373,7 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
     const int64_t row_g = static_cast<int64_t>(b) * N + 8 * e + a;
     const int64_t coff = static_cast<int64_t>(b) * N;
     const int64_t nrows = N * B, nel = E * B;
-    const bool ell = ell_val != nullptr;   // no element-block copy for the factored form
+    const bool ell = valid && ell_val != nullptr;   // no element-block copy for the factored form
     if (ell && a == 0) {
         for (int sl = 0; sl < 3; ++sl) {
             ell_nbr[sl * nel + g] = -1;
@@ -376,12 +391,19 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
     if (ell)
         for (int j = 0; j < 12; ++j) ell_val[j * nrows + row_g] = 0.0;
     const int64_t rb = elem_off[g] + static_cast<int64_t>(a) * L;
-    rowptr[row_g] = rb;
+    const int64_t lo = elem_off[g0], hi = elem_off[gend];
+    const bool staged = hi - lo <= kHexStage;   // always, at <= 13 entries per row
+    if (valid) rowptr[row_g] = rb;
     int pos = 0;
-    for (int gi = 0; gi < ng; ++gi) {
+    for (int gi = 0; valid && gi < ng; ++gi) {
         if (gface[gi] < 0) {
-            col[rb + pos] = static_cast<int32_t>(coff + 8 * e + a);
-            val[rb + pos] = 1.0;
+            if (staged) {
+                s_col[rb - lo + pos] = static_cast<int32_t>(coff + 8 * e + a);
+                s_val[rb - lo + pos] = 1.0;
+            } else {
+                col[rb + pos] = static_cast<int32_t>(coff + 8 * e + a);
+                val[rb + pos] = 1.0;
+            }
             ++pos;
             continue;
         }
@@ -392,13 +414,24 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
             if (((cu >> ax) & 1) != 1 - side) continue;
             double sv = 0.0;
             for (int c = 0; c < 8; ++c) sv += Di[c] * (F.odn * ref[REF_X + F.face * 64 + c * 8 + cu]);
-            col[rb + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
-            val[rb + pos] = sv;
+            if (staged) {
+                s_col[rb - lo + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
+                s_val[rb - lo + pos] = sv;
+            } else {
+                col[rb + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
+                val[rb + pos] = sv;
+            }
             if (ell) ell_val[(ax * 4 + j) * nrows + row_g] = sv;
             ++pos;
             ++j;
         }
     }
+    __syncthreads();
+    if (staged)
+        for (int64_t q = threadIdx.x; q < hi - lo; q += kHexBlock) {
+            col[lo + q] = s_col[q];
+            val[lo + q] = s_val[q];
+        }
 }
 
 __global__ void __launch_bounds__(128)
