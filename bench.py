@@ -43,13 +43,13 @@ def log(*a):
 
 
 def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1,
-                coarse_fp32=0, filter_r=0.0, use_graph=1, fine_factored=1):
+                coarse_fp32=0, filter_r=0.0, use_graph=1, fine_factored=1, omega=1.0):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
                relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
                autotune=1, streams=streams, coarse_fp32=coarse_fp32, filter_r=filter_r,
-               use_graph=use_graph, fine_factored=fine_factored)
+               use_graph=use_graph, fine_factored=fine_factored, omega=omega)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -223,6 +223,7 @@ def main():
                     help="replay each batch's V-cycle as a captured hipGraph (default: eager "
                          "launches, equally fast with several worker streams, and every "
                          "launch of the roofline kernel is then event-timed)")
+    ap.add_argument("--omega", type=float, default=1.0, help="Jacobi weight of the half-sweeps")
     ap.add_argument("--filter-r", type=float, default=1.0,
                     help="phi_R: drop R entries below phi_R x the row's largest (0 = keep all)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -253,7 +254,7 @@ def main():
 
     s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                     args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse,
-                    args.streams, filter_r=args.filter_r, use_graph=int(args.graph))
+                    args.streams, filter_r=args.filter_r, use_graph=int(args.graph), omega=args.omega)
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
     phi64 = timed_steps.last_phi.clone()

@@ -202,10 +202,10 @@ struct RowClasses {
 template <int NC>
 __global__ void __launch_bounds__(256)
 k_classify(int64_t n, int mode, const int64_t* __restrict__ a, const int64_t* __restrict__ ub,
-           RowClasses rc, int* __restrict__ cnt) {
+           RowClasses rc, int* __restrict__ cnt, const uint8_t* __restrict__ mask) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     int cls = -1;
-    if (i < n) {
+    if (i < n && (!mask || mask[i])) {
         const int64_t v = mode == 2 ? ub[i] : (a[i + 1] - a[i] - (mode == 1 ? 1 : 0));
         cls = NC - 1;
         for (int k = NC - 2; k >= 0; --k)
@@ -218,11 +218,12 @@ k_classify(int64_t n, int mode, const int64_t* __restrict__ a, const int64_t* __
     }
 }
 
-// Host side: classes of n rows; counts[k] = rows in class k.
+// Host side: classes of n rows (only rows with mask[i] != 0 when a mask is
+// given); counts[k] = rows in class k.
 template <int NC>
 void classify(int64_t n, int mode, const int64_t* a, const int64_t* ub,
               const std::array<int64_t, NC - 1>& bounds, DBuf<int32_t> (&lists)[NC], int (&counts)[NC],
-              hipStream_t s) {
+              hipStream_t s, const uint8_t* mask = nullptr) {
     RowClasses rc{};
     for (int k = 0; k < NC; ++k) {
         lists[k].alloc(static_cast<size_t>(std::max<int64_t>(n, 1)));
@@ -231,10 +232,17 @@ void classify(int64_t n, int mode, const int64_t* a, const int64_t* ub,
     }
     DBuf<int> cnt(NC);
     PAIR_HIP(hipMemsetAsync(cnt.p, 0, NC * sizeof(int), s));
-    hipLaunchKernelGGL(k_classify<NC>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, mode, a, ub, rc, cnt.p);
+    hipLaunchKernelGGL(k_classify<NC>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, mode, a, ub, rc, cnt.p,
+                       mask);
     PAIR_LAUNCH_CHECK();
     d2h(counts, cnt.p, NC, s);
     PAIR_HIP(hipStreamSynchronize(s));
+}
+
+// mask[col[e]] = 1 for every entry (the rows a sparse matrix refers to)
+__global__ void k_mark_cols(int64_t nnz, const int32_t* __restrict__ col, uint8_t* __restrict__ mask) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < nnz) mask[col[e]] = 1;
 }
 
 __global__ void k_to_float(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
@@ -1704,15 +1712,21 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         if (prm_.filter_r > 0.0) filter_restriction(L, c2f.p, total_c);
 
         // A P: merge the entries of each row of A that interpolate from the same
-        // coarse point (rows classed by length)
+        // coarse point (rows classed by length); only the rows R refers to are
+        // used by R (A P), and only those are formed
         DBuf<int32_t> ap_col(L.A.nnz);
         DBuf<double> ap_val(L.A.nnz);
         DBuf<int> ap_len(n);
         {
+            DBuf<uint8_t> need(n);
+            PAIR_HIP(hipMemsetAsync(need.p, 0, n, s_));
+            hipLaunchKernelGGL(k_mark_cols, dim3(grid_for(L.R.nnz, 256)), dim3(256), 0, s_, L.R.nnz,
+                               L.R.col.p, need.p);
+            PAIR_LAUNCH_CHECK();
             // rows by length: <= 16, <= 32 (registers), <= 64, <= 2048 (LDS)
             DBuf<int32_t> al[5];
             int na[5];
-            classify<5>(n, 0, L.A.rowptr.p, nullptr, {16, 32, 64, 2048}, al, na, s_);
+            classify<5>(n, 0, L.A.rowptr.p, nullptr, {16, 32, 64, 2048}, al, na, s_, need.p);
             PAIR_CHECK(na[4] == 0, "a row of a coarse operator has more than 2048 entries");
             if (na[0] > 0)
                 hipLaunchKernelGGL(k_ap_reg<16>, dim3(grid_for(static_cast<int64_t>(na[0]) * 16, 256)),
