@@ -30,6 +30,7 @@ namespace pair {
 namespace {
 
 constexpr int8_t ST_U = 0, ST_C = 1, ST_F = -1, ST_NP = 2;   // PMIS states
+constexpr int kRowG = 4;   // lanes per row of the row-scanning setup kernels
 constexpr uint64_t KEY_NONE = ~0ull;
 
 // ------------------------------------------------------------- row basics
@@ -1561,7 +1562,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         DBuf<uint8_t> sflag(L.A.nnz);
         DBuf<int> lam(n);
         PAIR_HIP(hipMemsetAsync(lam.p, 0, n * sizeof(int), s_));
-        hipLaunchKernelGGL(k_strength_fused<8>, dim3(grid_for(n * 8, 256)), dim3(256), 0, s_, n,
+        hipLaunchKernelGGL(k_strength_fused<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n,
                            L.A.rowptr.p, L.A.col.p, L.A.val.p, L.seg.p, d_part.p, prm_.theta,
                            prm_.eps_r, L.dinv.p, sflag.p, lam.p);
         PAIR_LAUNCH_CHECK();
@@ -1579,18 +1580,19 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                            d_part.p, lam.p, state.p, plist[0].p, pcnt.p);
         PAIR_LAUNCH_CHECK();
         {
-            const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(n * 8, 256), 8192));
-            const unsigned pgm = static_cast<unsigned>(std::min<int64_t>(grid_for(n * 8, 1024), 2048));
+            constexpr int kPmisG = 2;   // lanes per row (rows of ~13 entries: 2 beat 1, 4, 8, 16)
+            const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(n * kPmisG, 256), 8192));
+            const unsigned pgm = static_cast<unsigned>(std::min<int64_t>(grid_for(n * kPmisG, 1024), 2048));
             int cur = 0;
             for (int round = 0;; ++round) {
                 PAIR_CHECK(round < 100000, "PMIS did not terminate");
                 const int nxt = cur ^ 1;
                 uint8_t* nm_cur = notmax.p + (round & 1) * n;
                 uint8_t* nm_other = notmax.p + ((round & 1) ^ 1) * n;
-                hipLaunchKernelGGL(k_pmis_compare_list<8>, dim3(pg), dim3(256), 0, s_, plist[cur].p,
+                hipLaunchKernelGGL(k_pmis_compare_list<kPmisG>, dim3(pg), dim3(256), 0, s_, plist[cur].p,
                                    pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p,
                                    L.seg.p, d_off.p, l, prm_.seed, nm_cur, pcnt.p + nxt);
-                hipLaunchKernelGGL((k_pmis_mark_list<8, 1024>), dim3(pgm), dim3(1024), 0, s_, plist[cur].p,
+                hipLaunchKernelGGL((k_pmis_mark_list<kPmisG, 1024>), dim3(pgm), dim3(1024), 0, s_, plist[cur].p,
                                    pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, nm_cur,
                                    nm_other, plist[nxt].p, pcnt.p + nxt);
                 PAIR_LAUNCH_CHECK();
@@ -1668,7 +1670,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 
         // restriction
         DBuf<int64_t> rcnt(total_c);
-        hipLaunchKernelGGL(k_r_count<8>, dim3(grid_for(total_c * 8, 256)), dim3(256), 0, s_, total_c,
+        hipLaunchKernelGGL(k_r_count<kRowG>, dim3(grid_for(total_c * kRowG, 256)), dim3(256), 0, s_, total_c,
                            c2f.p, L.A.rowptr.p, L.A.col.p, sflag.p, L.cf.p, prm_.kmax, rcnt.p);
         PAIR_LAUNCH_CHECK();
         L.R.n = total_c;
@@ -1900,7 +1902,7 @@ void Hierarchy::make_fp32_copies() {
 void Hierarchy::filter_restriction(Level& L, const int32_t* c2f, int64_t nc) {
     if (nc == 0) return;
     DBuf<int64_t> cnt(nc);
-    hipLaunchKernelGGL(k_r_filter_count<8>, dim3(grid_for(nc * 8, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
+    hipLaunchKernelGGL(k_r_filter_count<kRowG>, dim3(grid_for(nc * kRowG, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
                        L.R.col.p, L.R.val.p, prm_.filter_r, cnt.p);
     PAIR_LAUNCH_CHECK();
     Csr F;
@@ -1910,7 +1912,7 @@ void Hierarchy::filter_restriction(Level& L, const int32_t* c2f, int64_t nc) {
     F.nnz = exclusive_scan(cnt.p, F.rowptr.p, nc, s_);
     F.col.alloc(F.nnz);
     F.val.alloc(F.nnz);
-    hipLaunchKernelGGL(k_r_filter_copy<8>, dim3(grid_for(nc * 8, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
+    hipLaunchKernelGGL(k_r_filter_copy<kRowG>, dim3(grid_for(nc * kRowG, 256)), dim3(256), 0, s_, nc, c2f, L.R.rowptr.p,
                        L.R.col.p, L.R.val.p, prm_.filter_r, F.rowptr.p, F.col.p, F.val.p);
     PAIR_LAUNCH_CHECK();
     L.R = std::move(F);   // the old arrays are reused only on this stream, after the copy
