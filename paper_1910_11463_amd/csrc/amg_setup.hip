@@ -1680,8 +1680,9 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
         if (l == 0 && finest_identity_) {
-            const unsigned g = static_cast<unsigned>(std::min<int64_t>((total_c + 3) / 4, 1 << 20));
-            hipLaunchKernelGGL(k_r_direct<16>, dim3(g), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
+            constexpr int kG = 4;   // lanes per row
+            const unsigned g = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kG - 1) / (64 / kG), 1 << 20));
+            hipLaunchKernelGGL(k_r_direct<kG>, dim3(g), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
                                L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
                                L.R.rowptr.p, L.R.col.p, L.R.val.p);
             PAIR_LAUNCH_CHECK();
