@@ -311,29 +311,42 @@ k_cf_counts(int64_t n, const int64_t* __restrict__ rowptr, const int8_t* __restr
 
 // One-point interpolation: the strongest strong C neighbour (largest |a_ij|,
 // then smallest column), one thread per row.
-__global__ void k_interp(int64_t n, const int64_t* __restrict__ rowptr,
-                         const int32_t* __restrict__ col, const double* __restrict__ val,
-                         const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
-                         const int32_t* __restrict__ cmap, int32_t* __restrict__ p,
-                         int32_t* __restrict__ c2f) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (cf[i] == 0) { p[i] = -1; return; }
-    if (cf[i] > 0) {
-        p[i] = cmap[i];
-        c2f[cmap[i]] = static_cast<int32_t>(i);
+// One-point interpolation, G lanes per row: an F row takes the strongest
+// strong C neighbour, the smallest column among equal magnitudes (the lanes'
+// candidates are combined by (magnitude, column)).
+template <int G>
+__global__ void __launch_bounds__(256)
+k_interp(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+         const double* __restrict__ val, const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
+         const int32_t* __restrict__ cmap, int32_t* __restrict__ p, int32_t* __restrict__ c2f) {
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const int sub = threadIdx.x % G;
+    if (i >= n) return;   // uniform within the group
+    const int8_t ci = cf[i];
+    if (ci == 0) { if (sub == 0) p[i] = -1; return; }
+    if (ci > 0) {
+        if (sub == 0) {
+            p[i] = cmap[i];
+            c2f[cmap[i]] = static_cast<int32_t>(i);
+        }
         return;
     }
     double best = -1.0;
-    int32_t bj = -1;
-    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        int32_t j = col[e];
+    int32_t bj = 0x7fffffff;
+    for (int64_t e = rowptr[i] + sub; e < rowptr[i + 1]; e += G) {
+        const int32_t j = col[e];
         if ((sflag[e] & 1) && cf[j] > 0) {
-            double a = fabs(val[e]);
-            if (a > best) { best = a; bj = j; }   // sorted columns: first max = smallest column
+            const double a = fabs(val[e]);
+            if (a > best || (a == best && j < bj)) { best = a; bj = j; }
         }
     }
-    p[i] = bj >= 0 ? cmap[bj] : -1;
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) {
+        const double ob = __shfl_xor(best, d, 64);
+        const int32_t oj = __shfl_xor(bj, d, 64);
+        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+    }
+    if (sub == 0) p[i] = best >= 0.0 ? cmap[bj] : -1;
 }
 
 // ------------------------------------------------------------- lAIR restriction
@@ -1664,7 +1677,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         }
         // interpolation and coarse-to-fine map
         DBuf<int32_t> c2f(total_c);
-        hipLaunchKernelGGL(k_interp, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
+        hipLaunchKernelGGL(k_interp<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
                            L.A.col.p, L.A.val.p, sflag.p, L.cf.p, cmap.p, L.p.p, c2f.p);
         PAIR_LAUNCH_CHECK();
 
