@@ -583,13 +583,16 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 // of i's element (its own block is I, with no stored off-diagonal entries), and
 // two upwind neighbours of one element are never face neighbours, so
 // A(R_i, R_i) = I.  The same selection of R_i as k_r_build (strong F points, at
-// most kmax of the largest |a_ij|); G lanes per row, loops uniform over the wave.
-template <int G>
+// most kmax of the largest |a_ij|), then the filter of filter_restriction when
+// phi > 0 (|z_j| >= phi max |z|, the C point's own entry kept), applied here
+// directly since |z_j| = |a_ij|.  COUNT: row lengths into rcnt; otherwise the
+// rows (offsets r_rowptr).  G lanes per row, loops uniform over the wave.
+template <int G, bool COUNT>
 __global__ void __launch_bounds__(64)
 k_r_direct(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
            const int32_t* __restrict__ col, const double* __restrict__ val,
-           const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf, int kmax,
-           const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
+           const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf, int kmax, double phi,
+           int64_t* __restrict__ rcnt, const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
            double* __restrict__ r_val) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x;
@@ -609,7 +612,27 @@ k_r_direct(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict
             const bool cand = have && e < re && r_candidate(i, col[e], sflag[e], cf);
             cnt += __popcll(__ballot(cand) & gmask);
         }
-        const int64_t rb = have ? r_rowptr[I] : 0;
+        // kept candidates (at most kmax) and their largest |a|
+        auto kept = [&](int64_t e, int32_t cj, double am) {
+            if (!r_candidate(i, cj, sflag[e], cf)) return false;
+            if (cnt <= kmax) return true;
+            int rank = 0;
+            for (int64_t q = rs; q < re; ++q) {
+                if (q == e || !r_candidate(i, col[q], sflag[q], cf)) continue;
+                const double bq = fabs(val[q]);
+                if (bq > am || (bq == am && col[q] < cj)) ++rank;
+            }
+            return rank < kmax;
+        };
+        double thr = 0.0;
+        if (phi > 0.0) {
+            double amax = 0.0;
+            for (int64_t e = rs + sub; e < re; e += G) {
+                const double am = fabs(val[e]);
+                if (kept(e, col[e], am)) amax = fmax(amax, am);
+            }
+            thr = phi * group_max<G>(amax);
+        }
         int filled = 0, before_i = 0;
         for (int64_t e0 = 0; e0 < lenw; e0 += G) {
             const int64_t e = rs + e0 + sub;
@@ -618,23 +641,13 @@ k_r_direct(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict
             double a = 0.0;
             if (have && e < re) {
                 cj = col[e];
-                keep = r_candidate(i, cj, sflag[e], cf);
-                if (keep) a = val[e];
-                if (keep && cnt > kmax) {
-                    const double am = fabs(a);
-                    int rank = 0;
-                    for (int64_t q = rs; q < re; ++q) {
-                        if (q == e || !r_candidate(i, col[q], sflag[q], cf)) continue;
-                        const double bq = fabs(val[q]);
-                        if (bq > am || (bq == am && col[q] < cj)) ++rank;
-                    }
-                    keep = rank < kmax;
-                }
+                a = val[e];
+                keep = kept(e, cj, fabs(a)) && (phi <= 0.0 || fabs(a) >= thr);
             }
             const uint64_t m = __ballot(keep) & gmask;
             const uint64_t lt = __ballot(keep && cj < i) & gmask;
-            if (keep) {
-                const int64_t pos = rb + filled + __popcll(m & below) + (cj > i ? 1 : 0);
+            if (!COUNT && keep) {
+                const int64_t pos = r_rowptr[I] + filled + __popcll(m & below) + (cj > i ? 1 : 0);
                 r_col[pos] = cj;
                 r_val[pos] = -a;
             }
@@ -642,8 +655,12 @@ k_r_direct(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict
             before_i += __popcll(lt);
         }
         if (have && sub == 0) {
-            r_col[rb + before_i] = static_cast<int32_t>(i);
-            r_val[rb + before_i] = 1.0;
+            if (COUNT) {
+                rcnt[I] = filled + 1;
+            } else {
+                r_col[r_rowptr[I] + before_i] = static_cast<int32_t>(i);
+                r_val[r_rowptr[I] + before_i] = 1.0;
+            }
         }
     }
 }
@@ -1683,8 +1700,16 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 
         // restriction
         DBuf<int64_t> rcnt(total_c);
-        hipLaunchKernelGGL(k_r_count<kRowG>, dim3(grid_for(total_c * kRowG, 256)), dim3(256), 0, s_, total_c,
-                           c2f.p, L.A.rowptr.p, L.A.col.p, sflag.p, L.cf.p, prm_.kmax, rcnt.p);
+        const bool direct = l == 0 && finest_identity_;
+        constexpr int kDG = 4;   // lanes per row of k_r_direct
+        const unsigned gdir = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kDG - 1) / (64 / kDG), 1 << 20));
+        if (direct)
+            hipLaunchKernelGGL((k_r_direct<kDG, true>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
+                               c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
+                               prm_.filter_r, rcnt.p, nullptr, nullptr, nullptr);
+        else
+            hipLaunchKernelGGL(k_r_count<kRowG>, dim3(grid_for(total_c * kRowG, 256)), dim3(256), 0, s_, total_c,
+                               c2f.p, L.A.rowptr.p, L.A.col.p, sflag.p, L.cf.p, prm_.kmax, rcnt.p);
         PAIR_LAUNCH_CHECK();
         L.R.n = total_c;
         L.R.ncols = n;
@@ -1692,12 +1717,10 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.nnz = exclusive_scan(rcnt.p, L.R.rowptr.p, total_c, s_);
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
-        if (l == 0 && finest_identity_) {
-            constexpr int kG = 4;   // lanes per row
-            const unsigned g = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kG - 1) / (64 / kG), 1 << 20));
-            hipLaunchKernelGGL(k_r_direct<kG>, dim3(g), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
-                               L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
-                               L.R.rowptr.p, L.R.col.p, L.R.val.p);
+        if (direct) {
+            hipLaunchKernelGGL((k_r_direct<kDG, false>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
+                               c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
+                               prm_.filter_r, nullptr, L.R.rowptr.p, L.R.col.p, L.R.val.p);
             PAIR_LAUNCH_CHECK();
             PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
         } else {
@@ -1725,7 +1748,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         }
         int nsing = 0;
         d2h(&nsing, d_counter.p, 1, s_);
-        if (prm_.filter_r > 0.0) filter_restriction(L, c2f.p, total_c);
+        if (prm_.filter_r > 0.0 && !direct) filter_restriction(L, c2f.p, total_c);   // direct: filtered already
 
         // A P: merge the entries of each row of A that interpolate from the same
         // coarse point (rows classed by length); only the rows R refers to are
