@@ -48,6 +48,7 @@ from typing import List, Optional
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 MASK64 = (1 << 64) - 1
 
@@ -307,12 +308,41 @@ def _relax(A, d, b, x, mask, omega):
     return x
 
 
+def hex_tiles(nx: int, ny: int, nz: int, tx: int, ty: int, tz: int) -> np.ndarray:
+    """Tile index of every row of a structured nx*ny*nz hex mesh (element
+    e = i + nx (j + ny k), 8 rows per element): boxes of tx*ty*tz elements
+    anchored at the origin, the last box along an axis cut by the mesh."""
+    e = np.arange(nx * ny * nz)
+    i, j, k = e % nx, (e // nx) % ny, e // (nx * ny)
+    mx, my = -(-nx // tx), -(-ny // ty)
+    t = (i // tx) + mx * ((j // ty) + my * (k // tz))
+    return np.repeat(t, 8)
+
+
+class TileSolver:
+    """Block Jacobi over tiles with exact local solves (the paper's relaxation by
+    an on-processor solve, Sec. "Use of Algebraic Multigrid": each processor
+    inverts its principal submatrix exactly; here a "processor" is a tile of
+    elements): x <- x + M^{-1} (b - A x), M the part of A that couples rows of
+    one tile to rows of the same tile.  The local solve is a sparse LU of M."""
+
+    def __init__(self, A: sp.csr_matrix, tiles: np.ndarray):
+        C = A.tocoo()
+        keep = tiles[C.row] == tiles[C.col]
+        M = sp.csc_matrix((C.data[keep], (C.row[keep], C.col[keep])), shape=A.shape)
+        self.lu = spla.splu(M)
+
+    def relax(self, A, b, x):
+        return x + self.lu.solve(b - A @ x)
+
+
 def vcycle(levels: List[Level], b: np.ndarray, x: np.ndarray, lev: int = 0,
            omega: float = 1.0, pre: str = "FC", post: str = "FC", pre_c=None,
-           post_c=None) -> np.ndarray:
+           post_c=None, tiles: Optional[TileSolver] = None) -> np.ndarray:
     """One V-cycle; each character of pre/post is one Jacobi half-sweep over the
-    F-points ("F") or the C-points ("C"); pre_c/post_c (default: the same) apply
-    on the coarser levels."""
+    F-points ("F") or the C-points ("C"), or on the finest level one tile sweep
+    ("T", undamped, needs `tiles`); pre_c/post_c (default: the same) apply on
+    the coarser levels."""
     L = levels[lev]
     if lev > 0:
         pre = pre if pre_c is None else pre_c
@@ -322,8 +352,16 @@ def vcycle(levels: List[Level], b: np.ndarray, x: np.ndarray, lev: int = 0,
     d = L.A.diagonal()
     F = L.cf < 0
     C = ~F
+
+    def smooth(x, ch):
+        if ch == "T":
+            if lev != 0 or tiles is None:
+                raise ValueError("tile sweeps need the finest level and a TileSolver")
+            return tiles.relax(L.A, b, x)
+        return _relax(L.A, d, b, x, F if ch == "F" else C, omega)
+
     for ch in pre:
-        x = _relax(L.A, d, b, x, F if ch == "F" else C, omega)
+        x = smooth(x, ch)
     r = b - L.A @ x
     bc = L.R @ r
     pc = pre if pre_c is None else pre_c
@@ -331,13 +369,13 @@ def vcycle(levels: List[Level], b: np.ndarray, x: np.ndarray, lev: int = 0,
     xc = vcycle(levels, bc, np.zeros(L.R.shape[0]), lev + 1, omega, pc, qc)
     x = x + L.P @ xc
     for ch in post:
-        x = _relax(L.A, d, b, x, F if ch == "F" else C, omega)
+        x = smooth(x, ch)
     return x
 
 
 def solve(levels: List[Level], b: np.ndarray, tol: float = 1e-10, maxit: int = 200,
           x0=None, omega: float = 1.0, pre: str = "FC", post: str = "FC", pre_c=None,
-          post_c=None):
+          post_c=None, tiles: Optional[TileSolver] = None):
     A = levels[0].A
     x = np.zeros_like(b) if x0 is None else x0.copy()
     nb = np.linalg.norm(b)
@@ -347,7 +385,7 @@ def solve(levels: List[Level], b: np.ndarray, tol: float = 1e-10, maxit: int = 2
         hist.append(rel)
         if rel <= tol:
             return x, it, hist
-        x = vcycle(levels, b, x, 0, omega, pre, post, pre_c, post_c)
+        x = vcycle(levels, b, x, 0, omega, pre, post, pre_c, post_c, tiles)
     rel = np.linalg.norm(b - A @ x) / nb
     hist.append(rel)
     return x, maxit, hist

@@ -195,3 +195,78 @@ def test_vcycle_converges_to_sweep(kind, n, order, m, sched):
     assert hist[-1] <= 1e-12
     xs = SW.sweep(b, f).ravel()
     assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
+
+
+def _tile_case(n=4, m=33, order=8):
+    prob, b, A = _transport_matrix("hex", n, m, order=order)
+    f = prob.rhs(m, None)
+    bt = np.einsum("eab,eb->ea", np.linalg.inv(b.D), f).ravel()
+    xs = SW.sweep(b, f).ravel()
+    return prob, A, bt, xs
+
+
+def test_tile_sweep_over_one_tile_is_the_exact_solve():
+    """A tile holding the whole mesh inverts A exactly: one tile sweep from any
+    start gives the topological block sweep's answer."""
+    n = 4
+    _, A, bt, xs = _tile_case(n)
+    ts = AR.TileSolver(A, AR.hex_tiles(n, n, n, n, n, n))
+    x0 = np.random.default_rng(3).standard_normal(A.shape[0])
+    x = ts.relax(A, bt, x0)
+    assert np.abs(x - xs).max() <= 1e-11 * np.abs(xs).max()
+
+
+def test_tile_sweep_over_single_elements_is_block_jacobi():
+    """One-element tiles: the local blocks are the element diagonal blocks, the
+    identity after block-inverse scaling, so a tile sweep is x + (b - A x)."""
+    n = 3
+    _, A, bt, _ = _tile_case(n, m=5, order=4)
+    Ad = A.toarray()
+    for e in range(n ** 3):
+        blk = Ad[8 * e:8 * e + 8, 8 * e:8 * e + 8]
+        assert np.abs(blk - np.eye(8)).max() <= 1e-13
+    ts = AR.TileSolver(A, AR.hex_tiles(n, n, n, 1, 1, 1))
+    x0 = np.random.default_rng(5).standard_normal(A.shape[0])
+    want = x0 + (bt - A @ x0)
+    assert np.abs(ts.relax(A, bt, x0) - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("tile,depth", [((2, 4, 4), 2), ((2, 2, 4), 3), ((2, 2, 2), 4),
+                                        ((3, 4, 1), 5)])
+def test_tile_sweeps_are_exact_after_the_longest_tile_path(tile, depth):
+    """Block Jacobi over tiles of a block-triangular (upwind) system: a tile is
+    exact one sweep after all tiles upwind of it, so the error vanishes after as
+    many sweeps as the longest upwind chain of tiles and not one sweep earlier
+    (direction 33 of S8 has no zero component; (3, 4, 1) cuts x raggedly)."""
+    n = 4
+    _, A, bt, xs = _tile_case(n)
+    ts = AR.TileSolver(A, AR.hex_tiles(n, n, n, *tile))
+    x = np.random.default_rng(9).standard_normal(A.shape[0])
+    errs = []
+    for _ in range(depth):
+        x = ts.relax(A, bt, x)
+        errs.append(np.abs(x - xs).max() / np.abs(xs).max())
+    assert errs[-2] > 1e-6
+    assert errs[-1] <= 1e-11
+
+
+def test_hex_tiles_partition():
+    t = AR.hex_tiles(5, 3, 2, 2, 2, 1)
+    assert t.shape == (5 * 3 * 2 * 8,)
+    el = t[::8]
+    # element (i, j, k) = (4, 2, 1): tiles (2, 1, 1) of a 3 x 2 x 2 grid of tiles
+    assert el[4 + 5 * (2 + 3 * 1)] == 2 + 3 * (1 + 2 * 1)
+    assert len(np.unique(el)) == 3 * 2 * 2
+
+
+def test_vcycle_with_tile_sweeps_converges_to_sweep():
+    n = 4
+    _, A, bt, xs = _tile_case(n)
+    levels = AR.setup(A, AR.Options(coarse_max=16, filter_r=1.0))
+    ts = AR.TileSolver(A, AR.hex_tiles(n, n, n, 2, 2, 4))
+    x, it, hist = AR.solve(levels, bt, tol=1e-12, maxit=60, pre="T", post="T", pre_c="F",
+                           post_c="", tiles=ts)
+    assert hist[-1] <= 1e-12
+    assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
+    with pytest.raises(ValueError):
+        AR.vcycle(levels, bt, np.zeros_like(bt), 0, 1.0, "T", "T", "F", "")
