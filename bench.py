@@ -43,13 +43,14 @@ def log(*a):
 
 
 def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1,
-                coarse_fp32=0, filter_r=0.0, use_graph=1, fine_factored=1, omega=1.0):
+                coarse_fp32=0, filter_r=0.0, use_graph=1, fine_factored=1, omega=1.0, tile_xy=8, tile_z=0):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
                relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
                autotune=1, streams=streams, coarse_fp32=coarse_fp32, filter_r=filter_r,
-               use_graph=use_graph, fine_factored=fine_factored, omega=omega)
+               use_graph=use_graph, fine_factored=fine_factored, omega=omega, tile_xy=tile_xy,
+               tile_z=tile_z)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -224,6 +225,8 @@ def main():
                          "launches, equally fast with several worker streams, and every "
                          "launch of the roofline kernel is then event-timed)")
     ap.add_argument("--omega", type=float, default=1.0, help="Jacobi weight of the half-sweeps")
+    ap.add_argument("--tile-xy", type=int, default=8, help="tile sweep boxes: elements along x and y")
+    ap.add_argument("--tile-z", type=int, default=0, help="tile sweep boxes: elements along z (0: all)")
     ap.add_argument("--filter-r", type=float, default=1.0,
                     help="phi_R: drop R entries below phi_R x the row's largest (0 = keep all)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -254,7 +257,8 @@ def main():
 
     s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                     args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse,
-                    args.streams, filter_r=args.filter_r, use_graph=int(args.graph), omega=args.omega)
+                    args.streams, filter_r=args.filter_r, use_graph=int(args.graph), omega=args.omega,
+                    tile_xy=args.tile_xy, tile_z=args.tile_z)
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
     phi64 = timed_steps.last_phi.clone()
@@ -287,7 +291,7 @@ def main():
         s1 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
                          args.relax_post_coarse, 1, filter_r=args.filter_r,
-                         use_graph=int(args.graph))
+                         use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z)
         timed_steps(s1, mode, 1, 0, cold=False)
         timed_steps(s1, mode, 1, 0, cold=False, profile=True)
         iso = profile_kinds()["relax_fine"]
@@ -298,7 +302,7 @@ def main():
         s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
                          args.relax_post_coarse, args.other_streams, filter_r=args.filter_r,
-                         use_graph=int(args.graph))
+                         use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z)
         osec, ost = timed_steps(s2, other, 1, 0, cold=True)
         wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
         s2.clear_cache()
@@ -319,7 +323,8 @@ def main():
         s3 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
                          args.relax_post_coarse, args.streams, coarse_fp32=1,
-                         filter_r=args.filter_r, use_graph=int(args.graph))
+                         filter_r=args.filter_r, use_graph=int(args.graph), tile_xy=args.tile_xy,
+                         tile_z=args.tile_z)
         csec, cst = timed_steps(s3, mode, 1, 1, cold=True)
         phi32 = timed_steps.last_phi
         wsec3, _ = timed_steps(s3, mode, 1, 0, cold=False)

@@ -78,7 +78,8 @@ typedef struct pair_options {
     int use_graph;            /* capture batched V-cycles in a hipGraph (1)     */
     int allow_any_weight_sum; /* accept quadrature weights not summing to 4 pi  */
     char relax_pre[16];       /* pre-smoothing half-sweeps, e.g. "FC" (default); up
-                                 to 15 characters from {F, C}                      */
+                                 to 15 characters from {F, C, T} (T: one tile sweep,
+                                 see tile_xy)                                        */
     char relax_post[16];      /* post-smoothing half-sweeps, e.g. "FC"; "FFC" = two
                                  Jacobi sweeps over F-points, then one over C-points */
     int autotune;             /* 1: time the row kernels of each level once per context
@@ -114,6 +115,16 @@ typedef struct pair_options {
                                  rounding).  Batches with a direction component of
                                  magnitude <= 1e-12 use the stored form.  0: always
                                  use the stored element-block values                  */
+    int tile_xy;              /* tile sweeps, letter "T" in relax_pre / relax_post
+                                 (finest level of a structured hex mesh with the
+                                 factored operator only): block Jacobi over boxes of
+                                 tile_xy x tile_xy x tile_z elements with an exact
+                                 forward solve inside each box — the relaxation by an
+                                 on-processor solve of Sec. "Use of Algebraic
+                                 Multigrid", a box standing for a processor; undamped
+                                 (omega does not apply).  tile_xy: 8 (default) or 16 */
+    int tile_z;               /* box height in elements; 0 (default): the mesh's whole
+                                 z extent                                            */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

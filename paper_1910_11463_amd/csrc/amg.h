@@ -41,6 +41,9 @@ struct AmgParams {
     int max_dense = 2048;   // largest coarsest level solved by a dense inverse
     std::string relax_pre = "FC", relax_post = "FC";   // half-sweep schedules, finest level
     std::string relax_pre_coarse = "FC", relax_post_coarse = "FC";   // coarser levels
+    // boxes of the tile sweeps ("T", factored finest level only): tile_xy x
+    // tile_xy x tile_z elements, tile_z = 0 meaning the mesh's whole z extent
+    int tile_xy = 8, tile_z = 0;
     std::shared_ptr<TuneCache> tune;   // null: fixed lanes-per-row table
     // lanes per row of the row kernels: index 0 = finest level, last entry used
     // for all deeper levels.  A function of the level index only, so that every

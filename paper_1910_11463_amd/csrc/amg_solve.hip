@@ -11,6 +11,7 @@
 // members that have converged (active = 0) or whose coarsest level this is
 // (relax = 0) are skipped.  Convergence is tested on |b - A x| / |b| of the
 // finest level after each cycle with fixed-order (reproducible) reductions.
+#include <algorithm>
 #include <cmath>
 
 #include "amg.h"
@@ -380,33 +381,13 @@ struct HexDir {
     int in;
 };
 
-__device__ __forceinline__ void hex_offdiag(int64_t g, uint32_t e, int nx, int ny, int nz, double sig,
-                                            const HexDir& dr, const double* __restrict__ x, double y[8]) {
+// y = D_e^{-1} A_eU x_U from the upwind neighbours' face values v_d[t] (t the
+// node index with bit d removed; zero where the face is on the inflow boundary).
+__device__ __forceinline__ void hex_face_solve(double sig, const HexDir& dr, const double v0[4],
+                                               const double v1[4], const double v2[4], double y[8]) {
     constexpr double kS2 = 1.4142135623730950488;      // sqrt 2
     constexpr double kC = 0.35355339059327376220;      // 1 / (2 sqrt 2)
     const int sx = dr.in & 1, sy = (dr.in >> 1) & 1, sz = (dr.in >> 2) & 1;
-    const uint32_t nxy = static_cast<uint32_t>(nx) * static_cast<uint32_t>(ny);
-    const uint32_t k = e / nxy, rem = e - k * nxy;
-    const uint32_t j = rem / static_cast<uint32_t>(nx), i = rem - j * static_cast<uint32_t>(nx);
-    // upwind face values: v_d[t], t the node index with bit d removed
-    double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0}, v2[4] = {0.0, 0.0, 0.0, 0.0};
-    if (sx ? (i + 1 < static_cast<uint32_t>(nx)) : (i > 0)) {
-        const double* xu = x + (g + (sx ? 1 : -1)) * 8 + (1 - sx);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) v0[t] = xu[2 * t];
-    }
-    if (sy ? (j + 1 < static_cast<uint32_t>(ny)) : (j > 0)) {
-        const double2* xu = reinterpret_cast<const double2*>(
-            x + (g + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
-        const double2 lo = xu[0], hi = xu[2];
-        v1[0] = lo.x; v1[1] = lo.y; v1[2] = hi.x; v1[3] = hi.y;
-    }
-    if (sz ? (k + 1 < static_cast<uint32_t>(nz)) : (k > 0)) {
-        const int64_t st = static_cast<int64_t>(nxy);
-        const double2* xu = reinterpret_cast<const double2*>(x + (g + (sz ? st : -st)) * 8 + 4 * (1 - sz));
-        const double2 lo = xu[0], hi = xu[1];
-        v2[0] = lo.x; v2[1] = lo.y; v2[2] = hi.x; v2[3] = hi.y;
-    }
     // g = sum_d -kap_d M1^{-1}[a_d][s_d] v_d
     double al[3][2];
 #pragma unroll
@@ -491,6 +472,34 @@ __device__ __forceinline__ void hex_offdiag(int64_t g, uint32_t e, int nx, int n
             y[ax + 2 * ay] = sz ? other : same;
             y[ax + 2 * ay + 4] = sz ? same : other;
         }
+}
+
+// Face values of element g's upwind neighbours read from x, then the solve above.
+__device__ __forceinline__ void hex_offdiag(int64_t g, uint32_t e, int nx, int ny, int nz, double sig,
+                                            const HexDir& dr, const double* __restrict__ x, double y[8]) {
+    const int sx = dr.in & 1, sy = (dr.in >> 1) & 1, sz = (dr.in >> 2) & 1;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * static_cast<uint32_t>(ny);
+    const uint32_t k = e / nxy, rem = e - k * nxy;
+    const uint32_t j = rem / static_cast<uint32_t>(nx), i = rem - j * static_cast<uint32_t>(nx);
+    double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0}, v2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (sx ? (i + 1 < static_cast<uint32_t>(nx)) : (i > 0)) {
+        const double* xu = x + (g + (sx ? 1 : -1)) * 8 + (1 - sx);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v0[t] = xu[2 * t];
+    }
+    if (sy ? (j + 1 < static_cast<uint32_t>(ny)) : (j > 0)) {
+        const double2* xu = reinterpret_cast<const double2*>(
+            x + (g + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
+        const double2 lo = xu[0], hi = xu[2];
+        v1[0] = lo.x; v1[1] = lo.y; v1[2] = hi.x; v1[3] = hi.y;
+    }
+    if (sz ? (k + 1 < static_cast<uint32_t>(nz)) : (k > 0)) {
+        const int64_t st = static_cast<int64_t>(nxy);
+        const double2* xu = reinterpret_cast<const double2*>(x + (g + (sz ? st : -st)) * 8 + 4 * (1 - sz));
+        const double2 lo = xu[0], hi = xu[1];
+        v2[0] = lo.x; v2[1] = lo.y; v2[2] = hi.x; v2[3] = hi.y;
+    }
+    hex_face_solve(sig, dr, v0, v1, v2, y);
 }
 
 __device__ __forceinline__ HexDir load_hex_dir(uint32_t m, const double* __restrict__ kap,
@@ -620,6 +629,112 @@ k_hex_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* 
     if (threadIdx.x == 0) partial[static_cast<int64_t>(m) * chunks + chunk] = acc;
 }
 
+// Tile sweep: block Jacobi over boxes of TXY x TXY x tz elements with an exact
+// solve inside each box (the relaxation by an on-processor solve of Sec. "Use
+// of Algebraic Multigrid", a box standing for a processor).  Within a box the
+// upwind operator is block lower triangular with identity diagonal blocks, so
+// the box solve is a forward substitution x_e = b_e - D_e^{-1} A_eU x_U in
+// upwind order.  A block per box runs it as a wavefront: primed coordinates
+// count from the box's inflow corner; thread (i', j') owns a column of the box
+// and at step s solves element k' = s - i' - j', whose x- and y-upwind
+// neighbours were solved at step s - 1 by threads (i'-1, j') and (i', j'-1)
+// (read from LDS) and whose z-upwind neighbour is its own previous element
+// (kept in registers).  Neighbours outside the box enter with their values in
+// xin (the previous iterate; none when xin_zero).  Boxes at the mesh's far
+// side are cut by it; a grid of members x boxes.
+template <int TXY>
+__global__ void __launch_bounds__(TXY * TXY)
+k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
+           const double* __restrict__ kap, const int32_t* __restrict__ inflow,
+           const double* __restrict__ sigt, const uint8_t* __restrict__ active,
+           const uint8_t* __restrict__ relax, const double* __restrict__ b,
+           const double* __restrict__ xin, double* __restrict__ xout, int xin_zero) {
+    constexpr int NT = TXY * TXY;
+    __shared__ double sh[2][8][NT];
+    const uint32_t per = static_cast<uint32_t>(mx) * static_cast<uint32_t>(my) * static_cast<uint32_t>(mz);
+    const uint32_t m = blockIdx.x / per;
+    uint32_t t = blockIdx.x - m * per;
+    const int ti = static_cast<int>(t % static_cast<uint32_t>(mx));
+    t /= static_cast<uint32_t>(mx);
+    const int tj = static_cast<int>(t % static_cast<uint32_t>(my));
+    const int tk = static_cast<int>(t / static_cast<uint32_t>(my));
+    if (!(active[m] && relax[m])) return;
+    const HexDir dr = load_hex_dir(m, kap, inflow);
+    const int sx = dr.in & 1, sy = (dr.in >> 1) & 1, sz = (dr.in >> 2) & 1;
+    const int x0 = ti * TXY, y0 = tj * TXY, z0 = tk * tz;
+    const int wx = min(TXY, nx - x0), wy = min(TXY, ny - y0), wz = min(tz, nz - z0);
+    const int tid = static_cast<int>(threadIdx.x);
+    const int ip = tid % TXY, jp = tid / TXY;
+    const bool lane = ip < wx && jp < wy;
+    const int i = x0 + (sx ? wx - 1 - ip : ip);
+    const int j = y0 + (sy ? wy - 1 - jp : jp);
+    // inflow-side neighbours outside the box but inside the mesh
+    const bool outx = ip == 0 && !xin_zero && (sx ? i + 1 < nx : i > 0);
+    const bool outy = jp == 0 && !xin_zero && (sy ? j + 1 < ny : j > 0);
+    const bool outz = !xin_zero && (sz ? z0 + wz < nz : z0 > 0);
+    const int64_t nxy = static_cast<int64_t>(nx) * ny;
+    const int64_t mbase = static_cast<int64_t>(m) * E;
+    const int64_t col = mbase + static_cast<int64_t>(j) * nx + i;
+    const int kfirst = sz ? z0 + wz - 1 : z0;
+    const int dk = sz ? -1 : 1;
+    double zf[4] = {0.0, 0.0, 0.0, 0.0};    // z-upwind face of the column's last element
+    const int nsteps = wx + wy + wz - 2;
+    for (int s = 0; s < nsteps; ++s) {
+        const int kp = s - ip - jp;
+        const int p = s & 1;
+        if (lane && kp >= 0 && kp < wz) {
+            const int k = kfirst + dk * kp;
+            const int64_t g = col + static_cast<int64_t>(k) * nxy;
+            double v0[4], v1[4], v2[4];
+            if (ip > 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v0[q] = sh[p ^ 1][(1 - sx) + 2 * q][tid - 1];
+            } else if (outx) {
+                const double* xu = xin + (g + (sx ? 1 : -1)) * 8 + (1 - sx);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v0[q] = xu[2 * q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v0[q] = 0.0;
+            }
+            if (jp > 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v1[q] = sh[p ^ 1][2 * (1 - sy) + (q & 1) + 4 * (q >> 1)][tid - TXY];
+            } else if (outy) {
+                const double2* xu = reinterpret_cast<const double2*>(
+                    xin + (g + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
+                const double2 lo = xu[0], hi = xu[2];
+                v1[0] = lo.x; v1[1] = lo.y; v1[2] = hi.x; v1[3] = hi.y;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v1[q] = 0.0;
+            }
+            if (kp > 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v2[q] = zf[q];
+            } else if (outz) {
+                const double2* xu = reinterpret_cast<const double2*>(xin + (g + (sz ? nxy : -nxy)) * 8 + 4 * (1 - sz));
+                const double2 lo = xu[0], hi = xu[1];
+                v2[0] = lo.x; v2[1] = lo.y; v2[2] = hi.x; v2[3] = hi.y;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v2[q] = 0.0;
+            }
+            double bv[8], y[8], xn[8];
+            load8(b + g * 8, bv);
+            hex_face_solve(sigt[g - mbase], dr, v0, v1, v2, y);
+#pragma unroll
+            for (int a = 0; a < 8; ++a) xn[a] = bv[a] - y[a];
+            store8(xout + g * 8, xn);
+#pragma unroll
+            for (int a = 0; a < 8; ++a) sh[p][a][tid] = xn[a];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) zf[q] = xn[4 * (1 - sz) + q];
+        }
+        __syncthreads();
+    }
+}
+
 // Class masks of the finest level: one wave per 64 rows.
 __global__ void __launch_bounds__(256)
 k_ell_cmask(int64_t n, const int8_t* __restrict__ cf, uint64_t* __restrict__ cmask,
@@ -673,6 +788,21 @@ double ell_residual_bytes(const Level& L, const FineEll& e) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     if (e.factored) return 24.0 * n + 8.0 * static_cast<double>(e.nel);
     return n * (24.0 * e.nf + 8.0 + 8.0 + 8.0 + 2.25) + 24.0 * static_cast<double>(e.nel);
+}
+
+// Tile sweep over all members: b read and x written once, sigma_t and the
+// direction data, and the previous iterate's face values (4 of 8) on every box
+// face that lies inside the mesh on the inflow side (none from x = 0).
+double tile_relax_bytes(const Level& L, const FineEll& e, int txy, int tz, bool zero) {
+    const double n = static_cast<double>(L.n_f + L.n_c);
+    const double members = n / (8.0 * static_cast<double>(e.E));
+    double b = 16.0 * n + members * (8.0 * static_cast<double>(e.E) + 28.0);
+    if (!zero) {
+        const double mx = (e.nx + txy - 1) / txy, my = (e.ny + txy - 1) / txy, mz = (e.nz + tz - 1) / tz;
+        const double faces = (mx - 1) * e.ny * e.nz + (my - 1) * e.nx * e.nz + (mz - 1) * e.nx * e.ny;
+        b += members * 32.0 * faces;
+    }
+    return b;
 }
 
 __global__ void k_zero_int(int* p) { *p = 0; }
@@ -749,6 +879,30 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
     const int kind = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
     for (char ch : sched) {
         const int8_t which = ch == 'F' ? -1 : 1;
+        if (ch == 'T') {
+            PAIR_CHECK(l == 0 && ell_ && ell_->factored,
+                       "tile sweeps (T) need the factored operator on the finest level");
+            const FineEll& E = *ell_;
+            const int txy = prm_.tile_xy, tz = prm_.tile_z > 0 ? std::min(prm_.tile_z, E.nz) : E.nz;
+            const int mx = (E.nx + txy - 1) / txy, my = (E.ny + txy - 1) / txy, mz = (E.nz + tz - 1) / tz;
+            const int64_t members = E.nel / static_cast<int64_t>(E.E);
+            const int64_t blocks = members * mx * my * mz;
+            PAIR_CHECK(blocks < (int64_t(1) << 31), "tile grid too large");
+            int h = prof_begin(s_, kind);
+            if (txy == 8)
+                hipLaunchKernelGGL(k_hex_tile<8>, dim3(static_cast<unsigned>(blocks)), dim3(64), 0, s_,
+                                   static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, tz, mx, my, mz, E.kap.p,
+                                   E.inflow.p, E.sigt.p, act, L.relax.p, L.b.p, cur, other, zero ? 1 : 0);
+            else
+                hipLaunchKernelGGL(k_hex_tile<16>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s_,
+                                   static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, tz, mx, my, mz, E.kap.p,
+                                   E.inflow.p, E.sigt.p, act, L.relax.p, L.b.p, cur, other, zero ? 1 : 0);
+            prof_end(s_, h, tile_relax_bytes(L, E, txy, tz, zero));
+            PAIR_LAUNCH_CHECK();
+            std::swap(cur, other);
+            zero = false;
+            continue;
+        }
         if (l == 0 && ell_) {
             const FineEll& E = *ell_;
             if (E.factored) {
@@ -1138,8 +1292,12 @@ double Hierarchy::solve_bytes_per_cycle() const {
         for (const std::string* sc : {&pre, &post}) {
             for (char ch : *sc) {
                 const int which = ch == 'F' ? -1 : 1;
-                bytes += (l == 0 && ell_) ? ell_relax_bytes(L, *ell_, which, zero)
-                                          : relax_bytes(L, which, zero, vb);
+                if (ch == 'T' && l == 0 && ell_) {
+                    const int tz = prm_.tile_z > 0 ? std::min(prm_.tile_z, ell_->nz) : ell_->nz;
+                    bytes += tile_relax_bytes(L, *ell_, prm_.tile_xy, tz, zero);
+                } else
+                    bytes += (l == 0 && ell_) ? ell_relax_bytes(L, *ell_, which, zero)
+                                              : relax_bytes(L, which, zero, vb);
                 zero = false;
             }
         }

@@ -98,19 +98,25 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.fixed_cycles >= 0 && o.fixed_cycles <= 10000, "fixed_cycles must be in [0, 10000]");
     PAIR_CHECK(o.filter_r >= 0.0 && o.filter_r <= 1.0, "filter_r must be in [0, 1]");
     PAIR_CHECK(o.fine_factored == 0 || o.fine_factored == 1, "fine_factored must be 0 or 1");
+    PAIR_CHECK(o.tile_xy == 8 || o.tile_xy == 16, "tile_xy must be 8 or 16");
+    PAIR_CHECK(o.tile_z >= 0 && o.tile_z <= (1 << 20), "tile_z must be in [0, 2^20]");
     constexpr size_t kS = sizeof(o.relax_pre);
-    auto sched_ok = [&](const char* c) {
+    auto sched_ok = [&](const char* c, bool tiles) {
         size_t n = strnlen(c, kS);
         if (n >= kS) return false;
         for (size_t i = 0; i < n; ++i)
-            if (c[i] != 'F' && c[i] != 'C') return false;
+            if (c[i] != 'F' && c[i] != 'C' && !(tiles && c[i] == 'T')) return false;
         return true;
     };
-    PAIR_CHECK(sched_ok(o.relax_pre) && sched_ok(o.relax_post),
-               "relax_pre / relax_post: up to 15 characters from {F, C}");
-    auto coarse_ok = [&](const char* c) { return std::strncmp(c, "=", kS) == 0 || sched_ok(c); };
-    PAIR_CHECK(coarse_ok(o.relax_pre_coarse) && coarse_ok(o.relax_post_coarse),
-               "relax_pre_coarse / relax_post_coarse: \"=\" or up to 15 characters from {F, C}");
+    PAIR_CHECK(sched_ok(o.relax_pre, true) && sched_ok(o.relax_post, true),
+               "relax_pre / relax_post: up to 15 characters from {F, C, T}");
+    auto coarse_ok = [&](const char* c, const char* fine) {
+        if (std::strncmp(c, "=", kS) == 0) return sched_ok(fine, false);
+        return sched_ok(c, false);
+    };
+    PAIR_CHECK(coarse_ok(o.relax_pre_coarse, o.relax_pre) && coarse_ok(o.relax_post_coarse, o.relax_post),
+               "relax_pre_coarse / relax_post_coarse: up to 15 characters from {F, C}, or \"=\" "
+               "when the finest level's schedule has no T");
     PAIR_CHECK(strnlen(o.relax_pre, kS) + strnlen(o.relax_post, kS) >= 1, "no relaxation at all");
 }
 
@@ -206,6 +212,8 @@ void pair_default_options(pair_options* o) {
     o->fixed_cycles = 0;
     o->filter_r = 0.0;
     o->fine_factored = 1;
+    o->tile_xy = 8;
+    o->tile_z = 0;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
@@ -245,7 +253,8 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
             opt->kmax != c.opt.kmax || opt->pmis_seed != c.opt.pmis_seed ||
             opt->batch_size != c.opt.batch_size || opt->streams != c.opt.streams ||
             opt->coarse_fp32 != c.opt.coarse_fp32 || opt->filter_r != c.opt.filter_r ||
-            opt->fine_factored != c.opt.fine_factored ||
+            opt->fine_factored != c.opt.fine_factored || opt->tile_xy != c.opt.tile_xy ||
+            opt->tile_z != c.opt.tile_z ||
             std::strncmp(opt->relax_pre, c.opt.relax_pre, sizeof(opt->relax_pre)) != 0 ||
             std::strncmp(opt->relax_post, c.opt.relax_post, sizeof(opt->relax_post)) != 0 ||
             std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, sizeof(opt->relax_pre_coarse)) != 0 ||
@@ -778,6 +787,8 @@ int pair_amg_setup(pair_amg* amg, int n_seg, const int64_t* seg_rows, int64_t n,
             cnt[k] = sr[k + 1] - sr[k];
         }
         AmgParams p = params_from_options(amg->opt);
+        PAIR_CHECK(p.relax_pre.find('T') == std::string::npos && p.relax_post.find('T') == std::string::npos,
+                   "tile sweeps (T) need the transport operator of a structured hex mesh");
         amg->H.reset(new Hierarchy(p, amg->s));
         amg->H->setup(std::move(A), off, cnt);
         amg->n_seg = n_seg;

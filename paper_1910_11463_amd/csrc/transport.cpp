@@ -67,6 +67,8 @@ AmgParams params_from_options(const pair_options& o) {
     p.relax_post_coarse = std::strcmp(o.relax_post_coarse, "=") ? o.relax_post_coarse : p.relax_post;
     p.coarse_fp32 = o.coarse_fp32 != 0;
     p.filter_r = o.filter_r;
+    p.tile_xy = o.tile_xy;
+    p.tile_z = o.tile_z;
     if (o.fixed_cycles > 0) {
         p.fixed_cycles = true;
         p.tol = 0.0;
@@ -105,6 +107,10 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     bool fact = opt.fine_factored && mesh.kind == PAIR_HEX8;
     for (int m : bt.dirs)
         for (int d = 0; d < 3; ++d) fact = fact && std::fabs(omega_h[3 * m + d]) > kZeroFluxTol;
+    const bool tiles = std::strchr(opt.relax_pre, 'T') || std::strchr(opt.relax_post, 'T');
+    PAIR_CHECK(fact || !tiles,
+               "tile sweeps (T) need a structured hex mesh, fine_factored = 1 and no direction "
+               "component of magnitude <= 1e-12");
     std::vector<double> kap;      // host sources of the copies below: kept until the
     std::vector<int32_t> in;      // stream synchronisation at the end of fine_assemble
     if (fact) {
