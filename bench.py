@@ -3,8 +3,11 @@
 
 One step = one "sweep replacement": every direction of the workload solved by
 pAIR from a zero initial guess to a relative scaled residual of 1e-8, cold
-(upwind DG assembly + block scaling + AIR setup + V(1,1) FC-Jacobi cycles +
-scalar-flux sum), for the first source iteration (right-hand side from q).
+(upwind DG assembly + block scaling + AIR setup + V-cycles + scalar-flux sum),
+for the first source iteration (right-hand side from q).  V-cycles: three tile
+sweeps (block Jacobi over 16 x 16 x 64-element boxes with an exact forward
+solve per box) before and after the coarse-grid correction on the finest
+level, one F-point Jacobi half-sweep before it on the coarser levels.
 Metric: DOF x directions per second.  Inputs (mesh, materials, quadrature) are
 resident on the GPU before the timed region.
 
@@ -13,12 +16,14 @@ directions) in batches of 16 directions (one block-diagonal hierarchy each),
 five batches in flight on five HIP streams, sigma_t log-uniform in [0.1, 10]
 (seed 2), sigma_s = 0.9 sigma_t, q = 1 in the central box.
 
-Printed JSON line also carries: the roofline of the dominant kernel (finest-level
-F/C Jacobi half-sweeps: algorithmic bytes / event-timed duration, against the
-8 TB/s HBM peak and a measured device copy; HBM traffic from the committed counter
-summary), the CPU oracle's exact sweep timed on the same workload, and secondary
-measurements in `extra`: warm solve (hierarchies kept), setup only, the roofline
-kernel alone on one stream, the batched mode, and full source iterations to 1e-8.
+Printed JSON line also carries: the roofline of the dominant kernel (of the
+event-timed kernels, the one with the largest summed duration in the timed
+region: algorithmic bytes / event-timed duration, against the 8 TB/s HBM peak
+and a measured device copy; HBM traffic from the committed counter summary),
+the CPU oracle's exact sweep timed on the same workload, and secondary
+measurements in `extra`: warm solve (hierarchies kept), setup only, the timed
+kernels alone on one stream, the other mode, F/C half-sweep ladders instead of
+tile sweeps, and full source iterations to 1e-8.
 """
 import argparse
 import json
@@ -32,10 +37,23 @@ if ROOT not in sys.path:
 
 METRIC = "DOF·dirs/s to 1e-8 residual, batched vs per-direction pAIR; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# rocprofv3 FETCH_SIZE + WRITE_SIZE of the roofline kernel, scaled by a copy
-# kernel of known size; valid only for the kernel source it was measured on
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hex_relax_hex64_s8_traffic.txt")
-ROOFLINE_SRC = os.path.join(ROOT, "paper_1910_11463_amd", "csrc", "amg_solve.hip")
+CSRC = os.path.join(ROOT, "paper_1910_11463_amd", "csrc")
+# Kernels timed with events inside the timed region (profile kinds of the
+# library); the one with the largest summed duration is reported as the
+# roofline kernel.  "traffic": rocprofv3 FETCH_SIZE + WRITE_SIZE per launch,
+# scaled by a copy kernel of known size, valid only for the source it was
+# measured on.
+FC_LADDER = "FCFCFCFCFCFCF"
+ROOFLINE_KERNELS = {
+    "relax_fine": {
+        "T": ("k_hex_tile (finest-level tile sweeps: block Jacobi over element boxes, exact "
+              "forward solve per box)", "k_hex_tile_hex64_s8_traffic.txt", "amg_solve.hip"),
+        "FC": ("k_hex_relax (finest-level F/C Jacobi half-sweeps, factored hex operator)",
+               "k_hex_relax_hex64_s8_traffic.txt", "amg_solve.hip")},
+    "r_build": {
+        "*": ("k_r_build (lAIR restriction rows with dense local systems, levels below the "
+              "finest)", "k_r_build_hex64_s8_traffic.txt", "amg_setup.hip")},
+}
 
 
 def log(*a):
@@ -59,21 +77,35 @@ def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post
     return s
 
 
-def measured_traffic():
-    """Bytes per launch of the roofline kernel from the committed counter
-    summary, or None if there is none or the kernel source has changed since."""
+def measured_traffic(traffic_file, src):
+    """Bytes per launch of a kernel from its committed counter summary, or None
+    if there is none or the kernel source has changed since."""
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(ROOT, "profiles", traffic_file)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(ROOFLINE_SRC, "rb").read()).hexdigest()
+    sha = hashlib.sha256(open(os.path.join(CSRC, src), "rb").read()).hexdigest()
     if kv.get("source_sha256") != sha or "traffic_bytes_per_launch" not in kv:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def roofline_kernel(kind, pre, post):
+    """(label, traffic file, source) of a profile kind under the given schedules."""
+    table = ROOFLINE_KERNELS[kind]
+    if "*" in table:
+        return table["*"]
+    letters = set(pre + post)
+    if letters == {"T"}:
+        return table["T"]
+    if "T" not in letters:
+        return table["FC"]
+    return ("finest-level relaxation (tile sweeps and F/C half-sweeps mixed)", None, None)
 
 
 def copy_probe(mib):
@@ -119,7 +151,7 @@ def timed_steps(s, mode, steps, warmup, cold=True, profile=False):
 def profile_kinds():
     import ctypes
     from paper_1910_11463_amd import binding as B
-    names = ["relax_fine", "residual_fine", "restrict_fine", "relax_coarse", "norm_fine"]
+    names = ["relax_fine", "residual_fine", "restrict_fine", "relax_coarse", "norm_fine", "r_build"]
     out = {}
     for k, nm in enumerate(names):
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
@@ -213,8 +245,8 @@ def main():
     ap.add_argument("--cpu-dirs", type=int, default=80)
     ap.add_argument("--si", default="1,3", help="workloads whose full source iteration is timed "
                     "(extra.source_iteration); empty for none")
-    ap.add_argument("--relax-pre", default="FCFCFCFCFCFCF")
-    ap.add_argument("--relax-post", default="FCFCFCFCFCFCF")
+    ap.add_argument("--relax-pre", default="TTT")
+    ap.add_argument("--relax-post", default="TTT")
     ap.add_argument("--relax-pre-coarse", default="F")
     ap.add_argument("--relax-post-coarse", default="")
     ap.add_argument("--streams", type=int, default=5,
@@ -225,7 +257,7 @@ def main():
                          "launches, equally fast with several worker streams, and every "
                          "launch of the roofline kernel is then event-timed)")
     ap.add_argument("--omega", type=float, default=1.0, help="Jacobi weight of the half-sweeps")
-    ap.add_argument("--tile-xy", type=int, default=8, help="tile sweep boxes: elements along x and y")
+    ap.add_argument("--tile-xy", type=int, default=16, help="tile sweep boxes: elements along x and y")
     ap.add_argument("--tile-z", type=int, default=0, help="tile sweep boxes: elements along z (0: all)")
     ap.add_argument("--filter-r", type=float, default=1.0,
                     help="phi_R: drop R entries below phi_R x the row's largest (0 = keep all)")
@@ -286,15 +318,21 @@ def main():
     ssec = time.perf_counter() - t0
     extra["setup_only"] = {"s": ssec, "dof_dirs_per_s": N * M / ssec}
     s.close()
+    # the roofline kernel: the event-timed kind with the largest summed duration
+    dom = max(ROOFLINE_KERNELS, key=lambda k: prof[k]["ms"])
     if not args.no_extra:
-        # the roofline kernel alone on the GPU: one stream, warm solve
+        # the timed kernels alone on the GPU: one stream, one cold step
         s1 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
                          args.relax_post_coarse, 1, filter_r=args.filter_r,
                          use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z)
-        timed_steps(s1, mode, 1, 0, cold=False)
-        timed_steps(s1, mode, 1, 0, cold=False, profile=True)
-        iso = profile_kinds()["relax_fine"]
+        timed_steps(s1, mode, 1, 0, cold=True)
+        timed_steps(s1, mode, 1, 0, cold=True, profile=True)
+        iso_all = profile_kinds()
+        extra["one_stream"] = {k: {"achieved": iso_all[k]["gbs"], "frac": iso_all[k]["gbs"] / HBM_PEAK_GBS,
+                                   "avg_us": iso_all[k]["avg_us"], "launches": iso_all[k]["launches"],
+                                   "ms": iso_all[k]["ms"]} for k in ROOFLINE_KERNELS}
+        iso = iso_all[dom]
         extra["roofline_one_stream"] = {"achieved": iso["gbs"], "frac": iso["gbs"] / HBM_PEAK_GBS,
                                         "avg_us": iso["avg_us"], "launches": iso["launches"]}
         s1.close()
@@ -333,16 +371,20 @@ def main():
                                 "phi_rel_diff_vs_fp64": float(torch.linalg.norm(phi32 - phi64) /
                                                               torch.linalg.norm(phi64))}
         s3.close()
-        # the finest level from stored element-block values instead of the factored form
-        s4 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, args.streams, filter_r=args.filter_r,
-                         use_graph=int(args.graph), fine_factored=0)
-        ssec4, _ = timed_steps(s4, mode, 1, 1, cold=True)
-        wsec4, _ = timed_steps(s4, mode, 1, 0, cold=False)
-        extra["stored_fine_operator"] = {"cold_dof_dirs_per_s": N * M / ssec4,
-                                         "warm_dof_dirs_per_s": N * M / wsec4}
-        s4.close()
+        # F/C half-sweep ladders instead of tile sweeps on the finest level, with
+        # the factored operator and with stored element-block values (tile
+        # sweeps need the factored form)
+        for key, fact in (("fc_ladders", 1), ("stored_fine_operator", 0)):
+            s4 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
+                             FC_LADDER, FC_LADDER, args.relax_pre_coarse, args.relax_post_coarse,
+                             args.streams, filter_r=args.filter_r, use_graph=int(args.graph),
+                             fine_factored=fact)
+            ssec4, st4 = timed_steps(s4, mode, 1, 1, cold=True)
+            wsec4, _ = timed_steps(s4, mode, 1, 0, cold=False)
+            extra[key] = {"relax": "V(%s,%s)" % (FC_LADDER, FC_LADDER),
+                          "cold_dof_dirs_per_s": N * M / ssec4, "warm_dof_dirs_per_s": N * M / wsec4,
+                          "vcycles_total": st4["vcycles_total"]}
+            s4.close()
         extra["source_iteration"] = []
         for c in [int(x) for x in args.si.split(",") if x.strip()]:
             r = source_iteration_time(c, device, args.streams)
@@ -350,16 +392,20 @@ def main():
                                                                     r["outer_iters"]))
             extra["source_iteration"].append(r)
 
-    relax = prof["relax_fine"]
-    traffic = measured_traffic()
+    relax = prof[dom]
+    label, tfile, tsrc = roofline_kernel(dom, args.relax_pre, args.relax_post)
+    traffic = measured_traffic(tfile, tsrc) if tfile else None
     copy_gbs = copy_bandwidth()
     roofline = {"bound": "hbm", "achieved": relax["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": relax["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_hex_relax (finest-level F/C Jacobi half-sweeps, factored hex operator)",
-                "launches": relax["launches"], "avg_us": relax["avg_us"],
+                "kernel": label, "launches": relax["launches"], "avg_us": relax["avg_us"],
+                "total_ms": relax["ms"],
                 "bytes_per_launch": relax["bytes"] / max(1, relax["launches"]),
                 "traffic_gbs": traffic / (relax["avg_us"] * 1e-6) / 1e9 if traffic else None,
-                "copy_gbs": copy_gbs, "frac_of_copy": relax["gbs"] / copy_gbs}
+                "copy_gbs": copy_gbs, "frac_of_copy": relax["gbs"] / copy_gbs,
+                "other_timed": {k: {"kernel": roofline_kernel(k, args.relax_pre, args.relax_post)[0],
+                                    "total_ms": prof[k]["ms"], "achieved": prof[k]["gbs"]}
+                                for k in ROOFLINE_KERNELS if k != dom}}
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -373,8 +419,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "mode": args.mode, "dof_per_dir": N, "dirs": M,
                    "tol": 1e-8, "step": "cold sweep replacement: assembly + AIR setup + V-cycles + phi",
-                   "relax": "V(%s,%s) Jacobi half-sweeps, coarser levels V(%s,%s)" % (
-                       args.relax_pre or "-", args.relax_post or "-", args.relax_pre_coarse or "-",
+                   "relax": "V(%s,%s) on the finest level (T: tile sweep over %dx%dx%s-element "
+                            "boxes; F/C: Jacobi half-sweep over F/C points), coarser levels V(%s,%s)" % (
+                       args.relax_pre or "-", args.relax_post or "-", args.tile_xy, args.tile_xy,
+                       str(args.tile_z) if args.tile_z > 0 else "nz", args.relax_pre_coarse or "-",
                        args.relax_post_coarse or "-"),
                    "streams": args.streams, "filter_r": args.filter_r, "graph": bool(args.graph),
                    "parallelism": "1 GPU"},

@@ -250,12 +250,15 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
  * selected launches (process-wide).  pair_profile_enable(1) clears the records
  * and starts recording, pair_profile_enable(0) stops.  Launches inside a
  * hipGraph capture are not timed.  kind: 0 = FC-Jacobi half-sweeps on the
- * finest level, 1 = finest-level residual, 2 = restriction from the finest
- * level, 3 = half-sweeps on coarser levels, 4 = convergence-test residual
- * norm.  Outputs: number of timed launches, their summed duration (ms) and
- * summed algorithmic bytes (what each launch must read and write: 8 B per
- * value, 4 B per column index, 8 B per row offset; a gathered vector counted
- * once per launch). */
+ * finest level (and tile sweeps), 1 = finest-level residual, 2 = restriction
+ * from the finest level, 3 = half-sweeps on coarser levels, 4 = convergence-
+ * test residual norm, 5 = setup: restriction rows with dense local systems
+ * (lAIR on the levels below the finest).  Outputs: number of timed launches,
+ * their summed duration (ms) and summed algorithmic bytes (what each launch
+ * must read and write: 8 B per value, 4 B per column index, 8 B per row
+ * offset; a gathered vector counted once per launch; for kind 5, counted on
+ * the device per restriction row: its row of A, the rows of A its local system
+ * reads, and its row of R). */
 int pair_profile_enable(int on);
 int pair_profile_read(int kind, int64_t* launches, double* total_ms, double* total_bytes);
 

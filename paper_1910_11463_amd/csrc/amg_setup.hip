@@ -25,6 +25,7 @@
 
 #include "amg.h"
 #include "kernels_common.h"
+#include "profile.h"
 
 namespace pair {
 namespace {
@@ -427,7 +428,8 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
           const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
           const double* __restrict__ val, const uint8_t* __restrict__ sflag,
           const int8_t* __restrict__ cf, int kmax, const int64_t* __restrict__ r_rowptr,
-          int32_t* __restrict__ r_col, double* __restrict__ r_val, int* __restrict__ singular) {
+          int32_t* __restrict__ r_col, double* __restrict__ r_val, int* __restrict__ singular,
+          unsigned long long* __restrict__ pbytes) {
     constexpr int RPW = 64 / G;
     constexpr int LD = G + 1;
     __shared__ double Mloc[RPW][G * LD];
@@ -571,6 +573,18 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
                 r_col[rb + before] = static_cast<int32_t>(i);
                 r_val[rb + before] = 1.0;
             }
+        }
+        if (pbytes) {
+            // algorithmic bytes of the row: list and c2f entries, its row offsets
+            // in A and R, its row of A (column, value, strength flag, cf of the
+            // column), the offsets and entries of the K rows its local system
+            // reads, and its row of R written
+            unsigned long long rb = 0;
+            if (have && sub == 0)
+                rb = 40ull + 14ull * static_cast<unsigned long long>(re - rs) + 16ull * K +
+                     12ull * static_cast<unsigned long long>(tot) + 12ull * (K + 1);
+            for (int d = 32; d >= 1; d >>= 1) rb += __shfl_xor(rb, d, 64);
+            if (lane == 0 && rb) atomicAdd(pbytes + (blockIdx.x % kProfSubSlots), rb);
         }
         __syncthreads();
     }
@@ -1611,17 +1625,20 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         PAIR_LAUNCH_CHECK();
         {
             constexpr int kPmisG = 2;   // lanes per row (rows of ~13 entries: 2 beat 1, 4, 8, 16)
-            const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(n * kPmisG, 256), 8192));
-            const unsigned pgm = static_cast<unsigned>(std::min<int64_t>(grid_for(n * kPmisG, 1024), 2048));
+            // grids sized by the last undecided count the host has seen (the
+            // lists only shrink), so late rounds launch few blocks
+            int64_t bound = n;
             int cur = 0;
             for (int round = 0;; ++round) {
                 PAIR_CHECK(round < 100000, "PMIS did not terminate");
                 const int nxt = cur ^ 1;
                 uint8_t* nm_cur = notmax.p + (round & 1) * n;
                 uint8_t* nm_other = notmax.p + ((round & 1) ^ 1) * n;
+                const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(bound * kPmisG, 256), 8192));
                 hipLaunchKernelGGL(k_pmis_compare_list<kPmisG>, dim3(pg), dim3(256), 0, s_, plist[cur].p,
                                    pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p,
                                    L.seg.p, d_off.p, l, prm_.seed, nm_cur, pcnt.p + nxt);
+                const unsigned pgm = static_cast<unsigned>(std::min<int64_t>(grid_for(bound * kPmisG, 1024), 2048));
                 hipLaunchKernelGGL((k_pmis_mark_list<kPmisG, 1024>), dim3(pgm), dim3(1024), 0, s_, plist[cur].p,
                                    pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, nm_cur,
                                    nm_other, plist[nxt].p, pcnt.p + nxt);
@@ -1632,6 +1649,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                     d2h(&und, pcnt.p + cur, 1, s_);
                     PAIR_HIP(hipStreamSynchronize(s_));
                     if (und == 0) break;
+                    bound = und;
                 }
             }
         }
@@ -1735,13 +1753,16 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                 if (nr == 0) continue;
                 const int rpw = 8 >> c;
                 const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
+                const int ph = prof_begin(s_, PROF_RBUILD);
+                unsigned long long* pb = prof_dev_bytes(ph);
 #define PAIR_RB_ARGS nr, rl[c].p, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, \
-                     L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p
+                     L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p, pb
                 if (c == 0) hipLaunchKernelGGL(k_r_build<8>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
                 else if (c == 1) hipLaunchKernelGGL(k_r_build<16>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
                 else if (c == 2) hipLaunchKernelGGL(k_r_build<32>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
                 else hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
 #undef PAIR_RB_ARGS
+                prof_end_dev(s_, ph);
                 PAIR_LAUNCH_CHECK();
             }
             PAIR_HIP(hipMemcpyAsync(d_counter.p, rsing.p, sizeof(int), hipMemcpyDeviceToDevice, s_));

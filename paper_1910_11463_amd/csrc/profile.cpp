@@ -12,11 +12,15 @@ struct Rec {
     hipEvent_t a, b;
     int kind;
     double bytes;
+    int slot;     // >= 0: bytes are in the device counters of this slot
 };
 std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
+constexpr int kMaxSlots = 4096;
+unsigned long long* g_slots = nullptr;   // kMaxSlots x kProfSubSlots, zeroed when enabled
+int g_next_slot = 0;
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
@@ -40,7 +44,7 @@ int prof_begin(hipStream_t s, int kind) {
         return -1;
     }
     std::lock_guard<std::mutex> g(g_mu);
-    Rec r{take_event(), take_event(), kind, 0.0};
+    Rec r{take_event(), take_event(), kind, 0.0, -1};
     PAIR_HIP(hipEventRecord(r.a, s));
     g_recs.push_back(r);
     return static_cast<int>(g_recs.size()) - 1;
@@ -53,6 +57,20 @@ void prof_end(hipStream_t s, int h, double bytes) {
     g_recs[h].bytes = bytes;
 }
 
+unsigned long long* prof_dev_bytes(int h) {
+    if (h < 0) return nullptr;
+    std::lock_guard<std::mutex> g(g_mu);
+    if (!g_slots || g_next_slot >= kMaxSlots) return nullptr;
+    g_recs[h].slot = g_next_slot++;
+    return g_slots + static_cast<size_t>(g_recs[h].slot) * kProfSubSlots;
+}
+
+void prof_end_dev(hipStream_t s, int h) {
+    if (h < 0) return;
+    std::lock_guard<std::mutex> g(g_mu);
+    PAIR_HIP(hipEventRecord(g_recs[h].b, s));
+}
+
 void prof_enable(bool on) {
     std::lock_guard<std::mutex> g(g_mu);
     if (on) {
@@ -62,6 +80,12 @@ void prof_enable(bool on) {
             g_pool.push_back(r.b);
         }
         g_recs.clear();
+        const size_t bytes = sizeof(unsigned long long) * kMaxSlots * kProfSubSlots;
+        if (!g_slots) PAIR_HIP(hipMalloc(&g_slots, bytes));
+        PAIR_HIP(hipDeviceSynchronize());
+        PAIR_HIP(hipMemset(g_slots, 0, bytes));
+        PAIR_HIP(hipDeviceSynchronize());
+        g_next_slot = 0;
     }
     g_on = on;
 }
@@ -70,13 +94,24 @@ void prof_read(int kind, int64_t* launches, double* total_ms, double* total_byte
     std::lock_guard<std::mutex> g(g_mu);
     int64_t n = 0;
     double ms = 0.0, by = 0.0;
+    std::vector<unsigned long long> slots;
     for (auto& r : g_recs) {
         if (r.kind != kind) continue;
         PAIR_HIP(hipEventSynchronize(r.b));
         float t = 0.f;
         PAIR_HIP(hipEventElapsedTime(&t, r.a, r.b));
         ms += t;
-        by += r.bytes;
+        if (r.slot >= 0) {
+            if (slots.empty()) {
+                slots.resize(static_cast<size_t>(g_next_slot) * kProfSubSlots);
+                PAIR_HIP(hipMemcpy(slots.data(), g_slots, slots.size() * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost));
+            }
+            for (int k = 0; k < kProfSubSlots; ++k)
+                by += static_cast<double>(slots[static_cast<size_t>(r.slot) * kProfSubSlots + k]);
+        } else {
+            by += r.bytes;
+        }
         ++n;
     }
     if (launches) *launches = n;

@@ -15,12 +15,20 @@ enum ProfKind : int {
     PROF_RESTRICT_FINE = 2,  // b_c = R r from the finest level
     PROF_RELAX_COARSE = 3,   // half-sweeps on all coarser levels
     PROF_NORM_FINE = 4,      // convergence test on the finest level
-    PROF_NKINDS = 5
+    PROF_RBUILD = 5,         // lAIR rows with dense local systems (coarser levels' setup)
+    PROF_NKINDS = 6
 };
 
 bool prof_enabled();
 // Returns a handle for prof_end (or -1 when disabled / capturing).
 int prof_begin(hipStream_t s, int kind);
 void prof_end(hipStream_t s, int handle, double bytes);
+// For kernels whose algorithmic bytes depend on data only the device sees: a
+// zeroed device array of kProfSubSlots counters the launch adds its bytes to
+// (any entry; they are summed when read), or nullptr when the handle is -1.
+// Close such a launch with prof_end_dev instead of prof_end.
+constexpr int kProfSubSlots = 64;
+unsigned long long* prof_dev_bytes(int handle);
+void prof_end_dev(hipStream_t s, int handle);
 
 }  // namespace pair

@@ -11,16 +11,19 @@ from tests.gpu_util import need_gpu, oracle_problem, rel, solver_for
 pytestmark = pytest.mark.gpu
 
 
-# the benchmark's launch configuration
-BENCH_OPTS = dict(relax_pre="FCFCFCFCFCFCF", relax_post="FCFCFCFCFCFCF", relax_pre_coarse="F",
-                  relax_post_coarse="", autotune=1, streams=5, batch_size=16, filter_r=1.0)
+# the benchmark's launch configuration (structured hexes: three tile sweeps
+# before and after the coarse-grid correction on the finest level)
+BENCH_OPTS = dict(relax_pre="TTT", relax_post="TTT", relax_pre_coarse="F", relax_post_coarse="",
+                  tile_xy=16, tile_z=0, autotune=1, streams=5, batch_size=16, filter_r=1.0)
+# the same with F/C half-sweep ladders (tets have no tile sweeps)
+FC_OPTS = dict(BENCH_OPTS, relax_pre="FCFCFCFCFCFCF", relax_post="FCFCFCFCFCFCF")
 
 
-def _sampled(cfg, dirs, mode, tol=1e-12):
+def _sampled(cfg, dirs, mode, tol=1e-12, opts=BENCH_OPTS):
     from oracle import source_iteration as si
     w = wl.make_config(cfg)
     print("full size", w.name, "mode", mode, flush=True)
-    s = solver_for(w, tol_inner=tol, max_inner=300, **BENCH_OPTS)
+    s = solver_for(w, tol_inner=tol, max_inner=300, **opts)
     psi, phi, st, rc = s.transport_sweep(mode=mode)
     assert rc == B.PAIR_OK
     assert st["relres_max"] <= tol
@@ -43,10 +46,17 @@ def test_structured_64(mode):
     assert max(errs) <= 1e-9
 
 
+def test_structured_64_fc_ladders():
+    """The same with the F/C half-sweep schedules instead of tile sweeps."""
+    need_gpu()
+    errs = _sampled(2, [11, 62], B.PAIR_BATCHED, opts=FC_OPTS)
+    assert max(errs) <= 1e-9
+
+
 def test_unstructured_tets_48():
     """48^3 x 6 jittered tets (2.65M DOF per direction), S4."""
     need_gpu()
-    errs = _sampled(3, [5, 18], B.PAIR_PLAIN)
+    errs = _sampled(3, [5, 18], B.PAIR_PLAIN, opts=FC_OPTS)
     assert max(errs) <= 1e-9
 
 
