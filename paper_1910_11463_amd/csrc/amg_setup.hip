@@ -44,7 +44,8 @@ __global__ void __launch_bounds__(256)
 k_strength_fused(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                  const double* __restrict__ val, const uint16_t* __restrict__ seg,
                  const uint8_t* __restrict__ part, double theta, double eps_r,
-                 double* __restrict__ dinv, uint8_t* __restrict__ sflag, int* __restrict__ lam) {
+                 double* __restrict__ dinv, uint8_t* __restrict__ sflag, int* __restrict__ lam,
+                 int64_t* __restrict__ scnt) {
     const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / G;
     const int sub = threadIdx.x % G;
     if (row >= n) return;
@@ -59,6 +60,7 @@ k_strength_fused(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* _
     d = group_sum<G>(d);   // exactly one lane holds the diagonal
     if (sub == 0) dinv[row] = d != 0.0 ? 1.0 / d : 0.0;
     const bool on = part[seg[row]] != 0 && m > 0.0;
+    int ns = 0;
     for (int64_t e = rs + sub; e < re; e += G) {
         const int32_t c = col[e];
         uint8_t f = 0;
@@ -68,7 +70,35 @@ k_strength_fused(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* _
             if (a >= eps_r * m) f |= 2;
         }
         sflag[e] = f;
-        if (f & 1) atomicAdd(&lam[c], 1);
+        if (f & 1) {
+            atomicAdd(&lam[c], 1);
+            ++ns;
+        }
+    }
+    ns = group_sum_int<G>(ns);
+    if (sub == 0) scnt[row] = ns;
+}
+
+// The strong (theta) entries of each row, in column order, as their own CSR
+// (scol at srp[i] ..): the PMIS rounds read only these.  G lanes per row.
+template <int G>
+__global__ void __launch_bounds__(256)
+k_strong_fill(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+              const uint8_t* __restrict__ sflag, const int64_t* __restrict__ srp,
+              int32_t* __restrict__ scol) {
+    const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / G;
+    const int sub = threadIdx.x % G;
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
+    const int64_t rs = rowptr[row], re = rowptr[row + 1];
+    int64_t pos = srp[row];
+    for (int64_t e0 = rs; e0 < re; e0 += G) {
+        const int64_t e = e0 + sub;
+        const bool st = e < re && (sflag[e] & 1);
+        const uint64_t m = __ballot(st) & gmask;
+        if (st) scol[pos + __popcll(m & ((1ull << lane) - 1ull))] = col[e];
+        pos += __popcll(m);
     }
 }
 
@@ -111,7 +141,7 @@ k_pmis_init_list(int64_t n, const uint16_t* __restrict__ seg,
 template <int G>
 __global__ void k_pmis_compare_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
                                     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                    const uint8_t* __restrict__ sflag, const int8_t* __restrict__ state,
+                                    const int8_t* __restrict__ state,
                                     const int* __restrict__ lam, const uint16_t* __restrict__ seg,
                                     const int64_t* __restrict__ off, int level, uint64_t seed,
                                     uint8_t* __restrict__ notmax, int* __restrict__ next_cnt) {
@@ -127,7 +157,6 @@ __global__ void k_pmis_compare_list(const int32_t* __restrict__ list, const int*
         const int lami = lam[i];
         const int64_t re = rowptr[i + 1];
         for (int64_t e = rowptr[i] + sub; e < re; e += G) {
-            if (!(sflag[e] & 1)) continue;
             const int64_t j = col[e];
             if (state[j] != ST_U) continue;
             const int64_t lj = j - base;
@@ -150,7 +179,7 @@ template <int G, int NT>
 __global__ void __launch_bounds__(NT)
 k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                 const uint8_t* __restrict__ sflag, int8_t* __restrict__ state,
+                 int8_t* __restrict__ state,
                  const uint8_t* __restrict__ notmax, uint8_t* __restrict__ notmax_other,
                  int32_t* __restrict__ next, int* __restrict__ next_cnt) {
     constexpr int RPB = NT / G;   // rows per block and iteration
@@ -172,7 +201,6 @@ k_pmis_mark_list(const int32_t* __restrict__ list, const int* __restrict__ cnt,
         if (live && !sel) {
             const int64_t re = rowptr[i + 1];
             for (int64_t e = rowptr[i] + sub; e < re; e += G) {
-                if (!(sflag[e] & 1)) continue;
                 const int32_t j = col[e];
                 const int8_t sj = state[j];
                 if (sj == ST_C || (sj == ST_U && notmax[j] == 0)) { f = true; break; }
@@ -1605,10 +1633,16 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         // strength + lambda (fused with 1/a_ii)
         DBuf<uint8_t> sflag(L.A.nnz);
         DBuf<int> lam(n);
+        DBuf<int64_t> scnt(n), srp(n + 1);
         PAIR_HIP(hipMemsetAsync(lam.p, 0, n * sizeof(int), s_));
         hipLaunchKernelGGL(k_strength_fused<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n,
                            L.A.rowptr.p, L.A.col.p, L.A.val.p, L.seg.p, d_part.p, prm_.theta,
-                           prm_.eps_r, L.dinv.p, sflag.p, lam.p);
+                           prm_.eps_r, L.dinv.p, sflag.p, lam.p, scnt.p);
+        PAIR_LAUNCH_CHECK();
+        const int64_t nstrong = exclusive_scan(scnt.p, srp.p, n, s_);
+        DBuf<int32_t> scol(std::max<int64_t>(nstrong, 1));
+        hipLaunchKernelGGL(k_strong_fill<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n,
+                           L.A.rowptr.p, L.A.col.p, sflag.p, srp.p, scol.p);
         PAIR_LAUNCH_CHECK();
 
         // PMIS: list-driven rounds, host check every few rounds
@@ -1636,11 +1670,11 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                 uint8_t* nm_other = notmax.p + ((round & 1) ^ 1) * n;
                 const unsigned pg = static_cast<unsigned>(std::min<int64_t>(grid_for(bound * kPmisG, 256), 8192));
                 hipLaunchKernelGGL(k_pmis_compare_list<kPmisG>, dim3(pg), dim3(256), 0, s_, plist[cur].p,
-                                   pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, lam.p,
+                                   pcnt.p + cur, srp.p, scol.p, state.p, lam.p,
                                    L.seg.p, d_off.p, l, prm_.seed, nm_cur, pcnt.p + nxt);
                 const unsigned pgm = static_cast<unsigned>(std::min<int64_t>(grid_for(bound * kPmisG, 1024), 2048));
                 hipLaunchKernelGGL((k_pmis_mark_list<kPmisG, 1024>), dim3(pgm), dim3(1024), 0, s_, plist[cur].p,
-                                   pcnt.p + cur, L.A.rowptr.p, L.A.col.p, sflag.p, state.p, nm_cur,
+                                   pcnt.p + cur, srp.p, scol.p, state.p, nm_cur,
                                    nm_other, plist[nxt].p, pcnt.p + nxt);
                 PAIR_LAUNCH_CHECK();
                 cur = nxt;
