@@ -119,20 +119,31 @@ __device__ __forceinline__ bool key_less(int li, uint64_t ri, int64_t ii, int lj
 // every decision depends only on the states, so the split is reproducible).
 // Kernels read the list length from device memory, so several rounds can be
 // queued without host synchronisation.
+// kRowsPT consecutive rows per thread, one list reservation per block: the
+// lists keep ascending row order within a block, which the kernels reading
+// them rely on for locality.
+constexpr int kRowsPT = 8;
+
 __global__ void __launch_bounds__(256)
 k_pmis_init_list(int64_t n, const uint16_t* __restrict__ seg,
                                  const uint8_t* __restrict__ part, const int* __restrict__ lam,
                                  int8_t* __restrict__ state, int32_t* __restrict__ list,
                                  int* __restrict__ cnt) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    bool und = false;
-    if (i < n) {
-        if (!part[seg[i]]) state[i] = ST_NP;
-        else if (lam[i] == 0) state[i] = ST_F;
-        else { state[i] = ST_U; und = true; }
+    const int64_t base = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * kRowsPT;
+    unsigned und = 0;
+#pragma unroll
+    for (int r = 0; r < kRowsPT; ++r) {
+        const int64_t i = base + r;
+        if (i < n) {
+            if (!part[seg[i]]) state[i] = ST_NP;
+            else if (lam[i] == 0) state[i] = ST_F;
+            else { state[i] = ST_U; und |= 1u << r; }
+        }
     }
-    const int slot = block_append<256>(und, cnt);
-    if (und) list[slot] = static_cast<int32_t>(i);
+    int slot = block_reserve<256>(__popc(und), cnt);
+#pragma unroll
+    for (int r = 0; r < kRowsPT; ++r)
+        if ((und >> r) & 1u) list[slot++] = static_cast<int32_t>(base + r);
 }
 
 // G lanes per undecided row, striding over its entries.  For every strong
@@ -233,18 +244,29 @@ template <int NC>
 __global__ void __launch_bounds__(256)
 k_classify(int64_t n, int mode, const int64_t* __restrict__ a, const int64_t* __restrict__ ub,
            RowClasses rc, int* __restrict__ cnt, const uint8_t* __restrict__ mask) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    int cls = -1;
-    if (i < n && (!mask || mask[i])) {
-        const int64_t v = mode == 2 ? ub[i] : (a[i + 1] - a[i] - (mode == 1 ? 1 : 0));
-        cls = NC - 1;
-        for (int k = NC - 2; k >= 0; --k)
-            if (v <= rc.bound[k]) cls = k;
+    const int64_t base = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * kRowsPT;
+    int8_t cls[kRowsPT];
+#pragma unroll
+    for (int r = 0; r < kRowsPT; ++r) {
+        const int64_t i = base + r;
+        cls[r] = -1;
+        if (i < n && (!mask || mask[i])) {
+            const int64_t v = mode == 2 ? ub[i] : (a[i + 1] - a[i] - (mode == 1 ? 1 : 0));
+            int c = NC - 1;
+            for (int k = NC - 2; k >= 0; --k)
+                if (v <= rc.bound[k]) c = k;
+            cls[r] = static_cast<int8_t>(c);
+        }
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        const int slot = block_append<256>(cls == k, &cnt[k]);
-        if (cls == k) rc.list[k][slot] = static_cast<int32_t>(i);
+        int c = 0;
+#pragma unroll
+        for (int r = 0; r < kRowsPT; ++r) c += cls[r] == k ? 1 : 0;
+        int slot = block_reserve<256>(c, &cnt[k]);
+#pragma unroll
+        for (int r = 0; r < kRowsPT; ++r)
+            if (cls[r] == k) rc.list[k][slot++] = static_cast<int32_t>(base + r);
     }
 }
 
@@ -262,8 +284,8 @@ void classify(int64_t n, int mode, const int64_t* a, const int64_t* ub,
     }
     DBuf<int> cnt(NC);
     PAIR_HIP(hipMemsetAsync(cnt.p, 0, NC * sizeof(int), s));
-    hipLaunchKernelGGL(k_classify<NC>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, mode, a, ub, rc, cnt.p,
-                       mask);
+    hipLaunchKernelGGL(k_classify<NC>, dim3(grid_for(n, 256 * kRowsPT)), dim3(256), 0, s, n, mode, a, ub, rc,
+                       cnt.p, mask);
     PAIR_LAUNCH_CHECK();
     d2h(counts, cnt.p, NC, s);
     PAIR_HIP(hipStreamSynchronize(s));
@@ -1654,7 +1676,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         DBuf<int> pcnt(2);
         PAIR_HIP(hipMemsetAsync(pcnt.p, 0, 2 * sizeof(int), s_));
         PAIR_HIP(hipMemsetAsync(notmax.p, 0, 2 * n, s_));
-        hipLaunchKernelGGL(k_pmis_init_list, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.seg.p,
+        hipLaunchKernelGGL(k_pmis_init_list, dim3(grid_for(n, 256 * kRowsPT)), dim3(256), 0, s_, n, L.seg.p,
                            d_part.p, lam.p, state.p, plist[0].p, pcnt.p);
         PAIR_LAUNCH_CHECK();
         {

@@ -78,6 +78,37 @@ __device__ __forceinline__ int block_append(bool pred, int* counter) {
     return pred ? slot : -1;
 }
 
+// Reserves c consecutive slots per thread in a global list (block-wide
+// exclusive scan of c, one atomicAdd on `counter` per block); returns the
+// thread's first slot.  Every thread of the NT-thread block must call it.
+template <int NT>
+__device__ __forceinline__ int block_reserve(int c, int* counter) {
+    __shared__ int s_w[NT / 64];
+    __shared__ int s_base;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_w[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            const int t = s_w[w];
+            s_w[w] = tot;
+            tot += t;
+        }
+        s_base = tot > 0 ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    const int slot = s_base + s_w[wid] + x - c;
+    __syncthreads();   // the next call may overwrite s_w / s_base
+    return slot;
+}
+
 // SplitMix64 (Steele, Lea & Flood 2014): add the golden-ratio increment, then
 // the variant-13 finaliser.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
