@@ -467,6 +467,19 @@ __device__ __forceinline__ void r_collect(bool have, int64_t i, int64_t rs, int6
     }
 }
 
+// Position of column c in the sorted cols[0, K) (K <= G), or -1: a search with
+// log2(G) fixed steps (no data-dependent loop exits).
+template <int G>
+__device__ __forceinline__ int col_pos(const int* cols, int K, int c) {
+    int pos = 0;
+#pragma unroll
+    for (int st = G / 2; st >= 1; st >>= 1) {
+        const int t = pos + st;
+        if ((t < K) & (cols[t] <= c)) pos = t;
+    }
+    return (K > 0 && cols[pos] == c) ? pos : -1;
+}
+
 // lAIR rows, G lanes per coarse row (G = 8, 16, 32 or 64 >= the row's local system
 // size K), 64 / G rows per wave.  Local system A(R_i,R_i)^T z = -A(i,R_i)^T in
 // LDS, Gaussian elimination with partial pivoting (lane r owns row r), back
@@ -532,10 +545,11 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = q0 + u * G;
-                int c = 0, hi = K - 1;   // last c with rpref[c] <= q
-                while (c < hi) {
-                    const int mid = (c + hi + 1) >> 1;
-                    if (rpref[g][mid] <= q) c = mid; else hi = mid - 1;
+                int c = 0;   // last c < K with rpref[c] <= q (fixed-step search)
+#pragma unroll
+                for (int st = G / 2; st >= 1; st >>= 1) {
+                    const int t = c + st;
+                    if ((t < K) & (rpref[g][t] <= q)) c = t;
                 }
                 cq[u] = c;
                 eq[u] = q < tot ? rbeg[g][c] + (q - rpref[g][c]) : -1;
@@ -549,25 +563,13 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (eq[u] < 0) continue;
-                int lo = 0, hi = K - 1;
-                while (lo <= hi) {
-                    const int mid = (lo + hi) >> 1;
-                    const int v = cols[g][mid];
-                    if (v == cc[u]) { Mloc[g][mid * LD + cq[u]] = vv[u]; break; }
-                    if (v < cc[u]) lo = mid + 1; else hi = mid - 1;
-                }
+                const int pos = col_pos<G>(cols[g], K, cc[u]);
+                if (eq[u] >= 0 && pos >= 0) Mloc[g][pos * LD + cq[u]] = vv[u];
             }
         }
         for (int64_t e = rs + sub; e < re; e += G) {
-            int32_t cc = col[e];
-            int lo = 0, hi = K - 1;
-            while (lo <= hi) {
-                int mid = (lo + hi) >> 1;
-                int v = cols[g][mid];
-                if (v == cc) { rhs[g][mid] = -val[e]; break; }
-                if (v < cc) lo = mid + 1; else hi = mid - 1;
-            }
+            const int pos = col_pos<G>(cols[g], K, col[e]);
+            if (pos >= 0) rhs[g][pos] = -val[e];
         }
         __syncthreads();
         bool sing = false;
