@@ -403,9 +403,14 @@ def main():
                 "bytes_per_launch": relax["bytes"] / max(1, relax["launches"]),
                 "traffic_gbs": traffic / (relax["avg_us"] * 1e-6) / 1e9 if traffic else None,
                 "copy_gbs": copy_gbs, "frac_of_copy": relax["gbs"] / copy_gbs,
-                "other_timed": {k: {"kernel": roofline_kernel(k, args.relax_pre, args.relax_post)[0],
-                                    "total_ms": prof[k]["ms"], "achieved": prof[k]["gbs"]}
-                                for k in ROOFLINE_KERNELS if k != dom}}
+                "other_timed": {}}
+    for k in ROOFLINE_KERNELS:
+        if k == dom:
+            continue
+        lab, tf, ts = roofline_kernel(k, args.relax_pre, args.relax_post)
+        roofline["other_timed"][k] = {"kernel": lab, "total_ms": prof[k]["ms"], "achieved": prof[k]["gbs"],
+                                      "frac": prof[k]["gbs"] / HBM_PEAK_GBS, "avg_us": prof[k]["avg_us"],
+                                      "traffic": measured_traffic(tf, ts) if tf else None}
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
