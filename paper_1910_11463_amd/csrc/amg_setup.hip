@@ -80,12 +80,13 @@ k_strength_fused(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* _
 }
 
 // The strong (theta) entries of each row, in column order, as their own CSR
-// (scol at srp[i] ..): the PMIS rounds read only these.  G lanes per row.
+// (scol / sval at srp[i] ..): the PMIS rounds and the interpolation read only
+// these.  G lanes per row.
 template <int G>
 __global__ void __launch_bounds__(256)
 k_strong_fill(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-              const uint8_t* __restrict__ sflag, const int64_t* __restrict__ srp,
-              int32_t* __restrict__ scol) {
+              const double* __restrict__ val, const uint8_t* __restrict__ sflag,
+              const int64_t* __restrict__ srp, int32_t* __restrict__ scol, double* __restrict__ sval) {
     const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / G;
     const int sub = threadIdx.x % G;
     const int lane = threadIdx.x & 63;
@@ -97,7 +98,11 @@ k_strong_fill(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __re
         const int64_t e = e0 + sub;
         const bool st = e < re && (sflag[e] & 1);
         const uint64_t m = __ballot(st) & gmask;
-        if (st) scol[pos + __popcll(m & ((1ull << lane) - 1ull))] = col[e];
+        if (st) {
+            const int64_t q = pos + __popcll(m & ((1ull << lane) - 1ull));
+            scol[q] = col[e];
+            sval[q] = val[e];
+        }
         pos += __popcll(m);
     }
 }
@@ -367,8 +372,8 @@ k_cf_counts(int64_t n, const int64_t* __restrict__ rowptr, const int8_t* __restr
 // candidates are combined by (magnitude, column)).
 template <int G>
 __global__ void __launch_bounds__(256)
-k_interp(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-         const double* __restrict__ val, const uint8_t* __restrict__ sflag, const int8_t* __restrict__ cf,
+k_interp(int64_t n, const int64_t* __restrict__ srp, const int32_t* __restrict__ scol,
+         const double* __restrict__ sval, const int8_t* __restrict__ cf,
          const int32_t* __restrict__ cmap, int32_t* __restrict__ p, int32_t* __restrict__ c2f) {
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / G;
     const int sub = threadIdx.x % G;
@@ -384,10 +389,11 @@ k_interp(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restric
     }
     double best = -1.0;
     int32_t bj = 0x7fffffff;
-    for (int64_t e = rowptr[i] + sub; e < rowptr[i + 1]; e += G) {
-        const int32_t j = col[e];
-        if ((sflag[e] & 1) && cf[j] > 0) {
-            const double a = fabs(val[e]);
+    const int64_t se = srp[i + 1];
+    for (int64_t e = srp[i] + sub; e < se; e += G) {
+        const int32_t j = scol[e];
+        if (cf[j] > 0) {
+            const double a = fabs(sval[e]);
             if (a > best || (a == best && j < bj)) { best = a; bj = j; }
         }
     }
@@ -1665,8 +1671,9 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         PAIR_LAUNCH_CHECK();
         const int64_t nstrong = exclusive_scan(scnt.p, srp.p, n, s_);
         DBuf<int32_t> scol(std::max<int64_t>(nstrong, 1));
+        DBuf<double> sval(std::max<int64_t>(nstrong, 1));
         hipLaunchKernelGGL(k_strong_fill<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n,
-                           L.A.rowptr.p, L.A.col.p, sflag.p, srp.p, scol.p);
+                           L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, srp.p, scol.p, sval.p);
         PAIR_LAUNCH_CHECK();
 
         // PMIS: list-driven rounds, host check every few rounds
@@ -1770,8 +1777,8 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         }
         // interpolation and coarse-to-fine map
         DBuf<int32_t> c2f(total_c);
-        hipLaunchKernelGGL(k_interp<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
-                           L.A.col.p, L.A.val.p, sflag.p, L.cf.p, cmap.p, L.p.p, c2f.p);
+        hipLaunchKernelGGL(k_interp<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n, srp.p,
+                           scol.p, sval.p, L.cf.p, cmap.p, L.p.p, c2f.p);
         PAIR_LAUNCH_CHECK();
 
         // restriction
