@@ -600,11 +600,13 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
                 if (sub == 0) { double t = rhs[g][p]; rhs[g][p] = rhs[g][piv]; rhs[g][piv] = t; }
             }
             __syncthreads();
-            if (go && sub > p && sub < K) {
-                const double l = Mloc[g][sub * LD + p] / Mloc[g][p * LD + p];
-                for (int c = p + 1; c < K; ++c) Mloc[g][sub * LD + c] -= l * Mloc[g][p * LD + c];
-                rhs[g][sub] -= l * rhs[g][p];
-            }
+            // every lane runs the wave's trip count; lanes with nothing to
+            // eliminate use l = 0 (rows and columns beyond K are zero, so they
+            // stay unchanged)
+            const bool upd = go && sub > p && sub < K;
+            const double l = upd ? Mloc[g][sub * LD + p] / Mloc[g][p * LD + p] : 0.0;
+            for (int c = p + 1; c < Kw; ++c) Mloc[g][sub * LD + c] -= l * Mloc[g][p * LD + c];
+            rhs[g][sub] -= l * rhs[g][p];
             __syncthreads();
         }
         // back substitution by columns: lane r finishes z_r, every lane above
