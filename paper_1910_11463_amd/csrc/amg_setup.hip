@@ -1240,6 +1240,7 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
 // and the range is written out by the whole wave, coalesced; otherwise each
 // thread writes its row directly.
 constexpr int kMergeR = 4;
+constexpr int kMergePB = 4;   // entries of each list held in registers
 constexpr int kMergeStage = 2048;
 
 template <bool NUMERIC>
@@ -1274,9 +1275,24 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
     if (have) {
         const int64_t rs = r_rowptr[I];
         const int rl = static_cast<int>(r_rowptr[I + 1] - rs);   // <= kMergeR
+        // each list's next kMergePB entries wait in registers (loaded together,
+        // so a list costs one dependent load round per kMergePB entries)
         int64_t pos[kMergeR], end[kMergeR];
         double rv[kMergeR];
-        int32_t head[kMergeR];
+        int32_t bc[kMergeR][kMergePB];
+        double bv[kMergeR][kMergePB];
+        int nb[kMergeR];
+        auto refill = [&](int t) {
+#pragma unroll
+            for (int q = 0; q < kMergePB; ++q) {
+                const int64_t e = pos[t] + q;
+                const bool in = e < end[t];
+                bc[t][q] = in ? ap_col[e] : kEnd;
+                if (NUMERIC) bv[t][q] = in ? ap_val[e] : 0.0;
+            }
+            pos[t] += kMergePB;
+            nb[t] = kMergePB;
+        };
 #pragma unroll
         for (int t = 0; t < kMergeR; ++t) {
             pos[t] = 0;
@@ -1288,22 +1304,27 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
                 end[t] = pos[t] + ap_len[k];
                 rv[t] = r_val[rs + t];
             }
-            head[t] = pos[t] < end[t] ? ap_col[pos[t]] : kEnd;
+            refill(t);
         }
         const int64_t ob = NUMERIC ? c_rowptr[I] : 0;
         int64_t n = 0;
         while (true) {
-            int32_t c = head[0];
+            int32_t c = bc[0][0];
 #pragma unroll
-            for (int t = 1; t < kMergeR; ++t) c = min(c, head[t]);
+            for (int t = 1; t < kMergeR; ++t) c = min(c, bc[t][0]);
             if (c == kEnd) break;
             double acc = 0.0;
 #pragma unroll
             for (int t = 0; t < kMergeR; ++t) {
-                if (head[t] != c) continue;
-                if (NUMERIC) acc = fma(rv[t], ap_val[pos[t]], acc);
-                ++pos[t];
-                head[t] = pos[t] < end[t] ? ap_col[pos[t]] : kEnd;
+                if (bc[t][0] != c) continue;
+                if (NUMERIC) acc = fma(rv[t], bv[t][0], acc);
+#pragma unroll
+                for (int q = 0; q + 1 < kMergePB; ++q) {
+                    bc[t][q] = bc[t][q + 1];
+                    if (NUMERIC) bv[t][q] = bv[t][q + 1];
+                }
+                bc[t][kMergePB - 1] = kEnd;
+                if (--nb[t] == 0 && pos[t] < end[t]) refill(t);
             }
             if (NUMERIC) {
                 if (staged) {
