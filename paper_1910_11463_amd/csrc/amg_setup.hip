@@ -1240,7 +1240,9 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
 // and the range is written out by the whole wave, coalesced; otherwise each
 // thread writes its row directly.
 constexpr int kMergeR = 4;
-constexpr int kMergePB = 4;   // entries of each list held in registers
+// entries of each list held in registers (numeric pass: columns and values)
+template <bool NUMERIC>
+constexpr int merge_pb() { return NUMERIC ? 4 : 8; }
 constexpr int kMergeStage = 2048;
 
 template <bool NUMERIC>
@@ -1251,6 +1253,7 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
             const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
             int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
             int32_t* __restrict__ c_col, double* __restrict__ c_val) {
+    constexpr int kMergePB = merge_pb<NUMERIC>();
     constexpr int32_t kEnd = 0x7fffffff;
     __shared__ int32_t s_col[NUMERIC ? kMergeStage : 1];
     __shared__ double s_val[NUMERIC ? kMergeStage : 1];
