@@ -1698,7 +1698,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         const int64_t nstrong = exclusive_scan(scnt.p, srp.p, n, s_);
         DBuf<int32_t> scol(std::max<int64_t>(nstrong, 1));
         DBuf<double> sval(std::max<int64_t>(nstrong, 1));
-        hipLaunchKernelGGL(k_strong_fill<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n,
+        hipLaunchKernelGGL(k_strong_fill<8>, dim3(grid_for(n * 8, 256)), dim3(256), 0, s_, n,
                            L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, srp.p, scol.p, sval.p);
         PAIR_LAUNCH_CHECK();
 
