@@ -341,7 +341,7 @@ def main():
                          args.relax_pre, args.relax_post, args.relax_pre_coarse,
                          args.relax_post_coarse, args.other_streams, filter_r=args.filter_r,
                          use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z)
-        osec, ost = timed_steps(s2, other, 1, 0, cold=True)
+        osec, ost = timed_steps(s2, other, 1, 1, cold=True)
         wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
         s2.clear_cache()
         torch.cuda.synchronize()
