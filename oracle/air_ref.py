@@ -80,6 +80,7 @@ class Options:
     relax_pre: str = "FC"      # half-sweeps before the coarse correction
     relax_post: str = "FC"     # and after it ("FFC": F, F, then C)
     filter_r: float = 0.0      # phi_R: drop R entries below phi_R * row max (0: keep all)
+    nair_degree: int = 0       # > 0: nAIR restriction of this Neumann degree instead of lAIR
 
 
 def _rows(A: sp.csr_matrix):
@@ -218,6 +219,62 @@ def lair_restriction(A: sp.csr_matrix, cf: np.ndarray, opts: Options) -> sp.csr_
     return R
 
 
+def _filter_rows(R: sp.csr_matrix, ci_of_row: np.ndarray, phi: float) -> sp.csr_matrix:
+    """Filtering of R after its construction (Sec. "SOC Parameter for Building
+    R"): in row I an entry off the C point's own column ci_of_row[I] stays iff
+    |r| >= phi * max over the row's other off-C entries; the C entry stays."""
+    R = R.tocsr()
+    rows, cols, vals = [], [], []
+    for I in range(R.shape[0]):
+        c = R.indices[R.indptr[I]:R.indptr[I + 1]]
+        v = R.data[R.indptr[I]:R.indptr[I + 1]]
+        off = c != ci_of_row[I]
+        zmax = float(np.abs(v[off]).max()) if off.any() else 0.0
+        keep = ~off | (np.abs(v) >= phi * zmax)
+        rows += [I] * int(keep.sum())
+        cols += c[keep].tolist()
+        vals += v[keep].tolist()
+    out = sp.csr_matrix((vals, (rows, cols)), shape=R.shape)
+    out.sort_indices()
+    return out
+
+
+def nair_restriction(A: sp.csr_matrix, cf: np.ndarray, opts: Options) -> sp.csr_matrix:
+    """Restriction by a truncated Neumann series (nAIR, Sec. "Use of Algebraic
+    Multigrid"; the paper cites the method without a formula, so this follows
+    the ideal restriction [-A_cf A_ff^{-1}, I] with A_ff^{-1} replaced by its
+    Neumann series around the diagonal, truncated after degree d):
+
+        R_cf = -A_cf  sum_{k=0..d} (I - D_ff^{-1} A_ff)^k  D_ff^{-1},   R = [R_cf, I],
+
+    D_ff the diagonal of A_ff, all entries of A (no strength test), then the
+    same filtering with phi_R as lAIR.  Rows are the C points in index order."""
+    A = A.tocsr()
+    F = np.flatnonzero(cf < 0)
+    C = np.flatnonzero(cf > 0)
+    n = A.shape[0]
+    Aff = A[F, :][:, F]
+    Acf = A[C, :][:, F]
+    Dinv = sp.diags(1.0 / Aff.diagonal())
+    M = sp.identity(len(F), format="csr") - Dinv @ Aff
+    S = sp.identity(len(F), format="csr")
+    term = sp.identity(len(F), format="csr")
+    for _ in range(opts.nair_degree):
+        term = term @ M
+        S = S + term
+    Rcf = -(Acf @ S @ Dinv)
+    Rcf = Rcf.tocoo()
+    rows = np.concatenate([Rcf.row, np.arange(len(C))])
+    cols = np.concatenate([F[Rcf.col], C])
+    vals = np.concatenate([Rcf.data, np.ones(len(C))])
+    R = sp.csr_matrix((vals, (rows, cols)), shape=(len(C), n))
+    R.sum_duplicates()
+    R.sort_indices()
+    if opts.filter_r > 0.0:
+        R = _filter_rows(R, C, opts.filter_r)
+    return R
+
+
 def one_point_interp(A: sp.csr_matrix, S: sp.csr_matrix, cf: np.ndarray) -> np.ndarray:
     """p[i] = coarse column of row i of P (value 1), or -1 for an empty row."""
     ci = coarse_index(cf)
@@ -294,7 +351,7 @@ def setup(A: sp.csr_matrix, opts: Options = Options()) -> List[Level]:
         if nc == 0 or nc > opts.max_coarse_ratio * n:
             break
         L.cf = cf
-        L.R = lair_restriction(A, cf, opts)
+        L.R = nair_restriction(A, cf, opts) if opts.nair_degree > 0 else lair_restriction(A, cf, opts)
         L.p = one_point_interp(A, S, cf)
         L.P = p_matrix(L.p, nc)
         A = galerkin(L.R, A, L.P)

@@ -270,3 +270,72 @@ def test_vcycle_with_tile_sweeps_converges_to_sweep():
     assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
     with pytest.raises(ValueError):
         AR.vcycle(levels, bt, np.zeros_like(bt), 0, 1.0, "T", "T", "F", "")
+
+
+def test_nair_degree1_matches_entrywise_formula():
+    """Degree-1 nAIR on a small nonsymmetric matrix with a non-unit diagonal,
+    against the series written out entry by entry:
+    r_ik = -a_ik/a_kk + sum_{j in F, j != k} (a_ij/a_jj)(a_jk/a_kk), r_ii = 1."""
+    rng = np.random.default_rng(21)
+    n = 12
+    D = rng.uniform(1.5, 3.0, n)
+    M = (rng.random((n, n)) < 0.35) * rng.uniform(-1.0, 1.0, (n, n))
+    np.fill_diagonal(M, D)
+    A = sp.csr_matrix(M)
+    cf = np.array([1, -1, -1, 1, -1, -1, 1, -1, 1, -1, -1, -1])
+    R = AR.nair_restriction(A, cf, AR.Options(nair_degree=1)).toarray()
+    C = np.flatnonzero(cf > 0)
+    F = np.flatnonzero(cf < 0)
+    want = np.zeros((len(C), n))
+    for I, i in enumerate(C):
+        want[I, i] = 1.0
+        for k in F:
+            v = -M[i, k] / M[k, k]
+            for j in F:
+                if j != k:
+                    v += (M[i, j] / M[j, j]) * (M[j, k] / M[k, k])
+            want[I, k] = v
+    assert np.abs(R - want).max() <= 1e-14 * np.abs(want).max()
+
+
+def test_nair_of_high_degree_is_the_ideal_restriction_on_upwind_operators():
+    """After block scaling the F-F couplings of an upwind operator only point
+    upwind and the element blocks are I, so I - A_ff is nilpotent: the Neumann
+    series ends, and nAIR of degree >= the longest upwind chain of elements
+    (7 on 3^3 hexes) is the ideal restriction [-A_cf A_ff^{-1}, I]; degree 1
+    is not."""
+    _, _, A = _transport_matrix("hex", 3, 33, order=8)
+    S = AR.strength(A, 0.25)
+    cf = AR.pmis(S, 0, 5)
+    ideal = AR.lair_restriction(A, cf, AR.Options(distance=None)).toarray()
+    hi = AR.nair_restriction(A, cf, AR.Options(nair_degree=8)).toarray()
+    assert np.abs(hi - ideal).max() <= 1e-10 * np.abs(ideal).max()
+    lo = AR.nair_restriction(A, cf, AR.Options(nair_degree=1)).toarray()
+    assert np.abs(lo - ideal).max() > 1e-3 * np.abs(ideal).max()
+
+
+def test_nair_filter_and_vcycle():
+    """The phi_R filter acts on nAIR rows as on lAIR rows (kept entries >= phi_R
+    times the row's largest off-C magnitude, the C entry stays), and V-cycles
+    with nAIR (degree 1, phi_R = 0.1) converge to the topological sweep."""
+    prob, blk, A = _transport_matrix("hex", 4, 33, order=8)
+    S = AR.strength(A, 0.25)
+    cf = AR.pmis(S, 0, 3)
+    full = AR.nair_restriction(A, cf, AR.Options(nair_degree=1)).tocsr()
+    filt = AR.nair_restriction(A, cf, AR.Options(nair_degree=1, filter_r=0.1)).tocsr()
+    C = np.flatnonzero(cf > 0)
+    for I, i in enumerate(C):
+        c = full.indices[full.indptr[I]:full.indptr[I + 1]]
+        v = full.data[full.indptr[I]:full.indptr[I + 1]]
+        off = c != i
+        thr = 0.1 * np.abs(v[off]).max() if off.any() else 0.0
+        want = sorted(c[~off | (np.abs(v) >= thr)].tolist())
+        assert filt.indices[filt.indptr[I]:filt.indptr[I + 1]].tolist() == want
+    f = prob.rhs(33, None)
+    bt = np.einsum("eab,eb->ea", np.linalg.inv(blk.D), f).ravel()
+    levels = AR.setup(A, AR.Options(coarse_max=16, nair_degree=1, filter_r=0.1))
+    assert len(levels) >= 2
+    x, it, hist = AR.solve(levels, bt, tol=1e-12, maxit=100, pre="FCF", post="FCF")
+    assert hist[-1] <= 1e-12
+    xs = SW.sweep(blk, f).ravel()
+    assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
