@@ -125,6 +125,12 @@ typedef struct pair_options {
                                  (omega does not apply).  tile_xy: 8 (default) or 16 */
     int tile_z;               /* box height in elements; 0 (default): the mesh's whole
                                  z extent                                            */
+    int nair_degree;          /* 0 (default): lAIR restriction.  1: nAIR of Neumann
+                                 degree 1 (Sec. "Use of Algebraic Multigrid" names the
+                                 truncated-Neumann-series restriction):
+                                 R_cf = -A_cf (I + (I - D_ff^-1 A_ff)) D_ff^-1 over all
+                                 entries of A, then the filter_r filter; a row with
+                                 more than 1024 contributions is an error            */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

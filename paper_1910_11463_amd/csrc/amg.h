@@ -44,6 +44,8 @@ struct AmgParams {
     // boxes of the tile sweeps ("T", factored finest level only): tile_xy x
     // tile_xy x tile_z elements, tile_z = 0 meaning the mesh's whole z extent
     int tile_xy = 8, tile_z = 0;
+    // > 0: restriction by nAIR of this Neumann degree (only 1) instead of lAIR
+    int nair_degree = 0;
     std::shared_ptr<TuneCache> tune;   // null: fixed lanes-per-row table
     // lanes per row of the row kernels: index 0 = finest level, last entry used
     // for all deeper levels.  A function of the level index only, so that every

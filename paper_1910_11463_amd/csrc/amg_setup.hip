@@ -651,6 +651,165 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 }
 
 
+
+// nAIR rows of Neumann degree 1 (the restriction [-A_cf A_ff^{-1}, I] with
+// A_ff^{-1} replaced by the first two terms of its Neumann series around the
+// diagonal): for C point i and F point k != i,
+//   r_ik = -a_ik / a_kk + sum_{j in F, j != k} (a_ij / a_jj) (a_jk / a_kk),
+// over all entries of A (no strength test), then the phi_R filter of the lAIR
+// rows and the C point's own 1.  One wave per row accumulates into an LDS hash
+// table keyed by column: first row i's direct terms, then row j's terms for
+// one F neighbour j after the other (a row of A has distinct columns, so no two
+// lanes add to one slot at once, and every column's sum is taken in the same
+// order in every launch).  The distinct columns are then ranked and filtered.
+// Rows with more than kNairCols distinct columns (or more than kNairNbr F
+// neighbours) count in overflow[0]; rows keeping more than KCAP F entries in
+// overflow[1] (the R A P kernels stage at most KCAP + 1 entries of a row of R).
+constexpr int kNairSlots = 2048;
+constexpr int kNairCols = 1024;
+constexpr int kNairNbr = 256;
+
+template <bool COUNT>
+__global__ void __launch_bounds__(64)
+k_nair1(int nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+        const int32_t* __restrict__ col, const double* __restrict__ val, const int8_t* __restrict__ cf,
+        const double* __restrict__ dinv, double phi, int64_t* __restrict__ rcnt,
+        const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col, double* __restrict__ r_val,
+        int* __restrict__ overflow) {
+    constexpr uint32_t kEmpty = 0xffffffffu;
+    constexpr uint32_t kMask = kNairSlots - 1;
+    __shared__ uint32_t hk[kNairSlots];
+    __shared__ double hv[kNairSlots];
+    __shared__ int32_t nj[kNairNbr];
+    __shared__ double nu_[kNairNbr];
+    __shared__ int32_t uk[kNairCols];
+    __shared__ double uv[kNairCols];
+    __shared__ int s_used;
+    const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
+    // slot of column c, inserted if absent (Knuth's multiplicative hash, linear
+    // probing); kNairSlots if the table is full (the row is then rejected)
+    auto slot_of = [&](uint32_t c) -> uint32_t {
+        uint32_t h = (c * 2654435761u) & kMask;
+        for (int probe = 0; probe < kNairSlots; ++probe) {
+            const uint32_t old = atomicCAS(&hk[h], kEmpty, c);
+            if (old == kEmpty) {
+                atomicAdd(&s_used, 1);
+                return h;
+            }
+            if (old == c) return h;
+            h = (h + 1) & kMask;
+        }
+        atomicAdd(&s_used, kNairSlots);   // marks the row as too long
+        return kNairSlots;
+    };
+    for (int I = blockIdx.x; I < nc; I += gridDim.x) {
+        const int64_t i = c2f[I];
+        const int64_t rs = rowptr[i], re = rowptr[i + 1];
+        for (int h = lane; h < kNairSlots; h += 64) {
+            hk[h] = kEmpty;
+            hv[h] = 0.0;
+        }
+        if (lane == 0) s_used = 0;
+        __syncthreads();
+        // row i: direct terms -a_ik / a_kk and the F neighbours (j, a_ij / a_jj)
+        int nn = 0;
+        for (int64_t e0 = rs; e0 < re; e0 += 64) {
+            const int64_t e = e0 + lane;
+            int32_t j = -1;
+            bool f = false;
+            if (e < re) {
+                j = col[e];
+                f = cf[j] < 0;
+            }
+            const uint64_t m = __ballot(f);
+            const int q = nn + __popcll(m & below);
+            if (f) {
+                const double u = val[e] * dinv[j];
+                if (q < kNairNbr) {
+                    nj[q] = j;
+                    nu_[q] = u;
+                }
+                const uint32_t h = slot_of(static_cast<uint32_t>(j));
+                if (h < kNairSlots) hv[h] = hv[h] - u;
+            }
+            nn += __popcll(m);
+        }
+        __syncthreads();
+        bool bad = nn > kNairNbr || s_used > kNairCols;
+        // row j's terms for each F neighbour j, one neighbour at a time
+        for (int t = 0; t < nn && !bad; ++t) {
+            const int32_t j = nj[t];
+            const double u = nu_[t];
+            const int64_t js = rowptr[j], je = rowptr[j + 1];
+            for (int64_t e0 = js; e0 < je; e0 += 64) {
+                const int64_t e = e0 + lane;
+                if (e < je) {
+                    const int32_t k = col[e];
+                    if (k != j && cf[k] < 0) {
+                        const uint32_t h = slot_of(static_cast<uint32_t>(k));
+                        if (h < kNairSlots) hv[h] = fma(u * val[e], dinv[k], hv[h]);
+                    }
+                }
+            }
+            __syncthreads();
+            bad = s_used > kNairCols;
+        }
+        if (bad) {
+            if (lane == 0) atomicAdd(overflow, 1);
+            if (COUNT && lane == 0) rcnt[I] = 1;
+            __syncthreads();
+            continue;
+        }
+        // the distinct columns, ranked by column
+        int nu = 0;
+        for (int h0 = 0; h0 < kNairSlots; h0 += 64) {
+            const int h = h0 + lane;
+            const bool occ = hk[h] != kEmpty;
+            const uint64_t m = __ballot(occ);
+            const int q = nu + __popcll(m & below);
+            if (occ) {
+                uk[q] = static_cast<int32_t>(hk[h]);
+                uv[q] = hv[h];
+            }
+            nu += __popcll(m);
+        }
+        __syncthreads();
+        double mx = 0.0;
+        for (int q = lane; q < nu; q += 64) mx = fmax(mx, fabs(uv[q]));
+        for (int d = 32; d >= 1; d >>= 1) mx = fmax(mx, __shfl_xor(mx, d, 64));
+        const double thr = phi * mx;
+        int kept = 0, before = 0;
+        const int64_t ob = COUNT ? 0 : r_rowptr[I];
+        for (int q = lane; q < nu; q += 64) {
+            if (!(fabs(uv[q]) >= thr)) continue;
+            const int32_t c = uk[q];
+            if (COUNT) {
+                ++kept;
+            } else {
+                int rank = 0;   // kept columns below c
+                for (int t = 0; t < nu; ++t) rank += (fabs(uv[t]) >= thr && uk[t] < c) ? 1 : 0;
+                const int64_t o = ob + rank + (c > i ? 1 : 0);
+                r_col[o] = c;
+                r_val[o] = uv[q];
+                before += c < i ? 1 : 0;
+            }
+        }
+        if (COUNT) {
+            for (int d = 32; d >= 1; d >>= 1) kept += __shfl_xor(kept, d, 64);
+            if (lane == 0) rcnt[I] = kept + 1;
+            if (lane == 0 && kept > KCAP) atomicAdd(overflow + 1, 1);
+        } else {
+            for (int d = 32; d >= 1; d >>= 1) before += __shfl_xor(before, d, 64);
+            if (lane == 0) {
+                r_col[ob + before] = static_cast<int32_t>(i);
+                r_val[ob + before] = 1.0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Restriction rows whose local systems are the identity, z = -A(i, R_i)^T and
 // the row [z, 1] in column order.  This holds on the finest level of a block-
 // scaled operator on a structured hex mesh: R_i lies in the upwind neighbours
@@ -1809,10 +1968,27 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 
         // restriction
         DBuf<int64_t> rcnt(total_c);
-        const bool direct = l == 0 && finest_identity_;
+        const bool nair = prm_.nair_degree > 0;
+        const bool direct = l == 0 && finest_identity_ && !nair;
+        const unsigned gnair = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(total_c, 1), 1 << 20));
+        DBuf<int> novf(nair ? 2 : 0);
+        if (nair) {
+            PAIR_HIP(hipMemsetAsync(novf.p, 0, 2 * sizeof(int), s_));
+            hipLaunchKernelGGL(k_nair1<true>, dim3(gnair), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
+                               L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, prm_.filter_r, rcnt.p,
+                               nullptr, nullptr, nullptr, novf.p);
+            PAIR_LAUNCH_CHECK();
+            int ovf[2] = {0, 0};
+            d2h(ovf, novf.p, 2, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            PAIR_CHECK(ovf[0] == 0, "nAIR: a restriction row has more than 1024 contributions");
+            PAIR_CHECK(ovf[1] == 0, "nAIR: a restriction row keeps more than 64 F entries (at most 64 "
+                                    "are supported); raise filter_r");
+        }
         constexpr int kDG = 4;   // lanes per row of k_r_direct
         const unsigned gdir = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kDG - 1) / (64 / kDG), 1 << 20));
-        if (direct)
+        if (nair) {
+        } else if (direct)
             hipLaunchKernelGGL((k_r_direct<kDG, true>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
                                c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
                                prm_.filter_r, rcnt.p, nullptr, nullptr, nullptr);
@@ -1826,7 +2002,13 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.nnz = exclusive_scan(rcnt.p, L.R.rowptr.p, total_c, s_);
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
-        if (direct) {
+        if (nair) {
+            hipLaunchKernelGGL(k_nair1<false>, dim3(gnair), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
+                               L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, prm_.filter_r, nullptr,
+                               L.R.rowptr.p, L.R.col.p, L.R.val.p, novf.p);
+            PAIR_LAUNCH_CHECK();
+            PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
+        } else if (direct) {
             hipLaunchKernelGGL((k_r_direct<kDG, false>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
                                c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
                                prm_.filter_r, nullptr, L.R.rowptr.p, L.R.col.p, L.R.val.p);
@@ -1860,7 +2042,8 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         }
         int nsing = 0;
         d2h(&nsing, d_counter.p, 1, s_);
-        if (prm_.filter_r > 0.0 && !direct) filter_restriction(L, c2f.p, total_c);   // direct: filtered already
+        if (prm_.filter_r > 0.0 && !direct && !nair)
+            filter_restriction(L, c2f.p, total_c);   // direct and nAIR: filtered already
 
         // A P: merge the entries of each row of A that interpolate from the same
         // coarse point (rows classed by length); only the rows R refers to are

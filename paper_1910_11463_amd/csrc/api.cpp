@@ -99,6 +99,7 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.filter_r >= 0.0 && o.filter_r <= 1.0, "filter_r must be in [0, 1]");
     PAIR_CHECK(o.fine_factored == 0 || o.fine_factored == 1, "fine_factored must be 0 or 1");
     PAIR_CHECK(o.tile_xy == 8 || o.tile_xy == 16, "tile_xy must be 8 or 16");
+    PAIR_CHECK(o.nair_degree == 0 || o.nair_degree == 1, "nair_degree must be 0 or 1");
     PAIR_CHECK(o.tile_z >= 0 && o.tile_z <= (1 << 20), "tile_z must be in [0, 2^20]");
     constexpr size_t kS = sizeof(o.relax_pre);
     auto sched_ok = [&](const char* c, bool tiles) {
@@ -214,6 +215,7 @@ void pair_default_options(pair_options* o) {
     o->fine_factored = 1;
     o->tile_xy = 8;
     o->tile_z = 0;
+    o->nair_degree = 0;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
@@ -254,7 +256,7 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
             opt->batch_size != c.opt.batch_size || opt->streams != c.opt.streams ||
             opt->coarse_fp32 != c.opt.coarse_fp32 || opt->filter_r != c.opt.filter_r ||
             opt->fine_factored != c.opt.fine_factored || opt->tile_xy != c.opt.tile_xy ||
-            opt->tile_z != c.opt.tile_z ||
+            opt->tile_z != c.opt.tile_z || opt->nair_degree != c.opt.nair_degree ||
             std::strncmp(opt->relax_pre, c.opt.relax_pre, sizeof(opt->relax_pre)) != 0 ||
             std::strncmp(opt->relax_post, c.opt.relax_post, sizeof(opt->relax_post)) != 0 ||
             std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, sizeof(opt->relax_pre_coarse)) != 0 ||

@@ -69,6 +69,7 @@ AmgParams params_from_options(const pair_options& o) {
     p.filter_r = o.filter_r;
     p.tile_xy = o.tile_xy;
     p.tile_z = o.tile_z;
+    p.nair_degree = o.nair_degree;
     if (o.fixed_cycles > 0) {
         p.fixed_cycles = true;
         p.tol = 0.0;

@@ -42,7 +42,7 @@ def test_default_options():
     assert (o.coarse_max, o.max_levels, o.kmax) == (64, 25, 64)
     assert o.tol_inner == 1e-8 and o.max_inner == 100
     assert o.streams == 1 and o.coarse_fp32 == 0 and o.fine_factored == 1
-    assert o.tile_xy == 8 and o.tile_z == 0
+    assert o.tile_xy == 8 and o.tile_z == 0 and o.nair_degree == 0
 
 
 def test_quadrature_matches_oracle():

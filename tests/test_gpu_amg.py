@@ -27,11 +27,12 @@ CASES = [(2, 6, 5), (3, 2, 7), (5, 5, 13), (4, 6, 40)]
 
 
 def _amg(A, coarse_max, seed=0, seg=None, kmax=64, pre="FC", post="FC", max_levels=25,
-         pre_c="=", post_c="=", filter_r=0.0):
+         pre_c="=", post_c="=", filter_r=0.0, **kw):
     from paper_1910_11463_amd.solver import Amg
     a = Amg(coarse_max=coarse_max, pmis_seed=seed, tol_inner=1e-10, max_inner=200, kmax=kmax,
             relax_pre=pre.encode(), relax_post=post.encode(), max_levels=max_levels,
-            relax_pre_coarse=pre_c.encode(), relax_post_coarse=post_c.encode(), filter_r=filter_r)
+            relax_pre_coarse=pre_c.encode(), relax_post_coarse=post_c.encode(), filter_r=filter_r,
+            **kw)
     a.setup(A.indptr, A.indices, A.data, seg)
     return a
 
@@ -188,3 +189,87 @@ def test_invalid_inputs_rejected():
     C = sp.csr_matrix(np.array([[1.0, 0.5], [0.5, 1.0]]))
     with pytest.raises(B.PairError):   # coupling across two one-row segments
         a.setup(C.indptr, C.indices, C.data, [0, 1, 2])
+
+
+@pytest.mark.parametrize("cfg,scale,m,phi", [(2, 6, 5, 0.1), (3, 2, 7, 0.1), (5, 5, 13, 0.1),
+                                             (4, 6, 40, 0.1), (3, 3, 5, 0.0), (1, 4, 0, 0.0)])
+def test_nair_matches_reference(cfg, scale, m, phi):
+    """Degree-1 nAIR, every coarsening step redone on the GPU from the oracle's
+    level matrix: the C/F split exact, the restriction's kept pattern the
+    oracle's except entries within 1e-9 (relative) of the phi_R threshold, its
+    values within 1e-12 of the largest; with phi_R = 0 every computed entry
+    is kept and the rows are compared densely."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A, _ = _matrix(cfg, scale, m)
+    print("nAIR parity", cfg, scale, m, phi, A.shape, flush=True)
+    ref = AR.setup(A, AR.Options(coarse_max=64, seed=3, nair_degree=1, filter_r=phi))
+    assert len(ref) >= 2
+    for l, L in enumerate(ref[:-1]):
+        if L.cf is None:
+            break
+        one = AR.setup(L.A, AR.Options(coarse_max=64, seed=3, max_levels=2, nair_degree=1, filter_r=phi))
+        full = AR.nair_restriction(L.A, one[0].cf, AR.Options(nair_degree=1)).tocsr()
+        g = _amg(L.A, 64, 3, max_levels=2, filter_r=phi, nair_degree=1)
+        got = g.level(0)
+        g.close()
+        assert np.array_equal(got["cf"], one[0].cf.astype(np.int8)), l
+        rp, rc, rv = got["r_rowptr"], got["r_col"], got["r_val"]
+        Rr = one[0].R.tocsr()
+        scale_v = np.abs(full.data).max()
+        cpts = np.flatnonzero(one[0].cf > 0)
+        if phi == 0.0:
+            dense_g = np.zeros((len(cpts), L.A.shape[0]))
+            for I in range(len(cpts)):
+                dense_g[I, rc[rp[I]:rp[I + 1]]] = rv[rp[I]:rp[I + 1]]
+            assert np.abs(dense_g - full.toarray()).max() <= 1e-12 * scale_v, l
+            continue
+        for I, i in enumerate(cpts):
+            c0 = full.indices[full.indptr[I]:full.indptr[I + 1]]
+            v0 = full.data[full.indptr[I]:full.indptr[I + 1]]
+            off = c0 != i
+            thr = phi * (np.abs(v0[off]).max() if off.any() else 0.0)
+            want = set(Rr.indices[Rr.indptr[I]:Rr.indptr[I + 1]].tolist())
+            have = dict(zip(rc[rp[I]:rp[I + 1]].tolist(), rv[rp[I]:rp[I + 1]].tolist()))
+            assert list(have) == sorted(have), (l, I)
+            assert have.get(int(i)) == 1.0
+            for c, v in zip(c0, v0):
+                if c == i or abs(abs(v) - thr) <= 1e-9 * max(thr, 1e-300):
+                    continue
+                assert (c in have) == (c in want), (l, I, c)
+                if c in have:
+                    assert abs(have[c] - v) <= 1e-12 * scale_v, (l, I, c)
+
+
+def test_nair_transport_sweep_matches_exact_sweep():
+    """A sweep replacement with nAIR hierarchies (degree 1, phi_R = 0.1) and
+    F/C schedules converges to the oracle's exact sweep."""
+    need_gpu()
+    from oracle import source_iteration as si
+    from tests.gpu_util import oracle_problem, rel, solver_for
+    w = wl.make_config(2, scale=10)
+    s = solver_for(w, tol_inner=1e-12, max_inner=300, batch_size=16, nair_degree=1, filter_r=0.1,
+                   relax_pre="FCFCF", relax_post="FCFCF", relax_pre_coarse="F", relax_post_coarse="F")
+    psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_BATCHED)
+    assert rc == B.PAIR_OK
+    print("nAIR sweep: levels %d, V-cycles %d" % (st["levels_max"], st["vcycles_total"]), flush=True)
+    ref = si.transport_sweep(oracle_problem(w), None)
+    for k in range(len(ref)):
+        assert rel(psi[k], ref[k]) <= 1e-9, (k, rel(psi[k], ref[k]))
+    s.close()
+
+
+def test_nair_rows_beyond_the_supported_length_are_rejected():
+    """Unfiltered nAIR rows can keep more than 64 F entries (128 on the second
+    level of this 6^3 S8 direction); the R A P kernels take at most 65 entries
+    per row of R, so the setup reports an error instead of building them."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A, _ = _matrix(2, 6, 5)
+    ref = AR.setup(A, AR.Options(coarse_max=64, seed=3, nair_degree=1))
+    A1 = ref[1].A
+    assert int(np.diff(AR.nair_restriction(A1, AR.setup(A1, AR.Options(
+        coarse_max=64, seed=3, max_levels=2, nair_degree=1))[0].cf, AR.Options(nair_degree=1)).indptr).max()) > 65
+    with pytest.raises(B.PairError) as e:
+        _amg(A1, 64, 3, max_levels=2, nair_degree=1)
+    assert "more than 64" in str(e.value)
