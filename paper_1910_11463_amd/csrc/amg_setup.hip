@@ -820,6 +820,8 @@ k_nair1(int nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ row
 // phi > 0 (|z_j| >= phi max |z|, the C point's own entry kept), applied here
 // directly since |z_j| = |a_ij|.  COUNT: row lengths into rcnt; otherwise the
 // rows (offsets r_rowptr).  G lanes per row, loops uniform over the wave.
+constexpr int kDirectPerLane = 4;   // entries per lane held in registers for short rows
+
 template <int G, bool COUNT>
 __global__ void __launch_bounds__(64)
 k_r_direct(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
@@ -839,6 +841,52 @@ k_r_direct(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict
         const int64_t rs = have ? rowptr[i] : 0, re = have ? rowptr[i + 1] : 0;
         int64_t lenw = re - rs;
         for (int d = 32; d >= 1; d >>= 1) lenw = max(lenw, static_cast<int64_t>(__shfl_xor(lenw, d, 64)));
+        if (lenw <= kDirectPerLane * G && lenw - 1 <= kmax) {
+            // short rows (every row of the wave at most kDirectPerLane * G
+            // entries, so no kmax truncation): one pass over the row into
+            // registers, then the filter and the writes from them
+            int32_t cjr[kDirectPerLane];
+            double ar[kDirectPerLane];
+            bool cr[kDirectPerLane];
+            double amax = 0.0;
+#pragma unroll
+            for (int u = 0; u < kDirectPerLane; ++u) {
+                const int64_t e = rs + u * G + sub;
+                cjr[u] = -1;
+                ar[u] = 0.0;
+                cr[u] = false;
+                if (have && e < re) {
+                    cjr[u] = col[e];
+                    ar[u] = val[e];
+                    cr[u] = r_candidate(i, cjr[u], sflag[e], cf);
+                    if (cr[u]) amax = fmax(amax, fabs(ar[u]));
+                }
+            }
+            const double thr = phi > 0.0 ? phi * group_max<G>(amax) : 0.0;
+            int filled = 0, before_i = 0;
+#pragma unroll
+            for (int u = 0; u < kDirectPerLane; ++u) {
+                const bool keep = cr[u] && (phi <= 0.0 || fabs(ar[u]) >= thr);
+                const uint64_t m = __ballot(keep) & gmask;
+                const uint64_t lt = __ballot(keep && cjr[u] < i) & gmask;
+                if (!COUNT && keep) {
+                    const int64_t pos = r_rowptr[I] + filled + __popcll(m & below) + (cjr[u] > i ? 1 : 0);
+                    r_col[pos] = cjr[u];
+                    r_val[pos] = -ar[u];
+                }
+                filled += __popcll(m);
+                before_i += __popcll(lt);
+            }
+            if (have && sub == 0) {
+                if (COUNT) {
+                    rcnt[I] = filled + 1;
+                } else {
+                    r_col[r_rowptr[I] + before_i] = static_cast<int32_t>(i);
+                    r_val[r_rowptr[I] + before_i] = 1.0;
+                }
+            }
+            continue;
+        }
         int cnt = 0;
         for (int64_t e0 = 0; e0 < lenw; e0 += G) {
             const int64_t e = rs + e0 + sub;
