@@ -39,6 +39,8 @@ constexpr uint64_t KEY_NONE = ~0ull;
 
 // Fused per-row pass, G lanes per row: 1/a_ii, max_{k != i}|a_ik|, strength
 // flags of every entry and lambda (number of rows strongly depending on a column).
+constexpr int kStrengthPerLane = 4;   // entries per lane held in registers for short rows
+
 template <int G>
 __global__ void __launch_bounds__(256)
 k_strength_fused(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -51,6 +53,47 @@ k_strength_fused(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* _
     if (row >= n) return;
     const int64_t rs = rowptr[row], re = rowptr[row + 1];
     double d = 0.0, m = 0.0;
+    if (re - rs <= kStrengthPerLane * G) {
+        // short row: one pass, the entries kept in registers
+        int32_t cr[kStrengthPerLane];
+        double vr[kStrengthPerLane];
+#pragma unroll
+        for (int u = 0; u < kStrengthPerLane; ++u) {
+            const int64_t e = rs + u * G + sub;
+            cr[u] = -1;
+            vr[u] = 0.0;
+            if (e < re) {
+                cr[u] = col[e];
+                vr[u] = val[e];
+                if (cr[u] == row) d = vr[u];
+                else m = fmax(m, fabs(vr[u]));
+            }
+        }
+        m = group_max<G>(m);
+        d = group_sum<G>(d);
+        if (sub == 0) dinv[row] = d != 0.0 ? 1.0 / d : 0.0;
+        const bool on = part[seg[row]] != 0 && m > 0.0;
+        int ns = 0;
+#pragma unroll
+        for (int u = 0; u < kStrengthPerLane; ++u) {
+            const int64_t e = rs + u * G + sub;
+            if (e >= re) continue;
+            uint8_t f = 0;
+            if (on && cr[u] != row) {
+                const double a = fabs(vr[u]);
+                if (a >= theta * m) f |= 1;
+                if (a >= eps_r * m) f |= 2;
+            }
+            sflag[e] = f;
+            if (f & 1) {
+                atomicAdd(&lam[cr[u]], 1);
+                ++ns;
+            }
+        }
+        ns = group_sum_int<G>(ns);
+        if (sub == 0) scnt[row] = ns;
+        return;
+    }
     for (int64_t e = rs + sub; e < re; e += G) {
         const double v = val[e];
         if (col[e] == row) d = v;
