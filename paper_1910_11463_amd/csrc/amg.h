@@ -27,17 +27,6 @@ struct TuneCache {
     std::map<int, std::pair<int, int>> lanes;
 };
 
-// Strength of connection of the finest level as the assembly writes it: the
-// flags of every stored entry (bit 0: theta, bit 1: eps_R), lambda (how many
-// rows depend strongly on each row) and each row's number of theta-strong
-// entries, for the thresholds given.
-struct FineStrength {
-    double theta = 0.0, eps_r = 0.0;
-    DBuf<uint8_t> sflag;
-    DBuf<int> lam;
-    DBuf<int64_t> scnt;
-};
-
 struct AmgParams {
     double theta = 0.25;
     double eps_r = 0.01;
@@ -199,9 +188,6 @@ public:
     // identity (block-scaled DG operator on a structured hex mesh), so R is
     // built there without local solves.  Call before setup().
     void set_finest_identity_local_systems(bool on) { finest_identity_ = on; }
-    // strength of the finest level computed during assembly (used when every
-    // member takes part in the first coarsening and the thresholds match)
-    void set_finest_strength(std::shared_ptr<FineStrength> fs) { finest_strength_ = std::move(fs); }
     // New parameters (tolerance, iteration limit, relaxation schedule); the
     // captured cycle graph bakes them in, so it is dropped.
     void set_params(const AmgParams& p);
@@ -229,7 +215,6 @@ private:
     DBuf<int64_t> moff_d_, mcnt_d_;   // finest-level member offsets / counts
     std::shared_ptr<FineEll> ell_;
     bool finest_identity_ = false;
-    std::shared_ptr<FineStrength> finest_strength_;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr;
     double last_bytes_ = 0.0;

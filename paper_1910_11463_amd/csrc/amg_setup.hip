@@ -39,11 +39,6 @@ constexpr uint64_t KEY_NONE = ~0ull;
 
 // Fused per-row pass, G lanes per row: 1/a_ii, max_{k != i}|a_ik|, strength
 // flags of every entry and lambda (number of rows strongly depending on a column).
-__global__ void __launch_bounds__(256) k_fill_one(int64_t n, double* __restrict__ p) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i < n) p[i] = 1.0;
-}
-
 constexpr int kStrengthPerLane = 4;   // entries per lane held in registers for short rows
 
 template <int G>
@@ -1941,35 +1936,15 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         h2d(d_off.p, L.off.data(), B_, s_);
         h2d(d_cnt.p, L.cnt.data(), B_, s_);
 
-        // strength + lambda (fused with 1/a_ii); on the finest level of a
-        // structured hex mesh the assembly computed it already (the unit
-        // diagonal gives 1/a_ii = 1), when every member takes part
-        DBuf<uint8_t> sflag;
-        DBuf<int> lam;
-        DBuf<int64_t> scnt, srp(n + 1);
-        bool all_part = true;
-        for (int b = 0; b < B_; ++b)
-            if (L.off[b] >= 0 && !part[b]) all_part = false;
-        std::shared_ptr<FineStrength> fs;
-        if (l == 0) fs = std::move(finest_strength_);
-        if (fs && all_part && fs->theta == prm_.theta && fs->eps_r == prm_.eps_r &&
-            fs->sflag.n == static_cast<size_t>(L.A.nnz) && fs->lam.n == static_cast<size_t>(n)) {
-            sflag = std::move(fs->sflag);
-            lam = std::move(fs->lam);
-            scnt = std::move(fs->scnt);
-            hipLaunchKernelGGL(k_fill_one, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.dinv.p);
-            PAIR_LAUNCH_CHECK();
-        } else {
-            sflag.alloc(L.A.nnz);
-            lam.alloc(n);
-            scnt.alloc(n);
-            PAIR_HIP(hipMemsetAsync(lam.p, 0, n * sizeof(int), s_));
-            hipLaunchKernelGGL(k_strength_fused<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n,
-                               L.A.rowptr.p, L.A.col.p, L.A.val.p, L.seg.p, d_part.p, prm_.theta,
-                               prm_.eps_r, L.dinv.p, sflag.p, lam.p, scnt.p);
-            PAIR_LAUNCH_CHECK();
-        }
-        fs.reset();
+        // strength + lambda (fused with 1/a_ii)
+        DBuf<uint8_t> sflag(L.A.nnz);
+        DBuf<int> lam(n);
+        DBuf<int64_t> scnt(n), srp(n + 1);
+        PAIR_HIP(hipMemsetAsync(lam.p, 0, n * sizeof(int), s_));
+        hipLaunchKernelGGL(k_strength_fused<kRowG>, dim3(grid_for(n * kRowG, 256)), dim3(256), 0, s_, n,
+                           L.A.rowptr.p, L.A.col.p, L.A.val.p, L.seg.p, d_part.p, prm_.theta,
+                           prm_.eps_r, L.dinv.p, sflag.p, lam.p, scnt.p);
+        PAIR_LAUNCH_CHECK();
         const int64_t nstrong = exclusive_scan(scnt.p, srp.p, n, s_);
         DBuf<int32_t> scol(std::max<int64_t>(nstrong, 1));
         DBuf<double> sval(std::max<int64_t>(nstrong, 1));

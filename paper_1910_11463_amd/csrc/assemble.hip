@@ -315,9 +315,7 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
                  const double* __restrict__ sigt, const int64_t* __restrict__ elem_off,
                  int64_t* __restrict__ rowptr, int32_t* __restrict__ col, double* __restrict__ val,
                  double* __restrict__ dinv, int* __restrict__ bad, int32_t* __restrict__ ell_nbr,
-                 int32_t* __restrict__ ell_nodes, double* __restrict__ ell_val, double theta,
-                 double eps_r, uint8_t* __restrict__ sflag, int* __restrict__ lam,
-                 int64_t* __restrict__ scnt) {
+                 int32_t* __restrict__ ell_nodes, double* __restrict__ ell_val) {
     __shared__ double s_val[kHexStage];
     __shared__ int32_t s_col[kHexStage];
     const int64_t gl = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -397,7 +395,6 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
     const bool staged = hi - lo <= kHexStage;   // always, at <= 13 entries per row
     if (valid) rowptr[row_g] = rb;
     int pos = 0;
-    double mrow = 0.0;   // largest off-diagonal magnitude of the row
     for (int gi = 0; valid && gi < ng; ++gi) {
         if (gface[gi] < 0) {
             if (staged) {
@@ -425,33 +422,9 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
                 val[rb + pos] = sv;
             }
             if (ell) ell_val[(ax * 4 + j) * nrows + row_g] = sv;
-            mrow = fmax(mrow, fabs(sv));
             ++pos;
             ++j;
         }
-    }
-    if (sflag && valid) {
-        // strength of connection of the row (the test of the setup's strength
-        // pass on the same values): |a_ij| >= theta max and >= eps_r max over the
-        // off-diagonal entries; lambda counts the rows depending on each column
-        const bool on = mrow > 0.0;
-        int ns = 0;
-        for (int q = 0; q < pos; ++q) {
-            const int32_t c = staged ? s_col[rb - lo + q] : col[rb + q];
-            const double v = staged ? s_val[rb - lo + q] : val[rb + q];
-            uint8_t f = 0;
-            if (on && c != static_cast<int32_t>(row_g)) {
-                const double av = fabs(v);
-                if (av >= theta * mrow) f |= 1;
-                if (av >= eps_r * mrow) f |= 2;
-            }
-            sflag[rb + q] = f;
-            if (f & 1) {
-                atomicAdd(&lam[c], 1);
-                ++ns;
-            }
-        }
-        scnt[row_g] = ns;
     }
     __syncthreads();
     if (staged)
@@ -716,8 +689,7 @@ void fine_counts(const DeviceMesh& m, const double* omega_d, const int* dirs_d, 
 
 void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d, int B,
                    const double* sigt, const int64_t* elem_off, int64_t total_nnz, int64_t* rowptr,
-                   int32_t* col, double* val, double* dinv, FineEll& ell, FineStrength* fs,
-                   hipStream_t s) {
+                   int32_t* col, double* val, double* dinv, FineEll& ell, hipStream_t s) {
     const int nf = m.kind == PAIR_HEX8 ? 4 : 3;
     PAIR_CHECK(!ell.factored || m.kind == PAIR_HEX8, "factored form needs a structured hex mesh");
     ell.k = m.k;
@@ -731,20 +703,10 @@ void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d
     }
     DBuf<int> bad(1);
     PAIR_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-    if (fs) {
-        PAIR_CHECK(m.kind == PAIR_HEX8, "strength during assembly needs a structured hex mesh");
-        const int64_t nrows = m.n_dof() * B;
-        fs->sflag.alloc(total_nnz);
-        fs->lam.alloc(nrows);
-        fs->scnt.alloc(nrows);
-        PAIR_HIP(hipMemsetAsync(fs->lam.p, 0, nrows * sizeof(int), s));
-    }
     if (m.kind == PAIR_HEX8)
         hipLaunchKernelGGL(k_fine_hex_lanes, dim3(grid_for(m.E * B * 8, 256)), dim3(256), 0, s, m.E, m.nx,
                            m.ny, m.nz, m.ref.p, omega_d, dirs_d, B, sigt, elem_off, rowptr, col,
-                           val, dinv, bad.p, ell.nbr.p, ell.nodes.p, ell.val.p, fs ? fs->theta : 0.0,
-                           fs ? fs->eps_r : 0.0, fs ? fs->sflag.p : nullptr, fs ? fs->lam.p : nullptr,
-                           fs ? fs->scnt.p : nullptr);
+                           val, dinv, bad.p, ell.nbr.p, ell.nodes.p, ell.val.p);
     else
         hipLaunchKernelGGL(k_fine_tet, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, m.nbr.p,
                            m.unode.p, m.nvec.p, m.mass.p, omega_d, dirs_d, B, sigt, elem_off,

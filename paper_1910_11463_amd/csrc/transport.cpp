@@ -84,7 +84,7 @@ AmgParams Context::amg_params() const {
     return p;
 }
 
-Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms, bool with_strength) {
+Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     const int B = static_cast<int>(bt.dirs.size());
     const int64_t E = mesh.E, N = this->N();
     double t0 = now_ms();
@@ -135,15 +135,8 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms, bool
         h2d(fe.inflow.p, in.data(), B, s);
         PAIR_HIP(hipMemcpyAsync(fe.sigt.p, sigt.p, E * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    std::shared_ptr<FineStrength> fstr;
-    if (with_strength && mesh.kind == PAIR_HEX8) {
-        fstr = std::make_shared<FineStrength>();
-        fstr->theta = opt.theta;
-        fstr->eps_r = opt.eps_r;
-    }
     fine_assemble(mesh, omega_d.p, dirs_d.p, B, sigt.p, eoff.p, nnz, A.rowptr.p, A.col.p, A.val.p,
-                  bt.dinv.p, fe, fstr.get(), s);
-    bt.fstr = std::move(fstr);
+                  bt.dinv.p, fe, s);
     if (t_assemble_ms) *t_assemble_ms += now_ms() - t0;
     return A;
 }
@@ -151,12 +144,11 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms, bool
 void Context::assemble_batch(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     const int B = static_cast<int>(bt.dirs.size());
     const int64_t N = this->N();
-    Csr A = assemble_fine(bt, s, t_assemble_ms, true);
+    Csr A = assemble_fine(bt, s, t_assemble_ms);
     std::vector<int64_t> off(B), cn(B, N);
     for (int b = 0; b < B; ++b) off[b] = static_cast<int64_t>(b) * N;
     bt.H.reset(new Hierarchy(amg_params(), s));
     bt.H->set_finest_identity_local_systems(mesh.kind == PAIR_HEX8);
-    bt.H->set_finest_strength(std::move(bt.fstr));
     bt.H->setup(std::move(A), off, cn);
     bt.H->set_fine_ell(bt.ell);
 }

@@ -42,7 +42,6 @@ struct Batch {
     DBuf<double> dinv;                     // [B][E][k*k] element block inverses
     std::unique_ptr<Hierarchy> H;
     std::shared_ptr<FineEll> ell;          // element-block copy of the finest level
-    std::shared_ptr<FineStrength> fstr;    // finest-level strength from the assembly (hexes)
 };
 
 struct SourceSpec {
@@ -92,7 +91,7 @@ struct Context {
     // building blocks
     void check_ready() const;
     void build_batches(int mode, pair_stats* st);
-    Csr assemble_fine(Batch& b, hipStream_t st, double* t_assemble_ms, bool with_strength = false);
+    Csr assemble_fine(Batch& b, hipStream_t st, double* t_assemble_ms);
     void assemble_batch(Batch& b, hipStream_t st, double* t_assemble_ms);
     void rhs_batch(const Batch& b, const SourceSpec& src, const double* phi_in, double* out,
                    hipStream_t st);
@@ -119,8 +118,7 @@ void fine_counts(const DeviceMesh& m, const double* omega_d, const int* dirs_d, 
                  int64_t* cnt, hipStream_t s);
 void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d, int B,
                    const double* sigt, const int64_t* elem_off, int64_t total_nnz, int64_t* rowptr,
-                   int32_t* col, double* val, double* dinv, FineEll& ell, FineStrength* fs,
-                   hipStream_t s);
+                   int32_t* col, double* val, double* dinv, FineEll& ell, hipStream_t s);
 void rhs_kernel(const DeviceMesh& m, int B, const int* dirs_d, const double* dinv,
                 const double* sigs, const double* q, const double* phi, const double* ext,
                 bool ext_per_dir, int64_t N, double* out, hipStream_t s);
