@@ -273,3 +273,34 @@ def test_nair_rows_beyond_the_supported_length_are_rejected():
     with pytest.raises(B.PairError) as e:
         _amg(A1, 64, 3, max_levels=2, nair_degree=1)
     assert "more than 64" in str(e.value)
+
+
+def test_r_build_byte_count_matches_host_count():
+    """The algorithmic bytes the lAIR row kernel adds up on the device (the
+    figure behind the benchmark's roofline) equal the per-row formula evaluated
+    on the host from the hierarchy it built: per C row 40 + 14 len_i + 16 K +
+    12 sum_{j in R_i} len_j + 12 (K + 1)."""
+    need_gpu()
+    import ctypes
+    A, _ = _matrix(2, 8, 5)
+    B.check(B.pair_profile_enable(1))
+    g = _amg(A, 64, 3)
+    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    B.check(B.pair_profile_read(5, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    B.check(B.pair_profile_enable(0))
+    want = 0
+    for l in range(g.num_levels() - 1):
+        lv = g.level(l)
+        rp, cf, rr, rc = lv["rowptr"], lv["cf"], lv["r_rowptr"], lv["r_col"]
+        if rr is None:
+            continue
+        lens = np.diff(rp)
+        for I, i in enumerate(np.flatnonzero(cf > 0)):
+            cols = rc[rr[I]:rr[I + 1]]
+            cols = cols[cols != i]
+            K = len(cols)
+            want += 40 + 14 * int(lens[i]) + 16 * K + 12 * int(lens[cols].sum()) + 12 * (K + 1)
+    print("r_build launches", n.value, "bytes", by.value, "host", want, flush=True)
+    assert n.value > 0 and ms.value > 0.0
+    assert int(by.value) == want
+    g.close()
