@@ -708,17 +708,41 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 // Rows with more than kNairCols distinct columns (or more than kNairNbr F
 // neighbours) count in overflow[0]; rows keeping more than KCAP F entries in
 // overflow[1] (the R A P kernels stage at most KCAP + 1 entries of a row of R).
+// Table sizes: the large form takes any row up to 1024 distinct columns and
+// 256 F neighbours (40 KB of LDS per wave); the small form (9 KB, four times
+// the waves per CU) is used on levels whose rows have at most 15 entries, where
+// no row can exceed it.
 constexpr int kNairSlots = 2048;
 constexpr int kNairCols = 1024;
 constexpr int kNairNbr = 256;
+constexpr int kNairSmallSlots = 512;
+constexpr int kNairSmallCols = 256;
+constexpr int kNairSmallNbr = 32;
+constexpr int kNairSmallRowLen = 15;   // 1 + 15 + 15 * 15 <= kNairSmallCols
+// medium form (20 KB) on the other levels; its rows that do not fit are
+// deferred to the large form
+constexpr int kNairMidSlots = 1024;
+constexpr int kNairMidCols = 512;
+constexpr int kNairMidNbr = 96;
 
-template <bool COUNT>
+__global__ void __launch_bounds__(256) k_max_row_len(int64_t n, const int64_t* __restrict__ rowptr,
+                                                     int* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    int len = i < n ? static_cast<int>(rowptr[i + 1] - rowptr[i]) : 0;
+    for (int d = 32; d >= 1; d >>= 1) len = max(len, __shfl_xor(len, d, 64));
+    if ((threadIdx.x & 63) == 0 && len > 0) atomicMax(out, len);
+}
+
+// DEFER: a row that does not fit is left to the large form (COUNT marks it
+// with rcnt = -1 and counts it in overflow[3]) instead of being an error.
+// rows: the C rows to do (null: all nc).
+template <bool COUNT, int kNairSlots, int kNairCols, int kNairNbr, bool DEFER>
 __global__ void __launch_bounds__(64)
-k_nair1(int nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
-        const int32_t* __restrict__ col, const double* __restrict__ val, const int8_t* __restrict__ cf,
-        const double* __restrict__ dinv, double phi, int64_t* __restrict__ rcnt,
-        const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col, double* __restrict__ r_val,
-        int* __restrict__ overflow) {
+k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2f,
+        const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, const double* __restrict__ val,
+        const int8_t* __restrict__ cf, const double* __restrict__ dinv, double phi,
+        int64_t* __restrict__ rcnt, const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
+        double* __restrict__ r_val, int* __restrict__ overflow) {
     constexpr uint32_t kEmpty = 0xffffffffu;
     constexpr uint32_t kMask = kNairSlots - 1;
     __shared__ uint32_t hk[kNairSlots];
@@ -746,7 +770,8 @@ k_nair1(int nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ row
         atomicAdd(&s_used, kNairSlots);   // marks the row as too long
         return kNairSlots;
     };
-    for (int I = blockIdx.x; I < nc; I += gridDim.x) {
+    for (int r = blockIdx.x; r < nc; r += gridDim.x) {
+        const int I = rows ? rows[r] : r;
         const int64_t i = c2f[I];
         const int64_t rs = rowptr[i], re = rowptr[i + 1];
         for (int h = lane; h < kNairSlots; h += 64) {
@@ -799,8 +824,15 @@ k_nair1(int nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ row
             bad = s_used > kNairCols;
         }
         if (bad) {
-            if (lane == 0) atomicAdd(overflow, 1);
-            if (COUNT && lane == 0) rcnt[I] = 1;
+            if (DEFER) {
+                if (COUNT && lane == 0) {
+                    rcnt[I] = -1;
+                    atomicAdd(overflow + 3, 1);
+                }
+            } else {
+                if (lane == 0) atomicAdd(overflow, 1);
+                if (COUNT && lane == 0) rcnt[I] = 1;
+            }
             __syncthreads();
             continue;
         }
@@ -2062,22 +2094,46 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         const bool nair = prm_.nair_degree > 0;
         const bool direct = l == 0 && finest_identity_ && !nair;
         const unsigned gnair = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(total_c, 1), 1 << 20));
-        DBuf<int> novf(nair ? 2 : 0);
+        constexpr int kDG = 4;   // lanes per row of k_r_direct
+        const unsigned gdir = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kDG - 1) / (64 / kDG), 1 << 20));
+        DBuf<int> novf(nair ? 4 : 0);
+        bool nair_small = false;
+        DBuf<int32_t> nair_def[2];   // class 0: the deferred rows
+        int nair_ndef[2] = {0, 0};
         if (nair) {
-            PAIR_HIP(hipMemsetAsync(novf.p, 0, 2 * sizeof(int), s_));
-            hipLaunchKernelGGL(k_nair1<true>, dim3(gnair), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
-                               L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, prm_.filter_r, rcnt.p,
-                               nullptr, nullptr, nullptr, novf.p);
-            PAIR_LAUNCH_CHECK();
-            int ovf[2] = {0, 0};
-            d2h(ovf, novf.p, 2, s_);
+            PAIR_HIP(hipMemsetAsync(novf.p, 0, 4 * sizeof(int), s_));
+            hipLaunchKernelGGL(k_max_row_len, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
+                               novf.p + 2);
+            int maxlen = 0;
+            d2h(&maxlen, novf.p + 2, 1, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            PAIR_CHECK(ovf[0] == 0, "nAIR: a restriction row has more than 1024 contributions");
+            nair_small = maxlen <= kNairSmallRowLen;
+#define PAIR_NAIR_COUNT(N, ROWS) N, ROWS, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, \
+                                 prm_.filter_r, rcnt.p, nullptr, nullptr, nullptr, novf.p
+            if (nair_small)
+                hipLaunchKernelGGL((k_nair1<true, kNairSmallSlots, kNairSmallCols, kNairSmallNbr, false>), dim3(gnair),
+                                   dim3(64), 0, s_, PAIR_NAIR_COUNT(static_cast<int>(total_c), nullptr));
+            else
+                hipLaunchKernelGGL((k_nair1<true, kNairMidSlots, kNairMidCols, kNairMidNbr, true>), dim3(gnair),
+                                   dim3(64), 0, s_, PAIR_NAIR_COUNT(static_cast<int>(total_c), nullptr));
+            PAIR_LAUNCH_CHECK();
+            int ovf[4] = {0, 0, 0, 0};
+            d2h(ovf, novf.p, 4, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            if (ovf[3] > 0) {
+                classify<2>(total_c, 2, nullptr, rcnt.p, {-1}, nair_def, nair_ndef, s_);
+                const unsigned gd = static_cast<unsigned>(std::min(nair_ndef[0], 1 << 20));
+                hipLaunchKernelGGL((k_nair1<true, kNairSlots, kNairCols, kNairNbr, false>), dim3(gd), dim3(64), 0,
+                                   s_, PAIR_NAIR_COUNT(nair_ndef[0], nair_def[0].p));
+                PAIR_LAUNCH_CHECK();
+                d2h(ovf, novf.p, 2, s_);
+                PAIR_HIP(hipStreamSynchronize(s_));
+            }
+#undef PAIR_NAIR_COUNT
+            PAIR_CHECK(ovf[0] == 0, "nAIR: a restriction row has more than 1024 distinct columns");
             PAIR_CHECK(ovf[1] == 0, "nAIR: a restriction row keeps more than 64 F entries (at most 64 "
                                     "are supported); raise filter_r");
         }
-        constexpr int kDG = 4;   // lanes per row of k_r_direct
-        const unsigned gdir = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kDG - 1) / (64 / kDG), 1 << 20));
         if (nair) {
         } else if (direct)
             hipLaunchKernelGGL((k_r_direct<kDG, true>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
@@ -2094,9 +2150,20 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
         if (nair) {
-            hipLaunchKernelGGL(k_nair1<false>, dim3(gnair), dim3(64), 0, s_, static_cast<int>(total_c), c2f.p,
-                               L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, prm_.filter_r, nullptr,
-                               L.R.rowptr.p, L.R.col.p, L.R.val.p, novf.p);
+#define PAIR_NAIR_FILL(N, ROWS) N, ROWS, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, \
+                                prm_.filter_r, nullptr, L.R.rowptr.p, L.R.col.p, L.R.val.p, novf.p
+            if (nair_small)
+                hipLaunchKernelGGL((k_nair1<false, kNairSmallSlots, kNairSmallCols, kNairSmallNbr, false>),
+                                   dim3(gnair), dim3(64), 0, s_, PAIR_NAIR_FILL(static_cast<int>(total_c), nullptr));
+            else
+                hipLaunchKernelGGL((k_nair1<false, kNairMidSlots, kNairMidCols, kNairMidNbr, true>), dim3(gnair),
+                                   dim3(64), 0, s_, PAIR_NAIR_FILL(static_cast<int>(total_c), nullptr));
+            if (nair_ndef[0] > 0) {
+                const unsigned gd = static_cast<unsigned>(std::min(nair_ndef[0], 1 << 20));
+                hipLaunchKernelGGL((k_nair1<false, kNairSlots, kNairCols, kNairNbr, false>), dim3(gd), dim3(64), 0,
+                                   s_, PAIR_NAIR_FILL(nair_ndef[0], nair_def[0].p));
+            }
+#undef PAIR_NAIR_FILL
             PAIR_LAUNCH_CHECK();
             PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
         } else if (direct) {

@@ -304,3 +304,45 @@ def test_r_build_byte_count_matches_host_count():
     assert n.value > 0 and ms.value > 0.0
     assert int(by.value) == want
     g.close()
+
+
+def test_nair_rows_with_many_neighbours_match_reference():
+    """nAIR rows with more F neighbours than the medium kernel holds (about 120
+    per row here, above its 96) are finished by the large kernel: a random
+    nonsymmetric matrix with 30% of entries filled, filtered with phi_R = 0.5,
+    against the oracle on the same matrix (split exact, kept pattern exact away
+    from the threshold, values within 1e-12)."""
+    need_gpu()
+    from oracle import air_ref as AR
+    rng = np.random.default_rng(17)
+    n = 400
+    M = (rng.random((n, n)) < 0.3) * rng.uniform(-1.0, 1.0, (n, n))
+    np.fill_diagonal(M, rng.uniform(40.0, 60.0, n))
+    A = sp.csr_matrix(M)
+    phi = 0.5
+    one = AR.setup(A, AR.Options(coarse_max=64, seed=3, max_levels=2, nair_degree=1, filter_r=phi))
+    full = AR.nair_restriction(A, one[0].cf, AR.Options(nair_degree=1)).tocsr()
+    cpts = np.flatnonzero(one[0].cf > 0)
+    fpts = one[0].cf < 0
+    nn = [int(fpts[A.indices[A.indptr[i]:A.indptr[i + 1]]].sum()) for i in cpts]
+    assert min(nn) > 96
+    g = _amg(A, 64, 3, max_levels=2, filter_r=phi, nair_degree=1)
+    got = g.level(0)
+    g.close()
+    assert np.array_equal(got["cf"], one[0].cf.astype(np.int8))
+    rp, rc, rv = got["r_rowptr"], got["r_col"], got["r_val"]
+    Rr = one[0].R.tocsr()
+    scale_v = np.abs(full.data).max()
+    for I, i in enumerate(cpts):
+        c0 = full.indices[full.indptr[I]:full.indptr[I + 1]]
+        v0 = full.data[full.indptr[I]:full.indptr[I + 1]]
+        off = c0 != i
+        thr = phi * np.abs(v0[off]).max()
+        want = set(Rr.indices[Rr.indptr[I]:Rr.indptr[I + 1]].tolist())
+        have = dict(zip(rc[rp[I]:rp[I + 1]].tolist(), rv[rp[I]:rp[I + 1]].tolist()))
+        for c, v in zip(c0, v0):
+            if c == i or abs(abs(v) - thr) <= 1e-9 * thr:
+                continue
+            assert (c in have) == (c in want), (I, c)
+            if c in have:
+                assert abs(have[c] - v) <= 1e-12 * scale_v
