@@ -12,7 +12,8 @@
 //      (strongest strong C-neighbour, smallest column on ties);
 //   5. lAIR restriction: per C-point i, the eps_R-strong F-neighbours R_i
 //      (at most kmax, the largest |a_ij| kept), z solving
-//      A(R_i,R_i)^T z = -A(i,R_i)^T, row [z, 1];
+//      A(R_i,R_i)^T z = -A(i,R_i)^T, row [z, 1] (or, as an option, nAIR: a
+//      truncated Neumann series for A_ff^{-1}); then the phi_R filter;
 //   6. Galerkin product A_c = R (A P): rows of A P merge the entries of A that
 //      interpolate from the same coarse point (sorted by (column, position),
 //      summed in position order); each row of R (A P) collects its distinct

@@ -1,12 +1,15 @@
-// AIR V(1,1) cycles with FC-Jacobi relaxation on all members of a hierarchy.
+// AIR V-cycles on all members of a hierarchy.
 //
 // Per level (Sec. "Use of Algebraic Multigrid": F-relaxation complements the
 // coarse-grid correction of AIR; pointwise Jacobi relaxation, Sec. "pAIR
-// Performance for Transport"):
-//   pre:  Jacobi over F-points, then over C-points   (x_i += w (b_i - (Ax)_i)/a_ii)
+// Performance for Transport"; relaxation by an on-processor forward solve):
+//   pre:  the level's schedule of relaxations: Jacobi over F-points ("F") or
+//         C-points ("C"), x_i += w (b_i - (Ax)_i)/a_ii, or on the finest level
+//         of a structured hex mesh a tile sweep ("T": block Jacobi over boxes of
+//         elements with an exact forward solve inside each box)
 //   r = b - A x;   b_c = R r;   recurse (dense inverse on a member's coarsest level)
 //   x += P x_c  (one-point interpolation by value)
-//   post: Jacobi over F-points, then over C-points
+//   post: the level's post-smoothing schedule
 // Every kernel covers all members present on a level in one launch; rows of
 // members that have converged (active = 0) or whose coarsest level this is
 // (relax = 0) are skipped.  Convergence is tested on |b - A x| / |b| of the

@@ -10,7 +10,7 @@
 namespace pair {
 
 enum ProfKind : int {
-    PROF_RELAX_FINE = 0,     // FC-Jacobi half-sweeps on the finest level
+    PROF_RELAX_FINE = 0,     // finest-level relaxation (F/C half-sweeps, tile sweeps)
     PROF_RESIDUAL_FINE = 1,  // r = b - A x on the finest level
     PROF_RESTRICT_FINE = 2,  // b_c = R r from the finest level
     PROF_RELAX_COARSE = 3,   // half-sweeps on all coarser levels
