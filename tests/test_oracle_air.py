@@ -339,3 +339,56 @@ def test_nair_filter_and_vcycle():
     assert hist[-1] <= 1e-12
     xs = SW.sweep(blk, f).ravel()
     assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
+
+
+# ---- distance-2 lAIR (Sec. "Use of Algebraic Multigrid": the neighbourhood of
+# a C point reaches F points within two strong connections)
+
+@pytest.mark.parametrize("kind,n,m", CASES)
+def test_distance2_pattern_is_two_hop_strong_f_reach(kind, n, m):
+    """Each row's F pattern is the set of F points reached from its C point by
+    one or two eps_R-strong connections through F points, written here as the
+    nonzeros of S_F + S_F S_F (S_F: the strength matrix with only F columns),
+    and the local ideal restriction holds on it: (R A)(i, R_i) = 0."""
+    _, _, A = _transport_matrix(kind, n, m)
+    S = AR.strength(A, 0.25)
+    cf = AR.pmis(S, 0, 5)
+    opts = AR.Options(distance=2)
+    R = AR.lair_restriction(A, cf, opts).tocsr()
+    SR = AR.strength(A, opts.eps_r).astype(bool).astype(np.int64)
+    DF = sp.diags((cf < 0).astype(np.int64))
+    SF = (SR @ DF).tocsr()
+    reach = (SF + SF @ SF).tocsr()
+    RA = (R @ A).tocsr()
+    longer = 0
+    R1 = AR.lair_restriction(A, cf, AR.Options(distance=1, kmax=10 ** 6)).tocsr()
+    for I, i in enumerate(np.flatnonzero(cf > 0)):
+        want = set(reach.indices[reach.indptr[i]:reach.indptr[i + 1]].tolist()) - {int(i)}
+        got = set(R.indices[R.indptr[I]:R.indptr[I + 1]].tolist()) - {int(i)}
+        assert got == want, I
+        have1 = set(R1.indices[R1.indptr[I]:R1.indptr[I + 1]].tolist()) - {int(i)}
+        assert have1 <= got
+        longer += len(got) > len(have1)
+        row = dict(zip(RA.indices[RA.indptr[I]:RA.indptr[I + 1]].tolist(),
+                       RA.data[RA.indptr[I]:RA.indptr[I + 1]].tolist()))
+        for k in got:
+            assert abs(row.get(k, 0.0)) <= 1e-12 * max(1.0, abs(A).max()), (I, k)
+    assert longer > 0
+
+
+def test_distance2_is_ideal_on_upwind_chain_with_short_f_runs():
+    """On a 1D upwind chain (lower bidiagonal) whose F runs have at most two
+    points, A_ff^{-1} couples each F point only to the F points up to two
+    steps upwind, so distance-2 lAIR equals the ideal restriction
+    -A_cf A_ff^{-1}; distance 1 misses the second upwind F point."""
+    n = 13
+    c = np.random.default_rng(4).uniform(0.5, 1.0, n)
+    A = (sp.eye(n) - sp.diags(c[1:], -1)).tocsr()
+    cf = np.where(np.arange(n) % 3 == 0, 1, -1).astype(np.int8)
+    ideal = AR.lair_restriction(A, cf, AR.Options(distance=None)).toarray()
+    d2 = AR.lair_restriction(A, cf, AR.Options(distance=2)).toarray()
+    d1 = AR.lair_restriction(A, cf, AR.Options(distance=1)).toarray()
+    assert np.abs(d2 - ideal).max() <= 1e-15
+    assert np.abs(d1 - ideal).max() > 0.1
+    # the ideal row of C point 3 by hand: -a_32 (A_ff^{-1})_{2,:} over F = {1, 2}
+    assert np.isclose(ideal[1, 2], c[3]) and np.isclose(ideal[1, 1], c[3] * c[2])
