@@ -57,7 +57,13 @@ enum { PAIR_PLAIN = 0, PAIR_BATCHED = 1 };
  * Space"; eq. soc), distance-1 lAIR, pointwise Jacobi relaxation (Sec. "pAIR
  * Performance for Transport"), here applied as FC-Jacobi in V(1,1) cycles. */
 typedef struct pair_options {
-    int lair_distance;        /* 1 (only distance 1 is implemented)             */
+    int lair_distance;        /* 1 (default): R_i = the eps_R-strong F neighbours
+                                 of C point i, at most kmax.  2: those and their own
+                                 eps_R-strong F neighbours, untruncated (Sec. "Use
+                                 of Algebraic Multigrid"); a local system of more
+                                 than 512 F points, or a row of R keeping more than
+                                 64 F entries after the filter_r filter, is an error.
+                                 Ignored when nair_degree > 0.                     */
     double theta;             /* coarsening strength threshold (0.25)           */
     double eps_r;             /* strength threshold for the pattern of R (0.01) */
     double omega;             /* Jacobi damping (1.0)                           */

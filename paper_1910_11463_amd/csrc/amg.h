@@ -46,6 +46,8 @@ struct AmgParams {
     int tile_xy = 8, tile_z = 0;
     // > 0: restriction by nAIR of this Neumann degree (only 1) instead of lAIR
     int nair_degree = 0;
+    // 2: distance-2 lAIR neighbourhoods (ignored when nair_degree > 0)
+    int lair_distance = 1;
     std::shared_ptr<TuneCache> tune;   // null: fixed lanes-per-row table
     // lanes per row of the row kernels: index 0 = finest level, last entry used
     // for all deeper levels.  A function of the level index only, so that every

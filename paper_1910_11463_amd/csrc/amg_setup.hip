@@ -11,7 +11,8 @@
 //   4. coarse numbering (exclusive scan), one-point interpolation by value
 //      (strongest strong C-neighbour, smallest column on ties);
 //   5. lAIR restriction: per C-point i, the eps_R-strong F-neighbours R_i
-//      (at most kmax, the largest |a_ij| kept), z solving
+//      (at most kmax, the largest |a_ij| kept; or, at distance 2, those and
+//      their own eps_R-strong F-neighbours, untruncated), z solving
 //      A(R_i,R_i)^T z = -A(i,R_i)^T, row [z, 1] (or, as an option, nAIR: a
 //      truncated Neumann series for A_ff^{-1}); then the phi_R filter;
 //   6. Galerkin product A_c = R (A P): rows of A P merge the entries of A that
@@ -694,6 +695,234 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
     }
 }
 
+
+// Distance-2 lAIR rows: R_i holds the eps_R-strong F neighbours of C point i
+// and, through each of them, their eps_R-strong F neighbours (no kmax
+// truncation).  One 256-thread block per row (grid-stride).  The pattern is
+// gathered into an LDS hash set; COUNT writes rcnt = K + 1, the largest K into
+// ctl[1] and flags rows of more than kD2Max F points in ctl[0].  Otherwise the
+// set is sorted by column and A(R_i,R_i)^T z = -A(i,R_i)^T is solved in a
+// dense K x K slice of `work` (ld x ld doubles per block, row-major) by
+// Gaussian elimination with partial pivoting (ties to the smaller row) and
+// back substitution; a singular system gives z = 0 and counts in `singular`.
+constexpr int kD2Max = 512;      // largest local system
+constexpr int kD2Slots = 2048;   // LDS hash set of a row's pattern
+
+// Adds column c to the set.  Inserts stop once more than kD2Max columns are in
+// (the row is then an overflow), so at most kD2Max + 256 slots ever fill and
+// every probe sequence meets an empty slot or c.
+__device__ __forceinline__ void d2_insert(int* hs, int* nset, int* ovf, int c) {
+    if (*reinterpret_cast<volatile int*>(nset) > kD2Max) {
+        *ovf = 1;
+        return;
+    }
+    unsigned h = (static_cast<unsigned>(c) * 2654435761u) & (kD2Slots - 1);
+    for (int p = 0; p < kD2Slots; ++p) {
+        const int prev = atomicCAS(&hs[h], -1, c);
+        if (prev == -1) {
+            if (atomicAdd(nset, 1) >= kD2Max) *ovf = 1;
+            return;
+        }
+        if (prev == c) return;
+        h = (h + 1) & (kD2Slots - 1);
+    }
+    *ovf = 1;
+}
+
+// First index of the sorted cols[0, K) holding a value >= c.
+__device__ __forceinline__ int d2_lower(const int* cols, int K, int c) {
+    int lo = 0, hi = K;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cols[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <bool COUNT>
+__global__ void __launch_bounds__(256)
+k_r_dist2(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+          const int32_t* __restrict__ col, const double* __restrict__ val, const uint8_t* __restrict__ sflag,
+          const int8_t* __restrict__ cf, int64_t* __restrict__ rcnt, int* __restrict__ ctl,
+          const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col, double* __restrict__ r_val,
+          double* __restrict__ work, int ld, int* __restrict__ singular) {
+    __shared__ int hs[kD2Slots];
+    __shared__ int cols[kD2Max + 256];
+    __shared__ int tmp[kD2Max + 256];
+    __shared__ double rhs[kD2Max];
+    __shared__ double lm[kD2Max];
+    __shared__ double red_v[4];
+    __shared__ int red_i[4];
+    __shared__ int nd1, nset, ovf, npiv;
+    __shared__ double pval;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double* M = COUNT ? nullptr : work + static_cast<size_t>(blockIdx.x) * ld * ld;
+    for (int I = blockIdx.x; I < nrows; I += gridDim.x) {
+        const int64_t i = c2f[I];
+        const int64_t rs = rowptr[i], re = rowptr[i + 1];
+        for (int q = t; q < kD2Slots; q += 256) hs[q] = -1;
+        if (t == 0) {
+            nd1 = 0;
+            nset = 0;
+            ovf = 0;
+        }
+        __syncthreads();
+        // distance 1: the strong F neighbours of i, listed and put in the set
+        for (int64_t e = rs + t; e < re; e += 256) {
+            const int32_t j = col[e];
+            if (r_candidate(i, j, sflag[e], cf)) {
+                const int q = atomicAdd(&nd1, 1);
+                if (q < kD2Max) tmp[q] = j;
+                else ovf = 1;
+                d2_insert(hs, &nset, &ovf, j);
+            }
+        }
+        __syncthreads();
+        // distance 2: the strong F neighbours of each of them
+        const int n1 = min(nd1, kD2Max);
+        for (int q = 0; q < n1; ++q) {
+            const int64_t j = tmp[q];
+            const int64_t js = rowptr[j], je = rowptr[j + 1];
+            for (int64_t e = js + t; e < je; e += 256) {
+                const int32_t k = col[e];
+                if (k != i && r_candidate(j, k, sflag[e], cf)) d2_insert(hs, &nset, &ovf, k);
+            }
+        }
+        __syncthreads();
+        const int K = nset;
+        if (COUNT) {
+            if (t == 0) {
+                rcnt[I] = ovf ? 1 : K + 1;
+                if (ovf) atomicOr(&ctl[0], 1);
+                else atomicMax(&ctl[1], K);
+            }
+            __syncthreads();   // the next row clears the LDS
+            continue;
+        }
+        // the set, compacted and sorted by column (rank = number of smaller columns)
+        if (t == 0) nd1 = 0;
+        __syncthreads();
+        for (int q = t; q < kD2Slots; q += 256) {
+            const int c = hs[q];
+            if (c >= 0) tmp[atomicAdd(&nd1, 1)] = c;
+        }
+        __syncthreads();
+        for (int a = t; a < K; a += 256) {
+            const int c = tmp[a];
+            int r = 0;
+            for (int b = 0; b < K; ++b) r += tmp[b] < c ? 1 : 0;
+            cols[r] = c;
+        }
+        for (int a = t; a < K; a += 256) rhs[a] = 0.0;
+        for (int r = w; r < K; r += 4)
+            for (int c = lane; c < K; c += 64) M[r * ld + c] = 0.0;
+        __syncthreads();
+        // M[r][c] = A(cols[c], cols[r]) (wave w takes rows c = w, w + 4, ... of A);
+        // rhs[r] = -A(i, cols[r])
+        for (int c = w; c < K; c += 4) {
+            const int64_t jc = cols[c];
+            const int64_t js = rowptr[jc], je = rowptr[jc + 1];
+            for (int64_t e = js + lane; e < je; e += 64) {
+                const int32_t cc = col[e];
+                const int pos = d2_lower(cols, K, cc);
+                if (pos < K && cols[pos] == cc) M[pos * ld + c] = val[e];
+            }
+        }
+        for (int64_t e = rs + t; e < re; e += 256) {
+            const int32_t cc = col[e];
+            const int pos = d2_lower(cols, K, cc);
+            if (pos < K && cols[pos] == cc) rhs[pos] = -val[e];
+        }
+        __syncthreads();
+        bool sing = false;
+        for (int p = 0; p < K; ++p) {
+            double v = -1.0;
+            int idx = K;
+            for (int r = p + t; r < K; r += 256) {
+                const double a = fabs(M[r * ld + p]);
+                if (a > v) {   // r increases: ties keep the smaller row
+                    v = a;
+                    idx = r;
+                }
+            }
+            for (int d = 32; d >= 1; d >>= 1) {
+                const double ov = __shfl_xor(v, d, 64);
+                const int oi = __shfl_xor(idx, d, 64);
+                if (ov > v || (ov == v && oi < idx)) {
+                    v = ov;
+                    idx = oi;
+                }
+            }
+            if (lane == 0) {
+                red_v[w] = v;
+                red_i[w] = idx;
+            }
+            __syncthreads();
+            if (t == 0) {
+                double bv = red_v[0];
+                int bi = red_i[0];
+                for (int q = 1; q < 4; ++q)
+                    if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < bi)) {
+                        bv = red_v[q];
+                        bi = red_i[q];
+                    }
+                pval = bv;
+                npiv = bi;
+            }
+            __syncthreads();
+            if (!(pval > 0.0)) {   // the same value in every thread: a uniform exit
+                sing = true;
+                break;
+            }
+            const int piv = npiv;
+            if (piv != p) {
+                for (int c = p + t; c < K; c += 256) {
+                    const double x = M[p * ld + c];
+                    M[p * ld + c] = M[piv * ld + c];
+                    M[piv * ld + c] = x;
+                }
+                if (t == 0) {
+                    const double x = rhs[p];
+                    rhs[p] = rhs[piv];
+                    rhs[piv] = x;
+                }
+            }
+            __syncthreads();
+            const double dpp = M[p * ld + p];
+            for (int r = p + 1 + t; r < K; r += 256) lm[r] = M[r * ld + p] / dpp;
+            __syncthreads();
+            for (int r = p + 1 + w; r < K; r += 4) {
+                const double l = lm[r];
+                for (int c = p + 1 + lane; c < K; c += 64) M[r * ld + c] -= l * M[p * ld + c];
+            }
+            for (int r = p + 1 + t; r < K; r += 256) rhs[r] -= lm[r] * rhs[p];
+            __syncthreads();
+        }
+        if (!sing) {
+            for (int r = K - 1; r >= 0; --r) {   // z_r into lm[r]
+                if (t == 0) lm[r] = rhs[r] / M[r * ld + r];
+                __syncthreads();
+                const double z = lm[r];
+                for (int q = t; q < r; q += 256) rhs[q] -= M[q * ld + r] * z;
+                __syncthreads();
+            }
+        }
+        if (sing && t == 0) atomicAdd(singular, 1);
+        const int64_t rb = r_rowptr[I];
+        for (int a = t; a < K; a += 256) {
+            const int pos = a + (cols[a] > i ? 1 : 0);
+            r_col[rb + pos] = cols[a];
+            r_val[rb + pos] = sing ? 0.0 : lm[a];
+        }
+        if (t == 0) {
+            const int before = d2_lower(cols, K, static_cast<int>(i));
+            r_col[rb + before] = static_cast<int32_t>(i);
+            r_val[rb + before] = 1.0;
+        }
+        __syncthreads();   // the next row reuses the LDS and the work slice
+    }
+}
 
 
 // nAIR rows of Neumann degree 1 (the restriction [-A_cf A_ff^{-1}, I] with
@@ -2093,7 +2322,10 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         // restriction
         DBuf<int64_t> rcnt(total_c);
         const bool nair = prm_.nair_degree > 0;
-        const bool direct = l == 0 && finest_identity_ && !nair;
+        const bool dist2 = prm_.lair_distance == 2 && !nair;
+        const bool direct = l == 0 && finest_identity_ && !nair && !dist2;
+        DBuf<int> d2ctl(dist2 ? 2 : 0);
+        int d2ld = 1;
         const unsigned gnair = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(total_c, 1), 1 << 20));
         constexpr int kDG = 4;   // lanes per row of k_r_direct
         const unsigned gdir = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kDG - 1) / (64 / kDG), 1 << 20));
@@ -2136,6 +2368,17 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                                     "are supported); raise filter_r");
         }
         if (nair) {
+        } else if (dist2) {
+            PAIR_HIP(hipMemsetAsync(d2ctl.p, 0, 2 * sizeof(int), s_));
+            hipLaunchKernelGGL(k_r_dist2<true>, dim3(gnair), dim3(256), 0, s_, static_cast<int>(total_c), c2f.p,
+                               L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, rcnt.p, d2ctl.p, nullptr,
+                               nullptr, nullptr, nullptr, 0, nullptr);
+            PAIR_LAUNCH_CHECK();
+            int ctl[2] = {0, 0};
+            d2h(ctl, d2ctl.p, 2, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            PAIR_CHECK(ctl[0] == 0, "distance-2 lAIR: a local system has more than 512 F points");
+            d2ld = std::max(1, ctl[1]);
         } else if (direct)
             hipLaunchKernelGGL((k_r_direct<kDG, true>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
                                c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
@@ -2167,6 +2410,19 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 #undef PAIR_NAIR_FILL
             PAIR_LAUNCH_CHECK();
             PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
+        } else if (dist2) {
+            // one dense ld x ld slice per block, at most 256 MiB in all
+            const int64_t slice = static_cast<int64_t>(d2ld) * d2ld;
+            const int64_t cap = std::max<int64_t>(1, (int64_t(256) << 20) / (slice * 8));
+            const unsigned gf = static_cast<unsigned>(std::min<int64_t>(std::min<int64_t>(total_c, cap), 4096));
+            DBuf<double> work(static_cast<size_t>(gf) * static_cast<size_t>(slice));
+            DBuf<int> rsing(1);
+            PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
+            hipLaunchKernelGGL(k_r_dist2<false>, dim3(gf), dim3(256), 0, s_, static_cast<int>(total_c), c2f.p,
+                               L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, nullptr, nullptr, L.R.rowptr.p,
+                               L.R.col.p, L.R.val.p, work.p, d2ld, rsing.p);
+            PAIR_LAUNCH_CHECK();
+            PAIR_HIP(hipMemcpyAsync(d_counter.p, rsing.p, sizeof(int), hipMemcpyDeviceToDevice, s_));
         } else if (direct) {
             hipLaunchKernelGGL((k_r_direct<kDG, false>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
                                c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
@@ -2203,6 +2459,19 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         d2h(&nsing, d_counter.p, 1, s_);
         if (prm_.filter_r > 0.0 && !direct && !nair)
             filter_restriction(L, c2f.p, total_c);   // direct and nAIR: filtered already
+        if (dist2) {
+            // the R A P kernels stage at most RMAX entries of a row of R
+            DBuf<int> mx(1);
+            PAIR_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s_));
+            hipLaunchKernelGGL(k_max_row_len, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
+                               L.R.rowptr.p, mx.p);
+            PAIR_LAUNCH_CHECK();
+            int longest = 0;
+            d2h(&longest, mx.p, 1, s_);
+            PAIR_HIP(hipStreamSynchronize(s_));
+            PAIR_CHECK(longest <= RMAX, "distance-2 lAIR: a restriction row keeps more than 64 F entries (at most "
+                                        "64 are supported); raise filter_r");
+        }
 
         // A P: merge the entries of each row of A that interpolate from the same
         // coarse point (rows classed by length); only the rows R refers to are

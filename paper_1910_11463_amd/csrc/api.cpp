@@ -83,7 +83,7 @@ void check_where(int where) {
 }
 
 void validate_options(const pair_options& o) {
-    PAIR_CHECK(o.lair_distance == 1, "only distance-1 lAIR is implemented");
+    PAIR_CHECK(o.lair_distance == 1 || o.lair_distance == 2, "lair_distance must be 1 or 2");
     PAIR_CHECK(o.theta > 0.0 && o.theta <= 1.0, "theta must be in (0, 1]");
     PAIR_CHECK(o.eps_r >= 0.0 && o.eps_r <= 1.0, "eps_r must be in [0, 1]");
     PAIR_CHECK(o.omega > 0.0 && o.omega <= 2.0, "omega must be in (0, 2]");
@@ -252,7 +252,7 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
         const bool amg_changed =
             opt->theta != c.opt.theta || opt->eps_r != c.opt.eps_r || opt->coarse_max != c.opt.coarse_max ||
             opt->max_levels != c.opt.max_levels || opt->max_coarse_ratio != c.opt.max_coarse_ratio ||
-            opt->kmax != c.opt.kmax || opt->pmis_seed != c.opt.pmis_seed ||
+            opt->lair_distance != c.opt.lair_distance || opt->kmax != c.opt.kmax || opt->pmis_seed != c.opt.pmis_seed ||
             opt->batch_size != c.opt.batch_size || opt->streams != c.opt.streams ||
             opt->coarse_fp32 != c.opt.coarse_fp32 || opt->filter_r != c.opt.filter_r ||
             opt->fine_factored != c.opt.fine_factored || opt->tile_xy != c.opt.tile_xy ||

@@ -70,6 +70,7 @@ AmgParams params_from_options(const pair_options& o) {
     p.tile_xy = o.tile_xy;
     p.tile_z = o.tile_z;
     p.nair_degree = o.nair_degree;
+    p.lair_distance = o.lair_distance;
     if (o.fixed_cycles > 0) {
         p.fixed_cycles = true;
         p.tol = 0.0;

@@ -346,3 +346,89 @@ def test_nair_rows_with_many_neighbours_match_reference():
             assert (c in have) == (c in want), (I, c)
             if c in have:
                 assert abs(have[c] - v) <= 1e-12 * scale_v
+
+
+@pytest.mark.parametrize("cfg,scale,m,phi", [(2, 6, 5, 0.1), (3, 2, 7, 0.1), (5, 5, 13, 0.1), (4, 6, 40, 0.1),
+                                             (2, 6, 5, 0.01), (1, 4, 0, 0.0), (3, 2, 7, 0.0), (2, 4, 17, 0.0)])
+def test_distance2_matches_reference(cfg, scale, m, phi):
+    """Distance-2 lAIR, every coarsening step redone on the GPU from the
+    oracle's level matrix: the C/F split exact; the restriction's kept pattern
+    the oracle's except entries within 1e-9 (relative) of the phi_R threshold;
+    values within 1e-11 of the row set's largest (local systems of up to ~115
+    unknowns here, eliminated in a different pivot order than LAPACK's); with
+    phi_R = 0 the rows are compared densely."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A, _ = _matrix(cfg, scale, m)
+    print("distance-2 parity", cfg, scale, m, phi, A.shape, flush=True)
+    ref = AR.setup(A, AR.Options(coarse_max=64, seed=3, distance=2, filter_r=phi))
+    assert len(ref) >= 2
+    for l, L in enumerate(ref[:-1]):
+        if L.cf is None:
+            break
+        one = AR.setup(L.A, AR.Options(coarse_max=64, seed=3, max_levels=2, distance=2, filter_r=phi))
+        full = AR.lair_restriction(L.A, one[0].cf, AR.Options(distance=2)).tocsr()
+        g = _amg(L.A, 64, 3, max_levels=2, filter_r=phi, lair_distance=2)
+        got = g.level(0)
+        g.close()
+        assert np.array_equal(got["cf"], one[0].cf.astype(np.int8)), l
+        rp, rc, rv = got["r_rowptr"], got["r_col"], got["r_val"]
+        Rr = one[0].R.tocsr()
+        scale_v = np.abs(full.data).max()
+        cpts = np.flatnonzero(one[0].cf > 0)
+        if phi == 0.0:
+            assert np.array_equal(rp, full.indptr) and np.array_equal(rc, full.indices), l
+            assert np.abs(rv - full.data).max() <= 1e-11 * scale_v, l
+            continue
+        for I, i in enumerate(cpts):
+            c0 = full.indices[full.indptr[I]:full.indptr[I + 1]]
+            v0 = full.data[full.indptr[I]:full.indptr[I + 1]]
+            off = c0 != i
+            thr = phi * (np.abs(v0[off]).max() if off.any() else 0.0)
+            want = set(Rr.indices[Rr.indptr[I]:Rr.indptr[I + 1]].tolist())
+            have = dict(zip(rc[rp[I]:rp[I + 1]].tolist(), rv[rp[I]:rp[I + 1]].tolist()))
+            assert list(have) == sorted(have), (l, I)
+            assert have.get(int(i)) == 1.0
+            for c, v in zip(c0, v0):
+                if c == i or abs(abs(v) - thr) <= 1e-9 * max(thr, 1e-300):
+                    continue
+                assert (c in have) == (c in want), (l, I, c)
+                if c in have:
+                    assert abs(have[c] - v) <= 1e-11 * scale_v, (l, I, c)
+
+
+def test_distance2_transport_sweep_matches_exact_sweep():
+    """A sweep replacement with distance-2 lAIR hierarchies (phi_R = 0.1) and
+    tile-sweep schedules converges to the oracle's exact sweep."""
+    need_gpu()
+    from oracle import source_iteration as si
+    from tests.gpu_util import oracle_problem, rel, solver_for
+    w = wl.make_config(2, scale=10)
+    s = solver_for(w, tol_inner=1e-12, max_inner=300, batch_size=16, lair_distance=2, filter_r=0.1,
+                   relax_pre="TT", relax_post="TT", relax_pre_coarse="F", relax_post_coarse="F")
+    psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_BATCHED)
+    assert rc == B.PAIR_OK
+    print("distance-2 sweep: levels %d, V-cycles %d" % (st["levels_max"], st["vcycles_total"]), flush=True)
+    ref = si.transport_sweep(oracle_problem(w), None)
+    for k in range(len(ref)):
+        assert rel(psi[k], ref[k]) <= 1e-9, (k, rel(psi[k], ref[k]))
+    s.close()
+
+
+def test_distance2_rows_beyond_the_supported_length_are_rejected():
+    """Unfiltered distance-2 rows keep up to 104 F entries on the second level
+    of this 6^3 S8 direction; the R A P kernels take at most 65 entries per row
+    of R, so the setup reports an error; an unknown distance is refused."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A, _ = _matrix(2, 6, 5)
+    ref = AR.setup(A, AR.Options(coarse_max=64, seed=3, distance=2))
+    A1 = ref[1].A
+    cf1 = AR.setup(A1, AR.Options(coarse_max=64, seed=3, max_levels=2, distance=2))[0].cf
+    assert int(np.diff(AR.lair_restriction(A1, cf1, AR.Options(distance=2)).indptr).max()) > 65
+    with pytest.raises(B.PairError) as e:
+        _amg(A1, 64, 3, max_levels=2, lair_distance=2)
+    assert "more than 64" in str(e.value)
+    with pytest.raises(B.PairError) as e:
+        _amg(A1, 64, 3, max_levels=2, lair_distance=3)
+    assert e.value.code == B.PAIR_E_INVALID
