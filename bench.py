@@ -62,14 +62,14 @@ def log(*a):
 
 def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1,
                 coarse_fp32=0, filter_r=0.0, use_graph=1, fine_factored=1, omega=1.0, tile_xy=8, tile_z=0,
-                nair_degree=0):
+                nair_degree=0, lair_distance=1):
     import torch
     from paper_1910_11463_amd.solver import Solver
     s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
                relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
                autotune=1, streams=streams, coarse_fp32=coarse_fp32, filter_r=filter_r,
                use_graph=use_graph, fine_factored=fine_factored, omega=omega, tile_xy=tile_xy,
-               tile_z=tile_z, nair_degree=nair_degree)
+               tile_z=tile_z, nair_degree=nair_degree, lair_distance=lair_distance)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -261,6 +261,7 @@ def main():
     ap.add_argument("--tile-xy", type=int, default=16, help="tile sweep boxes: elements along x and y")
     ap.add_argument("--tile-z", type=int, default=0, help="tile sweep boxes: elements along z (0: all)")
     ap.add_argument("--nair-degree", type=int, default=0, help="1: nAIR restriction instead of lAIR")
+    ap.add_argument("--lair-distance", type=int, default=1, help="2: distance-2 lAIR neighbourhoods")
     ap.add_argument("--filter-r", type=float, default=1.0,
                     help="phi_R: drop R entries below phi_R x the row's largest (0 = keep all)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -292,7 +293,8 @@ def main():
     s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                     args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse,
                     args.streams, filter_r=args.filter_r, use_graph=int(args.graph), omega=args.omega,
-                    tile_xy=args.tile_xy, tile_z=args.tile_z, nair_degree=args.nair_degree)
+                    tile_xy=args.tile_xy, tile_z=args.tile_z, nair_degree=args.nair_degree,
+                    lair_distance=args.lair_distance)
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
     phi64 = timed_steps.last_phi.clone()
@@ -387,30 +389,31 @@ def main():
                           "cold_dof_dirs_per_s": N * M / ssec4, "warm_dof_dirs_per_s": N * M / wsec4,
                           "vcycles_total": st4["vcycles_total"]}
             s4.close()
-        # nAIR (Neumann degree 1) restriction instead of lAIR, phi_R = 0.1 (the
-        # paper's nAIR setting), the same schedules
-        try:
-            s5 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                             args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                             args.relax_post_coarse, args.streams, filter_r=0.1,
-                             use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z,
-                             nair_degree=1)
-            nsec, nst = timed_steps(s5, mode, 1, 1, cold=True)
-            nwsec, _ = timed_steps(s5, mode, 1, 0, cold=False)
-            s5.clear_cache()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s5.prepare(mode)
-            torch.cuda.synchronize()
-            nssec = time.perf_counter() - t0
-            extra["nair_degree1"] = {"filter_r": 0.1, "cold_dof_dirs_per_s": N * M / nsec,
-                                     "warm_dof_dirs_per_s": N * M / nwsec,
-                                     "setup_only_dof_dirs_per_s": N * M / nssec,
-                                     "vcycles_total": nst["vcycles_total"],
-                                     "op_complexity": nst["op_complexity"], "levels": nst["levels_max"]}
-            s5.close()
-        except Exception as e:   # reported, not fatal: an extra measurement
-            extra["nair_degree1"] = {"error": str(e)}
+        # other restrictions with phi_R = 0.1 (the paper's setting for them), the
+        # same schedules: nAIR of Neumann degree 1, and distance-2 lAIR
+        for key, kw in (("nair_degree1", dict(nair_degree=1)), ("lair_distance2", dict(lair_distance=2))):
+            try:
+                s5 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
+                                 args.relax_pre, args.relax_post, args.relax_pre_coarse,
+                                 args.relax_post_coarse, args.streams, filter_r=0.1,
+                                 use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z, **kw)
+                nsec, nst = timed_steps(s5, mode, 1, 1, cold=True)
+                nwsec, _ = timed_steps(s5, mode, 1, 0, cold=False)
+                s5.clear_cache()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s5.prepare(mode)
+                torch.cuda.synchronize()
+                nssec = time.perf_counter() - t0
+                extra[key] = {"filter_r": 0.1, "cold_dof_dirs_per_s": N * M / nsec,
+                              "warm_dof_dirs_per_s": N * M / nwsec,
+                              "setup_only_dof_dirs_per_s": N * M / nssec,
+                              "vcycles_total": nst["vcycles_total"],
+                              "op_complexity": nst["op_complexity"], "levels": nst["levels_max"]}
+                log("%s: cold %.3g, setup only %.3g DOF*dirs/s" % (key, N * M / nsec, N * M / nssec))
+                s5.close()
+            except Exception as e:   # reported, not fatal: an extra measurement
+                extra[key] = {"error": str(e)}
         extra["source_iteration"] = []
         for c in [int(x) for x in args.si.split(",") if x.strip()]:
             r = source_iteration_time(c, device, args.streams)

@@ -61,9 +61,8 @@ typedef struct pair_options {
                                  of C point i, at most kmax.  2: those and their own
                                  eps_R-strong F neighbours, untruncated (Sec. "Use
                                  of Algebraic Multigrid"); a local system of more
-                                 than 512 F points, or a row of R keeping more than
-                                 64 F entries after the filter_r filter, is an error.
-                                 Ignored when nair_degree > 0.                     */
+                                 than 512 F points is an error.  Ignored when
+                                 nair_degree > 0.                                  */
     double theta;             /* coarsening strength threshold (0.25)           */
     double eps_r;             /* strength threshold for the pattern of R (0.01) */
     double omega;             /* Jacobi damping (1.0)                           */

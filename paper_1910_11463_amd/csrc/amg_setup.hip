@@ -1864,7 +1864,10 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
     }
 }
 
-// Rows with more products than fit in LDS: same algorithm on global scratch.
+// Rows with more products than fit in LDS, and rows of R longer than RMAX
+// entries: same algorithm on global scratch.  A row of R of more than RMAX
+// entries is staged in the global slices of block r (sld entries each), which
+// the host provides when such rows exist.
 template <bool NUMERIC>
 __global__ void __launch_bounds__(256)
 k_rap_global(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ scratch_off,
@@ -1874,7 +1877,8 @@ k_rap_global(int nrows, const int32_t* __restrict__ list, const int64_t* __restr
              const int64_t* __restrict__ rowptr, const int* __restrict__ ap_len,
              const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
              int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
-             int32_t* __restrict__ c_col, double* __restrict__ c_val) {
+             int32_t* __restrict__ c_col, double* __restrict__ c_val, int* __restrict__ gpref,
+             int64_t* __restrict__ gbase, double* __restrict__ grv, int sld) {
     __shared__ int s_pref[RMAX + 1];
     __shared__ int64_t s_base[RMAX];
     __shared__ double s_rv[RMAX];
@@ -1884,11 +1888,15 @@ k_rap_global(int nrows, const int32_t* __restrict__ list, const int64_t* __restr
     const int64_t I = list[r];
     const int64_t o = scratch_off[r];
     const int tbl = static_cast<int>(scratch_off[r + 1] - o);
+    const bool glob = r_rowptr[I + 1] - r_rowptr[I] > RMAX;   // the same in every thread
+    int* pref = glob ? gpref + static_cast<size_t>(r) * (sld + 1) : s_pref;
+    int64_t* base = glob ? gbase + static_cast<size_t>(r) * sld : s_base;
+    double* rv = glob ? grv + static_cast<size_t>(r) * sld : s_rv;
     int nl = rap_hash_row<256, NUMERIC>(I, tbl, kscr + o, pscr + o, cscr + o / 2, vscr + o / 2,
                                         r_rowptr, r_col, r_val, rowptr, ap_len, ap_col, ap_val,
                                         NUMERIC ? c_col + c_rowptr[I] : nullptr,
-                                        NUMERIC ? c_val + c_rowptr[I] : nullptr, s_pref, s_base,
-                                        s_rv, s_cnt);
+                                        NUMERIC ? c_val + c_rowptr[I] : nullptr, pref, base,
+                                        rv, s_cnt);
     if (!NUMERIC && threadIdx.x == 0) cnt_out[I] = nl;
 }
 
@@ -1899,8 +1907,10 @@ __global__ void k_rap_ub(int64_t nc, const int64_t* __restrict__ r_rowptr,
     if (I >= nc) return;
     int64_t s = 0;
     for (int64_t e = r_rowptr[I]; e < r_rowptr[I + 1]; ++e) s += ap_len[r_col[e]];
-    // rows of at most kMergeR R entries are merged (class 0, marked by 0)
-    ub[I] = r_rowptr[I + 1] - r_rowptr[I] <= kMergeR ? 0 : (s > 0 ? s : 1);
+    // rows of at most kMergeR R entries are merged (class 0, marked by 0); rows
+    // of more than RMAX entries go to the global class (more than 2048)
+    const int64_t rl = r_rowptr[I + 1] - r_rowptr[I];
+    ub[I] = rl <= kMergeR ? 0 : (rl > RMAX ? (s > 2048 ? s : 2049) : (s > 0 ? s : 1));
 }
 
 // ------------------------------------------------------------- coarse dense inverse
@@ -2459,18 +2469,16 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         d2h(&nsing, d_counter.p, 1, s_);
         if (prm_.filter_r > 0.0 && !direct && !nair)
             filter_restriction(L, c2f.p, total_c);   // direct and nAIR: filtered already
+        int r_longest = 0;   // longest row of R when it can exceed RMAX (distance 2)
         if (dist2) {
-            // the R A P kernels stage at most RMAX entries of a row of R
+            // rows of R longer than RMAX are staged in global memory by k_rap_global
             DBuf<int> mx(1);
             PAIR_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s_));
             hipLaunchKernelGGL(k_max_row_len, dim3(grid_for(total_c, 256)), dim3(256), 0, s_, total_c,
                                L.R.rowptr.p, mx.p);
             PAIR_LAUNCH_CHECK();
-            int longest = 0;
-            d2h(&longest, mx.p, 1, s_);
+            d2h(&r_longest, mx.p, 1, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            PAIR_CHECK(longest <= RMAX, "distance-2 lAIR: a restriction row keeps more than 64 F entries (at most "
-                                        "64 are supported); raise filter_r");
         }
 
         // A P: merge the entries of each row of A that interpolate from the same
@@ -2543,6 +2551,11 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             gcols.alloc(gscr_off_h.back() / 2);
             gvals.alloc(gscr_off_h.back() / 2);
         }
+        // staging of rows of R longer than RMAX (all of them are in the global class)
+        const int sld = r_longest > RMAX ? r_longest : 0;
+        DBuf<int> gpref(sld > 0 ? static_cast<size_t>(lcount[5]) * (sld + 1) : 0);
+        DBuf<int64_t> gbase(sld > 0 ? static_cast<size_t>(lcount[5]) * sld : 0);
+        DBuf<double> grv(sld > 0 ? static_cast<size_t>(lcount[5]) * sld : 0);
                 auto run_rap = [&](bool numeric, Csr* C) {
             int64_t* cnt_out = ccnt.p;
             const int64_t* crp = numeric ? C->rowptr.p : nullptr;
@@ -2593,12 +2606,14 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                     hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[5]), dim3(256), 0, s_,
                                        lcount[5], lists[5].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
-                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
+                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval, gpref.p,
+                                       gbase.p, grv.p, sld);
                 else
                     hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[5]), dim3(256), 0, s_,
                                        lcount[5], lists[5].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
                                        gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
-                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval);
+                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval, gpref.p,
+                                       gbase.p, grv.p, sld);
                 PAIR_LAUNCH_CHECK();
             }
         };

@@ -349,14 +349,15 @@ def test_nair_rows_with_many_neighbours_match_reference():
 
 
 @pytest.mark.parametrize("cfg,scale,m,phi", [(2, 6, 5, 0.1), (3, 2, 7, 0.1), (5, 5, 13, 0.1), (4, 6, 40, 0.1),
-                                             (2, 6, 5, 0.01), (1, 4, 0, 0.0), (3, 2, 7, 0.0), (2, 4, 17, 0.0)])
+                                             (2, 6, 5, 0.01), (1, 4, 0, 0.0), (3, 2, 7, 0.0), (2, 4, 17, 0.0),
+                                             (2, 6, 5, 0.0), (5, 5, 13, 0.0), (4, 6, 40, 0.0)])
 def test_distance2_matches_reference(cfg, scale, m, phi):
     """Distance-2 lAIR, every coarsening step redone on the GPU from the
     oracle's level matrix: the C/F split exact; the restriction's kept pattern
     the oracle's except entries within 1e-9 (relative) of the phi_R threshold;
     values within 1e-11 of the row set's largest (local systems of up to ~115
     unknowns here, eliminated in a different pivot order than LAPACK's); with
-    phi_R = 0 the rows are compared densely."""
+    phi_R = 0 the rows (up to 108 entries) are compared entry by entry."""
     need_gpu()
     from oracle import air_ref as AR
     A, _ = _matrix(cfg, scale, m)
@@ -415,20 +416,46 @@ def test_distance2_transport_sweep_matches_exact_sweep():
     s.close()
 
 
-def test_distance2_rows_beyond_the_supported_length_are_rejected():
-    """Unfiltered distance-2 rows keep up to 104 F entries on the second level
-    of this 6^3 S8 direction; the R A P kernels take at most 65 entries per row
-    of R, so the setup reports an error; an unknown distance is refused."""
+def _random_matrix(n, fill, diag, seed):
+    rng = np.random.default_rng(seed)
+    M = (rng.random((n, n)) < fill) * rng.uniform(-1.0, 1.0, (n, n))
+    np.fill_diagonal(M, rng.uniform(diag, 1.5 * diag, n))
+    return sp.csr_matrix(M)
+
+
+def test_distance2_long_rows_and_large_systems_match_reference():
+    """Distance-2 rows of 90-291 entries (local systems of that size, rows of R
+    staged in global memory by the R A P kernel): a random nonsymmetric 600 x 600
+    matrix with 3% of entries filled, unfiltered, against the oracle: split
+    exact, R's pattern exact and values within 1e-11 of the largest, and the
+    Galerkin coarse operator within 1e-11 of its largest entry."""
     need_gpu()
     from oracle import air_ref as AR
-    A, _ = _matrix(2, 6, 5)
-    ref = AR.setup(A, AR.Options(coarse_max=64, seed=3, distance=2))
-    A1 = ref[1].A
-    cf1 = AR.setup(A1, AR.Options(coarse_max=64, seed=3, max_levels=2, distance=2))[0].cf
-    assert int(np.diff(AR.lair_restriction(A1, cf1, AR.Options(distance=2)).indptr).max()) > 65
+    A = _random_matrix(600, 0.03, 10.0, 29)
+    one = AR.setup(A, AR.Options(coarse_max=64, seed=3, max_levels=2, distance=2))
+    R = one[0].R.tocsr()
+    assert np.diff(R.indptr).min() > 65 and np.diff(R.indptr).max() > 256
+    g = _amg(A, 64, 3, max_levels=2, lair_distance=2)
+    got, coarse = g.level(0), g.level(1)
+    g.close()
+    assert np.array_equal(got["cf"], one[0].cf.astype(np.int8))
+    assert np.array_equal(got["r_rowptr"], R.indptr) and np.array_equal(got["r_col"], R.indices)
+    assert np.abs(got["r_val"] - R.data).max() <= 1e-11 * np.abs(R.data).max()
+    Ac = one[1].A.toarray()
+    n1 = Ac.shape[0]
+    Cg = sp.csr_matrix((coarse["val"], coarse["col"], coarse["rowptr"]), shape=(n1, n1)).toarray()
+    assert np.abs(Cg - Ac).max() <= 1e-11 * np.abs(Ac).max()
+
+
+def test_distance2_limits_are_reported():
+    """A local system of more than 512 F points (about 1430 here: a random
+    1500 x 1500 matrix with 8% of entries filled reaches nearly every F point in
+    two strong steps) is an error, and so is an unknown distance."""
+    need_gpu()
+    A = _random_matrix(1500, 0.08, 40.0, 23)
     with pytest.raises(B.PairError) as e:
-        _amg(A1, 64, 3, max_levels=2, lair_distance=2)
-    assert "more than 64" in str(e.value)
+        _amg(A, 64, 3, max_levels=2, lair_distance=2)
+    assert "more than 512" in str(e.value)
     with pytest.raises(B.PairError) as e:
-        _amg(A1, 64, 3, max_levels=2, lair_distance=3)
+        _amg(A, 64, 3, max_levels=2, lair_distance=3)
     assert e.value.code == B.PAIR_E_INVALID
