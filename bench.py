@@ -389,9 +389,10 @@ def main():
                           "cold_dof_dirs_per_s": N * M / ssec4, "warm_dof_dirs_per_s": N * M / wsec4,
                           "vcycles_total": st4["vcycles_total"]}
             s4.close()
-        # other restrictions with phi_R = 0.1 (the paper's setting for them), the
-        # same schedules: nAIR of Neumann degree 1, and distance-2 lAIR
-        for key, kw in (("nair_degree1", dict(nair_degree=1)), ("lair_distance2", dict(lair_distance=2))):
+        # nAIR of Neumann degree 1 with phi_R = 0.1 (the paper's nAIR setting), the
+        # same schedules.  (Distance-2 lAIR, --lair-distance 2, takes about a minute
+        # per step here and is left to explicit runs.)
+        for key, kw in (("nair_degree1", dict(nair_degree=1)),):
             try:
                 s5 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                                  args.relax_pre, args.relax_post, args.relax_pre_coarse,

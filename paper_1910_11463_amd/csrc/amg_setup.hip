@@ -536,7 +536,7 @@ __device__ __forceinline__ int col_pos(const int* cols, int K, int c) {
 // LDS, Gaussian elimination with partial pivoting (lane r owns row r), back
 // substitution by columns with the solution entries broadcast by shuffles.
 // Loops run to the largest K of the wave so every lane reaches every barrier.
-template <int G>
+template <int G, bool GIVEN = false>
 __global__ void __launch_bounds__(64)
 k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict__ c2f,
           const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -561,7 +561,21 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         const int64_t i = have ? c2f[I] : 0;
         const int64_t rs = have ? rowptr[i] : 0, re = have ? rowptr[i + 1] : 0;
         const int K = have ? static_cast<int>(r_rowptr[I + 1] - r_rowptr[I]) - 1 : 0;
-        r_collect<G>(have, i, rs, re, sub, lane, gmask, kmax, col, val, sflag, cf, cols[g]);
+        if (GIVEN) {
+            // the pattern is already in row I of R (sorted, with i): copy it without i
+            const int64_t rb0 = have ? r_rowptr[I] : 0;
+            int filled = 0;
+            for (int q0 = 0; q0 <= G; q0 += G) {
+                const int q = q0 + sub;
+                const int32_t c = (have && q <= K) ? r_col[rb0 + q] : -1;
+                const bool keep = c >= 0 && c != i;
+                const uint64_t m = __ballot(keep) & gmask;
+                if (keep) cols[g][filled + __popcll(m & ((1ull << lane) - 1ull))] = c;
+                filled += __popcll(m);
+            }
+        } else {
+            r_collect<G>(have, i, rs, re, sub, lane, gmask, kmax, col, val, sflag, cf, cols[g]);
+        }
         if (sub == 0) kw[g] = K;
         __syncthreads();
         int Kw = 0;
@@ -700,11 +714,14 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 // and, through each of them, their eps_R-strong F neighbours (no kmax
 // truncation).  One 256-thread block per row (grid-stride).  The pattern is
 // gathered into an LDS hash set; COUNT writes rcnt = K + 1, the largest K into
-// ctl[1] and flags rows of more than kD2Max F points in ctl[0].  Otherwise the
-// set is sorted by column and A(R_i,R_i)^T z = -A(i,R_i)^T is solved in a
+// ctl[1] and flags rows of more than kD2Max F points in ctl[0] (MODE 0).  The
+// set is then sorted by column and either written to the row of R with i
+// (MODE 1: the pattern, for k_r_build<G, true> to solve rows of K <= 64), or
+// (MODE 2, the rows of `list`) A(R_i,R_i)^T z = -A(i,R_i)^T is solved in a
 // dense K x K slice of `work` (ld x ld doubles per block, row-major) by
 // Gaussian elimination with partial pivoting (ties to the smaller row) and
 // back substitution; a singular system gives z = 0 and counts in `singular`.
+// list: the rows to do (null: all nrows).
 constexpr int kD2Max = 512;      // largest local system
 constexpr int kD2Slots = 2048;   // LDS hash set of a row's pattern
 
@@ -740,13 +757,14 @@ __device__ __forceinline__ int d2_lower(const int* cols, int K, int c) {
     return lo;
 }
 
-template <bool COUNT>
+template <int MODE>
 __global__ void __launch_bounds__(256)
-k_r_dist2(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
           const int32_t* __restrict__ col, const double* __restrict__ val, const uint8_t* __restrict__ sflag,
           const int8_t* __restrict__ cf, int64_t* __restrict__ rcnt, int* __restrict__ ctl,
           const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col, double* __restrict__ r_val,
           double* __restrict__ work, int ld, int* __restrict__ singular) {
+    constexpr bool COUNT = MODE == 0;
     __shared__ int hs[kD2Slots];
     __shared__ int cols[kD2Max + 256];
     __shared__ int tmp[kD2Max + 256];
@@ -757,8 +775,9 @@ k_r_dist2(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict_
     __shared__ int nd1, nset, ovf, npiv;
     __shared__ double pval;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    double* M = COUNT ? nullptr : work + static_cast<size_t>(blockIdx.x) * ld * ld;
-    for (int I = blockIdx.x; I < nrows; I += gridDim.x) {
+    double* M = MODE == 2 ? work + static_cast<size_t>(blockIdx.x) * ld * ld : nullptr;
+    for (int it = blockIdx.x; it < nrows; it += gridDim.x) {
+        const int64_t I = list ? list[it] : it;
         const int64_t i = c2f[I];
         const int64_t rs = rowptr[i], re = rowptr[i + 1];
         for (int q = t; q < kD2Slots; q += 256) hs[q] = -1;
@@ -813,6 +832,14 @@ k_r_dist2(int nrows, const int32_t* __restrict__ c2f, const int64_t* __restrict_
             int r = 0;
             for (int b = 0; b < K; ++b) r += tmp[b] < c ? 1 : 0;
             cols[r] = c;
+        }
+        if (MODE == 1) {   // the pattern into row I of R (with i), for k_r_build
+            __syncthreads();
+            const int64_t rb = r_rowptr[I];
+            for (int a = t; a < K; a += 256) r_col[rb + a + (cols[a] > i ? 1 : 0)] = cols[a];
+            if (t == 0) r_col[rb + d2_lower(cols, K, static_cast<int>(i))] = static_cast<int32_t>(i);
+            __syncthreads();
+            continue;
         }
         for (int a = t; a < K; a += 256) rhs[a] = 0.0;
         for (int r = w; r < K; r += 4)
@@ -1878,7 +1905,7 @@ k_rap_global(int nrows, const int32_t* __restrict__ list, const int64_t* __restr
              const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
              int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
              int32_t* __restrict__ c_col, double* __restrict__ c_val, int* __restrict__ gpref,
-             int64_t* __restrict__ gbase, double* __restrict__ grv, int sld) {
+             int64_t* __restrict__ gbase, double* __restrict__ grv, int sld, int64_t obase) {
     __shared__ int s_pref[RMAX + 1];
     __shared__ int64_t s_base[RMAX];
     __shared__ double s_rv[RMAX];
@@ -1886,8 +1913,8 @@ k_rap_global(int nrows, const int32_t* __restrict__ list, const int64_t* __restr
     const int r = blockIdx.x;
     if (r >= nrows) return;
     const int64_t I = list[r];
-    const int64_t o = scratch_off[r];
-    const int tbl = static_cast<int>(scratch_off[r + 1] - o);
+    const int64_t o = scratch_off[r] - obase;   // offsets of this launch's rows start at obase
+    const int tbl = static_cast<int>(scratch_off[r + 1] - scratch_off[r]);
     const bool glob = r_rowptr[I + 1] - r_rowptr[I] > RMAX;   // the same in every thread
     int* pref = glob ? gpref + static_cast<size_t>(r) * (sld + 1) : s_pref;
     int64_t* base = glob ? gbase + static_cast<size_t>(r) * sld : s_base;
@@ -2380,7 +2407,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         if (nair) {
         } else if (dist2) {
             PAIR_HIP(hipMemsetAsync(d2ctl.p, 0, 2 * sizeof(int), s_));
-            hipLaunchKernelGGL(k_r_dist2<true>, dim3(gnair), dim3(256), 0, s_, static_cast<int>(total_c), c2f.p,
+            hipLaunchKernelGGL(k_r_dist2<0>, dim3(gnair), dim3(256), 0, s_, static_cast<int>(total_c), nullptr, c2f.p,
                                L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, rcnt.p, d2ctl.p, nullptr,
                                nullptr, nullptr, nullptr, 0, nullptr);
             PAIR_LAUNCH_CHECK();
@@ -2421,17 +2448,43 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             PAIR_LAUNCH_CHECK();
             PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
         } else if (dist2) {
-            // one dense ld x ld slice per block, at most 256 MiB in all
-            const int64_t slice = static_cast<int64_t>(d2ld) * d2ld;
-            const int64_t cap = std::max<int64_t>(1, (int64_t(256) << 20) / (slice * 8));
-            const unsigned gf = static_cast<unsigned>(std::min<int64_t>(std::min<int64_t>(total_c, cap), 4096));
-            DBuf<double> work(static_cast<size_t>(gf) * static_cast<size_t>(slice));
+            // the patterns; then rows of K <= 64 by k_r_build (one wave, LDS), the
+            // longer ones by k_r_dist2 (one block, dense system in global memory)
+            hipLaunchKernelGGL(k_r_dist2<1>, dim3(gnair), dim3(256), 0, s_, static_cast<int>(total_c), nullptr,
+                               c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, nullptr, nullptr,
+                               L.R.rowptr.p, L.R.col.p, nullptr, nullptr, 0, nullptr);
+            PAIR_LAUNCH_CHECK();
+            DBuf<int32_t> rl[5];
+            int nrc[5];
             DBuf<int> rsing(1);
             PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
-            hipLaunchKernelGGL(k_r_dist2<false>, dim3(gf), dim3(256), 0, s_, static_cast<int>(total_c), c2f.p,
-                               L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, nullptr, nullptr, L.R.rowptr.p,
-                               L.R.col.p, L.R.val.p, work.p, d2ld, rsing.p);
-            PAIR_LAUNCH_CHECK();
+            classify<5>(total_c, 1, L.R.rowptr.p, nullptr, {8, 16, 32, 64}, rl, nrc, s_);
+            for (int c = 0; c < 4; ++c) {
+                const int nr = nrc[c];
+                if (nr == 0) continue;
+                const int rpw = 8 >> c;
+                const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
+#define PAIR_RB_ARGS nr, rl[c].p, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, \
+                     L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p, nullptr
+                if (c == 0) hipLaunchKernelGGL((k_r_build<8, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 1) hipLaunchKernelGGL((k_r_build<16, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 2) hipLaunchKernelGGL((k_r_build<32, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else hipLaunchKernelGGL((k_r_build<64, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+#undef PAIR_RB_ARGS
+                PAIR_LAUNCH_CHECK();
+            }
+            if (nrc[4] > 0) {
+                // one dense ld x ld slice per block, at most 4 GiB in all (2048
+                // blocks of the largest systems, 512 unknowns)
+                const int64_t slice = static_cast<int64_t>(d2ld) * d2ld;
+                const int64_t cap = std::max<int64_t>(1, (int64_t(4) << 30) / (slice * 8));
+                const unsigned gf = static_cast<unsigned>(std::min<int64_t>(std::min<int64_t>(nrc[4], cap), 4096));
+                DBuf<double> work(static_cast<size_t>(gf) * static_cast<size_t>(slice));
+                hipLaunchKernelGGL(k_r_dist2<2>, dim3(gf), dim3(256), 0, s_, nrc[4], rl[4].p, c2f.p, L.A.rowptr.p,
+                                   L.A.col.p, L.A.val.p, sflag.p, L.cf.p, nullptr, nullptr, L.R.rowptr.p, L.R.col.p,
+                                   L.R.val.p, work.p, d2ld, rsing.p);
+                PAIR_LAUNCH_CHECK();
+            }
             PAIR_HIP(hipMemcpyAsync(d_counter.p, rsing.p, sizeof(int), hipMemcpyDeviceToDevice, s_));
         } else if (direct) {
             hipLaunchKernelGGL((k_r_direct<kDG, false>), dim3(gdir), dim3(64), 0, s_, static_cast<int>(total_c),
@@ -2528,6 +2581,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         classify<6>(total_c, 2, nullptr, ub.p, {0, 128, 256, 1024, 2048}, lists, lcount, s_);
         // hash-table scratch for the global class: 2 * pow2(products) slots per row
         std::vector<int64_t> gscr_off_h;
+        std::vector<int> gchunks;   // first rows of the global class's launches, then lcount[5]
         DBuf<int64_t> gscr_off;
         DBuf<uint32_t> gkeys, gcols;
         DBuf<int32_t> gpos;
@@ -2546,10 +2600,22 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             }
             gscr_off.alloc(lcount[5] + 1);
             h2d(gscr_off.p, gscr_off_h.data(), lcount[5] + 1, s_);
-            gkeys.alloc(gscr_off_h.back());
-            gpos.alloc(gscr_off_h.back());
-            gcols.alloc(gscr_off_h.back() / 2);
-            gvals.alloc(gscr_off_h.back() / 2);
+            // launches over consecutive rows whose tables together hold at most
+            // kRapGlobalSlots slots (or one row), sharing one scratch
+            constexpr int64_t kRapGlobalSlots = int64_t(1) << 28;
+            int64_t most = 0;
+            for (int a = 0; a < lcount[5];) {
+                int b = a + 1;
+                while (b < lcount[5] && gscr_off_h[b + 1] - gscr_off_h[a] <= kRapGlobalSlots) ++b;
+                gchunks.push_back(a);
+                most = std::max(most, gscr_off_h[b] - gscr_off_h[a]);
+                a = b;
+            }
+            gchunks.push_back(lcount[5]);
+            gkeys.alloc(most);
+            gpos.alloc(most);
+            gcols.alloc(most / 2);
+            gvals.alloc(most / 2);
         }
         // staging of rows of R longer than RMAX (all of them are in the global class)
         const int sld = r_longest > RMAX ? r_longest : 0;
@@ -2601,19 +2667,18 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             }
 #undef PAIR_RAP_ARGS
             PAIR_LAUNCH_CHECK();
-            if (lcount[5] > 0) {
+            for (size_t k = 0; k + 1 < gchunks.size(); ++k) {
+                const int a = gchunks[k], nr = gchunks[k + 1] - a;
+                const size_t pa = sld > 0 ? static_cast<size_t>(a) * (sld + 1) : 0;
+                const size_t ba = sld > 0 ? static_cast<size_t>(a) * sld : 0;
+#define PAIR_RAPG_ARGS nr, lists[5].p + a, gscr_off.p + a, gkeys.p, gpos.p, gcols.p, gvals.p, L.R.rowptr.p, \
+                       L.R.col.p, L.R.val.p, L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval, \
+                       gpref.p + pa, gbase.p + ba, grv.p + ba, sld, gscr_off_h[a]
                 if (numeric)
-                    hipLaunchKernelGGL((k_rap_global<true>), dim3(lcount[5]), dim3(256), 0, s_,
-                                       lcount[5], lists[5].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
-                                       gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
-                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval, gpref.p,
-                                       gbase.p, grv.p, sld);
+                    hipLaunchKernelGGL((k_rap_global<true>), dim3(nr), dim3(256), 0, s_, PAIR_RAPG_ARGS);
                 else
-                    hipLaunchKernelGGL((k_rap_global<false>), dim3(lcount[5]), dim3(256), 0, s_,
-                                       lcount[5], lists[5].p, gscr_off.p, gkeys.p, gpos.p, gcols.p,
-                                       gvals.p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p,
-                                       ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval, gpref.p,
-                                       gbase.p, grv.p, sld);
+                    hipLaunchKernelGGL((k_rap_global<false>), dim3(nr), dim3(256), 0, s_, PAIR_RAPG_ARGS);
+#undef PAIR_RAPG_ARGS
                 PAIR_LAUNCH_CHECK();
             }
         };
