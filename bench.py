@@ -390,11 +390,14 @@ def main():
                           "vcycles_total": st4["vcycles_total"]}
             s4.close()
         # nAIR of Neumann degree 1 with phi_R = 0.1 (the paper's nAIR setting), the
-        # same schedules.  (Distance-2 lAIR, --lair-distance 2, takes about a minute
-        # per step here and is left to explicit runs.)
-        for key, kw in (("nair_degree1", dict(nair_degree=1)),):
+        # same schedules; and distance-2 lAIR with phi_R = 0.1 on the same workload
+        # at 32^3 elements (about a minute per step at full size: --lair-distance 2)
+        w32 = wl.make_config(args.config, scale=32)
+        for key, kw, wv in (("nair_degree1", dict(nair_degree=1), w),
+                            ("lair_distance2_32", dict(lair_distance=2), w32)):
+            Nv, Mv = wv.mesh.n_dof, wv.n_dir
             try:
-                s5 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
+                s5 = make_solver(wv, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
                                  args.relax_pre, args.relax_post, args.relax_pre_coarse,
                                  args.relax_post_coarse, args.streams, filter_r=0.1,
                                  use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z, **kw)
@@ -406,12 +409,12 @@ def main():
                 s5.prepare(mode)
                 torch.cuda.synchronize()
                 nssec = time.perf_counter() - t0
-                extra[key] = {"filter_r": 0.1, "cold_dof_dirs_per_s": N * M / nsec,
-                              "warm_dof_dirs_per_s": N * M / nwsec,
-                              "setup_only_dof_dirs_per_s": N * M / nssec,
+                extra[key] = {"workload": wv.name, "filter_r": 0.1, "cold_dof_dirs_per_s": Nv * Mv / nsec,
+                              "warm_dof_dirs_per_s": Nv * Mv / nwsec,
+                              "setup_only_dof_dirs_per_s": Nv * Mv / nssec,
                               "vcycles_total": nst["vcycles_total"],
                               "op_complexity": nst["op_complexity"], "levels": nst["levels_max"]}
-                log("%s: cold %.3g, setup only %.3g DOF*dirs/s" % (key, N * M / nsec, N * M / nssec))
+                log("%s: cold %.3g, setup only %.3g DOF*dirs/s" % (key, Nv * Mv / nsec, Nv * Mv / nssec))
                 s5.close()
             except Exception as e:   # reported, not fatal: an extra measurement
                 extra[key] = {"error": str(e)}
