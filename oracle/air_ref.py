@@ -33,6 +33,10 @@ pseudorandom number generators", OOPSLA 2014) on the key
 seed*2^40 + level*2^32 + i; the GPU library implements the same published
 generator on its own.
 
+Pinned by (tests/test_oracle_strength.py): the strength test and the kmax
+truncation on hand-written rows whose strong sets and truncated
+neighbourhoods are written out by hand (diagonal outside the maximum, ">=" on
+the threshold, absolute values, stored zeros, ties by smaller column).
 Pinned by (tests/test_oracle_air.py): the ideal-restriction identities
 (R A P equals the Schur complement A_cc - A_cf A_ff^{-1} A_fc for any
 one-point P; a two-level cycle with ideal R, exact F-solve and exact coarse

@@ -231,10 +231,30 @@ def rhs(topo: Topology, sigma_s, q, phi=None, ext=None) -> np.ndarray:
     return f
 
 
+def _tri_rule(n: int = 5):
+    """Collapsed (Duffy) Gauss rule on the reference triangle: barycentric
+    coordinates [q,3] and weights [q] summing to 1 (the rule integrates a
+    function's mean over the triangle; multiply by the area)."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    x = 0.5 * (x + 1.0)
+    w = 0.5 * w
+    lam, wt = [], []
+    for s, ws in zip(x, w):
+        for t, wt_ in zip(x, w):
+            l1 = s
+            l2 = t * (1.0 - s)
+            lam.append((1.0 - l1 - l2, l1, l2))
+            wt.append(2.0 * ws * wt_ * (1.0 - s))
+    return np.array(lam), np.array(wt)
+
+
 def inflow_rhs(topo: Topology, blocks: Blocks, g: Callable) -> np.ndarray:
-    """-sum_{inflow boundary faces} (Omega.n) int_f g phi_a  (hex meshes), with a
-    5x5 Gauss rule on each face.  g maps points [n,3] -> values [n]."""
-    assert topo.kind == 0
+    """-sum_{inflow boundary faces} (Omega.n) int_f g phi_a  (eq.
+    weak_form_transport, the inflow term on Gamma^-), integrated by quadrature:
+    a 5x5 Gauss rule on each hex face, a 25-point collapsed Gauss rule on each
+    tet face.  g maps points [n,3] -> values [n]."""
+    if topo.kind == 1:
+        return _tet_inflow_rhs(topo, blocks, g)
     xg, wg = np.polynomial.legendre.leggauss(5)
     xg = 0.5 * (xg + 1.0)
     wg = 0.5 * wg
@@ -263,6 +283,55 @@ def inflow_rhs(topo: Topology, blocks: Blocks, g: Callable) -> np.ndarray:
                     c2 = t2 if (a >> o2) & 1 else 1.0 - t2
                     out[ids, a] -= blocks.odn[ids, f] * wt * gv * c1 * c2
     return out
+
+
+def _tet_inflow_rhs(topo: Topology, blocks: Blocks, g: Callable) -> np.ndarray:
+    """Tet faces: the P1 basis of a face node is its barycentric coordinate on
+    the face, and the face area is |nvec|/2."""
+    lam, wq = _tri_rule(5)
+    out = np.zeros((topo.E, 4))
+    X = topo.xyz[topo.elem_vert]                      # [E,4,3]
+    for f in range(4):
+        sel = (blocks.odn[:, f] < 0.0) & (topo.nbr[:, f] < 0)
+        if not np.any(sel):
+            continue
+        ids = np.flatnonzero(sel)
+        nodes = [a for a in range(4) if a != f]
+        P = X[ids][:, nodes]                          # [n,3,3] face vertices
+        area = 0.5 * topo.nlen[ids, f]
+        for lq, w in zip(lam, wq):
+            pts = np.einsum("j,njd->nd", lq, P)
+            gv = g(pts)
+            for j, a in enumerate(nodes):
+                out[ids, a] -= blocks.odn[ids, f] * area * w * gv * lq[j]
+    return out
+
+
+def inflow_rhs_nodal(topo: Topology, blocks: Blocks, g_nodal: np.ndarray) -> np.ndarray:
+    """The inflow term with g replaced by its nodal interpolant on each face:
+    -sum_{inflow boundary faces f} (Omega.n_f) F_f g_e, F_f the face mass
+    matrix of the element's basis and g_e [k] the values of g at the element's
+    nodes (only face nodes enter).  Equal to ``inflow_rhs`` whenever g is
+    bilinear on hex faces / linear on tet faces."""
+    g = np.asarray(g_nodal, dtype=np.float64).reshape(topo.E, topo.k)
+    out = np.zeros((topo.E, topo.k))
+    for f in range(topo.F):
+        sel = (blocks.odn[:, f] < 0.0) & (topo.nbr[:, f] < 0)
+        if not np.any(sel):
+            continue
+        Ff = _face_mass_e(topo, f, sel)               # [n,k,k]
+        out[sel] -= blocks.odn[sel, f][:, None] * np.einsum("nab,nb->na", Ff, g[sel])
+    return out
+
+
+def node_coordinates(topo: Topology) -> np.ndarray:
+    """Position of every DOF's node [E*k,3] (hex: origin + corner offsets;
+    tets: the element's vertices)."""
+    if topo.kind == 0:
+        h = np.array(topo.h)
+        off = np.array([[(a >> d) & 1 for d in range(3)] for a in range(8)], dtype=np.float64) * h
+        return (topo.origin[:, None, :] + off[None]).reshape(-1, 3)
+    return topo.xyz[topo.elem_vert].reshape(-1, 3)
 
 
 def hex_origins(mesh) -> np.ndarray:

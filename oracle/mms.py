@@ -89,3 +89,27 @@ def hex_l2_error(topo: dg.Topology, u_nodal: np.ndarray, exact, npts: int = 4) -
                 uh = u @ basis
                 err += wx * wy * wz * h.prod() * np.sum((uh - exact(pts)) ** 2)
     return math.sqrt(err)
+
+
+def tet_l2_error(topo: dg.Topology, u_nodal: np.ndarray, exact, npts: int = 5) -> float:
+    """|| u_h - exact ||_{L2} with u_h the P1 DG field [E*4], by the conical
+    product (collapsed Gauss) rule on every tetrahedron: the unit cube mapped
+    onto the tet with Jacobian 6 |T| (1-u)^2 (1-v)."""
+    x, w = GL(npts)
+    x = 0.5 * (x + 1.0)
+    w = 0.5 * w
+    X = topo.xyz[topo.elem_vert]                  # [E,4,3]
+    u = u_nodal.reshape(topo.E, 4)
+    err = 0.0
+    for tu, wu in zip(x, w):
+        for tv, wv in zip(x, w):
+            for tw, ww in zip(x, w):
+                l1 = tu
+                l2 = tv * (1.0 - tu)
+                l3 = tw * (1.0 - tu) * (1.0 - tv)
+                lam = np.array([1.0 - l1 - l2 - l3, l1, l2, l3])
+                jac = 6.0 * (1.0 - tu) ** 2 * (1.0 - tv)
+                pts = np.einsum("a,ead->ed", lam, X)
+                uh = u @ lam
+                err += wu * wv * ww * jac * np.sum(topo.vol * (uh - exact(pts)) ** 2)
+    return math.sqrt(err)

@@ -34,6 +34,7 @@ class Problem:
     w: np.ndarray                # [M]
     ext: Optional[np.ndarray] = None      # dual-space source [M,N] or [N] (added to each rhs)
     inflow: Optional[object] = None       # callable g(points, omega) for inflow boundary data
+    inflow_nodal: Optional[np.ndarray] = None   # nodal inflow values [M,N] or [N] (face interpolant)
     cache_blocks: bool = True
 
     def __post_init__(self):
@@ -64,6 +65,9 @@ class Problem:
         if self.inflow is not None:
             om = self.omega[m]
             f = f + dg.inflow_rhs(self.topo, self.blocks(m), lambda p: self.inflow(p, om))
+        if self.inflow_nodal is not None:
+            g = self.inflow_nodal[m] if self.inflow_nodal.ndim == 2 else self.inflow_nodal
+            f = f + dg.inflow_rhs_nodal(self.topo, self.blocks(m), g)
         return f
 
 
