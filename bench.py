@@ -163,27 +163,52 @@ def profile_kinds():
     return out
 
 
-def cpu_baseline(w, sample_dirs, threads, repeats=2):
-    """The oracle's exact sweep (assembly + topological block solve) on a sample
-    of directions of the same workload, timed on the host: one short warm-up,
-    then the best of `repeats` timed runs."""
-    from oracle import quadrature as Q, source_iteration as si
+def host_cpu():
+    """(model name, logical CPUs) of the host, from /proc/cpuinfo."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline(w, threads, one_thread_dirs=8, repeats=5):
+    """The oracle's compiled exact sweep (closed-form Q1 element matrices,
+    octant-ordered block solves, OpenMP over directions; oracle/cpu_sweep.c)
+    on the same workload and right-hand side (phi = 0), timed on the host:
+    all M directions with `threads` threads, best of `repeats` after one
+    warm-up; and one thread on a sample of directions, best of 3."""
+    import numpy as np
+    from oracle import cpu_sweep as CS, quadrature as Q
     om, wt = Q.level_symmetric(w.sn_order)
     m = w.mats
-    prob = si.Problem(w.mesh, m.sigma_t, m.sigma_s, m.q, om, wt, cache_blocks=False)
-    M = om.shape[0]
-    dirs = [int(round(k * M / sample_dirs)) % M for k in range(sample_dirs)]
-    si.transport_sweep(prob, None, threads=threads, dirs=dirs[:threads])
-    best = None
-    for _ in range(repeats):
-        t0 = time.perf_counter()
-        si.transport_sweep(prob, None, threads=threads, dirs=dirs)
-        dt = time.perf_counter() - t0
-        best = dt if best is None else min(best, dt)
-    return {"value": w.mesh.n_dof * len(dirs) / best, "unit": "DOF*dirs/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d of %d directions (assembly + exact block sweep, numpy + C), best of %d: %.1f s"
-                      % (len(dirs), M, repeats, best)}
+    M, N = om.shape[0], w.mesh.n_dof
+    psi = np.empty((M, N))
+
+    def timed(nd, th, reps):
+        best = None
+        CS.sweep_all(w.mesh, m.sigma_t, m.sigma_s, m.q, om[:nd], wt[:nd], threads=th, psi=psi[:nd])
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            CS.sweep_all(w.mesh, m.sigma_t, m.sigma_s, m.q, om[:nd], wt[:nd], threads=th, psi=psi[:nd])
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    best = timed(M, threads, repeats)
+    nd1 = min(one_thread_dirs, M)
+    best1 = timed(nd1, 1, 3)
+    model, ncpu = host_cpu()
+    return {"value": N * M / best, "unit": "DOF*dirs/s", "cores": threads, "kind": "oracle",
+            "sample": "compiled exact sweep (closed-form Q1 blocks, OpenMP over directions), all "
+                      "%d directions x %d DOF, phi = 0 right-hand side, best of %d after a warm-up: "
+                      "%.3f s" % (M, N, repeats, best),
+            "one_thread": {"value": N * nd1 / best1, "dirs": nd1, "best_s": best1},
+            "host": {"model": model, "logical_cpus": ncpu}}
 
 
 def copy_bandwidth(mib=1024, reps=5):
@@ -243,7 +268,6 @@ def main():
     ap.add_argument("--batch-size", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--cpu-dirs", type=int, default=80)
     ap.add_argument("--si", default="1,3", help="workloads whose full source iteration is timed "
                     "(extra.source_iteration); empty for none")
     ap.add_argument("--relax-pre", default="TTT")
@@ -447,8 +471,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(w, args.cpu_dirs, threads)
-        log("cpu baseline: %.3e DOF*dirs/s (%s)" % (cpu["value"], cpu["sample"]))
+        if w.mesh.kind == 0:
+            cpu = cpu_baseline(w, threads)
+            log("cpu baseline: %.3e DOF*dirs/s on %d threads, %.3e on one (%s)" % (
+                cpu["value"], threads, cpu["one_thread"]["value"], cpu["host"]["model"]))
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF*dirs/s", "n_gpus": 1,

@@ -48,7 +48,13 @@ enum {
 };
 
 enum { PAIR_HOST = 0, PAIR_DEVICE = 1 };
-enum { PAIR_HEX8 = 0, PAIR_TET4 = 1 };
+/* Element type of pair_set_mesh.  Only tetrahedra: hexahedral meshes enter as
+ * structured lattices through pair_set_mesh_hex, because the hex path relies on
+ * the lattice (element blocks from one reference element, the factored
+ * finest-level operator and the box tile sweeps); a general hexahedral mesh with
+ * non-affine (trilinear) elements would need per-element quadrature, which this
+ * library does not build. */
+enum { PAIR_TET4 = 1 };
 enum { PAIR_PLAIN = 0, PAIR_BATCHED = 1 };
 
 /* Solver parameters.  Defaults (pair_default_options) follow the paper's
@@ -162,49 +168,86 @@ typedef struct pair_stats {
 typedef struct pair_ctx pair_ctx;
 
 /* Sizes in bytes of pair_options and pair_stats as compiled into the library,
- * so a binding can check its own struct layout.  Never fails. */
+ * so a binding can check its own struct layout (plumbing of this C ABI; no
+ * passage of the paper).  Never fails. */
 int pair_abi_sizes(int64_t* options_size, int64_t* stats_size);
 
 /* ------------------------------------------------------------------ context */
-/* Create a context.  opt == NULL uses the defaults; hip_stream == NULL uses the
- * default stream.  The library owns every internal buffer (matrices,
- * hierarchies, work vectors); they live until pair_destroy. */
+/* Create a context: one S_N transport problem (eq. mono_transport) and its
+ * pAIR solver state.  opt == NULL uses the defaults (parameters of Sec. "Weak
+ * Scaling with Parallelism in Space"); hip_stream == NULL creates a stream of
+ * the library's own.  The library owns every internal buffer (matrices,
+ * hierarchies, work vectors); they live until pair_destroy.  *out is NULL on
+ * failure.  Errors: PAIR_E_INVALID (bad options), PAIR_E_HIP. */
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream);
+/* Release a context and everything it owns (NULL is ignored). */
 void pair_destroy(pair_ctx* ctx);
+/* Message of the last failed call on ctx (owned by ctx, valid until the next
+ * call on it). */
 const char* pair_last_error(const pair_ctx* ctx);
+/* Replace the options (validated as in pair_create).  A change of any
+ * parameter the hierarchies depend on (strength thresholds, coarsening,
+ * restriction, schedules, batching) drops them; tolerances and iteration limits
+ * apply to later solves only. */
 int pair_set_options(pair_ctx* ctx, const pair_options* opt);
 
-/* Level-symmetric S_N quadrature (order 2, 4 or 8: M = 8, 24, 80 directions),
+/* Level-symmetric S_N quadrature for the discrete-ordinates sum of eq.
+ * angular_quad (order 2, 4 or 8: M = 8, 24, 80 directions),
  * weights summing to 4 pi, octant-major order (octant bit 0/1/2 set = negative
  * x/y/z cosine; triples (i,j,k) of cosine levels, i then j ascending).  omega
  * [M][3], w [M], host memory, sized by the caller (pass NULL to query *M). */
 int pair_quadrature_level_symmetric(int order, int* M, double* omega, double* w);
 
 /* ------------------------------------------------------------------ problem */
-/* Structured hex mesh nx*ny*nz of axis-aligned boxes on [lo3, hi3]. */
+/* Structured hex mesh nx*ny*nz of axis-aligned boxes on [lo3, hi3] (lo3/hi3
+ * host [3]; NULL = unit cube), trilinear Q1 DG elements with 8 nodes (Sec.
+ * "Problem Formulation": isoparametric multilinear elements, block size 8 in
+ * 3-D).  Clears materials, sources, inflow data and cached operators.
+ * PAIR_E_INVALID for non-positive sizes or more than 2^28 elements. */
 int pair_set_mesh_hex(pair_ctx* ctx, int nx, int ny, int nz, const double* lo3, const double* hi3);
 
-/* General mesh: elem_type PAIR_TET4 (P1 tets).  xyz [n_vert][3], elem_vert
+/* General mesh: elem_type PAIR_TET4 (P1 tets: the upwind DG form of eq.
+ * weak_form_transport on linear simplices).  xyz [n_vert][3], elem_vert
  * [n_elem][4], host memory, copied.  Face adjacency is built inside; an element
  * of zero volume or a face shared by more than two elements gives
- * PAIR_E_INVALID.  (Structured hexes use pair_set_mesh_hex.) */
+ * PAIR_E_INVALID.  Any other elem_type is PAIR_E_INVALID (structured hexes use
+ * pair_set_mesh_hex).  Clears materials, sources, inflow data and caches. */
 int pair_set_mesh(pair_ctx* ctx, int elem_type, int64_t n_vert, const double* xyz,
                   int64_t n_elem, const int32_t* elem_vert);
 
-/* Directions omega [M][3] (unit vectors) and weights w [M], host memory. */
+/* Discrete ordinates of eq. angular_quad: directions omega [M][3] (unit
+ * vectors) and weights w [M] > 0 summing to 4 pi (unless
+ * allow_any_weight_sum), host memory, copied.  Clears inflow data,
+ * per-direction sources and cached operators. */
 int pair_set_quadrature(pair_ctx* ctx, int M, const double* omega, const double* w);
 
-/* Element-constant total and scattering cross sections and isotropic source,
- * each [n_elem].  sigma_t > 0, sigma_s >= 0, all finite (else PAIR_E_INVALID).
- * Hierarchies are rebuilt only if sigma_t changed. */
+/* Element-constant total and scattering cross sections and isotropic source
+ * of eq. mono_transport, each [n_elem] in element order, in the memory space
+ * `where`, copied.  sigma_t > 0, sigma_s >= 0, all finite (else
+ * PAIR_E_INVALID); PAIR_E_STATE before a mesh.  The operators depend on
+ * sigma_t only, so hierarchies are rebuilt only if sigma_t changed. */
 int pair_set_materials(pair_ctx* ctx, const double* sigma_t, const double* sigma_s,
                        const double* q, int where);
 
 /* Optional extra source in dual space (already integrated against the test
- * functions, i.e. it is added to the unscaled right-hand side): src [N] for
- * every direction (per_direction = 0) or [M][N] (per_direction = 1).
- * Pass src = NULL to clear. */
+ * functions of eq. weak_form_transport, i.e. it is added to the unscaled
+ * right-hand side): src [N] for every direction (per_direction = 0) or [M][N]
+ * (per_direction = 1), copied.  Pass src = NULL to clear. */
 int pair_set_dual_source(pair_ctx* ctx, const double* src, int per_direction, int where);
+
+/* Inflow boundary data g on Gamma^- (the boundary term of eq.
+ * weak_form_transport, -int_{Gamma^-} (Omega.n) g v; default g = 0, vacuum).
+ * g [N] holds the value of g at every DOF's node (DOF layout above).  On each
+ * boundary face through which direction m enters, g is replaced by its nodal
+ * interpolant (bilinear on hex faces, linear on tet faces) and integrated
+ * exactly against the test functions, so only the values at the nodes of such
+ * faces are read.  m in [0, M): direction m; m = -1: the same g for every
+ * direction.  g = NULL sets vacuum (for direction m, or for all with m = -1).
+ * Memory space `where`, copied (host values must be finite).  Setting the mesh
+ * or the quadrature again clears the inflow data.  pair_adjoint solves its
+ * transposed systems with vacuum boundaries (g does not enter the gradient).
+ * PAIR_E_STATE before mesh and quadrature; PAIR_E_INVALID for m out of range. */
+int pair_set_inflow(pair_ctx* ctx, int m, const double* g, int where);
 
 /* -------------------------------------------------------------------- solve */
 /* Source iteration to tol_outer (Sec. "Accuracy of Spatial Solves": Richardson
@@ -231,11 +274,15 @@ int pair_transport_sweep(pair_ctx* ctx, int mode, const double* phi_in, double* 
  * receives the setup statistics: t_assemble_ms, t_setup_ms, levels, sizes. */
 int pair_prepare(pair_ctx* ctx, int mode, pair_stats* st);
 
-/* Drop cached fine operators and hierarchies (the next solve is cold). */
+/* Drop cached fine operators and hierarchies, so the next solve is cold (the
+ * paper's setting: a direction's matrix and hierarchy are built for its solve
+ * and then cleared, Sec. "pAIR Performance for Transport"). */
 int pair_clear_cache(pair_ctx* ctx);
 
 /* Adjoint gradients of J = c^T phi, with c = grad_phi (the dual-space
- * derivative dJ/dphi, [N]).  Requires a converged pair_solve with keep_psi = 1
+ * derivative dJ/dphi, [N]), for the fixed point of the block system of Sec.
+ * "Accuracy of Spatial Solves" (the derivation is the Lagrangian of that
+ * system; the paper has no adjoint).  Requires a converged pair_solve with keep_psi = 1
  * on the same context.  The adjoint system is solved with the same pAIR
  * hierarchies: the transposed DG operator of direction m is the operator of
  * the reflected direction -Omega_m, which must be in the quadrature set.
@@ -244,8 +291,10 @@ int pair_clear_cache(pair_ctx* ctx);
 int pair_adjoint(pair_ctx* ctx, int mode, const double* grad_phi, double* dJ_dsigt,
                  double* dJ_dsigs, double* phi_adj_out, int where, pair_stats* st);
 
-/* Per-direction results of the last solve: V-cycles, convergence factor and
- * final relative residual of direction m (last source iteration). */
+/* Per-direction results of the last solve: V-cycles, convergence factor
+ * (|r_k|/|r_0|)^(1/k), the quantity whose average over directions the paper
+ * reports in Sec. "pAIR Performance for Transport", and final relative
+ * residual of direction m (last source iteration).  Any pointer may be NULL. */
 int pair_direction_info(pair_ctx* ctx, int m, int* vcycles, double* cf, double* relres);
 
 /* Export the block-scaled fine operator D^{-1}A of direction m (Sec. "Sweeping
@@ -257,7 +306,9 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
                               int32_t* col, double* val, double* b);
 
 /* --------------------------------------------------------------- profiling */
-/* Per-kernel timing with HIP events recorded on the library's stream around
+/* Measurement plumbing (no passage of the paper; the paper reports setup and
+ * solve times only, Sec. "SOC Parameter for Building R").
+ * Per-kernel timing with HIP events recorded on the library's stream around
  * selected launches (process-wide).  pair_profile_enable(1) clears the records
  * and starts recording, pair_profile_enable(0) stops.  Launches inside a
  * hipGraph capture are not timed.  kind: 0 = FC-Jacobi half-sweeps on the
@@ -274,10 +325,12 @@ int pair_profile_enable(int on);
 int pair_profile_read(int kind, int64_t* launches, double* total_ms, double* total_bytes);
 
 /* ------------------------------------------------------- generic AIR solver */
-/* The AIR hierarchy and V-cycle as a black-box solver for a given sparse
- * matrix, or a block-diagonal batch of independent matrices ("segments").
- * Used for component-level parity of the setup (strength, C/F split,
- * restriction, interpolation, Galerkin product). */
+/* The AIR hierarchy and V-cycle (Sec. "Use of Algebraic Multigrid": strength,
+ * C/F split, lAIR or nAIR restriction, one-point interpolation, R A P; Sec.
+ * "pAIR Performance for Transport": Jacobi relaxation) as a black-box solver
+ * for a given sparse matrix, or a block-diagonal batch of independent matrices
+ * ("segments").  Used for component-level parity of the setup.  Handles own
+ * their hierarchy; errors are reported as for pair_ctx. */
 typedef struct pair_amg pair_amg;
 
 int pair_amg_create(pair_amg** out, const pair_options* opt, void* hip_stream);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpair.so")
 
 PAIR_OK, PAIR_E_INVALID, PAIR_E_HIP, PAIR_E_OOM, PAIR_E_NOCONV, PAIR_E_STATE = 0, -1, -2, -3, -4, -5
 PAIR_HOST, PAIR_DEVICE = 0, 1
-PAIR_HEX8, PAIR_TET4 = 0, 1
+PAIR_TET4 = 1
 PAIR_PLAIN, PAIR_BATCHED = 0, 1
 PAIR_MAX_LEVELS = 32
 
@@ -79,6 +79,7 @@ _SIGS = {
     "pair_set_quadrature": (c_int, [P, c_int, P, P]),
     "pair_set_materials": (c_int, [P, P, P, P, c_int]),
     "pair_set_dual_source": (c_int, [P, P, c_int, c_int]),
+    "pair_set_inflow": (c_int, [P, c_int, P, c_int]),
     "pair_solve": (c_int, [P, c_int, P, P, P, c_int, P]),
     "pair_transport_sweep": (c_int, [P, c_int, P, P, P, c_int, P]),
     "pair_prepare": (c_int, [P, c_int, P]),

@@ -287,7 +287,7 @@ int pair_set_mesh_hex(pair_ctx* ctx, int nx, int ny, int nz, const double* lo3, 
         const int64_t E = static_cast<int64_t>(nx) * ny * nz;
         PAIR_CHECK(E * 8 < (int64_t(1) << 31), "mesh too large");
         DeviceMesh m;
-        m.kind = PAIR_HEX8;
+        m.kind = kHexMesh;
         m.E = E;
         m.k = 8;
         m.F = 6;
@@ -310,6 +310,8 @@ int pair_set_mesh_hex(pair_ctx* ctx, int nx, int ny, int nz, const double* lo3, 
         c.have_mesh = true;
         c.have_mats = false;
         c.have_ext = false;
+        c.inflow.reset();
+        c.have_inflow = false;
         invalidate(c);
     });
 }
@@ -344,6 +346,8 @@ int pair_set_mesh(pair_ctx* ctx, int elem_type, int64_t n_vert, const double* xy
         c.have_mesh = true;
         c.have_mats = false;
         c.have_ext = false;
+        c.inflow.reset();
+        c.have_inflow = false;
         invalidate(c);
     });
 }
@@ -373,6 +377,8 @@ int pair_set_quadrature(pair_ctx* ctx, int M, const double* omega, const double*
         PAIR_HIP(hipStreamSynchronize(c.s));
         c.have_quad = true;
         c.have_ext = c.have_ext && !c.ext_per_dir;
+        c.inflow.reset();
+        c.have_inflow = false;
         invalidate(c);
     });
 }
@@ -438,6 +444,45 @@ int pair_set_dual_source(pair_ctx* ctx, const double* src, int per_direction, in
     });
 }
 
+int pair_set_inflow(pair_ctx* ctx, int m, const double* g, int where) {
+    if (!ctx) return PAIR_E_INVALID;
+    return guarded(ctx->c.err, ctx->c.s, [&] {
+        Context& c = ctx->c;
+        if (!c.have_mesh || !c.have_quad) throw Error(E_STATE, "set the mesh and the quadrature first");
+        PAIR_CHECK(m >= -1 && m < c.M, "direction index out of range (-1 = every direction)");
+        const int64_t N = c.N();
+        const size_t total = static_cast<size_t>(c.M) * N;
+        if (!g && m == -1) {
+            c.inflow.reset();
+            c.have_inflow = false;
+            c.psi_valid = false;
+            return;
+        }
+        if (g) check_where(where);
+        if (!c.inflow.p) {
+            if (!g) return;      // clearing one direction of an all-vacuum problem
+            c.inflow.alloc(total);
+            PAIR_HIP(hipMemsetAsync(c.inflow.p, 0, total * sizeof(double), c.s));
+        }
+        const hipMemcpyKind kind = where == PAIR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        const int m0 = m < 0 ? 0 : m, m1 = m < 0 ? c.M : m + 1;
+        for (int k = m0; k < m1; ++k) {
+            double* dst = c.inflow.p + static_cast<size_t>(k) * N;
+            if (g) {
+                if (where == PAIR_HOST) {
+                    for (int64_t i = 0; i < N; ++i) PAIR_CHECK(std::isfinite(g[i]), "inflow values must be finite");
+                }
+                PAIR_HIP(hipMemcpyAsync(dst, g, N * sizeof(double), kind, c.s));
+            } else {
+                PAIR_HIP(hipMemsetAsync(dst, 0, N * sizeof(double), c.s));
+            }
+        }
+        PAIR_HIP(hipStreamSynchronize(c.s));
+        c.have_inflow = true;
+        c.psi_valid = false;
+    });
+}
+
 static void fill_stats_complexity(Context& c, pair_stats* st) {
     if (!st) return;
     double oc = 0.0;
@@ -471,6 +516,7 @@ int pair_transport_sweep(pair_ctx* ctx, int mode, const double* phi_in, double* 
         src.q = c.q.p;
         src.ext = c.have_ext ? c.ext.p : nullptr;
         src.ext_per_dir = c.ext_per_dir;
+        src.inflow = c.have_inflow ? c.inflow.p : nullptr;
         bool ok = c.sweep(mode, src, phin.p, c.psi.p, c.phi.p, st, false);
         c.psi_valid = true;
         if (psi_out) from_device(psi_out, c.psi.p, static_cast<size_t>(c.M) * N, where, c.s);
@@ -564,6 +610,7 @@ int pair_solve(pair_ctx* ctx, int mode, const double* phi0, double* phi_out, dou
         src.q = c.q.p;
         src.ext = c.have_ext ? c.ext.p : nullptr;
         src.ext_per_dir = c.ext_per_dir;
+        src.inflow = c.have_inflow ? c.inflow.p : nullptr;
         rc = solve_impl(c, mode, src, phi0d.p, c.psi, c.phi, st);
         from_device(phi_out, c.phi.p, N, where, c.s);
         if (psi_out) from_device(psi_out, c.psi.p, static_cast<size_t>(c.M) * N, where, c.s);
@@ -690,6 +737,7 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
             src.q = c.q.p;
             src.ext = c.have_ext ? c.ext.p : nullptr;
             src.ext_per_dir = c.ext_per_dir;
+            src.inflow = c.have_inflow ? c.inflow.p : nullptr;
             DBuf<double> tmp(N);
             c.rhs_batch(bt, src, nullptr, tmp.p, c.s);
             d2h(b, tmp.p, N, c.s);

@@ -221,7 +221,7 @@ __global__ void k_fine_counts(int kind, int64_t E, int nx, int ny, int nz, const
     const int64_t e = g % E;
     const int m = dirs[b];
     const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
-    if (kind == PAIR_HEX8) {
+    if (kind == kHexMesh) {
         HexFace fc[3];
         int ni = hex_inflow_faces(e, nx, ny, nz, om, fc);
         cnt[g] = 8 * (1 + 4 * ni);
@@ -549,12 +549,58 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
 __global__ void k_set_last(int64_t* rowptr, int64_t n, int64_t v) { rowptr[n] = v; }
 
 // ----------------------------------------------------------------- rhs
+// Inflow term of the weak form on the boundary faces through which Omega
+// enters: f_a -= (Omega.n_f) sum_c F_f[a][c] g_c, with g replaced by its nodal
+// interpolant on the face (F_f the face mass matrix).  Hex faces: F_f from the
+// reference element; unit normals +-e_axis.  Tet faces: F_f = area (1 + delta)/12
+// on the three face nodes with area = |nvec|/2 and Omega.n area = (Omega.nvec)/2.
+template <int K>
+__device__ __forceinline__ void add_inflow(int64_t e, const double om[3], const double* __restrict__ g,
+                                           int nx, int ny, int nz, const double* __restrict__ fref,
+                                           const int32_t* __restrict__ nbr,
+                                           const double* __restrict__ nvec, double f[K]) {
+    if constexpr (K == 8) {
+        const int64_t idx[3] = {e % nx, (e / nx) % ny, e / (static_cast<int64_t>(nx) * ny)};
+        const int64_t nn[3] = {nx, ny, nz};
+        for (int ax = 0; ax < 3; ++ax) {
+            if (fabs(om[ax]) <= kZeroFluxTol) continue;
+            const int side = om[ax] > 0.0 ? 0 : 1;          // the face Omega enters through
+            if (side == 0 ? idx[ax] != 0 : idx[ax] != nn[ax] - 1) continue;
+            const double odn = -fabs(om[ax]);
+            const double* F = fref + (2 * ax + side) * 64;
+            for (int a = 0; a < 8; ++a) {
+                if (((a >> ax) & 1) != side) continue;
+                double s = 0.0;
+                for (int c = 0; c < 8; ++c)
+                    if (((c >> ax) & 1) == side) s += F[a * 8 + c] * g[c];
+                f[a] -= odn * s;
+            }
+        }
+    } else {
+        for (int fc = 0; fc < 4; ++fc) {
+            if (nbr[e * 4 + fc] >= 0) continue;
+            const double* n = nvec + (e * 4 + fc) * 3;
+            const double on = om[0] * n[0] + om[1] * n[1] + om[2] * n[2];
+            const double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            if (fabs(on) <= kZeroFluxTol * nl || on > 0.0) continue;
+            double gs = 0.0;
+            for (int a = 0; a < 4; ++a)
+                if (a != fc) gs += g[a];
+            for (int a = 0; a < 4; ++a)
+                if (a != fc) f[a] -= on / 24.0 * (g[a] + gs);
+        }
+    }
+}
+
 template <int K>
 __global__ void k_rhs(int64_t E, int B, const int* __restrict__ dirs, const double* __restrict__ dinv,
                       const double* __restrict__ mref, const double* __restrict__ mass,
                       const double* __restrict__ sigs, const double* __restrict__ q,
                       const double* __restrict__ phi, const double* __restrict__ ext,
-                      int ext_per_dir, double* __restrict__ out) {
+                      int ext_per_dir, const double* __restrict__ inflow,
+                      const double* __restrict__ omega, int nx, int ny, int nz,
+                      const double* __restrict__ fref, const int32_t* __restrict__ nbr,
+                      const double* __restrict__ nvec, double* __restrict__ out) {
     int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= E * B) return;
     const int b = static_cast<int>(g / E);
@@ -570,6 +616,14 @@ __global__ void k_rhs(int64_t E, int B, const int* __restrict__ dirs, const doub
         for (int c = 0; c < K; ++c) s += Me[a * K + c] * src[c];
         f[a] = s / kFourPi;
         if (ext) f[a] += ext_per_dir ? ext[static_cast<int64_t>(dirs[b]) * N + e * K + a] : ext[e * K + a];
+    }
+    if (inflow) {
+        const int m = dirs[b];
+        const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
+        double gv[K];
+        const double* gm = inflow + static_cast<int64_t>(m) * N + e * K;
+        for (int c = 0; c < K; ++c) gv[c] = gm[c];
+        add_inflow<K>(e, om, gv, nx, ny, nz, fref, nbr, nvec, f);
     }
     const double* Di = dinv + (static_cast<int64_t>(b) * E + e) * K * K;
     for (int a = 0; a < K; ++a) {
@@ -690,8 +744,8 @@ void fine_counts(const DeviceMesh& m, const double* omega_d, const int* dirs_d, 
 void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d, int B,
                    const double* sigt, const int64_t* elem_off, int64_t total_nnz, int64_t* rowptr,
                    int32_t* col, double* val, double* dinv, FineEll& ell, hipStream_t s) {
-    const int nf = m.kind == PAIR_HEX8 ? 4 : 3;
-    PAIR_CHECK(!ell.factored || m.kind == PAIR_HEX8, "factored form needs a structured hex mesh");
+    const int nf = m.kind == kHexMesh ? 4 : 3;
+    PAIR_CHECK(!ell.factored || m.kind == kHexMesh, "factored form needs a structured hex mesh");
     ell.k = m.k;
     ell.nf = nf;
     ell.nel = m.E * B;
@@ -703,7 +757,7 @@ void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d
     }
     DBuf<int> bad(1);
     PAIR_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-    if (m.kind == PAIR_HEX8)
+    if (m.kind == kHexMesh)
         hipLaunchKernelGGL(k_fine_hex_lanes, dim3(grid_for(m.E * B * 8, 256)), dim3(256), 0, s, m.E, m.nx,
                            m.ny, m.nz, m.ref.p, omega_d, dirs_d, B, sigt, elem_off, rowptr, col,
                            val, dinv, bad.p, ell.nbr.p, ell.nodes.p, ell.val.p);
@@ -723,14 +777,16 @@ void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d
 
 void rhs_kernel(const DeviceMesh& m, int B, const int* dirs_d, const double* dinv,
                 const double* sigs, const double* q, const double* phi, const double* ext,
-                bool ext_per_dir, int64_t /*N*/, double* out, hipStream_t s) {
-    if (m.kind == PAIR_HEX8)
+                bool ext_per_dir, const double* inflow, const double* omega_d, int64_t /*N*/,
+                double* out, hipStream_t s) {
+    if (m.kind == kHexMesh)
         hipLaunchKernelGGL(k_rhs<8>, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, B, dirs_d,
                            dinv, m.ref.p + REF_M, nullptr, sigs, q, phi, ext, ext_per_dir ? 1 : 0,
-                           out);
+                           inflow, omega_d, m.nx, m.ny, m.nz, m.ref.p + REF_F, nullptr, nullptr, out);
     else
         hipLaunchKernelGGL(k_rhs<4>, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, B, dirs_d,
-                           dinv, nullptr, m.mass.p, sigs, q, phi, ext, ext_per_dir ? 1 : 0, out);
+                           dinv, nullptr, m.mass.p, sigs, q, phi, ext, ext_per_dir ? 1 : 0, inflow,
+                           omega_d, 0, 0, 0, nullptr, m.nbr.p, m.nvec.p, out);
     PAIR_LAUNCH_CHECK();
 }
 
@@ -752,7 +808,7 @@ void diff_norms(int64_t N, const double* a, const double* b, double* out2, hipSt
 void adjoint_contract(const DeviceMesh& m, int M, const double* w_d, const int* refl_d,
                       const double* psi, const double* psi_adj, const double* phi,
                       const double* phi_adj, double* g_t, double* g_s, hipStream_t s) {
-    if (m.kind == PAIR_HEX8)
+    if (m.kind == kHexMesh)
         hipLaunchKernelGGL(k_adjoint_contract<8>, dim3(grid_for(m.E, 128)), dim3(128), 0, s, m.E, M,
                            w_d, refl_d, m.ref.p + REF_M, nullptr, psi, psi_adj, phi, phi_adj, g_t,
                            g_s);

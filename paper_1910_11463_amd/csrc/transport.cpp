@@ -106,7 +106,7 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     bt.ell = std::make_shared<FineEll>();
     FineEll& fe = *bt.ell;
     // factored finest-level operator: structured hexes, every |Omega_d| > tol
-    bool fact = opt.fine_factored && mesh.kind == PAIR_HEX8;
+    bool fact = opt.fine_factored && mesh.kind == kHexMesh;
     for (int m : bt.dirs)
         for (int d = 0; d < 3; ++d) fact = fact && std::fabs(omega_h[3 * m + d]) > kZeroFluxTol;
     const bool tiles = std::strchr(opt.relax_pre, 'T') || std::strchr(opt.relax_post, 'T');
@@ -149,7 +149,7 @@ void Context::assemble_batch(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     std::vector<int64_t> off(B), cn(B, N);
     for (int b = 0; b < B; ++b) off[b] = static_cast<int64_t>(b) * N;
     bt.H.reset(new Hierarchy(amg_params(), s));
-    bt.H->set_finest_identity_local_systems(mesh.kind == PAIR_HEX8);
+    bt.H->set_finest_identity_local_systems(mesh.kind == kHexMesh);
     bt.H->setup(std::move(A), off, cn);
     bt.H->set_fine_ell(bt.ell);
 }
@@ -179,8 +179,8 @@ void Context::rhs_batch(const Batch& bt, const SourceSpec& src, const double* ph
     const int B = static_cast<int>(bt.dirs.size());
     DBuf<int> dirs_d(B);
     h2d(dirs_d.p, bt.dirs.data(), B, s);
-    rhs_kernel(mesh, B, dirs_d.p, bt.dinv.p, sigs.p, src.q, phi_in, src.ext, src.ext_per_dir, N(),
-               out, s);
+    rhs_kernel(mesh, B, dirs_d.p, bt.dinv.p, sigs.p, src.q, phi_in, src.ext, src.ext_per_dir,
+               src.inflow, omega_d.p, N(), out, s);
     PAIR_HIP(hipStreamSynchronize(s));
 }
 
@@ -231,12 +231,24 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
     auto finish = [&](size_t i, Batch& bt) {
         if (st) {
             Hierarchy& H = *bt.H;
-            if (i == 0)
-                for (int l = 0; l < std::min(H.num_levels(), PAIR_MAX_LEVELS); ++l) {
+            if (i == 0) {
+                // member 0 of batch 0 is direction 0: its rows and entries per level
+                const int nl = std::min(H.num_levels(), PAIR_MAX_LEVELS);
+                std::vector<int64_t> ends(2 * static_cast<size_t>(nl), 0);
+                const hipStream_t hs = batch_stream(i);
+                for (int l = 0; l < nl; ++l) {
+                    Level& Lv = H.level(l);
+                    if (Lv.off[0] < 0) continue;
+                    d2h(&ends[2 * l], Lv.A.rowptr.p + Lv.off[0], 1, hs);
+                    d2h(&ends[2 * l + 1], Lv.A.rowptr.p + Lv.off[0] + Lv.cnt[0], 1, hs);
+                }
+                PAIR_HIP(hipStreamSynchronize(hs));
+                for (int l = 0; l < nl; ++l) {
                     Level& Lv = H.level(l);
                     st->level_n[l] = Lv.off[0] >= 0 ? Lv.cnt[0] : 0;
-                    st->level_nnz[l] = Lv.off[0] >= 0 ? Lv.A.nnz : 0;
+                    st->level_nnz[l] = Lv.off[0] >= 0 ? ends[2 * l + 1] - ends[2 * l] : 0;
                 }
+            }
             for (int b = 0; b < H.members(); ++b) st->levels_max = std::max(st->levels_max, H.member_levels(b));
         }
         if (!opt.keep_hierarchy) {

@@ -14,9 +14,12 @@ namespace pair {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;
 constexpr double kZeroFluxTol = 1e-12;
+// Mesh kinds: structured hexes (pair_set_mesh_hex) and tets (PAIR_TET4).
+constexpr int kHexMesh = 0;
+static_assert(PAIR_TET4 != kHexMesh, "mesh kinds must differ");
 
 struct DeviceMesh {
-    int kind = -1;            // PAIR_HEX8 / PAIR_TET4
+    int kind = -1;            // kHexMesh or PAIR_TET4
     int64_t E = 0;
     int k = 0;                // nodes per element
     int F = 0;                // faces per element
@@ -48,6 +51,7 @@ struct SourceSpec {
     const double* q = nullptr;        // [E] isotropic element source (device) or null
     const double* ext = nullptr;      // dual-space source (device) or null
     bool ext_per_dir = false;         // ext is [M][N] instead of [N]
+    const double* inflow = nullptr;   // nodal inflow data [M][N] (device) or null (vacuum)
 };
 
 struct Context {
@@ -71,6 +75,9 @@ struct Context {
     DBuf<double> ext;                   // dual source
     bool ext_per_dir = false;
     bool have_ext = false;
+
+    DBuf<double> inflow;                // [M][N] nodal inflow values (zero: vacuum)
+    bool have_inflow = false;
 
     // cached operators
     std::vector<Batch> batches;
@@ -121,7 +128,8 @@ void fine_assemble(const DeviceMesh& m, const double* omega_d, const int* dirs_d
                    int32_t* col, double* val, double* dinv, FineEll& ell, hipStream_t s);
 void rhs_kernel(const DeviceMesh& m, int B, const int* dirs_d, const double* dinv,
                 const double* sigs, const double* q, const double* phi, const double* ext,
-                bool ext_per_dir, int64_t N, double* out, hipStream_t s);
+                bool ext_per_dir, const double* inflow, const double* omega_d, int64_t N,
+                double* out, hipStream_t s);
 void phi_accumulate(int64_t N, int B, const double* w_batch_d, const double* x, double* phi,
                     bool first, hipStream_t s);
 void diff_norms(int64_t N, const double* a, const double* b, double* out2, hipStream_t s);

@@ -60,6 +60,9 @@ class Solver:
         self.M = 0
         self.N = 0
         self.E = 0
+        # incremented by every call that changes the problem or the solution
+        # the adjoint would read (TransportSolve checks it in backward)
+        self.state = 0
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -79,6 +82,7 @@ class Solver:
             if k.startswith("relax_") and isinstance(v, str):
                 v = v.encode()
             setattr(self.opt, k, v)
+        self.state += 1
         self._chk(B.pair_set_options(self.h, ctypes.byref(self.opt)))
 
     def set_mesh_hex(self, nx, ny=None, nz=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
@@ -86,6 +90,7 @@ class Solver:
         nz = nx if nz is None else nz
         lo = np.asarray(lo, dtype=np.float64)
         hi = np.asarray(hi, dtype=np.float64)
+        self.state += 1
         self._chk(B.pair_set_mesh_hex(self.h, nx, ny, nz, lo, hi))
         self.E = nx * ny * nz
         self.N = 8 * self.E
@@ -93,6 +98,7 @@ class Solver:
     def set_mesh_tet(self, xyz, elem_vert):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         ev = np.ascontiguousarray(elem_vert, dtype=np.int32)
+        self.state += 1
         self._chk(B.pair_set_mesh(self.h, B.PAIR_TET4, xyz.shape[0], xyz, ev.shape[0], ev))
         self.E = ev.shape[0]
         self.N = 4 * self.E
@@ -107,6 +113,7 @@ class Solver:
     def set_quadrature(self, omega, w):
         omega = np.ascontiguousarray(omega, dtype=np.float64)
         w = np.ascontiguousarray(w, dtype=np.float64)
+        self.state += 1
         self._chk(B.pair_set_quadrature(self.h, w.shape[0], omega, w))
         self.M = w.shape[0]
 
@@ -123,15 +130,27 @@ class Solver:
         st, ss, qq = _f64(sigma_t), _f64(sigma_s), _f64(q)
         if _where(st) != _where(ss) or _where(st) != _where(qq):
             raise ValueError("sigma_t, sigma_s and q must live in the same memory space")
+        self.state += 1
         self._chk(B.pair_set_materials(self.h, st, ss, qq, _where(st)))
         self.q = qq
 
     def set_dual_source(self, src, per_direction=False):
+        self.state += 1
         if src is None:
             self._chk(B.pair_set_dual_source(self.h, None, 0, B.PAIR_HOST))
             return
         s = _f64(src)
         self._chk(B.pair_set_dual_source(self.h, s, 1 if per_direction else 0, _where(s)))
+
+    def set_inflow(self, g, m=-1):
+        """Nodal inflow values g [N] (value of g at every DOF's node) for
+        direction m (-1: every direction); g = None sets vacuum."""
+        self.state += 1
+        if g is None:
+            self._chk(B.pair_set_inflow(self.h, m, None, B.PAIR_HOST))
+            return
+        gg = _f64(g)
+        self._chk(B.pair_set_inflow(self.h, m, gg, _where(gg)))
 
     # ---------------------------------------------------------------- solves
     def _out(self, shape, device):
@@ -150,6 +169,7 @@ class Solver:
             if _where(phi0) != where:
                 raise ValueError("phi0 must live where the outputs do")
         st = B.pair_stats()
+        self.state += 1
         rc = self._chk(B.pair_solve(self.h, mode, phi0, phi, psi, where, ctypes.byref(st)),
                        allow_noconv=True)
         return phi, psi, st.as_dict(), rc
@@ -162,6 +182,7 @@ class Solver:
         if phi_in is not None:
             phi_in = _f64(phi_in)
         st = B.pair_stats()
+        self.state += 1
         rc = self._chk(B.pair_transport_sweep(self.h, mode, phi_in, psi, phi, where,
                                               ctypes.byref(st)), allow_noconv=True)
         return psi, phi, st.as_dict(), rc
@@ -310,12 +331,19 @@ def _transport_fn():
             if rc != B.PAIR_OK:
                 raise B.PairError(rc, "forward solve did not converge")
             ctx.solver = solver
+            ctx.state = solver.state
             ctx.mode = mode
             out = phi if device else torch.from_numpy(phi)
             return out.to(sigma_t.dtype)
 
         @staticmethod
         def backward(ctx, grad_phi):
+            # the adjoint reads the solver's last forward solution, operators
+            # and cross sections: refuse if anything changed since this forward
+            if ctx.solver.state != ctx.state:
+                raise RuntimeError("TransportSolve.backward: the solver was used for another solve "
+                                   "or its problem changed after this forward pass; the gradient "
+                                   "would belong to that other state (use one solver per forward)")
             g = grad_phi.detach().to(torch.float64).contiguous()
             gt, gs, _, _, rc = ctx.solver.adjoint(g, mode=ctx.mode)
             if rc != B.PAIR_OK:
