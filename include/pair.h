@@ -363,6 +363,23 @@ int pair_amg_get_level(pair_amg* amg, int level, int64_t* rowptr, int32_t* col, 
 int pair_amg_solve(pair_amg* amg, const double* b, double* x, int where, int* iters,
                    double* relres);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc or hipFree, tight serving loops): the same V-cycles as
+ * pair_amg_solve on a hierarchy built earlier by pair_amg_setup, with no device
+ * (or library host-heap) allocation in the call and no graph.  b [n] and x [n]
+ * (initial guess, overwritten) are device pointers on the handle's device,
+ * which must be current (else PAIR_E_STATE); iters / relres [n_seg] host, may
+ * be NULL.  The solve's per-member scratch (partial sums of the norms, norms,
+ * relative residuals, counters, flags, member offsets: 8 ceil(r / 512) + 53
+ * bytes per segment, r the largest segment's rows, plus at most 2.5 KiB of
+ * alignment) lives in one fixed 1 MiB device array per GPU, held until the
+ * process ends; a hierarchy needing more is rejected with PAIR_E_INVALID
+ * before any GPU work.  Every call on a GPU
+ * shares that array (it keeps the last call's contents; this call writes
+ * everything it reads), so calls that overlap on one GPU, from any handle or
+ * thread, race: serialise them.  Profiling records are not taken. */
+int pair_amg_solve_noalloc(pair_amg* amg, const double* b, double* x, int* iters, double* relres);
+
 #ifdef __cplusplus
 }
 #endif

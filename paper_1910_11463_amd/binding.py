@@ -98,6 +98,7 @@ _SIGS = {
     "pair_amg_level_sizes": (c_int, [P, c_int, P, P, P]),
     "pair_amg_get_level": (c_int, [P, c_int, P, P, P, P, P, P, P, P]),
     "pair_amg_solve": (c_int, [P, P, P, c_int, P, P]),
+    "pair_amg_solve_noalloc": (c_int, [P, P, P, P, P]),
 }
 
 _lib = None

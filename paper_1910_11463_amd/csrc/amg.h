@@ -146,6 +146,23 @@ struct Level {
     int lpr_r = 8;                 // lanes per row for kernels on R
 };
 
+// The solve's per-member scratch as plain device pointers: either the
+// hierarchy's own SolveBufs (and finest-level member offsets / counts), or a
+// caller-provided region carved by Hierarchy::carve_solve_scratch.
+struct SolveView {
+    double* partial = nullptr;     // [chunks][members] partial sums of the norms
+    double* bnorm2 = nullptr;      // per member
+    double* rnorm2 = nullptr;
+    double* relres = nullptr;
+    double* relres0 = nullptr;
+    int* iters = nullptr;
+    uint8_t* active = nullptr;
+    int* n_active = nullptr;       // scalar
+    int64_t* moff = nullptr;       // finest-level first row per member
+    int64_t* mcnt = nullptr;       // finest-level rows per member
+    int chunks = 0;
+};
+
 struct SolveBufs {
     DBuf<double> partial;          // per (member, chunk) partial sums
     DBuf<double> bnorm2, rnorm2;   // per member
@@ -169,6 +186,12 @@ public:
     // tol or max_iter.  use_graph captures one cycle + convergence test as a
     // hipGraph and replays it.  Returns true if all members converged.
     bool solve(bool use_graph, bool x_is_zero);
+    // The same V-cycles with the per-member scratch in the caller's device
+    // region `scratch` of at least solve_scratch_bytes() bytes (256-byte
+    // aligned): no device memory is allocated and no graph is used; the region
+    // is overwritten (what must start at zero is cleared here).
+    bool solve_in(void* scratch, bool x_is_zero);
+    size_t solve_scratch_bytes() const;
 
     double* b0() { return levels_[0].b.p; }
     double* x0() { return levels_[0].x.p; }
@@ -211,9 +234,15 @@ private:
     int B_ = 0;
     std::vector<Level> levels_;
     std::vector<int> nlev_;
+    SolveView carve_solve_scratch(void* base) const;
+    bool solve_impl(bool use_graph, bool x_is_zero);
+
     SolveBufs sb_;
+    SolveView sv_;                    // the scratch the solve kernels use
     std::vector<int> iters_h_;
     std::vector<double> relres_h_, cf_h_;
+    std::vector<double> r0_h_;        // host staging of the solve's results,
+    std::vector<uint8_t> act_h_;      // sized at setup
     DBuf<int64_t> moff_d_, mcnt_d_;   // finest-level member offsets / counts
     std::shared_ptr<FineEll> ell_;
     bool finest_identity_ = false;

@@ -2714,6 +2714,17 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
     for (int b = 0; b < B_; ++b) maxcnt = std::max(maxcnt, levels_[0].cnt[b]);
     sb_.chunks = static_cast<int>((maxcnt + 511) / 512);
     sb_.partial.alloc(static_cast<size_t>(sb_.chunks) * B_);
+    moff_d_.alloc(B_);
+    mcnt_d_.alloc(B_);
+    h2d(moff_d_.p, levels_[0].off.data(), B_, s_);
+    h2d(mcnt_d_.p, levels_[0].cnt.data(), B_, s_);
+    sv_ = SolveView{sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p, sb_.relres.p, sb_.relres0.p,
+                    sb_.iters.p, sb_.active.p, sb_.n_active.p, moff_d_.p, mcnt_d_.p, sb_.chunks};
+    iters_h_.assign(B_, 0);
+    relres_h_.assign(B_, 0.0);
+    cf_h_.assign(B_, 0.0);
+    r0_h_.assign(B_, 0.0);
+    act_h_.assign(B_, 0);
     if (prm_.coarse_fp32) make_fp32_copies();
     PAIR_HIP(hipStreamSynchronize(s_));
     if (prm_.tune) tune_lanes();

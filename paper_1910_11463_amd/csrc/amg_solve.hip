@@ -878,7 +878,7 @@ double restrict_bytes(const Level& L, double vb = 8.0) {
 double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur, double* other,
                           bool zero) {
     const int64_t n = L.A.n;
-    const uint8_t* act = sb_.active.p;
+    const uint8_t* act = sv_.active;
     const int kind = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
     for (char ch : sched) {
         const int8_t which = ch == 'F' ? -1 : 1;
@@ -953,8 +953,10 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
 
 void Hierarchy::vcycle_launches(bool x_is_zero) {
     const int nl = static_cast<int>(levels_.size());
-    const uint8_t* act = sb_.active.p;
-    std::vector<double*> cur(nl, nullptr);
+    const uint8_t* act = sv_.active;
+    constexpr int kMaxLevels = 32;      // options.max_levels <= PAIR_MAX_LEVELS = 32
+    PAIR_CHECK(nl <= kMaxLevels, "too many levels");
+    double* cur[kMaxLevels] = {};
     // down
     for (int l = 0; l < nl; ++l) {
         Level& L = levels_[l];
@@ -1155,83 +1157,133 @@ void Hierarchy::set_params(const AmgParams& p) {
 
 void Hierarchy::launch_cycle_and_test(bool x_is_zero, int /*it_offset*/) {
     Level& L0 = levels_[0];
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sb_.n_active.p);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sv_.n_active);
     vcycle_launches(x_is_zero);
     if (ell_ && ell_->factored) {
         const FineEll& E = *ell_;
         int h = prof_begin(s_, PROF_NORM_FINE);
-        hipLaunchKernelGGL(k_hex_norm_partial, dim3(sb_.chunks, B_), dim3(64), 0, s_, sb_.chunks,
-                           moff_d_.p, mcnt_d_.p, static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, E.kap.p,
-                           E.inflow.p, E.sigt.p, sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+        hipLaunchKernelGGL(k_hex_norm_partial, dim3(sv_.chunks, B_), dim3(64), 0, s_, sv_.chunks,
+                           sv_.moff, sv_.mcnt, static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, E.kap.p,
+                           E.inflow.p, E.sigt.p, sv_.active, L0.b.p, L0.x.p, sv_.partial);
         prof_end(s_, h, ell_residual_bytes(L0, E) - 8.0 * L0.A.n);
     } else if (ell_) {
         const FineEll& E = *ell_;
         dispatch_ell(E, [&](auto kc, auto fc) {
             constexpr int K = decltype(kc)::value, NF = decltype(fc)::value;
             int h = prof_begin(s_, PROF_NORM_FINE);
-            hipLaunchKernelGGL((k_ell_norm_partial<K, NF>), dim3(sb_.chunks, B_), dim3(kBlock), 0, s_,
-                               sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.n, E.nel, E.nF, E.nbr.p,
-                               E.nodes.p, E.val.p, E.cmask.p, E.fbase.p, sb_.active.p, L0.b.p, L0.x.p,
-                               sb_.partial.p);
+            hipLaunchKernelGGL((k_ell_norm_partial<K, NF>), dim3(sv_.chunks, B_), dim3(kBlock), 0, s_,
+                               sv_.chunks, sv_.moff, sv_.mcnt, L0.A.n, E.nel, E.nF, E.nbr.p,
+                               E.nodes.p, E.val.p, E.cmask.p, E.fbase.p, sv_.active, L0.b.p, L0.x.p,
+                               sv_.partial);
             prof_end(s_, h, ell_residual_bytes(L0, E) - 8.0 * L0.A.n);
         });
     } else dispatch_lpr(L0.lpr, [&](auto lc) {
         constexpr int LPR = decltype(lc)::value;
         int h = prof_begin(s_, PROF_NORM_FINE);
-        hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sb_.chunks, B_), dim3(kBlock), 0, s_, 1,
-                           sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p, L0.A.val.p,
-                           sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+        hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sv_.chunks, B_), dim3(kBlock), 0, s_, 1,
+                           sv_.chunks, sv_.moff, sv_.mcnt, L0.A.rowptr.p, L0.A.col.p, L0.A.val.p,
+                           sv_.active, L0.b.p, L0.x.p, sv_.partial);
         prof_end(s_, h, 12.0 * L0.A.nnz + 8.0 * L0.A.n * 3.0);
     });
-    hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 1, B_, sb_.chunks,
-                       moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p, sb_.relres.p,
-                       sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p, prm_.tol,
+    hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 1, B_, sv_.chunks,
+                       sv_.moff, sv_.partial, sv_.bnorm2, sv_.rnorm2, sv_.relres,
+                       sv_.relres0, sv_.iters, sv_.active, sv_.n_active, prm_.tol,
                        prm_.max_iter, 0);
     PAIR_LAUNCH_CHECK();
 }
 
-bool Hierarchy::solve(bool use_graph, bool x_is_zero) {
-    Level& L0 = levels_[0];
-    if (!moff_d_.p) {
-        moff_d_.alloc(B_);
-        mcnt_d_.alloc(B_);
-        h2d(moff_d_.p, L0.off.data(), B_, s_);
-        h2d(mcnt_d_.p, L0.cnt.data(), B_, s_);
+bool Hierarchy::solve(bool use_graph, bool x_is_zero) { return solve_impl(use_graph, x_is_zero); }
+
+namespace {
+constexpr size_t kAlign = 256;
+size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+}  // namespace
+
+size_t Hierarchy::solve_scratch_bytes() const {
+    const size_t B = static_cast<size_t>(B_);
+    return align_up(8 * static_cast<size_t>(sb_.chunks) * B) + 4 * align_up(8 * B) + align_up(4 * B) +
+           align_up(B) + align_up(4) + 2 * align_up(8 * B);
+}
+
+SolveView Hierarchy::carve_solve_scratch(void* base) const {
+    const size_t B = static_cast<size_t>(B_);
+    char* p = static_cast<char*>(base);
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += align_up(bytes);
+        return q;
+    };
+    SolveView v;
+    v.chunks = sb_.chunks;
+    v.partial = reinterpret_cast<double*>(take(8 * static_cast<size_t>(sb_.chunks) * B));
+    v.bnorm2 = reinterpret_cast<double*>(take(8 * B));
+    v.rnorm2 = reinterpret_cast<double*>(take(8 * B));
+    v.relres = reinterpret_cast<double*>(take(8 * B));
+    v.relres0 = reinterpret_cast<double*>(take(8 * B));
+    v.iters = reinterpret_cast<int*>(take(4 * B));
+    v.active = reinterpret_cast<uint8_t*>(take(B));
+    v.n_active = reinterpret_cast<int*>(take(4));
+    v.moff = reinterpret_cast<int64_t*>(take(8 * B));
+    v.mcnt = reinterpret_cast<int64_t*>(take(8 * B));
+    return v;
+}
+
+bool Hierarchy::solve_in(void* scratch, bool x_is_zero) {
+    PAIR_CHECK(scratch, "null scratch region");
+    const SolveView own = sv_;
+    sv_ = carve_solve_scratch(scratch);
+    bool ok = false;
+    try {
+        // every entry the kernels read before writing: the member offsets and
+        // counts; norms, flags and counters are written by k_norm_finalize /
+        // k_zero_int before they are read
+        h2d(sv_.moff, levels_[0].off.data(), B_, s_);
+        h2d(sv_.mcnt, levels_[0].cnt.data(), B_, s_);
+        ProfSuspend no_records;
+        ok = solve_impl(false, x_is_zero);
+    } catch (...) {
+        sv_ = own;
+        throw;
     }
+    sv_ = own;
+    return ok;
+}
+
+bool Hierarchy::solve_impl(bool use_graph, bool x_is_zero) {
+    Level& L0 = levels_[0];
     // |b| per member and the initial state
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sb_.n_active.p);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s_, sv_.n_active);
     dispatch_lpr(L0.lpr, [&](auto lc) {
         constexpr int LPR = decltype(lc)::value;
-        hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sb_.chunks, B_), dim3(kBlock), 0, s_, 0,
-                           sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p, L0.A.val.p,
-                           sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+        hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sv_.chunks, B_), dim3(kBlock), 0, s_, 0,
+                           sv_.chunks, sv_.moff, sv_.mcnt, L0.A.rowptr.p, L0.A.col.p, L0.A.val.p,
+                           sv_.active, L0.b.p, L0.x.p, sv_.partial);
     });
-    hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 0, B_, sb_.chunks,
-                       moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p, sb_.relres.p,
-                       sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p, prm_.tol,
+    hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 0, B_, sv_.chunks,
+                       sv_.moff, sv_.partial, sv_.bnorm2, sv_.rnorm2, sv_.relres,
+                       sv_.relres0, sv_.iters, sv_.active, sv_.n_active, prm_.tol,
                        prm_.max_iter, x_is_zero ? 1 : 0);
     PAIR_LAUNCH_CHECK();
     if (!x_is_zero) {
         dispatch_lpr(L0.lpr, [&](auto lc) {
             constexpr int LPR = decltype(lc)::value;
-            hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sb_.chunks, B_), dim3(kBlock), 0, s_, 1,
-                               sb_.chunks, moff_d_.p, mcnt_d_.p, L0.A.rowptr.p, L0.A.col.p,
-                               L0.A.val.p, sb_.active.p, L0.b.p, L0.x.p, sb_.partial.p);
+            hipLaunchKernelGGL(k_norm_partial<LPR>, dim3(sv_.chunks, B_), dim3(kBlock), 0, s_, 1,
+                               sv_.chunks, sv_.moff, sv_.mcnt, L0.A.rowptr.p, L0.A.col.p,
+                               L0.A.val.p, sv_.active, L0.b.p, L0.x.p, sv_.partial);
         });
         hipLaunchKernelGGL(k_norm_finalize, dim3(B_), dim3(256), 0, s_, 2, B_,
-                           sb_.chunks, moff_d_.p, sb_.partial.p, sb_.bnorm2.p, sb_.rnorm2.p,
-                           sb_.relres.p, sb_.relres0.p, sb_.iters.p, sb_.active.p, sb_.n_active.p,
+                           sv_.chunks, sv_.moff, sv_.partial, sv_.bnorm2, sv_.rnorm2,
+                           sv_.relres, sv_.relres0, sv_.iters, sv_.active, sv_.n_active,
                            prm_.tol, prm_.max_iter, 0);
         PAIR_LAUNCH_CHECK();
     } else {
         // x = 0 exactly on entry: members with b = 0 are done (x = 0 is exact)
         PAIR_HIP(hipMemsetAsync(L0.x.p, 0, L0.A.n * sizeof(double), s_));
     }
-    std::vector<uint8_t> act(B_);
-    d2h(act.data(), sb_.active.p, B_, s_);
+    d2h(act_h_.data(), sv_.active, B_, s_);
     PAIR_HIP(hipStreamSynchronize(s_));
     int n_act = 0;
-    for (auto a : act) n_act += a;
+    for (auto a : act_h_) n_act += a;
 
     int cycles = 0;
     bool first = true;
@@ -1250,24 +1302,21 @@ bool Hierarchy::solve(bool use_graph, bool x_is_zero) {
         }
         first = false;
         ++cycles;
-        d2h(&n_act, sb_.n_active.p, 1, s_);
+        d2h(&n_act, sv_.n_active, 1, s_);
         PAIR_HIP(hipStreamSynchronize(s_));
     }
     last_bytes_ = cycles * solve_bytes_per_cycle();
-    // per-member results
-    iters_h_.assign(B_, 0);
-    relres_h_.assign(B_, 0.0);
-    std::vector<double> r0(B_);
-    d2h(iters_h_.data(), sb_.iters.p, B_, s_);
-    d2h(relres_h_.data(), sb_.relres.p, B_, s_);
-    d2h(r0.data(), sb_.relres0.p, B_, s_);
+    // per-member results (host vectors sized at setup: assign does not reallocate)
+    d2h(iters_h_.data(), sv_.iters, B_, s_);
+    d2h(relres_h_.data(), sv_.relres, B_, s_);
+    d2h(r0_h_.data(), sv_.relres0, B_, s_);
     PAIR_HIP(hipStreamSynchronize(s_));
-    cf_h_.assign(B_, 0.0);
+    std::fill(cf_h_.begin(), cf_h_.end(), 0.0);
     bool ok = true;
     for (int b = 0; b < B_; ++b) {
         if (L0.off[b] < 0) continue;
-        if (iters_h_[b] > 0 && r0[b] > 0.0 && relres_h_[b] > 0.0)
-            cf_h_[b] = std::pow(relres_h_[b] / r0[b], 1.0 / iters_h_[b]);
+        if (iters_h_[b] > 0 && r0_h_[b] > 0.0 && relres_h_[b] > 0.0)
+            cf_h_[b] = std::pow(relres_h_[b] / r0_h_[b], 1.0 / iters_h_[b]);
         if (!prm_.fixed_cycles && !(relres_h_[b] <= prm_.tol)) ok = false;
     }
     return ok;

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <tuple>
 
 #include "profile.h"
@@ -24,6 +25,7 @@ struct pair_ctx {
 struct pair_amg {
     pair_options opt{};
     hipStream_t s = nullptr;
+    int device = -1;          // device current at pair_amg_create
     bool own_stream = false;
     std::string err;
     std::unique_ptr<Hierarchy> H;
@@ -772,6 +774,7 @@ int pair_amg_create(pair_amg** out, const pair_options* opt, void* hip_stream) {
             a->opt = *opt;
         }
         a->s = make_stream(hip_stream, a->own_stream);
+        PAIR_HIP(hipGetDevice(&a->device));
     });
     if (rc != PAIR_OK) {
         delete a;
@@ -900,6 +903,72 @@ int pair_amg_solve(pair_amg* amg, const double* b, double* x, int where, int* it
         PAIR_HIP(hipMemcpyAsync(amg->H->x0(), x, n * sizeof(double), kind, amg->s));
         bool ok = amg->H->solve(amg->opt.use_graph != 0, false);
         from_device(x, amg->H->x0(), n, where, amg->s);
+        PAIR_HIP(hipStreamSynchronize(amg->s));
+        for (int k = 0; k < amg->n_seg; ++k) {
+            if (iters) iters[k] = amg->H->iters_h()[k];
+            if (relres) relres[k] = amg->H->relres_h()[k];
+        }
+        if (!ok) {
+            rc = PAIR_E_NOCONV;
+            amg->err = "not every segment reached tol_inner";
+        }
+    });
+    return grc != PAIR_OK ? grc : rc;
+}
+
+// ------------------------------------------------- allocation-free solve
+// The per-solve scratch of pair_amg_solve_noalloc lives in this file-scope
+// device array: one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (in host code it is a stand-in, not a
+// device address); it uses the address hipGetSymbolAddress returns on each
+// device, looked up once per device with that device current.
+}  // extern "C"
+
+static constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch` (the calling thread's current device).
+void* scratch_address(int dev) {
+    PAIR_CHECK(dev >= 0 && dev < kMaxDevices, "device index out of range");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        PAIR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        PAIR_CHECK(p != nullptr, "no device address for the solve scratch");
+        g_scratch_dev[dev] = p;
+    }
+    return g_scratch_dev[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int pair_amg_solve_noalloc(pair_amg* amg, const double* b, double* x, int* iters, double* relres) {
+    if (!amg) return PAIR_E_INVALID;
+    int rc = PAIR_OK;
+    int grc = guarded(amg->err, amg->s, [&] {
+        if (!amg->H) throw Error(E_STATE, "no hierarchy");
+        PAIR_CHECK(b && x, "null vector");
+        int dev = -1;
+        PAIR_HIP(hipGetDevice(&dev));
+        if (dev != amg->device)
+            throw Error(E_STATE, "pair_amg_solve_noalloc must run with the handle's device current");
+        const size_t need = amg->H->solve_scratch_bytes();
+        PAIR_CHECK(need <= kNoAllocScratchBytes,
+                   "pair_amg_solve_noalloc: this hierarchy needs " + std::to_string(need) +
+                       " bytes of solve scratch, more than the fixed " +
+                       std::to_string(kNoAllocScratchBytes) + " (use pair_amg_solve)");
+        void* ptr = scratch_address(dev);
+        const int64_t n = amg->n;
+        PAIR_HIP(hipMemcpyAsync(amg->H->b0(), b, n * sizeof(double), hipMemcpyDeviceToDevice, amg->s));
+        PAIR_HIP(hipMemcpyAsync(amg->H->x0(), x, n * sizeof(double), hipMemcpyDeviceToDevice, amg->s));
+        const bool ok = amg->H->solve_in(ptr, false);
+        PAIR_HIP(hipMemcpyAsync(x, amg->H->x0(), n * sizeof(double), hipMemcpyDeviceToDevice, amg->s));
         PAIR_HIP(hipStreamSynchronize(amg->s));
         for (int k = 0; k < amg->n_seg; ++k) {
             if (iters) iters[k] = amg->H->iters_h()[k];

@@ -34,10 +34,15 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
+thread_local bool t_suspended = false;
+
 bool prof_enabled() { return g_on; }
 
+ProfSuspend::ProfSuspend() : prev(t_suspended) { t_suspended = true; }
+ProfSuspend::~ProfSuspend() { t_suspended = prev; }
+
 int prof_begin(hipStream_t s, int kind) {
-    if (!g_on || kind < 0 || kind >= PROF_NKINDS) return -1;
+    if (!g_on || t_suspended || kind < 0 || kind >= PROF_NKINDS) return -1;
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();

@@ -20,6 +20,15 @@ enum ProfKind : int {
 };
 
 bool prof_enabled();
+// While alive, the calling thread records nothing (no events are created and
+// no records grow): used where a call must not allocate.
+struct ProfSuspend {
+    ProfSuspend();
+    ~ProfSuspend();
+    ProfSuspend(const ProfSuspend&) = delete;
+    ProfSuspend& operator=(const ProfSuspend&) = delete;
+    bool prev;
+};
 // Returns a handle for prof_end (or -1 when disabled / capturing).
 int prof_begin(hipStream_t s, int kind);
 void prof_end(hipStream_t s, int handle, double bytes);
