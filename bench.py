@@ -60,16 +60,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_solver(w, mode_batch_size, device, pre="FC", post="FC", pre_c="=", post_c="=", streams=1,
-                coarse_fp32=0, filter_r=0.0, use_graph=1, fine_factored=1, omega=1.0, tile_xy=8, tile_z=0,
-                nair_degree=0, lair_distance=1):
+def make_solver(w, batch_size, device, **opts):
+    """A Solver on workload w with the benchmark's defaults (tol 1e-8,
+    hierarchies kept, lanes per row autotuned), overridden by opts."""
     import torch
     from paper_1910_11463_amd.solver import Solver
-    s = Solver(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=mode_batch_size,
-               relax_pre=pre, relax_post=post, relax_pre_coarse=pre_c, relax_post_coarse=post_c,
-               autotune=1, streams=streams, coarse_fp32=coarse_fp32, filter_r=filter_r,
-               use_graph=use_graph, fine_factored=fine_factored, omega=omega, tile_xy=tile_xy,
-               tile_z=tile_z, nair_degree=nair_degree, lair_distance=lair_distance)
+    kw = dict(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=batch_size, autotune=1)
+    kw.update(opts)
+    s = Solver(**kw)
     s.set_mesh(w.mesh)
     om, wt = Solver.level_symmetric(w.sn_order)
     s.set_quadrature(om, wt)
@@ -152,7 +150,8 @@ def timed_steps(s, mode, steps, warmup, cold=True, profile=False):
 def profile_kinds():
     import ctypes
     from paper_1910_11463_amd import binding as B
-    names = ["relax_fine", "residual_fine", "restrict_fine", "relax_coarse", "norm_fine", "r_build"]
+    names = ["relax_fine", "residual_fine", "restrict_fine", "relax_coarse", "norm_fine", "r_build",
+             "r_build_once"]
     out = {}
     for k, nm in enumerate(names):
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
@@ -230,31 +229,105 @@ def copy_bandwidth(mib=1024, reps=5):
     return 2.0 * n * 8 / sec / 1e9
 
 
-def source_iteration_time(cfg, device, streams):
+def kernel_roofline(prof, kind):
+    """Achieved algorithmic bandwidth of one event-timed profile kind."""
+    k = prof[kind]
+    return {"achieved_gbs": k["gbs"], "frac": k["gbs"] / HBM_PEAK_GBS, "launches": k["launches"],
+            "avg_us": k["avg_us"]}
+
+
+def entry(w, mode, batch_size, device, opts, warmup=1, warm=True, setup=False, profile=True):
+    """Cold sweep replacement (after `warmup` cold warm-up steps), then a warm
+    one with the hierarchies kept, optionally setup only; rates in
+    DOF*dirs/s, statistics of the cold step, the warm solve's algorithmic
+    bandwidth (the V-cycle kernels' bytes / warm time) and, with profile, the
+    finest-level relaxation kernel's event-timed bandwidth in the cold step
+    (eager launches only: replayed graphs are not timed)."""
+    import torch
+    from paper_1910_11463_amd import binding as B
+    N, M = w.mesh.n_dof, w.n_dir
+    s = make_solver(w, batch_size, device, **opts)
+    sec, st = timed_steps(s, mode, 1, warmup, cold=True, profile=profile)
+    out = {"workload": w.name, "mode": "batched" if mode == B.PAIR_BATCHED else "plain",
+           "batch_size": batch_size if mode == B.PAIR_BATCHED else 1,
+           "cold_s": sec, "cold_dof_dirs_per_s": N * M / sec,
+           "vcycles_total": st["vcycles_total"], "vcycles_max": st["vcycles_max"],
+           "cf_mean": st["cf_mean"], "levels": st["levels_max"], "op_complexity": st["op_complexity"]}
+    if profile:
+        prof = profile_kinds()
+        out["relax_fine_kernel"] = kernel_roofline(prof, "relax_fine")
+    if warm:
+        wsec, wst = timed_steps(s, mode, 1, 0, cold=False)
+        out.update({"warm_s": wsec, "warm_dof_dirs_per_s": N * M / wsec,
+                    "warm_solve_gbs": wst["bytes_solve"] / wsec / 1e9,
+                    "warm_solve_frac": wst["bytes_solve"] / wsec / 1e9 / HBM_PEAK_GBS,
+                    "warm_vcycles_total": wst["vcycles_total"]})
+    if setup:
+        s.clear_cache()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.prepare(mode)
+        torch.cuda.synchronize()
+        ssec = time.perf_counter() - t0
+        out.update({"setup_only_s": ssec, "setup_only_dof_dirs_per_s": N * M / ssec})
+    s.close()
+    return out
+
+
+def source_iteration_time(cfg, device, opts, label):
     """End-to-end source iteration to 1e-8 in phi (error-estimate stop) on a
-    workload: cold start, hierarchies built once and kept."""
+    workload: cold start, hierarchies built once and kept, inner tolerance
+    1e-9."""
     import torch
     from paper_1910_11463_amd import binding as B
     from paper_1910_11463_amd import workloads as wl
-    from paper_1910_11463_amd.solver import Solver
     w = wl.make_config(cfg)
-    s = Solver(tol_inner=1e-9, max_inner=200, tol_outer=1e-8, outer_estimate=1, max_outer=2000,
-               keep_hierarchy=1, relax_pre="FFCF", relax_post="FFCF", relax_pre_coarse="F",
-               relax_post_coarse="F", autotune=1, streams=streams)
-    s.set_mesh(w.mesh)
-    om, wt = Solver.level_symmetric(w.sn_order)
-    s.set_quadrature(om, wt)
-    dev = lambda a: torch.tensor(a, dtype=torch.float64, device=device)
-    s.set_materials(dev(w.mats.sigma_t), dev(w.mats.sigma_s), dev(w.mats.q))
+    kw = dict(tol_inner=1e-9, max_inner=200, tol_outer=1e-8, outer_estimate=1, max_outer=2000)
+    kw.update(opts)
+    s = make_solver(w, kw.pop("batch_size", 16), device, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, st, rc = s.solve(mode=B.PAIR_PLAIN, device=True)
+    _, _, st, rc = s.solve(mode=B.PAIR_BATCHED, device=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     s.close()
-    return {"workload": w.name, "seconds": dt, "outer_iters": st["outer_iters"],
-            "vcycles_total": st["vcycles_total"], "converged": rc == B.PAIR_OK,
-            "relax": "V(FFCF,FFCF), coarser levels V(F,F)", "tol_inner": 1e-9}
+    return {"workload": w.name, "schedule": label, "warm_start": bool(opts.get("warm_start", 0)),
+            "seconds": dt, "outer_iters": st["outer_iters"], "vcycles_total": st["vcycles_total"],
+            "converged": rc == B.PAIR_OK, "tol_inner": 1e-9, "tol_outer": 1e-8,
+            "dof_dirs_per_s_per_sweep": w.mesh.n_dof * w.n_dir * st["outer_iters"] / dt}
+
+
+def adjoint_time(device, opts):
+    """Gradient of the detector functional on the 32^3 S4 adjoint workload:
+    forward source iteration to 1e-8, then the adjoint (transposed pAIR
+    solves through the reflected directions' hierarchies) and the contraction
+    into dJ/dsigma_t and dJ/dsigma_s for every element."""
+    import numpy as np
+    import torch
+    from paper_1910_11463_amd import binding as B
+    from paper_1910_11463_amd import workloads as wl
+    w = wl.make_config(5)
+    kw = dict(tol_inner=1e-9, max_inner=200, tol_outer=1e-8, outer_estimate=1)
+    kw.update(opts)
+    s = make_solver(w, kw.pop("batch_size", 24), device, **kw)
+    # detector vector c_e = M_e 1 on detector elements (mass of a Q1 box: (h^3/8) per node)
+    h = 1.0 / w.mesh.nx
+    c = np.zeros((w.mesh.n_elem, 8))
+    c[w.detector] = h ** 3 / 8.0
+    cg = torch.tensor(c.ravel(), device=device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, _, st, rc = s.solve(mode=B.PAIR_BATCHED, device=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gt, gs, _, ast, rc2 = s.adjoint(cg, mode=B.PAIR_BATCHED)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    return {"workload": w.name, "forward_s": t1 - t0, "adjoint_s": t2 - t1, "gradient_s": t2 - t0,
+            "forward_outer_iters": st["outer_iters"], "adjoint_outer_iters": ast["outer_iters"],
+            "elements": w.mesh.n_elem, "converged": rc == B.PAIR_OK and rc2 == B.PAIR_OK,
+            "J": float(torch.dot(cg, phi))}
 
 
 def main():
@@ -268,8 +341,6 @@ def main():
     ap.add_argument("--batch-size", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--si", default="1,3", help="workloads whose full source iteration is timed "
-                    "(extra.source_iteration); empty for none")
     ap.add_argument("--relax-pre", default="TTT")
     ap.add_argument("--relax-post", default="TTT")
     ap.add_argument("--relax-pre-coarse", default="F")
@@ -277,10 +348,8 @@ def main():
     ap.add_argument("--streams", type=int, default=5,
                     help="direction batches set up and solved at once, one HIP stream each")
     ap.add_argument("--other-streams", type=int, default=8, help="streams for the other mode")
-    ap.add_argument("--graph", action="store_true",
-                    help="replay each batch's V-cycle as a captured hipGraph (default: eager "
-                         "launches, equally fast with several worker streams, and every "
-                         "launch of the roofline kernel is then event-timed)")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every V-cycle kernel eagerly instead of replaying captured graphs")
     ap.add_argument("--omega", type=float, default=1.0, help="Jacobi weight of the half-sweeps")
     ap.add_argument("--tile-xy", type=int, default=16, help="tile sweep boxes: elements along x and y")
     ap.add_argument("--tile-z", type=int, default=0, help="tile sweep boxes: elements along z (0: all)")
@@ -312,13 +381,16 @@ def main():
     w = wl.make_config(args.config, scale=args.scale)
     N, M = w.mesh.n_dof, w.n_dir
     mode = B.PAIR_PLAIN if args.mode == "plain" else B.PAIR_BATCHED
+    graph = 0 if args.eager else 1
     log("workload %s: N=%d, M=%d, mode=%s" % (w.name, N, M, args.mode))
+    head = dict(relax_pre=args.relax_pre, relax_post=args.relax_post,
+                relax_pre_coarse=args.relax_pre_coarse, relax_post_coarse=args.relax_post_coarse,
+                streams=args.streams, filter_r=args.filter_r, use_graph=graph, omega=args.omega,
+                tile_xy=args.tile_xy, tile_z=args.tile_z, nair_degree=args.nair_degree,
+                lair_distance=args.lair_distance)
+    bs = args.batch_size if mode == B.PAIR_BATCHED else 0
 
-    s = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                    args.relax_pre, args.relax_post, args.relax_pre_coarse, args.relax_post_coarse,
-                    args.streams, filter_r=args.filter_r, use_graph=int(args.graph), omega=args.omega,
-                    tile_xy=args.tile_xy, tile_z=args.tile_z, nair_degree=args.nair_degree,
-                    lair_distance=args.lair_distance)
+    s = make_solver(w, bs, device, **head)
     sec, st = timed_steps(s, mode, args.steps, args.warmup, cold=True, profile=True)
     prof = profile_kinds()
     phi64 = timed_steps.last_phi.clone()
@@ -329,7 +401,10 @@ def main():
     # warm solve (hierarchies cached, as in every source iteration after the first)
     wsec, wst = timed_steps(s, mode, 1, 0, cold=False)
     extra["warm_solve"] = {"s_per_sweep": wsec, "dof_dirs_per_s": N * M / wsec,
-                           "vcycles_total": wst["vcycles_total"], "solve_ms": wst["t_solve_ms"]}
+                           "vcycles_total": wst["vcycles_total"], "solve_ms": wst["t_solve_ms"],
+                           "solve_bytes": wst["bytes_solve"],
+                           "achieved_gbs": wst["bytes_solve"] / wsec / 1e9,
+                           "frac": wst["bytes_solve"] / wsec / 1e9 / HBM_PEAK_GBS}
     # a fixed 4 V-cycles per direction (enough for discretisation accuracy at
     # 32^3 in the accuracy study; not the 1e-8 metric): warm sweep rate
     s.set_options(fixed_cycles=4)
@@ -341,7 +416,7 @@ def main():
     s.clear_cache()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sst = s.prepare(mode)
+    s.prepare(mode)
     torch.cuda.synchronize()
     ssec = time.perf_counter() - t0
     extra["setup_only"] = {"s": ssec, "dof_dirs_per_s": N * M / ssec}
@@ -349,11 +424,8 @@ def main():
     # the roofline kernel: the event-timed kind with the largest summed duration
     dom = max(ROOFLINE_KERNELS, key=lambda k: prof[k]["ms"])
     if not args.no_extra:
-        # the timed kernels alone on the GPU: one stream, one cold step
-        s1 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, 1, filter_r=args.filter_r,
-                         use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z)
+        # the timed kernels alone on the GPU: one stream, eager launches, one cold step
+        s1 = make_solver(w, bs, device, **dict(head, streams=1, use_graph=0))
         timed_steps(s1, mode, 1, 0, cold=True)
         timed_steps(s1, mode, 1, 0, cold=True, profile=True)
         iso_all = profile_kinds()
@@ -363,34 +435,28 @@ def main():
         iso = iso_all[dom]
         extra["roofline_one_stream"] = {"achieved": iso["gbs"], "frac": iso["gbs"] / HBM_PEAK_GBS,
                                         "avg_us": iso["avg_us"], "launches": iso["launches"]}
+        if dom == "r_build":
+            once = iso_all["r_build_once"]
+            extra["roofline_one_stream"]["gather_once_per_launch"] = {
+                "achieved": once["bytes"] / (iso["ms"] * 1e-3) / 1e9 if iso["ms"] > 0 else 0.0,
+                "frac": once["bytes"] / (iso["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS if iso["ms"] > 0 else 0.0,
+                "bytes_per_launch": once["bytes"] / max(1, once["launches"])}
         s1.close()
+        # the other mode on the same workload
         other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
-        s2 = make_solver(w, args.batch_size if other == B.PAIR_BATCHED else 0, device,
-                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, args.other_streams, filter_r=args.filter_r,
-                         use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z)
-        osec, ost = timed_steps(s2, other, 1, 1, cold=True)
-        wsec2, _ = timed_steps(s2, other, 1, 0, cold=False)
-        s2.clear_cache()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s2.prepare(other)
-        torch.cuda.synchronize()
-        ssec2 = time.perf_counter() - t0
-        extra["other_mode"] = {"mode": "batched" if other == B.PAIR_BATCHED else "plain",
-                               "batch_size": args.batch_size if other == B.PAIR_BATCHED else 1,
-                               "streams": args.other_streams,
-                               "cold_dof_dirs_per_s": N * M / osec,
-                               "warm_dof_dirs_per_s": N * M / wsec2,
-                               "setup_only_dof_dirs_per_s": N * M / ssec2,
-                               "vcycles_max": ost["vcycles_max"]}
-        s2.close()
+        extra["other_mode"] = entry(w, other, args.batch_size, device,
+                                    dict(head, streams=args.other_streams), setup=True, profile=False)
+        log("other mode: cold %.3g DOF*dirs/s" % extra["other_mode"]["cold_dof_dirs_per_s"])
+        # the method as the small workload states it: FC-Jacobi V(1,1) on every
+        # level, distance-1 lAIR, no filtering of R
+        v11 = dict(relax_pre="FC", relax_post="FC", relax_pre_coarse="=", relax_post_coarse="=",
+                   streams=args.streams, filter_r=0.0, use_graph=0, tile_xy=args.tile_xy)
+        extra["a9_v11"] = entry(w, mode, args.batch_size, device, v11, setup=True)
+        log("a9 V(1,1): cold %.3g DOF*dirs/s, %d V-cycles, cf %.3f" % (
+            extra["a9_v11"]["cold_dof_dirs_per_s"], extra["a9_v11"]["vcycles_total"],
+            extra["a9_v11"]["cf_mean"]))
         # optional FP32 operators below the finest level: rate and effect on phi
-        s3 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                         args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                         args.relax_post_coarse, args.streams, coarse_fp32=1,
-                         filter_r=args.filter_r, use_graph=int(args.graph), tile_xy=args.tile_xy,
-                         tile_z=args.tile_z)
+        s3 = make_solver(w, bs, device, **dict(head, coarse_fp32=1))
         csec, cst = timed_steps(s3, mode, 1, 1, cold=True)
         phi32 = timed_steps.last_phi
         wsec3, _ = timed_steps(s3, mode, 1, 0, cold=False)
@@ -399,55 +465,46 @@ def main():
                                 "phi_rel_diff_vs_fp64": float(torch.linalg.norm(phi32 - phi64) /
                                                               torch.linalg.norm(phi64))}
         s3.close()
-        # F/C half-sweep ladders instead of tile sweeps on the finest level, with
-        # the factored operator and with stored element-block values (tile
-        # sweeps need the factored form)
-        for key, fact in (("fc_ladders", 1), ("stored_fine_operator", 0)):
-            s4 = make_solver(w, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                             FC_LADDER, FC_LADDER, args.relax_pre_coarse, args.relax_post_coarse,
-                             args.streams, filter_r=args.filter_r, use_graph=int(args.graph),
-                             fine_factored=fact)
-            ssec4, st4 = timed_steps(s4, mode, 1, 1, cold=True)
-            wsec4, _ = timed_steps(s4, mode, 1, 0, cold=False)
-            extra[key] = {"relax": "V(%s,%s)" % (FC_LADDER, FC_LADDER),
-                          "cold_dof_dirs_per_s": N * M / ssec4, "warm_dof_dirs_per_s": N * M / wsec4,
-                          "vcycles_total": st4["vcycles_total"]}
-            s4.close()
-        # nAIR of Neumann degree 1 with phi_R = 0.1 (the paper's nAIR setting), the
-        # same schedules; and distance-2 lAIR with phi_R = 0.1 on the same workload
-        # at 32^3 elements (about a minute per step at full size: --lair-distance 2)
-        w32 = wl.make_config(args.config, scale=32)
-        for key, kw, wv in (("nair_degree1", dict(nair_degree=1), w),
-                            ("lair_distance2_32", dict(lair_distance=2), w32)):
-            Nv, Mv = wv.mesh.n_dof, wv.n_dir
-            try:
-                s5 = make_solver(wv, args.batch_size if mode == B.PAIR_BATCHED else 0, device,
-                                 args.relax_pre, args.relax_post, args.relax_pre_coarse,
-                                 args.relax_post_coarse, args.streams, filter_r=0.1,
-                                 use_graph=int(args.graph), tile_xy=args.tile_xy, tile_z=args.tile_z, **kw)
-                nsec, nst = timed_steps(s5, mode, 1, 1, cold=True)
-                nwsec, _ = timed_steps(s5, mode, 1, 0, cold=False)
-                s5.clear_cache()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                s5.prepare(mode)
-                torch.cuda.synchronize()
-                nssec = time.perf_counter() - t0
-                extra[key] = {"workload": wv.name, "filter_r": 0.1, "cold_dof_dirs_per_s": Nv * Mv / nsec,
-                              "warm_dof_dirs_per_s": Nv * Mv / nwsec,
-                              "setup_only_dof_dirs_per_s": Nv * Mv / nssec,
-                              "vcycles_total": nst["vcycles_total"],
-                              "op_complexity": nst["op_complexity"], "levels": nst["levels_max"]}
-                log("%s: cold %.3g, setup only %.3g DOF*dirs/s" % (key, Nv * Mv / nsec, Nv * Mv / nssec))
-                s5.close()
-            except Exception as e:   # reported, not fatal: an extra measurement
-                extra[key] = {"error": str(e)}
-        extra["source_iteration"] = []
-        for c in [int(x) for x in args.si.split(",") if x.strip()]:
-            r = source_iteration_time(c, device, args.streams)
-            log("source iteration %s: %.2f s, %d outer iterations" % (r["workload"], r["seconds"],
-                                                                    r["outer_iters"]))
-            extra["source_iteration"].append(r)
+        # F/C half-sweep ladders instead of tile sweeps on the finest level
+        extra["fc_ladders"] = entry(w, mode, args.batch_size, device,
+                                    dict(head, relax_pre=FC_LADDER, relax_post=FC_LADDER, use_graph=0))
+        # nAIR of Neumann degree 1 with phi_R = 0.1 (the paper's nAIR setting)
+        try:
+            extra["nair_degree1"] = entry(w, mode, args.batch_size, device,
+                                          dict(head, nair_degree=1, filter_r=0.1), setup=True, profile=False)
+        except Exception as e:   # reported, not fatal: an extra measurement
+            extra["nair_degree1"] = {"error": str(e)}
+        # batched directions: the 32^3 S8 checkerboard, all 80 directions in one
+        # hierarchy (every V-cycle one graph replay) vs one direction per
+        # hierarchy on several streams, with the F/C V(1,1) cycles and with the
+        # headline's schedules
+        w4 = wl.make_config(4)
+        extra["batched_c4"] = {}
+        for label, sched in (("v11", v11), ("headline", head)):
+            for mname, md, bsz, strm in (("batched", B.PAIR_BATCHED, w4.n_dir, 1),
+                                        ("plain", B.PAIR_PLAIN, 0, args.other_streams)):
+                extra["batched_c4"]["%s_%s" % (label, mname)] = entry(
+                    w4, md, bsz, device, dict(sched, streams=strm, use_graph=1), setup=True, profile=False)
+            log("C4 %s: batched cold %.3g warm %.3g; plain cold %.3g warm %.3g DOF*dirs/s" % (
+                label, extra["batched_c4"][label + "_batched"]["cold_dof_dirs_per_s"],
+                extra["batched_c4"][label + "_batched"]["warm_dof_dirs_per_s"],
+                extra["batched_c4"][label + "_plain"]["cold_dof_dirs_per_s"],
+                extra["batched_c4"][label + "_plain"]["warm_dof_dirs_per_s"]))
+        # end-to-end source iterations to 1e-8 in phi
+        extra["source_iteration"] = [
+            source_iteration_time(1, device, dict(v11, streams=1), "V(FC,FC) on every level"),
+            source_iteration_time(2, device, dict(head, warm_start=0), "headline"),
+            source_iteration_time(2, device, dict(head, warm_start=1), "headline"),
+            source_iteration_time(3, device, dict(relax_pre="FFCF", relax_post="FFCF",
+                                                  relax_pre_coarse="F", relax_post_coarse="F",
+                                                  streams=args.streams, use_graph=graph),
+                                  "V(FFCF,FFCF), coarser levels V(F,F)"),
+        ]
+        for r in extra["source_iteration"]:
+            log("source iteration %s (%s, warm start %s): %.2f s, %d outer iterations" % (
+                r["workload"], r["schedule"], r["warm_start"], r["seconds"], r["outer_iters"]))
+        extra["adjoint_c5"] = adjoint_time(device, dict(head, batch_size=24))
+        log("adjoint gradient: %.2f s" % extra["adjoint_c5"]["gradient_s"])
 
     relax = prof[dom]
     label, tfile, tsrc = roofline_kernel(dom, args.relax_pre, args.relax_post)
@@ -461,6 +518,12 @@ def main():
                 "traffic_gbs": traffic / (relax["avg_us"] * 1e-6) / 1e9 if traffic else None,
                 "copy_gbs": copy_gbs, "frac_of_copy": relax["gbs"] / copy_gbs,
                 "other_timed": {}}
+    if dom == "r_build" and prof["r_build_once"]["launches"]:
+        once = prof["r_build_once"]
+        roofline["gather_once_per_launch"] = {
+            "bytes_per_launch": once["bytes"] / once["launches"],
+            "achieved": once["bytes"] / (relax["ms"] * 1e-3) / 1e9,
+            "frac": once["bytes"] / (relax["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     for k in ROOFLINE_KERNELS:
         if k == dom:
             continue
@@ -482,13 +545,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "mode": args.mode, "dof_per_dir": N, "dirs": M,
+                   "batch_size": bs if mode == B.PAIR_BATCHED else 1,
                    "tol": 1e-8, "step": "cold sweep replacement: assembly + AIR setup + V-cycles + phi",
                    "relax": "V(%s,%s) on the finest level (T: tile sweep over %dx%dx%s-element "
                             "boxes; F/C: Jacobi half-sweep over F/C points), coarser levels V(%s,%s)" % (
                        args.relax_pre or "-", args.relax_post or "-", args.tile_xy, args.tile_xy,
                        str(args.tile_z) if args.tile_z > 0 else "nz", args.relax_pre_coarse or "-",
                        args.relax_post_coarse or "-"),
-                   "streams": args.streams, "filter_r": args.filter_r, "graph": bool(args.graph),
+                   "streams": args.streams, "filter_r": args.filter_r, "graph": bool(graph),
                    "parallelism": "1 GPU"},
         "stats": {"vcycles_total": st["vcycles_total"], "vcycles_max": st["vcycles_max"],
                   "cf_mean": st["cf_mean"], "levels": st["levels_max"],

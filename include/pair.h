@@ -315,7 +315,9 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
  * finest level (and tile sweeps), 1 = finest-level residual, 2 = restriction
  * from the finest level, 3 = half-sweeps on coarser levels, 4 = convergence-
  * test residual norm, 5 = setup: restriction rows with dense local systems
- * (lAIR on the levels below the finest).  Outputs: number of timed launches,
+ * (lAIR on the levels below the finest), 6 = the same launches with each
+ * gathered row of A counted once per launch (kind 5 counts it once per local
+ * system that reads it).  Outputs: number of timed launches,
  * their summed duration (ms) and summed algorithmic bytes (what each launch
  * must read and write: 8 B per value, 4 B per column index, 8 B per row
  * offset; a gathered vector counted once per launch; for kind 5, counted on

@@ -183,8 +183,10 @@ public:
 
     // V-cycles on all members from the current x of level 0 (set by the
     // caller through x0()) for right-hand side b0() until every member meets
-    // tol or max_iter.  use_graph captures one cycle + convergence test as a
-    // hipGraph and replays it.  Returns true if all members converged.
+    // tol or max_iter.  use_graph captures the cycle + convergence test as
+    // hipGraphs (one for a first cycle from x = 0, one for every other cycle)
+    // and replays them for every cycle; the graphs stay with the hierarchy.
+    // Returns true if all members converged.
     bool solve(bool use_graph, bool x_is_zero);
     // The same V-cycles with the per-member scratch in the caller's device
     // region `scratch` of at least solve_scratch_bytes() bytes (256-byte
@@ -246,8 +248,10 @@ private:
     DBuf<int64_t> moff_d_, mcnt_d_;   // finest-level member offsets / counts
     std::shared_ptr<FineEll> ell_;
     bool finest_identity_ = false;
-    hipGraph_t graph_ = nullptr;
-    hipGraphExec_t graph_exec_ = nullptr;
+    // captured cycles: graph_ any cycle, graph0_ the first cycle from x = 0
+    // (its relaxation starts from zero and skips reading x)
+    hipGraph_t graph_ = nullptr, graph0_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr, graph0_exec_ = nullptr;
     double last_bytes_ = 0.0;
 
 public:

@@ -710,6 +710,37 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 }
 
 
+// Profiling only: the algorithmic bytes of one k_r_build launch with every
+// gathered row of A counted once per launch (however many local systems read
+// it).  Per C row of `list`: the list and c2f entries and its row offsets in A
+// and R (40 B), its row of A (column, value, strength flag, cf of the column:
+// 14 B per entry) and its row of R written (12 B per entry); per distinct row
+// j of A read by the launch's local systems (first setter of its bit in
+// `seen`): its offsets (16 B) and entries (12 B each).
+__global__ void k_r_gather_once(int nrows, const int32_t* __restrict__ list,
+                                const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+                                const int64_t* __restrict__ r_rowptr, const int32_t* __restrict__ r_col,
+                                unsigned* __restrict__ seen, unsigned long long* __restrict__ pbytes) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long b = 0;
+    if (t < nrows) {
+        const int64_t I = list[t];
+        const int64_t i = c2f[I];
+        const int64_t rb = r_rowptr[I], re = r_rowptr[I + 1];
+        b = 40ull + 14ull * static_cast<unsigned long long>(rowptr[i + 1] - rowptr[i]) +
+            12ull * static_cast<unsigned long long>(re - rb);
+        for (int64_t q = rb; q < re; ++q) {
+            const int32_t j = r_col[q];
+            if (j == i) continue;
+            const unsigned bit = 1u << (j & 31);
+            if (!(atomicOr(&seen[j >> 5], bit) & bit))
+                b += 16ull + 12ull * static_cast<unsigned long long>(rowptr[j + 1] - rowptr[j]);
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) b += __shfl_xor(b, d, 64);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(pbytes + (blockIdx.x % kProfSubSlots), b);
+}
+
 // Distance-2 lAIR rows: R_i holds the eps_R-strong F neighbours of C point i
 // and, through each of them, their eps_R-strong F neighbours (no kmax
 // truncation).  One 256-thread block per row (grid-stride).  The pattern is
@@ -2504,6 +2535,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                 if (nr == 0) continue;
                 const int rpw = 8 >> c;
                 const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
+                const int ph1 = prof_begin(s_, PROF_RBUILD_ONCE);
                 const int ph = prof_begin(s_, PROF_RBUILD);
                 unsigned long long* pb = prof_dev_bytes(ph);
 #define PAIR_RB_ARGS nr, rl[c].p, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, \
@@ -2514,7 +2546,17 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                 else hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
 #undef PAIR_RB_ARGS
                 prof_end_dev(s_, ph);
+                prof_end_dev(s_, ph1);
                 PAIR_LAUNCH_CHECK();
+                if (unsigned long long* pb1 = prof_dev_bytes(ph1)) {
+                    // outside the timed pair: the same launch's bytes with
+                    // gathered rows counted once
+                    DBuf<unsigned> seen((n + 31) / 32);
+                    PAIR_HIP(hipMemsetAsync(seen.p, 0, seen.bytes(), s_));
+                    hipLaunchKernelGGL(k_r_gather_once, dim3(grid_for(nr, 256)), dim3(256), 0, s_, nr,
+                                       rl[c].p, c2f.p, L.A.rowptr.p, L.R.rowptr.p, L.R.col.p, seen.p, pb1);
+                    PAIR_LAUNCH_CHECK();
+                }
             }
             PAIR_HIP(hipMemcpyAsync(d_counter.p, rsing.p, sizeof(int), hipMemcpyDeviceToDevice, s_));
         }

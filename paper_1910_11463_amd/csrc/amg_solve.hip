@@ -1146,8 +1146,10 @@ void Hierarchy::tune_lanes() {
 }
 
 void Hierarchy::drop_graph() {
-    if (graph_exec_) { (void)hipGraphExecDestroy(graph_exec_); graph_exec_ = nullptr; }
-    if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
+    for (hipGraphExec_t* e : {&graph_exec_, &graph0_exec_})
+        if (*e) { (void)hipGraphExecDestroy(*e); *e = nullptr; }
+    for (hipGraph_t* g : {&graph_, &graph0_})
+        if (*g) { (void)hipGraphDestroy(*g); *g = nullptr; }
 }
 
 void Hierarchy::set_params(const AmgParams& p) {
@@ -1289,16 +1291,19 @@ bool Hierarchy::solve_impl(bool use_graph, bool x_is_zero) {
     bool first = true;
     while (n_act > 0) {
         PAIR_CHECK(cycles <= prm_.max_iter + 1, "V-cycle loop did not stop");
-        if (first || !use_graph) {
-            launch_cycle_and_test(first && x_is_zero, cycles);
+        const bool from_zero = first && x_is_zero;
+        if (!use_graph) {
+            launch_cycle_and_test(from_zero, cycles);
         } else {
-            if (!graph_exec_) {
+            hipGraph_t& gr = from_zero ? graph0_ : graph_;
+            hipGraphExec_t& ex = from_zero ? graph0_exec_ : graph_exec_;
+            if (!ex) {
                 PAIR_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
-                launch_cycle_and_test(false, cycles);
-                PAIR_HIP(hipStreamEndCapture(s_, &graph_));
-                PAIR_HIP(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0));
+                launch_cycle_and_test(from_zero, cycles);
+                PAIR_HIP(hipStreamEndCapture(s_, &gr));
+                PAIR_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
             }
-            PAIR_HIP(hipGraphLaunch(graph_exec_, s_));
+            PAIR_HIP(hipGraphLaunch(ex, s_));
         }
         first = false;
         ++cycles;

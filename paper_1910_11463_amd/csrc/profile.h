@@ -16,7 +16,8 @@ enum ProfKind : int {
     PROF_RELAX_COARSE = 3,   // half-sweeps on all coarser levels
     PROF_NORM_FINE = 4,      // convergence test on the finest level
     PROF_RBUILD = 5,         // lAIR rows with dense local systems (coarser levels' setup)
-    PROF_NKINDS = 6
+    PROF_RBUILD_ONCE = 6,    // the same launches, a gathered row of A counted once per launch
+    PROF_NKINDS = 7
 };
 
 bool prof_enabled();

@@ -40,3 +40,29 @@ def test_adjoint_matches_dense_adjoint_and_fd(kind, order):
         fd_s.append((vals[2] - vals[3]) / (2 * h))
     assert np.linalg.norm(np.array(fd_t) - gt) <= 1e-7 * np.linalg.norm(fd_t)
     assert np.linalg.norm(np.array(fd_s) - gs) <= 1e-7 * np.linalg.norm(fd_s)
+
+
+def test_stored_central_differences_agree_with_the_oracle_adjoint():
+    """The stored central differences of the 32^3 S4 workload (written by
+    tests/golden/make_c5_fd.py with the compiled exact sweep) against the
+    oracle's adjoint gradients computed here with the NumPy assembly and
+    source iteration: two independent routes to dJ/dsigma on 16 elements."""
+    import os
+    from paper_1910_11463_amd import workloads as wl
+    from oracle import adjoint as ADJ, quadrature as Q, source_iteration as si
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_fd_gradients.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    e = np.array([int(r[0]) for r in rows])
+    fdt = np.array([float(r[1]) for r in rows])
+    fds = np.array([float(r[2]) for r in rows])
+    w = wl.make_config(5)
+    assert np.array_equal(e, w.fd_elems)
+    om, wt = Q.level_symmetric(w.sn_order)
+    prob = si.Problem(w.mesh, w.mats.sigma_t, w.mats.sigma_s, w.mats.q, om, wt)
+    threads = os.cpu_count() or 1
+    fwd = si.source_iteration(prob, tol=1e-14, threads=threads)
+    c = ADJ.detector_source(prob, w.detector)
+    adj = si.source_iteration(ADJ.adjoint_problem(prob, c), tol=1e-14, threads=threads)
+    gt, gs = ADJ.gradients(prob, fwd.psi, fwd.phi, adj.psi, adj.phi, w.sn_order)
+    assert np.linalg.norm(gt[e] - fdt) <= 1e-5 * np.linalg.norm(fdt)
+    assert np.linalg.norm(gs[e] - fds) <= 1e-5 * np.linalg.norm(fds)
