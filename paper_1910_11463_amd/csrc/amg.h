@@ -184,8 +184,9 @@ public:
     // V-cycles on all members from the current x of level 0 (set by the
     // caller through x0()) for right-hand side b0() until every member meets
     // tol or max_iter.  use_graph captures the cycle + convergence test as
-    // hipGraphs (one for a first cycle from x = 0, one for every other cycle)
-    // and replays them for every cycle; the graphs stay with the hierarchy.
+    // hipGraphs (one for a first cycle from x = 0, one for every other cycle),
+    // each the second time that kind of cycle is needed, and replays them from
+    // then on; the graphs stay with the hierarchy.
     // Returns true if all members converged.
     bool solve(bool use_graph, bool x_is_zero);
     // The same V-cycles with the per-member scratch in the caller's device
@@ -252,6 +253,9 @@ private:
     // (its relaxation starts from zero and skips reading x)
     hipGraph_t graph_ = nullptr, graph0_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr, graph0_exec_ = nullptr;
+    // eager launches of each cycle kind so far: a kind is captured when it is
+    // needed again, so a solve of one cycle pays for no capture it never replays
+    int eager_uses_ = 0, eager_uses0_ = 0;
     double last_bytes_ = 0.0;
 
 public:

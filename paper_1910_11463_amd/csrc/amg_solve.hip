@@ -1150,6 +1150,7 @@ void Hierarchy::drop_graph() {
         if (*e) { (void)hipGraphExecDestroy(*e); *e = nullptr; }
     for (hipGraph_t* g : {&graph_, &graph0_})
         if (*g) { (void)hipGraphDestroy(*g); *g = nullptr; }
+    eager_uses_ = eager_uses0_ = 0;
 }
 
 void Hierarchy::set_params(const AmgParams& p) {
@@ -1292,11 +1293,13 @@ bool Hierarchy::solve_impl(bool use_graph, bool x_is_zero) {
     while (n_act > 0) {
         PAIR_CHECK(cycles <= prm_.max_iter + 1, "V-cycle loop did not stop");
         const bool from_zero = first && x_is_zero;
-        if (!use_graph) {
+        hipGraph_t& gr = from_zero ? graph0_ : graph_;
+        hipGraphExec_t& ex = from_zero ? graph0_exec_ : graph_exec_;
+        int& eager = from_zero ? eager_uses0_ : eager_uses_;
+        if (!use_graph || (!ex && eager == 0)) {
             launch_cycle_and_test(from_zero, cycles);
+            ++eager;
         } else {
-            hipGraph_t& gr = from_zero ? graph0_ : graph_;
-            hipGraphExec_t& ex = from_zero ? graph0_exec_ : graph_exec_;
             if (!ex) {
                 PAIR_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
                 launch_cycle_and_test(from_zero, cycles);

@@ -504,6 +504,7 @@ int pair_transport_sweep(pair_ctx* ctx, int mode, const double* phi_in, double* 
     if (!ctx) return PAIR_E_INVALID;
     int rc = PAIR_OK;
     int grc = guarded(ctx->c.err, ctx->c.s, [&] {
+        TraceRange trace_range("pair_transport_sweep");
         Context& c = ctx->c;
         check_where(where);
         c.check_ready();
@@ -599,6 +600,7 @@ int pair_solve(pair_ctx* ctx, int mode, const double* phi0, double* phi_out, dou
     if (!ctx) return PAIR_E_INVALID;
     int rc = PAIR_OK;
     int grc = guarded(ctx->c.err, ctx->c.s, [&] {
+        TraceRange trace_range("pair_solve");
         Context& c = ctx->c;
         check_where(where);
         c.check_ready();
@@ -627,6 +629,7 @@ int pair_adjoint(pair_ctx* ctx, int mode, const double* grad_phi, double* dJ_dsi
     if (!ctx) return PAIR_E_INVALID;
     int rc = PAIR_OK;
     int grc = guarded(ctx->c.err, ctx->c.s, [&] {
+        TraceRange trace_range("pair_adjoint");
         Context& c = ctx->c;
         check_where(where);
         c.check_ready();
@@ -685,6 +688,7 @@ int pair_adjoint(pair_ctx* ctx, int mode, const double* grad_phi, double* dJ_dsi
 int pair_prepare(pair_ctx* ctx, int mode, pair_stats* st) {
     if (!ctx) return PAIR_E_INVALID;
     return guarded(ctx->c.err, ctx->c.s, [&] {
+        TraceRange trace_range("pair_prepare");
         Context& c = ctx->c;
         c.check_ready();
         PAIR_CHECK(mode == PAIR_PLAIN || mode == PAIR_BATCHED, "mode must be PAIR_PLAIN or PAIR_BATCHED");
@@ -792,6 +796,7 @@ int pair_amg_setup(pair_amg* amg, int n_seg, const int64_t* seg_rows, int64_t n,
                    const int32_t* col, const double* val, int where) {
     if (!amg) return PAIR_E_INVALID;
     return guarded(amg->err, amg->s, [&] {
+        TraceRange trace_range("pair_amg_setup");
         check_where(where);
         PAIR_CHECK(n_seg >= 1 && n_seg <= 65535 && seg_rows && rowptr && col && val, "bad arguments");
         PAIR_CHECK(n >= 1 && n < (int64_t(1) << 31), "matrix size out of range");
@@ -894,6 +899,7 @@ int pair_amg_solve(pair_amg* amg, const double* b, double* x, int where, int* it
     if (!amg) return PAIR_E_INVALID;
     int rc = PAIR_OK;
     int grc = guarded(amg->err, amg->s, [&] {
+        TraceRange trace_range("pair_amg_solve");
         check_where(where);
         if (!amg->H) throw Error(E_STATE, "no hierarchy");
         PAIR_CHECK(b && x, "null vector");

@@ -4,6 +4,8 @@
 #include <mutex>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.h"
 
 namespace pair {
@@ -35,6 +37,9 @@ hipEvent_t take_event() {
 }  // namespace
 
 thread_local bool t_suspended = false;
+
+TraceRange::TraceRange(const char* name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
 
 bool prof_enabled() { return g_on; }
 

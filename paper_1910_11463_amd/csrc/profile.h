@@ -9,6 +9,15 @@
 
 namespace pair {
 
+// A named range for tracing tools (roctx push/pop on the calling thread):
+// rocprofv3 --marker-trace shows it beside the kernels it encloses.
+struct TraceRange {
+    explicit TraceRange(const char* name);
+    ~TraceRange();
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+
 enum ProfKind : int {
     PROF_RELAX_FINE = 0,     // finest-level relaxation (F/C half-sweeps, tile sweeps)
     PROF_RESIDUAL_FINE = 1,  // r = b - A x on the finest level

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <thread>
 
+#include "profile.h"
 #include "transport.h"
 
 namespace pair {
@@ -263,6 +264,7 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
         double ta = 0.0, tsu = 0.0;
         const double t0 = now_ms();
         if (!bt.H) {
+            TraceRange tr("pair batch setup");
             assemble_batch(bt, ss, &ta);
             tsu = now_ms() - t0 - ta;
         }
@@ -280,7 +282,11 @@ bool Context::sweep(int mode, const SourceSpec& src, const double* phi_in, doubl
         if (use_warm)
             for (int b = 0; b < B; ++b) d2d(x0 + b * N, psi.p + static_cast<int64_t>(bt.dirs[b]) * N, N, ss);
         const double t2 = now_ms();
-        const bool ok = bt.H->solve(opt.use_graph != 0, !use_warm);
+        bool ok;
+        {
+            TraceRange tr("pair batch solve");
+            ok = bt.H->solve(opt.use_graph != 0, !use_warm);
+        }
         const double t3 = now_ms();
         for (int b = 0; b < B; ++b) {
             const int m = bt.dirs[b];
