@@ -310,7 +310,9 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
  * solve times only, Sec. "SOC Parameter for Building R").
  * Per-kernel timing with HIP events recorded on the library's stream around
  * selected launches (process-wide).  pair_profile_enable(1) clears the records
- * and starts recording, pair_profile_enable(0) stops.  Launches inside a
+ * and starts recording, pair_profile_enable(2) also runs the profiling-only
+ * passes that kind 6 needs (extra kernels after the timed launches: not for
+ * timed regions), pair_profile_enable(0) stops.  Launches inside a
  * hipGraph capture are not timed.  kind: 0 = FC-Jacobi half-sweeps on the
  * finest level (and tile sweeps), 1 = finest-level residual, 2 = restriction
  * from the finest level, 3 = half-sweeps on coarser levels, 4 = convergence-

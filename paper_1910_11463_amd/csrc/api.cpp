@@ -14,7 +14,7 @@ using namespace pair;
 
 namespace pair {
 int level_symmetric(int order, std::vector<double>& omega, std::vector<double>& w);
-void prof_enable(bool on);
+void prof_enable(int on);
 void prof_read(int kind, int64_t* launches, double* total_ms, double* total_bytes);
 }
 
@@ -755,7 +755,7 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
 // ----------------------------------------------------------------- profiling
 int pair_profile_enable(int on) {
     std::string err;
-    return guarded(err, nullptr, [&] { prof_enable(on != 0); });
+    return guarded(err, nullptr, [&] { prof_enable(on); });
 }
 
 int pair_profile_read(int kind, int64_t* launches, double* total_ms, double* total_bytes) {

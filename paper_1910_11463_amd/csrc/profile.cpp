@@ -18,6 +18,7 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+bool g_extra = false;    // also the profiling-only passes (PROF_RBUILD_ONCE)
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 constexpr int kMaxSlots = 4096;
@@ -48,6 +49,7 @@ ProfSuspend::~ProfSuspend() { t_suspended = prev; }
 
 int prof_begin(hipStream_t s, int kind) {
     if (!g_on || t_suspended || kind < 0 || kind >= PROF_NKINDS) return -1;
+    if (kind == PROF_RBUILD_ONCE && !g_extra) return -1;
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();
@@ -81,8 +83,9 @@ void prof_end_dev(hipStream_t s, int h) {
     PAIR_HIP(hipEventRecord(g_recs[h].b, s));
 }
 
-void prof_enable(bool on) {
+void prof_enable(int on) {
     std::lock_guard<std::mutex> g(g_mu);
+    g_extra = on >= 2;
     if (on) {
         for (auto& r : g_recs) {
             (void)hipEventSynchronize(r.b);
@@ -97,7 +100,7 @@ void prof_enable(bool on) {
         PAIR_HIP(hipDeviceSynchronize());
         g_next_slot = 0;
     }
-    g_on = on;
+    g_on = on != 0;
 }
 
 void prof_read(int kind, int64_t* launches, double* total_ms, double* total_bytes) {
