@@ -645,14 +645,7 @@ k_hex_norm_partial(int chunks, const int64_t* __restrict__ moff, const int64_t* 
 // (kept in registers).  Neighbours outside the box enter with their values in
 // xin (the previous iterate; none when xin_zero).  Boxes at the mesh's far
 // side are cut by it; a grid of members x boxes.
-//
-// A launch has one thread per element column of the whole batch, so a SIMD
-// usually holds a single wave of it and nothing else hides the latency of a
-// step's loads: every thread therefore loads what it needs for step s + PD
-// (b and sigma_t of that element, its out-of-box upwind faces) during step s,
-// into a ring of PD register slots (the step loop is unrolled by PD so that
-// the slot of a step is known at compile time).
-template <int TXY, int PD>
+template <int TXY>
 __global__ void __launch_bounds__(TXY * TXY)
 k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
            const double* __restrict__ kap, const int32_t* __restrict__ inflow,
@@ -687,81 +680,63 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
     const int64_t col = mbase + static_cast<int64_t>(j) * nx + i;
     const int kfirst = sz ? z0 + wz - 1 : z0;
     const int dk = sz ? -1 : 1;
-    double zf[4] = {0.0, 0.0, 0.0, 0.0};    // z-upwind face of the column's next element
-    // prefetch ring: slot r holds the inputs of the element of step s == r (mod PD)
-    double pb[PD][8], ps[PD], pvx[PD][4], pvy[PD][4];
-    // inputs of the element this thread solves at step s (nothing outside its column)
-    auto fetch = [&](int s, double* bq, double& sq, double* vx, double* vy) {
-        const int kp = s - ip - jp;
-        if (!(lane && kp >= 0 && kp < wz)) return;
-        const int64_t g = col + static_cast<int64_t>(kfirst + dk * kp) * nxy;
-        load8(b + g * 8, bq);
-        sq = sigt[g - mbase];
-        if (outx) {
-            const double* xu = xin + (g + (sx ? 1 : -1)) * 8 + (1 - sx);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) vx[q] = xu[2 * q];
-        }
-        if (outy) {
-            const double2* xu = reinterpret_cast<const double2*>(
-                xin + (g + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
-            const double2 lo = xu[0], hi = xu[2];
-            vy[0] = lo.x; vy[1] = lo.y; vy[2] = hi.x; vy[3] = hi.y;
-        }
-        if (kp == 0 && outz) {
-            const double2* xu = reinterpret_cast<const double2*>(xin + (g + (sz ? nxy : -nxy)) * 8 + 4 * (1 - sz));
-            const double2 lo = xu[0], hi = xu[1];
-            zf[0] = lo.x; zf[1] = lo.y; zf[2] = hi.x; zf[3] = hi.y;
-        }
-    };
-#pragma unroll
-    for (int r = 0; r < PD; ++r) fetch(r, pb[r], ps[r], pvx[r], pvy[r]);
+    double zf[4] = {0.0, 0.0, 0.0, 0.0};    // z-upwind face of the column's last element
     const int nsteps = wx + wy + wz - 2;
-    for (int s0 = 0; s0 < nsteps; s0 += PD) {
+    for (int s = 0; s < nsteps; ++s) {
+        const int kp = s - ip - jp;
+        const int p = s & 1;
+        if (lane && kp >= 0 && kp < wz) {
+            const int k = kfirst + dk * kp;
+            const int64_t g = col + static_cast<int64_t>(k) * nxy;
+            double v0[4], v1[4], v2[4];
+            if (ip > 0) {
 #pragma unroll
-        for (int r = 0; r < PD; ++r) {
-            const int s = s0 + r;
-            if (s >= nsteps) break;
-            const int kp = s - ip - jp;
-            const int p = s & 1;
-            if (lane && kp >= 0 && kp < wz) {
-                const int k = kfirst + dk * kp;
-                const int64_t g = col + static_cast<int64_t>(k) * nxy;
-                double v0[4], v1[4], v2[4];
-                if (ip > 0) {
+                for (int q = 0; q < 4; ++q) v0[q] = sh[p ^ 1][(1 - sx) + 2 * q][tid - 1];
+            } else if (outx) {
+                const double* xu = xin + (g + (sx ? 1 : -1)) * 8 + (1 - sx);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v0[q] = sh[p ^ 1][(1 - sx) + 2 * q][tid - 1];
-                } else {
+                for (int q = 0; q < 4; ++q) v0[q] = xu[2 * q];
+            } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v0[q] = outx ? pvx[r][q] : 0.0;
-                }
-                if (jp > 0) {
+                for (int q = 0; q < 4; ++q) v0[q] = 0.0;
+            }
+            if (jp > 0) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v1[q] = sh[p ^ 1][2 * (1 - sy) + (q & 1) + 4 * (q >> 1)][tid - TXY];
-                } else {
+                for (int q = 0; q < 4; ++q) v1[q] = sh[p ^ 1][2 * (1 - sy) + (q & 1) + 4 * (q >> 1)][tid - TXY];
+            } else if (outy) {
+                const double2* xu = reinterpret_cast<const double2*>(
+                    xin + (g + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
+                const double2 lo = xu[0], hi = xu[2];
+                v1[0] = lo.x; v1[1] = lo.y; v1[2] = hi.x; v1[3] = hi.y;
+            } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v1[q] = outy ? pvy[r][q] : 0.0;
-                }
+                for (int q = 0; q < 4; ++q) v1[q] = 0.0;
+            }
+            if (kp > 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v2[q] = zf[q];
-                double y[8], xn[8];
-                hex_face_solve(ps[r], dr, v0, v1, v2, y);
+            } else if (outz) {
+                const double2* xu = reinterpret_cast<const double2*>(xin + (g + (sz ? nxy : -nxy)) * 8 + 4 * (1 - sz));
+                const double2 lo = xu[0], hi = xu[1];
+                v2[0] = lo.x; v2[1] = lo.y; v2[2] = hi.x; v2[3] = hi.y;
+            } else {
 #pragma unroll
-                for (int a = 0; a < 8; ++a) xn[a] = pb[r][a] - y[a];
-                store8(xout + g * 8, xn);
-#pragma unroll
-                for (int a = 0; a < 8; ++a) sh[p][a][tid] = xn[a];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) zf[q] = xn[4 * (1 - sz) + q];
+                for (int q = 0; q < 4; ++q) v2[q] = 0.0;
             }
-            // the slot is free again: the inputs of step s + PD
-            fetch(s + PD, pb[r], ps[r], pvx[r], pvy[r]);
-            __syncthreads();
+            double bv[8], y[8], xn[8];
+            load8(b + g * 8, bv);
+            hex_face_solve(sigt[g - mbase], dr, v0, v1, v2, y);
+#pragma unroll
+            for (int a = 0; a < 8; ++a) xn[a] = bv[a] - y[a];
+            store8(xout + g * 8, xn);
+#pragma unroll
+            for (int a = 0; a < 8; ++a) sh[p][a][tid] = xn[a];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) zf[q] = xn[4 * (1 - sz) + q];
         }
+        __syncthreads();
     }
 }
-
-constexpr int kTilePrefetch = 4;   // steps of inputs in flight per thread of k_hex_tile
 
 // Class masks of the finest level: one wave per 64 rows.
 __global__ void __launch_bounds__(256)
@@ -918,11 +893,11 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
             PAIR_CHECK(blocks < (int64_t(1) << 31), "tile grid too large");
             int h = prof_begin(s_, kind);
             if (txy == 8)
-                hipLaunchKernelGGL((k_hex_tile<8, kTilePrefetch>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, s_,
+                hipLaunchKernelGGL(k_hex_tile<8>, dim3(static_cast<unsigned>(blocks)), dim3(64), 0, s_,
                                    static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, tz, mx, my, mz, E.kap.p,
                                    E.inflow.p, E.sigt.p, act, L.relax.p, L.b.p, cur, other, zero ? 1 : 0);
             else
-                hipLaunchKernelGGL((k_hex_tile<16, kTilePrefetch>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s_,
+                hipLaunchKernelGGL(k_hex_tile<16>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s_,
                                    static_cast<uint32_t>(E.E), E.nx, E.ny, E.nz, tz, mx, my, mz, E.kap.p,
                                    E.inflow.p, E.sigt.p, act, L.relax.p, L.b.p, cur, other, zero ? 1 : 0);
             prof_end(s_, h, tile_relax_bytes(L, E, txy, tz, zero));
