@@ -2489,6 +2489,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             int nrc[5];
             DBuf<int> rsing(1);
             PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
+            // mode 1 classifies by K = row length of R - 1: K <= 8, 16, 32, 64, longer
             classify<5>(total_c, 1, L.R.rowptr.p, nullptr, {8, 16, 32, 64}, rl, nrc, s_);
             for (int c = 0; c < 4; ++c) {
                 const int nr = nrc[c];
@@ -2659,11 +2660,15 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             gcols.alloc(most / 2);
             gvals.alloc(most / 2);
         }
-        // staging of rows of R longer than RMAX (all of them are in the global class)
+        // staging of rows of R longer than RMAX (all of them are in the global
+        // class): one slice per row of a launch, indexed by the row's position in
+        // its launch, so sized for the launch with the most rows
         const int sld = r_longest > RMAX ? r_longest : 0;
-        DBuf<int> gpref(sld > 0 ? static_cast<size_t>(lcount[5]) * (sld + 1) : 0);
-        DBuf<int64_t> gbase(sld > 0 ? static_cast<size_t>(lcount[5]) * sld : 0);
-        DBuf<double> grv(sld > 0 ? static_cast<size_t>(lcount[5]) * sld : 0);
+        int chunk_rows = 0;
+        for (size_t k = 0; k + 1 < gchunks.size(); ++k) chunk_rows = std::max(chunk_rows, gchunks[k + 1] - gchunks[k]);
+        DBuf<int> gpref(sld > 0 ? static_cast<size_t>(chunk_rows) * (sld + 1) : 0);
+        DBuf<int64_t> gbase(sld > 0 ? static_cast<size_t>(chunk_rows) * sld : 0);
+        DBuf<double> grv(sld > 0 ? static_cast<size_t>(chunk_rows) * sld : 0);
                 auto run_rap = [&](bool numeric, Csr* C) {
             int64_t* cnt_out = ccnt.p;
             const int64_t* crp = numeric ? C->rowptr.p : nullptr;
@@ -2711,11 +2716,10 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             PAIR_LAUNCH_CHECK();
             for (size_t k = 0; k + 1 < gchunks.size(); ++k) {
                 const int a = gchunks[k], nr = gchunks[k + 1] - a;
-                const size_t pa = sld > 0 ? static_cast<size_t>(a) * (sld + 1) : 0;
-                const size_t ba = sld > 0 ? static_cast<size_t>(a) * sld : 0;
+                // launches run in turn on this stream, so each reuses the staging slices
 #define PAIR_RAPG_ARGS nr, lists[5].p + a, gscr_off.p + a, gkeys.p, gpos.p, gcols.p, gvals.p, L.R.rowptr.p, \
                        L.R.col.p, L.R.val.p, L.A.rowptr.p, ap_len.p, ap_col.p, ap_val.p, cnt_out, crp, ccol, cval, \
-                       gpref.p + pa, gbase.p + ba, grv.p + ba, sld, gscr_off_h[a]
+                       gpref.p, gbase.p, grv.p, sld, gscr_off_h[a]
                 if (numeric)
                     hipLaunchKernelGGL((k_rap_global<true>), dim3(nr), dim3(256), 0, s_, PAIR_RAPG_ARGS);
                 else
