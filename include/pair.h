@@ -127,13 +127,14 @@ typedef struct pair_options {
                                  magnitude <= 1e-12 use the stored form.  0: always
                                  use the stored element-block values                  */
     int tile_xy;              /* tile sweeps, letter "T" in relax_pre / relax_post
-                                 (finest level of a structured hex mesh with the
-                                 factored operator only): block Jacobi over boxes of
+                                 (finest level only; on a structured hex mesh with
+                                 the factored operator): block Jacobi over boxes of
                                  tile_xy x tile_xy x tile_z elements with an exact
                                  forward solve inside each box — the relaxation by an
                                  on-processor solve of Sec. "Use of Algebraic
                                  Multigrid", a box standing for a processor; undamped
-                                 (omega does not apply).  tile_xy: 8 (default) or 16 */
+                                 (omega does not apply).  tile_xy: 8 (default) or 16.
+                                 Tet meshes use tet_tile_boxes instead               */
     int tile_z;               /* box height in elements; 0 (default): the mesh's whole
                                  z extent                                            */
     int nair_degree;          /* 0 (default): lAIR restriction.  1: nAIR of Neumann
@@ -142,6 +143,14 @@ typedef struct pair_options {
                                  R_cf = -A_cf (I + (I - D_ff^-1 A_ff)) D_ff^-1 over all
                                  entries of A, then the filter_r filter; a row with
                                  more than 1024 contributions is an error            */
+    int tet_tile_boxes;       /* tile sweeps ("T") on a tet mesh: the mesh's bounding box
+                                 is cut into tet_tile_boxes^3 equal boxes and an element
+                                 belongs to the box of its centroid (x0+x1+x2+x3)/4; one
+                                 tile sweep is block Jacobi over these tiles with an exact
+                                 solve inside each (upwind order, no cycles inside a tile,
+                                 else PAIR_E_INVALID).  0 (default): the smallest count
+                                 with n_elem <= 384 count^3.  A tile may hold at most 1024
+                                 elements                                              */
 } pair_options;
 
 void pair_default_options(pair_options* opt);

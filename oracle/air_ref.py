@@ -380,6 +380,38 @@ def hex_tiles(nx: int, ny: int, nz: int, tx: int, ty: int, tz: int) -> np.ndarra
     return np.repeat(t, 8)
 
 
+TET_TILE_TARGET = 384      # mean tets per tile when the box count is automatic
+
+
+def tet_tile_boxes(E: int, nbox: int = 0) -> int:
+    """Boxes per axis of the tet tiles: nbox if > 0, else the smallest count
+    with E <= 384 nbox^3 (a box of about 4 x 4 x 4 Kuhn cubes)."""
+    if nbox > 0:
+        return nbox
+    n = 1
+    while E > TET_TILE_TARGET * n ** 3:
+        n += 1
+    return n
+
+
+def tet_tiles(xyz: np.ndarray, elem_vert: np.ndarray, nbox: int = 0) -> np.ndarray:
+    """Tile index of every row of a P1 tet mesh (4 rows per element, DOF 4 t + a):
+    the mesh's bounding box cut into nbox^3 equal boxes, an element in the box of
+    its centroid ((x0 + x1 + x2 + x3) / 4, summed in vertex order; a coordinate
+    exactly on the far face goes to the last box)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    ev = np.asarray(elem_vert, dtype=np.int64)
+    nb = tet_tile_boxes(ev.shape[0], nbox)
+    X = xyz[ev]                                   # [E,4,3]
+    c = (((X[:, 0] + X[:, 1]) + X[:, 2]) + X[:, 3]) * 0.25
+    lo = xyz.min(axis=0)
+    hi = xyz.max(axis=0)
+    q = np.floor((c - lo) / (hi - lo) * nb).astype(np.int64)
+    q = np.clip(q, 0, nb - 1)
+    t = q[:, 0] + nb * (q[:, 1] + nb * q[:, 2])
+    return np.repeat(t, 4)
+
+
 class TileSolver:
     """Block Jacobi over tiles with exact local solves (the paper's relaxation by
     an on-processor solve, Sec. "Use of Algebraic Multigrid": each processor

@@ -41,7 +41,8 @@ class pair_options(ctypes.Structure):
                 ("relax_pre_coarse", ctypes.c_char * 16), ("relax_post_coarse", ctypes.c_char * 16),
                 ("streams", c_int), ("coarse_fp32", c_int), ("fixed_cycles", c_int),
                 ("filter_r", c_double), ("fine_factored", c_int),
-                ("tile_xy", c_int), ("tile_z", c_int), ("nair_degree", c_int)]
+                ("tile_xy", c_int), ("tile_z", c_int), ("nair_degree", c_int),
+                ("tet_tile_boxes", c_int)]
 
 
 class pair_stats(ctypes.Structure):

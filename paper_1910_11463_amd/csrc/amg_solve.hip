@@ -738,6 +738,133 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
     }
 }
 
+// ---------------------------------------------------------------- tet tiles
+// Tile sweep on a tet mesh (stored element blocks): block Jacobi over the
+// element tiles with an exact solve inside each, the relaxation by an
+// on-processor solve of Sec. "Use of Algebraic Multigrid" with a tile standing
+// for a processor.  The scaled operator restricted to a tile is block lower
+// triangular in upwind order with identity diagonal blocks, so the solve is a
+// forward substitution by upwind levels: level L holds the elements whose
+// longest upwind path inside the tile has L steps, independent of each other.
+// One wave per (member, tile); four lanes per element (one per row), sixteen
+// elements at a time; the tile's new values are kept in LDS for the levels
+// above, values of upwind elements outside the tile come from xin (the
+// previous iterate; none when xin_zero).
+constexpr int kTetTileMax = 1024;   // elements of a tile (LDS: 32 B each)
+
+template <int NF>
+__global__ void __launch_bounds__(64)
+k_tet_tile(int T, int Lmax, int64_t E, int64_t nel, int64_t n, int64_t nF,
+           const int32_t* __restrict__ tile_ptr, const int32_t* __restrict__ loc,
+           const int32_t* __restrict__ tile_of, const int32_t* __restrict__ order,
+           const int32_t* __restrict__ lvl, const int32_t* __restrict__ nbr,
+           const int32_t* __restrict__ nodes, const double* __restrict__ val,
+           const uint64_t* __restrict__ cmask, const int64_t* __restrict__ fbase,
+           const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
+           const double* __restrict__ b, const double* __restrict__ xin, double* __restrict__ xout,
+           int xin_zero) {
+    extern __shared__ double xt[];          // [tile size][4]
+    const int64_t m = blockIdx.x / T;
+    const int t = static_cast<int>(blockIdx.x - m * T);
+    if (!(active[m] && relax[m])) return;
+    const int64_t tb = tile_ptr[t];
+    const int32_t* lv = lvl + (m * T + t) * (Lmax + 2);
+    const int sub = threadIdx.x & 3, q0 = threadIdx.x >> 2;
+    const int64_t mE = m * E;
+    for (int L = 0; L <= Lmax; ++L) {
+        const int a0 = lv[L], a1 = lv[L + 1];
+        if (a0 >= a1) break;                 // levels are dense: the tile is done
+        for (int q = a0 + q0; q < a1; q += 16) {
+            const int32_t e = order[mE + tb + q];
+            const int64_t g = mE + e;
+            const int64_t row = 4 * g + sub;
+            const EllRow<NF> er(row, n, nF, cmask, fbase, val);
+            const EllNbr nb(g, nel, nbr, nodes);
+            double s = 0.0;
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+                if (nb.u[sl] < 0) continue;
+                const int64_t ul = nb.u[sl] - mE;
+                const bool in = tile_of[ul] == t;
+                const double* xs = in ? xt + 4 * loc[ul] : (xin_zero ? nullptr : xin + 4 * nb.u[sl]);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    const double xu = xs ? xs[(nb.pk[sl] >> (3 * j)) & 7] : 0.0;
+                    s += er.v[(sl * NF + j) * er.stride + er.p] * xu;
+                }
+            }
+            const double xn = b[row] - s;
+            xout[row] = xn;
+            xt[4 * loc[e] + sub] = xn;
+        }
+        __syncthreads();
+    }
+}
+
+// Longest upwind path inside the tile, every element of the batch (g = m E + e):
+// lev[g] = max(lev[U] + 1) over its upwind neighbours U in the same tile.  In
+// place and monotone: repeated until nothing changes (the unique fixed point
+// is reached whatever the update order); a cycle inside a tile never settles.
+__global__ void k_tet_levels(int64_t nel, int64_t E, const int32_t* __restrict__ nbr,
+                             const int32_t* __restrict__ tile_of, int* __restrict__ lev,
+                             int* __restrict__ changed) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nel) return;
+    const int64_t mE = g / E * E;
+    const int t = tile_of[g - mE];
+    int L = 0;
+    for (int sl = 0; sl < 3; ++sl) {
+        const int32_t u = nbr[sl * nel + g];
+        if (u >= 0 && tile_of[u - mE] == t) L = max(L, __atomic_load_n(&lev[u], __ATOMIC_RELAXED) + 1);
+    }
+    if (L > lev[g]) {
+        __atomic_store_n(&lev[g], L, __ATOMIC_RELAXED);
+        *changed = 1;
+    }
+}
+
+__global__ void k_tet_level_max(int64_t nel, const int* __restrict__ lev, int* __restrict__ mx) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int v = g < nel ? lev[g] : 0;
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+}
+
+// bucket (member, tile, level) of every element: count, then scatter
+__global__ void k_tet_bucket_count(int64_t nel, int64_t E, int T, int Lmax,
+                                   const int32_t* __restrict__ tile_of, const int* __restrict__ lev,
+                                   unsigned long long* __restrict__ cnt) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nel) return;
+    const int64_t m = g / E;
+    const int64_t k = (m * T + tile_of[g - m * E]) * (Lmax + 1) + lev[g];
+    atomicAdd(&cnt[k], 1ull);
+}
+
+__global__ void k_tet_bucket_scatter(int64_t nel, int64_t E, int T, int Lmax,
+                                     const int32_t* __restrict__ tile_of, const int* __restrict__ lev,
+                                     const int64_t* __restrict__ off, unsigned long long* __restrict__ cur,
+                                     int32_t* __restrict__ order) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nel) return;
+    const int64_t m = g / E;
+    const int64_t k = (m * T + tile_of[g - m * E]) * (Lmax + 1) + lev[g];
+    const int64_t pos = off[k] + static_cast<int64_t>(atomicAdd(&cur[k], 1ull));
+    order[pos] = static_cast<int32_t>(g - m * E);
+}
+
+// level offsets of every (member, tile) relative to the tile's first position
+__global__ void k_tet_level_offsets(int B, int T, int Lmax, int64_t E, const int32_t* __restrict__ tile_ptr,
+                                    const int64_t* __restrict__ off, int32_t* __restrict__ lvl) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= static_cast<int64_t>(B) * T) return;
+    const int64_t m = k / T;
+    const int t = static_cast<int>(k - m * T);
+    const int64_t base = m * E + tile_ptr[t];
+    for (int L = 0; L <= Lmax; ++L) lvl[k * (Lmax + 2) + L] = static_cast<int32_t>(off[k * (Lmax + 1) + L] - base);
+    lvl[k * (Lmax + 2) + Lmax + 1] = tile_ptr[t + 1] - tile_ptr[t];
+}
+
 // Class masks of the finest level: one wave per 64 rows.
 __global__ void __launch_bounds__(256)
 k_ell_cmask(int64_t n, const int8_t* __restrict__ cf, uint64_t* __restrict__ cmask,
@@ -791,6 +918,19 @@ double ell_residual_bytes(const Level& L, const FineEll& e) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     if (e.factored) return 24.0 * n + 8.0 * static_cast<double>(e.nel);
     return n * (24.0 * e.nf + 8.0 + 8.0 + 8.0 + 2.25) + 24.0 * static_cast<double>(e.nel);
+}
+
+// Tile sweep on tets: b read, x written, the rows' element-block values and
+// neighbour lists, the tile data and the order once, and the previous iterate's
+// face values of upwind elements outside the tile (counted as every face: an
+// upper bound; none from x = 0).
+double tet_tile_relax_bytes(const Level& L, const FineEll& e, bool zero) {
+    const double n = static_cast<double>(L.n_f + L.n_c);
+    const double nel = static_cast<double>(e.nel);
+    double b = 16.0 * n + n * 24.0 * e.nf + 24.0 * nel + 4.0 * nel + 8.0 * static_cast<double>(e.E) +
+               4.0 * static_cast<double>(e.lvl.n);
+    if (!zero) b += 8.0 * e.nf * 3.0 * nel;
+    return b;
 }
 
 // Tile sweep over all members: b read and x written once, sigma_t and the
@@ -872,6 +1012,63 @@ double restrict_bytes(const Level& L, double vb = 8.0) {
 
 }  // namespace
 
+void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* loc, const int32_t* tile_ptr,
+                       int T, int tmax, hipStream_t s) {
+    PAIR_CHECK(!fe.factored && fe.k == 4 && fe.nf == 3, "tet tile schedule needs the stored tet form");
+    const int64_t nel = fe.nel;          // elements of the batch
+    const int64_t Em = fe.E;             // elements per member
+    PAIR_CHECK(Em > 0 && nel % Em == 0, "tet tile schedule: elements per member unknown");
+    const int B = static_cast<int>(nel / Em);
+    fe.tile_of.alloc(Em);
+    fe.tile_loc.alloc(Em);
+    fe.tile_ptr.alloc(T + 1);
+    d2d(fe.tile_of.p, tile_of, Em, s);
+    d2d(fe.tile_loc.p, loc, Em, s);
+    d2d(fe.tile_ptr.p, tile_ptr, T + 1, s);
+    DBuf<int> lev(nel), flag(2);
+    PAIR_HIP(hipMemsetAsync(lev.p, 0, nel * sizeof(int), s));
+    int changed = 1, it = 0;
+    while (changed) {
+        PAIR_CHECK(++it <= tmax + 1, "tile sweeps: an upwind cycle inside a tet tile (the exact tile "
+                                     "solve needs an acyclic upwind order inside each tile)");
+        PAIR_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_tet_levels, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.nbr.p,
+                           fe.tile_of.p, lev.p, flag.p);
+        PAIR_LAUNCH_CHECK();
+        d2h(&changed, flag.p, 1, s);
+        PAIR_HIP(hipStreamSynchronize(s));
+    }
+    PAIR_HIP(hipMemsetAsync(flag.p + 1, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_tet_level_max, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, lev.p, flag.p + 1);
+    PAIR_LAUNCH_CHECK();
+    int Lmax = 0;
+    d2h(&Lmax, flag.p + 1, 1, s);
+    PAIR_HIP(hipStreamSynchronize(s));
+    const int64_t nb = static_cast<int64_t>(B) * T * (Lmax + 1);
+    DBuf<unsigned long long> cnt(nb), cur(nb);
+    DBuf<int64_t> off(nb + 1);
+    PAIR_HIP(hipMemsetAsync(cnt.p, 0, nb * sizeof(unsigned long long), s));
+    PAIR_HIP(hipMemsetAsync(cur.p, 0, nb * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_tet_bucket_count, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, T, Lmax,
+                       fe.tile_of.p, lev.p, cnt.p);
+    PAIR_LAUNCH_CHECK();
+    exclusive_scan(reinterpret_cast<const int64_t*>(cnt.p), off.p, nb, s);
+    fe.order.alloc(nel);
+    hipLaunchKernelGGL(k_tet_bucket_scatter, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, T, Lmax,
+                       fe.tile_of.p, lev.p, off.p, cur.p, fe.order.p);
+    PAIR_LAUNCH_CHECK();
+    fe.lvl.alloc(static_cast<size_t>(B) * T * (Lmax + 2));
+    hipLaunchKernelGGL(k_tet_level_offsets, dim3(grid_for(static_cast<int64_t>(B) * T, 256)), dim3(256), 0, s,
+                       B, T, Lmax, Em, fe.tile_ptr.p, off.p, fe.lvl.p);
+    PAIR_LAUNCH_CHECK();
+    PAIR_HIP(hipStreamSynchronize(s));
+    fe.tet_tiles = true;
+    fe.T = T;
+    fe.Lmax = Lmax;
+    fe.tmax = tmax;
+}
+
+
 // Half-sweeps of a schedule ("FC", "FFC", ...) alternating between two buffers;
 // returns the buffer holding the result.  `zero`: cur is known to be 0 (the
 // first half-sweep then reads neither the matrix nor cur).
@@ -882,9 +1079,26 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
     const int kind = l == 0 ? PROF_RELAX_FINE : PROF_RELAX_COARSE;
     for (char ch : sched) {
         const int8_t which = ch == 'F' ? -1 : 1;
+        if (ch == 'T' && l == 0 && ell_ && ell_->tet_tiles) {
+            const FineEll& E = *ell_;
+            const int64_t members = E.nel / E.E;
+            const int64_t blocks = members * E.T;
+            PAIR_CHECK(blocks < (int64_t(1) << 31), "tile grid too large");
+            int h = prof_begin(s_, kind);
+            hipLaunchKernelGGL(k_tet_tile<3>, dim3(static_cast<unsigned>(blocks)), dim3(64),
+                               static_cast<size_t>(E.tmax) * 4 * sizeof(double), s_, E.T, E.Lmax, E.E, E.nel,
+                               E.nrows, E.nF, E.tile_ptr.p, E.tile_loc.p, E.tile_of.p, E.order.p, E.lvl.p,
+                               E.nbr.p, E.nodes.p, E.val.p, E.cmask.p, E.fbase.p, act, L.relax.p, L.b.p, cur,
+                               other, zero ? 1 : 0);
+            prof_end(s_, h, tet_tile_relax_bytes(L, E, zero));
+            PAIR_LAUNCH_CHECK();
+            std::swap(cur, other);
+            zero = false;
+            continue;
+        }
         if (ch == 'T') {
             PAIR_CHECK(l == 0 && ell_ && ell_->factored,
-                       "tile sweeps (T) need the factored operator on the finest level");
+                       "tile sweeps (T) need the factored operator or tet tiles on the finest level");
             const FineEll& E = *ell_;
             const int txy = prm_.tile_xy, tz = prm_.tile_z > 0 ? std::min(prm_.tile_z, E.nz) : E.nz;
             const int mx = (E.nx + txy - 1) / txy, my = (E.ny + txy - 1) / txy, mz = (E.nz + tz - 1) / tz;
@@ -1352,7 +1566,9 @@ double Hierarchy::solve_bytes_per_cycle() const {
         for (const std::string* sc : {&pre, &post}) {
             for (char ch : *sc) {
                 const int which = ch == 'F' ? -1 : 1;
-                if (ch == 'T' && l == 0 && ell_) {
+                if (ch == 'T' && l == 0 && ell_ && ell_->tet_tiles) {
+                    bytes += tet_tile_relax_bytes(L, *ell_, zero);
+                } else if (ch == 'T' && l == 0 && ell_) {
                     const int tz = prm_.tile_z > 0 ? std::min(prm_.tile_z, ell_->nz) : ell_->nz;
                     bytes += tile_relax_bytes(L, *ell_, prm_.tile_xy, tz, zero);
                 } else

@@ -103,6 +103,7 @@ void validate_options(const pair_options& o) {
     PAIR_CHECK(o.tile_xy == 8 || o.tile_xy == 16, "tile_xy must be 8 or 16");
     PAIR_CHECK(o.nair_degree == 0 || o.nair_degree == 1, "nair_degree must be 0 or 1");
     PAIR_CHECK(o.tile_z >= 0 && o.tile_z <= (1 << 20), "tile_z must be in [0, 2^20]");
+    PAIR_CHECK(o.tet_tile_boxes >= 0 && o.tet_tile_boxes <= 1024, "tet_tile_boxes must be in [0, 1024]");
     constexpr size_t kS = sizeof(o.relax_pre);
     auto sched_ok = [&](const char* c, bool tiles) {
         size_t n = strnlen(c, kS);
@@ -218,6 +219,7 @@ void pair_default_options(pair_options* o) {
     o->tile_xy = 8;
     o->tile_z = 0;
     o->nair_degree = 0;
+    o->tet_tile_boxes = 0;
 }
 
 int pair_create(pair_ctx** out, const pair_options* opt, void* hip_stream) {
@@ -259,6 +261,7 @@ int pair_set_options(pair_ctx* ctx, const pair_options* opt) {
             opt->coarse_fp32 != c.opt.coarse_fp32 || opt->filter_r != c.opt.filter_r ||
             opt->fine_factored != c.opt.fine_factored || opt->tile_xy != c.opt.tile_xy ||
             opt->tile_z != c.opt.tile_z || opt->nair_degree != c.opt.nair_degree ||
+            opt->tet_tile_boxes != c.opt.tet_tile_boxes ||
             std::strncmp(opt->relax_pre, c.opt.relax_pre, sizeof(opt->relax_pre)) != 0 ||
             std::strncmp(opt->relax_post, c.opt.relax_post, sizeof(opt->relax_post)) != 0 ||
             std::strncmp(opt->relax_pre_coarse, c.opt.relax_pre_coarse, sizeof(opt->relax_pre_coarse)) != 0 ||
@@ -344,6 +347,9 @@ int pair_set_mesh(pair_ctx* ctx, int elem_type, int64_t n_vert, const double* xy
         h2d(m.ev.p, elem_vert, n_elem * 4, c.s);
         h2d(m.nbr.p, nbr.data(), n_elem * 4, c.s);
         tet_geometry(m, n_vert, c.s);
+        c.tet_xyz_h.assign(xyz, xyz + n_vert * 3);
+        c.tet_ev_h.assign(elem_vert, elem_vert + n_elem * 4);
+        c.tet_tiles_nbox = -1;
         c.mesh = std::move(m);
         c.have_mesh = true;
         c.have_mats = false;

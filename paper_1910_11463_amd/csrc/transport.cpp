@@ -111,9 +111,11 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     for (int m : bt.dirs)
         for (int d = 0; d < 3; ++d) fact = fact && std::fabs(omega_h[3 * m + d]) > kZeroFluxTol;
     const bool tiles = std::strchr(opt.relax_pre, 'T') || std::strchr(opt.relax_post, 'T');
-    PAIR_CHECK(fact || !tiles,
-               "tile sweeps (T) need a structured hex mesh, fine_factored = 1 and no direction "
-               "component of magnitude <= 1e-12");
+    PAIR_CHECK(fact || !tiles || mesh.kind == PAIR_TET4,
+               "tile sweeps (T) on hexes need fine_factored = 1 and no direction component of "
+               "magnitude <= 1e-12");
+    if (tiles && mesh.kind == PAIR_TET4) build_tet_tiles(s);
+    fe.E = E;
     std::vector<double> kap;      // host sources of the copies below: kept until the
     std::vector<int32_t> in;      // stream synchronisation at the end of fine_assemble
     if (fact) {
@@ -139,8 +141,65 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     }
     fine_assemble(mesh, omega_d.p, dirs_d.p, B, sigt.p, eoff.p, nnz, A.rowptr.p, A.col.p, A.val.p,
                   bt.dinv.p, fe, s);
+    if (tiles && mesh.kind == PAIR_TET4)
+        tet_tile_schedule(fe, tet_tile_of.p, tet_tile_loc.p, tet_tile_ptr.p, tet_ntiles, tet_tile_max, s);
     if (t_assemble_ms) *t_assemble_ms += now_ms() - t0;
     return A;
+}
+
+// Tiles of tile sweeps on a tet mesh (member-independent, built once per mesh
+// and box count): the bounding box of the vertices cut into nb^3 equal boxes,
+// an element in the box of its centroid ((x0 + x1 + x2 + x3) / 4, summed in
+// vertex order), the last box taking a centroid on the far face; nb from
+// tet_tile_boxes, or the smallest count with E <= 384 nb^3.
+void Context::build_tet_tiles(hipStream_t st) {
+    std::lock_guard<std::mutex> lock(tet_tiles_mu);
+    const int64_t E = mesh.E;
+    int nb = opt.tet_tile_boxes;
+    if (nb <= 0) {
+        nb = 1;
+        while (E > int64_t(384) * nb * nb * nb) ++nb;
+    }
+    if (tet_tiles_nbox == nb && tet_tile_of.p) return;
+    const int64_t nv = static_cast<int64_t>(tet_xyz_h.size() / 3);
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = tet_xyz_h[d];
+    for (int64_t v = 0; v < nv; ++v)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], tet_xyz_h[3 * v + d]);
+            hi[d] = std::max(hi[d], tet_xyz_h[3 * v + d]);
+        }
+    const int64_t T = static_cast<int64_t>(nb) * nb * nb;
+    PAIR_CHECK(T < (int64_t(1) << 30), "too many tet tiles");
+    std::vector<int32_t> tof(E), loc(E), tptr(T + 1, 0);
+    for (int64_t e = 0; e < E; ++e) {
+        int q[3];
+        for (int d = 0; d < 3; ++d) {
+            const int32_t* ve = &tet_ev_h[4 * e];
+            const double c = (((tet_xyz_h[3 * ve[0] + d] + tet_xyz_h[3 * ve[1] + d]) + tet_xyz_h[3 * ve[2] + d]) +
+                              tet_xyz_h[3 * ve[3] + d]) * 0.25;
+            const double f = std::floor((c - lo[d]) / (hi[d] - lo[d]) * nb);
+            q[d] = static_cast<int>(std::min<double>(std::max<double>(f, 0.0), nb - 1));
+        }
+        tof[e] = q[0] + nb * (q[1] + nb * q[2]);
+        loc[e] = tptr[tof[e] + 1]++;
+    }
+    int tmax = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        tmax = std::max(tmax, tptr[t + 1]);
+        tptr[t + 1] += tptr[t];
+    }
+    PAIR_CHECK(tmax <= 1024, "a tet tile holds more than 1024 elements: raise tet_tile_boxes");
+    tet_tile_of.alloc(E);
+    tet_tile_loc.alloc(E);
+    tet_tile_ptr.alloc(T + 1);
+    h2d(tet_tile_of.p, tof.data(), E, st);
+    h2d(tet_tile_loc.p, loc.data(), E, st);
+    h2d(tet_tile_ptr.p, tptr.data(), T + 1, st);
+    PAIR_HIP(hipStreamSynchronize(st));
+    tet_ntiles = static_cast<int>(T);
+    tet_tile_max = tmax;
+    tet_tiles_nbox = nb;
 }
 
 void Context::assemble_batch(Batch& bt, hipStream_t s, double* t_assemble_ms) {

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -78,6 +79,15 @@ struct Context {
 
     DBuf<double> inflow;                // [M][N] nodal inflow values (zero: vacuum)
     bool have_inflow = false;
+
+    // tet meshes: host copies (tile assignment) and the tiles of tile sweeps
+    std::vector<double> tet_xyz_h;
+    std::vector<int32_t> tet_ev_h;
+    int tet_tiles_nbox = -1;            // box count the device tiles below were built for
+    int tet_ntiles = 0, tet_tile_max = 0;
+    DBuf<int32_t> tet_tile_of, tet_tile_loc, tet_tile_ptr;
+    std::mutex tet_tiles_mu;            // worker threads may assemble batches at once
+    void build_tet_tiles(hipStream_t st);
 
     // cached operators
     std::vector<Batch> batches;

@@ -114,15 +114,24 @@ def test_one_box_is_the_exact_solve():
 def test_tile_schedule_errors():
     need_gpu()
     from paper_1910_11463_amd.solver import Solver
-    w = wl.make_config(3, scale=2)
-    s = solver_for(w, relax_pre="T", relax_post="F", relax_pre_coarse="F", relax_post_coarse="F")
+    w = wl.make_config(2, scale=3)
+    s = solver_for(w, relax_pre="T", relax_post="F", relax_pre_coarse="F", relax_post_coarse="F",
+                   fine_factored=0)
     with pytest.raises(B.PairError) as e:
         s.transport_sweep(mode=B.PAIR_BATCHED)
     assert "tile sweeps" in str(e.value)
     s.close()
+    # a tet tile holding more than 1024 elements
+    w = wl.make_config(3, scale=6)
+    s = solver_for(w, relax_pre="T", relax_post="T", relax_pre_coarse="F", relax_post_coarse="",
+                   tet_tile_boxes=1)
+    with pytest.raises(B.PairError) as e:
+        s.transport_sweep(mode=B.PAIR_BATCHED)
+    assert "more than 1024" in str(e.value)
+    s.close()
     s = Solver()
     for bad in (dict(relax_pre="T"), dict(relax_pre="FT", relax_pre_coarse="T"),
-                dict(tile_xy=4), dict(tile_z=-1)):
+                dict(tile_xy=4), dict(tile_z=-1), dict(tet_tile_boxes=-1)):
         with pytest.raises(B.PairError) as e:
             s.set_options(**bad)
         assert e.value.code == B.PAIR_E_INVALID
@@ -169,3 +178,95 @@ def test_tile_streams_bitwise():
         s.close()
     for x, y in zip(out[0], out[1]):
         assert np.array_equal(x, y)
+
+
+def _tets(n, seed):
+    mesh = wl.kuhn_tet_mesh(n, jitter=0.2, seed=seed)
+    E = mesh.n_elem
+    st = wl.log_uniform(E, 0.1, 10.0, seed=seed + 1)
+    return wl.Workload("tet%d^3x6-S4" % n, mesh, wl.Materials(st, 0.5 * st, np.ones(E)), 4)
+
+
+# (mesh size, tet_tile_boxes, pre, post, directions)
+TET_CASES = [(5, 2, "T", "T", (0, 7, 13, 23)), (5, 0, "TF", "FT", (2, 19)), (4, 3, "TT", "C", (5, 11))]
+
+
+@pytest.mark.parametrize("case", range(len(TET_CASES)))
+def test_tet_tile_cycles_match_oracle_two_level_cycles(case):
+    """Jittered tets: two two-level V-cycles from x = 0 per direction with tile
+    sweeps over the centroid-box tiles on the finest level, against the
+    oracle's setup, TileSolver (sparse LU of the tile-diagonal part) and
+    V-cycle on the library's exported operator."""
+    need_gpu()
+    from oracle import air_ref as ar
+    n, nbox, pre, post, dirs = TET_CASES[case]
+    w = _tets(n, seed=20 + case)
+    s = solver_for(w, fixed_cycles=2, filter_r=1.0, batch_size=12, max_levels=2, relax_pre=pre,
+                   relax_post=post, relax_pre_coarse="F", relax_post_coarse="", tet_tile_boxes=nbox)
+    _print("tet tiles", w.name, "boxes", nbox, "schedules", pre, post)
+    psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_BATCHED)
+    assert rc == B.PAIR_OK
+    tiles = ar.tet_tiles(w.mesh.xyz, w.mesh.elem_vert, nbox)
+    opts = ar.Options(filter_r=1.0, max_levels=2)
+    for m in dirs:
+        rp, col, val, b = s.export_fine_operator(m)
+        A = sp.csr_matrix((val, col, rp), shape=(b.shape[0], b.shape[0]))
+        levels = ar.setup(A, opts)
+        ts = ar.TileSolver(A, tiles)
+        x = np.zeros_like(b)
+        for _ in range(2):
+            x = ar.vcycle(levels, b, x, pre=pre, post=post, pre_c="F", post_c="", tiles=ts)
+        _print("  direction", m, "rel diff %.2e" % rel(psi[m], x))
+        assert len(levels) == 2
+        assert rel(psi[m], x) <= 1e-12, m
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [B.PAIR_PLAIN, B.PAIR_BATCHED])
+def test_tet_tile_solve_converges_to_exact_sweep(mode):
+    """Full hierarchies with tet tile sweeps reach the oracle's exact sweep."""
+    need_gpu()
+    from oracle import source_iteration as si
+    w = wl.make_config(3, scale=8)
+    s = solver_for(w, tol_inner=1e-12, max_inner=200, batch_size=12, filter_r=1.0,
+                   relax_pre="TT", relax_post="TT", relax_pre_coarse="F", relax_post_coarse="")
+    _print("tet tile solve", w.name, "mode", mode)
+    psi, phi, st, rc = s.transport_sweep(mode=mode)
+    assert rc == B.PAIR_OK
+    ref = si.transport_sweep(oracle_problem(w), None)
+    for m in range(len(ref)):
+        assert rel(psi[m], ref[m]) <= 1e-9, (m, rel(psi[m], ref[m]))
+    _print("  V-cycles max", st["vcycles_max"])
+    s.close()
+
+
+def test_tet_one_tile_is_the_exact_solve():
+    """One tile holding the whole tet mesh: one tile sweep is the exact solve."""
+    need_gpu()
+    from oracle import source_iteration as si
+    w = wl.make_config(3, scale=5)              # 750 tets, one tile
+    s = solver_for(w, fixed_cycles=1, filter_r=1.0, batch_size=12, relax_pre="T", relax_post="",
+                   relax_pre_coarse="F", relax_post_coarse="", tet_tile_boxes=1)
+    psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_BATCHED)
+    assert rc == B.PAIR_OK
+    ref = si.transport_sweep(oracle_problem(w), None)
+    for m in range(len(ref)):
+        assert rel(psi[m], ref[m]) <= 1e-12, (m, rel(psi[m], ref[m]))
+    s.close()
+
+
+def test_tet_tile_batched_equals_plain_and_streams_bitwise():
+    """Tet tile sweeps: batched == plain, and three worker streams == one, bitwise."""
+    need_gpu()
+    w = _tets(7, seed=31)
+    opts = dict(relax_pre="TT", relax_post="TT", relax_pre_coarse="F", relax_post_coarse="", filter_r=1.0,
+                tol_inner=1e-10, max_inner=60)
+    out = []
+    for mode, bs, streams in ((B.PAIR_PLAIN, 0, 1), (B.PAIR_BATCHED, 8, 1), (B.PAIR_BATCHED, 8, 3)):
+        s = solver_for(w, batch_size=bs, streams=streams, **opts)
+        psi, phi, _, rc = s.transport_sweep(mode=mode)
+        assert rc == B.PAIR_OK
+        out.append((psi, phi))
+        s.close()
+    for k in (1, 2):
+        assert np.array_equal(out[0][0], out[k][0]) and np.array_equal(out[0][1], out[k][1])

@@ -392,3 +392,42 @@ def test_distance2_is_ideal_on_upwind_chain_with_short_f_runs():
     assert np.abs(d1 - ideal).max() > 0.1
     # the ideal row of C point 3 by hand: -a_32 (A_ff^{-1})_{2,:} over F = {1, 2}
     assert np.isclose(ideal[1, 2], c[3]) and np.isclose(ideal[1, 1], c[3] * c[2])
+
+
+def test_tet_tiles_partition_by_centroid_box():
+    """Every element is in exactly one tile, the tile of the box holding its
+    centroid; the automatic box count keeps the mean tile at <= 384 tets."""
+    mesh = wl.kuhn_tet_mesh(6, jitter=0.2, seed=4)
+    E = mesh.n_elem
+    nb = AR.tet_tile_boxes(E)
+    assert E <= 384 * nb ** 3 and (nb == 1 or E > 384 * (nb - 1) ** 3)
+    t = AR.tet_tiles(mesh.xyz, mesh.elem_vert)
+    assert t.shape == (4 * E,) and np.all(t[0::4] == t[3::4])
+    te = t[0::4]
+    c = mesh.xyz[mesh.elem_vert].mean(axis=1)
+    lo, hi = mesh.xyz.min(axis=0), mesh.xyz.max(axis=0)
+    for e in range(0, E, 7):
+        q = (te[e] % nb, (te[e] // nb) % nb, te[e] // nb ** 2)
+        for d in range(3):
+            a = lo[d] + (hi[d] - lo[d]) * q[d] / nb
+            b = lo[d] + (hi[d] - lo[d]) * (q[d] + 1) / nb
+            assert a - 1e-12 <= c[e, d] <= b + 1e-12
+    assert len(np.unique(te)) > 1
+
+
+def test_tet_tile_sweeps_one_tile_exact_and_vcycle_converges():
+    """On jittered tets: a tile sweep over one tile holding the whole mesh is
+    the exact solve; V-cycles with tile sweeps over the automatic tiles reach
+    the sweep answer."""
+    prob, b, A = _transport_matrix("tet", 6, 9)
+    rhs = np.linalg.solve(b.D, prob.rhs(9, None)[..., None])[..., 0].ravel()
+    exact = SW.sweep(b, prob.rhs(9, None)).ravel()
+    one = AR.TileSolver(A, np.zeros(A.shape[0], dtype=np.int64))
+    x = one.relax(A, rhs, np.zeros_like(rhs))
+    assert np.abs(x - exact).max() <= 1e-12 * np.abs(exact).max()
+    tiles = AR.tet_tiles(prob.mesh.xyz, prob.mesh.elem_vert, 2)
+    ts = AR.TileSolver(A, tiles)
+    levels = AR.setup(A, AR.Options())
+    xs, it, hist = AR.solve(levels, rhs, tol=1e-12, maxit=60, pre="T", post="T", pre_c="F", post_c="", tiles=ts)
+    assert hist[-1] <= 1e-12
+    assert np.abs(xs - exact).max() <= 1e-10 * np.abs(exact).max()
