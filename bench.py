@@ -49,7 +49,12 @@ ROOFLINE_KERNELS = {
         "T": ("k_hex_tile (finest-level tile sweeps: block Jacobi over element boxes, exact "
               "forward solve per box)", "k_hex_tile_hex64_s8_traffic.txt", "amg_solve.hip"),
         "FC": ("k_hex_relax (finest-level F/C Jacobi half-sweeps, factored hex operator)",
-               "k_hex_relax_hex64_s8_traffic.txt", "amg_solve.hip")},
+               "k_hex_relax_hex64_s8_traffic.txt", "amg_solve.hip"),
+        "T_tet": ("k_tet_tile (finest-level tile sweeps over centroid-box tet tiles, exact "
+                  "forward solve per tile by upwind levels)", "k_tet_tile_tet48_s4_traffic.txt",
+                  "amg_solve.hip"),
+        "FC_tet": ("k_ell_relax (finest-level F/C Jacobi half-sweeps, stored element blocks)",
+                   None, None)},
     "r_build": {
         "*": ("k_r_build (lAIR restriction rows with dense local systems, levels below the "
               "finest)", "k_r_build_hex64_s8_traffic.txt", "amg_setup.hip")},
@@ -94,16 +99,17 @@ def measured_traffic(traffic_file, src):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def roofline_kernel(kind, pre, post):
+def roofline_kernel(kind, pre, post, tet=False):
     """(label, traffic file, source) of a profile kind under the given schedules."""
     table = ROOFLINE_KERNELS[kind]
     if "*" in table:
         return table["*"]
     letters = set(pre + post)
+    sfx = "_tet" if tet else ""
     if letters == {"T"}:
-        return table["T"]
+        return table["T" + sfx]
     if "T" not in letters:
-        return table["FC"]
+        return table["FC" + sfx]
     return ("finest-level relaxation (tile sweeps and F/C half-sweeps mixed)", None, None)
 
 
@@ -502,6 +508,10 @@ def main():
                                                   relax_pre_coarse="F", relax_post_coarse="F",
                                                   streams=args.streams, use_graph=graph),
                                   "V(FFCF,FFCF), coarser levels V(F,F)"),
+            source_iteration_time(3, device, dict(relax_pre="TTT", relax_post="TTT",
+                                                  relax_pre_coarse="F", relax_post_coarse="F",
+                                                  streams=args.streams, use_graph=graph),
+                                  "V(TTT,TTT) over centroid-box tet tiles, coarser levels V(F,F)"),
         ]
         for r in extra["source_iteration"]:
             log("source iteration %s (%s, warm start %s): %.2f s, %d outer iterations" % (
@@ -510,7 +520,7 @@ def main():
         log("adjoint gradient: %.2f s" % extra["adjoint_c5"]["gradient_s"])
 
     relax = prof[dom]
-    label, tfile, tsrc = roofline_kernel(dom, args.relax_pre, args.relax_post)
+    label, tfile, tsrc = roofline_kernel(dom, args.relax_pre, args.relax_post, w.mesh.kind != 0)
     traffic = measured_traffic(tfile, tsrc) if tfile else None
     copy_gbs = copy_bandwidth()
     roofline = {"bound": "hbm", "achieved": relax["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -532,7 +542,7 @@ def main():
     for k in ROOFLINE_KERNELS:
         if k == dom:
             continue
-        lab, tf, ts = roofline_kernel(k, args.relax_pre, args.relax_post)
+        lab, tf, ts = roofline_kernel(k, args.relax_pre, args.relax_post, w.mesh.kind != 0)
         roofline["other_timed"][k] = {"kernel": lab, "total_ms": prof[k]["ms"], "achieved": prof[k]["gbs"],
                                       "frac": prof[k]["gbs"] / HBM_PEAK_GBS, "avg_us": prof[k]["avg_us"],
                                       "traffic": measured_traffic(tf, ts) if tf else None}

@@ -117,23 +117,28 @@ struct FineEll {
     DBuf<int32_t> inflow;          // [member] bit d set: inflow through the high face (Omega_d < 0)
     DBuf<double> sigt;             // [E] sigma_t per element
     // tile sweeps on a tet mesh (stored form): the element tiles (member-
-    // independent: tile of every element, its position in its tile, tile
-    // offsets) and, per member, every tile's elements in upwind level order:
-    // order[m*E + tile_ptr[t] + q] is the q-th element of tile t for member m,
-    // levels L = 0..Lmax at positions lvl[(m*T + t)*(Lmax + 2) + L] ..
-    // lvl[... + L + 1] (the last entry is the tile's size)
+    // independent: tile of every element, tile offsets) and, per member,
+    // every tile's elements in upwind level order: order[m*E + tile_ptr[t] + q]
+    // is the q-th element of tile t for member m, levels L = 0..Lmax at
+    // positions lvl[(m*T + t)*(Lmax + 2) + L] .. lvl[... + L + 1] (the last
+    // entry is the tile's size).  The same positions index the packed records
+    // trec (element, three neighbour source codes), tpk (face nodes) and
+    // values tval (k_tet_tile_pack); tout counts upwind faces across tiles.
     bool tet_tiles = false;
     int T = 0, Lmax = 0, tmax = 0;
-    DBuf<int32_t> tile_of, tile_loc, tile_ptr, order, lvl;
+    int64_t tout = 0;
+    DBuf<int32_t> tile_of, tile_ptr, order, lvl, trec, tpk;
+    DBuf<double> tval;
 };
 
 // Upwind level schedule of the tet tiles of a batch (FineEll of the stored
 // form with its neighbour lists): the longest upwind path of every element
-// inside its tile, then every tile's elements sorted by it.  tile_of / loc /
-// tile_ptr: device, member-independent (copied into fe).  Throws
-// PAIR_E_INVALID if some tile holds an upwind cycle.
-void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* loc, const int32_t* tile_ptr,
-                       int T, int tmax, hipStream_t s);
+// inside its tile, then every tile's elements sorted by it, and the records
+// and values packed in that order.  tile_of / tile_ptr: device, member-
+// independent (copied into fe).  Must run before the class regrouping of the
+// values.  Throws PAIR_E_INVALID if some tile holds an upwind cycle.
+void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr, int T, int tmax,
+                       hipStream_t s);
 
 struct Level {
     Csr A;                         // all members present at this level, concatenated

@@ -747,55 +747,144 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
 // forward substitution by upwind levels: level L holds the elements whose
 // longest upwind path inside the tile has L steps, independent of each other.
 // One wave per (member, tile); four lanes per element (one per row), sixteen
-// elements at a time; the tile's new values are kept in LDS for the levels
-// above, values of upwind elements outside the tile come from xin (the
+// elements at a time.  The tile's data are packed per member in level order
+// (k_tet_tile_pack), so each step reads contiguous records and values; the
+// tile's new values are kept in LDS at their level-order position for the
+// levels above, values of upwind elements outside the tile come from xin (the
 // previous iterate; none when xin_zero).
 constexpr int kTetTileMax = 1024;   // elements of a tile (LDS: 32 B each)
 
+// Source code of an upwind neighbour in a packed record: -1 none, <= -2 the
+// tile's element at level-order position -2 - code, >= 0 the batch element
+// outside the tile.
+__device__ __forceinline__ int32_t tet_src_code(int32_t u, int64_t mE, int t, int64_t tbase,
+                                                const int32_t* __restrict__ tile_of,
+                                                const int32_t* __restrict__ posof) {
+    if (u < 0) return -1;
+    if (tile_of[u - mE] != t) return u;
+    return -2 - static_cast<int32_t>(posof[u] - tbase);
+}
+
+// Packed per-(member, tile) data in level order, position k = m E + tile_ptr[t]
+// + q: rec[4k..4k+3] = element, source codes of slots 0..2; pk[k] = the three
+// slots' face nodes, 9 bits each; tval[(k*3NF + s*NF + j)*4 + r] = value of row
+// r of the element for slot s, face node j.  Values are read from the
+// assembly layout val[(s*NF + j)*nrows + row] (before any class regrouping).
+// nout counts upwind faces that lie outside their tile.
+template <int NF>
+__global__ void __launch_bounds__(256)
+k_tet_tile_pack(int64_t nel, int64_t E, int64_t nrows, const int32_t* __restrict__ order,
+                const int32_t* __restrict__ tile_of, const int32_t* __restrict__ tile_ptr,
+                const int32_t* __restrict__ posof, const int32_t* __restrict__ nbr,
+                const int32_t* __restrict__ nodes, const double* __restrict__ val,
+                int32_t* __restrict__ rec, int32_t* __restrict__ pk, double* __restrict__ tval,
+                unsigned long long* __restrict__ nout) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int outside = 0;
+    if (k < nel) {
+        const int64_t m = k / E, mE = m * E;
+        const int32_t e = order[k];
+        const int64_t g = mE + e;
+        const int t = tile_of[e];
+        const int64_t tbase = mE + tile_ptr[t];
+        int32_t code[3];
+        int32_t pks = 0;
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+            code[sl] = tet_src_code(nbr[sl * nel + g], mE, t, tbase, tile_of, posof);
+            outside += code[sl] >= 0;
+            pks |= (nodes[sl * nel + g] & ((1 << (3 * NF)) - 1)) << (3 * NF * sl);
+        }
+        reinterpret_cast<int4*>(rec)[k] = make_int4(e, code[0], code[1], code[2]);
+        pk[k] = pks;
+#pragma unroll
+        for (int q = 0; q < 3 * NF; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tval[(k * 3 * NF + q) * 4 + r] = val[q * nrows + 4 * g + r];
+    }
+    for (int d = 32; d >= 1; d >>= 1) outside += __shfl_xor(outside, d, 64);
+    if ((threadIdx.x & 63) == 0 && outside) atomicAdd(nout, static_cast<unsigned long long>(outside));
+}
+
+// level-order position of every batch element
+__global__ void k_tet_posof(int64_t nel, int64_t E, const int32_t* __restrict__ order, int32_t* __restrict__ posof) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nel) return;
+    posof[k / E * E + order[k]] = static_cast<int32_t>(k);
+}
+
 template <int NF>
 __global__ void __launch_bounds__(64)
-k_tet_tile(int T, int Lmax, int64_t E, int64_t nel, int64_t n, int64_t nF,
-           const int32_t* __restrict__ tile_ptr, const int32_t* __restrict__ loc,
-           const int32_t* __restrict__ tile_of, const int32_t* __restrict__ order,
-           const int32_t* __restrict__ lvl, const int32_t* __restrict__ nbr,
-           const int32_t* __restrict__ nodes, const double* __restrict__ val,
-           const uint64_t* __restrict__ cmask, const int64_t* __restrict__ fbase,
+k_tet_tile(int T, int Lmax, int64_t E, const int32_t* __restrict__ tile_ptr, const int32_t* __restrict__ lvl,
+           const int32_t* __restrict__ rec, const int32_t* __restrict__ pk, const double* __restrict__ tval,
            const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
            const double* __restrict__ b, const double* __restrict__ xin, double* __restrict__ xout,
            int xin_zero) {
-    extern __shared__ double xt[];          // [tile size][4]
+    extern __shared__ double xt[];          // [tile size][4], level order
     const int64_t m = blockIdx.x / T;
     const int t = static_cast<int>(blockIdx.x - m * T);
     if (!(active[m] && relax[m])) return;
-    const int64_t tb = tile_ptr[t];
+    const int64_t base = m * E + tile_ptr[t];
     const int32_t* lv = lvl + (m * T + t) * (Lmax + 2);
-    const int sub = threadIdx.x & 3, q0 = threadIdx.x >> 2;
+    const int4* rec4 = reinterpret_cast<const int4*>(rec);
+    const int sub = threadIdx.x & 3;
     const int64_t mE = m * E;
+    const int size = lv[Lmax + 1];
+    // lane group q0 takes the positions q0, q0 + 16, ... in order: a level of
+    // at most 16 elements is one step, and the group's next record is known
+    // before the level it belongs to starts
+    int p = threadIdx.x >> 2;
+    int4 rc = make_int4(0, -1, -1, -1);
+    int32_t pks = 0;
+    if (p < size) {
+        rc = rec4[base + p];
+        pks = pk[base + p];
+    }
     for (int L = 0; L <= Lmax; ++L) {
-        const int a0 = lv[L], a1 = lv[L + 1];
-        if (a0 >= a1) break;                 // levels are dense: the tile is done
-        for (int q = a0 + q0; q < a1; q += 16) {
-            const int32_t e = order[mE + tb + q];
-            const int64_t g = mE + e;
-            const int64_t row = 4 * g + sub;
-            const EllRow<NF> er(row, n, nF, cmask, fbase, val);
-            const EllNbr nb(g, nel, nbr, nodes);
+        const int a1 = lv[L + 1];
+        if (lv[L] >= a1) break;              // levels are dense: the tile is done
+        while (p < a1) {
+            const int64_t k = base + p;
+            // every global load of the step first: values, b, upwind values
+            // outside the tile (previous iterate), then the next record
+            const double* tv = tval + k * (3 * NF * 4) + sub;
+            const int64_t row = 4 * (mE + rc.x) + sub;
+            const int32_t code[3] = {rc.y, rc.z, rc.w};
+            double v[3 * NF], xo[3 * NF];
+#pragma unroll
+            for (int q = 0; q < 3 * NF; ++q) v[q] = tv[4 * q];
+            const double bv = b[row];
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+                const bool out = code[sl] >= 0 && !xin_zero;
+                const double* xu = xin + 4 * static_cast<int64_t>(out ? code[sl] : 0);
+#pragma unroll
+                for (int j = 0; j < NF; ++j)
+                    xo[sl * NF + j] = out ? xu[(pks >> (3 * NF * sl + 3 * j)) & 7] : 0.0;
+            }
+            int4 rcn = make_int4(0, -1, -1, -1);
+            int32_t pkn = 0;
+            if (p + 16 < size) {
+                rcn = rec4[k + 16];
+                pkn = pk[k + 16];
+            }
             double s = 0.0;
 #pragma unroll
             for (int sl = 0; sl < 3; ++sl) {
-                if (nb.u[sl] < 0) continue;
-                const int64_t ul = nb.u[sl] - mE;
-                const bool in = tile_of[ul] == t;
-                const double* xs = in ? xt + 4 * loc[ul] : (xin_zero ? nullptr : xin + 4 * nb.u[sl]);
+                if (code[sl] == -1) continue;
+                const double* xs = xt + 4 * (-2 - code[sl]);
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
-                    const double xu = xs ? xs[(nb.pk[sl] >> (3 * j)) & 7] : 0.0;
-                    s += er.v[(sl * NF + j) * er.stride + er.p] * xu;
+                    const double xu = code[sl] <= -2 ? xs[(pks >> (3 * NF * sl + 3 * j)) & 7] : xo[sl * NF + j];
+                    s += v[sl * NF + j] * xu;
                 }
             }
-            const double xn = b[row] - s;
+            const double xn = bv - s;
             xout[row] = xn;
-            xt[4 * loc[e] + sub] = xn;
+            xt[4 * p + sub] = xn;
+            rc = rcn;
+            pks = pkn;
+            p += 16;
         }
         __syncthreads();
     }
@@ -920,16 +1009,16 @@ double ell_residual_bytes(const Level& L, const FineEll& e) {
     return n * (24.0 * e.nf + 8.0 + 8.0 + 8.0 + 2.25) + 24.0 * static_cast<double>(e.nel);
 }
 
-// Tile sweep on tets: b read, x written, the rows' element-block values and
-// neighbour lists, the tile data and the order once, and the previous iterate's
-// face values of upwind elements outside the tile (counted as every face: an
-// upper bound; none from x = 0).
+// Tile sweep on tets: b read and x written once, the packed records (20 B per
+// element) and values (the rows' block entries, 24 NF B per row), the level
+// offsets and tile offsets, and the previous iterate's face values (NF of 4)
+// of every upwind neighbour outside its tile (none from x = 0).
 double tet_tile_relax_bytes(const Level& L, const FineEll& e, bool zero) {
     const double n = static_cast<double>(L.n_f + L.n_c);
     const double nel = static_cast<double>(e.nel);
-    double b = 16.0 * n + n * 24.0 * e.nf + 24.0 * nel + 4.0 * nel + 8.0 * static_cast<double>(e.E) +
-               4.0 * static_cast<double>(e.lvl.n);
-    if (!zero) b += 8.0 * e.nf * 3.0 * nel;
+    double b = 16.0 * n + n * 24.0 * e.nf + 20.0 * nel + 4.0 * static_cast<double>(e.lvl.n) +
+               4.0 * static_cast<double>(e.T + 1);
+    if (!zero) b += 8.0 * e.nf * static_cast<double>(e.tout);
     return b;
 }
 
@@ -1012,7 +1101,7 @@ double restrict_bytes(const Level& L, double vb = 8.0) {
 
 }  // namespace
 
-void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* loc, const int32_t* tile_ptr,
+void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr,
                        int T, int tmax, hipStream_t s) {
     PAIR_CHECK(!fe.factored && fe.k == 4 && fe.nf == 3, "tet tile schedule needs the stored tet form");
     const int64_t nel = fe.nel;          // elements of the batch
@@ -1020,10 +1109,8 @@ void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* loc, 
     PAIR_CHECK(Em > 0 && nel % Em == 0, "tet tile schedule: elements per member unknown");
     const int B = static_cast<int>(nel / Em);
     fe.tile_of.alloc(Em);
-    fe.tile_loc.alloc(Em);
     fe.tile_ptr.alloc(T + 1);
     d2d(fe.tile_of.p, tile_of, Em, s);
-    d2d(fe.tile_loc.p, loc, Em, s);
     d2d(fe.tile_ptr.p, tile_ptr, T + 1, s);
     DBuf<int> lev(nel), flag(2);
     PAIR_HIP(hipMemsetAsync(lev.p, 0, nel * sizeof(int), s));
@@ -1061,7 +1148,26 @@ void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* loc, 
     hipLaunchKernelGGL(k_tet_level_offsets, dim3(grid_for(static_cast<int64_t>(B) * T, 256)), dim3(256), 0, s,
                        B, T, Lmax, Em, fe.tile_ptr.p, off.p, fe.lvl.p);
     PAIR_LAUNCH_CHECK();
+    // level-order packing of records and values (from the assembly layout:
+    // the schedule is built before the class regrouping)
+    PAIR_CHECK(!fe.split, "tet tile schedule after the class regrouping");
+    PAIR_CHECK(nel < (int64_t(1) << 31), "tet tile schedule: too many elements");
+    DBuf<int32_t> posof(nel);
+    hipLaunchKernelGGL(k_tet_posof, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.order.p, posof.p);
+    PAIR_LAUNCH_CHECK();
+    fe.trec.alloc(4 * nel);
+    fe.tpk.alloc(nel);
+    fe.tval.alloc(static_cast<size_t>(nel) * 3 * fe.nf * 4);
+    DBuf<unsigned long long> nout(1);
+    PAIR_HIP(hipMemsetAsync(nout.p, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_tet_tile_pack<3>, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.nrows,
+                       fe.order.p, fe.tile_of.p, fe.tile_ptr.p, posof.p, fe.nbr.p, fe.nodes.p, fe.val.p,
+                       fe.trec.p, fe.tpk.p, fe.tval.p, nout.p);
+    PAIR_LAUNCH_CHECK();
+    unsigned long long no = 0;
+    d2h(&no, nout.p, 1, s);
     PAIR_HIP(hipStreamSynchronize(s));
+    fe.tout = static_cast<int64_t>(no);
     fe.tet_tiles = true;
     fe.T = T;
     fe.Lmax = Lmax;
@@ -1086,9 +1192,8 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
             PAIR_CHECK(blocks < (int64_t(1) << 31), "tile grid too large");
             int h = prof_begin(s_, kind);
             hipLaunchKernelGGL(k_tet_tile<3>, dim3(static_cast<unsigned>(blocks)), dim3(64),
-                               static_cast<size_t>(E.tmax) * 4 * sizeof(double), s_, E.T, E.Lmax, E.E, E.nel,
-                               E.nrows, E.nF, E.tile_ptr.p, E.tile_loc.p, E.tile_of.p, E.order.p, E.lvl.p,
-                               E.nbr.p, E.nodes.p, E.val.p, E.cmask.p, E.fbase.p, act, L.relax.p, L.b.p, cur,
+                               static_cast<size_t>(E.tmax) * 4 * sizeof(double), s_, E.T, E.Lmax, E.E,
+                               E.tile_ptr.p, E.lvl.p, E.trec.p, E.tpk.p, E.tval.p, act, L.relax.p, L.b.p, cur,
                                other, zero ? 1 : 0);
             prof_end(s_, h, tet_tile_relax_bytes(L, E, zero));
             PAIR_LAUNCH_CHECK();

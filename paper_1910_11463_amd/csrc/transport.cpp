@@ -142,7 +142,7 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     fine_assemble(mesh, omega_d.p, dirs_d.p, B, sigt.p, eoff.p, nnz, A.rowptr.p, A.col.p, A.val.p,
                   bt.dinv.p, fe, s);
     if (tiles && mesh.kind == PAIR_TET4)
-        tet_tile_schedule(fe, tet_tile_of.p, tet_tile_loc.p, tet_tile_ptr.p, tet_ntiles, tet_tile_max, s);
+        tet_tile_schedule(fe, tet_tile_of.p, tet_tile_ptr.p, tet_ntiles, tet_tile_max, s);
     if (t_assemble_ms) *t_assemble_ms += now_ms() - t0;
     return A;
 }
@@ -171,7 +171,7 @@ void Context::build_tet_tiles(hipStream_t st) {
         }
     const int64_t T = static_cast<int64_t>(nb) * nb * nb;
     PAIR_CHECK(T < (int64_t(1) << 30), "too many tet tiles");
-    std::vector<int32_t> tof(E), loc(E), tptr(T + 1, 0);
+    std::vector<int32_t> tof(E), tptr(T + 1, 0);
     for (int64_t e = 0; e < E; ++e) {
         int q[3];
         for (int d = 0; d < 3; ++d) {
@@ -182,7 +182,7 @@ void Context::build_tet_tiles(hipStream_t st) {
             q[d] = static_cast<int>(std::min<double>(std::max<double>(f, 0.0), nb - 1));
         }
         tof[e] = q[0] + nb * (q[1] + nb * q[2]);
-        loc[e] = tptr[tof[e] + 1]++;
+        ++tptr[tof[e] + 1];
     }
     int tmax = 0;
     for (int64_t t = 0; t < T; ++t) {
@@ -191,10 +191,8 @@ void Context::build_tet_tiles(hipStream_t st) {
     }
     PAIR_CHECK(tmax <= 1024, "a tet tile holds more than 1024 elements: raise tet_tile_boxes");
     tet_tile_of.alloc(E);
-    tet_tile_loc.alloc(E);
     tet_tile_ptr.alloc(T + 1);
     h2d(tet_tile_of.p, tof.data(), E, st);
-    h2d(tet_tile_loc.p, loc.data(), E, st);
     h2d(tet_tile_ptr.p, tptr.data(), T + 1, st);
     PAIR_HIP(hipStreamSynchronize(st));
     tet_ntiles = static_cast<int>(T);

@@ -85,7 +85,7 @@ struct Context {
     std::vector<int32_t> tet_ev_h;
     int tet_tiles_nbox = -1;            // box count the device tiles below were built for
     int tet_ntiles = 0, tet_tile_max = 0;
-    DBuf<int32_t> tet_tile_of, tet_tile_loc, tet_tile_ptr;
+    DBuf<int32_t> tet_tile_of, tet_tile_ptr;
     std::mutex tet_tiles_mu;            // worker threads may assemble batches at once
     void build_tet_tiles(hipStream_t st);
 

@@ -18,8 +18,12 @@ pytestmark = pytest.mark.gpu
 # before and after the coarse-grid correction on the finest level)
 BENCH_OPTS = dict(relax_pre="TTT", relax_post="TTT", relax_pre_coarse="F", relax_post_coarse="",
                   tile_xy=16, tile_z=0, autotune=1, streams=5, batch_size=16, filter_r=1.0)
-# the same with F/C half-sweep ladders (tets have no tile sweeps)
+# the same with F/C half-sweep ladders
 FC_OPTS = dict(BENCH_OPTS, relax_pre="FCFCFCFCFCFCF", relax_post="FCFCFCFCFCFCF")
+# tets: three tile sweeps over the default centroid-box tiles, as the
+# benchmark's tet source iteration runs them
+TET_OPTS = dict(relax_pre="TTT", relax_post="TTT", relax_pre_coarse="F", relax_post_coarse="F",
+                streams=5, batch_size=16, filter_r=1.0)
 
 
 def _reference(w, dirs):
@@ -81,10 +85,15 @@ def test_structured_64_fc_ladders():
     assert max(errs) <= 1e-9
 
 
-def test_unstructured_tets_48():
-    """48^3 x 6 jittered tets (2.65M DOF per direction), S4."""
+@pytest.mark.parametrize("sched", ["fc_plain", "tiles_batched"])
+def test_unstructured_tets_48(sched):
+    """48^3 x 6 jittered tets (2.65M DOF per direction), S4: F/C ladders one
+    direction at a time, and tile sweeps in batches of 16 on 5 streams."""
     need_gpu()
-    errs = _checked(3, B.PAIR_PLAIN, opts=FC_OPTS)
+    if sched == "fc_plain":
+        errs = _checked(3, B.PAIR_PLAIN, opts=FC_OPTS)
+    else:
+        errs = _checked(3, B.PAIR_BATCHED, opts=TET_OPTS)
     assert max(errs) <= 1e-9
 
 
