@@ -124,10 +124,15 @@ struct FineEll {
     // entry is the tile's size).  The same positions index the packed records
     // trec (element, three neighbour source codes), tpk (face nodes) and
     // values tval (k_tet_tile_pack); tout counts upwind faces across tiles.
+    // Tiles with upwind cycles (scheduled on the host): each level lists its
+    // single elements first, then its strongly connected sets from position
+    // lvls[(m*T + t)*(Lmax + 1) + L] on, each contiguous, tscc[k] = first
+    // position | size << 16 for their elements; max_set = 1: none (lvls and
+    // tscc empty).
     bool tet_tiles = false;
-    int T = 0, Lmax = 0, tmax = 0;
+    int T = 0, Lmax = 0, tmax = 0, max_set = 1;
     int64_t tout = 0;
-    DBuf<int32_t> tile_of, tile_ptr, order, lvl, trec, tpk;
+    DBuf<int32_t> tile_of, tile_ptr, order, lvl, lvls, trec, tpk, tscc;
     DBuf<double> tval;
 };
 
@@ -136,7 +141,9 @@ struct FineEll {
 // inside its tile, then every tile's elements sorted by it, and the records
 // and values packed in that order.  tile_of / tile_ptr: device, member-
 // independent (copied into fe).  Must run before the class regrouping of the
-// values.  Throws PAIR_E_INVALID if some tile holds an upwind cycle.
+// values.  Tiles with upwind cycles get their strongly connected sets solved
+// exactly (scheduled on the host); throws PAIR_E_INVALID if such a set has
+// more than 16 elements.
 void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr, int T, int tmax,
                        hipStream_t s);
 

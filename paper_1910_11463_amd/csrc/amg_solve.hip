@@ -16,6 +16,8 @@
 // finest level after each cycle with fixed-order (reproducible) reductions.
 #include <algorithm>
 #include <cmath>
+#include <thread>
+#include <vector>
 
 #include "amg.h"
 #include "kernels_common.h"
@@ -813,26 +815,110 @@ __global__ void k_tet_posof(int64_t nel, int64_t E, const int32_t* __restrict__ 
     posof[k / E * E + order[k]] = static_cast<int32_t>(k);
 }
 
+// One strongly connected set of ns <= 16 tet elements of a tile (an upwind
+// cycle; every element depends on every other through elements of the set),
+// solved exactly: the 4 ns rows of the scaled operator restricted to the set,
+// unit diagonal blocks plus the couplings inside the set, in LDS (lane r owns
+// row r), right-hand side b minus the couplings to elements outside the set
+// (this tile's lower levels from LDS, other tiles from xin), then Gauss-Jordan
+// elimination with partial pivoting across the wave.
+constexpr int kSccMax = 16;        // elements of one set (64 rows, one wave)
+constexpr int kSccLd = 65;         // LDS row stride of the dense system
+
+template <int NF>
+__device__ void tet_scc_solve(int c0, int ns, int64_t base, int64_t mE, const int4* __restrict__ rec4,
+                              const int32_t* __restrict__ pk, const double* __restrict__ tval,
+                              const double* __restrict__ b, const double* __restrict__ xin,
+                              double* __restrict__ xout, int xin_zero, double* xt, double* dm) {
+    const int r = threadIdx.x;
+    const int nr = 4 * ns;
+    const bool own = r < nr;
+    double rhs = 0.0;
+    if (own) {
+        const int pe = c0 + (r >> 2), sub = r & 3;
+        const int64_t k = base + pe;
+        const int4 rc = rec4[k];
+        const int32_t pks = pk[k];
+        const double* tv = tval + k * (3 * NF * 4) + sub;
+        for (int c = 0; c < nr; ++c) dm[r * kSccLd + c] = c == r ? 1.0 : 0.0;
+        const int32_t code[3] = {rc.y, rc.z, rc.w};
+        double s = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+            if (code[sl] == -1) continue;
+#pragma unroll
+            for (int j = 0; j < NF; ++j) {
+                const int node = (pks >> (3 * NF * sl + 3 * j)) & 7;
+                const double v = tv[4 * (sl * NF + j)];
+                if (code[sl] <= -2) {
+                    const int pos = -2 - code[sl];
+                    if (pos >= c0 && pos < c0 + ns) dm[r * kSccLd + 4 * (pos - c0) + node] += v;
+                    else s += v * xt[4 * pos + node];
+                } else {
+                    s += v * (xin_zero ? 0.0 : xin[4 * static_cast<int64_t>(code[sl]) + node]);
+                }
+            }
+        }
+        rhs = b[4 * (mE + rc.x) + sub] - s;
+    }
+    bool done = !own;
+    int col = -1;
+    for (int c = 0; c < nr; ++c) {
+        double a = done ? -1.0 : fabs(dm[r * kSccLd + c]);
+        int who = r;
+        for (int d = 32; d >= 1; d >>= 1) {        // pivot: largest |entry|, lowest lane on ties
+            const double oa = __shfl_xor(a, d, 64);
+            const int ow = __shfl_xor(who, d, 64);
+            if (oa > a || (oa == a && ow < who)) {
+                a = oa;
+                who = ow;
+            }
+        }
+        const double pv = dm[who * kSccLd + c];
+        const double prhs = __shfl(rhs, who, 64);
+        if (r == who) {
+            done = true;
+            col = c;
+        } else if (own) {
+            const double f = dm[r * kSccLd + c] / pv;
+            if (f != 0.0) {
+                for (int c2 = c + 1; c2 < nr; ++c2) dm[r * kSccLd + c2] -= f * dm[who * kSccLd + c2];
+                rhs -= f * prhs;
+            }
+        }
+    }
+    if (own) {
+        const double xv = rhs / dm[r * kSccLd + col];
+        const int pe = c0 + (col >> 2);
+        const int4 rc = rec4[base + pe];
+        xout[4 * (mE + rc.x) + (col & 3)] = xv;
+        xt[4 * pe + (col & 3)] = xv;
+    }
+}
+
 template <int NF>
 __global__ void __launch_bounds__(64)
-k_tet_tile(int T, int Lmax, int64_t E, const int32_t* __restrict__ tile_ptr, const int32_t* __restrict__ lvl,
-           const int32_t* __restrict__ rec, const int32_t* __restrict__ pk, const double* __restrict__ tval,
+k_tet_tile(int T, int Lmax, int64_t E, int tmax, const int32_t* __restrict__ tile_ptr,
+           const int32_t* __restrict__ lvl, const int32_t* __restrict__ lvls, const int32_t* __restrict__ rec,
+           const int32_t* __restrict__ pk, const int32_t* __restrict__ tscc, const double* __restrict__ tval,
            const uint8_t* __restrict__ active, const uint8_t* __restrict__ relax,
            const double* __restrict__ b, const double* __restrict__ xin, double* __restrict__ xout,
            int xin_zero) {
-    extern __shared__ double xt[];          // [tile size][4], level order
+    extern __shared__ double xt[];          // [tmax][4], level order; then the dense set system
     const int64_t m = blockIdx.x / T;
     const int t = static_cast<int>(blockIdx.x - m * T);
     if (!(active[m] && relax[m])) return;
     const int64_t base = m * E + tile_ptr[t];
     const int32_t* lv = lvl + (m * T + t) * (Lmax + 2);
+    const int32_t* ls = lvls ? lvls + (m * T + t) * (Lmax + 1) : nullptr;
     const int4* rec4 = reinterpret_cast<const int4*>(rec);
     const int sub = threadIdx.x & 3;
     const int64_t mE = m * E;
     const int size = lv[Lmax + 1];
     // lane group q0 takes the positions q0, q0 + 16, ... in order: a level of
     // at most 16 elements is one step, and the group's next record is known
-    // before the level it belongs to starts
+    // before the level it belongs to starts.  Positions [as, a1) of a level
+    // hold its strongly connected sets, solved by the whole wave.
     int p = threadIdx.x >> 2;
     int4 rc = make_int4(0, -1, -1, -1);
     int32_t pks = 0;
@@ -843,8 +929,10 @@ k_tet_tile(int T, int Lmax, int64_t E, const int32_t* __restrict__ tile_ptr, con
     for (int L = 0; L <= Lmax; ++L) {
         const int a1 = lv[L + 1];
         if (lv[L] >= a1) break;              // levels are dense: the tile is done
+        const int as = ls ? ls[L] : a1;
         while (p < a1) {
             const int64_t k = base + p;
+            const bool single = p < as;
             // every global load of the step first: values, b, upwind values
             // outside the tile (previous iterate), then the next record
             const double* tv = tval + k * (3 * NF * 4) + sub;
@@ -856,7 +944,7 @@ k_tet_tile(int T, int Lmax, int64_t E, const int32_t* __restrict__ tile_ptr, con
             const double bv = b[row];
 #pragma unroll
             for (int sl = 0; sl < 3; ++sl) {
-                const bool out = code[sl] >= 0 && !xin_zero;
+                const bool out = single && code[sl] >= 0 && !xin_zero;
                 const double* xu = xin + 4 * static_cast<int64_t>(out ? code[sl] : 0);
 #pragma unroll
                 for (int j = 0; j < NF; ++j)
@@ -868,23 +956,30 @@ k_tet_tile(int T, int Lmax, int64_t E, const int32_t* __restrict__ tile_ptr, con
                 rcn = rec4[k + 16];
                 pkn = pk[k + 16];
             }
-            double s = 0.0;
+            if (single) {
+                double s = 0.0;
 #pragma unroll
-            for (int sl = 0; sl < 3; ++sl) {
-                if (code[sl] == -1) continue;
-                const double* xs = xt + 4 * (-2 - code[sl]);
+                for (int sl = 0; sl < 3; ++sl) {
+                    if (code[sl] == -1) continue;
+                    const double* xs = xt + 4 * (-2 - code[sl]);
 #pragma unroll
-                for (int j = 0; j < NF; ++j) {
-                    const double xu = code[sl] <= -2 ? xs[(pks >> (3 * NF * sl + 3 * j)) & 7] : xo[sl * NF + j];
-                    s += v[sl * NF + j] * xu;
+                    for (int j = 0; j < NF; ++j) {
+                        const double xu = code[sl] <= -2 ? xs[(pks >> (3 * NF * sl + 3 * j)) & 7] : xo[sl * NF + j];
+                        s += v[sl * NF + j] * xu;
+                    }
                 }
+                const double xn = bv - s;
+                xout[row] = xn;
+                xt[4 * p + sub] = xn;
             }
-            const double xn = bv - s;
-            xout[row] = xn;
-            xt[4 * p + sub] = xn;
             rc = rcn;
             pks = pkn;
             p += 16;
+        }
+        for (int c0 = as; c0 < a1;) {          // the level's strongly connected sets
+            const int ns = tscc[base + c0] >> 16;
+            tet_scc_solve<NF>(c0, ns, base, mE, rec4, pk, tval, b, xin, xout, xin_zero, xt, xt + 4 * tmax);
+            c0 += ns;
         }
         __syncthreads();
     }
@@ -1099,7 +1194,221 @@ double restrict_bytes(const Level& L, double vb = 8.0) {
            2.0 * nc;
 }
 
+// Schedule of tiles with upwind cycles, on the host: per member and tile,
+// the strongly connected components of the upwind graph restricted to the
+// tile (Tarjan's algorithm, iterative; a component is completed after every
+// component it depends on, so completion order is an upwind order), levels
+// of the condensed graph (longest upwind path), and the positions: per level
+// its single elements, then its components, each contiguous.  Outputs per
+// batch position k = m E + tile_ptr[t] + q: order (element), scc (first
+// position | size << 16 for elements of components, else 0); per (member,
+// tile) level starts lvl [Lmax + 2] (the last entry the tile's size) and
+// component starts lvls [Lmax + 1].
+struct CyclicSchedule {
+    std::vector<int32_t> order, scc, lvl, lvls;
+    int Lmax = 0, max_set = 1;
+};
+
+CyclicSchedule tet_schedule_cyclic(const std::vector<int32_t>& nbr, int64_t nel, int64_t Em, int B, int T,
+                                   const std::vector<int32_t>& tile_of, const std::vector<int32_t>& tile_ptr) {
+    // member-independent: the elements of every tile and each element's index in it
+    std::vector<int32_t> elems(Em), loc(Em), fill(tile_ptr.begin(), tile_ptr.end() - 1);
+    for (int64_t e = 0; e < Em; ++e) {
+        const int t = tile_of[e];
+        loc[e] = fill[t] - tile_ptr[t];
+        elems[fill[t]++] = static_cast<int32_t>(e);
+    }
+    struct Out {
+        std::vector<int32_t> pos_elem, pos_scc, lstart, sstart;
+    };
+    const int64_t work = static_cast<int64_t>(B) * T;
+    std::vector<Out> out(work);
+    std::vector<int> err(work, 0);
+    auto run = [&](int64_t w) {
+        const int64_t m = w / T, mE = m * Em;
+        const int t = static_cast<int>(w - m * T);
+        const int n = tile_ptr[t + 1] - tile_ptr[t];
+        const int32_t* te = elems.data() + tile_ptr[t];
+        auto dep = [&](int i, int sl) -> int {   // in-tile upwind neighbour of node i through slot sl, or -1
+            const int32_t u = nbr[static_cast<int64_t>(sl) * nel + mE + te[i]];
+            if (u < 0 || tile_of[u - mE] != t) return -1;
+            return loc[u - mE];
+        };
+        // Tarjan, iterative: frames (node, next slot)
+        std::vector<int> index(n, -1), low(n, 0), comp(n, -1), stack, csize;
+        std::vector<char> on(n, 0);
+        std::vector<std::pair<int, int>> frames;
+        int counter = 0, ncomp = 0;
+        for (int r = 0; r < n; ++r) {
+            if (index[r] >= 0) continue;
+            frames.push_back({r, 0});
+            index[r] = low[r] = counter++;
+            stack.push_back(r);
+            on[r] = 1;
+            while (!frames.empty()) {
+                auto& f = frames.back();
+                const int v = f.first;
+                if (f.second < 3) {
+                    const int u = dep(v, f.second++);
+                    if (u < 0) continue;
+                    if (index[u] < 0) {
+                        index[u] = low[u] = counter++;
+                        stack.push_back(u);
+                        on[u] = 1;
+                        frames.push_back({u, 0});
+                    } else if (on[u]) {
+                        low[v] = std::min(low[v], index[u]);
+                    }
+                    continue;
+                }
+                if (low[v] == index[v]) {
+                    int sz = 0, x;
+                    do {
+                        x = stack.back();
+                        stack.pop_back();
+                        on[x] = 0;
+                        comp[x] = ncomp;
+                        ++sz;
+                    } while (x != v);
+                    csize.push_back(sz);
+                    ++ncomp;
+                }
+                frames.pop_back();
+                if (!frames.empty()) {
+                    const int pv = frames.back().first;
+                    low[pv] = std::min(low[pv], low[v]);
+                }
+            }
+        }
+        // component levels in completion order (every upwind component first)
+        std::vector<int> clev(ncomp, 0);
+        std::vector<std::vector<int>> members(ncomp);
+        for (int i = 0; i < n; ++i) members[comp[i]].push_back(i);
+        int Lt = 0;
+        for (int c = 0; c < ncomp; ++c) {
+            if (csize[c] > kSccMax) err[w] = 1;
+            int L = 0;
+            for (int i : members[c])
+                for (int sl = 0; sl < 3; ++sl) {
+                    const int u = dep(i, sl);
+                    if (u >= 0 && comp[u] != c) L = std::max(L, clev[comp[u]] + 1);
+                }
+            clev[c] = L;
+            Lt = std::max(Lt, L);
+        }
+        Out& o = out[w];
+        o.lstart.assign(Lt + 2, 0);
+        o.sstart.assign(Lt + 1, 0);
+        o.pos_elem.reserve(n);
+        o.pos_scc.reserve(n);
+        std::vector<std::vector<int>> single(Lt + 1), sets(Lt + 1);
+        for (int c = 0; c < ncomp; ++c) (csize[c] == 1 ? single : sets)[clev[c]].push_back(c);
+        for (int L = 0; L <= Lt; ++L) {
+            o.lstart[L] = static_cast<int32_t>(o.pos_elem.size());
+            for (int c : single[L]) {
+                o.pos_elem.push_back(te[members[c][0]]);
+                o.pos_scc.push_back(0);
+            }
+            o.sstart[L] = static_cast<int32_t>(o.pos_elem.size());
+            for (int c : sets[L]) {
+                const int first = static_cast<int>(o.pos_elem.size());
+                for (int i : members[c]) {
+                    o.pos_elem.push_back(te[i]);
+                    o.pos_scc.push_back(first | (csize[c] << 16));
+                }
+            }
+        }
+        o.lstart[Lt + 1] = n;
+    };
+    const int nth = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(
+        {16, static_cast<int64_t>(std::thread::hardware_concurrency()), work})));
+    std::vector<std::thread> th;
+    for (int i = 0; i < nth; ++i)
+        th.emplace_back([&, i] {
+            for (int64_t w = i; w < work; w += nth) run(w);
+        });
+    for (auto& x : th) x.join();
+    for (int64_t w = 0; w < work; ++w)
+        PAIR_CHECK(!err[w], "tile sweeps: an upwind cycle of more than 16 elements inside a tet tile "
+                            "(the exact tile solve holds at most 16 elements of a cycle; use smaller tiles)");
+    CyclicSchedule cs;
+    for (const Out& o : out) cs.Lmax = std::max(cs.Lmax, static_cast<int>(o.sstart.size()) - 1);
+    const int Lmax = cs.Lmax;
+    cs.order.assign(nel, 0);
+    cs.scc.assign(nel, 0);
+    cs.lvl.assign(static_cast<size_t>(work) * (Lmax + 2), 0);
+    cs.lvls.assign(static_cast<size_t>(work) * (Lmax + 1), 0);
+    for (int64_t w = 0; w < work; ++w) {
+        const int64_t m = w / T;
+        const int t = static_cast<int>(w - m * T);
+        const Out& o = out[w];
+        const int n = tile_ptr[t + 1] - tile_ptr[t];
+        const int Lt = static_cast<int>(o.sstart.size()) - 1;
+        const int64_t k0 = m * Em + tile_ptr[t];
+        for (int q = 0; q < n; ++q) {
+            cs.order[k0 + q] = o.pos_elem[q];
+            cs.scc[k0 + q] = o.pos_scc[q];
+            if (o.pos_scc[q]) cs.max_set = std::max(cs.max_set, o.pos_scc[q] >> 16);
+        }
+        for (int L = 0; L <= Lmax + 1; ++L) cs.lvl[w * (Lmax + 2) + L] = L <= Lt ? o.lstart[L] : n;
+        for (int L = 0; L <= Lmax; ++L) cs.lvls[w * (Lmax + 1) + L] = L <= Lt ? o.sstart[L] : n;
+    }
+    return cs;
+}
+
 }  // namespace
+
+// Level-order packing of records and values for the tile kernel (from the
+// assembly layout of the values: the schedule is built before the class
+// regrouping); needs fe.order and fe.tile_of / tile_ptr.
+static void tet_tile_pack(FineEll& fe, hipStream_t s) {
+    const int64_t nel = fe.nel, Em = fe.E;
+    PAIR_CHECK(!fe.split, "tet tile schedule after the class regrouping");
+    PAIR_CHECK(nel < (int64_t(1) << 31), "tet tile schedule: too many elements");
+    DBuf<int32_t> posof(nel);
+    hipLaunchKernelGGL(k_tet_posof, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.order.p, posof.p);
+    PAIR_LAUNCH_CHECK();
+    fe.trec.alloc(4 * nel);
+    fe.tpk.alloc(nel);
+    fe.tval.alloc(static_cast<size_t>(nel) * 3 * fe.nf * 4);
+    DBuf<unsigned long long> nout(1);
+    PAIR_HIP(hipMemsetAsync(nout.p, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_tet_tile_pack<3>, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.nrows,
+                       fe.order.p, fe.tile_of.p, fe.tile_ptr.p, posof.p, fe.nbr.p, fe.nodes.p, fe.val.p,
+                       fe.trec.p, fe.tpk.p, fe.tval.p, nout.p);
+    PAIR_LAUNCH_CHECK();
+    unsigned long long no = 0;
+    d2h(&no, nout.p, 1, s);
+    PAIR_HIP(hipStreamSynchronize(s));
+    fe.tout = static_cast<int64_t>(no);
+}
+
+static void tet_tile_schedule_cyclic(FineEll& fe, int T, int tmax, hipStream_t s) {
+    const int64_t nel = fe.nel, Em = fe.E;
+    const int B = static_cast<int>(nel / Em);
+    std::vector<int32_t> nbr(3 * nel), tof(Em), tptr(T + 1);
+    d2h(nbr.data(), fe.nbr.p, 3 * nel, s);
+    d2h(tof.data(), fe.tile_of.p, Em, s);
+    d2h(tptr.data(), fe.tile_ptr.p, T + 1, s);
+    PAIR_HIP(hipStreamSynchronize(s));
+    CyclicSchedule cs = tet_schedule_cyclic(nbr, nel, Em, B, T, tof, tptr);
+    PAIR_CHECK(cs.max_set == 1 || (static_cast<size_t>(tmax) * 4 + 64 * kSccLd) * sizeof(double) <= 65536,
+               "tile sweeps with upwind cycles: a tet tile may hold at most 1008 elements (LDS)");
+    fe.order.alloc(nel);
+    fe.tscc.alloc(nel);
+    fe.lvl.alloc(cs.lvl.size());
+    fe.lvls.alloc(cs.lvls.size());
+    h2d(fe.order.p, cs.order.data(), nel, s);
+    h2d(fe.tscc.p, cs.scc.data(), nel, s);
+    h2d(fe.lvl.p, cs.lvl.data(), cs.lvl.size(), s);
+    h2d(fe.lvls.p, cs.lvls.data(), cs.lvls.size(), s);
+    tet_tile_pack(fe, s);                 // synchronises the stream: the host vectors may go
+    fe.tet_tiles = true;
+    fe.T = T;
+    fe.Lmax = cs.Lmax;
+    fe.tmax = tmax;
+    fe.max_set = cs.max_set;
+}
 
 void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr,
                        int T, int tmax, hipStream_t s) {
@@ -1116,8 +1425,13 @@ void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_
     PAIR_HIP(hipMemsetAsync(lev.p, 0, nel * sizeof(int), s));
     int changed = 1, it = 0;
     while (changed) {
-        PAIR_CHECK(++it <= tmax + 1, "tile sweeps: an upwind cycle inside a tet tile (the exact tile "
-                                     "solve needs an acyclic upwind order inside each tile)");
+        if (++it > tmax + 1) {
+            // an acyclic tile settles within (its size) passes: some tile holds
+            // an upwind cycle, so the schedule is built on the host with its
+            // strongly connected sets
+            tet_tile_schedule_cyclic(fe, T, tmax, s);
+            return;
+        }
         PAIR_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
         hipLaunchKernelGGL(k_tet_levels, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.nbr.p,
                            fe.tile_of.p, lev.p, flag.p);
@@ -1148,30 +1462,14 @@ void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_
     hipLaunchKernelGGL(k_tet_level_offsets, dim3(grid_for(static_cast<int64_t>(B) * T, 256)), dim3(256), 0, s,
                        B, T, Lmax, Em, fe.tile_ptr.p, off.p, fe.lvl.p);
     PAIR_LAUNCH_CHECK();
-    // level-order packing of records and values (from the assembly layout:
-    // the schedule is built before the class regrouping)
-    PAIR_CHECK(!fe.split, "tet tile schedule after the class regrouping");
-    PAIR_CHECK(nel < (int64_t(1) << 31), "tet tile schedule: too many elements");
-    DBuf<int32_t> posof(nel);
-    hipLaunchKernelGGL(k_tet_posof, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.order.p, posof.p);
-    PAIR_LAUNCH_CHECK();
-    fe.trec.alloc(4 * nel);
-    fe.tpk.alloc(nel);
-    fe.tval.alloc(static_cast<size_t>(nel) * 3 * fe.nf * 4);
-    DBuf<unsigned long long> nout(1);
-    PAIR_HIP(hipMemsetAsync(nout.p, 0, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(k_tet_tile_pack<3>, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.nrows,
-                       fe.order.p, fe.tile_of.p, fe.tile_ptr.p, posof.p, fe.nbr.p, fe.nodes.p, fe.val.p,
-                       fe.trec.p, fe.tpk.p, fe.tval.p, nout.p);
-    PAIR_LAUNCH_CHECK();
-    unsigned long long no = 0;
-    d2h(&no, nout.p, 1, s);
-    PAIR_HIP(hipStreamSynchronize(s));
-    fe.tout = static_cast<int64_t>(no);
+    tet_tile_pack(fe, s);
     fe.tet_tiles = true;
     fe.T = T;
     fe.Lmax = Lmax;
     fe.tmax = tmax;
+    fe.max_set = 1;
+    fe.lvls.reset();
+    fe.tscc.reset();
 }
 
 
@@ -1191,10 +1489,10 @@ double* Hierarchy::sweeps(Level& L, int l, const std::string& sched, double* cur
             const int64_t blocks = members * E.T;
             PAIR_CHECK(blocks < (int64_t(1) << 31), "tile grid too large");
             int h = prof_begin(s_, kind);
-            hipLaunchKernelGGL(k_tet_tile<3>, dim3(static_cast<unsigned>(blocks)), dim3(64),
-                               static_cast<size_t>(E.tmax) * 4 * sizeof(double), s_, E.T, E.Lmax, E.E,
-                               E.tile_ptr.p, E.lvl.p, E.trec.p, E.tpk.p, E.tval.p, act, L.relax.p, L.b.p, cur,
-                               other, zero ? 1 : 0);
+            const size_t lds = (static_cast<size_t>(E.tmax) * 4 + (E.max_set > 1 ? 64 * kSccLd : 0)) * sizeof(double);
+            hipLaunchKernelGGL(k_tet_tile<3>, dim3(static_cast<unsigned>(blocks)), dim3(64), lds, s_, E.T,
+                               E.Lmax, E.E, E.tmax, E.tile_ptr.p, E.lvl.p, E.lvls.p, E.trec.p, E.tpk.p,
+                               E.tscc.p, E.tval.p, act, L.relax.p, L.b.p, cur, other, zero ? 1 : 0);
             prof_end(s_, h, tet_tile_relax_bytes(L, E, zero));
             PAIR_LAUNCH_CHECK();
             std::swap(cur, other);

@@ -180,8 +180,8 @@ def test_tile_streams_bitwise():
         assert np.array_equal(x, y)
 
 
-def _tets(n, seed):
-    mesh = wl.kuhn_tet_mesh(n, jitter=0.2, seed=seed)
+def _tets(n, seed, jitter=0.2):
+    mesh = wl.kuhn_tet_mesh(n, jitter=jitter, seed=seed)
     E = mesh.n_elem
     st = wl.log_uniform(E, 0.1, 10.0, seed=seed + 1)
     return wl.Workload("tet%d^3x6-S4" % n, mesh, wl.Materials(st, 0.5 * st, np.ones(E)), 4)
@@ -270,3 +270,93 @@ def test_tet_tile_batched_equals_plain_and_streams_bitwise():
         s.close()
     for k in (1, 2):
         assert np.array_equal(out[0][0], out[k][0]) and np.array_equal(out[0][1], out[k][1])
+
+
+# Strongly jittered tets whose upwind graphs have cycles inside the tiles
+# (strongly connected sets of up to 5-7 elements in every S4 direction, found
+# with the oracle's topology): the tile solve condenses them and solves each
+# set densely.
+@pytest.mark.parametrize("nbox", [2, 1])
+def test_tet_tiles_with_upwind_cycles_match_oracle(nbox):
+    """Two two-level V-cycles with TT/TT on a mesh with in-tile cycles against
+    the oracle's TileSolver (sparse LU of the tile-diagonal part) on the
+    exported operator; one tile: a single T sweep is the oracle's exact sweep
+    (dense solves of the cycles)."""
+    need_gpu()
+    from oracle import air_ref as ar, source_iteration as si
+    # 2 x 2 x 2 tiles: sets of up to 7 elements; one tile: up to 5
+    w = _tets(5, seed=50, jitter=0.42) if nbox == 2 else _tets(5, seed=44, jitter=0.4)
+    _print("tet tiles with cycles, boxes", nbox)
+    if nbox == 2:
+        s = solver_for(w, fixed_cycles=2, filter_r=1.0, batch_size=12, max_levels=2, relax_pre="TT",
+                       relax_post="TT", relax_pre_coarse="F", relax_post_coarse="", tet_tile_boxes=nbox)
+        psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_BATCHED)
+        assert rc == B.PAIR_OK
+        tiles = ar.tet_tiles(w.mesh.xyz, w.mesh.elem_vert, nbox)
+        for m in (0, 9, 17):
+            rp, col, val, b = s.export_fine_operator(m)
+            A = sp.csr_matrix((val, col, rp), shape=(b.shape[0], b.shape[0]))
+            levels = ar.setup(A, ar.Options(filter_r=1.0, max_levels=2))
+            ts = ar.TileSolver(A, tiles)
+            x = np.zeros_like(b)
+            for _ in range(2):
+                x = ar.vcycle(levels, b, x, pre="TT", post="TT", pre_c="F", post_c="", tiles=ts)
+            _print("  direction", m, "rel diff %.2e" % rel(psi[m], x))
+            assert rel(psi[m], x) <= 1e-12, m
+    else:
+        s = solver_for(w, fixed_cycles=1, filter_r=1.0, batch_size=12, relax_pre="T", relax_post="",
+                       relax_pre_coarse="F", relax_post_coarse="", tet_tile_boxes=1)
+        psi, phi, st, rc = s.transport_sweep(mode=B.PAIR_BATCHED)
+        assert rc == B.PAIR_OK
+        ref = si.transport_sweep(oracle_problem(w), None)
+        for m in range(len(ref)):
+            assert rel(psi[m], ref[m]) <= 1e-11, (m, rel(psi[m], ref[m]))
+    s.close()
+
+
+def test_tet_tiles_with_upwind_cycles_converge_and_agree_bitwise():
+    """5^3 x 6 tets, jitter 0.42, 2 x 2 x 2 tiles (cycles of up to 7 elements
+    inside the tiles): full hierarchies with TT/TT reach the oracle's exact
+    sweep, and plain, batched and three-stream solves agree bitwise.  On so
+    distorted a mesh the AIR hierarchy diverges for some directions (in the
+    oracle too, with tile or F/C relaxation alike); the six S4 directions used
+    here converge in the oracle in 14-28 V-cycles."""
+    need_gpu()
+    from paper_1910_11463_amd.solver import Solver
+    from oracle import quadrature as Q, source_iteration as si
+    w = _tets(5, seed=50, jitter=0.42)
+    om, wt = Q.level_symmetric(4)
+    dirs = [1, 4, 14, 18, 19, 20]
+    om, wt = om[dirs], wt[dirs] * (4 * np.pi / wt[dirs].sum())    # a quadrature of its own
+    opts = dict(relax_pre="TT", relax_post="TT", relax_pre_coarse="F", relax_post_coarse="", filter_r=1.0,
+                tol_inner=1e-12, max_inner=200, tet_tile_boxes=2)
+    out = []
+    for mode, bs, streams in ((B.PAIR_BATCHED, 4, 1), (B.PAIR_PLAIN, 0, 1), (B.PAIR_BATCHED, 4, 3)):
+        _print("cyclic tets, mode", mode, "streams", streams)
+        s = Solver(batch_size=bs, streams=streams, **opts)
+        s.set_mesh(w.mesh)
+        s.set_quadrature(om, wt)
+        s.set_materials(w.mats.sigma_t, w.mats.sigma_s, w.mats.q)
+        psi, phi, st, rc = s.transport_sweep(mode=mode)
+        assert rc == B.PAIR_OK
+        out.append((psi, phi))
+        s.close()
+    m = w.mats
+    ref = si.transport_sweep(si.Problem(w.mesh, m.sigma_t, m.sigma_s, m.q, om, wt), None)
+    for k in range(len(dirs)):
+        assert rel(out[0][0][k], ref[k]) <= 1e-9, (k, rel(out[0][0][k], ref[k]))
+    for k in (1, 2):
+        assert np.array_equal(out[0][0], out[k][0]) and np.array_equal(out[0][1], out[k][1])
+
+
+def test_tet_tile_cycle_over_16_elements_is_rejected():
+    """An in-tile cycle of 23 elements (jitter 0.48, one tile) exceeds the dense
+    set solve: an error naming the limit, not a wrong answer."""
+    need_gpu()
+    w = _tets(5, seed=48, jitter=0.48)
+    s = solver_for(w, relax_pre="T", relax_post="T", relax_pre_coarse="F", relax_post_coarse="",
+                   tet_tile_boxes=1)
+    with pytest.raises(B.PairError) as e:
+        s.transport_sweep(mode=B.PAIR_BATCHED)
+    assert "more than 16 elements" in str(e.value)
+    s.close()

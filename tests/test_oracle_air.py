@@ -431,3 +431,41 @@ def test_tet_tile_sweeps_one_tile_exact_and_vcycle_converges():
     xs, it, hist = AR.solve(levels, rhs, tol=1e-12, maxit=60, pre="T", post="T", pre_c="F", post_c="", tiles=ts)
     assert hist[-1] <= 1e-12
     assert np.abs(xs - exact).max() <= 1e-10 * np.abs(exact).max()
+
+
+def test_tet_tile_solver_exact_on_a_mesh_with_upwind_cycles():
+    """A strongly jittered tet mesh whose upwind graph has cycles inside the
+    tiles (checked: the exact sweep reports multi-element cycles, and the
+    tile-restricted graph has strongly connected sets): one tile over the mesh
+    is the exact solve (the sweep's dense solves of the cycles), and V-cycles
+    with TT over 2 x 2 x 2 tiles reach it."""
+    from scipy.sparse.csgraph import connected_components
+    from oracle import sweep as SWP
+    mesh = wl.kuhn_tet_mesh(5, jitter=0.42, seed=50)
+    E = mesh.n_elem
+    st = np.random.default_rng(3).uniform(0.1, 3.0, E)
+    om, w = Q.level_symmetric(4)
+    prob = si.Problem(mesh, st, 0.5 * st, np.ones(E), om, w)
+    m = 7
+    b = prob.blocks(m)
+    A = dg.scaled_csr(prob.topo, b)
+    rhs_blocks = prob.rhs(m, None)
+    exact, ncyc = SWP.sweep_raw(b.D, b.nbr, b.Cpl, rhs_blocks)
+    assert ncyc > 0
+    exact = exact.ravel()
+    rhs = np.linalg.solve(b.D, rhs_blocks[..., None])[..., 0].ravel()
+    tiles = AR.tet_tiles(mesh.xyz, mesh.elem_vert, 2)
+    C = A.tocoo()
+    keep = (tiles[C.row] == tiles[C.col]) & (C.row // 4 != C.col // 4)
+    G = sp.csr_matrix((np.ones(keep.sum()), (C.row[keep] // 4, C.col[keep] // 4)), shape=(E, E))
+    _, lab = connected_components(G, directed=True, connection="strong")
+    assert np.bincount(lab).max() > 1           # G has in-tile edges only
+    one = AR.TileSolver(A, np.zeros(A.shape[0], dtype=np.int64))
+    x = one.relax(A, rhs, np.zeros_like(rhs))
+    assert np.abs(x - exact).max() <= 1e-11 * np.abs(exact).max()
+    ts = AR.TileSolver(A, tiles)
+    levels = AR.setup(A, AR.Options())
+    xs, it, hist = AR.solve(levels, rhs, tol=1e-12, maxit=300, pre="TT", post="TT", pre_c="F", post_c="",
+                            tiles=ts)
+    assert hist[-1] <= 1e-12
+    assert np.abs(xs - exact).max() <= 1e-9 * np.abs(exact).max()
