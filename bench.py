@@ -160,7 +160,7 @@ def profile_kinds():
     import ctypes
     from paper_1910_11463_amd import binding as B
     names = ["relax_fine", "residual_fine", "restrict_fine", "relax_coarse", "norm_fine", "r_build",
-             "r_build_once"]
+             "r_build_once", "r_pattern"]
     out = {}
     for k, nm in enumerate(names):
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()

@@ -328,7 +328,9 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
  * test residual norm, 5 = setup: restriction rows with dense local systems
  * (lAIR on the levels below the finest), 6 = the same launches with each
  * gathered row of A counted once per launch (kind 5 counts it once per local
- * system that reads it).  Outputs: number of timed launches,
+ * system that reads it), 7 = setup: the patterns of those restriction rows
+ * (their strong F points, truncated to kmax), selected before kind 5's launches
+ * solve their local systems.  Outputs: number of timed launches,
  * their summed duration (ms) and summed algorithmic bytes (what each launch
  * must read and write: 8 B per value, 4 B per column index, 8 B per row
  * offset; a gathered vector counted once per launch; for kind 5, counted on

@@ -472,6 +472,62 @@ k_r_count(int64_t nc, const int32_t* __restrict__ c2f, const int64_t* __restrict
     if (sub == 0) rcnt[I] = (c < kmax ? c : kmax) + 1;
 }
 
+// The pattern of every lAIR row (the strong F points of row i of A, at most
+// kmax of them: the largest |a_ij|, ties to the smaller column; the selection
+// of r_collect), with i itself, in column order, into row I of R (whose
+// offsets k_r_count's sizes gave), for k_r_build<G, true>.  G lanes per row,
+// no LDS: the dependent gathers (c2f, the row of A, cf of its columns) run at
+// full occupancy instead of inside the LDS-bound local-system kernel.
+template <int G>
+__global__ void __launch_bounds__(256)
+k_r_pattern(int64_t nc, const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
+            const int32_t* __restrict__ col, const double* __restrict__ val, const uint8_t* __restrict__ sflag,
+            const int8_t* __restrict__ cf, int kmax, const int64_t* __restrict__ r_rowptr,
+            int32_t* __restrict__ r_col) {
+    const int64_t I = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const int sub = threadIdx.x & (G - 1);
+    const int lane = threadIdx.x & 63;
+    const uint64_t gmask = ((G == 64) ? ~0ull : ((1ull << G) - 1ull)) << (lane & ~(G - 1));
+    if (I >= nc) return;   // uniform within the group
+    const int64_t i = c2f[I];
+    const int64_t rs = rowptr[i], re = rowptr[i + 1];
+    const int64_t rb = r_rowptr[I];
+    const int K = static_cast<int>(r_rowptr[I + 1] - rb) - 1;
+    int cnt = K;             // K < kmax: every candidate is kept
+    if (K >= kmax) {
+        cnt = 0;
+        for (int64_t e = rs + sub; e < re; e += G)
+            if (r_candidate(i, col[e], sflag[e], cf)) ++cnt;
+        cnt = group_sum_int<G>(cnt);
+    }
+    int filled = 0, before = 0;
+    for (int64_t e0 = rs; e0 < re; e0 += G) {
+        const int64_t e = e0 + sub;
+        bool keep = false;
+        int32_t cj = -1;
+        if (e < re) {
+            cj = col[e];
+            keep = r_candidate(i, cj, sflag[e], cf);
+            if (keep && cnt > kmax) {
+                const double a = fabs(val[e]);
+                int rank = 0;
+                for (int64_t q = rs; q < re; ++q) {
+                    if (q == e || !r_candidate(i, col[q], sflag[q], cf)) continue;
+                    const double bq = fabs(val[q]);
+                    if (bq > a || (bq == a && col[q] < cj)) ++rank;
+                }
+                keep = rank < kmax;
+            }
+        }
+        const uint64_t m = __ballot(keep) & gmask;
+        const uint64_t lt = __ballot(keep && cj < i) & gmask;
+        if (keep) r_col[rb + filled + __popcll(m & ((1ull << lane) - 1ull)) + (cj > i ? 1 : 0)] = cj;
+        filled += __popcll(m);
+        before += __popcll(lt);
+    }
+    if (sub == 0) r_col[rb + before] = static_cast<int32_t>(i);
+}
+
 constexpr int KCAP = 64;      // largest local system (one wave: lane = row)
 
 // The F points of the local system of C point i (strong R-candidates of row i,
@@ -602,7 +658,9 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         __syncthreads();
         // Mloc[r][c] = A(cols[c], cols[r]); rhs[r] = -A(i, cols[r]).  The
         // entries of all K rows are spread over the lanes as one flat list, four
-        // per lane at a time with all their loads issued before any is used.
+        // per lane at a time with all their loads issued before any is used
+        // (sixteen at a time: 138 instead of 82 VGPRs, one wave less per SIMD,
+        // slower).
         constexpr int U = 4;
         for (int q0 = sub; q0 < tot; q0 += U * G) {
             int cq[U];
@@ -696,12 +754,14 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         if (pbytes) {
             // algorithmic bytes of the row: list and c2f entries, its row offsets
             // in A and R, its row of A (column, value, strength flag, cf of the
-            // column), the offsets and entries of the K rows its local system
+            // column; with the pattern given: column and value, and the pattern
+            // read), the offsets and entries of the K rows its local system
             // reads, and its row of R written
             unsigned long long rb = 0;
             if (have && sub == 0)
-                rb = 40ull + 14ull * static_cast<unsigned long long>(re - rs) + 16ull * K +
-                     12ull * static_cast<unsigned long long>(tot) + 12ull * (K + 1);
+                rb = 40ull + (GIVEN ? 12ull : 14ull) * static_cast<unsigned long long>(re - rs) +
+                     (GIVEN ? 4ull * (K + 1) : 0ull) + 16ull * K + 12ull * static_cast<unsigned long long>(tot) +
+                     12ull * (K + 1);
             for (int d = 32; d >= 1; d >>= 1) rb += __shfl_xor(rb, d, 64);
             if (lane == 0 && rb) atomicAdd(pbytes + (blockIdx.x % kProfSubSlots), rb);
         }
@@ -714,21 +774,23 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 // gathered row of A counted once per launch (however many local systems read
 // it).  Per C row of `list`: the list and c2f entries and its row offsets in A
 // and R (40 B), its row of A (column, value, strength flag, cf of the column:
-// 14 B per entry) and its row of R written (12 B per entry); per distinct row
+// 14 B per entry; with the pattern given, column and value and 4 B per
+// pattern entry read) and its row of R written (12 B per entry); per distinct row
 // j of A read by the launch's local systems (first setter of its bit in
 // `seen`): its offsets (16 B) and entries (12 B each).
 __global__ void k_r_gather_once(int nrows, const int32_t* __restrict__ list,
                                 const int32_t* __restrict__ c2f, const int64_t* __restrict__ rowptr,
                                 const int64_t* __restrict__ r_rowptr, const int32_t* __restrict__ r_col,
-                                unsigned* __restrict__ seen, unsigned long long* __restrict__ pbytes) {
+                                unsigned* __restrict__ seen, unsigned long long* __restrict__ pbytes,
+                                int given) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long b = 0;
     if (t < nrows) {
         const int64_t I = list[t];
         const int64_t i = c2f[I];
         const int64_t rb = r_rowptr[I], re = r_rowptr[I + 1];
-        b = 40ull + 14ull * static_cast<unsigned long long>(rowptr[i + 1] - rowptr[i]) +
-            12ull * static_cast<unsigned long long>(re - rb);
+        b = 40ull + (given ? 12ull : 14ull) * static_cast<unsigned long long>(rowptr[i + 1] - rowptr[i]) +
+            (given ? 16ull : 12ull) * static_cast<unsigned long long>(re - rb);
         for (int64_t q = rb; q < re; ++q) {
             const int32_t j = r_col[q];
             if (j == i) continue;
@@ -2525,7 +2587,23 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             PAIR_LAUNCH_CHECK();
             PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
         } else {
-            // local systems by size K: <= 8, <= 16, <= 32, <= 64 (64 / G rows per wave)
+            // the patterns into R first (full occupancy: the gathers that select
+            // them), then the local systems by size K: <= 8, <= 16, <= 32, <= 64
+            // (64 / G rows per wave), each reading its pattern from R
+            {
+                const int ph = prof_begin(s_, PROF_RPATTERN);
+                hipLaunchKernelGGL(k_r_pattern<kRowG>, dim3(grid_for(total_c * kRowG, 256)), dim3(256), 0, s_,
+                                   total_c, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax,
+                                   L.R.rowptr.p, L.R.col.p);
+                // the row's offsets, c2f entry and row of A (column, strength
+                // flag, cf of the column, at the level's mean row length;
+                // values only to rank truncated rows, not counted), the row
+                // offsets of R, the pattern written
+                prof_end(s_, ph, 28.0 * static_cast<double>(total_c) + 4.0 * static_cast<double>(L.R.nnz) +
+                                     6.0 * static_cast<double>(total_c) *
+                                         (static_cast<double>(L.A.nnz) / static_cast<double>(std::max<int64_t>(1, n))));
+                PAIR_LAUNCH_CHECK();
+            }
             DBuf<int32_t> rl[4];
             int nrc[4];
             DBuf<int> rsing(1);
@@ -2541,10 +2619,10 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                 unsigned long long* pb = prof_dev_bytes(ph);
 #define PAIR_RB_ARGS nr, rl[c].p, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, \
                      L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p, pb
-                if (c == 0) hipLaunchKernelGGL(k_r_build<8>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
-                else if (c == 1) hipLaunchKernelGGL(k_r_build<16>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
-                else if (c == 2) hipLaunchKernelGGL(k_r_build<32>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
-                else hipLaunchKernelGGL(k_r_build<64>, dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                if (c == 0) hipLaunchKernelGGL((k_r_build<8, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 1) hipLaunchKernelGGL((k_r_build<16, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 2) hipLaunchKernelGGL((k_r_build<32, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else hipLaunchKernelGGL((k_r_build<64, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
 #undef PAIR_RB_ARGS
                 prof_end_dev(s_, ph);
                 prof_end_dev(s_, ph1);
@@ -2555,7 +2633,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                     DBuf<unsigned> seen((n + 31) / 32);
                     PAIR_HIP(hipMemsetAsync(seen.p, 0, seen.bytes(), s_));
                     hipLaunchKernelGGL(k_r_gather_once, dim3(grid_for(nr, 256)), dim3(256), 0, s_, nr,
-                                       rl[c].p, c2f.p, L.A.rowptr.p, L.R.rowptr.p, L.R.col.p, seen.p, pb1);
+                                       rl[c].p, c2f.p, L.A.rowptr.p, L.R.rowptr.p, L.R.col.p, seen.p, pb1, 1);
                     PAIR_LAUNCH_CHECK();
                 }
             }

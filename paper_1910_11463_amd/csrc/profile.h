@@ -26,7 +26,8 @@ enum ProfKind : int {
     PROF_NORM_FINE = 4,      // convergence test on the finest level
     PROF_RBUILD = 5,         // lAIR rows with dense local systems (coarser levels' setup)
     PROF_RBUILD_ONCE = 6,    // the same launches, a gathered row of A counted once per launch
-    PROF_NKINDS = 7
+    PROF_RPATTERN = 7,       // the lAIR rows' patterns selected before their local systems
+    PROF_NKINDS = 8
 };
 
 bool prof_enabled();

@@ -278,8 +278,9 @@ def test_nair_rows_beyond_the_supported_length_are_rejected():
 def test_r_build_byte_count_matches_host_count():
     """The algorithmic bytes the lAIR row kernel adds up on the device (the
     figure behind the benchmark's roofline) equal the per-row formula evaluated
-    on the host from the hierarchy it built: per C row 40 + 14 len_i + 16 K +
-    12 sum_{j in R_i} len_j + 12 (K + 1)."""
+    on the host from the hierarchy it built (the row's pattern given, read from
+    R): per C row 40 + 12 len_i + 4 (K + 1) + 16 K + 12 sum_{j in R_i} len_j +
+    12 (K + 1)."""
     need_gpu()
     import ctypes
     A, _ = _matrix(2, 8, 5)
@@ -299,7 +300,7 @@ def test_r_build_byte_count_matches_host_count():
             cols = rc[rr[I]:rr[I + 1]]
             cols = cols[cols != i]
             K = len(cols)
-            want += 40 + 14 * int(lens[i]) + 16 * K + 12 * int(lens[cols].sum()) + 12 * (K + 1)
+            want += 40 + 12 * int(lens[i]) + 4 * (K + 1) + 16 * K + 12 * int(lens[cols].sum()) + 12 * (K + 1)
     print("r_build launches", n.value, "bytes", by.value, "host", want, flush=True)
     assert n.value > 0 and ms.value > 0.0
     assert int(by.value) == want
