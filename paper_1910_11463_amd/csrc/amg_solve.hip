@@ -386,11 +386,35 @@ struct HexDir {
     int in;
 };
 
+constexpr double kHexS2 = 1.4142135623730950488;      // sqrt 2
+
+// The eigenvalues sigma_t + kap_x lam_ex + kap_y lam_ey + kap_z lam_0 (lam =
+// 2 +- i sqrt2) of an element's diagonal block in the Kronecker-sum basis:
+// real part mr, imaginary parts mi, and 1 / |.|^2.  Depend only on sigma_t and
+// the direction, so a sweep can form them ahead of the element's face values.
+struct HexDen {
+    double mr, mi[2][2], inv[2][2];
+};
+
+__device__ __forceinline__ HexDen hex_den(double sig, const HexDir& dr) {
+    HexDen d;
+    d.mr = sig + 2.0 * (dr.kap[0] + dr.kap[1] + dr.kap[2]);
+#pragma unroll
+    for (int ex = 0; ex < 2; ++ex)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey) {
+            d.mi[ex][ey] = kHexS2 * ((ex ? -dr.kap[0] : dr.kap[0]) + (ey ? -dr.kap[1] : dr.kap[1]) + dr.kap[2]);
+            d.inv[ex][ey] = 1.0 / (d.mr * d.mr + d.mi[ex][ey] * d.mi[ex][ey]);
+        }
+    return d;
+}
+
 // y = D_e^{-1} A_eU x_U from the upwind neighbours' face values v_d[t] (t the
-// node index with bit d removed; zero where the face is on the inflow boundary).
-__device__ __forceinline__ void hex_face_solve(double sig, const HexDir& dr, const double v0[4],
-                                               const double v1[4], const double v2[4], double y[8]) {
-    constexpr double kS2 = 1.4142135623730950488;      // sqrt 2
+// node index with bit d removed; zero where the face is on the inflow boundary),
+// with the element's eigenvalues from hex_den.
+__device__ __forceinline__ void hex_face_solve_den(const HexDen& dn, const HexDir& dr, const double v0[4],
+                                                   const double v1[4], const double v2[4], double y[8]) {
+    constexpr double kS2 = kHexS2;
     constexpr double kC = 0.35355339059327376220;      // 1 / (2 sqrt 2)
     const int sx = dr.in & 1, sy = (dr.in >> 1) & 1, sz = (dr.in >> 2) & 1;
     // g = sum_d -kap_d M1^{-1}[a_d][s_d] v_d
@@ -436,14 +460,14 @@ __device__ __forceinline__ void hex_face_solve(double sig, const HexDir& dr, con
         gr[1][ey] = hr - kC * si; gi[1][ey] = hi + kC * sr;
     }
     // divide by sigma_t + kap_x lam_ex + kap_y lam_ey + kap_z lam_0, lam = 2 +- i sqrt2
-    const double mr = sig + 2.0 * (dr.kap[0] + dr.kap[1] + dr.kap[2]);
+    const double mr = dn.mr;
     double zr[2][2], zi[2][2];
 #pragma unroll
     for (int ex = 0; ex < 2; ++ex)
 #pragma unroll
         for (int ey = 0; ey < 2; ++ey) {
-            const double mi = kS2 * ((ex ? -dr.kap[0] : dr.kap[0]) + (ey ? -dr.kap[1] : dr.kap[1]) + dr.kap[2]);
-            const double inv = 1.0 / (mr * mr + mi * mi);
+            const double mi = dn.mi[ex][ey];
+            const double inv = dn.inv[ex][ey];
             zr[ex][ey] = (gr[ex][ey] * mr + gi[ex][ey] * mi) * inv;
             zi[ex][ey] = (gi[ex][ey] * mr - gr[ex][ey] * mi) * inv;
         }
@@ -477,6 +501,11 @@ __device__ __forceinline__ void hex_face_solve(double sig, const HexDir& dr, con
             y[ax + 2 * ay] = sz ? other : same;
             y[ax + 2 * ay + 4] = sz ? same : other;
         }
+}
+
+__device__ __forceinline__ void hex_face_solve(double sig, const HexDir& dr, const double v0[4],
+                                               const double v1[4], const double v2[4], double y[8]) {
+    hex_face_solve_den(hex_den(sig, dr), dr, v0, v1, v2, y);
 }
 
 // Face values of element g's upwind neighbours read from x, then the solve above.
@@ -684,6 +713,12 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
     const int dk = sz ? -1 : 1;
     double zf[4] = {0.0, 0.0, 0.0, 0.0};    // z-upwind face of the column's last element
     const int nsteps = wx + wy + wz - 2;
+    // the column's elements in order: sigma_t loaded two elements ahead and the
+    // eigenvalue reciprocals formed one element ahead, off the step's chain
+    const int64_t cbase = col - mbase + static_cast<int64_t>(kfirst) * nxy;
+    const int64_t cstep = static_cast<int64_t>(dk) * nxy;
+    HexDen den = hex_den(lane && wz > 0 ? sigt[cbase] : 0.0, dr);
+    double sig_n = lane && wz > 1 ? sigt[cbase + cstep] : 0.0;
     for (int s = 0; s < nsteps; ++s) {
         const int kp = s - ip - jp;
         const int p = s & 1;
@@ -727,7 +762,10 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
             }
             double bv[8], y[8], xn[8];
             load8(b + g * 8, bv);
-            hex_face_solve(sigt[g - mbase], dr, v0, v1, v2, y);
+            const HexDen den_n = hex_den(sig_n, dr);
+            sig_n = kp + 2 < wz ? sigt[cbase + (kp + 2) * cstep] : 0.0;
+            hex_face_solve_den(den, dr, v0, v1, v2, y);
+            den = den_n;
 #pragma unroll
             for (int a = 0; a < 8; ++a) xn[a] = bv[a] - y[a];
             store8(xout + g * 8, xn);
