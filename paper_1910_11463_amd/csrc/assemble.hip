@@ -356,35 +356,37 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
     for (int64_t q = threadIdx.x; q < (gend - g0) * 64; q += kHexBlock) dinv[g0 * 64 + q] = s_val[q];
     __syncthreads();
 
-    HexFace fc[3];
-    const int ni = hex_inflow_faces(e, nx, ny, nz, om, fc);
-    int64_t gid[4];
-    int gface[4];
-    int ng = 0;
-    gid[ng] = e; gface[ng] = -1; ++ng;
-    for (int q = 0; q < ni; ++q) { gid[ng] = fc[q].U; gface[ng] = q; ++ng; }
-    for (int i = 1; i < ng; ++i)
-        for (int j = i; j > 0 && gid[j - 1] > gid[j]; --j) {
-            int64_t t = gid[j]; gid[j] = gid[j - 1]; gid[j - 1] = t;
-            int tf = gface[j]; gface[j] = gface[j - 1]; gface[j - 1] = tf;
-        }
+    // inflow faces per axis (constant indices only: no per-thread memory)
+    const int64_t nxy = static_cast<int64_t>(nx) * ny;
+    const int64_t ei = e % nx, ej = (e / nx) % ny, ek = e / nxy;
+    bool has[3];
+    int side[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t id = d == 0 ? ei : (d == 1 ? ej : ek);
+        const int64_t nd = d == 0 ? nx : (d == 1 ? ny : nz);
+        side[d] = om[d] > 0.0 ? 0 : 1;       // inflow through the low side when Omega_d > 0
+        has[d] = fabs(om[d]) > kZeroFluxTol && (side[d] == 0 ? id > 0 : id < nd - 1);
+    }
+    const int ni = static_cast<int>(has[0]) + static_cast<int>(has[1]) + static_cast<int>(has[2]);
     const int L = 1 + 4 * ni;
     const int64_t N = E * 8;
     const int64_t row_g = static_cast<int64_t>(b) * N + 8 * e + a;
     const int64_t coff = static_cast<int64_t>(b) * N;
     const int64_t nrows = N * B, nel = E * B;
     const bool ell = valid && ell_val != nullptr;   // no element-block copy for the factored form
+    const int64_t stride3[3] = {1, nx, nxy};
     if (ell && a == 0) {
-        for (int sl = 0; sl < 3; ++sl) {
-            ell_nbr[sl * nel + g] = -1;
-            ell_nodes[sl * nel + g] = 0;
-        }
-        for (int q = 0; q < ni; ++q) {
-            const int ax = fc[q].face >> 1, side = fc[q].face & 1;
-            ell_nbr[ax * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + fc[q].U);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            ell_nbr[ax * nel + g] = -1;
+            ell_nodes[ax * nel + g] = 0;
+            if (!has[ax]) continue;
+            const int64_t U = side[ax] == 0 ? e - stride3[ax] : e + stride3[ax];
+            ell_nbr[ax * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + U);
             int packed = 0, j = 0;
             for (int cu = 0; cu < 8; ++cu)
-                if (((cu >> ax) & 1) == 1 - side) { packed |= cu << (3 * j); ++j; }
+                if (((cu >> ax) & 1) == 1 - side[ax]) { packed |= cu << (3 * j); ++j; }
             ell_nodes[ax * nel + g] = packed;
         }
     }
@@ -394,9 +396,14 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
     const int64_t lo = elem_off[g0], hi = elem_off[gend];
     const bool staged = hi - lo <= kHexStage;   // always, at <= 13 entries per row
     if (valid) rowptr[row_g] = rb;
+    // entries in column order: upwind neighbours below e (strides nx*ny, nx, 1,
+    // i.e. axes 2, 1, 0 on their low side), the diagonal, neighbours above e
+    // (axes 0, 1, 2 on their high side)
     int pos = 0;
-    for (int gi = 0; valid && gi < ng; ++gi) {
-        if (gface[gi] < 0) {
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+        if (!valid) break;
+        if (o == 3) {
             if (staged) {
                 s_col[rb - lo + pos] = static_cast<int32_t>(coff + 8 * e + a);
                 s_val[rb - lo + pos] = 1.0;
@@ -407,18 +414,22 @@ k_fine_hex_lanes(int64_t E, int nx, int ny, int nz, const double* __restrict__ r
             ++pos;
             continue;
         }
-        const HexFace& F = fc[gface[gi]];
-        const int ax = F.face >> 1, side = F.face & 1;
+        const int ax = o < 3 ? 2 - o : o - 4;
+        const int sd = o < 3 ? 0 : 1;
+        if (!has[ax] || side[ax] != sd) continue;
+        const int64_t U = sd == 0 ? e - stride3[ax] : e + stride3[ax];
+        const int face = 2 * ax + sd;
+        const double odn = -fabs(om[ax]);
         int j = 0;
         for (int cu = 0; cu < 8; ++cu) {
-            if (((cu >> ax) & 1) != 1 - side) continue;
+            if (((cu >> ax) & 1) != 1 - sd) continue;
             double sv = 0.0;
-            for (int c = 0; c < 8; ++c) sv += Di[c] * (F.odn * ref[REF_X + F.face * 64 + c * 8 + cu]);
+            for (int c = 0; c < 8; ++c) sv += Di[c] * (odn * ref[REF_X + face * 64 + c * 8 + cu]);
             if (staged) {
-                s_col[rb - lo + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
+                s_col[rb - lo + pos] = static_cast<int32_t>(coff + 8 * U + cu);
                 s_val[rb - lo + pos] = sv;
             } else {
-                col[rb + pos] = static_cast<int32_t>(coff + 8 * F.U + cu);
+                col[rb + pos] = static_cast<int32_t>(coff + 8 * U + cu);
                 val[rb + pos] = sv;
             }
             if (ell) ell_val[(ax * 4 + j) * nrows + row_g] = sv;
@@ -451,6 +462,7 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
     const double st = sigt[t];
     double on[4];
     bool zero[4];
+#pragma unroll
     for (int f = 0; f < 4; ++f) {
         const double* n = nvec + (t * 4 + f) * 3;
         on[f] = om[0] * n[0] + om[1] * n[1] + om[2] * n[2];
@@ -458,10 +470,13 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
         zero[f] = fabs(on[f]) <= kZeroFluxTol * nl;
     }
     double D[16], Di[16];
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
             // C_ac = (Omega . grad lambda_a) |T| / 4 = -(Omega . n_a) / 24
             double v = st * mass[t * 16 + a * 4 + c] + on[a] / 24.0;
+#pragma unroll
             for (int f = 0; f < 4; ++f) {
                 if (zero[f] || on[f] <= 0.0 || a == f || c == f) continue;
                 v += on[f] * (a == c ? 2.0 : 1.0) / 24.0;
@@ -470,20 +485,21 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
         }
     if (!small_inverse<4>(D, Di)) atomicAdd(bad, 1);
     double* dst = dinv + (static_cast<int64_t>(b) * E + t) * 16;
+#pragma unroll
     for (int r = 0; r < 16; ++r) dst[r] = Di[r];
 
-    TetFace fc[4];
-    const int ni = tet_inflow_faces(t, nbr, nvec, om, fc);
-    int64_t gid[5];
-    int gface[5];
-    int ng = 0;
-    gid[ng] = t; gface[ng] = -1; ++ng;
-    for (int q = 0; q < ni; ++q) { gid[ng] = fc[q].U; gface[ng] = q; ++ng; }
-    for (int i = 1; i < ng; ++i)
-        for (int j = i; j > 0 && gid[j - 1] > gid[j]; --j) {
-            int64_t tt = gid[j]; gid[j] = gid[j - 1]; gid[j - 1] = tt;
-            int tf = gface[j]; gface[j] = gface[j - 1]; gface[j - 1] = tf;
-        }
+    // inflow faces (an upwind neighbour across a face Omega enters through),
+    // with constant indices only: no per-thread memory
+    bool inf[4];
+    int64_t Uf[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int32_t U = nbr[t * 4 + f];
+        inf[f] = !zero[f] && !(on[f] > 0.0) && U >= 0;
+        Uf[f] = U;
+    }
+    const int ni = static_cast<int>(inf[0]) + static_cast<int>(inf[1]) + static_cast<int>(inf[2]) +
+                   static_cast<int>(inf[3]);
     const int L = 1 + 3 * ni;
     const int64_t N = E * 4;
     const int64_t row0 = static_cast<int64_t>(b) * N + 4 * t;
@@ -492,55 +508,69 @@ k_fine_tet(int64_t E, const int32_t* __restrict__ nbr, const int8_t* __restrict_
     // element-block (ELL) copy: slot = position in the inflow-face list, U's
     // three face nodes in ascending local order
     const int64_t nrows = N * B, nel = E * B;
+#pragma unroll
     for (int sl = 0; sl < 3; ++sl) {
         ell_nbr[sl * nel + g] = -1;
         ell_nodes[sl * nel + g] = 0;
     }
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
         for (int j = 0; j < 9; ++j) ell_val[j * nrows + row0 + a] = 0.0;
-    for (int q = 0; q < ni; ++q) {
-        int un[3], qq = 0;
-        for (int a2 = 0; a2 < 4; ++a2)
-            if (a2 != fc[q].face) { un[qq] = unode[(t * 4 + fc[q].face) * 3 + qq]; ++qq; }
-        for (int i = 1; i < 3; ++i)
-            for (int j = i; j > 0 && un[j - 1] > un[j]; --j) { int tmp = un[j]; un[j] = un[j - 1]; un[j - 1] = tmp; }
-        ell_nbr[q * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + fc[q].U);
-        ell_nodes[q * nel + g] = un[0] | (un[1] << 3) | (un[2] << 6);
+    // per inflow face: its slot, U's face nodes sorted (value, position in
+    // e's face order), and the CSR offset of its entries within a row (rows'
+    // entries ascend by column: groups ordered by element, e's own diagonal
+    // entry one wide, each face three wide)
+    int slot[4], pf[4], us[4][3], uj[4][3];
+    int pd = 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        slot[f] = 0;
+        pf[f] = t < Uf[f] ? 1 : 0;
+#pragma unroll
+        for (int f2 = 0; f2 < 4; ++f2) {
+            if (f2 < f) slot[f] += inf[f2] ? 1 : 0;
+            if (f2 != f && inf[f2] && Uf[f2] < Uf[f]) pf[f] += 3;
+        }
+        pd += (inf[f] && Uf[f] < t) ? 3 : 0;
+        int v0 = unode[(t * 4 + f) * 3 + 0], v1 = unode[(t * 4 + f) * 3 + 1], v2 = unode[(t * 4 + f) * 3 + 2];
+        int j0 = 0, j1 = 1, j2 = 2;
+        // three compare-exchanges: (0,1), (1,2), (0,1)
+        if (v0 > v1) { int tv = v0; v0 = v1; v1 = tv; int tj = j0; j0 = j1; j1 = tj; }
+        if (v1 > v2) { int tv = v1; v1 = v2; v2 = tv; int tj = j1; j1 = j2; j2 = tj; }
+        if (v0 > v1) { int tv = v0; v0 = v1; v1 = tv; int tj = j0; j0 = j1; j1 = tj; }
+        us[f][0] = v0; us[f][1] = v1; us[f][2] = v2;
+        uj[f][0] = j0; uj[f][1] = j1; uj[f][2] = j2;
+        if (inf[f]) {
+            ell_nbr[slot[f] * nel + g] = static_cast<int32_t>(static_cast<int64_t>(b) * E + Uf[f]);
+            ell_nodes[slot[f] * nel + g] = v0 | (v1 << 3) | (v2 << 6);
+        }
     }
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int64_t rb = base + static_cast<int64_t>(a) * L;
         rowptr[row0 + a] = rb;
-        int pos = 0;
-        for (int gi = 0; gi < ng; ++gi) {
-            if (gface[gi] < 0) {
-                col[rb + pos] = static_cast<int32_t>(coff + 4 * t + a);
-                val[rb + pos] = 1.0;
-                ++pos;
-                continue;
-            }
-            const TetFace& F = fc[gface[gi]];
-            // e's face nodes j (local order, skipping F.face) and U's matching nodes
-            int en[3], un[3], q = 0;
-            for (int a2 = 0; a2 < 4; ++a2)
-                if (a2 != F.face) { en[q] = a2; un[q] = unode[(t * 4 + F.face) * 3 + q]; ++q; }
-            // emit U's three nodes in ascending local order
-            int ord[3] = {0, 1, 2};
-            for (int i = 1; i < 3; ++i)
-                for (int j = i; j > 0 && un[ord[j - 1]] > un[ord[j]]; --j) {
-                    int tmp = ord[j]; ord[j] = ord[j - 1]; ord[j - 1] = tmp;
-                }
+        col[rb + pd] = static_cast<int32_t>(coff + 4 * t + a);
+        val[rb + pd] = 1.0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (!inf[f]) continue;
+            // e's face nodes (local order, skipping f)
+            const int en[3] = {f == 0 ? 1 : 0, f <= 1 ? 2 : 1, f <= 2 ? 3 : 2};
+            // A[a][U node] = (Omega.n)/24 * (1 + [node of e on the same vertex]),
+            // U's three nodes in ascending local order
+#pragma unroll
             for (int oi = 0; oi < 3; ++oi) {
-                const int jcol = ord[oi];
-                // A[c][U node jcol] = (Omega.n)/24 * (1 + [node c of e is the same vertex])
+                const int jcol = uj[f][oi];
                 double s = 0.0;
+#pragma unroll
                 for (int qq = 0; qq < 3; ++qq) {
-                    const double acj = F.odn * (qq == jcol ? 2.0 : 1.0) / 24.0;
+                    const double acj = on[f] * (qq == jcol ? 2.0 : 1.0) / 24.0;
                     s += Di[a * 4 + en[qq]] * acj;
                 }
-                col[rb + pos] = static_cast<int32_t>(coff + 4 * F.U + un[jcol]);
-                val[rb + pos] = s;
-                ell_val[(gface[gi] * 3 + oi) * nrows + row0 + a] = s;
-                ++pos;
+                col[rb + pf[f] + oi] = static_cast<int32_t>(coff + 4 * Uf[f] + us[f][oi]);
+                val[rb + pf[f] + oi] = s;
+                ell_val[(slot[f] * 3 + oi) * nrows + row0 + a] = s;
             }
         }
     }
@@ -560,23 +590,28 @@ __device__ __forceinline__ void add_inflow(int64_t e, const double om[3], const 
                                            const int32_t* __restrict__ nbr,
                                            const double* __restrict__ nvec, double f[K]) {
     if constexpr (K == 8) {
-        const int64_t idx[3] = {e % nx, (e / nx) % ny, e / (static_cast<int64_t>(nx) * ny)};
-        const int64_t nn[3] = {nx, ny, nz};
+        const int64_t ei = e % nx, ej = (e / nx) % ny, ek = e / (static_cast<int64_t>(nx) * ny);
+#pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             if (fabs(om[ax]) <= kZeroFluxTol) continue;
             const int side = om[ax] > 0.0 ? 0 : 1;          // the face Omega enters through
-            if (side == 0 ? idx[ax] != 0 : idx[ax] != nn[ax] - 1) continue;
+            const int64_t id = ax == 0 ? ei : (ax == 1 ? ej : ek);
+            const int64_t nd = ax == 0 ? nx : (ax == 1 ? ny : nz);
+            if (side == 0 ? id != 0 : id != nd - 1) continue;
             const double odn = -fabs(om[ax]);
             const double* F = fref + (2 * ax + side) * 64;
+#pragma unroll
             for (int a = 0; a < 8; ++a) {
                 if (((a >> ax) & 1) != side) continue;
                 double s = 0.0;
+#pragma unroll
                 for (int c = 0; c < 8; ++c)
                     if (((c >> ax) & 1) == side) s += F[a * 8 + c] * g[c];
                 f[a] -= odn * s;
             }
         }
     } else {
+#pragma unroll
         for (int fc = 0; fc < 4; ++fc) {
             if (nbr[e * 4 + fc] >= 0) continue;
             const double* n = nvec + (e * 4 + fc) * 3;
@@ -584,8 +619,10 @@ __device__ __forceinline__ void add_inflow(int64_t e, const double om[3], const 
             const double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
             if (fabs(on) <= kZeroFluxTol * nl || on > 0.0) continue;
             double gs = 0.0;
+#pragma unroll
             for (int a = 0; a < 4; ++a)
                 if (a != fc) gs += g[a];
+#pragma unroll
             for (int a = 0; a < 4; ++a)
                 if (a != fc) f[a] -= on / 24.0 * (g[a] + gs);
         }
@@ -609,10 +646,13 @@ __global__ void k_rhs(int64_t E, int B, const int* __restrict__ dirs, const doub
     double src[K], f[K];
     const double qe = q ? q[e] : 0.0;
     const double se = sigs[e];
+#pragma unroll
     for (int c = 0; c < K; ++c) src[c] = (phi ? se * phi[e * K + c] : 0.0) + qe;
     const double* Me = mass ? mass + e * K * K : mref;
+#pragma unroll
     for (int a = 0; a < K; ++a) {
         double s = 0.0;
+#pragma unroll
         for (int c = 0; c < K; ++c) s += Me[a * K + c] * src[c];
         f[a] = s / kFourPi;
         if (ext) f[a] += ext_per_dir ? ext[static_cast<int64_t>(dirs[b]) * N + e * K + a] : ext[e * K + a];
@@ -622,12 +662,15 @@ __global__ void k_rhs(int64_t E, int B, const int* __restrict__ dirs, const doub
         const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
         double gv[K];
         const double* gm = inflow + static_cast<int64_t>(m) * N + e * K;
+#pragma unroll
         for (int c = 0; c < K; ++c) gv[c] = gm[c];
         add_inflow<K>(e, om, gv, nx, ny, nz, fref, nbr, nvec, f);
     }
     const double* Di = dinv + (static_cast<int64_t>(b) * E + e) * K * K;
+#pragma unroll
     for (int a = 0; a < K; ++a) {
         double s = 0.0;
+#pragma unroll
         for (int c = 0; c < K; ++c) s += Di[a * K + c] * f[c];
         out[static_cast<int64_t>(b) * N + e * K + a] = s;
     }
