@@ -711,6 +711,16 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
     const int64_t col = mbase + static_cast<int64_t>(j) * nx + i;
     const int kfirst = sz ? z0 + wz - 1 : z0;
     const int dk = sz ? -1 : 1;
+    // stores by whole 128-byte pairs: elements i and i ^ 1 of one x-row share a
+    // line (when nx is even); the later of the two lanes (larger ip: one step
+    // later, same z) writes both, the partner's values from the exchange
+    // buffer, the earlier stores nothing; an element without a partner in
+    // the box stores alone
+    const int ipart = i ^ 1;
+    const bool pin = lane && ipart >= x0 && ipart < x0 + wx;
+    const int ip_part = sx ? x0 + wx - 1 - ipart : ipart - x0;
+    const bool store_pair = pin && ip_part == ip - 1;
+    const bool store_none = pin && ip_part == ip + 1;
     double zf[4] = {0.0, 0.0, 0.0, 0.0};    // z-upwind face of the column's last element
     const int nsteps = wx + wy + wz - 2;
     // the column's elements in order: sigma_t loaded two elements ahead and the
@@ -768,7 +778,20 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
             den = den_n;
 #pragma unroll
             for (int a = 0; a < 8; ++a) xn[a] = bv[a] - y[a];
-            store8(xout + g * 8, xn);
+            if (store_pair) {
+                double pv[8];
+#pragma unroll
+                for (int a = 0; a < 8; ++a) pv[a] = sh[p ^ 1][a][tid - 1];
+                if (i & 1) {
+                    store8(xout + (g - 1) * 8, pv);
+                    store8(xout + g * 8, xn);
+                } else {
+                    store8(xout + g * 8, xn);
+                    store8(xout + (g + 1) * 8, pv);
+                }
+            } else if (!store_none) {
+                store8(xout + g * 8, xn);
+            }
 #pragma unroll
             for (int a = 0; a < 8; ++a) sh[p][a][tid] = xn[a];
 #pragma unroll
