@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libpair.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["primitives.hip", "amg_setup.hip", "amg_solve.hip", "assemble.hip",
-           "transport.cpp", "quadrature.cpp", "api.cpp", "profile.cpp"]
+           "transport.cpp", "quadrature.cpp", "api.cpp", "profile.cpp", "tet_schedule.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PAIR_OFFLOAD_ARCH", "gfx950")

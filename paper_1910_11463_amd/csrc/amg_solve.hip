@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "amg.h"
+#include "tet_schedule.h"
 #include "kernels_common.h"
 #include "profile.h"
 
@@ -883,7 +884,6 @@ __global__ void k_tet_posof(int64_t nel, int64_t E, const int32_t* __restrict__ 
 // row r), right-hand side b minus the couplings to elements outside the set
 // (this tile's lower levels from LDS, other tiles from xin), then Gauss-Jordan
 // elimination with partial pivoting across the wave.
-constexpr int kSccMax = 16;        // elements of one set (64 rows, one wave)
 constexpr int kSccLd = 65;         // LDS row stride of the dense system
 
 template <int NF>
@@ -1255,168 +1255,6 @@ double restrict_bytes(const Level& L, double vb = 8.0) {
            2.0 * nc;
 }
 
-// Schedule of tiles with upwind cycles, on the host: per member and tile,
-// the strongly connected components of the upwind graph restricted to the
-// tile (Tarjan's algorithm, iterative; a component is completed after every
-// component it depends on, so completion order is an upwind order), levels
-// of the condensed graph (longest upwind path), and the positions: per level
-// its single elements, then its components, each contiguous.  Outputs per
-// batch position k = m E + tile_ptr[t] + q: order (element), scc (first
-// position | size << 16 for elements of components, else 0); per (member,
-// tile) level starts lvl [Lmax + 2] (the last entry the tile's size) and
-// component starts lvls [Lmax + 1].
-struct CyclicSchedule {
-    std::vector<int32_t> order, scc, lvl, lvls;
-    int Lmax = 0, max_set = 1;
-};
-
-CyclicSchedule tet_schedule_cyclic(const std::vector<int32_t>& nbr, int64_t nel, int64_t Em, int B, int T,
-                                   const std::vector<int32_t>& tile_of, const std::vector<int32_t>& tile_ptr) {
-    // member-independent: the elements of every tile and each element's index in it
-    std::vector<int32_t> elems(Em), loc(Em), fill(tile_ptr.begin(), tile_ptr.end() - 1);
-    for (int64_t e = 0; e < Em; ++e) {
-        const int t = tile_of[e];
-        loc[e] = fill[t] - tile_ptr[t];
-        elems[fill[t]++] = static_cast<int32_t>(e);
-    }
-    struct Out {
-        std::vector<int32_t> pos_elem, pos_scc, lstart, sstart;
-    };
-    const int64_t work = static_cast<int64_t>(B) * T;
-    std::vector<Out> out(work);
-    std::vector<int> err(work, 0);
-    auto run = [&](int64_t w) {
-        const int64_t m = w / T, mE = m * Em;
-        const int t = static_cast<int>(w - m * T);
-        const int n = tile_ptr[t + 1] - tile_ptr[t];
-        const int32_t* te = elems.data() + tile_ptr[t];
-        auto dep = [&](int i, int sl) -> int {   // in-tile upwind neighbour of node i through slot sl, or -1
-            const int32_t u = nbr[static_cast<int64_t>(sl) * nel + mE + te[i]];
-            if (u < 0 || tile_of[u - mE] != t) return -1;
-            return loc[u - mE];
-        };
-        // Tarjan, iterative: frames (node, next slot)
-        std::vector<int> index(n, -1), low(n, 0), comp(n, -1), stack, csize;
-        std::vector<char> on(n, 0);
-        std::vector<std::pair<int, int>> frames;
-        int counter = 0, ncomp = 0;
-        for (int r = 0; r < n; ++r) {
-            if (index[r] >= 0) continue;
-            frames.push_back({r, 0});
-            index[r] = low[r] = counter++;
-            stack.push_back(r);
-            on[r] = 1;
-            while (!frames.empty()) {
-                auto& f = frames.back();
-                const int v = f.first;
-                if (f.second < 3) {
-                    const int u = dep(v, f.second++);
-                    if (u < 0) continue;
-                    if (index[u] < 0) {
-                        index[u] = low[u] = counter++;
-                        stack.push_back(u);
-                        on[u] = 1;
-                        frames.push_back({u, 0});
-                    } else if (on[u]) {
-                        low[v] = std::min(low[v], index[u]);
-                    }
-                    continue;
-                }
-                if (low[v] == index[v]) {
-                    int sz = 0, x;
-                    do {
-                        x = stack.back();
-                        stack.pop_back();
-                        on[x] = 0;
-                        comp[x] = ncomp;
-                        ++sz;
-                    } while (x != v);
-                    csize.push_back(sz);
-                    ++ncomp;
-                }
-                frames.pop_back();
-                if (!frames.empty()) {
-                    const int pv = frames.back().first;
-                    low[pv] = std::min(low[pv], low[v]);
-                }
-            }
-        }
-        // component levels in completion order (every upwind component first)
-        std::vector<int> clev(ncomp, 0);
-        std::vector<std::vector<int>> members(ncomp);
-        for (int i = 0; i < n; ++i) members[comp[i]].push_back(i);
-        int Lt = 0;
-        for (int c = 0; c < ncomp; ++c) {
-            if (csize[c] > kSccMax) err[w] = 1;
-            int L = 0;
-            for (int i : members[c])
-                for (int sl = 0; sl < 3; ++sl) {
-                    const int u = dep(i, sl);
-                    if (u >= 0 && comp[u] != c) L = std::max(L, clev[comp[u]] + 1);
-                }
-            clev[c] = L;
-            Lt = std::max(Lt, L);
-        }
-        Out& o = out[w];
-        o.lstart.assign(Lt + 2, 0);
-        o.sstart.assign(Lt + 1, 0);
-        o.pos_elem.reserve(n);
-        o.pos_scc.reserve(n);
-        std::vector<std::vector<int>> single(Lt + 1), sets(Lt + 1);
-        for (int c = 0; c < ncomp; ++c) (csize[c] == 1 ? single : sets)[clev[c]].push_back(c);
-        for (int L = 0; L <= Lt; ++L) {
-            o.lstart[L] = static_cast<int32_t>(o.pos_elem.size());
-            for (int c : single[L]) {
-                o.pos_elem.push_back(te[members[c][0]]);
-                o.pos_scc.push_back(0);
-            }
-            o.sstart[L] = static_cast<int32_t>(o.pos_elem.size());
-            for (int c : sets[L]) {
-                const int first = static_cast<int>(o.pos_elem.size());
-                for (int i : members[c]) {
-                    o.pos_elem.push_back(te[i]);
-                    o.pos_scc.push_back(first | (csize[c] << 16));
-                }
-            }
-        }
-        o.lstart[Lt + 1] = n;
-    };
-    const int nth = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(
-        {16, static_cast<int64_t>(std::thread::hardware_concurrency()), work})));
-    std::vector<std::thread> th;
-    for (int i = 0; i < nth; ++i)
-        th.emplace_back([&, i] {
-            for (int64_t w = i; w < work; w += nth) run(w);
-        });
-    for (auto& x : th) x.join();
-    for (int64_t w = 0; w < work; ++w)
-        PAIR_CHECK(!err[w], "tile sweeps: an upwind cycle of more than 16 elements inside a tet tile "
-                            "(the exact tile solve holds at most 16 elements of a cycle; use smaller tiles)");
-    CyclicSchedule cs;
-    for (const Out& o : out) cs.Lmax = std::max(cs.Lmax, static_cast<int>(o.sstart.size()) - 1);
-    const int Lmax = cs.Lmax;
-    cs.order.assign(nel, 0);
-    cs.scc.assign(nel, 0);
-    cs.lvl.assign(static_cast<size_t>(work) * (Lmax + 2), 0);
-    cs.lvls.assign(static_cast<size_t>(work) * (Lmax + 1), 0);
-    for (int64_t w = 0; w < work; ++w) {
-        const int64_t m = w / T;
-        const int t = static_cast<int>(w - m * T);
-        const Out& o = out[w];
-        const int n = tile_ptr[t + 1] - tile_ptr[t];
-        const int Lt = static_cast<int>(o.sstart.size()) - 1;
-        const int64_t k0 = m * Em + tile_ptr[t];
-        for (int q = 0; q < n; ++q) {
-            cs.order[k0 + q] = o.pos_elem[q];
-            cs.scc[k0 + q] = o.pos_scc[q];
-            if (o.pos_scc[q]) cs.max_set = std::max(cs.max_set, o.pos_scc[q] >> 16);
-        }
-        for (int L = 0; L <= Lmax + 1; ++L) cs.lvl[w * (Lmax + 2) + L] = L <= Lt ? o.lstart[L] : n;
-        for (int L = 0; L <= Lmax; ++L) cs.lvls[w * (Lmax + 1) + L] = L <= Lt ? o.sstart[L] : n;
-    }
-    return cs;
-}
-
 }  // namespace
 
 // Level-order packing of records and values for the tile kernel (from the
@@ -1453,6 +1291,8 @@ static void tet_tile_schedule_cyclic(FineEll& fe, int T, int tmax, hipStream_t s
     d2h(tptr.data(), fe.tile_ptr.p, T + 1, s);
     PAIR_HIP(hipStreamSynchronize(s));
     CyclicSchedule cs = tet_schedule_cyclic(nbr, nel, Em, B, T, tof, tptr);
+    PAIR_CHECK(!cs.too_large, "tile sweeps: an upwind cycle of more than 16 elements inside a tet tile "
+                              "(the exact tile solve holds at most 16 elements of a cycle; use smaller tiles)");
     PAIR_CHECK(cs.max_set == 1 || (static_cast<size_t>(tmax) * 4 + 64 * kSccLd) * sizeof(double) <= 65536,
                "tile sweeps with upwind cycles: a tet tile may hold at most 1008 elements (LDS)");
     fe.order.alloc(nel);
