@@ -147,10 +147,12 @@ typedef struct pair_options {
                                  is cut into tet_tile_boxes^3 equal boxes and an element
                                  belongs to the box of its centroid (x0+x1+x2+x3)/4; one
                                  tile sweep is block Jacobi over these tiles with an exact
-                                 solve inside each (upwind order, no cycles inside a tile,
-                                 else PAIR_E_INVALID).  0 (default): the smallest count
-                                 with n_elem <= 384 count^3.  A tile may hold at most 1024
-                                 elements                                              */
+                                 solve inside each (upwind order; an upwind cycle inside
+                                 a tile is solved as one dense system of its elements, at
+                                 most 16 of them, else PAIR_E_INVALID).  0 (default):
+                                 the smallest count with n_elem <= 384 count^3.  A tile
+                                 may hold at most 1024 elements (1008 where it has a
+                                 cycle), else PAIR_E_INVALID                           */
 } pair_options;
 
 void pair_default_options(pair_options* opt);
