@@ -139,13 +139,14 @@ struct FineEll {
 // Upwind level schedule of the tet tiles of a batch (FineEll of the stored
 // form with its neighbour lists): the longest upwind path of every element
 // inside its tile, then every tile's elements sorted by it, and the records
-// and values packed in that order.  tile_of / tile_ptr: device, member-
-// independent (copied into fe).  Must run before the class regrouping of the
+// and values packed in that order.  tile_of / tile_ptr / tile_elems (each
+// tile's elements in order) / tile_loc (an element's position in its tile):
+// device, member-independent (tile_of and tile_ptr copied into fe).  Must run before the class regrouping of the
 // values.  Tiles with upwind cycles get their strongly connected sets solved
 // exactly (scheduled on the host); throws PAIR_E_INVALID if such a set has
 // more than 16 elements.
-void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr, int T, int tmax,
-                       hipStream_t s);
+void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr, const int32_t* tile_elems,
+                       const int32_t* tile_loc, int T, int tmax, hipStream_t s);
 
 struct Level {
     Csr A;                         // all members present at this level, concatenated

@@ -1046,33 +1046,67 @@ k_tet_tile(int T, int Lmax, int64_t E, int tmax, const int32_t* __restrict__ til
     }
 }
 
-// Longest upwind path inside the tile, every element of the batch (g = m E + e):
-// lev[g] = max(lev[U] + 1) over its upwind neighbours U in the same tile.  In
-// place and monotone: repeated until nothing changes (the unique fixed point
-// is reached whatever the update order); a cycle inside a tile never settles.
-__global__ void k_tet_levels(int64_t nel, int64_t E, const int32_t* __restrict__ nbr,
-                             const int32_t* __restrict__ tile_of, int* __restrict__ lev,
-                             int* __restrict__ changed) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= nel) return;
-    const int64_t mE = g / E * E;
-    const int t = tile_of[g - mE];
-    int L = 0;
-    for (int sl = 0; sl < 3; ++sl) {
-        const int32_t u = nbr[sl * nel + g];
-        if (u >= 0 && tile_of[u - mE] == t) L = max(L, __atomic_load_n(&lev[u], __ATOMIC_RELAXED) + 1);
+// Longest upwind path inside each tile, one block per (member, tile): the
+// tile's in-tile upwind neighbours (positions in the tile) and levels in LDS,
+// lev[q] = max(lev[u] + 1) over them, in place and monotone, until a pass
+// changes nothing (at most the longest path + 1 passes).  A tile that still
+// changes after (its size + 1) passes has an upwind cycle: flag[0] is set and
+// its levels are not written.  flag[1] = the largest level (atomic max).
+constexpr int kTetLevBlock = 256;
+__global__ void __launch_bounds__(kTetLevBlock)
+k_tet_tile_levels(int T, int64_t E, int64_t nel, const int32_t* __restrict__ tile_ptr,
+                  const int32_t* __restrict__ tile_elems, const int32_t* __restrict__ tile_loc,
+                  const int32_t* __restrict__ tile_of, const int32_t* __restrict__ nbr, int* __restrict__ lev,
+                  int* __restrict__ flag) {
+    __shared__ int16_t snb[kTetTileMax][3];
+    __shared__ int slev[kTetTileMax];
+    __shared__ int changed;
+    const int64_t m = blockIdx.x / T;
+    const int t = static_cast<int>(blockIdx.x - m * T);
+    const int64_t mE = m * E;
+    const int t0 = tile_ptr[t], n = tile_ptr[t + 1] - t0;
+    for (int q = threadIdx.x; q < n; q += kTetLevBlock) {
+        const int32_t e = tile_elems[t0 + q];
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+            const int32_t u = nbr[sl * nel + mE + e];
+            snb[q][sl] = static_cast<int16_t>(u >= 0 && tile_of[u - mE] == t ? tile_loc[u - mE] : -1);
+        }
+        slev[q] = 0;
     }
-    if (L > lev[g]) {
-        __atomic_store_n(&lev[g], L, __ATOMIC_RELAXED);
-        *changed = 1;
+    int passes = 0;
+    for (;;) {
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < n; q += kTetLevBlock) {
+            int L = slev[q];
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+                const int u = snb[q][sl];
+                if (u >= 0) L = max(L, __atomic_load_n(&slev[u], __ATOMIC_RELAXED) + 1);
+            }
+            if (L > slev[q]) {
+                __atomic_store_n(&slev[q], L, __ATOMIC_RELAXED);
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        const bool again = changed != 0;
+        ++passes;
+        __syncthreads();                 // every thread has read `changed` before it is cleared
+        if (!again) break;
+        if (passes > n + 1) {
+            if (threadIdx.x == 0) atomicOr(&flag[0], 1);
+            return;                      // uniform: every thread took the same branch
+        }
     }
-}
-
-__global__ void k_tet_level_max(int64_t nel, const int* __restrict__ lev, int* __restrict__ mx) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    int v = g < nel ? lev[g] : 0;
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+    int mx = 0;
+    for (int q = threadIdx.x; q < n; q += kTetLevBlock) {
+        lev[mE + tile_elems[t0 + q]] = slev[q];
+        mx = max(mx, slev[q]);
+    }
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
+    if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(&flag[1], mx);
 }
 
 // bucket (member, tile, level) of every element: count, then scatter
@@ -1311,8 +1345,8 @@ static void tet_tile_schedule_cyclic(FineEll& fe, int T, int tmax, hipStream_t s
     fe.max_set = cs.max_set;
 }
 
-void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr,
-                       int T, int tmax, hipStream_t s) {
+void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_ptr, const int32_t* tile_elems,
+                       const int32_t* tile_loc, int T, int tmax, hipStream_t s) {
     PAIR_CHECK(!fe.factored && fe.k == 4 && fe.nf == 3, "tet tile schedule needs the stored tet form");
     const int64_t nel = fe.nel;          // elements of the batch
     const int64_t Em = fe.E;             // elements per member
@@ -1322,30 +1356,24 @@ void tet_tile_schedule(FineEll& fe, const int32_t* tile_of, const int32_t* tile_
     fe.tile_ptr.alloc(T + 1);
     d2d(fe.tile_of.p, tile_of, Em, s);
     d2d(fe.tile_ptr.p, tile_ptr, T + 1, s);
+    PAIR_CHECK(tmax <= kTetTileMax, "a tet tile holds more than 1024 elements");
     DBuf<int> lev(nel), flag(2);
-    PAIR_HIP(hipMemsetAsync(lev.p, 0, nel * sizeof(int), s));
-    int changed = 1, it = 0;
-    while (changed) {
-        if (++it > tmax + 1) {
-            // an acyclic tile settles within (its size) passes: some tile holds
-            // an upwind cycle, so the schedule is built on the host with its
-            // strongly connected sets
-            tet_tile_schedule_cyclic(fe, T, tmax, s);
-            return;
-        }
-        PAIR_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
-        hipLaunchKernelGGL(k_tet_levels, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, Em, fe.nbr.p,
-                           fe.tile_of.p, lev.p, flag.p);
-        PAIR_LAUNCH_CHECK();
-        d2h(&changed, flag.p, 1, s);
-        PAIR_HIP(hipStreamSynchronize(s));
-    }
-    PAIR_HIP(hipMemsetAsync(flag.p + 1, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_tet_level_max, dim3(grid_for(nel, 256)), dim3(256), 0, s, nel, lev.p, flag.p + 1);
+    PAIR_HIP(hipMemsetAsync(flag.p, 0, 2 * sizeof(int), s));
+    PAIR_CHECK(static_cast<int64_t>(B) * T < (int64_t(1) << 31), "tet tile grid too large");
+    hipLaunchKernelGGL(k_tet_tile_levels, dim3(static_cast<unsigned>(static_cast<int64_t>(B) * T)),
+                       dim3(kTetLevBlock), 0, s, T, Em, nel, fe.tile_ptr.p, tile_elems, tile_loc, fe.tile_of.p,
+                       fe.nbr.p, lev.p, flag.p);
     PAIR_LAUNCH_CHECK();
-    int Lmax = 0;
-    d2h(&Lmax, flag.p + 1, 1, s);
+    int hf[2] = {0, 0};
+    d2h(hf, flag.p, 2, s);
     PAIR_HIP(hipStreamSynchronize(s));
+    if (hf[0]) {
+        // some tile holds an upwind cycle: the schedule is built on the host with
+        // its strongly connected sets
+        tet_tile_schedule_cyclic(fe, T, tmax, s);
+        return;
+    }
+    const int Lmax = hf[1];
     const int64_t nb = static_cast<int64_t>(B) * T * (Lmax + 1);
     DBuf<unsigned long long> cnt(nb), cur(nb);
     DBuf<int64_t> off(nb + 1);

@@ -142,7 +142,8 @@ Csr Context::assemble_fine(Batch& bt, hipStream_t s, double* t_assemble_ms) {
     fine_assemble(mesh, omega_d.p, dirs_d.p, B, sigt.p, eoff.p, nnz, A.rowptr.p, A.col.p, A.val.p,
                   bt.dinv.p, fe, s);
     if (tiles && mesh.kind == PAIR_TET4)
-        tet_tile_schedule(fe, tet_tile_of.p, tet_tile_ptr.p, tet_ntiles, tet_tile_max, s);
+        tet_tile_schedule(fe, tet_tile_of.p, tet_tile_ptr.p, tet_tile_elems.p, tet_tile_loc.p, tet_ntiles,
+                          tet_tile_max, s);
     if (t_assemble_ms) *t_assemble_ms += now_ms() - t0;
     return A;
 }
@@ -190,10 +191,19 @@ void Context::build_tet_tiles(hipStream_t st) {
         tptr[t + 1] += tptr[t];
     }
     PAIR_CHECK(tmax <= 1024, "a tet tile holds more than 1024 elements: raise tet_tile_boxes");
+    std::vector<int32_t> elems(E), loc(E), fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+        loc[e] = fill[tof[e]] - tptr[tof[e]];
+        elems[fill[tof[e]]++] = static_cast<int32_t>(e);
+    }
     tet_tile_of.alloc(E);
     tet_tile_ptr.alloc(T + 1);
+    tet_tile_elems.alloc(E);
+    tet_tile_loc.alloc(E);
     h2d(tet_tile_of.p, tof.data(), E, st);
     h2d(tet_tile_ptr.p, tptr.data(), T + 1, st);
+    h2d(tet_tile_elems.p, elems.data(), E, st);
+    h2d(tet_tile_loc.p, loc.data(), E, st);
     PAIR_HIP(hipStreamSynchronize(st));
     tet_ntiles = static_cast<int>(T);
     tet_tile_max = tmax;

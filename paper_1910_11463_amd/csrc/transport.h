@@ -86,6 +86,7 @@ struct Context {
     int tet_tiles_nbox = -1;            // box count the device tiles below were built for
     int tet_ntiles = 0, tet_tile_max = 0;
     DBuf<int32_t> tet_tile_of, tet_tile_ptr;
+    DBuf<int32_t> tet_tile_elems, tet_tile_loc;   // elements of each tile in order; position in its tile
     std::mutex tet_tiles_mu;            // worker threads may assemble batches at once
     void build_tet_tiles(hipStream_t st);
 
