@@ -187,8 +187,10 @@ def _tets(n, seed, jitter=0.2):
     return wl.Workload("tet%d^3x6-S4" % n, mesh, wl.Materials(st, 0.5 * st, np.ones(E)), 4)
 
 
-# (mesh size, tet_tile_boxes, pre, post, directions)
-TET_CASES = [(5, 2, "T", "T", (0, 7, 13, 23)), (5, 0, "TF", "FT", (2, 19)), (4, 3, "TT", "C", (5, 11))]
+# (mesh size, tet_tile_boxes, pre, post, directions); the last: 10^3 boxes over
+# 384 tets, so most tiles are empty or hold one or two elements
+TET_CASES = [(5, 2, "T", "T", (0, 7, 13, 23)), (5, 0, "TF", "FT", (2, 19)), (4, 3, "TT", "C", (5, 11)),
+             (4, 10, "T", "T", (0, 9, 17))]
 
 
 @pytest.mark.parametrize("case", range(len(TET_CASES)))
