@@ -508,10 +508,10 @@ def main():
                                                   relax_pre_coarse="F", relax_post_coarse="F",
                                                   streams=args.streams, use_graph=graph),
                                   "V(FFCF,FFCF), coarser levels V(F,F)"),
-            source_iteration_time(3, device, dict(relax_pre="TTT", relax_post="TTT",
+            source_iteration_time(3, device, dict(relax_pre="TTTTT", relax_post="TTTTT",
                                                   relax_pre_coarse="F", relax_post_coarse="F",
                                                   streams=args.streams, use_graph=graph),
-                                  "V(TTT,TTT) over centroid-box tet tiles, coarser levels V(F,F)"),
+                                  "V(TTTTT,TTTTT) over centroid-box tet tiles, coarser levels V(F,F)"),
         ]
         for r in extra["source_iteration"]:
             log("source iteration %s (%s, warm start %s): %.2f s, %d outer iterations" % (

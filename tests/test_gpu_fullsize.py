@@ -20,9 +20,9 @@ BENCH_OPTS = dict(relax_pre="TTT", relax_post="TTT", relax_pre_coarse="F", relax
                   tile_xy=16, tile_z=0, autotune=1, streams=5, batch_size=16, filter_r=1.0)
 # the same with F/C half-sweep ladders
 FC_OPTS = dict(BENCH_OPTS, relax_pre="FCFCFCFCFCFCF", relax_post="FCFCFCFCFCFCF")
-# tets: three tile sweeps over the default centroid-box tiles, as the
+# tets: five tile sweeps over the default centroid-box tiles, as the
 # benchmark's tet source iteration runs them
-TET_OPTS = dict(relax_pre="TTT", relax_post="TTT", relax_pre_coarse="F", relax_post_coarse="F",
+TET_OPTS = dict(relax_pre="TTTTT", relax_post="TTTTT", relax_pre_coarse="F", relax_post_coarse="F",
                 streams=5, batch_size=16, filter_r=1.0)
 
 
