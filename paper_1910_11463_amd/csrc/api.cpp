@@ -852,7 +852,7 @@ int pair_amg_setup(pair_amg* amg, int n_seg, const int64_t* seg_rows, int64_t n,
         }
         AmgParams p = params_from_options(amg->opt);
         PAIR_CHECK(p.relax_pre.find('T') == std::string::npos && p.relax_post.find('T') == std::string::npos,
-                   "tile sweeps (T) need the transport operator of a structured hex mesh");
+                   "tile sweeps (T) need a transport operator with its mesh (structured hexes or tets)");
         amg->H.reset(new Hierarchy(p, amg->s));
         amg->H->setup(std::move(A), off, cnt);
         amg->n_seg = n_seg;
