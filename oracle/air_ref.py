@@ -9,6 +9,9 @@ Sec. "SOC Parameter for Building R"):
 2. C/F splitting of the strength graph (PMIS, a parallel maximal-independent-set
    split; the paper uses Falgout coarsening, which on one process reduces to a
    sequential first pass, so a parallel split is used here and on the GPU);
+   as an option on the finest level, the Ruge-Stueben first pass inside given
+   row groups (``Options.cf_groups``, ``rs_first_pass``), the per-processor
+   pass of that coarsening, to study its effect on convergence;
 3. restriction R by local approximate ideal restriction (lAIR): for each
    C-point i, the F-points strongly connected to i in the R-strength sense
    (eq. soc with epsilon_R = 0.01, absolute values) form R_i, and the row
@@ -42,12 +45,18 @@ Pinned by (tests/test_oracle_air.py): the ideal-restriction identities
 one-point P; a two-level cycle with ideal R, exact F-solve and exact coarse
 solve is exact), the lAIR defining identity (R A)(i, R_i) = 0, PMIS validity
 (independence and coverage), dense R @ A @ P, and convergence of the V-cycle to
-the exact sweep answer.  Convergence *rates* are not pinned by the paper's
-numbers (parity unpinned; Table 5 only gives a sanity range).
+the exact sweep answer; the Ruge-Stueben first pass by a chain whose split is
+worked out by hand, by its invariants on random graphs (every C point's
+dependents are F, no C point depends on another, an F point either has no
+dependents or depends on a C point, the first C point has the largest
+measure) and by its groups (links between groups dropped).  Convergence
+*rates* are not pinned by the paper's numbers (parity unpinned; Table 5 only
+gives a sanity range).
 """
 from __future__ import annotations
 
 import dataclasses
+import heapq
 from typing import List, Optional
 
 import numpy as np
@@ -85,6 +94,9 @@ class Options:
     relax_post: str = "FC"     # and after it ("FFC": F, F, then C)
     filter_r: float = 0.0      # phi_R: drop R entries below phi_R * row max (0: keep all)
     nair_degree: int = 0       # > 0: nAIR restriction of this Neumann degree instead of lAIR
+    # finest level only: the Ruge-Stueben first pass inside these row groups
+    # (one group id per row) instead of PMIS; coarser levels keep PMIS
+    cf_groups: Optional[np.ndarray] = None
 
 
 def _rows(A: sp.csr_matrix):
@@ -339,6 +351,50 @@ class Level:
     P: Optional[sp.csr_matrix] = None
 
 
+def rs_first_pass(S: sp.csr_matrix, groups: Optional[np.ndarray] = None) -> np.ndarray:
+    """Ruge-Stueben first pass (the splitting the paper's Falgout coarsening runs
+    inside each processor's rows, Sec. "Weak Scaling with Parallelism in Space"):
+    cf[i] = +1 (C) / -1 (F).  With `groups`, strong links between rows of
+    different groups are dropped first (a processor sees only its own rows).
+
+    lambda_i = #{j : S[j,i]} (points strongly depending on i); points with
+    lambda_i = 0 start as F.  Repeatedly the undecided point with the largest
+    lambda (ties: the smaller index) becomes C; every undecided point that
+    strongly depends on it becomes F, and each such new F point raises by one
+    the lambda of every undecided point it strongly depends on (an F dependent
+    counts twice); the new C point lowers by one the lambda of every undecided
+    point it strongly depends on (a C point no longer counts)."""
+    n = S.shape[0]
+    S = sp.csr_matrix(S)
+    if groups is not None:
+        C = S.tocoo()
+        keep = groups[C.row] == groups[C.col]
+        S = sp.csr_matrix((np.ones(int(keep.sum()), dtype=np.int8), (C.row[keep], C.col[keep])), shape=(n, n))
+    ST = S.T.tocsr()
+    lam = np.diff(ST.indptr).astype(np.int64)
+    cf = np.zeros(n, dtype=np.int64)
+    cf[lam == 0] = -1
+    heap = [(-int(lam[i]), i) for i in range(n) if cf[i] == 0]
+    heapq.heapify(heap)
+    while heap:
+        negl, i = heapq.heappop(heap)
+        if cf[i] != 0 or -negl != lam[i]:
+            continue                       # decided, or a stale entry
+        cf[i] = 1
+        for j in ST.indices[ST.indptr[i]:ST.indptr[i + 1]]:      # j depends on i
+            if cf[j] == 0:
+                cf[j] = -1
+                for k in S.indices[S.indptr[j]:S.indptr[j + 1]]:   # j depends on k
+                    if cf[k] == 0:
+                        lam[k] += 1
+                        heapq.heappush(heap, (-int(lam[k]), int(k)))
+        for k in S.indices[S.indptr[i]:S.indptr[i + 1]]:          # i depends on k
+            if cf[k] == 0:
+                lam[k] -= 1
+                heapq.heappush(heap, (-int(lam[k]), int(k)))
+    return cf
+
+
 def setup(A: sp.csr_matrix, opts: Options = Options()) -> List[Level]:
     levels = []
     A = sp.csr_matrix(A)
@@ -350,7 +406,10 @@ def setup(A: sp.csr_matrix, opts: Options = Options()) -> List[Level]:
         if n <= opts.coarse_max or lev == opts.max_levels - 1:
             break
         S = strength(A, opts.theta)
-        cf = pmis(S, lev, opts.seed)
+        if lev == 0 and opts.cf_groups is not None:
+            cf = rs_first_pass(S, opts.cf_groups)
+        else:
+            cf = pmis(S, lev, opts.seed)
         nc = int((cf > 0).sum())
         if nc == 0 or nc > opts.max_coarse_ratio * n:
             break
