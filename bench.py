@@ -58,6 +58,10 @@ ROOFLINE_KERNELS = {
     "r_build": {
         "*": ("k_r_build (lAIR restriction rows with dense local systems, levels below the "
               "finest)", "k_r_build_hex64_s8_traffic.txt", "amg_setup.hip")},
+    "rap_merge": {
+        "*": ("k_rap_merge (Galerkin R (A P) rows of at most four R entries, merged from the "
+              "sorted rows of A P; numeric pass)", "k_rap_merge_hex64_s8_traffic.txt",
+              "amg_setup.hip")},
 }
 
 
@@ -160,7 +164,7 @@ def profile_kinds():
     import ctypes
     from paper_1910_11463_amd import binding as B
     names = ["relax_fine", "residual_fine", "restrict_fine", "relax_coarse", "norm_fine", "r_build",
-             "r_build_once", "r_pattern"]
+             "r_build_once", "r_pattern", "rap_merge"]
     out = {}
     for k, nm in enumerate(names):
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()

@@ -332,7 +332,10 @@ int pair_export_fine_operator(pair_ctx* ctx, int m, int64_t* nnz, int64_t* rowpt
  * gathered row of A counted once per launch (kind 5 counts it once per local
  * system that reads it), 7 = setup: the patterns of those restriction rows
  * (their strong F points, truncated to kmax), selected before kind 5's launches
- * solve their local systems.  Outputs: number of timed launches,
+ * solve their local systems, 8 = setup: the rows of the coarse operator R (A P)
+ * whose row of R has at most four entries, merged from the sorted rows of A P
+ * (numeric pass; bytes counted on the device per coarse row: its row of R, the
+ * rows of A P it reads, its output row).  Outputs: number of timed launches,
  * their summed duration (ms) and summed algorithmic bytes (what each launch
  * must read and write: 8 B per value, 4 B per column index, 8 B per row
  * offset; a gathered vector counted once per launch; for kind 5, counted on

@@ -574,6 +574,34 @@ __device__ __forceinline__ void r_collect(bool have, int64_t i, int64_t rs, int6
     }
 }
 
+// Cross-lane moves inside rows of 16 lanes by DPP (a VALU operand modifier, no
+// LDS round trip): 0x140 mirrors the 16 lanes, 0x141 each half of 8, 0x4E swaps
+// lane pairs 2 apart within each quad, 0xB1 neighbours.
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_int<CTRL>(static_cast<int>(b));
+    const int hi = dpp_int<CTRL>(static_cast<int>(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+// Largest v over each group of G consecutive lanes (G = 8 or 16); every lane of
+// the group ends with it.  With 16 lanes, lane l first holds the max of the pair
+// {l, 15 - l}, then of four lanes, then eight, then all sixteen (with 8, the
+// mirror of 16 is left out).  fmax skips NaN operands.
+template <int G>
+__device__ __forceinline__ double group_max_dpp(double v) {
+    static_assert(G == 8 || G == 16, "DPP groups of 8 or 16 lanes");
+    if constexpr (G == 16) v = fmax(v, dpp_double<0x140>(v));
+    v = fmax(v, dpp_double<0x141>(v));
+    v = fmax(v, dpp_double<0x4E>(v));
+    v = fmax(v, dpp_double<0xB1>(v));
+    return v;
+}
+
 // Position of column c in the sorted cols[0, K) (K <= G), or -1: a search with
 // log2(G) fixed steps (no data-dependent loop exits).
 template <int G>
@@ -588,10 +616,12 @@ __device__ __forceinline__ int col_pos(const int* cols, int K, int c) {
 }
 
 // lAIR rows, G lanes per coarse row (G = 8, 16, 32 or 64 >= the row's local system
-// size K), 64 / G rows per wave.  Local system A(R_i,R_i)^T z = -A(i,R_i)^T in
-// LDS, Gaussian elimination with partial pivoting (lane r owns row r), back
-// substitution by columns with the solution entries broadcast by shuffles.
-// Loops run to the largest K of the wave so every lane reaches every barrier.
+// size K), 64 / G rows per wave.  Local system A(R_i,R_i)^T z = -A(i,R_i)^T
+// gathered into LDS, lane r owning row r.  K <= 16: Gauss-Jordan with partial
+// pivoting on rows held in registers.  Larger K: Gaussian elimination with
+// partial pivoting in LDS, back substitution by columns with the solution
+// entries broadcast by shuffles.  Loops run to the largest K of the wave so every
+// lane reaches every barrier.
 template <int G, bool GIVEN = false>
 __global__ void __launch_bounds__(64)
 k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict__ c2f,
@@ -696,14 +726,27 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         }
         __syncthreads();
         bool sing = false;
+        // Gauss-Jordan with partial pivoting, lane r owning row r: at step p the
+        // pivot row is swapped into row p and column p is removed from every other
+        // row, those above p included (in lockstep that costs nothing over the
+        // rows below), so after K steps row r holds only its diagonal entry and
+        // z_r is one division, with no back substitution.
         for (int p = 0; p < Kw; ++p) {
             const bool act = p < K && !sing;
             double v = (act && sub >= p && sub < K) ? fabs(Mloc[g][sub * LD + p]) : -1.0;
             int idx = sub;
-            for (int d = G / 2; d >= 1; d >>= 1) {
-                double ov = __shfl_xor(v, d, 64);
-                int oi = __shfl_xor(idx, d, 64);
-                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+            if constexpr (G <= 16) {
+                // the group's largest |entry|, then its first row holding it
+                const double vmax = group_max_dpp<G>(v);
+                const uint64_t hit = __ballot(v == vmax) & gmask;
+                idx = __ffsll(static_cast<unsigned long long>(hit >> (lane & ~(G - 1)))) - 1;
+                v = vmax;
+            } else {
+                for (int d = G / 2; d >= 1; d >>= 1) {
+                    double ov = __shfl_xor(v, d, 64);
+                    int oi = __shfl_xor(idx, d, 64);
+                    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+                }
             }
             if (act && !(v > 0.0)) sing = true;
             const bool go = act && !sing;
@@ -720,22 +763,19 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
             // every lane runs the wave's trip count; lanes with nothing to
             // eliminate use l = 0 (rows and columns beyond K are zero, so they
             // stay unchanged)
-            const bool upd = go && sub > p && sub < K;
-            const double l = upd ? Mloc[g][sub * LD + p] / Mloc[g][p * LD + p] : 0.0;
+            const bool upd = go && sub != p && sub < K;
+            // multiplier = entry times the pivot's reciprocal (hardware estimate and
+            // two Newton steps), as LAPACK scales a column by 1 / pivot
+            const double d = Mloc[g][p * LD + p];
+            double rinv = __builtin_amdgcn_rcp(d);
+            rinv = fma(fma(-d, rinv, 1.0), rinv, rinv);
+            rinv = fma(fma(-d, rinv, 1.0), rinv, rinv);
+            const double l = upd ? Mloc[g][sub * LD + p] * rinv : 0.0;
             for (int c = p + 1; c < Kw; ++c) Mloc[g][sub * LD + c] -= l * Mloc[g][p * LD + c];
             rhs[g][sub] -= l * rhs[g][p];
             __syncthreads();
         }
-        // back substitution by columns: lane r finishes z_r, every lane above
-        // removes its multiple from its own right-hand side
-        const int gl = lane & ~(G - 1);
-        double rr = sub < K ? rhs[g][sub] : 0.0;
-        double zr = 0.0;
-        for (int r = Kw - 1; r >= 0; --r) {
-            if (!sing && r < K && sub == r) zr = rr / Mloc[g][r * LD + r];
-            const double zb = __shfl(zr, gl + r, 64);
-            if (!sing && r < K && sub < r) rr -= Mloc[g][sub * LD + r] * zb;
-        }
+        const double zr = (!sing && sub < K) ? rhs[g][sub] / Mloc[g][sub * LD + sub] : 0.0;
         if (have && sing && sub == 0) atomicAdd(singular, 1);
         if (have) {
             const int64_t rb = r_rowptr[I];
@@ -1870,7 +1910,10 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
 // block: when the wave's rows are consecutive (their output is one contiguous
 // range) and the range fits kMergeStage entries, the rows are merged into LDS
 // and the range is written out by the whole wave, coalesced; otherwise each
-// thread writes its row directly.
+// thread writes its row directly.  With pbytes (numeric pass, profiling) each
+// row adds its algorithmic bytes: the list entry, its two row offsets in R, its
+// row of R, per entry of R the row's offset and length in A P and that row of
+// A P, its output offset and its row of R A P (12 B per column and value).
 constexpr int kMergeR = 4;
 // entries of each list held in registers (numeric pass: columns and values)
 template <bool NUMERIC>
@@ -1884,7 +1927,8 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
             const int64_t* __restrict__ rowptr, const int* __restrict__ ap_len,
             const int32_t* __restrict__ ap_col, const double* __restrict__ ap_val,
             int64_t* __restrict__ cnt_out, const int64_t* __restrict__ c_rowptr,
-            int32_t* __restrict__ c_col, double* __restrict__ c_val) {
+            int32_t* __restrict__ c_col, double* __restrict__ c_val,
+            unsigned long long* __restrict__ pbytes) {
     constexpr int kMergePB = merge_pb<NUMERIC>();
     constexpr int32_t kEnd = 0x7fffffff;
     __shared__ int32_t s_col[NUMERIC ? kMergeStage : 1];
@@ -1907,6 +1951,7 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
             staged = hi - lo <= kMergeStage;
         }
     }
+    unsigned long long rbytes = 0;
     if (have) {
         const int64_t rs = r_rowptr[I];
         const int rl = static_cast<int>(r_rowptr[I + 1] - rs);   // <= kMergeR
@@ -1939,8 +1984,10 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
                 end[t] = pos[t] + ap_len[k];
                 rv[t] = r_val[rs + t];
             }
+            rbytes += 24ull + 12ull * static_cast<unsigned long long>(end[t] - pos[t]);
             refill(t);
         }
+        rbytes = 28ull + rbytes - 24ull * (kMergeR - rl);
         const int64_t ob = NUMERIC ? c_rowptr[I] : 0;
         int64_t n = 0;
         while (true) {
@@ -1973,6 +2020,11 @@ k_rap_merge(int nrows, const int32_t* __restrict__ list, const int64_t* __restri
             ++n;
         }
         if (!NUMERIC) cnt_out[I] = n;
+        rbytes += 12ull * static_cast<unsigned long long>(n);
+    }
+    if (NUMERIC && pbytes) {
+        for (int d = 32; d >= 1; d >>= 1) rbytes += __shfl_xor(rbytes, d, 64);
+        if (threadIdx.x == 0 && rbytes) atomicAdd(pbytes + (blockIdx.x % kProfSubSlots), rbytes);
     }
     if (NUMERIC) {
         __syncthreads();
@@ -2756,12 +2808,15 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 #define PAIR_RAP_ARGS(c) lcount[c], lists[c].p, L.R.rowptr.p, L.R.col.p, L.R.val.p, L.A.rowptr.p, \
                          ap_len.p, ap_col.p, ap_val.p
             if (lcount[0] > 0) {
-                if (numeric)
+                if (numeric) {
+                    const int ph = prof_begin(s_, PROF_RAP_MERGE);
                     hipLaunchKernelGGL(k_rap_merge<true>, dim3(grid_for(lcount[0], 64)), dim3(64), 0, s_,
-                                       PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval);
-                else
+                                       PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval, prof_dev_bytes(ph));
+                    prof_end_dev(s_, ph);
+                } else {
                     hipLaunchKernelGGL(k_rap_merge<false>, dim3(grid_for(lcount[0], 256)), dim3(256), 0,
-                                       s_, PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval);
+                                       s_, PAIR_RAP_ARGS(0), cnt_out, crp, ccol, cval, nullptr);
+                }
             }
             if (numeric) {
                 if (lcount[1] > 0)

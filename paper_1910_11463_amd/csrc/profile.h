@@ -27,7 +27,8 @@ enum ProfKind : int {
     PROF_RBUILD = 5,         // lAIR rows with dense local systems (coarser levels' setup)
     PROF_RBUILD_ONCE = 6,    // the same launches, a gathered row of A counted once per launch
     PROF_RPATTERN = 7,       // the lAIR rows' patterns selected before their local systems
-    PROF_NKINDS = 8
+    PROF_RAP_MERGE = 8,      // R (A P) rows of at most four R entries, by merging (numeric pass)
+    PROF_NKINDS = 9
 };
 
 bool prof_enabled();

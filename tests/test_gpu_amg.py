@@ -307,6 +307,48 @@ def test_r_build_byte_count_matches_host_count():
     g.close()
 
 
+def test_rap_merge_byte_count_matches_host_count():
+    """The algorithmic bytes the merging R (A P) kernel adds up on the device
+    (a candidate for the benchmark's roofline kernel) equal the per-row formula
+    evaluated on the host from the hierarchy it built: for every coarse row I
+    whose row of R has rl <= 4 entries, 28 (list entry, two offsets in R, the
+    output offset) + sum over its R entries k of (24 + 12 len_AP(k)) + 12 nnz of
+    row I of the next level's operator, where len_AP(k) counts the distinct
+    coarse points that the columns of row k of A interpolate from (one-point
+    P)."""
+    need_gpu()
+    import ctypes
+    A, _ = _matrix(2, 8, 5)
+    B.check(B.pair_profile_enable(1))
+    g = _amg(A, 64, 3)
+    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    B.check(B.pair_profile_read(8, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    B.check(B.pair_profile_enable(0))
+    want = 0
+    for l in range(g.num_levels() - 1):
+        lv, nx = g.level(l), g.level(l + 1)
+        rp, col, p, rr, rc = lv["rowptr"], lv["col"], lv["p"], lv["r_rowptr"], lv["r_col"]
+        if rr is None:
+            continue
+        ap_len = {}
+        clen = np.diff(nx["rowptr"])
+        for I in range(len(rr) - 1):
+            ks = rc[rr[I]:rr[I + 1]]
+            if len(ks) > 4:
+                continue
+            row = 28 + 12 * int(clen[I])
+            for k in ks:
+                if k not in ap_len:
+                    pk = p[col[rp[k]:rp[k + 1]]]
+                    ap_len[k] = len(np.unique(pk[pk >= 0]))
+                row += 24 + 12 * ap_len[k]
+            want += row
+    print("rap_merge launches", n.value, "bytes", by.value, "host", want, flush=True)
+    assert n.value > 0 and ms.value > 0.0
+    assert int(by.value) == want
+    g.close()
+
+
 def test_nair_rows_with_many_neighbours_match_reference():
     """nAIR rows with more F neighbours than the medium kernel holds (about 120
     per row here, above its 96) are finished by the large kernel: a random
