@@ -1915,10 +1915,16 @@ k_rap_num(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict
 // row of R, per entry of R the row's offset and length in A P and that row of
 // A P, its output offset and its row of R A P (12 B per column and value).
 constexpr int kMergeR = 4;
-// entries of each list held in registers (numeric pass: columns and values)
+// Entries of each list held in registers (numeric pass: columns and values),
+// loaded together on each refill, so that most of a line of a row of A P is
+// used before the caches drop it.  The numeric pass is LDS-bound by its
+// staging (18 KB per one-wave block, about two waves per SIMD), so its
+// registers go to these refills (four at a time: 708 us per launch of the
+// 64^3 S8 benchmark alone; twelve with 1536 staged entries: 523 us; the
+// symbolic pass 198 -> 167 us from eight to twelve).
 template <bool NUMERIC>
-constexpr int merge_pb() { return NUMERIC ? 4 : 8; }
-constexpr int kMergeStage = 2048;
+constexpr int merge_pb() { return 12; }
+constexpr int kMergeStage = 1536;
 
 template <bool NUMERIC>
 __global__ void __launch_bounds__(NUMERIC ? 64 : 256)
