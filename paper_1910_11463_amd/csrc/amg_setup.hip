@@ -622,7 +622,7 @@ __device__ __forceinline__ int col_pos(const int* cols, int K, int c) {
 // partial pivoting in LDS, back substitution by columns with the solution
 // entries broadcast by shuffles.  Loops run to the largest K of the wave so every
 // lane reaches every barrier.
-template <int G, bool GIVEN = false>
+template <int G, bool GIVEN = false, int KM = G>
 __global__ void __launch_bounds__(64)
 k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict__ c2f,
           const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -630,9 +630,13 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
           const int8_t* __restrict__ cf, int kmax, const int64_t* __restrict__ r_rowptr,
           int32_t* __restrict__ r_col, double* __restrict__ r_val, int* __restrict__ singular,
           unsigned long long* __restrict__ pbytes) {
+    // KM: the largest local system of the launch's rows (the host's size
+    // classes guarantee K <= KM); the dense systems take KM x (KM + 1) doubles
+    // of LDS each, which sets the occupancy
+    static_assert(KM <= G, "a local system's rows are owned by lanes of its group");
     constexpr int RPW = 64 / G;
-    constexpr int LD = G + 1;
-    __shared__ double Mloc[RPW][G * LD];
+    constexpr int LD = KM + 1;
+    __shared__ double Mloc[RPW][KM * LD];
     __shared__ double rhs[RPW][G];
     __shared__ int cols[RPW][G];
     __shared__ int kw[RPW];
@@ -666,7 +670,8 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         __syncthreads();
         int Kw = 0;
         for (int q = 0; q < RPW; ++q) Kw = max(Kw, kw[q]);
-        for (int r = 0; r < G; ++r) Mloc[g][r * LD + sub] = 0.0;
+        if (sub < KM)
+            for (int r = 0; r < KM; ++r) Mloc[g][r * LD + sub] = 0.0;
         rhs[g][sub] = 0.0;
         // rows cols[c] of A (lane c): start, and the prefix of their lengths
         int64_t myb = 0;
@@ -771,7 +776,8 @@ k_r_build(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
             rinv = fma(fma(-d, rinv, 1.0), rinv, rinv);
             rinv = fma(fma(-d, rinv, 1.0), rinv, rinv);
             const double l = upd ? Mloc[g][sub * LD + p] * rinv : 0.0;
-            for (int c = p + 1; c < Kw; ++c) Mloc[g][sub * LD + c] -= l * Mloc[g][p * LD + c];
+            if (sub < KM)
+                for (int c = p + 1; c < Kw; ++c) Mloc[g][sub * LD + c] -= l * Mloc[g][p * LD + c];
             rhs[g][sub] -= l * rhs[g][p];
             __syncthreads();
         }
@@ -2662,15 +2668,19 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                                          (static_cast<double>(L.A.nnz) / static_cast<double>(std::max<int64_t>(1, n))));
                 PAIR_LAUNCH_CHECK();
             }
-            DBuf<int32_t> rl[4];
-            int nrc[4];
+            // size classes K <= 8, 9-12, 13-16, 17-32, 33-64: 8, 16, 16, 32, 64 lanes per
+            // system (the 9-12 class with LDS for 12 unknowns: ~6 waves per SIMD
+            // instead of ~3.75)
+            DBuf<int32_t> rl[5];
+            int nrc[5];
             DBuf<int> rsing(1);
             PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
-            classify<4>(total_c, 1, L.R.rowptr.p, nullptr, {8, 16, 32}, rl, nrc, s_);
-            for (int c = 0; c < 4; ++c) {
+            classify<5>(total_c, 1, L.R.rowptr.p, nullptr, {8, 12, 16, 32}, rl, nrc, s_);
+            for (int c = 0; c < 5; ++c) {
                 const int nr = nrc[c];
                 if (nr == 0) continue;
-                const int rpw = 8 >> c;
+                constexpr int kRowsPerWave[5] = {8, 4, 4, 2, 1};
+                const int rpw = kRowsPerWave[c];
                 const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
                 const int ph1 = prof_begin(s_, PROF_RBUILD_ONCE);
                 const int ph = prof_begin(s_, PROF_RBUILD);
@@ -2678,8 +2688,9 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
 #define PAIR_RB_ARGS nr, rl[c].p, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, sflag.p, L.cf.p, prm_.kmax, \
                      L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p, pb
                 if (c == 0) hipLaunchKernelGGL((k_r_build<8, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
-                else if (c == 1) hipLaunchKernelGGL((k_r_build<16, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
-                else if (c == 2) hipLaunchKernelGGL((k_r_build<32, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 1) hipLaunchKernelGGL((k_r_build<16, true, 12>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 2) hipLaunchKernelGGL((k_r_build<16, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 3) hipLaunchKernelGGL((k_r_build<32, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
                 else hipLaunchKernelGGL((k_r_build<64, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
 #undef PAIR_RB_ARGS
                 prof_end_dev(s_, ph);
