@@ -69,11 +69,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# A closed solver hands its device memory back (tens of GB for the 64^3 S8
+# hierarchies), and the driver clears freed device memory in the background; a
+# solver timed right after another one was closed shares the GPU with that
+# clearing (measured: the 64^3 S8 source iteration took 1.3-1.4 s with a pause
+# before it and 2.7-4.0 s back to back).  So a new solver is made only
+# SETTLE_S seconds after the last close (outside every timed region).
+SETTLE_S = 3.0
+_last_close = [None]
+
+
+def close_solver(s):
+    import torch
+    s.close()
+    torch.cuda.synchronize()
+    _last_close[0] = time.perf_counter()
+
+
 def make_solver(w, batch_size, device, **opts):
     """A Solver on workload w with the benchmark's defaults (tol 1e-8,
     hierarchies kept, lanes per row autotuned), overridden by opts."""
     import torch
     from paper_1910_11463_amd.solver import Solver
+    if _last_close[0] is not None:
+        wait = SETTLE_S - (time.perf_counter() - _last_close[0])
+        if wait > 0:
+            time.sleep(wait)
     kw = dict(tol_inner=1e-8, max_inner=100, keep_hierarchy=1, batch_size=batch_size, autotune=1)
     kw.update(opts)
     s = Solver(**kw)
@@ -283,7 +304,7 @@ def entry(w, mode, batch_size, device, opts, warmup=1, warm=True, setup=False, p
         torch.cuda.synchronize()
         ssec = time.perf_counter() - t0
         out.update({"setup_only_s": ssec, "setup_only_dof_dirs_per_s": N * M / ssec})
-    s.close()
+    close_solver(s)
     return out
 
 
@@ -303,7 +324,7 @@ def source_iteration_time(cfg, device, opts, label):
     _, _, st, rc = s.solve(mode=B.PAIR_BATCHED, device=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    s.close()
+    close_solver(s)
     return {"workload": w.name, "schedule": label, "warm_start": bool(opts.get("warm_start", 0)),
             "seconds": dt, "outer_iters": st["outer_iters"], "vcycles_total": st["vcycles_total"],
             "converged": rc == B.PAIR_OK, "tol_inner": 1e-9, "tol_outer": 1e-8,
@@ -336,7 +357,7 @@ def adjoint_time(device, opts):
     gt, gs, _, ast, rc2 = s.adjoint(cg, mode=B.PAIR_BATCHED)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    s.close()
+    close_solver(s)
     return {"workload": w.name, "forward_s": t1 - t0, "adjoint_s": t2 - t1, "gradient_s": t2 - t0,
             "forward_outer_iters": st["outer_iters"], "adjoint_outer_iters": ast["outer_iters"],
             "elements": w.mesh.n_elem, "converged": rc == B.PAIR_OK and rc2 == B.PAIR_OK,
@@ -433,7 +454,7 @@ def main():
     torch.cuda.synchronize()
     ssec = time.perf_counter() - t0
     extra["setup_only"] = {"s": ssec, "dof_dirs_per_s": N * M / ssec}
-    s.close()
+    close_solver(s)
     # the roofline kernel: the event-timed kind with the largest summed duration
     dom = max(ROOFLINE_KERNELS, key=lambda k: prof[k]["ms"])
     if not args.no_extra:
@@ -454,7 +475,7 @@ def main():
                 "achieved": once["bytes"] / (iso["ms"] * 1e-3) / 1e9 if iso["ms"] > 0 else 0.0,
                 "frac": once["bytes"] / (iso["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS if iso["ms"] > 0 else 0.0,
                 "bytes_per_launch": once["bytes"] / max(1, once["launches"])}
-        s1.close()
+        close_solver(s1)
         # the other mode on the same workload
         other = B.PAIR_BATCHED if mode == B.PAIR_PLAIN else B.PAIR_PLAIN
         extra["other_mode"] = entry(w, other, args.batch_size, device,
@@ -477,7 +498,7 @@ def main():
                                 "vcycles_total": cst["vcycles_total"],
                                 "phi_rel_diff_vs_fp64": float(torch.linalg.norm(phi32 - phi64) /
                                                               torch.linalg.norm(phi64))}
-        s3.close()
+        close_solver(s3)
         # F/C half-sweep ladders instead of tile sweeps on the finest level
         extra["fc_ladders"] = entry(w, mode, args.batch_size, device,
                                     dict(head, relax_pre=FC_LADDER, relax_post=FC_LADDER, use_graph=0))
