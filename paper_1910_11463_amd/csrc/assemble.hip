@@ -584,6 +584,28 @@ __global__ void k_set_last(int64_t* rowptr, int64_t n, int64_t v) { rowptr[n] = 
 // interpolant on the face (F_f the face mass matrix).  Hex faces: F_f from the
 // reference element; unit normals +-e_axis.  Tet faces: F_f = area (1 + delta)/12
 // on the three face nodes with area = |nvec|/2 and Omega.n area = (Omega.nvec)/2.
+// One hex face of axis AX.  The face mass matrix of the reference element is
+// exactly zero in the rows and columns of the four nodes off the face (each such
+// entry has a basis factor that vanishes on it), so the product runs over all
+// 8 x 8 entries: the same sums, with every index known at compile time (a node
+// set chosen at run time made the compiler index f through scratch memory).
+template <int AX>
+__device__ __forceinline__ void hex_inflow_axis(int64_t id, int64_t nd, double om_ax, const double* __restrict__ fref,
+                                                const double* g, double* f) {
+    if (fabs(om_ax) <= kZeroFluxTol) return;
+    const int side = om_ax > 0.0 ? 0 : 1;          // the face Omega enters through
+    if (side == 0 ? id != 0 : id != nd - 1) return;
+    const double odn = -fabs(om_ax);
+    const double* F = fref + (2 * AX + side) * 64;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s += F[a * 8 + c] * g[c];
+        f[a] -= odn * s;
+    }
+}
+
 template <int K>
 __device__ __forceinline__ void add_inflow(int64_t e, const double om[3], const double* __restrict__ g,
                                            int nx, int ny, int nz, const double* __restrict__ fref,
@@ -591,25 +613,9 @@ __device__ __forceinline__ void add_inflow(int64_t e, const double om[3], const 
                                            const double* __restrict__ nvec, double f[K]) {
     if constexpr (K == 8) {
         const int64_t ei = e % nx, ej = (e / nx) % ny, ek = e / (static_cast<int64_t>(nx) * ny);
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            if (fabs(om[ax]) <= kZeroFluxTol) continue;
-            const int side = om[ax] > 0.0 ? 0 : 1;          // the face Omega enters through
-            const int64_t id = ax == 0 ? ei : (ax == 1 ? ej : ek);
-            const int64_t nd = ax == 0 ? nx : (ax == 1 ? ny : nz);
-            if (side == 0 ? id != 0 : id != nd - 1) continue;
-            const double odn = -fabs(om[ax]);
-            const double* F = fref + (2 * ax + side) * 64;
-#pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                if (((a >> ax) & 1) != side) continue;
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (((c >> ax) & 1) == side) s += F[a * 8 + c] * g[c];
-                f[a] -= odn * s;
-            }
-        }
+        hex_inflow_axis<0>(ei, nx, om[0], fref, g, f);
+        hex_inflow_axis<1>(ej, ny, om[1], fref, g, f);
+        hex_inflow_axis<2>(ek, nz, om[2], fref, g, f);
     } else {
 #pragma unroll
         for (int fc = 0; fc < 4; ++fc) {
@@ -629,8 +635,11 @@ __device__ __forceinline__ void add_inflow(int64_t e, const double om[3], const 
     }
 }
 
-template <int K>
-__global__ void k_rhs(int64_t E, int B, const int* __restrict__ dirs, const double* __restrict__ dinv,
+// INFLOW: the inflow term is compiled in (launched only when inflow data are
+// set, so the vacuum case keeps the smaller register footprint).
+template <int K, bool INFLOW>
+__global__ void __launch_bounds__(128)
+k_rhs(int64_t E, int B, const int* __restrict__ dirs, const double* __restrict__ dinv,
                       const double* __restrict__ mref, const double* __restrict__ mass,
                       const double* __restrict__ sigs, const double* __restrict__ q,
                       const double* __restrict__ phi, const double* __restrict__ ext,
@@ -657,7 +666,7 @@ __global__ void k_rhs(int64_t E, int B, const int* __restrict__ dirs, const doub
         f[a] = s / kFourPi;
         if (ext) f[a] += ext_per_dir ? ext[static_cast<int64_t>(dirs[b]) * N + e * K + a] : ext[e * K + a];
     }
-    if (inflow) {
+    if constexpr (INFLOW) {
         const int m = dirs[b];
         const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
         double gv[K];
@@ -716,9 +725,12 @@ __global__ void k_diff_final(const double* __restrict__ partial, double* __restr
 }
 
 // dJ/dsigma_t,e = -sum_m w_m x_{m,e}^T M_e psi_{m,e},  x_m = psi_adj[refl[m]];
-// dJ/dsigma_s,e = phi_adj_e^T M_e phi_e / (4 pi).
+// dJ/dsigma_s,e = phi_adj_e^T M_e phi_e / (4 pi).  128-thread blocks: the bound
+// lets the element's mass matrix stay in registers over the directions (with
+// the default bound of 1024 threads it spilled to scratch).
 template <int K>
-__global__ void k_adjoint_contract(int64_t E, int M, const double* __restrict__ w,
+__global__ void __launch_bounds__(128)
+k_adjoint_contract(int64_t E, int M, const double* __restrict__ w,
                                    const int* __restrict__ refl, const double* __restrict__ mref,
                                    const double* __restrict__ mass, const double* __restrict__ psi,
                                    const double* __restrict__ psia, const double* __restrict__ phi,
@@ -822,14 +834,23 @@ void rhs_kernel(const DeviceMesh& m, int B, const int* dirs_d, const double* din
                 const double* sigs, const double* q, const double* phi, const double* ext,
                 bool ext_per_dir, const double* inflow, const double* omega_d, int64_t /*N*/,
                 double* out, hipStream_t s) {
-    if (m.kind == kHexMesh)
-        hipLaunchKernelGGL(k_rhs<8>, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, B, dirs_d,
-                           dinv, m.ref.p + REF_M, nullptr, sigs, q, phi, ext, ext_per_dir ? 1 : 0,
-                           inflow, omega_d, m.nx, m.ny, m.nz, m.ref.p + REF_F, nullptr, nullptr, out);
-    else
-        hipLaunchKernelGGL(k_rhs<4>, dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, B, dirs_d,
-                           dinv, nullptr, m.mass.p, sigs, q, phi, ext, ext_per_dir ? 1 : 0, inflow,
-                           omega_d, 0, 0, 0, nullptr, m.nbr.p, m.nvec.p, out);
+#define PAIR_RHS_HEX(FLOW)                                                                         \
+    hipLaunchKernelGGL((k_rhs<8, FLOW>), dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, B, dirs_d, \
+                       dinv, m.ref.p + REF_M, nullptr, sigs, q, phi, ext, ext_per_dir ? 1 : 0, inflow,    \
+                       omega_d, m.nx, m.ny, m.nz, m.ref.p + REF_F, nullptr, nullptr, out)
+#define PAIR_RHS_TET(FLOW)                                                                         \
+    hipLaunchKernelGGL((k_rhs<4, FLOW>), dim3(grid_for(m.E * B, 128)), dim3(128), 0, s, m.E, B, dirs_d, \
+                       dinv, nullptr, m.mass.p, sigs, q, phi, ext, ext_per_dir ? 1 : 0, inflow, omega_d, \
+                       0, 0, 0, nullptr, m.nbr.p, m.nvec.p, out)
+    if (m.kind == kHexMesh) {
+        if (inflow) PAIR_RHS_HEX(true);
+        else PAIR_RHS_HEX(false);
+    } else {
+        if (inflow) PAIR_RHS_TET(true);
+        else PAIR_RHS_TET(false);
+    }
+#undef PAIR_RHS_HEX
+#undef PAIR_RHS_TET
     PAIR_LAUNCH_CHECK();
 }
 
