@@ -2668,18 +2668,18 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                                          (static_cast<double>(L.A.nnz) / static_cast<double>(std::max<int64_t>(1, n))));
                 PAIR_LAUNCH_CHECK();
             }
-            // size classes K <= 8, 9-12, 13-16, 17-32, 33-64: 8, 16, 16, 32, 64 lanes per
-            // system (the 9-12 class with LDS for 12 unknowns: ~6 waves per SIMD
-            // instead of ~3.75)
-            DBuf<int32_t> rl[5];
-            int nrc[5];
+            // size classes K <= 8, 9-12, 13-14, 15-16, 17-32, 33-64: 8, 16, 16, 16, 32,
+            // 64 lanes per system, the 16-lane classes with LDS for 12, 14 and 16
+            // unknowns (~6, ~4.75 and ~3.75 waves per SIMD)
+            DBuf<int32_t> rl[6];
+            int nrc[6];
             DBuf<int> rsing(1);
             PAIR_HIP(hipMemsetAsync(rsing.p, 0, sizeof(int), s_));
-            classify<5>(total_c, 1, L.R.rowptr.p, nullptr, {8, 12, 16, 32}, rl, nrc, s_);
-            for (int c = 0; c < 5; ++c) {
+            classify<6>(total_c, 1, L.R.rowptr.p, nullptr, {8, 12, 14, 16, 32}, rl, nrc, s_);
+            for (int c = 0; c < 6; ++c) {
                 const int nr = nrc[c];
                 if (nr == 0) continue;
-                constexpr int kRowsPerWave[5] = {8, 4, 4, 2, 1};
+                constexpr int kRowsPerWave[6] = {8, 4, 4, 4, 2, 1};
                 const int rpw = kRowsPerWave[c];
                 const unsigned g = static_cast<unsigned>(std::min<int64_t>((nr + rpw - 1) / rpw, 1 << 20));
                 const int ph1 = prof_begin(s_, PROF_RBUILD_ONCE);
@@ -2689,8 +2689,9 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
                      L.R.rowptr.p, L.R.col.p, L.R.val.p, rsing.p, pb
                 if (c == 0) hipLaunchKernelGGL((k_r_build<8, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
                 else if (c == 1) hipLaunchKernelGGL((k_r_build<16, true, 12>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
-                else if (c == 2) hipLaunchKernelGGL((k_r_build<16, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
-                else if (c == 3) hipLaunchKernelGGL((k_r_build<32, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 2) hipLaunchKernelGGL((k_r_build<16, true, 14>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 3) hipLaunchKernelGGL((k_r_build<16, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
+                else if (c == 4) hipLaunchKernelGGL((k_r_build<32, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
                 else hipLaunchKernelGGL((k_r_build<64, true>), dim3(g), dim3(64), 0, s_, PAIR_RB_ARGS);
 #undef PAIR_RB_ARGS
                 prof_end_dev(s_, ph);
