@@ -730,6 +730,27 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
     const int64_t cstep = static_cast<int64_t>(dk) * nxy;
     HexDen den = hex_den(lane && wz > 0 ? sigt[cbase] : 0.0, dr);
     double sig_n = lane && wz > 1 ? sigt[cbase + cstep] : 0.0;
+    // b of the column's next element and, for the lanes on the box's inflow
+    // sides, the face values of its x- and y-upwind neighbours outside the box:
+    // loaded at the end of a step (after its stores), first used after the next
+    // step's barrier
+    double bv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double ox[4] = {0.0, 0.0, 0.0, 0.0}, oy[4] = {0.0, 0.0, 0.0, 0.0};
+    auto load_next = [&](int64_t gn) {
+        load8(b + gn * 8, bv);
+        if (outx) {
+            const double* xu = xin + (gn + (sx ? 1 : -1)) * 8 + (1 - sx);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ox[q] = xu[2 * q];
+        }
+        if (outy) {
+            const double2* xu = reinterpret_cast<const double2*>(
+                xin + (gn + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
+            const double2 lo = xu[0], hi = xu[2];
+            oy[0] = lo.x; oy[1] = lo.y; oy[2] = hi.x; oy[3] = hi.y;
+        }
+    };
+    if (lane && wz > 0) load_next(col + static_cast<int64_t>(kfirst) * nxy);
     for (int s = 0; s < nsteps; ++s) {
         const int kp = s - ip - jp;
         const int p = s & 1;
@@ -741,9 +762,8 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v0[q] = sh[p ^ 1][(1 - sx) + 2 * q][tid - 1];
             } else if (outx) {
-                const double* xu = xin + (g + (sx ? 1 : -1)) * 8 + (1 - sx);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v0[q] = xu[2 * q];
+                for (int q = 0; q < 4; ++q) v0[q] = ox[q];
             } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v0[q] = 0.0;
@@ -752,10 +772,8 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v1[q] = sh[p ^ 1][2 * (1 - sy) + (q & 1) + 4 * (q >> 1)][tid - TXY];
             } else if (outy) {
-                const double2* xu = reinterpret_cast<const double2*>(
-                    xin + (g + (sy ? nx : -static_cast<int64_t>(nx))) * 8 + 2 * (1 - sy));
-                const double2 lo = xu[0], hi = xu[2];
-                v1[0] = lo.x; v1[1] = lo.y; v1[2] = hi.x; v1[3] = hi.y;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v1[q] = oy[q];
             } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v1[q] = 0.0;
@@ -771,10 +789,8 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v2[q] = 0.0;
             }
-            double bv[8], y[8], xn[8];
-            load8(b + g * 8, bv);
+            double y[8], xn[8];
             const HexDen den_n = hex_den(sig_n, dr);
-            sig_n = kp + 2 < wz ? sigt[cbase + (kp + 2) * cstep] : 0.0;
             hex_face_solve_den(den, dr, v0, v1, v2, y);
             den = den_n;
 #pragma unroll
@@ -797,6 +813,8 @@ k_hex_tile(uint32_t E, int nx, int ny, int nz, int tz, int mx, int my, int mz,
             for (int a = 0; a < 8; ++a) sh[p][a][tid] = xn[a];
 #pragma unroll
             for (int q = 0; q < 4; ++q) zf[q] = xn[4 * (1 - sz) + q];
+            if (kp + 1 < wz) load_next(g + cstep);
+            sig_n = kp + 2 < wz ? sigt[cbase + (kp + 2) * cstep] : 0.0;
         }
         __syncthreads();
     }
