@@ -41,7 +41,10 @@ constexpr uint64_t KEY_NONE = ~0ull;
 
 // Fused per-row pass, G lanes per row: 1/a_ii, max_{k != i}|a_ik|, strength
 // flags of every entry and lambda (number of rows strongly depending on a column).
-constexpr int kStrengthPerLane = 4;   // entries per lane held in registers for short rows
+// entries per lane held in registers for short rows: 8 (32 per row) covers the
+// coarse levels' rows, which with 4 (16 per row) were read twice (64^3 S8
+// benchmark, first coarse level: 1.73 -> 1.13 ms per launch)
+constexpr int kStrengthPerLane = 8;
 
 template <int G>
 __global__ void __launch_bounds__(256)
