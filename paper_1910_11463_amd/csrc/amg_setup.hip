@@ -24,6 +24,7 @@
 #include <array>
 #include <cmath>
 #include <numeric>
+#include <type_traits>
 
 #include "amg.h"
 #include "kernels_common.h"
@@ -1541,10 +1542,46 @@ __device__ __forceinline__ void block_count(bool flag, int* s_red, int& before, 
     __syncthreads();
 }
 
+// DPP moves with a fallback value: lanes whose source lies outside their row of
+// 16 lanes (the row shifts 0x101-0x10F left, 0x111-0x11F right) keep `old`.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t old, uint64_t x) {
+    const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(old), static_cast<int>(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(old >> 32), static_cast<int>(x >> 32), CTRL, 0xF,
+                                               0xF, false);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double old, double x) {
+    return __longlong_as_double(static_cast<long long>(
+        dpp_u64<CTRL>(static_cast<uint64_t>(__double_as_longlong(old)), static_cast<uint64_t>(__double_as_longlong(x)))));
+}
+// Compare-exchange with the partner lane the DPP pattern CTRL names (within the
+// lane's row of 16): the lane whose index has bit BIT clear keeps the minimum.
+template <int CTRL, int BIT>
+__device__ __forceinline__ void cmpx_dpp(uint64_t& key, int sub) {
+    const uint64_t o = dpp_u64<CTRL>(key, key);
+    key = (sub & BIT) == 0 ? (key < o ? key : o) : (key > o ? key : o);
+}
+// The same with the lane's partner at index ^ 4 (ds_swizzle, bit mode: lanes
+// of each 32 exchange by xor 4).
+__device__ __forceinline__ void cmpx_xor4(uint64_t& key, int sub) {
+    constexpr int kSwz = 0x1F | (4 << 10);
+    const int lo = __builtin_amdgcn_ds_swizzle(static_cast<int>(key), kSwz);
+    const int hi = __builtin_amdgcn_ds_swizzle(static_cast<int>(key >> 32), kSwz);
+    const uint64_t o = (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+    key = (sub & 4) == 0 ? (key < o ? key : o) : (key > o ? key : o);
+}
+
 // Rows of A with at most G entries (every finest-level row fits G = 32): G
-// lanes per row, keys sorted in registers with a shuffle bitonic network, each
-// run of equal coarse columns summed by a segmented scan in a fixed tree order
-// (reproducible; a row always takes the same kernel, whatever the batch).
+// lanes per row, keys sorted in registers with a bitonic network, each run of
+// equal coarse columns summed by a segmented scan in a fixed tree order
+// (reproducible; a row always takes the same kernel, whatever the batch).  With
+// G = 16 a row is one DPP row of lanes: the network is the form in which each
+// merge starts by comparing mirror images (partners i ^ 1, i ^ 3, i ^ 7, i ^ 15,
+// all DPP patterns) followed by half-cleaners (i ^ 4 by ds_swizzle, i ^ 2 and
+// i ^ 1 by DPP), and the scan's shifts are DPP row shifts; wider rows use
+// ds_bpermute shuffles.
 template <int G>
 __global__ void __launch_bounds__(256)
 k_ap_reg(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict__ rowptr,
@@ -1567,30 +1604,66 @@ k_ap_reg(int nrows, const int32_t* __restrict__ list, const int64_t* __restrict_
         v = val[rs + sub];
         if (c >= 0) key = (static_cast<uint64_t>(static_cast<uint32_t>(c)) << 32) | static_cast<uint32_t>(sub);
     }
+    uint64_t prev, next;
+    double acc;
+    bool tail;
+    if constexpr (G == 16) {
+        cmpx_dpp<0xB1, 1>(key, sub);                                   // blocks of 2
+        cmpx_dpp<0x1B, 2>(key, sub);                                   // blocks of 4
+        cmpx_dpp<0xB1, 1>(key, sub);
+        cmpx_dpp<0x141, 4>(key, sub);                                  // blocks of 8
+        cmpx_dpp<0x4E, 2>(key, sub);
+        cmpx_dpp<0xB1, 1>(key, sub);
+        cmpx_dpp<0x140, 8>(key, sub);                                  // blocks of 16
+        cmpx_xor4(key, sub);
+        cmpx_dpp<0x4E, 2>(key, sub);
+        cmpx_dpp<0xB1, 1>(key, sub);
+        prev = dpp_u64<0x111>(key, key);                               // lane sub - 1 (lane 0: itself)
+        next = dpp_u64<0x101>(key, key);                               // lane sub + 1 (lane 15: itself)
+    } else {
 #pragma unroll
-    for (int k = 2; k <= G; k <<= 1)
+        for (int k = 2; k <= G; k <<= 1)
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t other = __shfl_xor(key, j, 64);
-            const bool up = (sub & k) == 0;
-            const bool lower = (sub & j) == 0;
-            key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
-        }
-    const uint64_t prev = __shfl(key, base_l + (sub > 0 ? sub - 1 : 0), 64);
-    const uint64_t next = __shfl(key, base_l + (sub + 1 < G ? sub + 1 : G - 1), 64);
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const uint64_t other = __shfl_xor(key, j, 64);
+                const bool up = (sub & k) == 0;
+                const bool lower = (sub & j) == 0;
+                key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
+            }
+        prev = __shfl(key, base_l + (sub > 0 ? sub - 1 : 0), 64);
+        next = __shfl(key, base_l + (sub + 1 < G ? sub + 1 : G - 1), 64);
+    }
     const bool lead = key != KEY_NONE && (sub == 0 || (prev >> 32) != (key >> 32));
     // segmented suffix sums (Hillis-Steele): after the log2(G) steps the first
-    // lane of each run holds the sum of the run's values
-    double acc = __shfl(v, base_l + static_cast<int>(key & (G - 1)), 64);
-    bool tail = sub == G - 1 || (next >> 32) != (key >> 32);
+    // lane of each run holds the sum of the run's values.  A lane that is not
+    // yet a tail has its run's end at most G - 1 - d lanes above it, so its
+    // source lane sub + d is always inside the group.
+    acc = __shfl(v, base_l + static_cast<int>(key & (G - 1)), 64);
+    tail = sub == G - 1 || (next >> 32) != (key >> 32);
+    if constexpr (G == 16) {
+        auto scan_step = [&](auto dc) {
+            constexpr int CTRL = 0x100 + decltype(dc)::value;         // row shift left by d
+            const double va = dpp_f64<CTRL>(acc, acc);
+            const bool ta = dpp_u64<CTRL>(1ull, static_cast<uint64_t>(tail)) != 0;
+            if (!tail) {
+                acc += va;
+                tail = ta;
+            }
+        };
+        scan_step(std::integral_constant<int, 1>{});
+        scan_step(std::integral_constant<int, 2>{});
+        scan_step(std::integral_constant<int, 4>{});
+        scan_step(std::integral_constant<int, 8>{});
+    } else {
 #pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-        const int src = base_l + (sub + d < G ? sub + d : G - 1);
-        const double va = __shfl(acc, src, 64);
-        const bool ta = __shfl(static_cast<int>(tail), src, 64) != 0;
-        if (!tail) {
-            acc += va;
-            tail = ta;
+        for (int d = 1; d < G; d <<= 1) {
+            const int src = base_l + (sub + d < G ? sub + d : G - 1);
+            const double va = __shfl(acc, src, 64);
+            const bool ta = __shfl(static_cast<int>(tail), src, 64) != 0;
+            if (!tail) {
+                acc += va;
+                tail = ta;
+            }
         }
     }
     const uint64_t lm = __ballot(lead) & gmask;
