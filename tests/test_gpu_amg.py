@@ -72,6 +72,48 @@ def test_hierarchy_matches_reference(cfg, scale, m, kmax):
         assert np.abs(nxt["val"] - R1.A.data).max() <= 1e-12 * np.abs(R1.A.data).max(), l
 
 
+def _ragged_matrix(n, lo, hi, diag, seed):
+    """Random nonsymmetric matrix whose rows have their own fill fraction in
+    [lo, hi): row lengths from a few entries to over a hundred."""
+    rng = np.random.default_rng(seed)
+    fill = rng.uniform(lo, hi, n)[:, None]
+    M = (rng.random((n, n)) < fill) * rng.uniform(-1.0, 1.0, (n, n))
+    np.fill_diagonal(M, rng.uniform(diag, 1.5 * diag, n))
+    return sp.csr_matrix(M)
+
+
+@pytest.mark.parametrize("n,seed", [(600, 5), (800, 7)])
+def test_every_local_system_size_matches_reference(n, seed):
+    """Distance-1 restriction rows whose local systems fall in every size class
+    the GPU solves separately (K <= 8, 9-12, 13-14, 15-16, 17-32, 33-64, each
+    class's upper edge included where the matrix reaches it), with rows of more
+    than 64 strong F neighbours truncated to the 64 strongest: split and
+    interpolation exact, R's pattern exact, R and the Galerkin coarse operator
+    within 1e-12 of their largest entries."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A = _ragged_matrix(n, 0.004, 0.25, 40.0, seed)
+    one = AR.setup(A, AR.Options(coarse_max=64, seed=3, max_levels=2, kmax=64))
+    R = one[0].R.tocsr()
+    K = np.diff(R.indptr) - 1
+    cls = np.searchsorted([8, 12, 14, 16, 32], K, side="left")
+    assert (np.bincount(cls, minlength=6) > 0).all() and K.max() == 64
+    untrunc = AR.lair_restriction(A, one[0].cf, AR.Options(kmax=10 ** 6)).tocsr()
+    assert (np.diff(untrunc.indptr) - 1 > 64).sum() >= 3
+    print("local system classes", n, seed, np.bincount(cls, minlength=6).tolist(), flush=True)
+    g = _amg(A, 64, 3, max_levels=2, kmax=64)
+    got, coarse = g.level(0), g.level(1)
+    g.close()
+    assert np.array_equal(got["cf"], one[0].cf.astype(np.int8))
+    assert np.array_equal(got["p"], one[0].p.astype(np.int32))
+    assert np.array_equal(got["r_rowptr"], R.indptr) and np.array_equal(got["r_col"], R.indices)
+    assert np.abs(got["r_val"] - R.data).max() <= 1e-12 * np.abs(R.data).max()
+    Ac = one[1].A.toarray()
+    n1 = Ac.shape[0]
+    Cg = sp.csr_matrix((coarse["val"], coarse["col"], coarse["rowptr"]), shape=(n1, n1)).toarray()
+    assert np.abs(Cg - Ac).max() <= 1e-12 * np.abs(Ac).max()
+
+
 @pytest.mark.parametrize("cfg,scale,m", CASES[:3])
 def test_filtered_restriction_matches_reference(cfg, scale, m):
     """R filtered with phi_R = 0.2 from the reference's level matrix: the kept
