@@ -114,6 +114,32 @@ def test_every_local_system_size_matches_reference(n, seed):
     assert np.abs(Cg - Ac).max() <= 1e-12 * np.abs(Ac).max()
 
 
+@pytest.mark.parametrize("distance", [1, 2])
+def test_singular_local_system_is_reported(distance):
+    """40 independent 3 x 3 blocks [[10, -3, -2], [-20, 4, 4], [-24, 4, 4]] (each
+    scaled by its own power of two; the block itself is nonsingular): the first
+    point is the C point (both others depend on it strongly), its two F
+    neighbours form the local system [[4, 4], [4, 4]] times the scale.  With a
+    power-of-two scale the elimination is exact, so the second pivot is exactly
+    zero, the condition under which LAPACK's solve fails too; the setup reports
+    every such row as an error instead of writing R.  (Under another scale the
+    multiplier 4s * (1 / 4s) can round off 1 and leave a pivot of one unit in
+    the last place: nearly singular systems are solved, not reported, on either
+    side.)"""
+    need_gpu()
+    from oracle import air_ref as AR
+    rng = np.random.default_rng(1)
+    blk = np.array([[10.0, -3.0, -2.0], [-20.0, 4.0, 4.0], [-24.0, 4.0, 4.0]])
+    A = sp.csr_matrix(sp.block_diag([2.0 ** rng.integers(-4, 5) * blk for _ in range(40)]))
+    cf = AR.pmis(AR.strength(A, 0.25), 0, 3)
+    assert np.array_equal(cf, np.tile([1, -1, -1], 40))
+    with pytest.raises(np.linalg.LinAlgError):
+        AR.lair_restriction(A, cf, AR.Options(distance=distance))
+    with pytest.raises(B.PairError) as e:
+        _amg(A, 8, 3, max_levels=2, lair_distance=distance)
+    assert "singular local lAIR system in 40 rows" in str(e.value)
+
+
 @pytest.mark.parametrize("cfg,scale,m", CASES[:3])
 def test_filtered_restriction_matches_reference(cfg, scale, m):
     """R filtered with phi_R = 0.2 from the reference's level matrix: the kept
