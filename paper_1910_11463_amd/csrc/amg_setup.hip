@@ -1101,29 +1101,37 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 //   r_ik = -a_ik / a_kk + sum_{j in F, j != k} (a_ij / a_jj) (a_jk / a_kk),
 // over all entries of A (no strength test), then the phi_R filter of the lAIR
 // rows and the C point's own 1.  One wave per row accumulates into an LDS hash
-// table keyed by column: first row i's direct terms, then row j's terms for
-// one F neighbour j after the other (a row of A has distinct columns, so no two
-// lanes add to one slot at once, and every column's sum is taken in the same
-// order in every launch).  The distinct columns are then ranked and filtered.
+// table keyed by column.  The gathers are issued together: row i's entries with
+// cf, 1/a_jj and the row offsets of every column j, then the products of all F
+// neighbours' rows a chunk at a time (their columns, values, cf and 1/a_kk in
+// two round trips), staged in LDS as (slot, (u_j a_jk) / a_kk).  Only the sums
+// are then taken neighbour by neighbour, from LDS: the direct term first, then
+// row j's terms for one F neighbour j after the other in row i's column order
+// (a row of A has distinct columns, so no two lanes add to one slot at once, and
+// every column's sum is taken in the same order in every launch).  The kept
+// columns are then compacted and ranked.
 // Rows with more than kNairCols distinct columns (or more than kNairNbr F
 // neighbours) count in overflow[0]; rows keeping more than KCAP F entries in
 // overflow[1] (the R A P kernels stage at most KCAP + 1 entries of a row of R).
 // Table sizes: the large form takes any row up to 1024 distinct columns and
-// 256 F neighbours (40 KB of LDS per wave); the small form (9 KB, four times
-// the waves per CU) is used on levels whose rows have at most 15 entries, where
-// no row can exceed it.
+// 256 F neighbours (42 KB of LDS per wave); the small form (5 KB, 32 waves per
+// CU) is used first on levels whose rows have at most 15 entries (so at most 14
+// F neighbours), the medium form (10 KB, 256 columns, 64 F neighbours) first on
+// the others.  A row that does not fit a form is deferred to the next larger
+// one: small, medium, wide medium (20 KB, 512 columns, 96 F neighbours), large.
 constexpr int kNairSlots = 2048;
 constexpr int kNairCols = 1024;
 constexpr int kNairNbr = 256;
-constexpr int kNairSmallSlots = 512;
-constexpr int kNairSmallCols = 256;
-constexpr int kNairSmallNbr = 32;
-constexpr int kNairSmallRowLen = 15;   // 1 + 15 + 15 * 15 <= kNairSmallCols
-// medium form (20 KB) on the other levels; its rows that do not fit are
-// deferred to the large form
-constexpr int kNairMidSlots = 1024;
-constexpr int kNairMidCols = 512;
-constexpr int kNairMidNbr = 96;
+constexpr int kNairSmallSlots = 256;
+constexpr int kNairSmallCols = 128;
+constexpr int kNairSmallNbr = 16;
+constexpr int kNairSmallRowLen = 15;
+constexpr int kNairMidSlots = 512;
+constexpr int kNairMidCols = 256;
+constexpr int kNairMidNbr = 64;
+constexpr int kNairWideSlots = 1024;
+constexpr int kNairWideCols = 512;
+constexpr int kNairWideNbr = 96;
 
 __global__ void __launch_bounds__(256) k_max_row_len(int64_t n, const int64_t* __restrict__ rowptr,
                                                      int* __restrict__ out) {
@@ -1145,10 +1153,17 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
         double* __restrict__ r_val, int* __restrict__ overflow) {
     constexpr uint32_t kEmpty = 0xffffffffu;
     constexpr uint32_t kMask = kNairSlots - 1;
+    // products staged per chunk: slot in uk, value in uv (at most 8 per lane)
+    constexpr int kChunk = kNairCols < 512 ? kNairCols : 512;
+    constexpr int kPer = kChunk / 64;
+    constexpr int kNR = (kNairNbr + 1 + 63) / 64;   // registers holding noff
+    static_assert(kChunk % 64 == 0 && kNairCols + kChunk <= kNairSlots, "nAIR table sizes");
     __shared__ uint32_t hk[kNairSlots];
     __shared__ double hv[kNairSlots];
     __shared__ int32_t nj[kNairNbr];
     __shared__ double nu_[kNairNbr];
+    __shared__ int64_t njs[kNairNbr];        // start of neighbour t's row in A
+    __shared__ int32_t noff[kNairNbr + 1];   // its first product
     __shared__ int32_t uk[kNairCols];
     __shared__ double uv[kNairCols];
     __shared__ int s_used;
@@ -1170,6 +1185,16 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
         atomicAdd(&s_used, kNairSlots);   // marks the row as too long
         return kNairSlots;
     };
+    // the neighbour t whose products hold position f: noff[t] <= f < noff[t + 1]
+    auto owner = [&](int f, int nn) -> int {
+        int lo = 0, hi = nn;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (noff[mid] <= f) lo = mid;
+            else hi = mid;
+        }
+        return lo;
+    };
     for (int r = blockIdx.x; r < nc; r += gridDim.x) {
         const int I = rows ? rows[r] : r;
         const int64_t i = c2f[I];
@@ -1180,48 +1205,123 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
         }
         if (lane == 0) s_used = 0;
         __syncthreads();
-        // row i: direct terms -a_ik / a_kk and the F neighbours (j, a_ij / a_jj)
-        int nn = 0;
+        // row i: direct terms -a_ik / a_kk, the F neighbours (j, a_ij / a_jj),
+        // their rows' offsets and their first products (lengths scanned)
+        int nn = 0, np = 0;
         for (int64_t e0 = rs; e0 < re; e0 += 64) {
             const int64_t e = e0 + lane;
             int32_t j = -1;
             bool f = false;
+            double u = 0.0;
+            int64_t js = 0;
+            int len = 0;
             if (e < re) {
                 j = col[e];
-                f = cf[j] < 0;
+                const double a = val[e];
+                const int8_t cj = cf[j];
+                const double dj = dinv[j];
+                js = rowptr[j];
+                const int64_t je = rowptr[j + 1];
+                f = cj < 0;
+                u = a * dj;
+                len = static_cast<int>(je - js);
             }
             const uint64_t m = __ballot(f);
             const int q = nn + __popcll(m & below);
+            int x = f ? len : 0;   // inclusive scan of the F rows' lengths
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(x, d, 64);
+                if (lane >= d) x += y;
+            }
             if (f) {
-                const double u = val[e] * dinv[j];
                 if (q < kNairNbr) {
                     nj[q] = j;
                     nu_[q] = u;
+                    njs[q] = js;
+                    noff[q] = np + x - len;
                 }
                 const uint32_t h = slot_of(static_cast<uint32_t>(j));
                 if (h < kNairSlots) hv[h] = hv[h] - u;
             }
             nn += __popcll(m);
+            np += __shfl(x, 63, 64);
         }
+        if (lane == 0 && nn <= kNairNbr) noff[nn] = np;
         __syncthreads();
         bool bad = nn > kNairNbr || s_used > kNairCols;
-        // row j's terms for each F neighbour j, one neighbour at a time
-        for (int t = 0; t < nn && !bad; ++t) {
-            const int32_t j = nj[t];
-            const double u = nu_[t];
-            const int64_t js = rowptr[j], je = rowptr[j + 1];
-            for (int64_t e0 = js; e0 < je; e0 += 64) {
-                const int64_t e = e0 + lane;
-                if (e < je) {
-                    const int32_t k = col[e];
-                    if (k != j && cf[k] < 0) {
-                        const uint32_t h = slot_of(static_cast<uint32_t>(k));
-                        if (h < kNairSlots) hv[h] = fma(u * val[e], dinv[k], hv[h]);
-                    }
+        // noff[t] for a wave-uniform t, from registers (lane t % 64 of noffr[t / 64])
+        int noffr[kNR];
+#pragma unroll
+        for (int k = 0; k < kNR; ++k) {
+            const int t = k * 64 + lane;
+            noffr[k] = t <= min(nn, kNairNbr) ? noff[t] : 0;
+        }
+        auto noff_at = [&](int t) -> int {
+            int v = 0;
+#pragma unroll
+            for (int k = 0; k < kNR; ++k) {
+                const int x = __builtin_amdgcn_readlane(noffr[k], t & 63);
+                v = (t >> 6) == k ? x : v;
+            }
+            return v;
+        };
+        // the F neighbours' rows, kChunk products at a time
+        for (int f0 = 0; f0 < np && !bad; f0 += kChunk) {
+            const int fe = min(np, f0 + kChunk);
+            int32_t kk[kPer];
+            int own[kPer];
+            double av[kPer];
+            bool ok[kPer];
+#pragma unroll
+            for (int s = 0; s < kPer; ++s) {
+                const int f = f0 + s * 64 + lane;
+                ok[s] = f < fe;
+                kk[s] = 0;
+                own[s] = 0;
+                av[s] = 0.0;
+                if (ok[s]) {
+                    const int t = owner(f, nn);
+                    const int64_t e = njs[t] + (f - noff[t]);
+                    own[s] = t;
+                    kk[s] = col[e];
+                    av[s] = nu_[t] * val[e];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < kPer; ++s) {
+                if (ok[s]) {
+                    const int32_t k = kk[s];
+                    const int8_t ck = cf[k];
+                    av[s] *= dinv[k];
+                    ok[s] = k != nj[own[s]] && ck < 0;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < kPer; ++s) {
+                const int q = s * 64 + lane;
+                if (f0 + q < fe) {
+                    const uint32_t h = ok[s] ? slot_of(static_cast<uint32_t>(kk[s])) : kEmpty;
+                    uk[q] = h < kNairSlots ? h : kEmpty;
+                    uv[q] = av[s];
                 }
             }
             __syncthreads();
+            // the sums, one neighbour's products after the other
+            int t = owner(f0, nn);
+            int nt0 = noff_at(t);
+            for (; t < nn && nt0 < fe; ++t) {
+                const int nt1 = noff_at(t + 1);
+                const int a0 = max(nt0, f0) - f0, a1 = min(nt1, fe) - f0;
+                for (int q = a0 + lane; q < a1; q += 64) {
+                    const uint32_t h = uk[q];
+                    if (h != kEmpty) hv[h] += uv[q];
+                }
+                nt0 = nt1;
+                __syncthreads();
+            }
             bad = s_used > kNairCols;
+            __syncthreads();
         }
         if (bad) {
             if (DEFER) {
@@ -1236,7 +1336,7 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
             __syncthreads();
             continue;
         }
-        // the distinct columns, ranked by column
+        // the distinct columns
         int nu = 0;
         for (int h0 = 0; h0 < kNairSlots; h0 += 64) {
             const int h = h0 + lane;
@@ -1254,27 +1354,45 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
         for (int q = lane; q < nu; q += 64) mx = fmax(mx, fabs(uv[q]));
         for (int d = 32; d >= 1; d >>= 1) mx = fmax(mx, __shfl_xor(mx, d, 64));
         const double thr = phi * mx;
-        int kept = 0, before = 0;
-        const int64_t ob = COUNT ? 0 : r_rowptr[I];
-        for (int q = lane; q < nu; q += 64) {
-            if (!(fabs(uv[q]) >= thr)) continue;
-            const int32_t c = uk[q];
-            if (COUNT) {
-                ++kept;
-            } else {
-                int rank = 0;   // kept columns below c
-                for (int t = 0; t < nu; ++t) rank += (fabs(uv[t]) >= thr && uk[t] < c) ? 1 : 0;
+        // the kept ones, compacted in place (a chunk is read before it is written,
+        // and no position beyond the one read is written)
+        int nk = 0;
+        for (int q0 = 0; q0 < nu; q0 += 64) {
+            const int q = q0 + lane;
+            int32_t c = 0;
+            double v = 0.0;
+            bool keep = false;
+            if (q < nu) {
+                c = uk[q];
+                v = uv[q];
+                keep = fabs(v) >= thr;
+            }
+            const uint64_t m = __ballot(keep);
+            if (keep) {
+                const int o = nk + __popcll(m & below);
+                uk[o] = c;
+                uv[o] = v;
+            }
+            nk += __popcll(m);
+        }
+        __syncthreads();
+        if (COUNT) {
+            if (lane == 0) rcnt[I] = nk + 1;
+            if (lane == 0 && nk > KCAP) atomicAdd(overflow + 1, 1);
+        } else {
+            // ranked by column among the kept (at most KCAP: longer rows stop the
+            // setup after the count pass), the C point's 1 in its place
+            const int64_t ob = r_rowptr[I];
+            int before = 0;
+            for (int q = lane; q < nk; q += 64) {
+                const int32_t c = uk[q];
+                int rank = 0;
+                for (int t = 0; t < nk; ++t) rank += uk[t] < c ? 1 : 0;
                 const int64_t o = ob + rank + (c > i ? 1 : 0);
                 r_col[o] = c;
                 r_val[o] = uv[q];
                 before += c < i ? 1 : 0;
             }
-        }
-        if (COUNT) {
-            for (int d = 32; d >= 1; d >>= 1) kept += __shfl_xor(kept, d, 64);
-            if (lane == 0) rcnt[I] = kept + 1;
-            if (lane == 0 && kept > KCAP) atomicAdd(overflow + 1, 1);
-        } else {
             for (int d = 32; d >= 1; d >>= 1) before += __shfl_xor(before, d, 64);
             if (lane == 0) {
                 r_col[ob + before] = static_cast<int32_t>(i);
@@ -2600,9 +2718,43 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         constexpr int kDG = 4;   // lanes per row of k_r_direct
         const unsigned gdir = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kDG - 1) / (64 / kDG), 1 << 20));
         DBuf<int> novf(nair ? 4 : 0);
-        bool nair_small = false;
-        DBuf<int32_t> nair_def[2];   // class 0: the deferred rows
-        int nair_ndef[2] = {0, 0};
+        // nAIR forms (0 small, 1 medium, 2 wide medium, 3 large) from the first
+        // to the large one; nair_list[s] holds the rows deferred to stage s >= 1
+        int nair_form[4] = {1, 2, 3, -1};
+        DBuf<int32_t> nair_list[4][2];   // class 0 of each: the deferred rows
+        int nair_nlist[4][2] = {};
+        auto nair_launch = [&](int form, bool count, int nrows, const int32_t* rows) {
+            const unsigned g = static_cast<unsigned>(std::min(std::max(nrows, 1), 1 << 20));
+#define PAIR_NAIR_ARGS nrows, rows, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, prm_.filter_r, \
+                       count ? rcnt.p : nullptr, count ? nullptr : L.R.rowptr.p, count ? nullptr : L.R.col.p,     \
+                       count ? nullptr : L.R.val.p, novf.p
+            if (form == 0 && count)
+                hipLaunchKernelGGL((k_nair1<true, kNairSmallSlots, kNairSmallCols, kNairSmallNbr, true>), dim3(g),
+                                   dim3(64), 0, s_, PAIR_NAIR_ARGS);
+            else if (form == 0)
+                hipLaunchKernelGGL((k_nair1<false, kNairSmallSlots, kNairSmallCols, kNairSmallNbr, true>), dim3(g),
+                                   dim3(64), 0, s_, PAIR_NAIR_ARGS);
+            else if (form == 1 && count)
+                hipLaunchKernelGGL((k_nair1<true, kNairMidSlots, kNairMidCols, kNairMidNbr, true>), dim3(g), dim3(64),
+                                   0, s_, PAIR_NAIR_ARGS);
+            else if (form == 1)
+                hipLaunchKernelGGL((k_nair1<false, kNairMidSlots, kNairMidCols, kNairMidNbr, true>), dim3(g),
+                                   dim3(64), 0, s_, PAIR_NAIR_ARGS);
+            else if (form == 2 && count)
+                hipLaunchKernelGGL((k_nair1<true, kNairWideSlots, kNairWideCols, kNairWideNbr, true>), dim3(g),
+                                   dim3(64), 0, s_, PAIR_NAIR_ARGS);
+            else if (form == 2)
+                hipLaunchKernelGGL((k_nair1<false, kNairWideSlots, kNairWideCols, kNairWideNbr, true>), dim3(g),
+                                   dim3(64), 0, s_, PAIR_NAIR_ARGS);
+            else if (count)
+                hipLaunchKernelGGL((k_nair1<true, kNairSlots, kNairCols, kNairNbr, false>), dim3(g), dim3(64), 0, s_,
+                                   PAIR_NAIR_ARGS);
+            else
+                hipLaunchKernelGGL((k_nair1<false, kNairSlots, kNairCols, kNairNbr, false>), dim3(g), dim3(64), 0, s_,
+                                   PAIR_NAIR_ARGS);
+#undef PAIR_NAIR_ARGS
+            PAIR_LAUNCH_CHECK();
+        };
         if (nair) {
             PAIR_HIP(hipMemsetAsync(novf.p, 0, 4 * sizeof(int), s_));
             hipLaunchKernelGGL(k_max_row_len, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
@@ -2610,29 +2762,22 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             int maxlen = 0;
             d2h(&maxlen, novf.p + 2, 1, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            nair_small = maxlen <= kNairSmallRowLen;
-#define PAIR_NAIR_COUNT(N, ROWS) N, ROWS, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, \
-                                 prm_.filter_r, rcnt.p, nullptr, nullptr, nullptr, novf.p
-            if (nair_small)
-                hipLaunchKernelGGL((k_nair1<true, kNairSmallSlots, kNairSmallCols, kNairSmallNbr, false>), dim3(gnair),
-                                   dim3(64), 0, s_, PAIR_NAIR_COUNT(static_cast<int>(total_c), nullptr));
-            else
-                hipLaunchKernelGGL((k_nair1<true, kNairMidSlots, kNairMidCols, kNairMidNbr, true>), dim3(gnair),
-                                   dim3(64), 0, s_, PAIR_NAIR_COUNT(static_cast<int>(total_c), nullptr));
-            PAIR_LAUNCH_CHECK();
+            if (maxlen <= kNairSmallRowLen)
+                for (int st = 0; st < 4; ++st) nair_form[st] = st;
+            // the count pass: every row by the first form, then the rows each form
+            // deferred (rcnt = -1) by the next
+            nair_launch(nair_form[0], true, static_cast<int>(total_c), nullptr);
             int ovf[4] = {0, 0, 0, 0};
             d2h(ovf, novf.p, 4, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            if (ovf[3] > 0) {
-                classify<2>(total_c, 2, nullptr, rcnt.p, {-1}, nair_def, nair_ndef, s_);
-                const unsigned gd = static_cast<unsigned>(std::min(nair_ndef[0], 1 << 20));
-                hipLaunchKernelGGL((k_nair1<true, kNairSlots, kNairCols, kNairNbr, false>), dim3(gd), dim3(64), 0,
-                                   s_, PAIR_NAIR_COUNT(nair_ndef[0], nair_def[0].p));
-                PAIR_LAUNCH_CHECK();
-                d2h(ovf, novf.p, 2, s_);
+            for (int st = 1; st < 4 && nair_form[st] >= 0 && ovf[3] > 0; ++st) {
+                classify<2>(total_c, 2, nullptr, rcnt.p, {-1}, nair_list[st], nair_nlist[st], s_);
+                PAIR_HIP(hipMemsetAsync(novf.p + 3, 0, sizeof(int), s_));
+                nair_launch(nair_form[st], true, nair_nlist[st][0], nair_list[st][0].p);
+                d2h(ovf, novf.p, 4, s_);
                 PAIR_HIP(hipStreamSynchronize(s_));
             }
-#undef PAIR_NAIR_COUNT
+            PAIR_CHECK(ovf[3] == 0, "nAIR: deferred rows left after the large form");
             PAIR_CHECK(ovf[0] == 0, "nAIR: a restriction row has more than 1024 distinct columns");
             PAIR_CHECK(ovf[1] == 0, "nAIR: a restriction row keeps more than 64 F entries (at most 64 "
                                     "are supported); raise filter_r");
@@ -2664,21 +2809,10 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
         if (nair) {
-#define PAIR_NAIR_FILL(N, ROWS) N, ROWS, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, \
-                                prm_.filter_r, nullptr, L.R.rowptr.p, L.R.col.p, L.R.val.p, novf.p
-            if (nair_small)
-                hipLaunchKernelGGL((k_nair1<false, kNairSmallSlots, kNairSmallCols, kNairSmallNbr, false>),
-                                   dim3(gnair), dim3(64), 0, s_, PAIR_NAIR_FILL(static_cast<int>(total_c), nullptr));
-            else
-                hipLaunchKernelGGL((k_nair1<false, kNairMidSlots, kNairMidCols, kNairMidNbr, true>), dim3(gnair),
-                                   dim3(64), 0, s_, PAIR_NAIR_FILL(static_cast<int>(total_c), nullptr));
-            if (nair_ndef[0] > 0) {
-                const unsigned gd = static_cast<unsigned>(std::min(nair_ndef[0], 1 << 20));
-                hipLaunchKernelGGL((k_nair1<false, kNairSlots, kNairCols, kNairNbr, false>), dim3(gd), dim3(64), 0,
-                                   s_, PAIR_NAIR_FILL(nair_ndef[0], nair_def[0].p));
-            }
-#undef PAIR_NAIR_FILL
-            PAIR_LAUNCH_CHECK();
+            // the rows in the forms the count pass found for them
+            nair_launch(nair_form[0], false, static_cast<int>(total_c), nullptr);
+            for (int st = 1; st < 4 && nair_form[st] >= 0; ++st)
+                if (nair_nlist[st][0] > 0) nair_launch(nair_form[st], false, nair_nlist[st][0], nair_list[st][0].p);
             PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
         } else if (dist2) {
             // the patterns; then rows of K <= 64 by k_r_build (one wave, LDS), the

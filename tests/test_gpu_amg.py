@@ -309,6 +309,63 @@ def test_nair_matches_reference(cfg, scale, m, phi):
                     assert abs(have[c] - v) <= 1e-12 * scale_v, (l, I, c)
 
 
+def _rowlen_matrix(n, lo, hi, diag, seed):
+    """Random nonsymmetric matrix whose row i holds its diagonal and between
+    lo - 1 and hi - 1 off-diagonal entries at random distinct columns."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        k = int(rng.integers(lo, hi + 1))
+        c = rng.choice(np.delete(np.arange(n), i), size=k - 1, replace=False)
+        rows += [i] * k
+        cols += [i] + c.tolist()
+        vals += [rng.uniform(diag, 1.5 * diag)] + rng.uniform(-1.0, 1.0, k - 1).tolist()
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
+@pytest.mark.parametrize("n,lo,hi,seed,over", [(3000, 12, 15, 3, (128,)), (4000, 20, 34, 6, (256, 512))])
+def test_nair_rows_deferred_to_larger_tables_match_reference(n, lo, hi, seed, over):
+    """nAIR rows with more distinct columns than a table holds are finished by
+    the next larger one: rows of at most 15 entries (first the 128-column
+    table) of which some reach 129-151 distinct F columns, and rows of 20-34
+    entries (first the 256-column table) that all reach more than 256 and some
+    more than 512 (the 512-column table, then the 1024-column one).  Split
+    exact, kept pattern exact away from the phi_R = 0.5 threshold, values within
+    1e-12 of the largest."""
+    need_gpu()
+    from oracle import air_ref as AR
+    A = _rowlen_matrix(n, lo, hi, 20.0, seed)
+    phi = 0.5
+    one = AR.setup(A, AR.Options(coarse_max=64, seed=3, max_levels=2, nair_degree=1, filter_r=phi))
+    full = AR.nair_restriction(A, one[0].cf, AR.Options(nair_degree=1)).tocsr()
+    nf = np.diff(full.indptr) - 1          # distinct F columns of each row
+    for c in over:
+        assert (nf > c).any()
+    print("nAIR deferral", n, lo, hi, "distinct F max", nf.max(), [(c, int((nf > c).sum())) for c in over],
+          flush=True)
+    g = _amg(A, 64, 3, max_levels=2, filter_r=phi, nair_degree=1)
+    got = g.level(0)
+    g.close()
+    assert np.array_equal(got["cf"], one[0].cf.astype(np.int8))
+    rp, rc, rv = got["r_rowptr"], got["r_col"], got["r_val"]
+    Rr = one[0].R.tocsr()
+    scale_v = np.abs(full.data).max()
+    for I, i in enumerate(np.flatnonzero(one[0].cf > 0)):
+        c0 = full.indices[full.indptr[I]:full.indptr[I + 1]]
+        v0 = full.data[full.indptr[I]:full.indptr[I + 1]]
+        off = c0 != i
+        thr = phi * np.abs(v0[off]).max()
+        want = set(Rr.indices[Rr.indptr[I]:Rr.indptr[I + 1]].tolist())
+        have = dict(zip(rc[rp[I]:rp[I + 1]].tolist(), rv[rp[I]:rp[I + 1]].tolist()))
+        assert list(have) == sorted(have) and have.get(int(i)) == 1.0, I
+        for c, v in zip(c0, v0):
+            if c == i or abs(abs(v) - thr) <= 1e-9 * thr:
+                continue
+            assert (c in have) == (c in want), (I, c)
+            if c in have:
+                assert abs(have[c] - v) <= 1e-12 * scale_v, (I, c)
+
+
 def test_nair_transport_sweep_matches_exact_sweep():
     """A sweep replacement with nAIR hierarchies (degree 1, phi_R = 0.1) and
     F/C schedules converges to the oracle's exact sweep."""
