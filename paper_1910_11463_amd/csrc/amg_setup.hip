@@ -1109,7 +1109,10 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
 // row j's terms for one F neighbour j after the other in row i's column order
 // (a row of A has distinct columns, so no two lanes add to one slot at once, and
 // every column's sum is taken in the same order in every launch).  The kept
-// columns are then compacted and ranked.
+// columns are then compacted and ranked.  The count pass also writes each row
+// of at most cap entries to a staging slot of its own (k_nair_unstage places
+// it in R once the row offsets are known), so only the longer rows are computed
+// a second time.
 // Rows with more than kNairCols distinct columns (or more than kNairNbr F
 // neighbours) count in overflow[0]; rows keeping more than KCAP F entries in
 // overflow[1] (the R A P kernels stage at most KCAP + 1 entries of a row of R).
@@ -1133,12 +1136,39 @@ constexpr int kNairWideSlots = 1024;
 constexpr int kNairWideCols = 512;
 constexpr int kNairWideNbr = 96;
 
+// the longest row (grid-stride; one atomic per block)
 __global__ void __launch_bounds__(256) k_max_row_len(int64_t n, const int64_t* __restrict__ rowptr,
                                                      int* __restrict__ out) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    int len = i < n ? static_cast<int>(rowptr[i + 1] - rowptr[i]) : 0;
+    __shared__ int wmax[4];
+    int len = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256)
+        len = max(len, static_cast<int>(rowptr[i + 1] - rowptr[i]));
     for (int d = 32; d >= 1; d >>= 1) len = max(len, __shfl_xor(len, d, 64));
-    if ((threadIdx.x & 63) == 0 && len > 0) atomicMax(out, len);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = len;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int m = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+        if (m > 0) atomicMax(out, m);
+    }
+}
+
+// staged nAIR rows (at most cap entries each) into R; longer rows are written
+// by a fill pass
+__global__ void __launch_bounds__(256) k_nair_unstage(int64_t nc, int cap, const int64_t* __restrict__ rcnt,
+                                                      const int64_t* __restrict__ r_rowptr,
+                                                      const int32_t* __restrict__ s_col,
+                                                      const double* __restrict__ s_val, int32_t* __restrict__ r_col,
+                                                      double* __restrict__ r_val) {
+    const int64_t x = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t I = x / cap;
+    const int k = static_cast<int>(x - I * cap);
+    if (I >= nc) return;
+    const int64_t len = rcnt[I];
+    if (len > cap || k >= len) return;
+    const int64_t o = r_rowptr[I] + k;
+    r_col[o] = s_col[x];
+    r_val[o] = s_val[x];
 }
 
 // DEFER: a row that does not fit is left to the large form (COUNT marks it
@@ -1150,7 +1180,8 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
         const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, const double* __restrict__ val,
         const int8_t* __restrict__ cf, const double* __restrict__ dinv, double phi,
         int64_t* __restrict__ rcnt, const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
-        double* __restrict__ r_val, int* __restrict__ overflow) {
+        double* __restrict__ r_val, int* __restrict__ overflow, int cap, int32_t* __restrict__ s_col,
+        double* __restrict__ s_val, int32_t* __restrict__ olist) {
     constexpr uint32_t kEmpty = 0xffffffffu;
     constexpr uint32_t kMask = kNairSlots - 1;
     // products staged per chunk: slot in uk, value in uv (at most 8 per lane)
@@ -1376,27 +1407,37 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
             nk += __popcll(m);
         }
         __syncthreads();
+        // COUNT: the row's length, and a row of at most cap entries written to its
+        // staging slot (I * cap), a longer one listed in olist (overflow[4]
+        // entries) for a fill pass of this form; otherwise the row into R
+        bool write = true;
         if (COUNT) {
-            if (lane == 0) rcnt[I] = nk + 1;
-            if (lane == 0 && nk > KCAP) atomicAdd(overflow + 1, 1);
-        } else {
+            write = nk + 1 <= cap;
+            if (lane == 0) {
+                rcnt[I] = nk + 1;
+                if (nk > KCAP) atomicAdd(overflow + 1, 1);
+                if (!write) olist[atomicAdd(overflow + 4, 1)] = I;
+            }
+        }
+        if (write) {
             // ranked by column among the kept (at most KCAP: longer rows stop the
             // setup after the count pass), the C point's 1 in its place
-            const int64_t ob = r_rowptr[I];
+            int32_t* const oc = COUNT ? s_col + static_cast<int64_t>(I) * cap : r_col + r_rowptr[I];
+            double* const ov = COUNT ? s_val + static_cast<int64_t>(I) * cap : r_val + r_rowptr[I];
             int before = 0;
             for (int q = lane; q < nk; q += 64) {
                 const int32_t c = uk[q];
                 int rank = 0;
                 for (int t = 0; t < nk; ++t) rank += uk[t] < c ? 1 : 0;
-                const int64_t o = ob + rank + (c > i ? 1 : 0);
-                r_col[o] = c;
-                r_val[o] = uv[q];
+                const int o = rank + (c > i ? 1 : 0);
+                oc[o] = c;
+                ov[o] = uv[q];
                 before += c < i ? 1 : 0;
             }
             for (int d = 32; d >= 1; d >>= 1) before += __shfl_xor(before, d, 64);
             if (lane == 0) {
-                r_col[ob + before] = static_cast<int32_t>(i);
-                r_val[ob + before] = 1.0;
+                oc[before] = static_cast<int32_t>(i);
+                ov[before] = 1.0;
             }
         }
         __syncthreads();
@@ -2717,7 +2758,14 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         const unsigned gnair = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(total_c, 1), 1 << 20));
         constexpr int kDG = 4;   // lanes per row of k_r_direct
         const unsigned gdir = static_cast<unsigned>(std::min<int64_t>((total_c + 64 / kDG - 1) / (64 / kDG), 1 << 20));
-        DBuf<int> novf(nair ? 4 : 0);
+        // novf: [0] rows beyond the large form, [1] rows keeping more than KCAP,
+        // [2] the longest row of A, [3] rows deferred, [4] rows longer than their
+        // staging slot
+        DBuf<int> novf(nair ? 5 : 0);
+        DBuf<int32_t> nair_scol, nair_olist;
+        DBuf<double> nair_sval;
+        int nair_cap = 32;
+        int nair_oseg[5] = {0, 0, 0, 0, 0};   // olist entries of stage st: [oseg[st], oseg[st + 1])
         // nAIR forms (0 small, 1 medium, 2 wide medium, 3 large) from the first
         // to the large one; nair_list[s] holds the rows deferred to stage s >= 1
         int nair_form[4] = {1, 2, 3, -1};
@@ -2727,7 +2775,7 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             const unsigned g = static_cast<unsigned>(std::min(std::max(nrows, 1), 1 << 20));
 #define PAIR_NAIR_ARGS nrows, rows, c2f.p, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, L.dinv.p, prm_.filter_r, \
                        count ? rcnt.p : nullptr, count ? nullptr : L.R.rowptr.p, count ? nullptr : L.R.col.p,     \
-                       count ? nullptr : L.R.val.p, novf.p
+                       count ? nullptr : L.R.val.p, novf.p, nair_cap, nair_scol.p, nair_sval.p, nair_olist.p
             if (form == 0 && count)
                 hipLaunchKernelGGL((k_nair1<true, kNairSmallSlots, kNairSmallCols, kNairSmallNbr, true>), dim3(g),
                                    dim3(64), 0, s_, PAIR_NAIR_ARGS);
@@ -2756,27 +2804,42 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
             PAIR_LAUNCH_CHECK();
         };
         if (nair) {
-            PAIR_HIP(hipMemsetAsync(novf.p, 0, 4 * sizeof(int), s_));
-            hipLaunchKernelGGL(k_max_row_len, dim3(grid_for(n, 256)), dim3(256), 0, s_, n, L.A.rowptr.p,
-                               novf.p + 2);
+            PAIR_HIP(hipMemsetAsync(novf.p, 0, 5 * sizeof(int), s_));
+            hipLaunchKernelGGL(k_max_row_len, dim3(std::min<int64_t>(grid_for(n, 256), 1024)), dim3(256), 0, s_, n,
+                               L.A.rowptr.p, novf.p + 2);
             int maxlen = 0;
             d2h(&maxlen, novf.p + 2, 1, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
-            if (maxlen <= kNairSmallRowLen)
+            // the first form: small for rows of at most 15 entries, the wide medium
+            // one where rows average more than 40 entries (most of their rows
+            // exceed 256 distinct columns), else the medium one
+            if (maxlen <= kNairSmallRowLen) {
                 for (int st = 0; st < 4; ++st) nair_form[st] = st;
+                nair_cap = 24;
+            } else if (L.A.nnz > 40 * n) {
+                nair_form[0] = 2;
+                nair_form[1] = 3;
+                nair_form[2] = -1;
+            }
+            nair_scol.alloc(static_cast<size_t>(total_c) * nair_cap);
+            nair_sval.alloc(static_cast<size_t>(total_c) * nair_cap);
+            nair_olist.alloc(static_cast<size_t>(total_c));
             // the count pass: every row by the first form, then the rows each form
             // deferred (rcnt = -1) by the next
             nair_launch(nair_form[0], true, static_cast<int>(total_c), nullptr);
-            int ovf[4] = {0, 0, 0, 0};
-            d2h(ovf, novf.p, 4, s_);
+            int ovf[5] = {0, 0, 0, 0, 0};
+            d2h(ovf, novf.p, 5, s_);
             PAIR_HIP(hipStreamSynchronize(s_));
+            nair_oseg[1] = ovf[4];
             for (int st = 1; st < 4 && nair_form[st] >= 0 && ovf[3] > 0; ++st) {
                 classify<2>(total_c, 2, nullptr, rcnt.p, {-1}, nair_list[st], nair_nlist[st], s_);
                 PAIR_HIP(hipMemsetAsync(novf.p + 3, 0, sizeof(int), s_));
                 nair_launch(nair_form[st], true, nair_nlist[st][0], nair_list[st][0].p);
-                d2h(ovf, novf.p, 4, s_);
+                d2h(ovf, novf.p, 5, s_);
                 PAIR_HIP(hipStreamSynchronize(s_));
+                nair_oseg[st + 1] = ovf[4];
             }
+            for (int st = 1; st < 5; ++st) nair_oseg[st] = std::max(nair_oseg[st], nair_oseg[st - 1]);
             PAIR_CHECK(ovf[3] == 0, "nAIR: deferred rows left after the large form");
             PAIR_CHECK(ovf[0] == 0, "nAIR: a restriction row has more than 1024 distinct columns");
             PAIR_CHECK(ovf[1] == 0, "nAIR: a restriction row keeps more than 64 F entries (at most 64 "
@@ -2809,10 +2872,16 @@ void Hierarchy::setup(Csr&& A0, const std::vector<int64_t>& off0, const std::vec
         L.R.col.alloc(L.R.nnz);
         L.R.val.alloc(L.R.nnz);
         if (nair) {
-            // the rows in the forms the count pass found for them
-            nair_launch(nair_form[0], false, static_cast<int>(total_c), nullptr);
-            for (int st = 1; st < 4 && nair_form[st] >= 0; ++st)
-                if (nair_nlist[st][0] > 0) nair_launch(nair_form[st], false, nair_nlist[st][0], nair_list[st][0].p);
+            // the staged rows, then the longer ones by the form that counted them
+            hipLaunchKernelGGL(k_nair_unstage, dim3(grid_for(total_c * nair_cap, 256)), dim3(256), 0, s_, total_c,
+                               nair_cap, rcnt.p, L.R.rowptr.p, nair_scol.p, nair_sval.p, L.R.col.p, L.R.val.p);
+            PAIR_LAUNCH_CHECK();
+            for (int st = 0; st < 4 && nair_form[st] >= 0; ++st)
+                if (nair_oseg[st + 1] > nair_oseg[st])
+                    nair_launch(nair_form[st], false, nair_oseg[st + 1] - nair_oseg[st],
+                                nair_olist.p + nair_oseg[st]);
+            nair_scol.reset();
+            nair_sval.reset();
             PAIR_HIP(hipMemsetAsync(d_counter.p, 0, sizeof(int), s_));
         } else if (dist2) {
             // the patterns; then rows of K <= 64 by k_r_build (one wave, LDS), the

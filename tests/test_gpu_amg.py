@@ -323,24 +323,31 @@ def _rowlen_matrix(n, lo, hi, diag, seed):
     return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
 
 
-@pytest.mark.parametrize("n,lo,hi,seed,over", [(3000, 12, 15, 3, (128,)), (4000, 20, 34, 6, (256, 512))])
-def test_nair_rows_deferred_to_larger_tables_match_reference(n, lo, hi, seed, over):
+@pytest.mark.parametrize("n,lo,hi,seed,diag,phi,over", [(3000, 12, 15, 3, 20.0, 0.5, (128,)),
+                                                          (4000, 20, 34, 6, 20.0, 0.5, (256, 512)),
+                                                          (3000, 12, 15, 3, 2.0, 0.2, (128,)),
+                                                          (4000, 20, 34, 6, 3.0, 0.23, (256, 512))])
+def test_nair_rows_deferred_to_larger_tables_match_reference(n, lo, hi, seed, diag, phi, over):
     """nAIR rows with more distinct columns than a table holds are finished by
     the next larger one: rows of at most 15 entries (first the 128-column
     table) of which some reach 129-151 distinct F columns, and rows of 20-34
     entries (first the 256-column table) that all reach more than 256 and some
-    more than 512 (the 512-column table, then the 1024-column one).  Split
-    exact, kept pattern exact away from the phi_R = 0.5 threshold, values within
-    1e-12 of the largest."""
+    more than 512 (the 512-column table, then the 1024-column one).  With a
+    weak diagonal and a low phi_R, deferred rows also keep more than 32
+    entries (longer than their staging slot: computed again by the table that
+    took them).  Split exact, kept pattern exact away from the phi_R threshold,
+    values within 1e-12 of the largest."""
     need_gpu()
     from oracle import air_ref as AR
-    A = _rowlen_matrix(n, lo, hi, 20.0, seed)
-    phi = 0.5
+    A = _rowlen_matrix(n, lo, hi, diag, seed)
     one = AR.setup(A, AR.Options(coarse_max=64, seed=3, max_levels=2, nair_degree=1, filter_r=phi))
     full = AR.nair_restriction(A, one[0].cf, AR.Options(nair_degree=1)).tocsr()
     nf = np.diff(full.indptr) - 1          # distinct F columns of each row
     for c in over:
         assert (nf > c).any()
+    kept = np.diff(one[0].R.indptr)
+    if phi < 0.5:
+        assert ((nf > over[0]) & (kept > 32)).any()
     print("nAIR deferral", n, lo, hi, "distinct F max", nf.max(), [(c, int((nf > c).sum())) for c in over],
           flush=True)
     g = _amg(A, 64, 3, max_levels=2, filter_r=phi, nair_degree=1)
