@@ -1304,6 +1304,9 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
             int own[kPer];
             double av[kPer];
             bool ok[kPer];
+            // this lane's products f0 + lane + 64 s have nondecreasing owners: one
+            // search, then steps forward
+            int tl = f0 + lane < fe ? owner(f0 + lane, nn) : 0;
 #pragma unroll
             for (int s = 0; s < kPer; ++s) {
                 const int f = f0 + s * 64 + lane;
@@ -1312,11 +1315,11 @@ k_nair1(int nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ c2
                 own[s] = 0;
                 av[s] = 0.0;
                 if (ok[s]) {
-                    const int t = owner(f, nn);
-                    const int64_t e = njs[t] + (f - noff[t]);
-                    own[s] = t;
+                    while (noff[tl + 1] <= f) ++tl;
+                    const int64_t e = njs[tl] + (f - noff[tl]);
+                    own[s] = tl;
                     kk[s] = col[e];
-                    av[s] = nu_[t] * val[e];
+                    av[s] = nu_[tl] * val[e];
                 }
             }
 #pragma unroll
