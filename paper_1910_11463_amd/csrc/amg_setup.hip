@@ -867,6 +867,7 @@ __global__ void k_r_gather_once(int nrows, const int32_t* __restrict__ list,
 // list: the rows to do (null: all nrows).
 constexpr int kD2Max = 512;      // largest local system
 constexpr int kD2Slots = 2048;   // LDS hash set of a row's pattern
+constexpr int kD2Nb = 8;         // panel width of the blocked elimination
 
 // Adds column c to the set.  Inserts stop once more than kD2Max columns are in
 // (the row is then an overflow), so at most kD2Max + 256 slots ever fill and
@@ -917,6 +918,10 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
     __shared__ int red_i[4];
     __shared__ int nd1, nset, ovf, npiv;
     __shared__ double pval;
+    __shared__ double up[MODE == 2 ? kD2Nb * kD2Max : 1];   // a panel's block row U12
+    __shared__ double sw_a[kD2Nb], sw_b[kD2Nb], prow[kD2Nb];   // panel rows being swapped, the pivot row
+    __shared__ int piv_rec[kD2Nb];                              // the panel's pivot rows
+    static_assert(kD2Max <= 512, "two rows of a local system per thread");
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     double* M = MODE == 2 ? work + static_cast<size_t>(blockIdx.x) * ld * ld : nullptr;
     for (int it = blockIdx.x; it < nrows; it += gridDim.x) {
@@ -1006,75 +1011,222 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         }
         __syncthreads();
         bool sing = false;
-        for (int p = 0; p < K; ++p) {
-            double v = -1.0;
-            int idx = K;
-            for (int r = p + t; r < K; r += 256) {
-                const double a = fabs(M[r * ld + p]);
-                if (a > v) {   // r increases: ties keep the smaller row
-                    v = a;
-                    idx = r;
-                }
+        // LU with partial pivoting in panels of kD2Nb columns.  Each panel is
+        // factored column by column with its rows in registers (thread t holds
+        // rows t and t + 256): the pivot searched over the whole column below,
+        // the two rows swapped through LDS, the multipliers kept in place below
+        // the diagonal and applied to the right-hand side at once, the panel's
+        // own columns updated from the pivot row in LDS.  The panel goes back to
+        // M, its row swaps are applied to the columns right of it, the block row
+        // right of the panel is solved with its unit lower triangle (U12, staged
+        // in LDS) and the rows below it are updated once, A22 -= L21 U12, instead
+        // of once per column: every entry sees the same subtractions in the same
+        // order as in column-by-column elimination.
+        for (int p0 = 0; p0 < K && !sing; p0 += kD2Nb) {
+            const int nbw = min(kD2Nb, K - p0);
+            const int pe = p0 + nbw;
+            double v[2][kD2Nb];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = t + 256 * h;
+#pragma unroll
+                for (int a = 0; a < kD2Nb; ++a) v[h][a] = (r >= p0 && r < K && a < nbw) ? M[r * ld + p0 + a] : 0.0;
             }
-            for (int d = 32; d >= 1; d >>= 1) {
-                const double ov = __shfl_xor(v, d, 64);
-                const int oi = __shfl_xor(idx, d, 64);
-                if (ov > v || (ov == v && oi < idx)) {
-                    v = ov;
-                    idx = oi;
-                }
-            }
-            if (lane == 0) {
-                red_v[w] = v;
-                red_i[w] = idx;
-            }
-            __syncthreads();
-            if (t == 0) {
-                double bv = red_v[0];
-                int bi = red_i[0];
-                for (int q = 1; q < 4; ++q)
-                    if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < bi)) {
-                        bv = red_v[q];
-                        bi = red_i[q];
+#pragma unroll
+            for (int a = 0; a < kD2Nb; ++a) {
+                if (a >= nbw) break;
+                const int p = p0 + a;
+                double v_ = -1.0;
+                int idx = K;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {   // rows in increasing order: ties keep the smaller
+                    const int r = t + 256 * h;
+                    if (r >= p && r < K && fabs(v[h][a]) > v_) {
+                        v_ = fabs(v[h][a]);
+                        idx = r;
                     }
-                pval = bv;
-                npiv = bi;
-            }
-            __syncthreads();
-            if (!(pval > 0.0)) {   // the same value in every thread: a uniform exit
-                sing = true;
-                break;
-            }
-            const int piv = npiv;
-            if (piv != p) {
-                for (int c = p + t; c < K; c += 256) {
-                    const double x = M[p * ld + c];
-                    M[p * ld + c] = M[piv * ld + c];
-                    M[piv * ld + c] = x;
                 }
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const double ov = __shfl_xor(v_, d, 64);
+                    const int oi = __shfl_xor(idx, d, 64);
+                    if (ov > v_ || (ov == v_ && oi < idx)) {
+                        v_ = ov;
+                        idx = oi;
+                    }
+                }
+                if (lane == 0) {
+                    red_v[w] = v_;
+                    red_i[w] = idx;
+                }
+                __syncthreads();
                 if (t == 0) {
-                    const double x = rhs[p];
-                    rhs[p] = rhs[piv];
-                    rhs[piv] = x;
+                    double bv = red_v[0];
+                    int bi = red_i[0];
+                    for (int q = 1; q < 4; ++q)
+                        if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < bi)) {
+                            bv = red_v[q];
+                            bi = red_i[q];
+                        }
+                    pval = bv;
+                    npiv = bi;
+                    piv_rec[a] = bi;
+                }
+                __syncthreads();
+                if (!(pval > 0.0)) {   // the same value in every thread: a uniform exit
+                    sing = true;
+                    break;
+                }
+                const int piv = npiv;
+                if (piv != p) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (t + 256 * h == p)
+#pragma unroll
+                            for (int c = 0; c < kD2Nb; ++c) sw_a[c] = v[h][c];
+                        if (t + 256 * h == piv)
+#pragma unroll
+                            for (int c = 0; c < kD2Nb; ++c) sw_b[c] = v[h][c];
+                    }
+                    if (t == 0) {
+                        const double x = rhs[p];
+                        rhs[p] = rhs[piv];
+                        rhs[piv] = x;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (t + 256 * h == p)
+#pragma unroll
+                            for (int c = 0; c < kD2Nb; ++c) v[h][c] = sw_b[c];
+                        if (t + 256 * h == piv)
+#pragma unroll
+                            for (int c = 0; c < kD2Nb; ++c) v[h][c] = sw_a[c];
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if (t + 256 * h == p)
+#pragma unroll
+                        for (int c = 0; c < kD2Nb; ++c) prow[c] = v[h][c];
+                __syncthreads();
+                const double dpp = prow[a];
+                const double bp = rhs[p];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = t + 256 * h;
+                    if (r > p && r < K) {
+                        const double l = v[h][a] / dpp;
+                        v[h][a] = l;
+                        rhs[r] -= l * bp;
+#pragma unroll
+                        for (int c = a + 1; c < kD2Nb; ++c)
+                            if (c < nbw) v[h][c] -= l * prow[c];
+                    }
+                }
+                __syncthreads();
+            }
+            if (sing) break;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = t + 256 * h;
+                if (r >= p0 && r < K)
+#pragma unroll
+                    for (int a = 0; a < kD2Nb; ++a)
+                        if (a < nbw) M[r * ld + p0 + a] = v[h][a];
+            }
+            // the panel's row swaps, in order, on the columns right of it
+            for (int c = pe + t; c < K; c += 256)
+                for (int a = 0; a < nbw; ++a) {
+                    const int q = piv_rec[a];
+                    if (q != p0 + a) {
+                        const double x = M[(p0 + a) * ld + c];
+                        M[(p0 + a) * ld + c] = M[q * ld + c];
+                        M[q * ld + c] = x;
+                    }
+                }
+            __syncthreads();
+            if (sing || pe >= K) continue;
+            // U12 = L11^-1 A12: one column per thread (its nbw entries loaded
+            // together, the triangle's entries are the same for every thread)
+            for (int c = pe + t; c < K; c += 256) {
+                double u[kD2Nb];
+#pragma unroll
+                for (int a = 0; a < kD2Nb; ++a) u[a] = a < nbw ? M[(p0 + a) * ld + c] : 0.0;
+#pragma unroll
+                for (int a = 0; a < kD2Nb; ++a) {
+                    if (a < nbw) {
+                        double x = u[a];
+#pragma unroll
+                        for (int b2 = 0; b2 < a; ++b2) x -= M[(p0 + a) * ld + p0 + b2] * u[b2];
+                        u[a] = x;
+                        M[(p0 + a) * ld + c] = x;
+                        up[a * kD2Max + c] = x;
+                    }
                 }
             }
             __syncthreads();
-            const double dpp = M[p * ld + p];
-            for (int r = p + 1 + t; r < K; r += 256) lm[r] = M[r * ld + p] / dpp;
-            __syncthreads();
-            for (int r = p + 1 + w; r < K; r += 4) {
-                const double l = lm[r];
-                for (int c = p + 1 + lane; c < K; c += 64) M[r * ld + c] -= l * M[p * ld + c];
+            // A22 -= L21 U12: wave w takes rows pe + w + 4 m, two rows and up to
+            // four column slots per lane at a time, every load issued before the
+            // first store (K <= 512: one pass of 256 columns covers at most two)
+            for (int r0 = pe + 2 * w; r0 < K; r0 += 8) {
+                double l[2][kD2Nb];
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int a = 0; a < kD2Nb; ++a)
+                        l[h][a] = (a < nbw && r0 + h < K) ? M[(r0 + h) * ld + p0 + a] : 0.0;
+                for (int c0 = pe + lane; c0 < K; c0 += 256) {
+                    double x[2][4];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int c = c0 + 64 * j;
+                            x[h][j] = (r0 + h < K && c < K) ? M[(r0 + h) * ld + c] : 0.0;
+                        }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int c = c0 + 64 * j;
+                        if (c >= K) continue;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            if (r0 + h >= K) continue;
+                            double y = x[h][j];
+#pragma unroll
+                            for (int a = 0; a < kD2Nb; ++a)
+                                if (a < nbw) y -= l[h][a] * up[a * kD2Max + c];
+                            M[(r0 + h) * ld + c] = y;
+                        }
+                    }
+                }
             }
-            for (int r = p + 1 + t; r < K; r += 256) rhs[r] -= lm[r] * rhs[p];
             __syncthreads();
         }
         if (!sing) {
-            for (int r = K - 1; r >= 0; --r) {   // z_r into lm[r]
-                if (t == 0) lm[r] = rhs[r] / M[r * ld + r];
+            // back substitution, z_r into lm[r], in blocks of kD2Nb rows from the
+            // bottom: the block's triangle read into LDS and solved by one thread,
+            // then the rows above updated by the block's z, each right-hand side
+            // taking its subtractions in decreasing column order as row by row
+            for (int r1 = K; r1 > 0; r1 -= kD2Nb) {
+                const int r0 = max(0, r1 - kD2Nb);
+                const int nb = r1 - r0;
+                for (int q = t; q < nb * nb; q += 256) {
+                    const int a = q / nb, b2 = q - (q / nb) * nb;
+                    up[a * kD2Nb + b2] = M[(r0 + a) * ld + r0 + b2];
+                }
                 __syncthreads();
-                const double z = lm[r];
-                for (int q = t; q < r; q += 256) rhs[q] -= M[q * ld + r] * z;
+                if (t == 0)
+                    for (int a = nb - 1; a >= 0; --a) {
+                        double x = rhs[r0 + a];
+                        for (int b2 = nb - 1; b2 > a; --b2) x -= up[a * kD2Nb + b2] * lm[r0 + b2];
+                        lm[r0 + a] = x / up[a * kD2Nb + a];
+                    }
+                __syncthreads();
+                for (int q = t; q < r0; q += 256) {
+                    double x = rhs[q];
+                    for (int b2 = nb - 1; b2 >= 0; --b2) x -= M[q * ld + r0 + b2] * lm[r0 + b2];
+                    rhs[q] = x;
+                }
                 __syncthreads();
             }
         }
