@@ -1059,24 +1059,20 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
                     red_i[w] = idx;
                 }
                 __syncthreads();
-                if (t == 0) {
-                    double bv = red_v[0];
-                    int bi = red_i[0];
-                    for (int q = 1; q < 4; ++q)
-                        if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < bi)) {
-                            bv = red_v[q];
-                            bi = red_i[q];
-                        }
-                    pval = bv;
-                    npiv = bi;
-                    piv_rec[a] = bi;
-                }
-                __syncthreads();
-                if (!(pval > 0.0)) {   // the same value in every thread: a uniform exit
+                // every thread takes the same maximum of the four waves' (a
+                // thread writes red_v again only after two more barriers)
+                double bv = red_v[0];
+                int piv = red_i[0];
+                for (int q = 1; q < 4; ++q)
+                    if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < piv)) {
+                        bv = red_v[q];
+                        piv = red_i[q];
+                    }
+                if (t == 0) piv_rec[a] = piv;
+                if (!(bv > 0.0)) {   // the same value in every thread: a uniform exit
                     sing = true;
                     break;
                 }
-                const int piv = npiv;
                 if (piv != p) {
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
@@ -1123,8 +1119,11 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
                             if (c < nbw) v[h][c] -= l * prow[c];
                     }
                 }
-                __syncthreads();
+                // no barrier here: the next step writes shared memory (red_v, sw_a,
+                // sw_b, prow, rhs) only after a barrier that every thread reaches
+                // once done with this step's reads
             }
+            __syncthreads();
             if (sing) break;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
