@@ -909,9 +909,10 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
           const int64_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col, double* __restrict__ r_val,
           double* __restrict__ work, int ld, int* __restrict__ singular) {
     constexpr bool COUNT = MODE == 0;
-    __shared__ int hs[kD2Slots];
+    // MODE 2 reads each row's pattern from R (written by MODE 1): no hash set
+    __shared__ int hs[MODE == 2 ? 1 : kD2Slots];
     __shared__ int cols[kD2Max + 256];
-    __shared__ int tmp[kD2Max + 256];
+    __shared__ int tmp[MODE == 2 ? 1 : kD2Max + 256];
     __shared__ double rhs[kD2Max];
     __shared__ double lm[kD2Max];
     __shared__ double red_v[4];
@@ -928,66 +929,78 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
         const int64_t I = list ? list[it] : it;
         const int64_t i = c2f[I];
         const int64_t rs = rowptr[i], re = rowptr[i + 1];
-        for (int q = t; q < kD2Slots; q += 256) hs[q] = -1;
-        if (t == 0) {
-            nd1 = 0;
-            nset = 0;
-            ovf = 0;
-        }
-        __syncthreads();
-        // distance 1: the strong F neighbours of i, listed and put in the set
-        for (int64_t e = rs + t; e < re; e += 256) {
-            const int32_t j = col[e];
-            if (r_candidate(i, j, sflag[e], cf)) {
-                const int q = atomicAdd(&nd1, 1);
-                if (q < kD2Max) tmp[q] = j;
-                else ovf = 1;
-                d2_insert(hs, &nset, &ovf, j);
+        int K = 0;
+        if constexpr (MODE == 2) {
+            // the pattern, sorted, from row I of R without i itself
+            const int64_t rb0 = r_rowptr[I];
+            K = static_cast<int>(r_rowptr[I + 1] - rb0) - 1;
+            for (int a = t; a <= K; a += 256) {
+                const int32_t c = r_col[rb0 + a];
+                if (c != i) cols[a - (c > i ? 1 : 0)] = c;
             }
-        }
-        __syncthreads();
-        // distance 2: the strong F neighbours of each of them
-        const int n1 = min(nd1, kD2Max);
-        for (int q = 0; q < n1; ++q) {
-            const int64_t j = tmp[q];
-            const int64_t js = rowptr[j], je = rowptr[j + 1];
-            for (int64_t e = js + t; e < je; e += 256) {
-                const int32_t k = col[e];
-                if (k != i && r_candidate(j, k, sflag[e], cf)) d2_insert(hs, &nset, &ovf, k);
-            }
-        }
-        __syncthreads();
-        const int K = nset;
-        if (COUNT) {
+            __syncthreads();
+        } else {
+            for (int q = t; q < kD2Slots; q += 256) hs[q] = -1;
             if (t == 0) {
-                rcnt[I] = ovf ? 1 : K + 1;
-                if (ovf) atomicOr(&ctl[0], 1);
-                else atomicMax(&ctl[1], K);
+                nd1 = 0;
+                nset = 0;
+                ovf = 0;
             }
-            __syncthreads();   // the next row clears the LDS
-            continue;
-        }
-        // the set, compacted and sorted by column (rank = number of smaller columns)
-        if (t == 0) nd1 = 0;
-        __syncthreads();
-        for (int q = t; q < kD2Slots; q += 256) {
-            const int c = hs[q];
-            if (c >= 0) tmp[atomicAdd(&nd1, 1)] = c;
-        }
-        __syncthreads();
-        for (int a = t; a < K; a += 256) {
-            const int c = tmp[a];
-            int r = 0;
-            for (int b = 0; b < K; ++b) r += tmp[b] < c ? 1 : 0;
-            cols[r] = c;
-        }
-        if (MODE == 1) {   // the pattern into row I of R (with i), for k_r_build
             __syncthreads();
-            const int64_t rb = r_rowptr[I];
-            for (int a = t; a < K; a += 256) r_col[rb + a + (cols[a] > i ? 1 : 0)] = cols[a];
-            if (t == 0) r_col[rb + d2_lower(cols, K, static_cast<int>(i))] = static_cast<int32_t>(i);
+            // distance 1: the strong F neighbours of i, listed and put in the set
+            for (int64_t e = rs + t; e < re; e += 256) {
+                const int32_t j = col[e];
+                if (r_candidate(i, j, sflag[e], cf)) {
+                    const int q = atomicAdd(&nd1, 1);
+                    if (q < kD2Max) tmp[q] = j;
+                    else ovf = 1;
+                    d2_insert(hs, &nset, &ovf, j);
+                }
+            }
             __syncthreads();
-            continue;
+            // distance 2: the strong F neighbours of each of them
+            const int n1 = min(nd1, kD2Max);
+            for (int q = 0; q < n1; ++q) {
+                const int64_t j = tmp[q];
+                const int64_t js = rowptr[j], je = rowptr[j + 1];
+                for (int64_t e = js + t; e < je; e += 256) {
+                    const int32_t k = col[e];
+                    if (k != i && r_candidate(j, k, sflag[e], cf)) d2_insert(hs, &nset, &ovf, k);
+                }
+            }
+            __syncthreads();
+            K = nset;
+            if (COUNT) {
+                if (t == 0) {
+                    rcnt[I] = ovf ? 1 : K + 1;
+                    if (ovf) atomicOr(&ctl[0], 1);
+                    else atomicMax(&ctl[1], K);
+                }
+                __syncthreads();   // the next row clears the LDS
+                continue;
+            }
+            // the set, compacted and sorted by column (rank = number of smaller columns)
+            if (t == 0) nd1 = 0;
+            __syncthreads();
+            for (int q = t; q < kD2Slots; q += 256) {
+                const int c = hs[q];
+                if (c >= 0) tmp[atomicAdd(&nd1, 1)] = c;
+            }
+            __syncthreads();
+            for (int a = t; a < K; a += 256) {
+                const int c = tmp[a];
+                int r = 0;
+                for (int b = 0; b < K; ++b) r += tmp[b] < c ? 1 : 0;
+                cols[r] = c;
+            }
+            if (MODE == 1) {   // the pattern into row I of R (with i), for k_r_build
+                __syncthreads();
+                const int64_t rb = r_rowptr[I];
+                for (int a = t; a < K; a += 256) r_col[rb + a + (cols[a] > i ? 1 : 0)] = cols[a];
+                if (t == 0) r_col[rb + d2_lower(cols, K, static_cast<int>(i))] = static_cast<int32_t>(i);
+                __syncthreads();
+                continue;
+            }
         }
         for (int a = t; a < K; a += 256) rhs[a] = 0.0;
         for (int r = w; r < K; r += 4)
