@@ -1059,17 +1059,28 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
                         idx = r;
                     }
                 }
-                for (int d = 32; d >= 1; d >>= 1) {
-                    const double ov = __shfl_xor(v_, d, 64);
-                    const int oi = __shfl_xor(idx, d, 64);
-                    if (ov > v_ || (ov == v_ && oi < idx)) {
-                        v_ = ov;
-                        idx = oi;
+                // the wave's largest value, then the smallest row holding it: DPP
+                // inside rows of 16 lanes, the four rows combined by readlane
+                {
+                    auto rl = [](double x, int l) {
+                        const long long b = __double_as_longlong(x);
+                        const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+                        const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+                        return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+                    };
+                    const double gm = group_max_dpp<16>(v_);
+                    const double wm = fmax(fmax(rl(gm, 0), rl(gm, 16)), fmax(rl(gm, 32), rl(gm, 48)));
+                    int ci = v_ == wm ? idx : K;
+                    ci = min(ci, dpp_int<0x140>(ci));
+                    ci = min(ci, dpp_int<0x141>(ci));
+                    ci = min(ci, dpp_int<0x4E>(ci));
+                    ci = min(ci, dpp_int<0xB1>(ci));
+                    const int wi = min(min(__builtin_amdgcn_readlane(ci, 0), __builtin_amdgcn_readlane(ci, 16)),
+                                       min(__builtin_amdgcn_readlane(ci, 32), __builtin_amdgcn_readlane(ci, 48)));
+                    if (lane == 0) {
+                        red_v[w] = wm;
+                        red_i[w] = wi;
                     }
-                }
-                if (lane == 0) {
-                    red_v[w] = v_;
-                    red_i[w] = idx;
                 }
                 __syncthreads();
                 // every thread takes the same maximum of the four waves' (a
