@@ -857,14 +857,14 @@ __global__ void k_r_gather_once(int nrows, const int32_t* __restrict__ list,
 // and, through each of them, their eps_R-strong F neighbours (no kmax
 // truncation).  One 256-thread block per row (grid-stride).  The pattern is
 // gathered into an LDS hash set; COUNT writes rcnt = K + 1, the largest K into
-// ctl[1] and flags rows of more than kD2Max F points in ctl[0] (MODE 0).  The
-// set is then sorted by column and either written to the row of R with i
-// (MODE 1: the pattern, for k_r_build<G, true> to solve rows of K <= 64), or
-// (MODE 2, the rows of `list`) A(R_i,R_i)^T z = -A(i,R_i)^T is solved in a
-// dense K x K slice of `work` (ld x ld doubles per block, row-major) by
-// Gaussian elimination with partial pivoting (ties to the smaller row) and
-// back substitution; a singular system gives z = 0 and counts in `singular`.
-// list: the rows to do (null: all nrows).
+// ctl[1] and flags rows of more than kD2Max F points in ctl[0] (MODE 0).  MODE 1
+// sorts the set by column and writes it to the row of R with i (the pattern,
+// for k_r_build<G, true> to solve rows of K <= 64).  MODE 2 (the rows of
+// `list`) reads that pattern back from R and solves A(R_i,R_i)^T z =
+// -A(i,R_i)^T in a dense K x K slice of `work` (ld x ld doubles per block,
+// row-major) by LU with partial pivoting (ties to the smaller row) in panels of
+// kD2Nb columns and back substitution; a singular system gives z = 0 and
+// counts in `singular`.  list: the rows to do (null: all nrows).
 constexpr int kD2Max = 512;      // largest local system
 constexpr int kD2Slots = 2048;   // LDS hash set of a row's pattern
 constexpr int kD2Nb = 8;         // panel width of the blocked elimination
@@ -917,8 +917,7 @@ k_r_dist2(int nrows, const int32_t* __restrict__ list, const int32_t* __restrict
     __shared__ double lm[kD2Max];
     __shared__ double red_v[4];
     __shared__ int red_i[4];
-    __shared__ int nd1, nset, ovf, npiv;
-    __shared__ double pval;
+    __shared__ int nd1, nset, ovf;
     __shared__ double up[MODE == 2 ? kD2Nb * kD2Max : 1];   // a panel's block row U12
     __shared__ double sw_a[kD2Nb], sw_b[kD2Nb], prow[kD2Nb];   // panel rows being swapped, the pivot row
     __shared__ int piv_rec[kD2Nb];                              // the panel's pivot rows
@@ -1346,8 +1345,8 @@ __global__ void __launch_bounds__(256) k_nair_unstage(int64_t nc, int cap, const
     r_val[o] = s_val[x];
 }
 
-// DEFER: a row that does not fit is left to the large form (COUNT marks it
-// with rcnt = -1 and counts it in overflow[3]) instead of being an error.
+// DEFER: a row that does not fit is left to the next larger form (COUNT marks
+// it with rcnt = -1 and counts it in overflow[3]) instead of being an error.
 // rows: the C rows to do (null: all nc).
 template <bool COUNT, int kNairSlots, int kNairCols, int kNairNbr, bool DEFER>
 __global__ void __launch_bounds__(64)
