@@ -140,6 +140,42 @@ def test_singular_local_system_is_reported(distance):
     assert "singular local lAIR system in 40 rows" in str(e.value)
 
 
+def test_singular_long_distance2_system_is_reported():
+    """Distance-2 local systems of 70 unknowns (solved by the blocked LU of the
+    long-row kernel, not by the one-wave kernel of at most 64): 10 independent
+    blocks, each a C point whose 70 F neighbours all depend on it strongly, with
+    A(R, R) = 4 I except [[4, 4], [4, 4]] for two of them, scaled by a power of
+    two (the matrix itself is nonsingular).  The elimination is exact, the
+    pivot of the second of the two is exactly zero as in LAPACK's solve, and the
+    setup reports the 10 rows."""
+    need_gpu()
+    from oracle import air_ref as AR
+
+    def block(nf, scale):
+        M = np.zeros((nf + 1, nf + 1))
+        M[0, 0] = 100.0
+        M[0, 1:] = -1.0
+        M[0, 2] = -0.5            # columns 1 and 2 differ in row 0
+        for j in range(1, nf + 1):
+            M[j, j] = 4.0
+            M[j, 0] = -32.0
+        M[2, 0] = -64.0           # rows 1 and 2 differ in column 0
+        M[1, 2] = M[2, 1] = 4.0   # A(R, R) holds [[4, 4], [4, 4]] for F points 1 and 2
+        return scale * M
+
+    rng = np.random.default_rng(2)
+    A = sp.csr_matrix(sp.block_diag([block(70, 2.0 ** rng.integers(-3, 4)) for _ in range(10)]))
+    assert np.linalg.matrix_rank(A.toarray()) == A.shape[0]
+    cf = AR.pmis(AR.strength(A, 0.25), 0, 3)
+    assert np.array_equal(cf, np.tile([1] + [-1] * 70, 10))
+    assert len(AR._r_pattern(A, AR.strength(A, 0.01), cf, 0, AR.Options(distance=2))) == 70
+    with pytest.raises(np.linalg.LinAlgError):
+        AR.lair_restriction(A, cf, AR.Options(distance=2))
+    with pytest.raises(B.PairError) as e:
+        _amg(A, 8, 3, max_levels=2, lair_distance=2)
+    assert "singular local lAIR system in 10 rows" in str(e.value)
+
+
 @pytest.mark.parametrize("cfg,scale,m", CASES[:3])
 def test_filtered_restriction_matches_reference(cfg, scale, m):
     """R filtered with phi_R = 0.2 from the reference's level matrix: the kept
