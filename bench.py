@@ -508,6 +508,15 @@ def main():
                                           dict(head, nair_degree=1, filter_r=0.1), setup=True, profile=False)
         except Exception as e:   # reported, not fatal: an extra measurement
             extra["nair_degree1"] = {"error": str(e)}
+        # distance-2 lAIR with phi_R = 0.1 at 32^3 S8 (the paper's distance-2
+        # restriction; its local systems of more than 64 unknowns take the
+        # blocked LU)
+        try:
+            extra["lair_distance2_32"] = entry(wl.make_config(2, scale=32), mode, args.batch_size, device,
+                                               dict(head, lair_distance=2, filter_r=0.1), setup=True,
+                                               profile=False)
+        except Exception as e:   # reported, not fatal: an extra measurement
+            extra["lair_distance2_32"] = {"error": str(e)}
         # batched directions: the 32^3 S8 checkerboard, all 80 directions in one
         # hierarchy (every V-cycle one graph replay) vs one direction per
         # hierarchy on several streams, with the F/C V(1,1) cycles and with the
